@@ -1,0 +1,110 @@
+"""Monte Carlo estimators of E, the bare force and dE/dC (oracle).
+
+  E      = <E_L>                                     (eq. eval-observable)
+  F_bare = -<H> - 2 (<E_L P> - <E_L><P>)             (Appendix A SWCT force;
+           H = dE_L/dR_alpha + sum_i omega dE_L/dr_i,
+           P = dlnPsi/dR_alpha + sum_i [omega dlnPsi/dr_i + 1/2 grad_i omega])
+  dE/dC  = 2 (<E_L O> - <E_L><O>),  O = dln|Psi|/dC  (eq. fc-vmc-eval; the
+           paper prints a leading minus, while defining B = dE/dC in the
+           Z-vector equations; the sign is fixed here by B = dE/dC, which the
+           finite-difference check confirms)
+  <dE_L/dC> is reported separately; its expectation vanishes and the
+  covariance form drops it, as the paper does.
+
+All sums are FP64 with a shift s (the mean E_L of the first measured batch)
+subtracted from E_L, so that the covariances do not cancel catastrophically
+(E_L is hundreds of hartree).  Batches are summed by numpy (pairwise) and
+accumulated across batches with Neumaier compensation.  Block sums of E_L - s
+per `block_sweeps` sweeps give the blocked error bar.
+"""
+import numpy as np
+
+
+class _Neumaier:
+    def __init__(self, shape):
+        self.s = np.zeros(shape)
+        self.c = np.zeros(shape)
+
+    def add(self, x):
+        t = self.s + x
+        big = np.abs(self.s) >= np.abs(x)
+        self.c += np.where(big, (self.s - t) + x, (x - t) + self.s)
+        self.s = t
+
+    @property
+    def value(self):
+        return self.s + self.c
+
+
+class Accumulator:
+    def __init__(self, n_atoms, n_ao, n_occ, block_sweeps=1):
+        A, M, n = n_atoms, n_ao, n_occ
+        self.shift = None
+        self.K = 0
+        self.sums = {k: _Neumaier(sh) for k, sh in dict(
+            E=(), EE=(), H=(A, 3), P=(A, 3), EP=(A, 3), O=(M, n), EO=(M, n), G=(M, n)).items()}
+        self.block_sweeps = block_sweeps
+        self.block_sums = []
+        self.block_counts = []
+        self._cur_block = [0.0, 0]
+        self._sweeps_in_block = 0
+        self.block_F = []
+        self._blk = None
+
+    def _block_force(self, e, meas):
+        """Per-block force estimate (for blocked error bars of F)."""
+        if self._blk is None:
+            self._blk = dict(K=0, E=0.0, H=0.0, P=0.0, EP=0.0)
+        b = self._blk
+        b["K"] += e.shape[0]
+        b["E"] += np.sum(e)
+        b["H"] = b["H"] + np.sum(meas["H"], axis=0)
+        b["P"] = b["P"] + np.sum(meas["P"], axis=0)
+        b["EP"] = b["EP"] + np.einsum("w,wak->ak", e, meas["P"])
+
+    def add(self, meas):
+        E = np.asarray(meas["E_L"], dtype=np.float64)
+        if self.shift is None:
+            self.shift = float(np.mean(E))
+        e = E - self.shift
+        W = E.shape[0]
+        self.K += W
+        sm = self.sums
+        sm["E"].add(np.sum(e))
+        sm["EE"].add(np.sum(e * e))
+        sm["H"].add(np.sum(meas["H"], axis=0))
+        sm["P"].add(np.sum(meas["P"], axis=0))
+        sm["EP"].add(np.einsum("w,wak->ak", e, meas["P"]))
+        sm["O"].add(np.sum(meas["O"], axis=0))
+        sm["EO"].add(np.einsum("w,wmi->mi", e, meas["O"]))
+        sm["G"].add(np.sum(meas["G"], axis=0))
+        self._cur_block[0] += float(np.sum(e))
+        self._cur_block[1] += W
+        self._block_force(e, meas)
+        self._sweeps_in_block += 1
+        if self._sweeps_in_block == self.block_sweeps:
+            b = self._blk
+            k = float(b["K"])
+            self.block_F.append(-b["H"] / k - 2.0 * (b["EP"] / k - (b["E"] / k) * (b["P"] / k)))
+            self._blk = None
+            self.block_sums.append(self._cur_block[0])
+            self.block_counts.append(self._cur_block[1])
+            self._cur_block = [0.0, 0]
+            self._sweeps_in_block = 0
+
+    def result(self):
+        K = float(self.K)
+        v = {k: a.value / K for k, a in self.sums.items()}
+        E = self.shift + v["E"]
+        F = -v["H"] - 2.0 * (v["EP"] - v["E"] * v["P"])
+        dEdC = 2.0 * (v["EO"] - v["E"] * v["O"])
+        nb = len(self.block_sums)
+        if nb >= 2:
+            bm = np.array(self.block_sums) / np.array(self.block_counts)
+            sigma = float(np.std(bm, ddof=1) / np.sqrt(nb))
+            F_sigma = np.std(np.array(self.block_F), axis=0, ddof=1) / np.sqrt(nb)
+        else:
+            sigma = float("nan")
+            F_sigma = np.full_like(F, np.nan)
+        return dict(E=E, E_sigma=sigma, F_sigma=F_sigma, F_bare=F, dE_dC=dEdC, dEL_dC_mean=v["G"],
+                    var_E=v["EE"] - v["E"] ** 2, K=self.K, shift=self.shift)

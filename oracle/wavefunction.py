@@ -1,0 +1,206 @@
+"""Jastrow-Slater determinant, log|Psi| and the local energy (oracle).
+
+Follows Appendix A of the paper:
+  * Psi = J * det, with the determinant part the JAGP restricted to the
+    occupied MOs (eq. occ-expansion), i.e. det A_up * det A_dn with
+    A_sigma[e, i] = phi_i(r_e),  phi_i = sum_mu C_mu,i psi_mu (eq. restricted-C);
+    restricted closed shell: electrons 0..n_up-1 are spin up and the rest spin
+    down, both spins use the same C (Sec. II, restricted case).
+  * Two-body Pade Jastrow J2 = exp(sum_{i<j} v(r_ij)), v(r) = a r / (1 + F r)
+    (eq. twobody_v with a = 1/2); spin independent.
+  * Optional electron-nucleus cusp factor exp(sum_{e,alpha} -Z r/(1 + b r)):
+    the paper omits it because its ECPs remove the singularity; here it is used
+    only for the hydrogen-atom check.
+  * E_L = H Psi / Psi (Appendix A) with H the all-electron molecular
+    Hamiltonian, including the nuclear repulsion.
+
+The kinetic term uses
+    lap Psi / Psi |_e = lapD/D + 2 gradD/D . gradJ + lap J + |grad J|^2,
+with gradD/D|_e = sum_i Kinv[i,e] grad phi_i(r_e) and lapD/D likewise from the
+explicit inverse (for any invertible A, d det / det = tr(A^-1 dA)).
+
+All routines accept complex arrays and stay complex-analytic, so derivatives
+can be taken by the complex-step method (Squire & Trapp, SIAM Rev. 1998).
+"""
+import numpy as np
+
+from . import gto
+
+
+class System:
+    """Molecule + wavefunction parameters in the oracle's own layout."""
+
+    def __init__(self, mol, C=None):
+        self.xyz = np.array(mol.xyz, dtype=np.float64)
+        self.Z = np.array(mol.Z, dtype=np.float64)
+        self.table = gto.ShellTable(mol.basis)
+        self.C = np.array(mol.C if C is None else C)
+        self.n_up = int(mol.n_up)
+        self.n_dn = int(mol.n_dn)
+        self.N = self.n_up + self.n_dn
+        jas = mol.jastrow
+        self.a = float(jas.ee_a)
+        self.F = float(jas.ee_F)
+        self.en_on = int(jas.en_on)
+        self.en_b = float(jas.en_b)
+        self.A = self.xyz.shape[0]
+        self.M = self.table.n_ao
+        assert self.C.shape == (self.M, max(self.n_up, self.n_dn))
+
+    def spin_blocks(self):
+        """[(electron slice, number of orbitals)] for the up and down blocks."""
+        out = []
+        if self.n_up:
+            out.append((slice(0, self.n_up), self.n_up))
+        if self.n_dn:
+            out.append((slice(self.n_up, self.N), self.n_dn))
+        return out
+
+
+# --------------------------------------------------------------------------
+# determinants
+# --------------------------------------------------------------------------
+
+def lu_logdet(A):
+    """log|det A| and sign(det A) by LU with partial pivoting.
+
+    A: [W, n, n], real or complex.  Pivot rows are chosen by the largest
+    |Re|; the log is taken as 1/2 log(pivot^2) so that it stays analytic for
+    the complex step.  Returns (sign [W] real, logabs [W]).
+    """
+    A = np.array(A, copy=True)
+    W, n, _ = A.shape
+    sign = np.ones(W)
+    logabs = np.zeros(W, dtype=A.dtype)
+    w = np.arange(W)
+    for k in range(n):
+        p = k + np.argmax(np.abs(A[:, k:, k].real), axis=1)
+        swap = p != k
+        if np.any(swap):
+            rows_k = A[w, k, :].copy()
+            A[w, k, :] = A[w, p, :]
+            A[w, p, :] = rows_k
+            sign = np.where(swap, -sign, sign)
+        piv = A[:, k, k]
+        sign = sign * np.sign(piv.real)
+        logabs = logabs + 0.5 * np.log(piv * piv)
+        if k + 1 < n:
+            A[:, k + 1:, k] = A[:, k + 1:, k] / piv[:, None]
+            A[:, k + 1:, k + 1:] -= A[:, k + 1:, k, None] * A[:, k, None, k + 1:]
+    return sign, logabs
+
+
+def mo_matrices(system, R, r, C=None):
+    """AOs and MOs (value, gradient, Laplacian) at all electrons.
+
+    r: [W, N, 3].  Returns dict with ao_val [W,N,M], ao_grad [W,N,M,3],
+    ao_lap [W,N,M], phi [W,N,n], gphi [W,N,3,n], lphi [W,N,n].
+    """
+    C = system.C if C is None else C
+    ao_val, ao_grad, ao_lap = gto.eval_aos(system.table, R, r)
+    phi = ao_val @ C
+    gphi = np.einsum("wemk,mi->weki", ao_grad, C)
+    lphi = ao_lap @ C
+    return dict(ao_val=ao_val, ao_grad=ao_grad, ao_lap=ao_lap, phi=phi, gphi=gphi, lphi=lphi)
+
+
+# --------------------------------------------------------------------------
+# Jastrow and potential
+# --------------------------------------------------------------------------
+
+def pade(r, a, F):
+    """u, u', u'' of u(r) = a r / (1 + F r)."""
+    q = 1.0 / (1.0 + F * r)
+    return a * r * q, a * q * q, -2.0 * a * F * q * q * q
+
+
+def _pairs(r):
+    """All ordered pairs: d[w,i,j] = r_i - r_j, r_ij, and the off-diagonal mask.
+
+    The diagonal distance is set to 1 (then masked) so that no sqrt(0) enters
+    the complex-step derivative.
+    """
+    N = r.shape[1]
+    d = r[:, :, None, :] - r[:, None, :, :]
+    eye = np.eye(N)
+    rij = np.sqrt(np.sum(d * d, axis=-1) + eye)
+    return d, rij, 1.0 - eye
+
+
+def jastrow_terms(system, R, r):
+    """J [W], grad_e J [W,N,3], lap_e J [W,N]."""
+    W, N, _ = r.shape
+    dtype = np.result_type(r.dtype, np.asarray(R).dtype)
+    J = np.zeros(W, dtype=dtype)
+    g = np.zeros((W, N, 3), dtype=dtype)
+    h = np.zeros((W, N), dtype=dtype)
+    if N > 1:
+        d, rij, off = _pairs(r)                         # [W,N,N,3], [W,N,N], [N,N]
+        u, u1, u2 = pade(rij, system.a, system.F)
+        J = J + 0.5 * np.sum(u * off, axis=(1, 2))
+        g = g + np.sum((off * u1 / rij)[..., None] * d, axis=2)
+        h = h + np.sum(off * (u2 + 2.0 * u1 / rij), axis=2)
+    if system.en_on:
+        for al in range(system.A):
+            d = r - R[al]                                # [W, N, 3]
+            rr = np.sqrt(np.sum(d * d, axis=-1))
+            u, u1, u2 = pade(rr, -system.Z[al], system.en_b)
+            J = J + u.sum(axis=1)
+            g = g + (u1 / rr)[..., None] * d
+            h = h + u2 + 2.0 * u1 / rr
+    return J, g, h
+
+
+def potential(system, R, r):
+    """V = -sum Z/|r-R| + sum_{i<j} 1/r_ij + sum_{a<b} Z_a Z_b / R_ab  [W]."""
+    W, N, _ = r.shape
+    V = np.zeros(W, dtype=np.result_type(r.dtype, np.asarray(R).dtype))
+    for al in range(system.A):
+        d = r - R[al]
+        V = V - system.Z[al] * np.sum(1.0 / np.sqrt(np.sum(d * d, axis=-1)), axis=1)
+    if N > 1:
+        _, rij, off = _pairs(r)
+        V = V + 0.5 * np.sum(off / rij, axis=(1, 2))
+    for al in range(system.A):
+        for be in range(al + 1, system.A):
+            d = R[al] - R[be]
+            V = V + system.Z[al] * system.Z[be] / np.sqrt(np.sum(d * d))
+    return V
+
+
+# --------------------------------------------------------------------------
+# local energy
+# --------------------------------------------------------------------------
+
+def evaluate(system, R, r, C=None, keep=False):
+    """Per-walker E_L, log|Psi| and sign at nuclei R [A,3], electrons r [W,N,3].
+
+    With keep=True the intermediates needed for derivatives are returned too.
+    """
+    r = np.asarray(r)
+    W, N, _ = r.shape
+    mo = mo_matrices(system, R, r, C)
+    J, g, h = jastrow_terms(system, R, r)
+    dtype = np.result_type(mo["phi"].dtype, J.dtype)
+    b = np.zeros((W, N, 3), dtype=dtype)       # gradD/D at each electron
+    lapD = np.zeros((W, N), dtype=dtype)       # lapD/D at each electron
+    logdet = np.zeros(W, dtype=dtype)
+    sign = np.ones(W)
+    Kinv = []
+    for sl, n in system.spin_blocks():
+        A = mo["phi"][:, sl, :n]                         # [W, e, i]
+        s_, la = lu_logdet(A)
+        sign = sign * s_
+        logdet = logdet + la
+        K = np.linalg.inv(A)                             # K[w, i, e]
+        Kinv.append(K)
+        b[:, sl, :] = np.einsum("wie,weki->wek", K, mo["gphi"][:, sl, :, :n])
+        lapD[:, sl] = np.einsum("wie,wei->we", K, mo["lphi"][:, sl, :n])
+    kin_e = lapD + 2.0 * np.sum(b * g, axis=-1) + h + np.sum(g * g, axis=-1)
+    E_kin = -0.5 * kin_e.sum(axis=1)
+    V = potential(system, R, r)
+    out = dict(E_L=E_kin + V, lnpsi=logdet + J, sign=sign)
+    if keep:
+        out.update(mo)
+        out.update(Kinv=Kinv, b=b, lapD=lapD, g=g, h=h, J=J, V=V)
+    return out

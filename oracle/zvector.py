@@ -1,0 +1,45 @@
+"""Z-vector solve H z = -b (oracle).
+
+The Z-vector equations A Z = -B (eq. AZ_eq_B_elements) are linear in Z with
+the VMC derivative B on the right-hand side.  The orbital Hessian is supplied
+by the caller (the CPKS integrals are outside this path); for a symmetric
+positive definite H the solution is unique.
+
+Two solutions are given: a dense Cholesky solve (library routine) and
+conjugate gradients with the stopping rule of the GPU path,
+||r_k|| <= rtol ||b||, x_0 = 0 (Hestenes & Stiefel, 1952).
+"""
+import numpy as np
+
+
+def cholesky_solve(H, b):
+    L = np.linalg.cholesky(H)
+    y = np.linalg.solve(L, -b)
+    return np.linalg.solve(L.T, y)
+
+
+def cg_solve(H, b, rtol=1e-12, maxit=10000, jacobi=False):
+    """Returns (z, iterations, converged)."""
+    rhs = -np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(rhs)
+    r = rhs.copy()
+    Minv = 1.0 / np.diag(H) if jacobi else np.ones_like(rhs)
+    zr = Minv * r
+    p = zr.copy()
+    rz = float(r @ zr)
+    bn = float(np.linalg.norm(rhs))
+    if bn == 0.0:
+        return x, 0, True
+    for it in range(1, maxit + 1):
+        Hp = H @ p
+        alpha = rz / float(p @ Hp)
+        x += alpha * p
+        r -= alpha * Hp
+        if np.linalg.norm(r) <= rtol * bn:
+            return x, it, True
+        zr = Minv * r
+        rz_new = float(r @ zr)
+        p = zr + (rz_new / rz) * p
+        rz = rz_new
+    return x, maxit, False
+

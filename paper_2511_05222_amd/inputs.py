@@ -1,0 +1,345 @@
+"""Seeded synthetic inputs for the VMC force hot path.
+
+This module only *generates* inputs: geometries, cartesian GTO shell tables,
+molecular-orbital coefficient matrices and walker counts.  It evaluates no
+part of the Monte Carlo method (no orbitals at electron positions, no
+determinants, no Jastrow, no local energy); both the HIP path and the oracle
+consume what it returns, and neither's arithmetic lives here.
+
+The one piece of integral arithmetic here is the AO overlap matrix S, used
+only to make the random MO coefficients orthonormal in the S metric (the
+orthonormality constraint S_kl = delta_kl of the paper's Lagrangian, Sec. II).
+The hot path itself never forms S.
+
+Workload recipe (synthetic stand-ins for the paper's rMD17 molecules, Sec. IV):
+  * geometry: random sequential addition, uniform in a sphere of radius
+    1.74 * A**(1/3) bohr, rejecting any atom closer than 1.8 bohr to another;
+  * basis: cartesian shells, heavy atoms 3s2p1d and H 2s1p, three primitives
+    per shell with exponents log-uniform in [0.1, 50] (sorted descending) and
+    contraction coefficients uniform in [0.2, 1.0];
+  * MO coefficients: X ~ N(0,1)^{M x M}, C = X L^-T with L L^T = X^T S X, the
+    first n columns occupied;
+  * Jastrow: two-body Pade u(r) = a r / (1 + F r), a = 1/2, F = 1.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from functools import lru_cache
+from math import comb, pi, sqrt
+
+import numpy as np
+
+Z_OF = {"H": 1, "C": 6, "O": 8}
+
+# Shell recipe per element: list of angular momenta.
+SHELLS_OF = {
+    "H": [0, 0, 1],
+    "C": [0, 0, 0, 1, 1, 2],
+    "O": [0, 0, 0, 1, 1, 2],
+}
+
+N_CART = {0: 1, 1: 3, 2: 6}
+
+STO3G_H_EXP = (3.42525, 0.62391, 0.16886)
+STO3G_H_COEF = (0.15433, 0.53533, 0.44463)
+
+
+@dataclass
+class Basis:
+    """Cartesian contracted GTO shells.
+
+    shell_atom[s], shell_l[s], shell_nprim[s]; primitives of shell s occupy
+    prim_exp/prim_coef[off[s] : off[s] + shell_nprim[s]].  Coefficients
+    multiply unit-normalised primitives.
+    """
+
+    shell_atom: np.ndarray
+    shell_l: np.ndarray
+    shell_nprim: np.ndarray
+    prim_exp: np.ndarray
+    prim_coef: np.ndarray
+
+    @property
+    def n_shells(self) -> int:
+        return int(self.shell_l.shape[0])
+
+    @property
+    def n_ao(self) -> int:
+        return int(sum(N_CART[int(l)] for l in self.shell_l))
+
+    @property
+    def n_prim(self) -> int:
+        return int(self.prim_exp.shape[0])
+
+    def prim_offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.shell_nprim)[:-1]]).astype(np.int64)
+
+
+@dataclass
+class Jastrow:
+    ee_a: float = 0.5
+    ee_F: float = 1.0
+    en_on: int = 0
+    en_b: float = 0.0
+
+
+@dataclass
+class Molecule:
+    name: str
+    symbols: list
+    xyz: np.ndarray          # [A][3] bohr
+    Z: np.ndarray            # [A]
+    basis: Basis
+    C_full: np.ndarray       # [M][M]; first n_occ columns occupied
+    n_up: int
+    n_dn: int
+    jastrow: Jastrow = field(default_factory=Jastrow)
+
+    @property
+    def n_elec(self) -> int:
+        return self.n_up + self.n_dn
+
+    @property
+    def n_occ(self) -> int:
+        return max(self.n_up, self.n_dn)
+
+    @property
+    def C(self) -> np.ndarray:
+        return np.ascontiguousarray(self.C_full[:, : self.n_occ])
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.Z.shape[0])
+
+
+# ----------------------------------------------------------------------------
+# AO overlap (input preparation only)
+# ----------------------------------------------------------------------------
+
+def _cart_components(l):
+    if l == 0:
+        return [(0, 0, 0)]
+    if l == 1:
+        return [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    return [(2, 0, 0), (1, 1, 0), (1, 0, 1), (0, 2, 0), (0, 1, 1), (0, 0, 2)]
+
+
+def _dfact(n):
+    r = 1
+    while n > 1:
+        r *= n
+        n -= 2
+    return r
+
+
+def _gauss_moment(m, p):
+    """integral of t^m exp(-p t^2) over the real line."""
+    if m % 2:
+        return 0.0
+    k = m // 2
+    return _dfact(2 * k - 1) / (2.0 * p) ** k * sqrt(pi / p)
+
+
+def _overlap_1d(a, b, A, B, alpha, beta):
+    p = alpha + beta
+    P = (alpha * A + beta * B) / p
+    pre = np.exp(-alpha * beta / p * (A - B) ** 2)
+    s = 0.0
+    for i in range(a + 1):
+        for j in range(b + 1):
+            s += comb(a, i) * comb(b, j) * (P - A) ** (a - i) * (P - B) ** (b - j) * _gauss_moment(i + j, p)
+    return pre * s
+
+
+def _prim_norm(alpha, comp):
+    a, b, c = comp
+    l = a + b + c
+    return sqrt((2 * alpha / pi) ** 1.5 * (4 * alpha) ** l / (_dfact(2 * a - 1) * _dfact(2 * b - 1) * _dfact(2 * c - 1)))
+
+
+def overlap_matrix(xyz: np.ndarray, basis: Basis) -> np.ndarray:
+    """AO overlap for cartesian components renormalised to unit self-overlap."""
+    off = basis.prim_offsets()
+    aos = []  # (centre, comp, exps, coefs)
+    for s in range(basis.n_shells):
+        l = int(basis.shell_l[s])
+        sl = slice(off[s], off[s] + basis.shell_nprim[s])
+        for comp in _cart_components(l):
+            aos.append((xyz[basis.shell_atom[s]], comp, basis.prim_exp[sl], basis.prim_coef[sl]))
+    M = len(aos)
+    raw = np.zeros((M, M))
+    for m in range(M):
+        Am, cm, em, km = aos[m]
+        for n in range(m, M):
+            Bn, cn, en, kn = aos[n]
+            v = 0.0
+            for a1, c1 in zip(em, km):
+                n1 = _prim_norm(a1, cm)
+                for a2, c2 in zip(en, kn):
+                    n2 = _prim_norm(a2, cn)
+                    v += c1 * c2 * n1 * n2 * (
+                        _overlap_1d(cm[0], cn[0], Am[0], Bn[0], a1, a2)
+                        * _overlap_1d(cm[1], cn[1], Am[1], Bn[1], a1, a2)
+                        * _overlap_1d(cm[2], cn[2], Am[2], Bn[2], a1, a2)
+                    )
+            raw[m, n] = raw[n, m] = v
+    d = 1.0 / np.sqrt(np.diag(raw))
+    return raw * d[:, None] * d[None, :]
+
+
+# ----------------------------------------------------------------------------
+# Generators
+# ----------------------------------------------------------------------------
+
+def random_geometry(symbols, seed, min_dist=1.8, density_radius=1.74):
+    """Random sequential addition in a sphere of radius 1.74 A^(1/3) bohr."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = len(symbols)
+    Rs = density_radius * A ** (1.0 / 3.0)
+    pts = []
+    while len(pts) < A:
+        p = rng.uniform(-Rs, Rs, size=3)
+        if np.dot(p, p) > Rs * Rs:
+            continue
+        if all(np.linalg.norm(p - q) >= min_dist for q in pts):
+            pts.append(p)
+    return np.array(pts, dtype=np.float64)
+
+
+def random_basis(symbols, seed, nprim=3, exp_lo=0.1, exp_hi=50.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sa, sl, sn, pe, pc = [], [], [], [], []
+    for a, sym in enumerate(symbols):
+        for l in SHELLS_OF[sym]:
+            e = np.exp(rng.uniform(np.log(exp_lo), np.log(exp_hi), size=nprim))
+            e = np.sort(e)[::-1]
+            c = rng.uniform(0.2, 1.0, size=nprim)
+            sa.append(a)
+            sl.append(l)
+            sn.append(nprim)
+            pe.extend(e)
+            pc.extend(c)
+    return Basis(np.array(sa, np.int32), np.array(sl, np.int32), np.array(sn, np.int32),
+                 np.array(pe, np.float64), np.array(pc, np.float64))
+
+
+def s_orthonormal_coefficients(S, seed):
+    """C = X L^-T with L L^T = X^T S X, so that C^T S C = I."""
+    M = S.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = rng.standard_normal((M, M))
+    L = np.linalg.cholesky(X.T @ S @ X)
+    return np.linalg.solve(L, X.T).T
+
+
+def composition(n_atoms):
+    """Heavy/H counts for a molecule of n_atoms in the 9-21 atom family."""
+    n_c = int(round(2 + 7 * (n_atoms - 9) / 12))
+    n_o = int(round(1 + 3 * (n_atoms - 9) / 12))
+    n_h = n_atoms - n_c - n_o
+    if n_h % 2:
+        n_h -= 1
+        n_c += 1
+    return ["C"] * n_c + ["O"] * n_o + ["H"] * n_h
+
+
+def make_molecule(symbols, geom_seed, basis_seed, c_seed, name="molecule"):
+    xyz = random_geometry(symbols, geom_seed)
+    Z = np.array([Z_OF[s] for s in symbols], dtype=np.float64)
+    basis = random_basis(symbols, basis_seed)
+    S = overlap_matrix(xyz, basis)
+    C_full = s_orthonormal_coefficients(S, c_seed)
+    n_el = int(Z.sum())
+    assert n_el % 2 == 0
+    return Molecule(name, list(symbols), xyz, Z, basis, C_full, n_el // 2, n_el // 2)
+
+
+def make_h2(R=1.4, jastrow=None):
+    """H2 with one STO-3G s shell per atom and the bonding MO (1,1)/norm."""
+    xyz = np.array([[0.0, 0.0, 0.0], [R, 0.0, 0.0]])
+    basis = Basis(np.array([0, 1], np.int32), np.array([0, 0], np.int32), np.array([3, 3], np.int32),
+                  np.array(STO3G_H_EXP * 2, np.float64), np.array(STO3G_H_COEF * 2, np.float64))
+    S = overlap_matrix(xyz, basis)
+    s12 = S[0, 1]
+    C_full = np.array([[1.0, 1.0], [1.0, -1.0]])
+    C_full[:, 0] /= sqrt(2 + 2 * s12)
+    C_full[:, 1] /= sqrt(2 - 2 * s12)
+    return Molecule("H2", ["H", "H"], xyz, np.array([1.0, 1.0]), basis, C_full, 1, 1,
+                    jastrow if jastrow is not None else Jastrow())
+
+
+@dataclass
+class RunSpec:
+    """One benchmark/parity workload."""
+
+    molecule: Molecule
+    n_walkers: int
+    n_sweeps: int
+    seed: int
+    step_sigma: float = 0.5
+    precision: str = "fp64"
+
+
+@lru_cache(maxsize=None)
+def make_config(i: int) -> RunSpec:
+    """The five workloads: 0 = H2, 1 = 9 atoms, 2 = 21 atoms, 3 = 21 atoms
+    (differentiation, 256 walkers), 4 = first of the mixed-size family.
+
+    Results are cached; callers must not modify the returned arrays."""
+    if i == 0:
+        return RunSpec(make_h2(), 1024, 200, 0)
+    if i == 1:
+        mol = make_molecule(composition(9), 1, 11, 101, "9-atom C2OH6")
+        return RunSpec(mol, 16384, 100, 1)
+    if i == 2:
+        mol = make_molecule(composition(21), 2, 12, 102, "21-atom C9O4H8")
+        return RunSpec(mol, 65536, 10, 2, precision="mixed")
+    if i == 3:
+        mol = make_molecule(composition(21), 2, 12, 102, "21-atom C9O4H8")
+        return RunSpec(mol, 256, 50, 3)
+    if i == 4:
+        rng = np.random.Generator(np.random.PCG64(4))
+        A = int(rng.integers(9, 22))
+        mol = make_molecule(composition(A), 1000, 2000, 3000, f"{A}-atom mixed-family g0")
+        return RunSpec(mol, 8192, 10, 4, precision="mixed")
+    raise ValueError(i)
+
+
+def init_atom_of_electron(Z, n_up, n_dn):
+    """Atom index each electron starts at.
+
+    Atoms in input order each contribute Z electrons to a list; list entries
+    alternate spin up/down.  Electron e < n_up is the e-th up entry, electron
+    n_up + j the j-th down entry.
+    """
+    lst = []
+    for a, z in enumerate(Z):
+        lst.extend([a] * int(round(z)))
+    ups = lst[0::2]
+    dns = lst[1::2]
+    # polarised systems: surplus entries go to the majority spin
+    while len(ups) < n_up and dns:
+        ups.append(dns.pop())
+    while len(dns) < n_dn and ups:
+        dns.append(ups.pop())
+    out = np.array(ups[:n_up] + dns[:n_dn], dtype=np.int32)
+    assert out.shape[0] == n_up + n_dn
+    return out
+
+
+def initial_walkers(mol: Molecule, n_walkers: int, seed: int, sigma: float = 0.5) -> np.ndarray:
+    """Start positions [W][N][3]: each electron at its atom plus N(0, sigma^2)
+    per cartesian component (numpy PCG64, seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    atom = init_atom_of_electron(mol.Z, mol.n_up, mol.n_dn)
+    base = mol.xyz[atom]                                   # [N][3]
+    return base[None, :, :] + sigma * rng.standard_normal((n_walkers, mol.n_elec, 3))
+
+
+def seeded_spd(dim: int, seed: int, rank: int = 64) -> np.ndarray:
+    """Synthetic orbital Hessian H = diag(d) + G G^T / rank (SPD), with d
+    log-uniform in [0.5, 5] and G ~ N(0,1)^{dim x rank}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = np.exp(rng.uniform(np.log(0.5), np.log(5.0), size=dim))
+    G = rng.standard_normal((dim, rank))
+    return np.diag(d) + G @ G.T / rank

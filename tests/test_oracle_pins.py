@@ -1,0 +1,327 @@
+"""Pins of the FP64 oracle against closed forms, invariants and finite
+differences (no GPU).  Each test names the fact it relies on."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2511_05222_amd import inputs
+from oracle import derivatives as dv
+from oracle import estimators, gto, h2_closed_form, philox, sampler, vmc, zvector
+from oracle import wavefunction as wf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def h_atom(alpha=1e-14):
+    b = inputs.Basis(np.array([0], np.int32), np.array([0], np.int32), np.array([1], np.int32),
+                     np.array([alpha]), np.array([1.0]))
+    return inputs.Molecule("H", ["H"], np.zeros((1, 3)), np.array([1.0]), b, np.ones((1, 1)), 1, 0,
+                           inputs.Jastrow(0.0, 1.0, 1, 0.0))
+
+
+@pytest.fixture(scope="module")
+def mol9():
+    return inputs.make_config(1).molecule
+
+
+# --------------------------------------------------------------------------
+# P1: hydrogen atom, psi = exp(-r): E_L = -1/2 for every configuration.
+# With the cusp factor exp(-Z r) and one s Gaussian of exponent alpha the exact
+# local energy is -1/2 + 3 alpha - 2 alpha r - 2 alpha^2 r^2.
+# --------------------------------------------------------------------------
+def test_h_atom_local_energy_is_exact():
+    s = wf.System(h_atom())
+    r = np.random.default_rng(0).standard_normal((64, 1, 3)) * 3.0
+    out = wf.evaluate(s, s.xyz, r)
+    rr = np.linalg.norm(r[:, 0], axis=-1)
+    a = 1e-14
+    expect = -0.5 + 3 * a - 2 * a * rr - 2 * a * a * rr ** 2
+    assert np.max(np.abs(out["E_L"] - expect)) < 1e-12
+
+
+# P14: sampling |psi|^2 = exp(-2r)/pi: <r> = 3/2, <r^2> = 3 bohr^2.
+def test_h_atom_sampling_moments():
+    mol = h_atom()
+    s = wf.System(mol)
+    w = inputs.initial_walkers(mol, 4096, 5)
+    ch, _ = sampler.run(s, w, 40, 5, mode="sm")
+    rs = []
+    for t in range(40, 100):
+        ch.sweep(5, t)
+        rs.append(np.linalg.norm(ch.r[:, 0], axis=-1))
+    rs = np.array(rs)                         # [sweeps, walkers]
+    blocks_r = rs.reshape(6, -1).mean(axis=1)
+    blocks_r2 = (rs ** 2).reshape(6, -1).mean(axis=1)
+    m, sm = blocks_r.mean(), blocks_r.std(ddof=1) / np.sqrt(6)
+    m2, sm2 = blocks_r2.mean(), blocks_r2.std(ddof=1) / np.sqrt(6)
+    assert abs(m - 1.5) < 4 * sm + 1e-3
+    assert abs(m2 - 3.0) < 4 * sm2 + 3e-3
+
+
+# --------------------------------------------------------------------------
+# P2: H2 without Jastrow samples the RHF determinant; <E_L> is the closed-form
+# RHF energy and the bare SWCT force is -dE/dR (fixed seed, blocked error bars).
+# --------------------------------------------------------------------------
+def test_h2_closed_form_matches_textbook():
+    vals = dict(l.split() for l in open(os.path.join(GOLDEN, "h2_sto3g_rhf.txt")) if not l.startswith("#"))
+    e = h2_closed_form.rhf_energy(float(vals["R"]), inputs.STO3G_H_EXP, inputs.STO3G_H_COEF)
+    assert abs(e - float(vals["energy"])) < 1e-4
+
+
+def test_h2_vmc_energy_and_force():
+    mol = inputs.make_h2(jastrow=inputs.Jastrow(0.0, 1.0))
+    w = inputs.initial_walkers(mol, 1024, 0)
+    res = vmc.run(mol, w, 200, 0, block_sweeps=10, n_burn=50)
+    E_ref = h2_closed_form.rhf_energy(1.4, inputs.STO3G_H_EXP, inputs.STO3G_H_COEF)
+    F_ref = h2_closed_form.rhf_force(1.4, inputs.STO3G_H_EXP, inputs.STO3G_H_COEF)
+    assert abs(res["E"] - E_ref) < 3 * res["E_sigma"]
+    assert abs(res["F_bare"][1, 0] - F_ref) < 4 * res["F_sigma"][1, 0]
+    assert abs(res["F_bare"][0, 0] + F_ref) < 4 * res["F_sigma"][0, 0]
+    # P3: by the symmetry of the bonding MO, B_1 = -B_2 for every sample set
+    assert abs(res["dE_dC"][0, 0] + res["dE_dC"][1, 0]) < 1e-12 * np.abs(res["dE_dC"]).max() + 1e-15
+
+
+# --------------------------------------------------------------------------
+# P4: E_L and ln|Psi| depend on C only through span(C):
+#   C^T O = (number of spins) I per walker (constant) => C^T dE/dC = 0 per sample set;
+#   E_L(C M) = E_L(C)  => C^T dE_L/dC = 0 per walker.
+# P5: sum_alpha omega_alpha = 1 and translation invariance => sum_alpha F_alpha = 0.
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def run9(mol9):
+    w = inputs.initial_walkers(mol9, 32, 1)
+    return vmc.run(mol9, w, 3, 1, keep_samples=True)
+
+
+def test_invariants_9atom(run9, mol9):
+    C = mol9.C
+    n = C.shape[1]
+    for smp in run9["samples"]:
+        CtO = np.einsum("mj,wmi->wji", C, smp["O"])
+        assert np.allclose(CtO, 2 * np.eye(n)[None], atol=1e-9)
+        CtG = np.einsum("mj,wmi->wji", C, smp["G"])
+        assert np.abs(CtG).max() < 1e-10 * np.abs(smp["G"]).max()
+        assert np.abs(smp["H"].sum(axis=1)).max() < 1e-10 * np.abs(smp["H"]).max()
+        assert np.abs(smp["P"].sum(axis=1)).max() < 1e-10 * np.abs(smp["P"]).max() + 1e-12
+    assert np.abs(C.T @ run9["dE_dC"]).max() < 1e-9 * np.abs(run9["dE_dC"]).max()
+    assert np.abs(run9["F_bare"].sum(axis=0)).max() < 1e-9 * np.abs(run9["F_bare"]).max()
+
+
+# --------------------------------------------------------------------------
+# P6 / P7: the estimators are exact derivatives of a fixed-sample reweighted
+# energy.  E_hat(C, R) = sum_k w_k E_L,k / sum_k w_k with
+# w_k = exp(2 (ln|Psi_k(C,R)| - ln|Psi_k(C0,R0)|)) * Jac_k(R) (warped electrons).
+# Central differences (h = 1e-4) must match -F_bare and dE_dC + <dE_L/dC>.
+# --------------------------------------------------------------------------
+def _ehat(system, R, R0, r, lnpsi0, C=None):
+    E, lp, lj = dv.warped_values(system, R, R0, r, C)
+    w = np.exp(2.0 * (lp - lnpsi0) + lj)
+    return float(np.sum(w * E) / np.sum(w))
+
+
+def test_estimators_are_fixed_sample_derivatives(mol9):
+    s = wf.System(mol9)
+    w = inputs.initial_walkers(mol9, 16, 3)
+    ch, _ = sampler.run(s, w, 4, 3)
+    r = ch.r
+    R0 = s.xyz
+    m = dv.measure(s, R0, r)
+    acc = estimators.Accumulator(s.A, s.M, s.C.shape[1])
+    acc.add(m)
+    res = acc.result()
+    lnpsi0 = m["lnpsi"]
+    h = 1e-4
+    for al, k in [(0, 0), (2, 1), (5, 2), (8, 0)]:
+        Rp = R0.copy(); Rp[al, k] += h
+        Rm = R0.copy(); Rm[al, k] -= h
+        fd = (_ehat(s, Rp, R0, r, lnpsi0) - _ehat(s, Rm, R0, r, lnpsi0)) / (2 * h)
+        assert abs(fd + res["F_bare"][al, k]) < 1e-6 * max(1.0, abs(fd)), (al, k, fd, res["F_bare"][al, k])
+    rng = np.random.default_rng(7)
+    for _ in range(4):
+        mu, i = int(rng.integers(s.M)), int(rng.integers(s.C.shape[1]))
+        Cp = s.C.copy(); Cp[mu, i] += h
+        Cm = s.C.copy(); Cm[mu, i] -= h
+        fd = (_ehat(s, R0, R0, r, lnpsi0, Cp) - _ehat(s, R0, R0, r, lnpsi0, Cm)) / (2 * h)
+        an = res["dE_dC"][mu, i] + res["dEL_dC_mean"][mu, i]
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(fd)), (mu, i, fd, an)
+
+
+# P8: per-walker derivatives: complex step vs central differences; matrix
+# calculus dE_L/dC vs complex step along random directions.
+def test_per_walker_derivatives(mol9):
+    s = wf.System(mol9)
+    r = inputs.initial_walkers(mol9, 4, 9)
+    R0 = s.xyz
+    dE, dP, dJ = dv.nuclear_derivatives(s, R0, R0, r)
+    h = 1e-5
+    for al, k in [(1, 0), (4, 2)]:
+        Rp = R0.copy(); Rp[al, k] += h
+        Rm = R0.copy(); Rm[al, k] -= h
+        ep, pp, _ = dv.warped_values(s, Rp, R0, r)
+        em, pm, _ = dv.warped_values(s, Rm, R0, r)
+        assert np.allclose((ep - em) / (2 * h), dE[:, al, k], rtol=1e-5, atol=1e-5 * np.abs(dE).max())
+        assert np.allclose((pp - pm) / (2 * h), dP[:, al, k], rtol=1e-6, atol=1e-7)
+    O, G, _ = dv.coefficient_derivatives(s, R0, r)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        V = rng.standard_normal(s.C.shape)
+        ev = wf.evaluate(s, R0, r, s.C + 1e-30j * V)
+        assert np.allclose(ev["E_L"].imag / 1e-30, np.einsum("wmi,mi->w", G, V), rtol=1e-9, atol=1e-8)
+        assert np.allclose(ev["lnpsi"].imag / 1e-30, np.einsum("wmi,mi->w", O, V), rtol=1e-11, atol=1e-10)
+
+
+# P9: antisymmetry of the determinant.
+def test_same_spin_swap_flips_sign(mol9):
+    s = wf.System(mol9)
+    r = inputs.initial_walkers(mol9, 8, 11)
+    a = wf.evaluate(s, s.xyz, r)
+    r2 = r.copy()
+    r2[:, [2, 5]] = r2[:, [5, 2]]          # both spin up
+    b = wf.evaluate(s, s.xyz, r2)
+    assert np.array_equal(a["sign"], -b["sign"])
+    assert np.allclose(a["lnpsi"], b["lnpsi"], rtol=0, atol=1e-11)
+    assert np.allclose(a["E_L"], b["E_L"], rtol=1e-11, atol=1e-10)
+    r3 = r.copy()
+    up, dn = 1, s.n_up + 1
+    r3[:, [up, dn]] = r3[:, [dn, up]]
+    r3b = r3.copy()
+    r3b[:, [up, dn]] = r3b[:, [dn, up]]
+    assert np.allclose(wf.evaluate(s, s.xyz, r3b)["E_L"], a["E_L"], rtol=0, atol=0)
+
+
+# P10: lap Psi / Psi = lap ln|Psi| + |grad ln|Psi||^2.  grad ln|Psi| is checked
+# against the complex-step derivative of ln|Psi|, and lap ln|Psi| is the
+# complex-step divergence of that gradient; together they give the kinetic
+# energy independently of the determinant-Laplacian formula.
+def test_kinetic_identity(mol9):
+    s = wf.System(mol9)
+    r = inputs.initial_walkers(mol9, 3, 13)
+    ev = wf.evaluate(s, s.xyz, r, keep=True)
+    kin = ev["E_L"] - ev["V"]
+    grad = ev["b"] + ev["g"]                                   # [W,N,3]
+    hcs = 1e-30
+    lap = np.zeros(r.shape[0])
+    for e in range(s.N):
+        for k in range(3):
+            rc = r.astype(complex)
+            rc[:, e, k] += 1j * hcs
+            evc = wf.evaluate(s, s.xyz, rc, keep=True)
+            assert np.allclose(evc["lnpsi"].imag / hcs, grad[:, e, k], rtol=1e-10, atol=1e-10)
+            lap += (evc["b"] + evc["g"])[:, e, k].imag / hcs
+    tot = lap + np.sum(grad * grad, axis=(1, 2))
+    assert np.allclose(-0.5 * tot, kin, rtol=1e-10, atol=1e-10 * np.abs(kin).max())
+
+
+# P11: every cartesian AO has unit norm (spherical product quadrature of the
+# oracle's own values); gradient and Laplacian equal complex-step derivatives.
+def test_ao_normalisation_and_derivatives(mol9):
+    tab = gto.ShellTable(mol9.basis)
+    R = np.array(mol9.xyz)
+    # quadrature around atom 0 (heavy: s, p, d shells) and atom 8 (H)
+    xg, wg = np.polynomial.legendre.leggauss(64)
+    edges = [0, 0.05, 0.2, 0.6, 1.5, 3.5, 7.0, 14.0]
+    rq, wr = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        rq.append(0.5 * (b - a) * xg + 0.5 * (b + a))
+        wr.append(0.5 * (b - a) * wg)
+    rq, wr = np.concatenate(rq), np.concatenate(wr)
+    ct, wt = np.polynomial.legendre.leggauss(12)
+    ph = np.arange(24) * 2 * np.pi / 24
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([np.outer(st, np.cos(ph)), np.outer(st, np.sin(ph)), np.outer(ct, np.ones_like(ph))], -1).reshape(-1, 3)
+    wdir = np.outer(wt, np.full_like(ph, 2 * np.pi / 24)).ravel()
+    for atom in (0, 8):
+        pts = R[atom] + rq[:, None, None] * dirs[None, :, :]          # [nr, nd, 3]
+        wts = (wr * rq ** 2)[:, None] * wdir[None, :]
+        val, _, _ = gto.eval_aos(tab, R, pts.reshape(1, -1, 3))
+        val = val.reshape(len(rq), len(dirs), -1)
+        mine = tab.ao_atom == atom
+        norms = np.einsum("rd,rdm->m", wts, val[..., mine] ** 2)
+        assert np.allclose(norms, 1.0, atol=1e-9), norms
+    r = inputs.initial_walkers(mol9, 2, 17).reshape(1, -1, 3)
+    val, grad, lap = gto.eval_aos(tab, R, r)
+    hcs = 1e-30
+    lap_cs = np.zeros_like(lap)
+    for k in range(3):
+        rc = r.astype(complex); rc[..., k] += 1j * hcs
+        v2, g2, _ = gto.eval_aos(tab, R, rc)
+        assert np.allclose(v2.imag / hcs, grad[..., k], rtol=1e-12, atol=1e-12)
+        lap_cs += g2[..., k].imag / hcs
+    assert np.allclose(lap_cs, lap, rtol=1e-11, atol=1e-10)
+
+
+# The input MO coefficients are orthonormal in the overlap metric given by the
+# oracle's AOs (H2: the bonding MO has unit norm by quadrature).
+def test_h2_bonding_mo_norm():
+    mol = inputs.make_h2()
+    tab = gto.ShellTable(mol.basis)
+    xg, wg = np.polynomial.legendre.leggauss(80)
+    lim = 9.0
+    xs = lim * xg
+    ws = lim * wg
+    X = np.stack(np.meshgrid(xs + 0.7, xs, xs, indexing="ij"), -1)
+    W3 = ws[:, None, None] * ws[None, :, None] * ws[None, None, :]
+    val, _, _ = gto.eval_aos(tab, mol.xyz, X.reshape(1, -1, 3))
+    phi = (val @ mol.C)[0, :, 0].reshape(X.shape[:3])
+    assert abs(np.sum(W3 * phi ** 2) - 1.0) < 1e-6
+
+
+# P12: Sherman-Morrison ratios reproduce fresh-LU ratios: identical accept
+# sequences and identical positions in both modes.
+def test_sm_matches_exact_mode(mol9):
+    s = wf.System(mol9)
+    w = inputs.initial_walkers(mol9, 16, 21)
+    ch1, b1 = sampler.run(s, w, 3, 21, mode="exact")
+    ch2, b2 = sampler.run(s, w, 3, 21, mode="sm", refresh_period=1000)
+    assert np.array_equal(b1, b2)
+    assert np.array_equal(ch1.r, ch2.r)
+    K = ch2.K
+    phi = ch2.orbitals_at(ch2.r, s.C.shape[1])
+    for (sl, n), Kb in zip(s.spin_blocks(), K):
+        I = np.einsum("wie,wej->wij", Kb, phi[:, sl, :n])
+        assert np.abs(I - np.eye(n)).max() < 1e-10
+
+
+# P13: RNG: Box-Muller normals have N(0,1) moments; uniforms U[0,1).
+def test_rng_moments():
+    z = philox.move_normals(123, np.arange(400000), 7, 3).ravel()
+    n = z.size
+    assert abs(z.mean()) < 5 / np.sqrt(n)
+    assert abs(z.var() - 1) < 5 * np.sqrt(2 / n)
+    assert abs(np.mean(z ** 4) - 3) < 5 * np.sqrt(96 / n)
+    u = philox.move_uniform(123, np.arange(400000), 7, 3)
+    assert u.min() >= 0 and u.max() < 1
+    assert abs(u.mean() - 0.5) < 5 * np.sqrt(1 / 12 / u.size)
+    # distinct counters give distinct streams
+    a = philox.move_uniform(1, np.arange(1000), 0, 0)
+    b = philox.move_uniform(1, np.arange(1000), 0, 1)
+    c = philox.move_uniform(1, np.arange(1000), 1, 0)
+    assert not np.any(a == b) and not np.any(a == c)
+
+
+# P15: CG against the Cholesky solution of the same SPD system.
+def test_zvector_cg():
+    H = inputs.seeded_spd(300, 5)
+    b = np.random.default_rng(5).standard_normal(300)
+    z_ref = zvector.cholesky_solve(H, b)
+    z, it, ok = zvector.cg_solve(H, b, rtol=1e-12)
+    assert ok
+    assert np.linalg.norm(H @ z + b) <= 1e-12 * np.linalg.norm(b) * 1.0001
+    assert np.allclose(z, z_ref, rtol=1e-10, atol=1e-10 * np.abs(z_ref).max())
+    _, it1, ok1 = zvector.cg_solve(H, b, rtol=1e-12, maxit=1)
+    assert not ok1 and it1 == 1
+
+
+# P16: chains depend only on (seed, walker id, sweep index): splitting a run,
+# or running a subset of walkers, gives bitwise identical positions.
+def test_resume_and_subsets(mol9):
+    s = wf.System(mol9)
+    w = inputs.initial_walkers(mol9, 8, 2)
+    ch, bits = sampler.run(s, w, 4, 9)
+    ch_a, bits_a = sampler.run(s, w, 2, 9)
+    ch_b, bits_b = sampler.run(s, ch_a.r, 2, 9, sweep_offset=2)
+    assert np.array_equal(ch.r, ch_b.r)
+    assert np.array_equal(bits, np.concatenate([bits_a, bits_b]))
+    ch_s, bits_s = sampler.run(s, w[3:6], 4, 9, walker_ids=np.arange(3, 6))
+    assert np.array_equal(ch_s.r, ch.r[3:6])
