@@ -1,0 +1,254 @@
+/*
+ * vmc.h -- C ABI of the MI355X VMC force hot path.
+ *
+ * The library evaluates, for a Jastrow-correlated Slater determinant in a
+ * cartesian Gaussian-type-orbital basis (Nakano, Battaglia, Hutter,
+ * arXiv:2511.05222, Appendix A "Wavefunction Ansatz"), the quantities whose
+ * Monte Carlo averages give
+ *   E      = <E_L>                               (Appendix A, eq. eval-observable)
+ *   F_bare = Hellmann-Feynman + Pulay force with the space-warp transformation
+ *            (Appendix A, "Computing derivatives"; Sec. I, eqs. hf and pulay)
+ *   dE/dC  = 2 (<E_L O> - <E_L><O>),  O = d ln|Psi| / dC
+ *            (eq. fc-vmc-eval; B = dE/dC is the right-hand side of the
+ *            Z-vector equations, eq. AZ_eq_B_elements)
+ * and, optionally, solves H z = -b for a caller-supplied SPD orbital Hessian
+ * (Z-vector equations, Sec. II).
+ *
+ * Conventions
+ *   - All floating point arguments are IEEE double.  Lengths in bohr, energies
+ *     in hartree, forces in hartree/bohr.
+ *   - "host" pointers are read during the call only; "device" pointers are
+ *     device memory of the context's GPU, owned by the caller, and must stay
+ *     valid until the work queued on `stream` has completed.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call queues
+ *     its kernels on that stream and returns without synchronising, except
+ *     vmc_accumulate and zvector_solve, which synchronise the stream.
+ *   - Every function returns VMC_OK (0) or a negative status; none aborts,
+ *     throws or prints.  vmc_last_error(ctx) gives a human-readable detail.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Wavefunction (Appendix A):
+ *   psi_mu(r) = eta(a,b,c) x^a y^b z^c sum_k c'_k exp(-alpha_k |r-R_A|^2),
+ *     cartesian components, order s; x,y,z; xx,xy,xz,yy,yz,zz; contraction
+ *     coefficients multiply unit-normalised primitives and each cartesian
+ *     component is renormalised to unit norm (the library folds all norms).
+ *   phi_i = sum_mu C[mu][i] psi_mu                  (eq. restricted-C)
+ *   Psi   = det[phi_i(r_e)]_up * det[phi_i(r_e)]_dn * exp(sum_{i<j} u(r_ij)),
+ *           u(r) = a r / (1 + F r)                  (eqs. twobody_jastrow, twobody_v)
+ *   electrons 0..n_up-1 are spin up, n_up..N-1 spin down.
+ */
+#ifndef VMC_H
+#define VMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define VMC_OK           0
+#define VMC_EINVAL      -1   /* invalid argument or unsupported size            */
+#define VMC_ENOMEM      -2   /* device or host allocation failed                */
+#define VMC_EDEVICE     -3   /* HIP runtime error                               */
+#define VMC_ESINGULAR   -4   /* a Slater matrix had a zero pivot                */
+#define VMC_ENOTCONV    -5   /* iterative solver hit maxit                      */
+#define VMC_ENONFINITE  -6   /* non-finite value in an input or a result        */
+
+/* ---- precision modes ------------------------------------------------------ */
+#define VMC_FP64   0         /* every step in FP64                              */
+
+/* ---- flags ---------------------------------------------------------------- */
+#define VMC_SWEEP_MEASURE   1u   /* measure + accumulate after every sweep      */
+#define VMC_ACCUM_RESET     1u   /* clear the accumulators after reading them   */
+
+/* ---- limits (compile-time sizes of the kernels) --------------------------- */
+#define VMC_MAX_OCC      64      /* max orbitals per spin                        */
+#define VMC_MAX_ELEC    128      /* max electrons                                */
+#define VMC_MAX_AO     1024      /* max atomic orbitals                          */
+#define VMC_MAX_ATOMS    64      /* max nuclei                                   */
+#define VMC_MAX_L         2      /* max shell angular momentum (d)               */
+
+typedef struct vmc_ctx vmc_ctx;
+
+/* Basis set (host arrays, all of length n_shells unless noted).
+ * shell_atom[s] : index of the nucleus the shell sits on
+ * shell_l[s]    : angular momentum, 0..VMC_MAX_L
+ * shell_nprim[s]: primitives of shell s; they occupy prim_exp/prim_coef
+ *                 [sum_{t<s} shell_nprim[t], ... + shell_nprim[s])
+ * prim_exp      : exponents alpha_k > 0 (length sum shell_nprim)
+ * prim_coef     : contraction coefficients of unit-normalised primitives     */
+typedef struct {
+    int32_t n_shells;
+    const int32_t *shell_atom;
+    const int32_t *shell_l;
+    const int32_t *shell_nprim;
+    const double  *prim_exp;
+    const double  *prim_coef;
+} vmc_basis;
+
+/* Nuclei (host): xyz[A][3] bohr, Z[A] charges. */
+typedef struct {
+    int32_t n_atoms;
+    const double *xyz;
+    const double *Z;
+} vmc_nuclei;
+
+/* Occupied MO coefficients (host): C[n_ao][n_occ] row-major, restricted
+ * (both spins use the same C).  n_up == n_dn == n_occ is required.          */
+typedef struct {
+    int32_t n_ao;
+    int32_t n_occ;
+    int32_t n_up;
+    int32_t n_dn;
+    const double *C;
+} vmc_mo;
+
+/* Two-body Pade Jastrow u(r) = ee_a r / (1 + ee_F r), spin independent. */
+typedef struct {
+    double ee_a;
+    double ee_F;
+} vmc_jastrow;
+
+/* Run options.
+ * precision      : VMC_FP64
+ * refresh_period : the Slater inverse is recomputed from scratch after every
+ *                  refresh_period-th proposed move (counted per walker over
+ *                  the global move index sweep*N + e) and at every sweep start;
+ *                  Sherman-Morrison updates in between
+ * block_sweeps   : sweeps per block of the blocked energy error bar
+ * max_walkers    : largest n_walkers any call on this context will pass
+ * staging_walkers: walkers measured per launch (per-walker staging buffers);
+ *                  0 = as many as fit in 2 GiB of staging
+ * step_sigma     : proposal r' = r + step_sigma * N(0, I_3)                   */
+typedef struct {
+    int32_t precision;
+    int32_t refresh_period;
+    int32_t block_sweeps;
+    int32_t max_walkers;
+    int32_t staging_walkers;
+    double  step_sigma;
+} vmc_options;
+
+/* Per-walker outputs of one measurement (device arrays, any may be NULL).
+ * EL[W], lnpsi[W] (ln|Psi|), lnjac[W] (ln of the warp Jacobian),
+ * dEL_dR[W][A][3], dlnpsi_dR[W][A][3], dlnjac_dR[W][A][3]: derivatives with
+ *   respect to the nuclei of E_L, ln|Psi| and ln Jac of the warped
+ *   configuration (space-warp transformation, Appendix A, kappa = d^-4);
+ * O[W][n_ao][n_occ] = d ln|Psi| / dC, G[W][n_ao][n_occ] = d E_L / dC.        */
+typedef struct {
+    double *EL;
+    double *lnpsi;
+    double *lnjac;
+    double *dEL_dR;
+    double *dlnpsi_dR;
+    double *dlnjac_dR;
+    double *O;
+    double *G;
+} vmc_walker_out;
+
+/* Create a context on HIP device `device`: validates and deep-copies the host
+ * inputs (the caller may free them on return), folds the GTO normalisation,
+ * and allocates device state for opt->max_walkers walkers.
+ * Errors: VMC_EINVAL (l > 2, alpha <= 0, non-finite input, n_up != n_dn,
+ * n_occ != n_up, sizes beyond the VMC_MAX_* limits), VMC_ENOMEM, VMC_EDEVICE. */
+int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
+             const vmc_jastrow *jastrow, const vmc_options *opt, int32_t device,
+             vmc_ctx **out);
+
+/* Advance n_walkers independent Markov chains by nsteps sweeps (Appendix A,
+ * "Variational Monte Carlo Methods": MCMC sampling of |Psi|^2).
+ * walkers_dev  : device [n_walkers][N][3] positions, updated in place.
+ * A sweep proposes r'_e = r_e + step_sigma z for e = 0..N-1 in order and
+ * accepts iff u < |Psi'/Psi|^2; z and u come from Philox4x32-10 with key
+ * `seed` and counter (walker id, sweep index, electron | purpose << 16, 0),
+ * sweep index = sweep_offset + t, walker id = row of walkers_dev.
+ * flags & VMC_SWEEP_MEASURE: after every sweep measure every walker and add
+ *   the samples to the context's accumulators (read by vmc_accumulate).
+ * accept_dev   : optional device uint8 [nsteps][N][n_walkers], 1 = accepted.
+ * Errors: VMC_EINVAL (n_walkers > max_walkers or < 1, nsteps < 0),
+ * VMC_EDEVICE. */
+int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nsteps,
+              uint64_t seed, uint64_t sweep_offset, uint32_t flags, uint8_t *accept_dev,
+              void *stream);
+
+/* Read the estimators accumulated since the last reset (host outputs):
+ *   E[0] = <E_L>, E[1] = blocked error bar (NaN with < 2 blocks),
+ *   F_bare[A][3], dE_dC[n_ao][n_occ] (covariance form, eq. fc-vmc-eval with
+ *   B = dE/dC), dEL_dC_mean[n_ao][n_occ] = <dE_L/dC> (may be NULL),
+ *   n_samples (may be NULL).
+ * All sums are FP64, shifted by the mean E_L of the first measured batch and
+ * compensated (Neumaier).  Synchronises `stream`.
+ * flags & VMC_ACCUM_RESET clears the accumulators afterwards.
+ * Errors: VMC_EINVAL (no samples), VMC_ESINGULAR / VMC_ENONFINITE if any
+ * measured walker had a singular Slater matrix / non-finite E_L. */
+int vmc_accumulate(vmc_ctx *ctx, double *E, double *F_bare, double *dE_dC,
+                   double *dEL_dC_mean, int64_t *n_samples, uint32_t flags, void *stream);
+
+/* Per-walker measurement at fixed configurations for arbitrary MO
+ * coefficients C_dev[n_ao][n_occ] and nuclei R_dev[A][3] (device): electrons
+ * are warped r' = r + sum_a omega_a(r; R0) (R_a - R0_a) with weights taken at
+ * the sampling geometry R0_dev[A][3].  Fills the non-NULL fields of *out. */
+int vmc_measure(vmc_ctx *ctx, const double *walkers_dev, int64_t n_walkers,
+                const double *C_dev, const double *R_dev, const double *R0_dev,
+                const vmc_walker_out *out, void *stream);
+
+/* Forward of the fixed-sample reweighted energy (reweighting, Appendix A):
+ *   E_hat = sum_k w_k E_L,k / sum_k w_k,
+ *   w_k = exp(2 (ln|Psi_k| - lnpsi0_dev[k])) * Jac_k,
+ * evaluated with vmc_measure's conventions.  Outputs (device): EL[W],
+ * lnpsi[W], lnjac[W], wnorm[W] = w_k / sum w, Ehat[1]. */
+int vmc_eval(vmc_ctx *ctx, const double *walkers_dev, int64_t n_walkers,
+             const double *C_dev, const double *R_dev, const double *R0_dev,
+             const double *lnpsi0_dev, double *EL_dev, double *lnpsi_dev, double *lnjac_dev,
+             double *wnorm_dev, double *Ehat_dev, void *stream);
+
+/* Cotangents of E_hat with respect to the per-walker (E_L, ln|Psi|, ln Jac),
+ * scaled by the upstream gradient gE (host scalar):
+ *   gEL[k] = gE w_k,  gPsi[k] = 2 gE w_k (E_L,k - E_hat),
+ *   gJac[k] = gE w_k (E_L,k - E_hat),   w = wnorm (device arrays). */
+int vmc_energy_cotangents(vmc_ctx *ctx, int64_t n_walkers, double gE, const double *EL_dev,
+                          const double *wnorm_dev, const double *Ehat_dev, double *gEL_dev,
+                          double *gPsi_dev, double *gJac_dev, void *stream);
+
+/* Vector-Jacobian product of the per-walker map (C, R) -> (E_L, ln|Psi|, ln Jac)
+ * with per-walker cotangents gEL, gPsi, gJac (device [W]):
+ *   dC_dev[n_ao][n_occ] = sum_k gEL_k dE_L,k/dC + gPsi_k dln|Psi_k|/dC
+ *   dR_dev[A][3]        = sum_k gEL_k dE_L,k/dR + gPsi_k dln|Psi_k|/dR + gJac_k dlnJac_k/dR
+ * (hand-written reverse mode; forward intermediates are recomputed, not
+ * stored).  Outputs are overwritten. */
+int vmc_adjoint(vmc_ctx *ctx, const double *walkers_dev, int64_t n_walkers,
+                const double *C_dev, const double *R_dev, const double *R0_dev,
+                const double *gEL_dev, const double *gPsi_dev, const double *gJac_dev,
+                double *dC_dev, double *dR_dev, void *stream);
+
+/* Solve H z = -b (Z-vector equations A Z = -B, eq. AZ_eq_B_elements) by
+ * conjugate gradients in FP64 from z = 0 until ||H z + b|| <= rtol ||b||.
+ * H_dev[d][d] symmetric positive definite, b_dev[d], z_dev[d] (device).
+ * Host outputs: *iters = iterations used.  Synchronises `stream`.
+ * Errors: VMC_EINVAL (d < 1, rtol <= 0, maxit < 1), VMC_ENOTCONV (maxit
+ * reached; z holds the last iterate), VMC_ENONFINITE, VMC_ENOMEM, VMC_EDEVICE. */
+int zvector_solve(const double *H_dev, int64_t d, const double *b_dev, double *z_dev,
+                  double rtol, int32_t maxit, int32_t *iters, void *stream);
+
+/* Walkers processed per measurement launch (size of the per-walker staging);
+ * returns -1 for a NULL context. */
+int64_t vmc_staging_walkers(const vmc_ctx *ctx);
+
+/* Release the context and its device memory (NULL is ignored). */
+void vmc_free(vmc_ctx *ctx);
+
+/* Detail of the last error on ctx (never NULL; "" if none). */
+const char *vmc_last_error(const vmc_ctx *ctx);
+
+/* Detail of the last failed vmc_init in the calling thread (never NULL). */
+const char *vmc_init_error(void);
+
+/* Name of a status code. */
+const char *vmc_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VMC_H */

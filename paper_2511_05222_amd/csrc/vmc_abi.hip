@@ -1,0 +1,596 @@
+// vmc_abi.hip -- host side of the C ABI declared in include/vmc.h.
+//
+// Owns the context (validated inputs, folded GTO normalisation, device
+// buffers), sequences the kernels of vmc_kernels.hip on the caller's stream,
+// and finishes the estimators in FP64 on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vmc.h"
+#include "vmc_kernels.hpp"
+
+using vmcx::EstArgs;
+using vmcx::MeasLayout;
+using vmcx::SweepLayout;
+using vmcx::SysDev;
+using vmcx::WalkerOut;
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int64_t MAX_SEG = 64;
+constexpr int64_t MAX_BLOCKS = 1 << 16;
+constexpr size_t STAGING_BUDGET = size_t(1) << 31;   // bytes of per-walker staging
+
+int dfact(int n) {
+    int r = 1;
+    while (n > 1) {
+        r *= n;
+        n -= 2;
+    }
+    return r;
+}
+
+bool all_finite(const double *p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct vmc_ctx {
+    int device = 0;
+    int N = 0, n_up = 0, n_dn = 0, n_occ = 0, M = 0, A = 0, S = 0, P = 0;
+    vmc_options opt{};
+    double ee_a = 0.5, ee_F = 1.0;
+    std::string err;
+
+    std::vector<void *> allocs;
+    int *d_ao_shell = nullptr, *d_ao_pow = nullptr, *d_shell_atom = nullptr, *d_shell_p0 = nullptr,
+        *d_shell_np = nullptr;
+    double *d_ao_eta = nullptr, *d_prim_exp = nullptr, *d_prim_cp = nullptr, *d_C = nullptr, *d_R = nullptr,
+           *d_Z = nullptr;
+    SysDev sys{};
+    SweepLayout sl{};
+    MeasLayout ml{};
+
+    int64_t chunk = 0;
+    double *st_EL = nullptr, *st_lnpsi = nullptr, *st_lnjac = nullptr, *st_dEdR = nullptr, *st_dPdR = nullptr,
+           *st_dJdR = nullptr, *st_O = nullptr, *st_G = nullptr, *slab = nullptr;
+    double *st_gE = nullptr, *st_gP = nullptr, *st_gJ = nullptr;
+
+    int64_t n_est = 0;
+    double *acc = nullptr, *comp = nullptr, *partial = nullptr;
+    double *shift = nullptr;
+    int *shift_set = nullptr;
+    int *status = nullptr;
+    double *blocks = nullptr;
+    std::vector<int64_t> block_counts;
+    int64_t n_samples = 0;
+    int64_t sweeps_since_reset = 0;
+    double *vjp_acc = nullptr, *vjp_comp = nullptr, *vjp_out = nullptr;
+
+    int fail(int code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+
+    template <class T>
+    int dalloc(T **p, size_t n) {
+        void *q = nullptr;
+        if (hipMalloc(&q, n * sizeof(T) > 0 ? n * sizeof(T) : 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(VMC_ENOMEM, "hipMalloc of %zu bytes failed", n * sizeof(T));
+        }
+        allocs.push_back(q);
+        *p = (T *)q;
+        return VMC_OK;
+    }
+
+    template <class T>
+    int upload(T **p, const T *h, size_t n) {
+        int rc = dalloc(p, n);
+        if (rc) return rc;
+        if (hipMemcpy(*p, h, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(VMC_EDEVICE, "hipMemcpy to device failed");
+        return VMC_OK;
+    }
+};
+
+#define HIP_OK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) return (ctx)->fail(VMC_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static void layouts(vmc_ctx *c) {
+    const int N = c->N, n = c->n_occ, M = c->M;
+    int o = 0;
+    SweepLayout &s = c->sl;
+    s.pos = o; o += 3 * N;
+    s.K0 = o; o += n * n;
+    s.K1 = o; o += n * n;
+    s.aor = o; o += std::max(M, 1024);
+    s.phin = o; o += 64;
+    s.vrow = o; o += 64;
+    s.colj = o; o += 64;
+    s.part = o; o += 256;
+    s.red = o; o += 8;
+    s.misc = o; o += 8;
+    s.perm = o; o += 32;
+    s.bytes = (size_t)o * sizeof(double);
+
+    o = 0;
+    MeasLayout &m = c->ml;
+    m.p0 = o; o += 3 * N;
+    m.p = o; o += 3 * N;
+    m.K0 = o; o += c->n_up * c->n_up;
+    m.K1 = o; o += c->n_dn * c->n_dn;
+    m.X = o; o += N * n;
+    m.U = o; o += std::max(2048, n * n);
+    m.g = o; o += 3 * N;
+    m.h = o; o += N;
+    m.bD = o; o += 3 * N;
+    m.lapD = o; o += N;
+    m.dEdr = o; o += 3 * N;
+    m.tAOE = o; o += 3 * M;
+    m.tAOP = o; o += 3 * M;
+    m.Minv = o; o += 9 * N;
+    m.sg = o; o += 3 * N;
+    m.red = o; o += 8;
+    m.misc = o; o += 8;
+    m.perm = o; o += 32;
+    m.bytes = (size_t)o * sizeof(double);
+}
+
+static int set_device(vmc_ctx *c) {
+    HIP_OK(c, hipSetDevice(c->device));
+    return VMC_OK;
+}
+
+extern "C" {
+
+const char *vmc_strerror(int s) {
+    switch (s) {
+        case VMC_OK: return "VMC_OK";
+        case VMC_EINVAL: return "VMC_EINVAL";
+        case VMC_ENOMEM: return "VMC_ENOMEM";
+        case VMC_EDEVICE: return "VMC_EDEVICE";
+        case VMC_ESINGULAR: return "VMC_ESINGULAR";
+        case VMC_ENOTCONV: return "VMC_ENOTCONV";
+        case VMC_ENONFINITE: return "VMC_ENONFINITE";
+        default: return "VMC_UNKNOWN";
+    }
+}
+
+const char *vmc_last_error(const vmc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void vmc_free(vmc_ctx *ctx) {
+    if (!ctx) return;
+    if (!ctx->allocs.empty()) {
+        (void)hipSetDevice(ctx->device);
+        for (void *p : ctx->allocs) (void)hipFree(p);
+    }
+    delete ctx;
+}
+
+static thread_local std::string g_init_err;
+
+int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo, const vmc_jastrow *jas,
+             const vmc_options *opt, int32_t device, vmc_ctx **out) {
+    if (!out) return VMC_EINVAL;
+    *out = nullptr;
+    if (!basis || !nuclei || !mo || !jas || !opt) return VMC_EINVAL;
+    vmc_ctx *c = new (std::nothrow) vmc_ctx();
+    if (!c) return VMC_ENOMEM;
+    auto bail = [&](int rc) {
+        *out = nullptr;
+        g_init_err = c->err;
+        vmc_free(c);
+        return rc;
+    };
+    c->device = device;
+    c->opt = *opt;
+    const int S = basis->n_shells, A = nuclei->n_atoms;
+    if (S < 1 || A < 1 || A > VMC_MAX_ATOMS || !basis->shell_atom || !basis->shell_l || !basis->shell_nprim ||
+        !basis->prim_exp || !basis->prim_coef || !nuclei->xyz || !nuclei->Z || !mo->C)
+        return bail(c->fail(VMC_EINVAL, "missing arrays or bad counts (shells %d, atoms %d)", S, A));
+    int P = 0, M = 0;
+    for (int s = 0; s < S; ++s) {
+        const int l = basis->shell_l[s], np = basis->shell_nprim[s], at = basis->shell_atom[s];
+        if (l < 0 || l > VMC_MAX_L) return bail(c->fail(VMC_EINVAL, "shell %d: l = %d not supported", s, l));
+        if (np < 1) return bail(c->fail(VMC_EINVAL, "shell %d: %d primitives", s, np));
+        if (at < 0 || at >= A) return bail(c->fail(VMC_EINVAL, "shell %d: atom %d out of range", s, at));
+        P += np;
+        M += (l + 1) * (l + 2) / 2;
+    }
+    for (int k = 0; k < P; ++k) {
+        if (!(basis->prim_exp[k] > 0.0) || !std::isfinite(basis->prim_exp[k]))
+            return bail(c->fail(VMC_EINVAL, "primitive %d: exponent %g must be finite and > 0", k, basis->prim_exp[k]));
+        if (!std::isfinite(basis->prim_coef[k]))
+            return bail(c->fail(VMC_EINVAL, "primitive %d: non-finite coefficient", k));
+    }
+    if (M != mo->n_ao) return bail(c->fail(VMC_EINVAL, "n_ao = %d but the shells give %d AOs", mo->n_ao, M));
+    if (M > VMC_MAX_AO) return bail(c->fail(VMC_EINVAL, "n_ao = %d exceeds %d", M, VMC_MAX_AO));
+    if (mo->n_up != mo->n_dn || mo->n_up < 1 || mo->n_occ != mo->n_up)
+        return bail(c->fail(VMC_EINVAL, "need a closed shell with n_up = n_dn = n_occ >= 1 (got %d, %d, %d)",
+                            mo->n_up, mo->n_dn, mo->n_occ));
+    if (mo->n_occ > VMC_MAX_OCC || mo->n_up + mo->n_dn > VMC_MAX_ELEC)
+        return bail(c->fail(VMC_EINVAL, "n_occ = %d / N = %d exceed the limits", mo->n_occ, mo->n_up + mo->n_dn));
+    if (!all_finite(nuclei->xyz, 3 * A) || !all_finite(nuclei->Z, A) || !all_finite(mo->C, (int64_t)M * mo->n_occ))
+        return bail(c->fail(VMC_EINVAL, "non-finite nuclei or MO coefficients"));
+    if (!std::isfinite(jas->ee_a) || !std::isfinite(jas->ee_F) || jas->ee_F < 0.0)
+        return bail(c->fail(VMC_EINVAL, "bad Jastrow parameters"));
+    if (opt->precision != VMC_FP64)
+        return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 only)", opt->precision));
+    if (opt->refresh_period < 1 || opt->block_sweeps < 1 || opt->max_walkers < 1 || opt->staging_walkers < 0 ||
+        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma))
+        return bail(c->fail(VMC_EINVAL, "bad options"));
+    double Zsum = 0.0;
+    for (int a = 0; a < A; ++a) Zsum += nuclei->Z[a];
+    c->N = mo->n_up + mo->n_dn;
+    c->n_up = mo->n_up;
+    c->n_dn = mo->n_dn;
+    c->n_occ = mo->n_occ;
+    c->M = M;
+    c->A = A;
+    c->S = S;
+    c->P = P;
+    c->ee_a = jas->ee_a;
+    c->ee_F = jas->ee_F;
+    (void)Zsum;
+
+    // ---- fold normalisation -------------------------------------------------
+    std::vector<int> ao_shell, ao_pow, shell_p0(S);
+    std::vector<double> ao_eta, cp(P);
+    int p0 = 0;
+    for (int s = 0; s < S; ++s) {
+        const int l = basis->shell_l[s], np = basis->shell_nprim[s];
+        shell_p0[s] = p0;
+        std::vector<double> cn(np);
+        for (int k = 0; k < np; ++k) {
+            const double al = basis->prim_exp[p0 + k];
+            cn[k] = basis->prim_coef[p0 + k] * std::pow(2.0 * al / PI, 0.75) * std::pow(4.0 * al, 0.5 * l);
+        }
+        double ov = 0.0;
+        for (int k = 0; k < np; ++k)
+            for (int q = 0; q < np; ++q) {
+                const double pp = basis->prim_exp[p0 + k] + basis->prim_exp[p0 + q];
+                ov += cn[k] * cn[q] * std::pow(PI / pp, 1.5) / std::pow(2.0 * pp, l);
+            }
+        if (!(ov > 0.0)) return bail(c->fail(VMC_EINVAL, "shell %d has zero norm", s));
+        for (int k = 0; k < np; ++k) cp[p0 + k] = cn[k] / std::sqrt(ov);
+        p0 += np;
+        // cartesian components in order s; x,y,z; xx,xy,xz,yy,yz,zz
+        static const int comps[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                                         {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
+        const int first = l == 0 ? 0 : (l == 1 ? 1 : 4);
+        const int cnt = (l + 1) * (l + 2) / 2;
+        for (int q = 0; q < cnt; ++q) {
+            const int *cc = comps[first + q];
+            ao_shell.push_back(s);
+            ao_pow.push_back(cc[0] | (cc[1] << 4) | (cc[2] << 8));
+            ao_eta.push_back(1.0 / std::sqrt((double)(dfact(2 * cc[0] - 1) * dfact(2 * cc[1] - 1) * dfact(2 * cc[2] - 1))));
+        }
+    }
+
+    int rc;
+    if ((rc = set_device(c))) return bail(rc);
+    if ((rc = c->upload(&c->d_ao_shell, ao_shell.data(), M)) || (rc = c->upload(&c->d_ao_pow, ao_pow.data(), M)) ||
+        (rc = c->upload(&c->d_ao_eta, ao_eta.data(), M)) ||
+        (rc = c->upload(&c->d_shell_atom, (const int *)basis->shell_atom, S)) ||
+        (rc = c->upload(&c->d_shell_p0, shell_p0.data(), S)) ||
+        (rc = c->upload(&c->d_shell_np, (const int *)basis->shell_nprim, S)) ||
+        (rc = c->upload(&c->d_prim_exp, basis->prim_exp, P)) || (rc = c->upload(&c->d_prim_cp, cp.data(), P)) ||
+        (rc = c->upload(&c->d_C, mo->C, (size_t)M * c->n_occ)) || (rc = c->upload(&c->d_R, nuclei->xyz, 3 * A)) ||
+        (rc = c->upload(&c->d_Z, nuclei->Z, A)))
+        return bail(rc);
+
+    SysDev &sd = c->sys;
+    sd.N = c->N;
+    sd.n_up = c->n_up;
+    sd.n_dn = c->n_dn;
+    sd.n_occ = c->n_occ;
+    sd.M = M;
+    sd.A = A;
+    sd.ee_a = c->ee_a;
+    sd.ee_F = c->ee_F;
+    sd.basis = vmcx::BasisDev{M,          S,           c->d_ao_shell, c->d_ao_pow,   c->d_ao_eta,
+                              c->d_shell_atom, c->d_shell_p0, c->d_shell_np, c->d_prim_exp, c->d_prim_cp};
+    sd.Z = c->d_Z;
+    layouts(c);
+    if (c->sl.bytes > 160 * 1024 || c->ml.bytes > 160 * 1024)
+        return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu / %zu bytes)",
+                            c->sl.bytes, c->ml.bytes));
+    if (vmcx::configure_kernels(c->sl.bytes, c->ml.bytes) != hipSuccess)
+        return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the kernels"));
+
+    // ---- staging and accumulators -------------------------------------------
+    const int64_t Mn = (int64_t)M * c->n_occ, A3 = 3 * A;
+    const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + (size_t)c->N * 5 * c->n_occ + 3);
+    int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
+    chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, opt->max_walkers));
+    if (opt->staging_walkers > 0) chunk = std::min<int64_t>(chunk, opt->staging_walkers);
+    c->chunk = chunk;
+    if ((rc = c->dalloc(&c->st_EL, chunk)) || (rc = c->dalloc(&c->st_lnpsi, chunk)) ||
+        (rc = c->dalloc(&c->st_lnjac, chunk)) || (rc = c->dalloc(&c->st_dEdR, chunk * A3)) ||
+        (rc = c->dalloc(&c->st_dPdR, chunk * A3)) || (rc = c->dalloc(&c->st_dJdR, chunk * A3)) ||
+        (rc = c->dalloc(&c->st_O, chunk * Mn)) || (rc = c->dalloc(&c->st_G, chunk * Mn)) ||
+        (rc = c->dalloc(&c->slab, (size_t)chunk * c->N * 5 * c->n_occ)))
+        return bail(rc);
+    c->n_est = 2 + 3 * A3 + 3 * Mn;
+    const int64_t n_vjp = Mn + A3;
+    if ((rc = c->dalloc(&c->acc, c->n_est)) || (rc = c->dalloc(&c->comp, c->n_est)) ||
+        (rc = c->dalloc(&c->partial, MAX_SEG * std::max(c->n_est, n_vjp))) || (rc = c->dalloc(&c->shift, 1)) ||
+        (rc = c->dalloc(&c->shift_set, 1)) || (rc = c->dalloc(&c->status, 1)) ||
+        (rc = c->dalloc(&c->blocks, MAX_BLOCKS)) || (rc = c->dalloc(&c->vjp_acc, n_vjp)) ||
+        (rc = c->dalloc(&c->vjp_comp, n_vjp)) || (rc = c->dalloc(&c->vjp_out, n_vjp)))
+        return bail(rc);
+    if (hipMemset(c->acc, 0, c->n_est * 8) != hipSuccess || hipMemset(c->comp, 0, c->n_est * 8) != hipSuccess ||
+        hipMemset(c->shift, 0, 8) != hipSuccess || hipMemset(c->shift_set, 0, 4) != hipSuccess ||
+        hipMemset(c->status, 0, 4) != hipSuccess || hipMemset(c->blocks, 0, MAX_BLOCKS * 8) != hipSuccess)
+        return bail(c->fail(VMC_EDEVICE, "hipMemset failed"));
+    *out = c;
+    return VMC_OK;
+}
+
+int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t seed, uint64_t sweep_offset,
+              uint32_t flags, uint8_t *accept, void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (!walkers || W < 1 || W > c->opt.max_walkers || nsteps < 0)
+        return c->fail(VMC_EINVAL, "bad arguments: walkers=%p n_walkers=%lld (max %d) nsteps=%d", (void *)walkers,
+                       (long long)W, c->opt.max_walkers, nsteps);
+    if (sweep_offset + (uint64_t)nsteps > 0xFFFFFFFFull)
+        return c->fail(VMC_EINVAL, "sweep index beyond 2^32");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t Mn = (int64_t)c->M * c->n_occ, A3 = 3 * c->A;
+    for (int t = 0; t < nsteps; ++t) {
+        const uint32_t sidx = (uint32_t)(sweep_offset + t);
+        uint8_t *acc_t = accept ? accept + (size_t)t * c->N * W : nullptr;
+        HIP_OK(c, vmcx::launch_sweep(c->sys, c->d_C, c->d_R, walkers, (int)W, sidx, seed, c->opt.step_sigma,
+                                     c->opt.refresh_period, acc_t, c->status, c->sl, st));
+        if (!(flags & VMC_SWEEP_MEASURE)) continue;
+        const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
+        double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;
+        for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
+            const int64_t cw = std::min(c->chunk, W - c0);
+            WalkerOut o{c->st_EL, c->st_lnpsi, c->st_lnjac, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
+            HIP_OK(c, vmcx::launch_measure(c->sys, c->d_C, c->d_R, c->d_R, 0, walkers + c0 * c->N * 3, (int)cw, 1, o,
+                                           c->slab, c->status, c->ml, st));
+            HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
+            EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
+                      nullptr,  nullptr,    nullptr,    A3,         Mn};
+            HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, st));
+        }
+        if (blk_idx < MAX_BLOCKS) {
+            if ((int64_t)c->block_counts.size() <= blk_idx) c->block_counts.resize(blk_idx + 1, 0);
+            c->block_counts[blk_idx] += W;
+        }
+        c->n_samples += W;
+        c->sweeps_since_reset += 1;
+    }
+    return VMC_OK;
+}
+
+int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC, int64_t *n_samples,
+                   uint32_t flags, void *stream) {
+    if (!c) return VMC_EINVAL;
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (c->n_samples < 1) return c->fail(VMC_EINVAL, "no samples accumulated");
+    const int64_t n = c->n_est, Mn = (int64_t)c->M * c->n_occ, A3 = 3 * c->A;
+    std::vector<double> acc(n), comp(n);
+    double shift = 0.0;
+    int status = 0;
+    const int64_t nb = std::min<int64_t>((int64_t)c->block_counts.size(), MAX_BLOCKS);
+    std::vector<double> blocks(std::max<int64_t>(nb, 1));
+    HIP_OK(c, hipMemcpyAsync(acc.data(), c->acc, n * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(comp.data(), c->comp, n * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(&shift, c->shift, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(&status, c->status, 4, hipMemcpyDeviceToHost, st));
+    if (nb > 0) HIP_OK(c, hipMemcpyAsync(blocks.data(), c->blocks, nb * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+    const double K = (double)c->n_samples;
+    std::vector<double> v(n);
+    for (int64_t i = 0; i < n; ++i) v[i] = (acc[i] + comp[i]) / K;
+    const double vE = v[0];
+    const double *vH = &v[2], *vP = &v[2 + A3], *vEP = &v[2 + 2 * A3];
+    const double *vO = &v[2 + 3 * A3], *vEO = &v[2 + 3 * A3 + Mn], *vG = &v[2 + 3 * A3 + 2 * Mn];
+    if (E) {
+        E[0] = shift + vE;
+        // blocked error bar over complete blocks
+        int64_t full = (c->sweeps_since_reset / c->opt.block_sweeps);
+        full = std::min(full, nb);
+        if (full >= 2) {
+            double mean = 0.0;
+            std::vector<double> bm(full);
+            for (int64_t b = 0; b < full; ++b) {
+                bm[b] = blocks[b] / (double)c->block_counts[b];
+                mean += bm[b];
+            }
+            mean /= (double)full;
+            double var = 0.0;
+            for (int64_t b = 0; b < full; ++b) var += (bm[b] - mean) * (bm[b] - mean);
+            var /= (double)(full - 1);
+            E[1] = std::sqrt(var / (double)full);
+        } else {
+            E[1] = std::nan("");
+        }
+    }
+    if (F)
+        for (int64_t i = 0; i < A3; ++i) F[i] = -vH[i] - 2.0 * (vEP[i] - vE * vP[i]);
+    if (dEdC)
+        for (int64_t i = 0; i < Mn; ++i) dEdC[i] = 2.0 * (vEO[i] - vE * vO[i]);
+    if (dELdC)
+        for (int64_t i = 0; i < Mn; ++i) dELdC[i] = vG[i];
+    if (n_samples) *n_samples = c->n_samples;
+    if (flags & VMC_ACCUM_RESET) {
+        HIP_OK(c, hipMemsetAsync(c->acc, 0, n * 8, st));
+        HIP_OK(c, hipMemsetAsync(c->comp, 0, n * 8, st));
+        HIP_OK(c, hipMemsetAsync(c->shift_set, 0, 4, st));
+        HIP_OK(c, hipMemsetAsync(c->status, 0, 4, st));
+        HIP_OK(c, hipMemsetAsync(c->blocks, 0, MAX_BLOCKS * 8, st));
+        HIP_OK(c, hipStreamSynchronize(st));
+        c->block_counts.clear();
+        c->n_samples = 0;
+        c->sweeps_since_reset = 0;
+    }
+    if (status & vmcx::STATUS_SINGULAR) return c->fail(VMC_ESINGULAR, "a Slater matrix had a zero pivot");
+    if (status & vmcx::STATUS_NONFINITE) return c->fail(VMC_ENONFINITE, "non-finite local energy or ln|Psi|");
+    return VMC_OK;
+}
+
+int vmc_measure(vmc_ctx *c, const double *walkers, int64_t W, const double *C, const double *R, const double *R0,
+                const vmc_walker_out *out, void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (!walkers || !C || !R || !R0 || !out || W < 1)
+        return c->fail(VMC_EINVAL, "vmc_measure: null argument or n_walkers < 1");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int full = (out->dEL_dR || out->dlnpsi_dR || out->dlnjac_dR || out->O || out->G) ? 1 : 0;
+    const int warp = (R != R0) ? 1 : 0;
+    const int64_t Mn = (int64_t)c->M * c->n_occ, A3 = 3 * c->A;
+    for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
+        const int64_t cw = std::min(c->chunk, W - c0);
+        auto off = [&](double *p, int64_t stride) { return p ? p + c0 * stride : nullptr; };
+        WalkerOut o{off(out->EL, 1),      off(out->lnpsi, 1),  off(out->lnjac, 1),
+                    off(out->dEL_dR, A3), off(out->dlnpsi_dR, A3), off(out->dlnjac_dR, A3),
+                    off(out->O, Mn),      off(out->G, Mn)};
+        HIP_OK(c, vmcx::launch_measure(c->sys, C, R, R0, warp, walkers + c0 * c->N * 3, (int)cw, full, o, c->slab,
+                                       c->status, c->ml, st));
+    }
+    return VMC_OK;
+}
+
+int vmc_eval(vmc_ctx *c, const double *walkers, int64_t W, const double *C, const double *R, const double *R0,
+             const double *lnpsi0, double *EL, double *lnpsi, double *lnjac, double *wnorm, double *Ehat,
+             void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (!EL || !lnpsi || !lnjac) return c->fail(VMC_EINVAL, "vmc_eval: EL, lnpsi and lnjac are required");
+    vmc_walker_out o{EL, lnpsi, lnjac, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = vmc_measure(c, walkers, W, C, R, R0, &o, stream);
+    if (rc) return rc;
+    if (lnpsi0) {
+        if (!wnorm || !Ehat) return c->fail(VMC_EINVAL, "vmc_eval: wnorm and Ehat are required with lnpsi0");
+        HIP_OK(c, vmcx::launch_eval_weights(EL, lnpsi, lnjac, lnpsi0, W, wnorm, Ehat, (hipStream_t)stream));
+    }
+    return VMC_OK;
+}
+
+int vmc_energy_cotangents(vmc_ctx *c, int64_t W, double gE, const double *EL, const double *wnorm,
+                          const double *Ehat, double *gEL, double *gPsi, double *gJac, void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (W < 1 || !EL || !wnorm || !Ehat || !gEL || !gPsi || !gJac)
+        return c->fail(VMC_EINVAL, "vmc_energy_cotangents: bad arguments");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    HIP_OK(c, vmcx::launch_energy_cotangents(W, gE, EL, wnorm, Ehat, gEL, gPsi, gJac, (hipStream_t)stream));
+    return VMC_OK;
+}
+
+int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, const double *R, const double *R0,
+                const double *gEL, const double *gPsi, const double *gJac, double *dC, double *dR, void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (!walkers || !C || !R || !R0 || !gEL || !gPsi || !gJac || !dC || !dR || W < 1)
+        return c->fail(VMC_EINVAL, "vmc_adjoint: null argument or n_walkers < 1");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t Mn = (int64_t)c->M * c->n_occ, A3 = 3 * c->A, nv = Mn + A3;
+    HIP_OK(c, hipMemsetAsync(c->vjp_acc, 0, nv * 8, st));
+    HIP_OK(c, hipMemsetAsync(c->vjp_comp, 0, nv * 8, st));
+    const int warp = (R != R0) ? 1 : 0;
+    for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
+        const int64_t cw = std::min(c->chunk, W - c0);
+        WalkerOut o{c->st_EL, c->st_lnpsi, c->st_lnjac, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
+        HIP_OK(c, vmcx::launch_measure(c->sys, C, R, R0, warp, walkers + c0 * c->N * 3, (int)cw, 1, o, c->slab,
+                                       c->status, c->ml, st));
+        EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, nullptr,
+                  gEL + c0, gPsi + c0,  gJac + c0,  A3,         Mn};
+        HIP_OK(c, vmcx::launch_reduce(a, 1, nv, cw, c->partial, MAX_SEG, c->vjp_acc, c->vjp_comp, nullptr, st));
+    }
+    HIP_OK(c, vmcx::launch_combine(c->vjp_acc, c->vjp_comp, nv, c->vjp_out, st));
+    HIP_OK(c, hipMemcpyAsync(dC, c->vjp_out, Mn * 8, hipMemcpyDeviceToDevice, st));
+    HIP_OK(c, hipMemcpyAsync(dR, c->vjp_out + Mn, A3 * 8, hipMemcpyDeviceToDevice, st));
+    return VMC_OK;
+}
+
+int zvector_solve(const double *H, int64_t d, const double *b, double *z, double rtol, int32_t maxit,
+                  int32_t *iters, void *stream) {
+    if (!H || !b || !z || d < 1 || !(rtol > 0.0) || maxit < 1) return VMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int NPART = 64;
+    double *work = nullptr;
+    const size_t nwork = 3 * (size_t)d + NPART + 8;
+    if (hipMalloc(&work, nwork * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return VMC_ENOMEM;
+    }
+    double *r = work, *p = work + d, *Hp = work + 2 * d, *part = work + 3 * d;
+    double *sc = part + NPART;   // [0] rr, [1] rr_new, [2] pHp, [3] bb
+    double *rr = sc, *rr_new = sc + 1, *pHp = sc + 2, *bb = sc + 3;
+    int status = VMC_OK;
+    int it = 0;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && status == VMC_OK) status = VMC_EDEVICE;
+        return e == hipSuccess;
+    };
+    double h_bb = 0.0, h_rr = 0.0;
+    chk(vmcx::launch_cg_init(z, r, p, b, d, st));
+    chk(vmcx::launch_dot(r, r, d, part, NPART, rr, st));
+    chk(hipMemcpyAsync(bb, rr, 8, hipMemcpyDeviceToDevice, st));
+    chk(hipMemcpyAsync(&h_bb, bb, 8, hipMemcpyDeviceToHost, st));
+    chk(hipStreamSynchronize(st));
+    if (status == VMC_OK && !std::isfinite(h_bb)) status = VMC_ENONFINITE;
+    bool conv = (status == VMC_OK && h_bb == 0.0);
+    const double tol2 = rtol * rtol * h_bb;
+    while (status == VMC_OK && !conv && it < maxit) {
+        ++it;
+        chk(vmcx::launch_matvec(H, p, Hp, d, st));
+        chk(vmcx::launch_dot(p, Hp, d, part, NPART, pHp, st));
+        chk(vmcx::launch_cg_update_xr(z, r, p, Hp, d, rr, pHp, st));
+        chk(vmcx::launch_dot(r, r, d, part, NPART, rr_new, st));
+        chk(hipMemcpyAsync(&h_rr, rr_new, 8, hipMemcpyDeviceToHost, st));
+        chk(hipStreamSynchronize(st));
+        if (status != VMC_OK) break;
+        if (!std::isfinite(h_rr)) {
+            status = VMC_ENONFINITE;
+            break;
+        }
+        if (h_rr <= tol2) {
+            conv = true;
+            break;
+        }
+        chk(vmcx::launch_cg_update_p(p, r, d, rr_new, rr, st));
+        std::swap(rr, rr_new);
+    }
+    chk(hipStreamSynchronize(st));
+    (void)hipFree(work);
+    if (iters) *iters = it;
+    if (status != VMC_OK) return status;
+    return conv ? VMC_OK : VMC_ENOTCONV;
+}
+
+const char *vmc_init_error(void) { return g_init_err.c_str(); }
+
+int64_t vmc_staging_walkers(const vmc_ctx *c) { return c ? c->chunk : -1; }
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// vmc_device.hpp -- device math of the VMC hot path (gfx950).
+//
+// Everything here is __host__ __device__ so that the same arithmetic can be
+// checked on the CPU.  Kernels live in vmc_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vmcx {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 bit
+// multiplies with xor of the key; key advanced by the Weyl constants.
+// Counter layout of the Markov-chain draws: (walker, sweep, electron |
+// purpose << 16, 0), key = (seed lo, seed hi).
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+enum : uint32_t { PURPOSE_NORMAL = 0, PURPOSE_UNIFORM = 1 };
+
+__host__ __device__ inline U4 draw_words(uint64_t seed, uint32_t walker, uint32_t sweep,
+                                         uint32_t electron, uint32_t purpose) {
+    return philox4x32_10(U4{walker, sweep, (electron & 0xFFFFu) | (purpose << 16), 0u},
+                         (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// Box-Muller from two words: u1 in (0,1], u2 in [0,1).
+__host__ __device__ inline void box_muller(uint32_t a, uint32_t b, double &z0, double &z1) {
+    const double u1 = ((double)a + 1.0) * 2.3283064365386963e-10;   // 2^-32
+    const double u2 = (double)b * 2.3283064365386963e-10;
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 6.283185307179586 * u2;
+    z0 = rad * cos(ang);
+    z1 = rad * sin(ang);
+}
+
+// Three proposal normals and the accept uniform of one move.
+__host__ __device__ inline void move_draws(uint64_t seed, uint32_t walker, uint32_t sweep,
+                                           uint32_t electron, double z[3], double &u) {
+    const U4 a = draw_words(seed, walker, sweep, electron, PURPOSE_NORMAL);
+    double t;
+    box_muller(a.x, a.y, z[0], z[1]);
+    box_muller(a.z, a.w, z[2], t);
+    const U4 b = draw_words(seed, walker, sweep, electron, PURPOSE_UNIFORM);
+    const uint64_t bits = ((uint64_t)b.x << 21) | ((uint64_t)b.y >> 11);
+    u = (double)bits * 1.1102230246251565e-16;                      // 2^-53
+}
+
+// ---------------------------------------------------------------------------
+// Basis tables (device pointers), normalisation folded in by the host.
+// AO mu: shell ao_shell[mu], monomial exponents ao_pow[mu] = a | b<<4 | c<<8,
+// component factor ao_eta[mu]; shell s: atom, first primitive, count.
+// ---------------------------------------------------------------------------
+struct BasisDev {
+    int n_ao;
+    int n_shells;
+    const int *ao_shell;
+    const int *ao_pow;
+    const double *ao_eta;
+    const int *shell_atom;
+    const int *shell_p0;
+    const int *shell_np;
+    const double *prim_exp;
+    const double *prim_cp;   // radial coefficient incl. all norms
+};
+
+__host__ __device__ inline double ipow(double x, int k) {
+    // k in -2..2 for l <= 2 shells; negative powers only appear multiplied by 0
+    return k <= 0 ? (k == 0 ? 1.0 : 0.0) : (k == 1 ? x : x * x);
+}
+
+// Number of AO derivative components written by ao_eval<NC>:
+//   NC = 1  : value
+//   NC = 5  : value, d/dx, d/dy, d/dz, laplacian
+//   NC = 14 : + hessian xx,xy,xz,yy,yz,zz (5..10), d(lap)/dx,dy,dz (11..13)
+template <int NC>
+__host__ __device__ inline void ao_eval(const BasisDev &B, const double *R, int mu, double rx,
+                                        double ry, double rz, double *out) {
+    const int s = B.ao_shell[mu];
+    const int atom = B.shell_atom[s];
+    const double x = rx - R[3 * atom + 0];
+    const double y = ry - R[3 * atom + 1];
+    const double z = rz - R[3 * atom + 2];
+    const double rho = x * x + y * y + z * z;
+    const int p0 = B.shell_p0[s], np = B.shell_np[s];
+    double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0;
+    for (int k = 0; k < np; ++k) {
+        const double al = B.prim_exp[p0 + k];
+        const double e = B.prim_cp[p0 + k] * exp(-al * rho);
+        R0 += e;
+        if (NC > 1) {
+            R1 -= al * e;
+            R2 += al * al * e;
+            if (NC > 5) R3 -= al * al * al * e;
+        }
+    }
+    const int pw = B.ao_pow[mu];
+    const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15;
+    const int l = a + b + c;
+    const double eta = B.ao_eta[mu];
+    const double xa = ipow(x, a), yb = ipow(y, b), zc = ipow(z, c);
+    const double P = xa * yb * zc;
+    out[0] = eta * P * R0;
+    if (NC == 1) return;
+    // first derivatives of the monomial
+    const double Px = a * ipow(x, a - 1) * yb * zc;
+    const double Py = b * xa * ipow(y, b - 1) * zc;
+    const double Pz = c * xa * yb * ipow(z, c - 1);
+    // second derivatives of the monomial (l <= 2: constants or linear)
+    const double Pxx = a * (a - 1) * ipow(x, a - 2) * yb * zc;
+    const double Pyy = b * (b - 1) * xa * ipow(y, b - 2) * zc;
+    const double Pzz = c * (c - 1) * xa * yb * ipow(z, c - 2);
+    const double lapP = Pxx + Pyy + Pzz;
+    out[1] = eta * (Px * R0 + 2.0 * x * P * R1);
+    out[2] = eta * (Py * R0 + 2.0 * y * P * R1);
+    out[3] = eta * (Pz * R0 + 2.0 * z * P * R1);
+    // lap[P R(rho)] = lapP R + 4 (x.gradP) R' + P (6 R' + 4 rho R''), x.gradP = l P
+    out[4] = eta * (lapP * R0 + (4.0 * l + 6.0) * P * R1 + 4.0 * rho * P * R2);
+    if (NC == 5) return;
+    const double Pxy = a * b * ipow(x, a - 1) * ipow(y, b - 1) * zc;
+    const double Pxz = a * c * ipow(x, a - 1) * yb * ipow(z, c - 1);
+    const double Pyz = b * c * xa * ipow(y, b - 1) * ipow(z, c - 1);
+    // d_i d_j [P R] = P_ij R + 2 (x_j P_i + x_i P_j) R' + 2 delta_ij P R' + 4 x_i x_j P R''
+    out[5] = eta * (Pxx * R0 + 4.0 * x * Px * R1 + 2.0 * P * R1 + 4.0 * x * x * P * R2);
+    out[6] = eta * (Pxy * R0 + 2.0 * (y * Px + x * Py) * R1 + 4.0 * x * y * P * R2);
+    out[7] = eta * (Pxz * R0 + 2.0 * (z * Px + x * Pz) * R1 + 4.0 * x * z * P * R2);
+    out[8] = eta * (Pyy * R0 + 4.0 * y * Py * R1 + 2.0 * P * R1 + 4.0 * y * y * P * R2);
+    out[9] = eta * (Pyz * R0 + 2.0 * (z * Py + y * Pz) * R1 + 4.0 * y * z * P * R2);
+    out[10] = eta * (Pzz * R0 + 4.0 * z * Pz * R1 + 2.0 * P * R1 + 4.0 * z * z * P * R2);
+    // d_k lap[P R] with lapP constant for l <= 2:
+    //   (2 x_k lapP + (4l+6) P_k) R' + ((8l+20) x_k P + 4 rho P_k) R'' + 8 rho x_k P R'''
+    const double c1 = 4.0 * l + 6.0, c2 = 8.0 * l + 20.0;
+    out[11] = eta * ((2.0 * x * lapP + c1 * Px) * R1 + (c2 * x * P + 4.0 * rho * Px) * R2 + 8.0 * rho * x * P * R3);
+    out[12] = eta * ((2.0 * y * lapP + c1 * Py) * R1 + (c2 * y * P + 4.0 * rho * Py) * R2 + 8.0 * rho * y * P * R3);
+    out[13] = eta * ((2.0 * z * lapP + c1 * Pz) * R1 + (c2 * z * P + 4.0 * rho * Pz) * R2 + 8.0 * rho * z * P * R3);
+}
+
+// ---------------------------------------------------------------------------
+// Pade two-body Jastrow u(r) = a r / (1 + F r) and derivatives.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double pade_u(double r, double a, double F) {
+    return a * r / (1.0 + F * r);
+}
+
+struct PadeD {
+    double u, u1, u2, u3;
+};
+
+__host__ __device__ inline PadeD pade_all(double r, double a, double F) {
+    const double q = 1.0 / (1.0 + F * r);
+    const double q2 = q * q;
+    return PadeD{a * r * q, a * q2, -2.0 * a * F * q2 * q, 6.0 * a * F * F * q2 * q2};
+}
+
+}  // namespace vmcx

@@ -1,0 +1,326 @@
+"""Python binding of the C ABI in include/vmc.h (argument marshalling only).
+
+Every step of the path runs in the HIP library ``libvmcx.so``; this module
+passes device pointers of torch tensors and the current HIP stream.  Loading
+fails loudly if the library has not been built (``python -m
+paper_2511_05222_amd.build`` or ``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvmcx.so")
+
+VMC_OK, VMC_EINVAL, VMC_ENOMEM, VMC_EDEVICE, VMC_ESINGULAR, VMC_ENOTCONV, VMC_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+VMC_FP64 = 0
+VMC_SWEEP_MEASURE = 1
+VMC_ACCUM_RESET = 1
+
+EXPORTED = ["vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
+            "vmc_adjoint", "zvector_solve", "vmc_staging_walkers", "vmc_free", "vmc_last_error", "vmc_init_error",
+            "vmc_strerror"]
+
+
+class VmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class _Basis(ct.Structure):
+    _fields_ = [("n_shells", ct.c_int32), ("shell_atom", ct.POINTER(ct.c_int32)),
+                ("shell_l", ct.POINTER(ct.c_int32)), ("shell_nprim", ct.POINTER(ct.c_int32)),
+                ("prim_exp", ct.POINTER(ct.c_double)), ("prim_coef", ct.POINTER(ct.c_double))]
+
+
+class _Nuclei(ct.Structure):
+    _fields_ = [("n_atoms", ct.c_int32), ("xyz", ct.POINTER(ct.c_double)), ("Z", ct.POINTER(ct.c_double))]
+
+
+class _MO(ct.Structure):
+    _fields_ = [("n_ao", ct.c_int32), ("n_occ", ct.c_int32), ("n_up", ct.c_int32), ("n_dn", ct.c_int32),
+                ("C", ct.POINTER(ct.c_double))]
+
+
+class _Jastrow(ct.Structure):
+    _fields_ = [("ee_a", ct.c_double), ("ee_F", ct.c_double)]
+
+
+class _Options(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("refresh_period", ct.c_int32), ("block_sweeps", ct.c_int32),
+                ("max_walkers", ct.c_int32), ("staging_walkers", ct.c_int32), ("step_sigma", ct.c_double)]
+
+
+class _WalkerOut(ct.Structure):
+    _fields_ = [(k, ct.c_void_p) for k in ("EL", "lnpsi", "lnjac", "dEL_dR", "dlnpsi_dR", "dlnjac_dR", "O", "G")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvmcx.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing; run paper_2511_05222_amd/build.py")
+    L = ct.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, dbl = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_uint32, ct.c_uint64, ct.c_double
+    L.vmc_init.argtypes = [ct.POINTER(_Basis), ct.POINTER(_Nuclei), ct.POINTER(_MO), ct.POINTER(_Jastrow),
+                           ct.POINTER(_Options), i32, ct.POINTER(vp)]
+    L.vmc_sweep.argtypes = [vp, vp, i64, i32, u64, u64, u32, vp, vp]
+    L.vmc_accumulate.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp]
+    L.vmc_measure.argtypes = [vp, vp, i64, vp, vp, vp, ct.POINTER(_WalkerOut), vp]
+    L.vmc_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.vmc_energy_cotangents.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp]
+    L.vmc_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.zvector_solve.argtypes = [vp, i64, vp, vp, dbl, i32, ct.POINTER(i32), vp]
+    L.vmc_staging_walkers.argtypes = [vp]
+    L.vmc_staging_walkers.restype = ct.c_int64
+    L.vmc_free.argtypes = [vp]
+    L.vmc_free.restype = None
+    L.vmc_last_error.argtypes = [vp]
+    L.vmc_last_error.restype = ct.c_char_p
+    L.vmc_init_error.argtypes = []
+    L.vmc_init_error.restype = ct.c_char_p
+    L.vmc_strerror.argtypes = [ct.c_int]
+    L.vmc_strerror.restype = ct.c_char_p
+    for name in ("vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
+                 "vmc_adjoint", "zvector_solve"):
+        getattr(L, name).restype = ct.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_dev(t, shape, dtype=None):
+    import torch
+    dtype = dtype or torch.float64
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"expected a contiguous {dtype} device tensor of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device} (contiguous={t.is_contiguous()})")
+
+
+class Context:
+    """A wavefunction on one GPU plus its estimator accumulators."""
+
+    def __init__(self, mol, max_walkers, precision="fp64", refresh_period=32, block_sweeps=1,
+                 step_sigma=0.5, device=0, staging_walkers=0):
+        L = lib()
+        b = mol.basis
+        self._keep = [np.ascontiguousarray(b.shell_atom, np.int32), np.ascontiguousarray(b.shell_l, np.int32),
+                      np.ascontiguousarray(b.shell_nprim, np.int32), np.ascontiguousarray(b.prim_exp, np.float64),
+                      np.ascontiguousarray(b.prim_coef, np.float64), np.ascontiguousarray(mol.xyz, np.float64),
+                      np.ascontiguousarray(mol.Z, np.float64), np.ascontiguousarray(mol.C, np.float64)]
+        k = self._keep
+        ip = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_int32))
+        dp = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_double))
+        basis = _Basis(b.n_shells, ip(k[0]), ip(k[1]), ip(k[2]), dp(k[3]), dp(k[4]))
+        nuc = _Nuclei(mol.n_atoms, dp(k[5]), dp(k[6]))
+        n_ao = int(sum((int(l) + 1) * (int(l) + 2) // 2 for l in b.shell_l))
+        mo = _MO(n_ao, mol.n_occ, mol.n_up, mol.n_dn, dp(k[7]))
+        jas = _Jastrow(mol.jastrow.ee_a, mol.jastrow.ee_F)
+        if getattr(mol.jastrow, "en_on", 0):
+            raise VmcError(VMC_EINVAL, "the electron-nucleus Jastrow factor is not part of the HIP path")
+        prec = {"fp64": VMC_FP64}.get(precision)
+        if prec is None:
+            raise VmcError(VMC_EINVAL, f"precision {precision!r} is not available")
+        opt = _Options(prec, refresh_period, block_sweeps, int(max_walkers), int(staging_walkers), step_sigma)
+        h = ct.c_void_p()
+        rc = L.vmc_init(ct.byref(basis), ct.byref(nuc), ct.byref(mo), ct.byref(jas), ct.byref(opt), device,
+                        ct.byref(h))
+        if rc != VMC_OK:
+            raise VmcError(rc, L.vmc_init_error().decode())
+        self._h = h
+        self.mol = mol
+        self.N, self.A, self.M, self.n_occ = mol.n_elec, mol.n_atoms, n_ao, mol.n_occ
+        self.max_walkers = int(max_walkers)
+        self.device = device
+
+    # ------------------------------------------------------------------
+    def _rc(self, rc):
+        if rc != VMC_OK:
+            raise VmcError(rc, lib().vmc_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vmc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def sweep(self, walkers, nsteps, seed, sweep_offset=0, measure=True, accept=None):
+        import torch
+        W = walkers.shape[0]
+        _check_dev(walkers, (W, self.N, 3))
+        if accept is not None:
+            _check_dev(accept, (nsteps, self.N, W), torch.uint8)
+        self._rc(lib().vmc_sweep(self._h, _ptr(walkers), W, nsteps, ct.c_uint64(seed), ct.c_uint64(sweep_offset),
+                                 VMC_SWEEP_MEASURE if measure else 0, _ptr(accept), _stream()))
+
+    def accumulate(self, reset=True):
+        E = np.zeros(2)
+        F = np.zeros((self.A, 3))
+        dEdC = np.zeros((self.M, self.n_occ))
+        dELdC = np.zeros((self.M, self.n_occ))
+        ns = ct.c_int64(0)
+        dpn = lambda a: a.ctypes.data_as(ct.c_void_p)
+        self._rc(lib().vmc_accumulate(self._h, dpn(E), dpn(F), dpn(dEdC), dpn(dELdC), ct.byref(ns),
+                                      VMC_ACCUM_RESET if reset else 0, _stream()))
+        return dict(E=E[0], E_sigma=E[1], F_bare=F, dE_dC=dEdC, dEL_dC_mean=dELdC, n_samples=ns.value)
+
+    def chunk_walkers(self):
+        return int(lib().vmc_staging_walkers(self._h))
+
+    def measure(self, walkers, C=None, R=None, R0=None, outputs=("EL", "lnpsi", "lnjac", "dEL_dR", "dlnpsi_dR",
+                                                                  "dlnjac_dR", "O", "G")):
+        import torch
+        W = walkers.shape[0]
+        shapes = dict(EL=(W,), lnpsi=(W,), lnjac=(W,), dEL_dR=(W, self.A, 3), dlnpsi_dR=(W, self.A, 3),
+                      dlnjac_dR=(W, self.A, 3), O=(W, self.M, self.n_occ), G=(W, self.M, self.n_occ))
+        res = {k: torch.empty(shapes[k], dtype=torch.float64, device=walkers.device) for k in outputs}
+        return self.measure_into(walkers, res, C, R, R0)
+
+    def measure_into(self, walkers, res, C=None, R=None, R0=None):
+        """Per-walker measurement into the tensors of `res` (keys of vmc_walker_out)."""
+        W = walkers.shape[0]
+        dev = walkers.device
+        _check_dev(walkers, (W, self.N, 3))
+        C = self._dev_C(C, dev)
+        R, R0 = self._dev_R(R, R0, dev)
+        shapes = dict(EL=(W,), lnpsi=(W,), lnjac=(W,), dEL_dR=(W, self.A, 3), dlnpsi_dR=(W, self.A, 3),
+                      dlnjac_dR=(W, self.A, 3), O=(W, self.M, self.n_occ), G=(W, self.M, self.n_occ))
+        for k, t in res.items():
+            _check_dev(t, shapes[k])
+        wo = _WalkerOut(*[res[k].data_ptr() if k in res else None for k in
+                          ("EL", "lnpsi", "lnjac", "dEL_dR", "dlnpsi_dR", "dlnjac_dR", "O", "G")])
+        self._rc(lib().vmc_measure(self._h, _ptr(walkers), W, _ptr(C), _ptr(R), _ptr(R0), ct.byref(wo), _stream()))
+        return res
+
+    def _dev_C(self, C, dev):
+        import torch
+        if C is None:
+            C = torch.as_tensor(np.ascontiguousarray(self.mol.C), dtype=torch.float64, device=dev)
+        _check_dev(C, (self.M, self.n_occ))
+        return C
+
+    def _dev_R(self, R, R0, dev):
+        import torch
+        if R is None:
+            R = torch.as_tensor(np.ascontiguousarray(self.mol.xyz), dtype=torch.float64, device=dev)
+        _check_dev(R, (self.A, 3))
+        if R0 is None:
+            R0 = R
+        _check_dev(R0, (self.A, 3))
+        return R, R0
+
+    def eval(self, walkers, C, R, R0, lnpsi0):
+        import torch
+        W = walkers.shape[0]
+        dev = walkers.device
+        _check_dev(walkers, (W, self.N, 3))
+        _check_dev(lnpsi0, (W,))
+        out = {k: torch.empty(W, dtype=torch.float64, device=dev) for k in ("EL", "lnpsi", "lnjac", "wnorm")}
+        out["Ehat"] = torch.empty(1, dtype=torch.float64, device=dev)
+        self._rc(lib().vmc_eval(self._h, _ptr(walkers), W, _ptr(C), _ptr(R), _ptr(R0), _ptr(lnpsi0),
+                                _ptr(out["EL"]), _ptr(out["lnpsi"]), _ptr(out["lnjac"]), _ptr(out["wnorm"]),
+                                _ptr(out["Ehat"]), _stream()))
+        return out
+
+    def energy_cotangents(self, gE, EL, wnorm, Ehat):
+        import torch
+        W = EL.shape[0]
+        g = {k: torch.empty(W, dtype=torch.float64, device=EL.device) for k in ("gEL", "gPsi", "gJac")}
+        self._rc(lib().vmc_energy_cotangents(self._h, W, float(gE), _ptr(EL), _ptr(wnorm), _ptr(Ehat),
+                                             _ptr(g["gEL"]), _ptr(g["gPsi"]), _ptr(g["gJac"]), _stream()))
+        return g
+
+    def adjoint(self, walkers, C, R, R0, gEL, gPsi, gJac):
+        import torch
+        W = walkers.shape[0]
+        dev = walkers.device
+        for t in (gEL, gPsi, gJac):
+            _check_dev(t, (W,))
+        dC = torch.empty((self.M, self.n_occ), dtype=torch.float64, device=dev)
+        dR = torch.empty((self.A, 3), dtype=torch.float64, device=dev)
+        self._rc(lib().vmc_adjoint(self._h, _ptr(walkers), W, _ptr(C), _ptr(R), _ptr(R0), _ptr(gEL), _ptr(gPsi),
+                                   _ptr(gJac), _ptr(dC), _ptr(dR), _stream()))
+        return dC, dR
+
+
+def zvector_solve(H, b, rtol=1e-12, maxit=1000):
+    """Solve H z = -b by FP64 conjugate gradients on the GPU; returns (z, iterations)."""
+    import torch
+    d = b.shape[0]
+    _check_dev(H, (d, d))
+    _check_dev(b, (d,))
+    z = torch.empty_like(b)
+    it = ct.c_int32(0)
+    rc = lib().zvector_solve(_ptr(H), d, _ptr(b), _ptr(z), float(rtol), int(maxit), ct.byref(it), _stream())
+    if rc != VMC_OK:
+        raise VmcError(rc, lib().vmc_strerror(rc).decode())
+    return z, it.value
+
+
+def _make_energy_function():
+    import torch
+
+    class VMCEnergy(torch.autograd.Function):
+        """Fixed-sample reweighted energy E_hat(C, R) on given walkers.
+
+        forward : E_hat = sum_k w_k E_L,k / sum_k w_k with
+                  w_k = exp(2 (ln|Psi_k(C,R)| - lnpsi0_k)) * Jac_k(R)
+                  (electrons warped with the space-warp weights of R0);
+        backward: exact derivative via the hand-written adjoint kernel;
+                  nothing per walker is saved beyond E_L, the weights and E_hat.
+        """
+
+        @staticmethod
+        def forward(fctx, C, R, context, walkers, R0, lnpsi0):
+            C = C.detach().contiguous()
+            R = R.detach().contiguous()
+            out = context.eval(walkers, C, R, R0, lnpsi0)
+            fctx.context = context
+            fctx.save_for_backward(C, R, walkers, R0, out["EL"], out["wnorm"], out["Ehat"])
+            return out["Ehat"][0].clone()
+
+        @staticmethod
+        def backward(fctx, gE):
+            C, R, walkers, R0, EL, wnorm, Ehat = fctx.saved_tensors
+            context = fctx.context
+            g = context.energy_cotangents(float(gE), EL, wnorm, Ehat)
+            dC, dR = context.adjoint(walkers, C, R, R0, g["gEL"], g["gPsi"], g["gJac"])
+            return dC, dR, None, None, None, None
+
+    return VMCEnergy
+
+
+_VMCEnergy = None
+
+
+def vmc_energy(C, R, context, walkers, R0, lnpsi0):
+    """Differentiable fixed-sample energy (see VMCEnergy)."""
+    global _VMCEnergy
+    if _VMCEnergy is None:
+        _VMCEnergy = _make_energy_function()
+    return _VMCEnergy.apply(C, R, context, walkers, R0, lnpsi0)
