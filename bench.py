@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 METRIC = "walker-steps/s (fwd+adjoint) mixed vs FP64 on 1 GPU; force err Ha/bohr"
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_measure_9atom_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2511_05222_amd", "csrc", "vmc_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2511_05222_amd", "csrc", "vmc_pipeline.hip")
 COPY_BYTES = 1 << 30   # plain device copy used to calibrate the HBM byte counters
+WORKLOADS = {"9atom": 1, "21atom": 2}
 
 
 def measure_flops_per_walker(N, M, n):
@@ -75,6 +76,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--walkers", type=int, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="9atom")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--pmc-probe", action="store_true",
@@ -88,7 +90,7 @@ def main():
     import torch
     from paper_2511_05222_amd import inputs, vmc
 
-    spec = inputs.make_config(1)
+    spec = inputs.make_config(WORKLOADS[args.workload])
     mol = spec.molecule
     W = args.walkers or spec.n_walkers
     dev = torch.device("cuda:0")

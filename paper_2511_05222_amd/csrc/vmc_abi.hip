@@ -16,10 +16,14 @@
 
 #include "vmc.h"
 #include "vmc_kernels.hpp"
+#include "vmc_pipeline.hpp"
 
+using vmcx::AoTiles;
+using vmcx::DenseLayout;
+using vmcx::MeasBufs;
+using vmcx::MeasBufsD;
+using vmcx::SweepWLayout;
 using vmcx::EstArgs;
-using vmcx::MeasLayout;
-using vmcx::SweepLayout;
 using vmcx::SysDev;
 using vmcx::WalkerOut;
 
@@ -59,14 +63,20 @@ struct vmc_ctx {
         *d_shell_np = nullptr;
     double *d_ao_eta = nullptr, *d_prim_exp = nullptr, *d_prim_cp = nullptr, *d_C = nullptr, *d_R = nullptr,
            *d_Z = nullptr;
+    int *d_shell_l = nullptr, *d_shell_mu0 = nullptr;
+    int *d_tile = nullptr;   // [4][n_tiles]: first shell, end shell, first AO, end AO
+    AoTiles tiles{};
     SysDev sys{};
-    SweepLayout sl{};
-    MeasLayout ml{};
+    SweepWLayout swl{};
+    DenseLayout dl{};
 
     int64_t chunk = 0;
     double *st_EL = nullptr, *st_lnpsi = nullptr, *st_lnjac = nullptr, *st_dEdR = nullptr, *st_dPdR = nullptr,
-           *st_dJdR = nullptr, *st_O = nullptr, *st_G = nullptr, *slab = nullptr;
-    double *st_gE = nullptr, *st_gP = nullptr, *st_gJ = nullptr;
+           *st_dJdR = nullptr, *st_O = nullptr, *st_G = nullptr;
+    // measurement pipeline staging (chunk walkers)
+    double *mb_phi = nullptr, *mb_ktil = nullptr, *mb_abar = nullptr, *mb_gb = nullptr, *mb_dpart = nullptr,
+           *mb_tao = nullptr, *mb_posw = nullptr;
+    double *Amo = nullptr;   // [max_walkers][N][n] MO matrix maintained by the sweep
 
     int64_t n_est = 0;
     double *acc = nullptr, *comp = nullptr, *partial = nullptr;
@@ -117,44 +127,66 @@ struct vmc_ctx {
         if (e_ != hipSuccess) return (ctx)->fail(VMC_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// LDS layouts.  Sizes are in doubles; arrays of T = double here.
 static void layouts(vmc_ctx *c) {
     const int N = c->N, n = c->n_occ, M = c->M;
     int o = 0;
-    SweepLayout &s = c->sl;
+    SweepWLayout &s = c->swl;
+    const int nmax = std::max(c->n_up, c->n_dn);
+    s.ldc = M | 1;                        // odd strides: conflict-free per-lane rows
+    s.ldk = nmax | 1;
+    s.cdoubles = ((n * s.ldc + 1) / 2) * 2;   // C (FP64, transposed) resident for the block
     s.pos = o; o += 3 * N;
-    s.K0 = o; o += n * n;
-    s.K1 = o; o += n * n;
-    s.aor = o; o += std::max(M, 1024);
+    s.K = o; o += nmax * s.ldk;           // inverse of the spin block being swept (transposed)
+    s.psi = o; o += M;
     s.phin = o; o += 64;
     s.vrow = o; o += 64;
     s.colj = o; o += 64;
-    s.part = o; o += 256;
-    s.red = o; o += 8;
-    s.misc = o; o += 8;
+    s.gjs = o;             // FP64 refresh scratch: not needed when the inverse is FP64
+    s.col = o; o += 64;
     s.perm = o; o += 32;
-    s.bytes = (size_t)o * sizeof(double);
+    o = (o + 1) & ~1;      // keep every wavefront region 16-byte aligned
+    s.per_wave = o;
+    const size_t per_wave_bytes = (size_t)o * sizeof(double);
+    const size_t c_bytes = (size_t)s.cdoubles * sizeof(double);
+    const size_t avail = 160 * 1024 > c_bytes ? 160 * 1024 - c_bytes : 0;
+    s.wpb = (int)std::min<size_t>(4, avail / per_wave_bytes);
+    s.bytes = c_bytes + per_wave_bytes * std::max(s.wpb, 1);
 
     o = 0;
-    MeasLayout &m = c->ml;
-    m.p0 = o; o += 3 * N;
-    m.p = o; o += 3 * N;
-    m.K0 = o; o += c->n_up * c->n_up;
-    m.K1 = o; o += c->n_dn * c->n_dn;
-    m.X = o; o += N * n;
-    m.U = o; o += std::max(2048, n * n);
-    m.g = o; o += 3 * N;
-    m.h = o; o += N;
-    m.bD = o; o += 3 * N;
-    m.lapD = o; o += N;
-    m.dEdr = o; o += 3 * N;
-    m.tAOE = o; o += 3 * M;
-    m.tAOP = o; o += 3 * M;
-    m.Minv = o; o += 9 * N;
-    m.sg = o; o += 3 * N;
-    m.red = o; o += 8;
-    m.misc = o; o += 8;
-    m.perm = o; o += 32;
-    m.bytes = (size_t)o * sizeof(double);
+    DenseLayout &d = c->dl;
+    d.p = o; o += 3 * N;
+    d.K0 = o; o += c->n_up * c->n_up;
+    d.K1 = o; o += c->n_dn * c->n_dn;
+    d.X = o; o += N * n;
+    d.U = o; o += std::max(64, n * n);
+    d.g = o; o += 3 * N;
+    d.red = o; o += 8;
+    d.perm = o; o += 32;
+    d.bytes = (size_t)o * sizeof(double);
+}
+
+// One measurement of `cw` walkers at positions pos0 (device [cw][N][3]):
+// forward always; adjoint when `full`.  Outputs already offset to the chunk.
+static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double *C, const double *R,
+                       const double *R0, int warp, int full, const WalkerOut &o, hipStream_t st) {
+    const SysDev &S = c->sys;
+    const double *pos = pos0;
+    if (warp) {
+        HIP_OK(c, vmcx::launch_warp(S, R, R0, pos0, c->mb_posw, o.lnjac ? o.lnjac : c->st_lnjac, (int)cw, st));
+        pos = c->mb_posw;
+    } else if (o.lnjac) {
+        HIP_OK(c, hipMemsetAsync(o.lnjac, 0, cw * sizeof(double), st));
+    }
+    MeasBufs<double> mb{pos, pos0, c->mb_phi, full ? c->mb_ktil : nullptr, c->mb_abar, c->mb_gb, c->mb_dpart,
+                        c->mb_tao};
+    HIP_OK(c, vmcx::launch_mo_rows<double>(S, C, R, pos, cw * c->N, c->tiles, c->mb_phi, 5, st));
+    HIP_OK(c, vmcx::launch_walker_dense<double>(S, R, mb, o, c->status, c->dl, (int)cw, st));
+    if (!full) return VMC_OK;
+    HIP_OK(c, vmcx::launch_adjoint_ao<double>(S, C, R, mb, c->tiles, o, (int)cw, st));
+    MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
+    HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, c->tiles.n_tiles, o, warp, (int)cw, st));
+    return VMC_OK;
 }
 
 static int set_device(vmc_ctx *c) {
@@ -255,12 +287,13 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     (void)Zsum;
 
     // ---- fold normalisation -------------------------------------------------
-    std::vector<int> ao_shell, ao_pow, shell_p0(S);
+    std::vector<int> ao_shell, ao_pow, shell_p0(S), shell_mu0(S);
     std::vector<double> ao_eta, cp(P);
     int p0 = 0;
     for (int s = 0; s < S; ++s) {
         const int l = basis->shell_l[s], np = basis->shell_nprim[s];
         shell_p0[s] = p0;
+        shell_mu0[s] = (int)ao_shell.size();
         std::vector<double> cn(np);
         for (int k = 0; k < np; ++k) {
             const double al = basis->prim_exp[p0 + k];
@@ -288,8 +321,32 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         }
     }
 
+    // AO tiles: consecutive whole shells with at most 32 AOs
+    std::vector<int> tiles;   // s0, s1, mu0, mu1 per tile
+    for (int s = 0; s < S;) {
+        int s1 = s, cnt = 0;
+        while (s1 < S && cnt + (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2 <= 32) {
+            cnt += (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2;
+            ++s1;
+        }
+        tiles.push_back(s);
+        tiles.push_back(s1);
+        tiles.push_back(shell_mu0[s]);
+        tiles.push_back(s1 < S ? shell_mu0[s1] : M);
+        s = s1;
+    }
+    const int n_tiles = (int)tiles.size() / 4;
+    std::vector<int> tile_soa(4 * n_tiles);
+    for (int t = 0; t < n_tiles; ++t)
+        for (int k = 0; k < 4; ++k) tile_soa[k * n_tiles + t] = tiles[4 * t + k];
+
     int rc;
     if ((rc = set_device(c))) return bail(rc);
+    if ((rc = c->upload(&c->d_shell_l, (const int *)basis->shell_l, S)) ||
+        (rc = c->upload(&c->d_shell_mu0, shell_mu0.data(), S)) ||
+        (rc = c->upload(&c->d_tile, tile_soa.data(), 4 * n_tiles)))
+        return bail(rc);
+    c->tiles = AoTiles{c->d_tile, c->d_tile + n_tiles, c->d_tile + 2 * n_tiles, c->d_tile + 3 * n_tiles, n_tiles};
     if ((rc = c->upload(&c->d_ao_shell, ao_shell.data(), M)) || (rc = c->upload(&c->d_ao_pow, ao_pow.data(), M)) ||
         (rc = c->upload(&c->d_ao_eta, ao_eta.data(), M)) ||
         (rc = c->upload(&c->d_shell_atom, (const int *)basis->shell_atom, S)) ||
@@ -310,18 +367,21 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     sd.ee_a = c->ee_a;
     sd.ee_F = c->ee_F;
     sd.basis = vmcx::BasisDev{M,          S,           c->d_ao_shell, c->d_ao_pow,   c->d_ao_eta,
-                              c->d_shell_atom, c->d_shell_p0, c->d_shell_np, c->d_prim_exp, c->d_prim_cp};
+                              c->d_shell_atom, c->d_shell_p0, c->d_shell_np, c->d_prim_exp, c->d_prim_cp,
+                              c->d_shell_l, c->d_shell_mu0};
     sd.Z = c->d_Z;
     layouts(c);
-    if (c->sl.bytes > 160 * 1024 || c->ml.bytes > 160 * 1024)
+    if (c->swl.wpb < 1 || c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024)
         return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu / %zu bytes)",
-                            c->sl.bytes, c->ml.bytes));
-    if (vmcx::configure_kernels(c->sl.bytes, c->ml.bytes) != hipSuccess)
+                            c->swl.bytes, c->dl.bytes));
+    if (vmcx::configure_pipeline(c->dl.bytes) != hipSuccess || vmcx::configure_sweep(c->swl.bytes) != hipSuccess)
         return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the kernels"));
 
     // ---- staging and accumulators -------------------------------------------
     const int64_t Mn = (int64_t)M * c->n_occ, A3 = 3 * A;
-    const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + (size_t)c->N * 5 * c->n_occ + 3);
+    const int64_t Nn = (int64_t)c->N * c->n_occ;
+    const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
+                                                        3 * (int64_t)n_tiles * c->N + 6 * M + 3 * c->N);
     int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, opt->max_walkers));
     if (opt->staging_walkers > 0) chunk = std::min<int64_t>(chunk, opt->staging_walkers);
@@ -330,7 +390,11 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->st_lnjac, chunk)) || (rc = c->dalloc(&c->st_dEdR, chunk * A3)) ||
         (rc = c->dalloc(&c->st_dPdR, chunk * A3)) || (rc = c->dalloc(&c->st_dJdR, chunk * A3)) ||
         (rc = c->dalloc(&c->st_O, chunk * Mn)) || (rc = c->dalloc(&c->st_G, chunk * Mn)) ||
-        (rc = c->dalloc(&c->slab, (size_t)chunk * c->N * 5 * c->n_occ)))
+        (rc = c->dalloc(&c->mb_phi, chunk * 5 * Nn)) || (rc = c->dalloc(&c->mb_ktil, chunk * Nn)) ||
+        (rc = c->dalloc(&c->mb_abar, chunk * Nn)) || (rc = c->dalloc(&c->mb_gb, chunk * 6 * c->N)) ||
+        (rc = c->dalloc(&c->mb_dpart, chunk * 3 * (int64_t)n_tiles * c->N)) ||
+        (rc = c->dalloc(&c->mb_tao, chunk * 6 * M)) || (rc = c->dalloc(&c->mb_posw, chunk * 3 * c->N)) ||
+        (rc = c->dalloc(&c->Amo, (size_t)opt->max_walkers * Nn)))
         return bail(rc);
     c->n_est = 2 + 3 * A3 + 3 * Mn;
     const int64_t n_vjp = Mn + A3;
@@ -363,16 +427,18 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
     for (int t = 0; t < nsteps; ++t) {
         const uint32_t sidx = (uint32_t)(sweep_offset + t);
         uint8_t *acc_t = accept ? accept + (size_t)t * c->N * W : nullptr;
-        HIP_OK(c, vmcx::launch_sweep(c->sys, c->d_C, c->d_R, walkers, (int)W, sidx, seed, c->opt.step_sigma,
-                                     c->opt.refresh_period, acc_t, c->status, c->sl, st));
+        // the MO matrix of every walker from scratch, then the moves
+        HIP_OK(c, vmcx::launch_mo_rows<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles, c->Amo, 1, st));
+        HIP_OK(c, vmcx::launch_sweep_w<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, c->Amo, sidx, seed,
+                                               c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
+                                               st));
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
         const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
         double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;
         for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
             const int64_t cw = std::min(c->chunk, W - c0);
-            WalkerOut o{c->st_EL, c->st_lnpsi, c->st_lnjac, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
-            HIP_OK(c, vmcx::launch_measure(c->sys, c->d_C, c->d_R, c->d_R, 0, walkers + c0 * c->N * 3, (int)cw, 1, o,
-                                           c->slab, c->status, c->ml, st));
+            WalkerOut o{c->st_EL, c->st_lnpsi, nullptr, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
+            if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, c->d_C, c->d_R, c->d_R, 0, 1, o, st))) return rc;
             HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
             EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
                       nullptr,  nullptr,    nullptr,    A3,         Mn};
@@ -474,8 +540,7 @@ int vmc_measure(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
         WalkerOut o{off(out->EL, 1),      off(out->lnpsi, 1),  off(out->lnjac, 1),
                     off(out->dEL_dR, A3), off(out->dlnpsi_dR, A3), off(out->dlnjac_dR, A3),
                     off(out->O, Mn),      off(out->G, Mn)};
-        HIP_OK(c, vmcx::launch_measure(c->sys, C, R, R0, warp, walkers + c0 * c->N * 3, (int)cw, full, o, c->slab,
-                                       c->status, c->ml, st));
+        if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, C, R, R0, warp, full, o, st))) return rc;
     }
     return VMC_OK;
 }
@@ -521,8 +586,7 @@ int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
     for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
         const int64_t cw = std::min(c->chunk, W - c0);
         WalkerOut o{c->st_EL, c->st_lnpsi, c->st_lnjac, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
-        HIP_OK(c, vmcx::launch_measure(c->sys, C, R, R0, warp, walkers + c0 * c->N * 3, (int)cw, 1, o, c->slab,
-                                       c->status, c->ml, st));
+        if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, C, R, R0, warp, 1, o, st))) return rc;
         EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, nullptr,
                   gEL + c0, gPsi + c0,  gJac + c0,  A3,         Mn};
         HIP_OK(c, vmcx::launch_reduce(a, 1, nv, cw, c->partial, MAX_SEG, c->vjp_acc, c->vjp_comp, nullptr, st));

@@ -79,7 +79,106 @@ struct BasisDev {
     const int *shell_np;
     const double *prim_exp;
     const double *prim_cp;   // radial coefficient incl. all norms
+    const int *shell_l;
+    const int *shell_mu0;    // first AO of the shell
 };
+
+// Monomial exponents of cartesian component q of a shell with angular
+// momentum l, in the order s; x,y,z; xx,xy,xz,yy,yz,zz (packed a | b<<4 | c<<8).
+__host__ __device__ inline int cart_pow(int l, int q) {
+    const int first = l == 0 ? 0 : (l == 1 ? 1 : 4);
+    const int tab[10] = {0x000, 0x001, 0x010, 0x100, 0x002, 0x011, 0x101, 0x020, 0x110, 0x200};
+    return tab[first + q];
+}
+
+__host__ __device__ inline int n_cart(int l) { return (l + 1) * (l + 2) / 2; }
+
+template <typename T>
+__host__ __device__ inline T tpow(T x, int k) {
+    return k <= 0 ? (k == 0 ? T(1) : T(0)) : (k == 1 ? x : x * x);
+}
+
+// Radial sums of shell s at rho = |r - R_A|^2: R0 = sum c' e^{-a rho} and its
+// first three rho-derivatives (NC > 5 needs R3).
+template <int NC, typename T>
+__host__ __device__ inline void shell_radial(const BasisDev &B, int s, T rho, T &R0, T &R1, T &R2, T &R3) {
+    const int p0 = B.shell_p0[s], np = B.shell_np[s];
+    R0 = R1 = R2 = R3 = T(0);
+    for (int k = 0; k < np; ++k) {
+        const T al = (T)B.prim_exp[p0 + k];
+        const T e = (T)B.prim_cp[p0 + k] * exp(-al * rho);
+        R0 += e;
+        if (NC > 1) {
+            R1 -= al * e;
+            R2 += al * al * e;
+            if (NC > 5) R3 -= al * al * al * e;
+        }
+    }
+}
+
+// Derivative components of one cartesian AO eta x^a y^b z^c R(rho) (x,y,z
+// relative to the centre), written to out[0..NC):
+//   NC = 1  : value
+//   NC = 5  : value, d/dx, d/dy, d/dz, laplacian
+//   NC = 14 : + hessian xx,xy,xz,yy,yz,zz (5..10), d(lap)/dx,dy,dz (11..13)
+// Monomials have l <= 2, so their laplacian is constant.
+template <int NC, typename T>
+__host__ __device__ inline void ao_components(T x, T y, T z, T rho, T R0, T R1, T R2, T R3, int pw, T eta,
+                                              T *out) {
+    const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15;
+    const int l = a + b + c;
+    const T xa = tpow(x, a), yb = tpow(y, b), zc = tpow(z, c);
+    const T P = xa * yb * zc;
+    out[0] = eta * P * R0;
+    if (NC == 1) return;
+    const T Px = T(a) * tpow(x, a - 1) * yb * zc;
+    const T Py = T(b) * xa * tpow(y, b - 1) * zc;
+    const T Pz = T(c) * xa * yb * tpow(z, c - 1);
+    const T Pxx = T(a * (a - 1)) * tpow(x, a - 2) * yb * zc;
+    const T Pyy = T(b * (b - 1)) * xa * tpow(y, b - 2) * zc;
+    const T Pzz = T(c * (c - 1)) * xa * yb * tpow(z, c - 2);
+    const T lapP = Pxx + Pyy + Pzz;
+    const T two = T(2);
+    out[1] = eta * (Px * R0 + two * x * P * R1);
+    out[2] = eta * (Py * R0 + two * y * P * R1);
+    out[3] = eta * (Pz * R0 + two * z * P * R1);
+    // lap[P R(rho)] = lapP R + 4 (x.gradP) R' + P (6 R' + 4 rho R''), x.gradP = l P
+    out[4] = eta * (lapP * R0 + T(4 * l + 6) * P * R1 + T(4) * rho * P * R2);
+    if (NC == 5) return;
+    const T Pxy = T(a * b) * tpow(x, a - 1) * tpow(y, b - 1) * zc;
+    const T Pxz = T(a * c) * tpow(x, a - 1) * yb * tpow(z, c - 1);
+    const T Pyz = T(b * c) * xa * tpow(y, b - 1) * tpow(z, c - 1);
+    const T four = T(4);
+    // d_i d_j [P R] = P_ij R + 2 (x_j P_i + x_i P_j) R' + 2 delta_ij P R' + 4 x_i x_j P R''
+    out[5] = eta * (Pxx * R0 + four * x * Px * R1 + two * P * R1 + four * x * x * P * R2);
+    out[6] = eta * (Pxy * R0 + two * (y * Px + x * Py) * R1 + four * x * y * P * R2);
+    out[7] = eta * (Pxz * R0 + two * (z * Px + x * Pz) * R1 + four * x * z * P * R2);
+    out[8] = eta * (Pyy * R0 + four * y * Py * R1 + two * P * R1 + four * y * y * P * R2);
+    out[9] = eta * (Pyz * R0 + two * (z * Py + y * Pz) * R1 + four * y * z * P * R2);
+    out[10] = eta * (Pzz * R0 + four * z * Pz * R1 + two * P * R1 + four * z * z * P * R2);
+    // d_k lap[P R]: (2 x_k lapP + (4l+6) P_k) R' + ((8l+20) x_k P + 4 rho P_k) R'' + 8 rho x_k P R'''
+    const T c1 = T(4 * l + 6), c2 = T(8 * l + 20), eight = T(8);
+    out[11] = eta * ((two * x * lapP + c1 * Px) * R1 + (c2 * x * P + four * rho * Px) * R2 + eight * rho * x * P * R3);
+    out[12] = eta * ((two * y * lapP + c1 * Py) * R1 + (c2 * y * P + four * rho * Py) * R2 + eight * rho * y * P * R3);
+    out[13] = eta * ((two * z * lapP + c1 * Pz) * R1 + (c2 * z * P + four * rho * Pz) * R2 + eight * rho * z * P * R3);
+}
+
+// All cartesian components of shell s at electron (rx, ry, rz): out[q*NC + k].
+// The displacement is formed in FP64 and then rounded to T.  Returns the
+// number of components.
+template <int NC, typename T>
+__host__ __device__ inline int shell_eval(const BasisDev &B, const double *R, int s, double rx, double ry, double rz,
+                                          T *out) {
+    const int atom = B.shell_atom[s];
+    const T x = (T)(rx - R[3 * atom]), y = (T)(ry - R[3 * atom + 1]), z = (T)(rz - R[3 * atom + 2]);
+    const T rho = x * x + y * y + z * z;
+    T R0, R1, R2, R3;
+    shell_radial<NC, T>(B, s, rho, R0, R1, R2, R3);
+    const int l = B.shell_l[s], mu0 = B.shell_mu0[s], nc = n_cart(l);
+    for (int q = 0; q < nc; ++q)
+        ao_components<NC, T>(x, y, z, rho, R0, R1, R2, R3, cart_pow(l, q), (T)B.ao_eta[mu0 + q], out + q * NC);
+    return nc;
+}
 
 __host__ __device__ inline double ipow(double x, int k) {
     // k in -2..2 for l <= 2 shells; negative powers only appear multiplied by 0

@@ -21,18 +21,6 @@ struct SysDev {
     const double *Z;
 };
 
-// LDS offsets (in doubles) of the sweep kernel
-struct SweepLayout {
-    int pos, K0, K1, aor, phin, vrow, colj, part, red, misc, perm;
-    size_t bytes;
-};
-
-// LDS offsets (in doubles) of the measurement kernel
-struct MeasLayout {
-    int p0, p, K0, K1, X, U, g, h, bD, lapD, dEdr, tAOE, tAOP, Minv, sg, red, misc, perm;
-    size_t bytes;
-};
-
 struct WalkerOut {
     double *EL, *lnpsi, *lnjac, *dEL_dR, *dlnpsi_dR, *dlnjac_dR, *O, *G;
 };
@@ -44,13 +32,6 @@ struct EstArgs {
     int64_t A3, Mn;
 };
 
-hipError_t configure_kernels(size_t sweep_lds, size_t meas_lds);
-hipError_t launch_sweep(const SysDev &S, const double *C, const double *R, double *walkers, int W,
-                        uint32_t sweep, uint64_t seed, double sigma, int refresh_period,
-                        uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st);
-hipError_t launch_measure(const SysDev &S, const double *C, const double *R, const double *R0, int warp,
-                          const double *walkers, int W, int full, const WalkerOut &out, double *slab,
-                          int *status, const MeasLayout &L, hipStream_t st);
 hipError_t launch_reduce(const EstArgs &a, int mode, int64_t n_out, int64_t W, double *partial,
                          int64_t max_seg, double *acc, double *comp, double *blk, hipStream_t st);
 hipError_t launch_set_shift(const double *EL, int64_t W, double *shift, int *shift_set, hipStream_t st);

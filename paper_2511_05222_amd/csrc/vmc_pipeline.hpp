@@ -1,0 +1,69 @@
+// vmc_pipeline.hpp -- argument structs and launchers of vmc_pipeline.hip (internal).
+#pragma once
+
+#include "vmc_kernels.hpp"
+
+namespace vmcx {
+
+// AO tiles: consecutive whole shells with at most 32 AOs each.
+struct AoTiles {
+    const int *s0, *s1, *mu0, *mu1;
+    int n_tiles;
+};
+
+// Per-wavefront LDS offsets (doubles) of k_sweep_w.
+struct SweepWLayout {
+    int pos, K, psi, phin, vrow, colj, gjs, col, perm;
+    int cdoubles;   // doubles of the block-shared C at the start of LDS
+    int ldc;        // row stride (elements, odd) of the transposed C in LDS
+    int ldk;        // row stride (elements, odd) of the transposed inverse
+    int per_wave;   // doubles per wavefront
+    int wpb;        // walkers (wavefronts) per block
+    size_t bytes;   // per block
+};
+
+// LDS offsets (doubles) of k_walker_dense.
+struct DenseLayout {
+    int p, K0, K1, X, U, g, red, perm;
+    size_t bytes;
+};
+
+// Per-walker staging of one measurement launch (chunk of walkers).
+template <typename T>
+struct MeasBufs {
+    const double *pos;    // [W][N][3] evaluation (possibly warped) positions
+    const double *pos0;   // [W][N][3] sampling positions
+    T *phi;               // [W][N][5][n]   MO value, gradient, Laplacian rows
+    T *ktil;              // [W][N][n]      K[i][e] of the electron's spin block
+    T *abar;              // [W][N][n]      dE_L / dA[e][i]
+    double *gb;           // [W][N][6]      Jastrow gradient (0..2), det gradient (3..5)
+    double *dedr_part;    // [W][tiles][N][3]
+    double *tao;          // [W][M][6]      per-AO electron sums of t_k, s_k
+};
+
+struct MeasBufsD {
+    const double *pos, *pos0;
+    const double *gb, *dedr_part, *tao;
+};
+
+template <typename T>
+hipError_t launch_mo_rows(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
+                          const AoTiles &tiles, T *out, int nc, hipStream_t st);
+template <typename T>
+hipError_t launch_sweep_w(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
+                          uint32_t sweep, uint64_t seed, double sigma, int refresh_period, uint8_t *accept,
+                          int *status, const SweepWLayout &L, hipStream_t st);
+hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const double *pos0, double *posw,
+                       double *lnjac, int W, hipStream_t st);
+template <typename T>
+hipError_t launch_walker_dense(const SysDev &S, const double *R, const MeasBufs<T> &mb, const WalkerOut &out,
+                               int *status, const DenseLayout &L, int W, hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_ao(const SysDev &S, const T *C, const double *R, const MeasBufs<T> &mb,
+                             const AoTiles &tiles, const WalkerOut &out, int W, hipStream_t st);
+hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb, int n_tiles,
+                           const WalkerOut &out, int warp, int W, hipStream_t st);
+hipError_t configure_pipeline(size_t dense_lds);
+hipError_t configure_sweep(size_t sweep_lds);
+
+}  // namespace vmcx
