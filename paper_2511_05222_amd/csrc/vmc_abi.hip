@@ -64,8 +64,9 @@ struct vmc_ctx {
     double *d_ao_eta = nullptr, *d_prim_exp = nullptr, *d_prim_cp = nullptr, *d_C = nullptr, *d_R = nullptr,
            *d_Z = nullptr;
     int *d_shell_l = nullptr, *d_shell_mu0 = nullptr;
-    int *d_tile = nullptr;   // [4][n_tiles]: first shell, end shell, first AO, end AO
-    AoTiles tiles{};
+    int *d_tile = nullptr;   // [4][n_tiles]: first shell, end shell, first AO, end AO (<= 32 AOs)
+    int *d_tile16 = nullptr; // same with <= 16 AOs per tile
+    AoTiles tiles{}, tiles16{};
     SysDev sys{};
     SweepWLayout swl{};
     DenseLayout dl{};
@@ -180,7 +181,7 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     }
     MeasBufs<double> mb{pos, pos0, c->mb_phi, full ? c->mb_ktil : nullptr, c->mb_abar, c->mb_gb, c->mb_dpart,
                         c->mb_tao};
-    HIP_OK(c, vmcx::launch_mo_rows<double>(S, C, R, pos, cw * c->N, c->tiles, c->mb_phi, 5, st));
+    HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(S, C, R, pos, cw * c->N, c->tiles16, c->mb_phi, 5, st));
     HIP_OK(c, vmcx::launch_walker_dense<double>(S, R, mb, o, c->status, c->dl, (int)cw, st));
     if (!full) return VMC_OK;
     HIP_OK(c, vmcx::launch_adjoint_ao<double>(S, C, R, mb, c->tiles, o, (int)cw, st));
@@ -321,32 +322,41 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         }
     }
 
-    // AO tiles: consecutive whole shells with at most 32 AOs
-    std::vector<int> tiles;   // s0, s1, mu0, mu1 per tile
-    for (int s = 0; s < S;) {
-        int s1 = s, cnt = 0;
-        while (s1 < S && cnt + (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2 <= 32) {
-            cnt += (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2;
-            ++s1;
+    // AO tiles: consecutive whole shells with at most `cap` AOs, as four
+    // arrays (first shell, end shell, first AO, end AO)
+    auto make_tiles = [&](int cap) {
+        std::vector<int> tl;
+        for (int s = 0; s < S;) {
+            int s1 = s, cnt = 0;
+            while (s1 < S && cnt + (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2 <= cap) {
+                cnt += (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2;
+                ++s1;
+            }
+            tl.push_back(s);
+            tl.push_back(s1);
+            tl.push_back(shell_mu0[s]);
+            tl.push_back(s1 < S ? shell_mu0[s1] : M);
+            s = s1;
         }
-        tiles.push_back(s);
-        tiles.push_back(s1);
-        tiles.push_back(shell_mu0[s]);
-        tiles.push_back(s1 < S ? shell_mu0[s1] : M);
-        s = s1;
-    }
-    const int n_tiles = (int)tiles.size() / 4;
-    std::vector<int> tile_soa(4 * n_tiles);
-    for (int t = 0; t < n_tiles; ++t)
-        for (int k = 0; k < 4; ++k) tile_soa[k * n_tiles + t] = tiles[4 * t + k];
+        const int nt = (int)tl.size() / 4;
+        std::vector<int> soa(4 * nt);
+        for (int t = 0; t < nt; ++t)
+            for (int k = 0; k < 4; ++k) soa[k * nt + t] = tl[4 * t + k];
+        return soa;
+    };
+    const std::vector<int> tile32 = make_tiles(32), tile16 = make_tiles(16);
+    const int n_tiles = (int)tile32.size() / 4, n_tiles16 = (int)tile16.size() / 4;
 
     int rc;
     if ((rc = set_device(c))) return bail(rc);
     if ((rc = c->upload(&c->d_shell_l, (const int *)basis->shell_l, S)) ||
         (rc = c->upload(&c->d_shell_mu0, shell_mu0.data(), S)) ||
-        (rc = c->upload(&c->d_tile, tile_soa.data(), 4 * n_tiles)))
+        (rc = c->upload(&c->d_tile, tile32.data(), 4 * n_tiles)) ||
+        (rc = c->upload(&c->d_tile16, tile16.data(), 4 * n_tiles16)))
         return bail(rc);
     c->tiles = AoTiles{c->d_tile, c->d_tile + n_tiles, c->d_tile + 2 * n_tiles, c->d_tile + 3 * n_tiles, n_tiles};
+    c->tiles16 = AoTiles{c->d_tile16, c->d_tile16 + n_tiles16, c->d_tile16 + 2 * n_tiles16,
+                         c->d_tile16 + 3 * n_tiles16, n_tiles16};
     if ((rc = c->upload(&c->d_ao_shell, ao_shell.data(), M)) || (rc = c->upload(&c->d_ao_pow, ao_pow.data(), M)) ||
         (rc = c->upload(&c->d_ao_eta, ao_eta.data(), M)) ||
         (rc = c->upload(&c->d_shell_atom, (const int *)basis->shell_atom, S)) ||
@@ -428,7 +438,8 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
         const uint32_t sidx = (uint32_t)(sweep_offset + t);
         uint8_t *acc_t = accept ? accept + (size_t)t * c->N * W : nullptr;
         // the MO matrix of every walker from scratch, then the moves
-        HIP_OK(c, vmcx::launch_mo_rows<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles, c->Amo, 1, st));
+        HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16, c->Amo, 1,
+                                                   st));
         HIP_OK(c, vmcx::launch_sweep_w<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, c->Amo, sidx, seed,
                                                c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
                                                st));

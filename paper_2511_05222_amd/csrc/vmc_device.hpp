@@ -180,6 +180,42 @@ __host__ __device__ inline int shell_eval(const BasisDev &B, const double *R, in
     return nc;
 }
 
+// shell_eval with the angular momentum fixed at compile time, so that every
+// component index is a constant and nothing lands in per-lane scratch:
+// components are stored straight to dst[q*NC + k] (LDS or registers).
+template <int NC, typename T, int L>
+__host__ __device__ inline void shell_components(const BasisDev &B, int mu0, T x, T y, T z, T rho, T R0, T R1,
+                                                 T R2, T R3, T *dst) {
+#pragma unroll
+    for (int q = 0; q < (L + 1) * (L + 2) / 2; ++q) {
+        T o[NC];
+        ao_components<NC, T>(x, y, z, rho, R0, R1, R2, R3, cart_pow(L, q), (T)B.ao_eta[mu0 + q], o);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) dst[q * NC + k] = o[k];
+    }
+}
+
+template <int NC, typename T>
+__host__ __device__ inline int shell_eval_to(const BasisDev &B, const double *R, int s, double rx, double ry,
+                                             double rz, T *dst) {
+    const int atom = B.shell_atom[s];
+    const T x = (T)(rx - R[3 * atom]), y = (T)(ry - R[3 * atom + 1]), z = (T)(rz - R[3 * atom + 2]);
+    const T rho = x * x + y * y + z * z;
+    T R0, R1, R2, R3;
+    shell_radial<NC, T>(B, s, rho, R0, R1, R2, R3);
+    const int l = B.shell_l[s], mu0 = B.shell_mu0[s];
+    if (l == 0) {
+        shell_components<NC, T, 0>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
+        return 1;
+    }
+    if (l == 1) {
+        shell_components<NC, T, 1>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
+        return 3;
+    }
+    shell_components<NC, T, 2>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
+    return 6;
+}
+
 __host__ __device__ inline double ipow(double x, int k) {
     // k in -2..2 for l <= 2 shells; negative powers only appear multiplied by 0
     return k <= 0 ? (k == 0 ? 1.0 : 0.0) : (k == 1 ? x : x * x);

@@ -1,0 +1,138 @@
+// vmc_mo.hip -- MO rows of every (walker, electron) on the matrix cores.
+//
+//   out[row][c][i] = sum_mu AO_c(r_row)[mu] C[mu][i],   c < NC
+//   (NC = 1: values;  NC = 5: value, gradient, Laplacian)
+//
+// A block owns 64 rows (one 16-row tile per wavefront) and all n orbitals
+// (NT tiles of 16 columns).  AO tiles of whole shells (<= 16 AOs) are
+// produced in LDS by a shell-major GTO evaluation and consumed in k-steps of
+// 4 AOs by 16x16x4 MFMA (FP64: v_mfma_f64_16x16x4_f64; FP32:
+// v_mfma_f32_16x16x4_f32), accumulating in the arithmetic type T.
+#include "vmc_pipeline.hpp"
+
+namespace vmcx {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+    typedef v4d acc_t;
+    __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static acc_t fma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // row of accumulator register v held by lane l (column l % 16)
+    __device__ static int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+template <>
+struct Mfma<float> {
+    typedef v4f acc_t;
+    __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static acc_t fma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+template <typename T, int NC, int NT>
+__global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restrict__ C, const double *__restrict__ R,
+                                                      const double *__restrict__ pos, int64_t n_rows, AoTiles tiles,
+                                                      T *__restrict__ out) {
+    constexpr int RB = 64, MT = 16;
+    constexpr int RS = MT * NC + 1;    // odd row stride of the AO tile
+    constexpr int CS = 80;             // row stride of the C tile (lane groups hit disjoint banks)
+    __shared__ double sp[RB * 3];
+    __shared__ T aot[RB * RS];
+    __shared__ T ct[MT * CS];
+    typedef Mfma<T> MF;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = S.n_occ;
+    const int64_t row0 = (int64_t)blockIdx.x * RB;
+    for (int k = tid; k < RB * 3; k += 256) sp[k] = (row0 + k / 3) < n_rows ? pos[row0 * 3 + k] : 0.0;
+    typename MF::acc_t acc[NC][NT];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[c][t] = MF::zero();
+    const int ar = wave * 16 + (lane & 15);   // A-operand row of this lane
+    const int ak = lane >> 4;                 // A-operand k (AO within the k-step)
+    for (int tile = 0; tile < tiles.n_tiles; ++tile) {
+        const int s0 = tiles.s0[tile], s1 = tiles.s1[tile], mu0 = tiles.mu0[tile], mu1 = tiles.mu1[tile];
+        const int nsh = s1 - s0, nmu = mu1 - mu0;
+        __syncthreads();
+        for (int p = tid; p < RB * nsh; p += 256) {
+            const int r = p / nsh, s = s0 + (p - (p / nsh) * nsh);
+            shell_eval_to<NC, T>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
+                                 aot + r * RS + (S.basis.shell_mu0[s] - mu0) * NC);
+        }
+        // zero the padding AOs of the tile
+        for (int p = tid; p < RB * (MT - nmu) * NC; p += 256) {
+            const int r = p / ((MT - nmu) * NC), q = p - r * ((MT - nmu) * NC);
+            aot[r * RS + nmu * NC + q] = T(0);
+        }
+        for (int p = tid; p < MT * 64; p += 256) {
+            const int m = p >> 6, i = p & 63;
+            ct[m * CS + i] = (m < nmu && i < n) ? C[(size_t)(mu0 + m) * n + i] : T(0);
+        }
+        __syncthreads();
+        const int ksteps = (nmu + 3) >> 2;
+        for (int ks = 0; ks < ksteps; ++ks) {
+            const int m = ks * 4 + ak;
+            T a[NC], b[NT];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a[c] = aot[ar * RS + m * NC + c];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) b[t] = ct[m * CS + t * 16 + (lane & 15)];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[c][t] = MF::fma(a[c], b[t], acc[c][t]);
+        }
+    }
+    const int col = lane & 15;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int64_t row = row0 + wave * 16 + MF::row(lane, v);
+        if (row >= n_rows) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int i = t * 16 + col;
+                if (i < n) out[(row * NC + c) * n + i] = acc[c][t][v];
+            }
+    }
+}
+
+template <typename T, int NC>
+static hipError_t launch_nc(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
+                            const AoTiles &tiles, T *out, hipStream_t st) {
+    const dim3 g((unsigned)((n_rows + 63) / 64));
+    const int nt = (S.n_occ + 15) / 16;
+    if (nt == 1)
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 1>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+    else if (nt == 2)
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 2>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+    else if (nt == 3)
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 3>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+    else
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 4>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
+                               const AoTiles &tiles16, T *out, int nc, hipStream_t st) {
+    return nc == 1 ? launch_nc<T, 1>(S, C, R, pos, n_rows, tiles16, out, st)
+                   : launch_nc<T, 5>(S, C, R, pos, n_rows, tiles16, out, st);
+}
+
+template hipError_t launch_mo_rows_mfma<double>(const SysDev &, const double *, const double *, const double *,
+                                                int64_t, const AoTiles &, double *, int, hipStream_t);
+
+}  // namespace vmcx

@@ -50,6 +50,9 @@ template <typename T>
 hipError_t launch_mo_rows(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
                           const AoTiles &tiles, T *out, int nc, hipStream_t st);
 template <typename T>
+hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
+                               const AoTiles &tiles16, T *out, int nc, hipStream_t st);
+template <typename T>
 hipError_t launch_sweep_w(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
                           uint32_t sweep, uint64_t seed, double sigma, int refresh_period, uint8_t *accept,
                           int *status, const SweepWLayout &L, hipStream_t st);
