@@ -22,7 +22,7 @@ using vmcx::AoTiles;
 using vmcx::DenseLayout;
 using vmcx::MeasBufs;
 using vmcx::MeasBufsD;
-using vmcx::SweepWLayout;
+using vmcx::SweepLayout;
 using vmcx::EstArgs;
 using vmcx::SysDev;
 using vmcx::WalkerOut;
@@ -68,7 +68,7 @@ struct vmc_ctx {
     int *d_tile16 = nullptr; // same with <= 16 AOs per tile
     AoTiles tiles{}, tiles16{};
     SysDev sys{};
-    SweepWLayout swl{};
+    SweepLayout swl{};   // k_sweep_r, FP64
     DenseLayout dl{};
 
     int64_t chunk = 0;
@@ -128,33 +128,44 @@ struct vmc_ctx {
         if (e_ != hipSuccess) return (ctx)->fail(VMC_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-// LDS layouts.  Sizes are in doubles; arrays of T = double here.
-static void layouts(vmc_ctx *c) {
-    const int N = c->N, n = c->n_occ, M = c->M;
-    int o = 0;
-    SweepWLayout &s = c->swl;
-    const int nmax = std::max(c->n_up, c->n_dn);
-    s.ldc = M | 1;                        // odd strides: conflict-free per-lane rows
-    s.ldk = nmax | 1;
-    s.cdoubles = ((n * s.ldc + 1) / 2) * 2;   // C (FP64, transposed) resident for the block
-    s.pos = o; o += 3 * N;
-    s.K = o; o += nmax * s.ldk;           // inverse of the spin block being swept (transposed)
-    s.psi = o; o += M;
-    s.phin = o; o += 64;
-    s.vrow = o; o += 64;
-    s.colj = o; o += 64;
-    s.gjs = o;             // FP64 refresh scratch: not needed when the inverse is FP64
-    s.col = o; o += 64;
-    s.perm = o; o += 32;
-    o = (o + 1) & ~1;      // keep every wavefront region 16-byte aligned
-    s.per_wave = o;
-    const size_t per_wave_bytes = (size_t)o * sizeof(double);
-    const size_t c_bytes = (size_t)s.cdoubles * sizeof(double);
-    const size_t avail = 160 * 1024 > c_bytes ? 160 * 1024 - c_bytes : 0;
-    s.wpb = (int)std::min<size_t>(4, avail / per_wave_bytes);
-    s.bytes = c_bytes + per_wave_bytes * std::max(s.wpb, 1);
+// LDS layout of the sweep for an arithmetic type of ts bytes.
+static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
+    SweepLayout s{};
+    const int n = c->n_occ, M = c->M;
+    auto al = [](size_t b) { return (int)((b + 15) & ~(size_t)15); };
+    s.ldc = M | 1;   // odd stride: lanes walking their own row hit distinct banks
+    size_t o = al((size_t)n * s.ldc * ts);
+    s.off_R = (int)o;
+    o += al((size_t)3 * c->A * sizeof(double));
+    s.off_pexp = (int)o;
+    o += al((size_t)c->P * ts);
+    s.off_pcp = (int)o;
+    o += al((size_t)c->P * ts);
+    s.off_sha = (int)o;
+    o += al((size_t)c->S * 4);
+    s.off_shb = (int)o;
+    o += al((size_t)c->S * 4);
+    s.block_bytes = (int)o;
+    const int kn = vmcx::sweep_kn(n);
+    size_t w = 0;
+    s.off_psi = 0;
+    w += al((size_t)M * ts);
+    s.off_phin = (int)w;
+    w += al((size_t)kn * ts);
+    s.off_colj = (int)w;
+    w += al((size_t)kn * ts);
+    s.wave_bytes = (int)w;
+    int wpb = 8;
+    while (wpb > 1 && o + (size_t)wpb * w > 160 * 1024) --wpb;
+    s.wpb = wpb;
+    s.bytes = o + (size_t)wpb * w;
+    return s;
+}
 
-    o = 0;
+// LDS layout of k_walker_dense.  Sizes are in doubles.
+static void layouts(vmc_ctx *c) {
+    const int N = c->N, n = c->n_occ;
+    int o = 0;
     DenseLayout &d = c->dl;
     d.p = o; o += 3 * N;
     d.K0 = o; o += c->n_up * c->n_up;
@@ -259,6 +270,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     }
     if (M != mo->n_ao) return bail(c->fail(VMC_EINVAL, "n_ao = %d but the shells give %d AOs", mo->n_ao, M));
     if (M > VMC_MAX_AO) return bail(c->fail(VMC_EINVAL, "n_ao = %d exceeds %d", M, VMC_MAX_AO));
+    if (P >= 32768) return bail(c->fail(VMC_EINVAL, "%d primitives exceed 32767", P));
     if (mo->n_up != mo->n_dn || mo->n_up < 1 || mo->n_occ != mo->n_up)
         return bail(c->fail(VMC_EINVAL, "need a closed shell with n_up = n_dn = n_occ >= 1 (got %d, %d, %d)",
                             mo->n_up, mo->n_dn, mo->n_occ));
@@ -381,10 +393,12 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
                               c->d_shell_l, c->d_shell_mu0};
     sd.Z = c->d_Z;
     layouts(c);
-    if (c->swl.wpb < 1 || c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024)
+    c->swl = sweep_layout(c, sizeof(double));
+    if (c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024)
         return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu / %zu bytes)",
                             c->swl.bytes, c->dl.bytes));
-    if (vmcx::configure_pipeline(c->dl.bytes) != hipSuccess || vmcx::configure_sweep(c->swl.bytes) != hipSuccess)
+    if (vmcx::configure_pipeline(c->dl.bytes) != hipSuccess ||
+        vmcx::configure_sweep<double>(c->swl.bytes) != hipSuccess)
         return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the kernels"));
 
     // ---- staging and accumulators -------------------------------------------
@@ -437,12 +451,14 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
     for (int t = 0; t < nsteps; ++t) {
         const uint32_t sidx = (uint32_t)(sweep_offset + t);
         uint8_t *acc_t = accept ? accept + (size_t)t * c->N * W : nullptr;
-        // the MO matrix of every walker from scratch, then the moves
-        HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16, c->Amo, 1,
-                                                   st));
-        HIP_OK(c, vmcx::launch_sweep_w<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, c->Amo, sidx, seed,
-                                               c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
-                                               st));
+        // the MO matrix of every walker from the caller's positions; the
+        // sweeps keep it current (row e rewritten on each accepted move)
+        if (t == 0)
+            HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
+                                                       c->Amo, 1, st));
+        HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, c->Amo, sidx, seed,
+                                             c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
+                                             st));
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
         const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
         double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;

@@ -11,15 +11,25 @@ struct AoTiles {
     int n_tiles;
 };
 
-// Per-wavefront LDS offsets (doubles) of k_sweep_w.
-struct SweepWLayout {
-    int pos, K, psi, phin, vrow, colj, gjs, col, perm;
-    int cdoubles;   // doubles of the block-shared C at the start of LDS
-    int ldc;        // row stride (elements, odd) of the transposed C in LDS
-    int ldk;        // row stride (elements, odd) of the transposed inverse
-    int per_wave;   // doubles per wavefront
-    int wpb;        // walkers (wavefronts) per block
-    size_t bytes;   // per block
+// LDS layout of k_sweep_r (bytes): a block-shared region (C transposed with
+// odd row stride ldc, then the basis tables) followed by wpb wavefront regions.
+struct SweepLayout {
+    int ldc;                                        // row stride of Ct (elements)
+    int off_R, off_pexp, off_pcp, off_sha, off_shb;  // basis tables
+    int block_bytes;                                // block-shared region
+    int off_psi, off_phin, off_colj;                // within a wavefront region
+    int wave_bytes;
+    int wpb;                                        // walkers (wavefronts) per block
+    size_t bytes;                                   // per block
+};
+
+// Basis tables of the sweep in LDS: atom centres [A][3]; primitive exponents
+// and folded coefficients (type T); per shell atom | l << 8 | nprim << 12 and
+// first AO | first primitive << 16.
+struct SweepBasisLds {
+    double *R;
+    void *pexp, *pcp;
+    int *sha, *shb;
 };
 
 // LDS offsets (doubles) of k_walker_dense.
@@ -52,10 +62,11 @@ hipError_t launch_mo_rows(const SysDev &S, const T *C, const double *R, const do
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
                                const AoTiles &tiles16, T *out, int nc, hipStream_t st);
+int sweep_kn(int n_occ);
 template <typename T>
-hipError_t launch_sweep_w(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
-                          uint32_t sweep, uint64_t seed, double sigma, int refresh_period, uint8_t *accept,
-                          int *status, const SweepWLayout &L, hipStream_t st);
+hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo, uint32_t sweep,
+                        uint64_t seed, double sigma, int refresh_period, uint8_t *accept, int *status,
+                        const SweepLayout &L, hipStream_t st);
 hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const double *pos0, double *posw,
                        double *lnjac, int W, hipStream_t st);
 template <typename T>
@@ -67,6 +78,7 @@ hipError_t launch_adjoint_ao(const SysDev &S, const T *C, const double *R, const
 hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb, int n_tiles,
                            const WalkerOut &out, int warp, int W, hipStream_t st);
 hipError_t configure_pipeline(size_t dense_lds);
-hipError_t configure_sweep(size_t sweep_lds);
+template <typename T>
+hipError_t configure_sweep(size_t lds);
 
 }  // namespace vmcx

@@ -1,19 +1,22 @@
 // vmc_sweep.hip -- single-electron Metropolis sweeps on gfx950.
 //
-// One wavefront per walker, L.wpb walkers per block.  The MO coefficients C
-// stay resident in LDS for the whole sweep and are shared by the block's
-// walkers (every proposed move needs phi(r') = psi(r')^T C, i.e. all of C).
-// The MO matrix A[e][i] = phi_i(r_e) of every walker lives in HBM (built by
-// k_mo_rows before the sweep; row e rewritten on each accepted move of e).
-// Only the inverse K of the spin block being swept is kept in LDS; it is
-// rebuilt from A in FP64 when the sweep reaches the block's first electron
-// (no electron of that block has moved yet in this sweep, so this equals an
-// inverse built at the start of the sweep), after every refresh_period-th
-// proposed move, and after an accepted move with |ratio| < 1e-8.
-// The random numbers of all N moves are drawn lane-parallel at sweep start
-// (lane l draws for electrons l and l + 64) and read with readlane per move.
-#include <type_traits>
-
+// One wavefront per walker, L.wpb walkers per block.  Shared by the block in
+// LDS: the MO coefficients C (transposed, odd row stride; every proposed move
+// needs phi(r') = psi(r')^T C, i.e. all of C) and the basis tables (atom
+// centres, primitives, packed shell descriptors).  Per wavefront in LDS: the
+// AO values psi(r') and two broadcast vectors.  Everything else of the walker
+// lives in registers:
+//   * positions: lane l holds electrons l and l + 64;
+//   * the draws of this sweep: lane l holds those of electrons l and l + 64;
+//   * the inverse K of the spin block being swept: KN registers per lane,
+//     lane p_k holding column k (electron k of the block), register r holding
+//     orbital p_r, where p is the pivot order of the last rebuild (gj_regs).
+// The MO matrix A[e][i] = phi_i(r_e) of every walker lives in HBM (type T);
+// row e is rewritten on each accepted move of e.  K is rebuilt from A in FP64
+// at the block's first electron (no electron of the block has moved yet in
+// this sweep, so this equals an inverse built at the start of the sweep),
+// after every refresh_period-th proposed move that is not the block's last,
+// and after an accepted move with |ratio| < 1e-8.
 #include "vmc_pipeline.hpp"
 
 namespace vmcx {
@@ -30,21 +33,31 @@ __device__ inline double readlane_d(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Gauss-Jordan inversion with partial pivoting (FP64, n <= 64) by one
-// wavefront, on a matrix stored transposed: at[j*ld + i] = a[i][j] (ld odd,
-// so that lanes walking their own column are free of LDS bank conflicts).
-// The pivot of column k is the largest |a[i][k]|, i >= k.  On return
-// at[j*ld + i] = inverse[i][j].  col: n doubles.  log|det|, the singular
-// flag and the permutation are uniform across the wavefront.
-__device__ void gj_invert_wave_t(double *at, int n, int ld, double *col, int *perm, double &logabs, bool &singular) {
+__device__ inline float readlane_t(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double readlane_t(double v, int src) { return readlane_d(v, src); }
+
+// In-register Gauss-Jordan inversion (FP64) with partial pivoting by implicit
+// row choice.  The matrix is B = A^T of the spin block, padded to KN x KN with
+// an identity block: on entry lane c holds row c of B in Br[0..KN) (lanes >=
+// KN hold zeros and never pivot).  Step k eliminates column k, which a
+// rotation keeps in Br[0]: after the step every register moves down by one and
+// the new column k enters at Br[KN-1], so after KN steps the registers are
+// back in order.  The pivot of step k is the unused lane with the largest
+// |B[.][k]| (ties: lowest lane).  With p_k the pivot lane of step k the result
+// is R[p_k][j] = B^-1[k][p_j], i.e. lane p_k holds column k of K = A^-1 with
+// register j holding orbital p_j.  On return sig = k on lane p_k (lanes >= KN:
+// sig = lane).  A pivot with |pivot| <= 1e-300 or NaN sets bad.
+template <int KN>
+__device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad) {
     const int lane = threadIdx.x & 63;
-    const bool on = lane < n;
-    double *mine = at + lane * ld;   // column `lane` of a
-    double la = 0.0;
-    bool sing = false;
-    for (int k = 0; k < n; ++k) {
-        const double *ck = at + k * ld;   // column k of a
-        double best = (on && lane >= k) ? fabs(ck[lane]) : -1.0;
+    bool used = lane >= KN;
+    sig = lane;
+    for (int k = 0; k < KN; ++k) {
+        const double a0 = Br[0];
+        const double fa = fabs(a0);
+        double best = used ? -1.0 : (fa == fa ? fa : -0.5);
         int bi = lane;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -55,154 +68,166 @@ __device__ void gj_invert_wave_t(double *at, int n, int ld, double *col, int *pe
                 bi = oi;
             }
         }
-        const int p = bi < n ? bi : k;   // no comparable pivot (non-finite column): keep the row order
-        if (lane == 0) perm[k] = p;
-        if (p != k && on) {
-            const double t = mine[k];
-            mine[k] = mine[p];
-            mine[p] = t;
-        }
-        wave_sync_s();
-        double cv = 0.0;
-        if (on) {
-            cv = ck[lane];
-            col[lane] = lane == k ? 0.0 : cv;
-        }
-        wave_sync_s();
-        const double piv = readlane_d(cv, k);
-        if (!(fabs(piv) > 1e-300)) sing = true;
-        la += log(fabs(piv));
+        const int p = __builtin_amdgcn_readfirstlane(bi);
+        const double piv = readlane_d(a0, p);
+        if (!(fabs(piv) > 1e-300)) bad = true;
         const double inv = 1.0 / piv;
-        if (on) {
-            const double rk = (lane == k) ? inv : mine[k] * inv;
-            if (lane == k)
-                for (int i = 0; i < n; ++i) mine[i] = 0.0;
-            mine[k] = rk;
-            // a[i][lane] -= col[i] rk (col[k] = 0 keeps row k)
-            int i = 0;
-            for (; i + 4 <= n; i += 4) {
-                mine[i] -= col[i] * rk;
-                mine[i + 1] -= col[i + 1] * rk;
-                mine[i + 2] -= col[i + 2] * rk;
-                mine[i + 3] -= col[i + 3] * rk;
-            }
-            for (; i < n; ++i) mine[i] -= col[i] * rk;
+        const bool me = lane == p;
+        if (me) {
+            used = true;
+            sig = k;
         }
-        wave_sync_s();
-    }
-    // undo the row interchanges as column interchanges: lane = row
-    for (int k = n - 1; k >= 0; --k) {
-        const int p = perm[k];
-        if (p != k && on) {
-            const double t = at[k * ld + lane];
-            at[k * ld + lane] = at[p * ld + lane];
-            at[p * ld + lane] = t;
+        // pivot row: B[p][j] / piv;  other rows: B[i][j] - (B[i][k] / piv) B[p][j]
+        const double g = me ? -inv : a0 * inv;
+        const double h = me ? 0.0 : 1.0;
+#pragma unroll
+        for (int r = 0; r + 1 < KN; ++r) {
+            const double pr = readlane_d(Br[r + 1], p);
+            Br[r] = fma(-g, pr, h * Br[r + 1]);
         }
-        wave_sync_s();
+        Br[KN - 1] = me ? inv : -a0 * inv;
     }
-    logabs = la;
-    singular = sing;
 }
 
-// Kt = inverse of the spin block [off, off + nb) of the walker's MO matrix,
-// stored transposed: Kt[c*ld + i] = K[i][c] (K[i][c] pairs orbital i with
-// electron c of the block).
-template <typename T>
-__device__ void refresh_spin(const T *Aw, int n, int off, int nb, T *Kt, int ld, double *gjs, double *col, int *perm,
-                             bool &bad) {
+// Rebuild the inverse of spin block [off, off + nb) from the walker's MO
+// matrix Aw ([N][n], type T) into Kr, in the layout of gj_regs.
+template <typename T, int KN>
+__device__ inline void rebuild(const T *Aw, int n, int off, int nb, T (&Kr)[KN], int &sig, bool &bad) {
     const int lane = threadIdx.x & 63;
     // rows of A were written by this wavefront: make them visible to its loads
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-    constexpr bool in_place = std::is_same<T, double>::value;
-    double *at = in_place ? (double *)Kt : gjs;
-    // at[i*ld + e] = A[e][i]: column i of the Slater matrix (orbital i)
-    if (lane < nb)
-        for (int e = 0; e < nb; ++e) at[lane * ld + e] = (double)Aw[(size_t)(off + e) * n + lane];
-    wave_sync_s();
-    double la;
-    bool sing;
-    gj_invert_wave_t(at, nb, ld, col, perm, la, sing);
-    bad |= sing;
-    if (!in_place) {
-        if (lane < nb)
-            for (int i = 0; i < nb; ++i) Kt[lane * ld + i] = (T)at[lane * ld + i];
-        wave_sync_s();
+    // an opaque copy of the lane id keeps the KN padding values from being
+    // hoisted out of the sweep loop (they would stay live in registers)
+    int lz = lane;
+    asm volatile("" : "+v"(lz));
+    double Br[KN];
+#pragma unroll
+    for (int r = 0; r < KN; ++r) {
+        double v = (lz == r && r >= nb) ? 1.0 : 0.0;   // identity padding
+        if (lz < nb && r < nb) v = (double)Aw[(size_t)(off + r) * n + lz];
+        Br[r] = v;
+    }
+    gj_regs<KN>(Br, sig, bad);
+#pragma unroll
+    for (int r = 0; r < KN; ++r) Kr[r] = (T)Br[r];
+}
+
+// Values of the AOs of shell s at (rx, ry, rz) into psi, from the basis tables
+// in LDS.  Component factors: 1/sqrt(3) for xx, yy, zz; 1 otherwise.
+template <typename T>
+__device__ inline void shell_values_lds(const SweepBasisLds &B, int s, double rx, double ry, double rz, T *psi) {
+    const int sa = B.sha[s], sb = B.shb[s];
+    const int atom = sa & 255, l = (sa >> 8) & 15, np = sa >> 12;
+    const int mu0 = sb & 0xFFFF, p0 = sb >> 16;
+    const T x = (T)(rx - B.R[3 * atom]), y = (T)(ry - B.R[3 * atom + 1]), z = (T)(rz - B.R[3 * atom + 2]);
+    const T rho = x * x + y * y + z * z;
+    const T *pe = (const T *)B.pexp + p0, *pc = (const T *)B.pcp + p0;
+    T r0 = T(0);
+    for (int k = 0; k < np; ++k) r0 += pc[k] * exp(-pe[k] * rho);
+    T *o = psi + mu0;
+    if (l == 0) {
+        o[0] = r0;
+    } else if (l == 1) {
+        o[0] = x * r0;
+        o[1] = y * r0;
+        o[2] = z * r0;
+    } else {
+        const T e3 = T(0.57735026918962576451);   // 1/sqrt(3)
+        o[0] = e3 * (x * x) * r0;
+        o[1] = (x * y) * r0;
+        o[2] = (x * z) * r0;
+        o[3] = e3 * (y * y) * r0;
+        o[4] = (y * z) * r0;
+        o[5] = e3 * (z * z) * r0;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_sweep_w(SysDev S, const T *__restrict__ Cg, const double *__restrict__ R,
+template <typename T, int KN>
+__global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__ Cg, const double *__restrict__ R,
                                                   double *walkers, int W, T *Amo, uint32_t sweep, uint64_t seed,
                                                   double sigma, int refresh_period, uint8_t *accept, int *status,
-                                                  SweepWLayout L) {
-    extern __shared__ double smem[];
+                                                  SweepLayout L) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int N = S.N, nu = S.n_up, n = S.n_occ, M = S.M;
-    // C resident in LDS for the block, transposed: Ct[i*L.ldc + mu] = C[mu][i]
+    const int N = S.N, nu = S.n_up, n = S.n_occ, M = S.M, NS = S.basis.n_shells;
+    // block-shared: C transposed (Ct[i*ldc + mu] = C[mu][i]) and the basis
     T *Ct = (T *)smem;
     const int ldc = L.ldc;
+    SweepBasisLds B{(double *)(smem + L.off_R), smem + L.off_pexp, smem + L.off_pcp, (int *)(smem + L.off_sha),
+                    (int *)(smem + L.off_shb)};
     for (int k = threadIdx.x; k < M * n; k += blockDim.x) {
         const int mu = k / n, i = k - (k / n) * n;
         Ct[i * ldc + mu] = Cg[k];
     }
+    for (int k = threadIdx.x; k < 3 * S.A; k += blockDim.x) B.R[k] = R[k];
+    for (int k = threadIdx.x; k < NS; k += blockDim.x) {
+        const int p0 = S.basis.shell_p0[k], np = S.basis.shell_np[k];
+        B.sha[k] = S.basis.shell_atom[k] | (S.basis.shell_l[k] << 8) | (np << 12);
+        B.shb[k] = S.basis.shell_mu0[k] | (p0 << 16);
+        for (int q = 0; q < np; ++q) {
+            ((T *)B.pexp)[p0 + q] = (T)S.basis.prim_exp[p0 + q];
+            ((T *)B.pcp)[p0 + q] = (T)S.basis.prim_cp[p0 + q];
+        }
+    }
     __syncthreads();
     const int w = blockIdx.x * (int)(blockDim.x >> 6) + wave;
     if (w >= W) return;   // no block barrier follows
-    double *base = smem + L.cdoubles + (size_t)wave * L.per_wave;
-    double *pos = base + L.pos;
-    T *K = (T *)(base + L.K);
-    T *psi = (T *)(base + L.psi);
-    T *phin = (T *)(base + L.phin);
-    T *colj = (T *)(base + L.colj);
-    double *gjs = base + L.gjs;
-    double *col = base + L.col;
-    int *perm = (int *)(base + L.perm);
+    unsigned char *wbase = smem + L.block_bytes + (size_t)wave * L.wave_bytes;
+    T *psi = (T *)(wbase + L.off_psi);
+    T *phin = (T *)(wbase + L.off_phin);   // phin[r] = phi_{p_r}
+    T *colj = (T *)(wbase + L.off_colj);   // column of the moved electron
     double *wp = walkers + (size_t)w * N * 3;
     T *Aw = Amo + (size_t)w * N * n;
-    for (int i = lane; i < 3 * N; i += 64) pos[i] = wp[i];
-    // this sweep's draws: lane l holds those of electrons l and l + 64
-    double dz[2][3], du[2];
+    // positions and this sweep's draws: lane l holds electrons l and l + 64
+    double px[2], py[2], pz[2], dz[2][3], du[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int e = lane + 64 * h;
-        move_draws(seed, (uint32_t)w, sweep, (uint32_t)(e < N ? e : 0), dz[h], du[h]);
+        const bool on = e < N;
+        px[h] = on ? wp[3 * e] : 0.0;
+        py[h] = on ? wp[3 * e + 1] : 0.0;
+        pz[h] = on ? wp[3 * e + 2] : 0.0;
+        move_draws(seed, (uint32_t)w, sweep, (uint32_t)(on ? e : 0), dz[h], du[h]);
     }
-    wave_sync_s();
     bool bad = false;
+    T Kr[KN];
+    int sig = lane;
 
     const int npad = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
     const int G = 64 / npad;
     const int li = lane & (npad - 1), lg = lane / npad;
-    const int ldk = L.ldk;
     // lane group lg of the phi product covers AOs [m_lo, m_hi)
     const int mchunk = (M + G - 1) / G;
     const int m_lo = min(M, lg * mchunk), m_hi = min(M, m_lo + mchunk);
+    bool need = true;
     for (int e = 0; e < N; ++e) {
         const int b = e < nu ? 0 : 1;
         const int off = b ? nu : 0;
-        const int j = e - off;
+        const int jj = e - off;
         const int nb = b ? S.n_dn : nu;
-        if (j == 0) refresh_spin<T>(Aw, n, off, nb, K, ldk, gjs, col, perm, bad);
+        if (jj == 0) need = true;
+        if (need) {
+            rebuild<T, KN>(Aw, n, off, nb, Kr, sig, bad);
+            need = false;
+        }
         const int src = e & 63, h = e >> 6;
         const double z0 = readlane_d(h ? dz[1][0] : dz[0][0], src);
         const double z1 = readlane_d(h ? dz[1][1] : dz[0][1], src);
         const double z2 = readlane_d(h ? dz[1][2] : dz[0][2], src);
         const double u = readlane_d(h ? du[1] : du[0], src);
-        const double rx = pos[3 * e] + sigma * z0, ry = pos[3 * e + 1] + sigma * z1, rz = pos[3 * e + 2] + sigma * z2;
-        for (int s = lane; s < S.basis.n_shells; s += 64) {
-            T v[6];
-            const int nc = shell_eval<1, T>(S.basis, R, s, rx, ry, rz, v);
-            const int m0 = S.basis.shell_mu0[s];
-            for (int q = 0; q < nc; ++q) psi[m0 + q] = v[q];
-        }
+        const double ex = readlane_d(h ? px[1] : px[0], src);
+        const double ey = readlane_d(h ? py[1] : py[0], src);
+        const double ez = readlane_d(h ? pz[1] : pz[0], src);
+        const double rx = ex + sigma * z0, ry = ey + sigma * z1, rz = ez + sigma * z2;
+        for (int s = lane; s < NS; s += 64) shell_values_lds<T>(B, s, rx, ry, rz, psi);
+        // Jastrow difference over the pairs (e, k), k held by this lane
         double dj = 0.0;
-        {
-            const double ex = pos[3 * e], ey = pos[3 * e + 1], ez = pos[3 * e + 2];
-            for (int k = lane; k < N; k += 64) {
-                if (k == e) continue;
-                const double px = pos[3 * k], py = pos[3 * k + 1], pz = pos[3 * k + 2];
-                const double ax = rx - px, ay = ry - py, az = rz - pz;
-                const double bx = ex - px, by = ey - py, bz = ez - pz;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int k = lane + 64 * hh;
+            if (k < N && k != e) {
+                const double ax = rx - px[hh], ay = ry - py[hh], az = rz - pz[hh];
+                const double bx = ex - px[hh], by = ey - py[hh], bz = ez - pz[hh];
                 dj += pade_u(sqrt(ax * ax + ay * ay + az * az), S.ee_a, S.ee_F) -
                       pade_u(sqrt(bx * bx + by * by + bz * bz), S.ee_a, S.ee_F);
             }
@@ -210,7 +235,7 @@ __global__ __launch_bounds__(256) void k_sweep_w(SysDev S, const T *__restrict__
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) dj += __shfl_xor(dj, o, 64);
         wave_sync_s();
-        // phi_i(r') = sum_mu psi_mu C[mu][i]; lane group lg sums mu = lg (mod G)
+        // phi_i(r') = sum_mu psi_mu C[mu][i]; lane group lg sums its AO range
         T ph = T(0);
         if (li < nb) {
             T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0);
@@ -232,77 +257,113 @@ __global__ __launch_bounds__(256) void k_sweep_w(SysDev S, const T *__restrict__
             ph = (p0 + p1) + (p2 + p3);
         }
         for (int o = npad; o < 64; o <<= 1) ph += __shfl_xor(ph, o, 64);
-        if (lg == 0 && li < nb) phin[li] = ph;
+        // lane i < KN holds phi_i (zero from nb on): store it at the register
+        // slot of orbital i
+        if (lane < KN) phin[sig] = ph;
         wave_sync_s();
-        // v_c = sum_i phi_i K[i][c]; ratio = v_j
-        T v = T(0);
-        if (lane < nb) {
-            // v_c = sum_i phi_i K[i][c], lane c walks column c of K (contiguous in Kt)
-            T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
-            const T *kp = K + lane * ldk;
-            int i = 0;
-            for (; i + 4 <= nb; i += 4) {
-                v0 += phin[i] * kp[i];
-                v1 += phin[i + 1] * kp[i + 1];
-                v2 += phin[i + 2] * kp[i + 2];
-                v3 += phin[i + 3] * kp[i + 3];
-            }
-            for (; i < nb; ++i) v0 += phin[i] * kp[i];
-            v = (v0 + v1) + (v2 + v3);
+        // v = phi^T K for the column this lane holds
+        T v0 = T(0), v1 = T(0);
+#pragma unroll
+        for (int r = 0; r < KN; r += 2) {
+            v0 += phin[r] * Kr[r];
+            v1 += phin[r + 1] * Kr[r + 1];
         }
-        const double ratio = (double)__shfl(v, j, 64);
+        const T v = v0 + v1;
+        // the lane holding electron jj of the block
+        const int pj = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(sig == jj)));
+        const double ratio = (double)readlane_t(v, pj);
         const double qv = ratio * exp(dj);
         const bool acc = u < qv * qv;
         if (acc) {
-            // lane c < nb: column c of K; colj = old column j
-            if (lane < nb) {
-                colj[lane] = K[j * ldk + lane];   // K[lane][j]
-                Aw[(size_t)e * n + lane] = ph;
-            }
-            if (lane < 3) pos[3 * e + lane] = lane == 0 ? rx : (lane == 1 ? ry : rz);
-            wave_sync_s();
-            if (lane < nb) {
-                const T t = (v - (lane == j ? T(1) : T(0))) * (T)(1.0 / ratio);
-                T *kp = K + lane * ldk;
-                int i = 0;
-                for (; i + 4 <= nb; i += 4) {
-                    kp[i] -= colj[i] * t;
-                    kp[i + 1] -= colj[i + 1] * t;
-                    kp[i + 2] -= colj[i + 2] * t;
-                    kp[i + 3] -= colj[i + 3] * t;
+            if (lane < nb && lg == 0) Aw[(size_t)e * n + lane] = ph;
+            if (lane == src) {
+                if (h) {
+                    px[1] = rx;
+                    py[1] = ry;
+                    pz[1] = rz;
+                } else {
+                    px[0] = rx;
+                    py[0] = ry;
+                    pz[0] = rz;
                 }
-                for (; i < nb; ++i) kp[i] -= colj[i] * t;
+            }
+            if (lane == pj) {
+#pragma unroll
+                for (int r = 0; r < KN; ++r) colj[r] = Kr[r];
             }
             wave_sync_s();
-            if (fabs(ratio) < FORCED_REFRESH_RATIO) refresh_spin<T>(Aw, n, off, nb, K, ldk, gjs, col, perm, bad);
+            const T t = (v - (lane == pj ? T(1) : T(0))) * (T)(1.0 / ratio);
+#pragma unroll
+            for (int r = 0; r < KN; ++r) Kr[r] -= colj[r] * t;
+            if (fabs(ratio) < FORCED_REFRESH_RATIO) need = true;
         }
         if (accept != nullptr && lane == 0) accept[(size_t)e * W + w] = acc ? 1 : 0;
         const uint64_t m = (uint64_t)sweep * (uint64_t)N + (uint64_t)e;
         // the next move of this spin block needs a fresh inverse; a block that
         // has no further move in this sweep is rebuilt at the next sweep anyway
-        if (((m + 1) % (uint64_t)refresh_period) == 0 && j < nb - 1)
-            refresh_spin<T>(Aw, n, off, nb, K, ldk, gjs, col, perm, bad);
+        if (((m + 1) % (uint64_t)refresh_period) == 0 && jj < nb - 1) need = true;
     }
-    for (int i = lane; i < 3 * N; i += 64) wp[i] = pos[i];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = lane + 64 * h;
+        if (e < N) {
+            wp[3 * e] = px[h];
+            wp[3 * e + 1] = py[h];
+            wp[3 * e + 2] = pz[h];
+        }
+    }
     if (bad && lane == 0) atomicOr(status, STATUS_SINGULAR);
 }
 
-template <typename T>
-hipError_t launch_sweep_w(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
-                          uint32_t sweep, uint64_t seed, double sigma, int refresh_period, uint8_t *accept,
-                          int *status, const SweepWLayout &L, hipStream_t st) {
-    hipLaunchKernelGGL(k_sweep_w<T>, dim3((unsigned)((W + L.wpb - 1) / L.wpb)), dim3(64 * L.wpb), L.bytes, st, S, C,
-                       R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L);
+template <typename T, int KN>
+static hipError_t launch_kn(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
+                            uint32_t sweep, uint64_t seed, double sigma, int refresh_period, uint8_t *accept,
+                            int *status, const SweepLayout &L, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep_r<T, KN>), dim3((unsigned)((W + L.wpb - 1) / L.wpb)), dim3(64 * L.wpb), L.bytes, st,
+                       S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L);
     return hipGetLastError();
 }
 
-hipError_t configure_sweep(size_t sweep_lds) {
-    return hipFuncSetAttribute((const void *)k_sweep_w<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)sweep_lds);
+int sweep_kn(int n_occ) { return n_occ <= 16 ? 16 : (n_occ <= 32 ? 32 : (n_occ <= 48 ? 48 : 64)); }
+
+template <typename T>
+hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo, uint32_t sweep,
+                        uint64_t seed, double sigma, int refresh_period, uint8_t *accept, int *status,
+                        const SweepLayout &L, hipStream_t st) {
+    switch (sweep_kn(S.n_occ)) {
+        case 16:
+            return launch_kn<T, 16>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
+                                    st);
+        case 32:
+            return launch_kn<T, 32>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
+                                    st);
+        case 48:
+            return launch_kn<T, 48>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
+                                    st);
+        default:
+            return launch_kn<T, 64>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
+                                    st);
+    }
 }
 
-template hipError_t launch_sweep_w<double>(const SysDev &, const double *, const double *, double *, int, double *,
-                                           uint32_t, uint64_t, double, int, uint8_t *, int *, const SweepWLayout &,
-                                           hipStream_t);
+template <typename T>
+hipError_t configure_sweep(size_t lds) {
+    const void *f[4] = {(const void *)k_sweep_r<T, 16>, (const void *)k_sweep_r<T, 32>,
+                        (const void *)k_sweep_r<T, 48>, (const void *)k_sweep_r<T, 64>};
+    for (const void *g : f) {
+        const hipError_t e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_sweep<double>(const SysDev &, const double *, const double *, double *, int, double *,
+                                         uint32_t, uint64_t, double, int, uint8_t *, int *, const SweepLayout &,
+                                         hipStream_t);
+template hipError_t launch_sweep<float>(const SysDev &, const float *, const double *, double *, int, float *,
+                                        uint32_t, uint64_t, double, int, uint8_t *, int *, const SweepLayout &,
+                                        hipStream_t);
+template hipError_t configure_sweep<double>(size_t);
+template hipError_t configure_sweep<float>(size_t);
 
 }  // namespace vmcx
