@@ -18,6 +18,7 @@
 #include "vmc_kernels.hpp"
 #include "vmc_pipeline.hpp"
 
+using vmcx::AdjLayout;
 using vmcx::AoTiles;
 using vmcx::DenseLayout;
 using vmcx::MeasBufs;
@@ -70,6 +71,7 @@ struct vmc_ctx {
     SysDev sys{};
     SweepLayout swl{};   // k_sweep_r, FP64
     DenseLayout dl{};
+    AdjLayout al{};      // k_adjoint_mfma, FP64
 
     int64_t chunk = 0;
     double *st_EL = nullptr, *st_lnpsi = nullptr, *st_lnjac = nullptr, *st_dEdR = nullptr, *st_dPdR = nullptr,
@@ -162,6 +164,25 @@ static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
     return s;
 }
 
+// LDS layout of the adjoint for an arithmetic type of ts bytes.
+static AdjLayout adjoint_layout(const vmc_ctx *c, size_t ts) {
+    AdjLayout a{};
+    auto al = [](size_t b) { return (int)((b + 15) & ~(size_t)15); };
+    const int nt = (c->n_occ + 15) / 16, N = c->N;
+    a.ldk = 16 * nt + 1;
+    a.rt = (N + 15) / 16;
+    const int kb = al((size_t)a.rt * 16 * a.ldk * ts);
+    a.off_k = 0;
+    a.off_a = kb;
+    a.off_p = 2 * kb;
+    a.off_g = a.off_p + al((size_t)3 * N * 8);
+    a.off_d = a.off_g + al((size_t)3 * N * 8);
+    a.waves = 8;
+    while (a.waves > 1 && (size_t)a.off_d + (size_t)a.waves * 3 * N * 8 > 160 * 1024) a.waves /= 2;
+    a.bytes = (size_t)a.off_d + (size_t)a.waves * 3 * N * 8;
+    return a;
+}
+
 // LDS layout of k_walker_dense.  Sizes are in doubles.
 static void layouts(vmc_ctx *c) {
     const int N = c->N, n = c->n_occ;
@@ -195,9 +216,9 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(S, C, R, pos, cw * c->N, c->tiles16, c->mb_phi, 5, st));
     HIP_OK(c, vmcx::launch_walker_dense<double>(S, R, mb, o, c->status, c->dl, (int)cw, st));
     if (!full) return VMC_OK;
-    HIP_OK(c, vmcx::launch_adjoint_ao<double>(S, C, R, mb, c->tiles, o, (int)cw, st));
+    HIP_OK(c, vmcx::launch_adjoint<double>(S, C, R, mb, o, c->al, (int)cw, st));
     MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
-    HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, c->tiles.n_tiles, o, warp, (int)cw, st));
+    HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, o, warp, (int)cw, st));
     return VMC_OK;
 }
 
@@ -394,18 +415,20 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     sd.Z = c->d_Z;
     layouts(c);
     c->swl = sweep_layout(c, sizeof(double));
-    if (c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024)
-        return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu / %zu bytes)",
-                            c->swl.bytes, c->dl.bytes));
+    c->al = adjoint_layout(c, sizeof(double));
+    if (c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024 || c->al.bytes > 160 * 1024)
+        return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu / %zu / %zu bytes)",
+                            c->swl.bytes, c->dl.bytes, c->al.bytes));
     if (vmcx::configure_pipeline(c->dl.bytes) != hipSuccess ||
-        vmcx::configure_sweep<double>(c->swl.bytes) != hipSuccess)
+        vmcx::configure_sweep<double>(c->swl.bytes) != hipSuccess ||
+        vmcx::configure_adjoint<double>(c->al.bytes) != hipSuccess)
         return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the kernels"));
 
     // ---- staging and accumulators -------------------------------------------
     const int64_t Mn = (int64_t)M * c->n_occ, A3 = 3 * A;
     const int64_t Nn = (int64_t)c->N * c->n_occ;
     const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
-                                                        3 * (int64_t)n_tiles * c->N + 6 * M + 3 * c->N);
+                                                        3 * (int64_t)c->N + 6 * M + 3 * c->N);
     int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, opt->max_walkers));
     if (opt->staging_walkers > 0) chunk = std::min<int64_t>(chunk, opt->staging_walkers);
@@ -416,7 +439,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->st_O, chunk * Mn)) || (rc = c->dalloc(&c->st_G, chunk * Mn)) ||
         (rc = c->dalloc(&c->mb_phi, chunk * 5 * Nn)) || (rc = c->dalloc(&c->mb_ktil, chunk * Nn)) ||
         (rc = c->dalloc(&c->mb_abar, chunk * Nn)) || (rc = c->dalloc(&c->mb_gb, chunk * 6 * c->N)) ||
-        (rc = c->dalloc(&c->mb_dpart, chunk * 3 * (int64_t)n_tiles * c->N)) ||
+        (rc = c->dalloc(&c->mb_dpart, chunk * 3 * (int64_t)c->N)) ||
         (rc = c->dalloc(&c->mb_tao, chunk * 6 * M)) || (rc = c->dalloc(&c->mb_posw, chunk * 3 * c->N)) ||
         (rc = c->dalloc(&c->Amo, (size_t)opt->max_walkers * Nn)))
         return bail(rc);

@@ -1,0 +1,205 @@
+// vmc_adjoint.hip -- AO-space adjoint of one measurement on the matrix cores.
+//
+// One block per walker; the block's wavefronts take 16-AO sub-tiles in turn.
+// For a sub-tile (AOs mu) and 16-electron row tile (electrons e):
+//   kappa[e][mu] = sum_i K~[e][i] C[mu][i],  a[e][mu] = sum_i Abar[e][i] C[mu][i]
+// on 16x16x4 MFMA (A = K~ or Abar from LDS, B = C held in registers).  The
+// accumulator of that product holds, in every lane, the (e, mu) pairs that
+// the lane then evaluates (AO value, gradient, Hessian, grad-Laplacian):
+//   t_k = a d_k psi - kappa (sum_d g_d d_k d_d psi + 1/2 d_k lap psi)
+//   s_k = kappa d_k psi,   q = -g . grad psi - 1/2 lap psi
+// and those per-lane values are exactly the A operand (rows mu, k = e) of the
+// outer products
+//   O[mu][i] = sum_e psi[e][mu] K~[e][i]
+//   G[mu][i] = sum_e psi[e][mu] Abar[e][i] + q[e][mu] K~[e][i]
+// whose B operand (K~, Abar rows e) comes from LDS.  Per AO the electron sums
+// of t_k and s_k go to tao; per electron the AO sums of t_k (dE_L/dr_e, the
+// determinant part) go to dedr_part, in a fixed order.
+#include "vmc_pipeline.hpp"
+#include "vmc_mfma.hpp"
+
+namespace vmcx {
+
+template <typename T, int NT>
+__global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restrict__ C,
+                                                      const double *__restrict__ R, MeasBufs<T> mb, WalkerOut out,
+                                                      AdjLayout L) {
+    typedef Mfma<T> MF;
+    constexpr int KS = 4 * NT;        // k-steps over orbitals (4 per step)
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int N = S.N, n = S.n_occ, M = S.M;
+    const int ldk = L.ldk, RT = L.rt;
+    T *Ks = (T *)(smem + L.off_k);    // [RT*16][ldk]  K~[e][i]
+    T *As = (T *)(smem + L.off_a);    // [RT*16][ldk]  Abar[e][i]
+    double *sp = (double *)(smem + L.off_p);    // [N][3]
+    double *sg = (double *)(smem + L.off_g);    // [N][3] Jastrow gradient
+    double *dpw = (double *)(smem + L.off_d);   // [nw][N][3] per-wave dE_L/dr_e partials
+    const T *ktw = mb.ktil + (size_t)w * N * n;
+    const T *abw = mb.abar + (size_t)w * N * n;
+    for (int k = tid; k < RT * 16 * ldk; k += blockDim.x) {
+        const int e = k / ldk, i = k - (k / ldk) * ldk;
+        const bool on = e < N && i < n;
+        Ks[k] = on ? ktw[(size_t)e * n + i] : T(0);
+        As[k] = on ? abw[(size_t)e * n + i] : T(0);
+    }
+    for (int k = tid; k < 3 * N; k += blockDim.x) {
+        sp[k] = mb.pos[(size_t)w * N * 3 + k];
+        sg[k] = mb.gb[(size_t)w * N * 6 + 6 * (k / 3) + (k - (k / 3) * 3)];
+    }
+    for (int k = tid; k < nw * 3 * N; k += blockDim.x) dpw[k] = 0.0;
+    __syncthreads();
+    double *dw = dpw + (size_t)wave * 3 * N;
+    const int ml = lane & 15, kg = lane >> 4;
+    const int n_sub = (M + 15) >> 4;
+    for (int st = wave; st < n_sub; st += nw) {
+        const int mu = 16 * st + ml;
+        const bool vm = mu < M;
+        // this lane's AO
+        int s = 0, pw = 0, atom = 0;
+        T eta = T(0);
+        if (vm) {
+            s = S.basis.ao_shell[mu];
+            pw = S.basis.ao_pow[mu];
+            eta = (T)S.basis.ao_eta[mu];
+            atom = S.basis.shell_atom[s];
+        }
+        const double Rx = R[3 * atom], Ry = R[3 * atom + 1], Rz = R[3 * atom + 2];
+        T cB[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int i = 4 * ks + kg;
+            cB[ks] = (vm && i < n) ? C[(size_t)mu * n + i] : T(0);
+        }
+        typename MF::acc_t accO[NT], accG[NT];
+#pragma unroll
+        for (int it = 0; it < NT; ++it) accO[it] = accG[it] = MF::zero();
+        double tl[6] = {0, 0, 0, 0, 0, 0};
+        for (int rt = 0; rt < RT; ++rt) {
+            typename MF::acc_t kap = MF::zero(), aa = MF::zero();
+            const T *kr = Ks + (16 * rt + ml) * ldk + kg;
+            const T *ar = As + (16 * rt + ml) * ldk + kg;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                kap = MF::fma(kr[4 * ks], cB[ks], kap);
+                aa = MF::fma(ar[4 * ks], cB[ks], aa);
+            }
+            // one (e, mu) evaluation at a time: unrolled, four would be live
+#pragma unroll 1
+            for (int v = 0; v < 4; ++v) {
+                const int e = 16 * rt + MF::row(lane, v);
+                T psi = T(0), q = T(0);
+                double t6[6] = {0, 0, 0, 0, 0, 0};
+                if (e < N && vm) {
+                    const T x = (T)(sp[3 * e] - Rx), y = (T)(sp[3 * e + 1] - Ry), z = (T)(sp[3 * e + 2] - Rz);
+                    const T rho = x * x + y * y + z * z;
+                    T R0, R1, R2, R3;
+                    shell_radial<14, T>(S.basis, s, rho, R0, R1, R2, R3);
+                    T d[14];
+                    ao_components<14, T>(x, y, z, rho, R0, R1, R2, R3, pw, eta, d);
+                    const T gx = (T)sg[3 * e], gy = (T)sg[3 * e + 1], gz = (T)sg[3 * e + 2];
+                    const T hgx = gx * d[5] + gy * d[6] + gz * d[7];
+                    const T hgy = gx * d[6] + gy * d[8] + gz * d[9];
+                    const T hgz = gx * d[7] + gy * d[9] + gz * d[10];
+                    const T half = T(0.5);
+                    const T kv = kap[v], av = aa[v];
+                    t6[0] = (double)(av * d[1] - kv * (hgx + half * d[11]));
+                    t6[1] = (double)(av * d[2] - kv * (hgy + half * d[12]));
+                    t6[2] = (double)(av * d[3] - kv * (hgz + half * d[13]));
+                    t6[3] = (double)(kv * d[1]);
+                    t6[4] = (double)(kv * d[2]);
+                    t6[5] = (double)(kv * d[3]);
+                    psi = d[0];
+                    q = -(gx * d[1] + gy * d[2] + gz * d[3]) - half * d[4];
+                }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) tl[c] += t6[c];
+                // AO sum of t_k for electron e over the 16 lanes of this row group
+                double d0 = t6[0], d1 = t6[1], d2 = t6[2];
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) {
+                    d0 += __shfl_xor(d0, off, 64);
+                    d1 += __shfl_xor(d1, off, 64);
+                    d2 += __shfl_xor(d2, off, 64);
+                }
+                if (ml == 0 && e < N) {
+                    dw[3 * e] += d0;
+                    dw[3 * e + 1] += d1;
+                    dw[3 * e + 2] += d2;
+                }
+                const T *kb = Ks + e * ldk + ml;
+                const T *ab = As + e * ldk + ml;
+#pragma unroll
+                for (int it = 0; it < NT; ++it) {
+                    const T bk = kb[16 * it], ba = ab[16 * it];
+                    accO[it] = MF::fma(psi, bk, accO[it]);
+                    accG[it] = MF::fma(psi, ba, accG[it]);
+                    accG[it] = MF::fma(q, bk, accG[it]);
+                }
+            }
+        }
+        // outer products of the walker for this sub-tile
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int mr = 16 * st + MF::row(lane, v);
+            if (mr >= M) continue;
+#pragma unroll
+            for (int it = 0; it < NT; ++it) {
+                const int i = 16 * it + ml;
+                if (i < n) {
+                    const size_t o = ((size_t)w * M + mr) * n + i;
+                    if (out.O) out.O[o] = (double)accO[it][v];
+                    if (out.G) out.G[o] = (double)accG[it][v];
+                }
+            }
+        }
+        // electron sums per AO: add the four row groups
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            tl[c] += __shfl_xor(tl[c], 16, 64);
+            tl[c] += __shfl_xor(tl[c], 32, 64);
+        }
+        if (kg == 0 && vm)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) mb.tao[((size_t)w * M + mu) * 6 + c] = tl[c];
+    }
+    __syncthreads();
+    // dE_L/dr_e (determinant part): the wavefronts' partials in a fixed order
+    double *dpart = mb.dedr_part + (size_t)w * N * 3;
+    for (int k = tid; k < 3 * N; k += blockDim.x) {
+        double acc = 0.0;
+        for (int q = 0; q < nw; ++q) acc += dpw[(size_t)q * 3 * N + k];
+        dpart[k] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_adjoint(const SysDev &S, const T *C, const double *R, const MeasBufs<T> &mb,
+                          const WalkerOut &out, const AdjLayout &L, int W, hipStream_t st) {
+    const dim3 g((unsigned)W), b((unsigned)(64 * L.waves));
+    switch ((S.n_occ + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_adjoint_mfma<T, 1>), g, b, L.bytes, st, S, C, R, mb, out, L); break;
+        case 2: hipLaunchKernelGGL((k_adjoint_mfma<T, 2>), g, b, L.bytes, st, S, C, R, mb, out, L); break;
+        case 3: hipLaunchKernelGGL((k_adjoint_mfma<T, 3>), g, b, L.bytes, st, S, C, R, mb, out, L); break;
+        default: hipLaunchKernelGGL((k_adjoint_mfma<T, 4>), g, b, L.bytes, st, S, C, R, mb, out, L); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t configure_adjoint(size_t lds) {
+    const void *f[4] = {(const void *)k_adjoint_mfma<T, 1>, (const void *)k_adjoint_mfma<T, 2>,
+                        (const void *)k_adjoint_mfma<T, 3>, (const void *)k_adjoint_mfma<T, 4>};
+    for (const void *g : f) {
+        const hipError_t e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_adjoint<double>(const SysDev &, const double *, const double *, const MeasBufs<double> &,
+                                           const WalkerOut &, const AdjLayout &, int, hipStream_t);
+template hipError_t configure_adjoint<double>(size_t);
+
+}  // namespace vmcx

@@ -8,36 +8,10 @@
 // produced in LDS by a shell-major GTO evaluation and consumed in k-steps of
 // 4 AOs by 16x16x4 MFMA (FP64: v_mfma_f64_16x16x4_f64; FP32:
 // v_mfma_f32_16x16x4_f32), accumulating in the arithmetic type T.
+#include "vmc_mfma.hpp"
 #include "vmc_pipeline.hpp"
 
 namespace vmcx {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mfma;
-
-template <>
-struct Mfma<double> {
-    typedef v4d acc_t;
-    __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
-    __device__ static acc_t fma(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // row of accumulator register v held by lane l (column l % 16)
-    __device__ static int row(int l, int v) { return (l >> 4) + 4 * v; }
-};
-
-template <>
-struct Mfma<float> {
-    typedef v4f acc_t;
-    __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
-    __device__ static acc_t fma(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
 
 template <typename T, int NC, int NT>
 __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restrict__ C, const double *__restrict__ R,

@@ -1,13 +1,7 @@
 // vmc_pipeline.hip -- batched gfx950 kernels of the VMC force hot path.
 //
-//   k_mo_rows      MO values (and gradients/Laplacians) of every (walker,
-//                  electron) row: a GEMM over AOs whose left operand is
-//                  produced in LDS by a shell-major GTO evaluation
 //   k_warp         space-warped electron positions and ln Jac per walker
 //   k_walker_dense per walker: Slater inverses, E_L, ln|Psi|, Abar = (K X K)^T/2
-//   k_adjoint_ao   AO-space adjoint per (AO tile, walker): back-projection,
-//                  GTO third derivatives, electron-position sums, outer
-//                  products dln|Psi|/dC and dE_L/dC
 //   k_finalize     per walker: Jastrow/potential terms of dE_L/dr, SWCT force
 //                  terms dE_L/dR, dln|Psi|/dR, dln Jac/dR
 //
@@ -99,82 +93,6 @@ __device__ void gj_invert_block(double *a, int n, double *col, int *perm, double
     __syncthreads();
     logabs = la;
     singular = sing;
-}
-
-// ---------------------------------------------------------------------------
-// k_mo_rows: out[row][c][i] = sum_mu AO_c(r_row)[mu] C[mu][i], c < NC.
-// 32 rows per block; AO tiles of whole shells (<= 32 AOs) staged in LDS.
-// Thread (ty, tx): rows 2ty, 2ty+1; orbitals tx + 16 q.
-// ---------------------------------------------------------------------------
-template <typename T, int NC>
-__global__ __launch_bounds__(256) void k_mo_rows(SysDev S, const T *__restrict__ C, const double *__restrict__ R,
-                                                 const double *__restrict__ pos, int64_t n_rows, AoTiles tiles,
-                                                 T *__restrict__ out) {
-    constexpr int RT = 32, MT = 32;
-    __shared__ double sp[RT * 3];
-    __shared__ T aot[RT][MT][NC];
-    __shared__ T ct[MT][64];
-    const int tid = threadIdx.x;
-    const int n = S.n_occ;
-    const int64_t row0 = (int64_t)blockIdx.x * RT;
-    for (int k = tid; k < RT * 3; k += 256) {
-        const int64_t r = row0 + k / 3;
-        sp[k] = r < n_rows ? pos[row0 * 3 + k] : 0.0;
-    }
-    const int ty = tid >> 4, tx = tid & 15;
-    T acc[2][NC][4];
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[r][c][q] = T(0);
-    for (int t = 0; t < tiles.n_tiles; ++t) {
-        const int s0 = tiles.s0[t], s1 = tiles.s1[t], mu0 = tiles.mu0[t], mu1 = tiles.mu1[t];
-        const int nsh = s1 - s0, nmu = mu1 - mu0;
-        __syncthreads();
-        for (int p = tid; p < RT * nsh; p += 256) {
-            const int r = p / nsh, s = s0 + (p - (p / nsh) * nsh);
-            T v[6 * NC];
-            const int nc = shell_eval<NC, T>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2], v);
-            const int m0 = S.basis.shell_mu0[s] - mu0;
-            for (int q = 0; q < nc; ++q)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) aot[r][m0 + q][c] = v[q * NC + c];
-        }
-        for (int p = tid; p < nmu * 64; p += 256) {
-            const int m = p >> 6, i = p & 63;
-            ct[m][i] = i < n ? C[(size_t)(mu0 + m) * n + i] : T(0);
-        }
-        __syncthreads();
-        for (int m = 0; m < nmu; ++m) {
-            T a[2][NC], cc[4];
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int c = 0; c < NC; ++c) a[r][c] = aot[2 * ty + r][m][c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) cc[q] = ct[m][tx + 16 * q];
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[r][c][q] += a[r][c] * cc[q];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int64_t row = row0 + 2 * ty + r;
-        if (row >= n_rows) continue;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = tx + 16 * q;
-                if (i < n) out[(row * NC + c) * n + i] = acc[r][c][q];
-            }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -316,7 +234,7 @@ __device__ void lds_gemm44(const double *A, int sai, int sak, const double *B, i
 //   Slater inverses K (Gauss-Jordan), Jastrow gradient g and Laplacian,
 //   det gradient b_e = sum_i K[i][e] grad phi_i(r_e), lapD_e likewise,
 //   E_L and ln|Psi|; with the adjoint: X = lap phi + 2 g.grad phi and
-//   Abar = 1/2 (K X K)^T, written with K~[e][i] = K[i][e] for k_adjoint_ao.
+//   Abar = 1/2 (K X K)^T, written with K~[e][i] = K[i][e] for the adjoint.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_walker_dense(SysDev S, const double *__restrict__ R,
@@ -455,179 +373,10 @@ __global__ __launch_bounds__(256) void k_walker_dense(SysDev S, const double *__
 }
 
 // ---------------------------------------------------------------------------
-// k_adjoint_ao: block (AO tile t, walker w).  Thread (ml = AO in tile,
-// es = electron slot 0..7).  Per electron chunk of 16:
-//   kappa[e][mu] = sum_i C[mu][i] K~[e][i],  a[e][mu] = sum_i C[mu][i] Abar[e][i]
-//   t_k = a d_k psi - kappa (sum_d g_d d_k d_d psi + 1/2 d_k lap psi)   (-> dE_L/dr_e, dE_L/dR)
-//   s_k = kappa d_k psi                                                 (-> dln|Psi|/dR)
-//   O[mu][i] += psi K~[e][i];  G[mu][i] += psi Abar[e][i] + q K~[e][i],
-//   q = -g . grad psi - 1/2 lap psi
-// ---------------------------------------------------------------------------
-template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void k_adjoint_ao(SysDev S, const T *__restrict__ C, const double *__restrict__ R,
-                                                    MeasBufs<T> mb, AoTiles tiles, WalkerOut out) {
-    constexpr int EC = 16;
-    __shared__ double sp[EC * 3];
-    __shared__ double sg[EC * 3];
-    __shared__ T kt[EC][NMAX];
-    __shared__ T ab[EC][NMAX];
-    __shared__ T rad[EC][32][4];
-    __shared__ T psi_t[EC][32];
-    __shared__ T q_t[EC][32];
-    __shared__ double red6[8][32][6];
-    const int t = blockIdx.x;
-    const int w = blockIdx.y;
-    const int tid = threadIdx.x;
-    const int ml = tid & 31, es = tid >> 5;
-    const int N = S.N, n = S.n_occ, M = S.M;
-    const int s0 = tiles.s0[t], s1 = tiles.s1[t], mu0 = tiles.mu0[t], mu1 = tiles.mu1[t];
-    const int nsh = s1 - s0, nmu = mu1 - mu0;
-    const int mu = mu0 + ml;
-    const bool mok = ml < nmu;
-    // this thread's AO: C row, shell, monomial, eta
-    T crow[NMAX];
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) crow[i] = (mok && i < n) ? C[(size_t)mu * n + i] : T(0);
-    int shl = 0, pw = 0;
-    T eta = T(0);
-    int atom = 0;
-    if (mok) {
-        const int s = S.basis.ao_shell[mu];
-        shl = s - s0;
-        pw = S.basis.ao_pow[mu];
-        eta = (T)S.basis.ao_eta[mu];
-        atom = S.basis.shell_atom[s];
-    }
-    const double Rx = R[3 * atom], Ry = R[3 * atom + 1], Rz = R[3 * atom + 2];
-    double tsum[6] = {0, 0, 0, 0, 0, 0};
-    constexpr int NI = (NMAX + 7) / 8;   // orbitals per thread in the outer products
-    T aO[NI], aG[NI];
-#pragma unroll
-    for (int k = 0; k < NI; ++k) aO[k] = aG[k] = T(0);
-    const double *posw = mb.pos + (size_t)w * N * 3;
-    const double *gbw = mb.gb + (size_t)w * N * 6;
-    const T *ktw = mb.ktil + (size_t)w * N * n;
-    const T *abw = mb.abar + (size_t)w * N * n;
-    double *dpart = mb.dedr_part + ((size_t)w * tiles.n_tiles + t) * N * 3;
-    for (int e0 = 0; e0 < N; e0 += EC) {
-        const int ne = min(EC, N - e0);
-        __syncthreads();
-        for (int k = tid; k < ne * 3; k += 256) {
-            sp[k] = posw[(size_t)e0 * 3 + k];
-            sg[k] = gbw[(size_t)(e0 + k / 3) * 6 + (k % 3)];
-        }
-        for (int k = tid; k < ne * NMAX; k += 256) {
-            const int e = k / NMAX, i = k - (k / NMAX) * NMAX;
-            kt[e][i] = i < n ? ktw[(size_t)(e0 + e) * n + i] : T(0);
-            ab[e][i] = i < n ? abw[(size_t)(e0 + e) * n + i] : T(0);
-        }
-        __syncthreads();
-        for (int k = tid; k < ne * nsh; k += 256) {
-            const int e = k / nsh, s = s0 + (k - (k / nsh) * nsh);
-            const int at = S.basis.shell_atom[s];
-            const T x = (T)(sp[3 * e] - R[3 * at]), y = (T)(sp[3 * e + 1] - R[3 * at + 1]),
-                    z = (T)(sp[3 * e + 2] - R[3 * at + 2]);
-            T R0, R1, R2, R3;
-            shell_radial<14, T>(S.basis, s, x * x + y * y + z * z, R0, R1, R2, R3);
-            rad[e][s - s0][0] = R0;
-            rad[e][s - s0][1] = R1;
-            rad[e][s - s0][2] = R2;
-            rad[e][s - s0][3] = R3;
-        }
-        __syncthreads();
-        for (int el = es; el < EC; el += 8) {
-            T psi = T(0), q = T(0);
-            double t6[6] = {0, 0, 0, 0, 0, 0};
-            if (el < ne && mok) {
-                T kap = T(0), aa = T(0);
-#pragma unroll
-                for (int i = 0; i < NMAX; ++i) {
-                    kap += crow[i] * kt[el][i];
-                    aa += crow[i] * ab[el][i];
-                }
-                const T x = (T)(sp[3 * el] - Rx), y = (T)(sp[3 * el + 1] - Ry), z = (T)(sp[3 * el + 2] - Rz);
-                T v[14];
-                ao_components<14, T>(x, y, z, x * x + y * y + z * z, rad[el][shl][0], rad[el][shl][1],
-                                     rad[el][shl][2], rad[el][shl][3], pw, eta, v);
-                const T gx = (T)sg[3 * el], gy = (T)sg[3 * el + 1], gz = (T)sg[3 * el + 2];
-                const T hgx = gx * v[5] + gy * v[6] + gz * v[7];
-                const T hgy = gx * v[6] + gy * v[8] + gz * v[9];
-                const T hgz = gx * v[7] + gy * v[9] + gz * v[10];
-                const T half = T(0.5);
-                t6[0] = (double)(aa * v[1] - kap * (hgx + half * v[11]));
-                t6[1] = (double)(aa * v[2] - kap * (hgy + half * v[12]));
-                t6[2] = (double)(aa * v[3] - kap * (hgz + half * v[13]));
-                t6[3] = (double)(kap * v[1]);
-                t6[4] = (double)(kap * v[2]);
-                t6[5] = (double)(kap * v[3]);
-                psi = v[0];
-                q = -(gx * v[1] + gy * v[2] + gz * v[3]) - half * v[4];
-            }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) tsum[c] += t6[c];
-            // sum over the AOs of the tile (32 lanes of this half-wave) -> dE_L/dr_e partial
-            double d0 = t6[0], d1 = t6[1], d2 = t6[2];
-#pragma unroll
-            for (int off = 16; off > 0; off >>= 1) {
-                d0 += __shfl_xor(d0, off, 64);
-                d1 += __shfl_xor(d1, off, 64);
-                d2 += __shfl_xor(d2, off, 64);
-            }
-            if (ml == 0 && el < ne) {
-                dpart[(size_t)(e0 + el) * 3 + 0] = d0;
-                dpart[(size_t)(e0 + el) * 3 + 1] = d1;
-                dpart[(size_t)(e0 + el) * 3 + 2] = d2;
-            }
-            psi_t[el][ml] = psi;
-            q_t[el][ml] = q;
-        }
-        __syncthreads();
-        if (mok)
-            for (int el = 0; el < ne; ++el) {
-                const T ps = psi_t[el][ml], qq = q_t[el][ml];
-#pragma unroll
-                for (int k = 0; k < NI; ++k) {
-                    const int i = es + 8 * k;
-                    if (i < NMAX) {
-                        const T kk = kt[el][i];
-                        aO[k] += ps * kk;
-                        aG[k] += ps * ab[el][i] + qq * kk;
-                    }
-                }
-            }
-    }
-    // outer products of this walker for the tile
-    if (mok) {
-#pragma unroll
-        for (int k = 0; k < NI; ++k) {
-            const int i = es + 8 * k;
-            if (i < n) {
-                const size_t o = ((size_t)w * M + mu) * n + i;
-                if (out.O) out.O[o] = (double)aO[k];
-                if (out.G) out.G[o] = (double)aG[k];
-            }
-        }
-    }
-    // per-AO sums over electrons (fixed order over es)
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 6; ++c) red6[es][ml][c] = tsum[c];
-    __syncthreads();
-    if (tid < 32 * 6) {
-        const int m = tid / 6, c = tid - (tid / 6) * 6;
-        if (m < nmu) {
-            double s = 0.0;
-            for (int k = 0; k < 8; ++k) s += red6[k][m][c];
-            mb.tao[((size_t)w * M + mu0 + m) * 6 + c] = s;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // k_finalize: one block per walker.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__restrict__ R,
-                                                  const double *__restrict__ R0, MeasBufsD mb, int n_tiles,
+                                                  const double *__restrict__ R0, MeasBufsD mb,
                                                   WalkerOut out, int warp) {
     extern __shared__ double smem[];
     const int w = blockIdx.x;
@@ -647,13 +396,8 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
     for (int i = tid; i < 6 * N; i += 128) gb[i] = mb.gb[(size_t)w * N * 6 + i];
     __syncthreads();
     for (int e = tid; e < N; e += 128) {
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-        for (int t = 0; t < n_tiles; ++t) {
-            const double *dp = mb.dedr_part + (((size_t)w * n_tiles + t) * N + e) * 3;
-            d0 += dp[0];
-            d1 += dp[1];
-            d2 += dp[2];
-        }
+        const double *dp = mb.dedr_part + ((size_t)w * N + e) * 3;
+        double d0 = dp[0], d1 = dp[1], d2 = dp[2];
         const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
         const double ge[3] = {-(gb[6 * e + 3] + gb[6 * e]), -(gb[6 * e + 4] + gb[6 * e + 1]),
                               -(gb[6 * e + 5] + gb[6 * e + 2])};
@@ -770,17 +514,6 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T>
-hipError_t launch_mo_rows(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
-                          const AoTiles &tiles, T *out, int nc, hipStream_t st) {
-    const dim3 g((unsigned)((n_rows + 31) / 32));
-    if (nc == 1)
-        hipLaunchKernelGGL((k_mo_rows<T, 1>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
-    else
-        hipLaunchKernelGGL((k_mo_rows<T, 5>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const double *pos0, double *posw,
                        double *lnjac, int W, hipStream_t st) {
     hipLaunchKernelGGL(k_warp, dim3(W), dim3(128), 0, st, S, R, R0, pos0, posw, lnjac, W);
@@ -794,26 +527,10 @@ hipError_t launch_walker_dense(const SysDev &S, const double *R, const MeasBufs<
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_adjoint_ao(const SysDev &S, const T *C, const double *R, const MeasBufs<T> &mb,
-                             const AoTiles &tiles, const WalkerOut &out, int W, hipStream_t st) {
-    const dim3 g((unsigned)tiles.n_tiles, (unsigned)W);
-    const int n = S.n_occ;
-    if (n <= 16)
-        hipLaunchKernelGGL((k_adjoint_ao<T, 16>), g, dim3(256), 0, st, S, C, R, mb, tiles, out);
-    else if (n <= 32)
-        hipLaunchKernelGGL((k_adjoint_ao<T, 32>), g, dim3(256), 0, st, S, C, R, mb, tiles, out);
-    else if (n <= 48)
-        hipLaunchKernelGGL((k_adjoint_ao<T, 48>), g, dim3(256), 0, st, S, C, R, mb, tiles, out);
-    else
-        hipLaunchKernelGGL((k_adjoint_ao<T, 64>), g, dim3(256), 0, st, S, C, R, mb, tiles, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb, int n_tiles,
+hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb,
                            const WalkerOut &out, int warp, int W, hipStream_t st) {
     const size_t lds = sizeof(double) * (size_t)S.N * (3 + 3 + 6 + 3 + 9 + 4) + sizeof(int) * (size_t)S.N;
-    hipLaunchKernelGGL(k_finalize, dim3(W), dim3(128), lds, st, S, R, R0, mb, n_tiles, out, warp);
+    hipLaunchKernelGGL(k_finalize, dim3(W), dim3(128), lds, st, S, R, R0, mb, out, warp);
     return hipGetLastError();
 }
 
@@ -822,12 +539,7 @@ hipError_t configure_pipeline(size_t dense_lds) {
                                (int)dense_lds);
 }
 
-template hipError_t launch_mo_rows<double>(const SysDev &, const double *, const double *, const double *, int64_t,
-                                           const AoTiles &, double *, int, hipStream_t);
 template hipError_t launch_walker_dense<double>(const SysDev &, const double *, const MeasBufs<double> &,
                                                 const WalkerOut &, int *, const DenseLayout &, int, hipStream_t);
-template hipError_t launch_adjoint_ao<double>(const SysDev &, const double *, const double *,
-                                              const MeasBufs<double> &, const AoTiles &, const WalkerOut &, int,
-                                              hipStream_t);
 
 }  // namespace vmcx

@@ -5,7 +5,7 @@
 
 namespace vmcx {
 
-// AO tiles: consecutive whole shells with at most 32 AOs each.
+// AO tiles: consecutive whole shells (at most 16 AOs each for k_mo_rows_mfma).
 struct AoTiles {
     const int *s0, *s1, *mu0, *mu1;
     int n_tiles;
@@ -38,6 +38,15 @@ struct DenseLayout {
     size_t bytes;
 };
 
+// LDS layout of k_adjoint_mfma (bytes).
+struct AdjLayout {
+    int ldk;                         // row stride (elements, odd) of K~ and Abar
+    int rt;                          // 16-electron row tiles
+    int off_k, off_a, off_p, off_g, off_d;
+    int waves;                       // wavefronts per block
+    size_t bytes;
+};
+
 // Per-walker staging of one measurement launch (chunk of walkers).
 template <typename T>
 struct MeasBufs {
@@ -47,7 +56,7 @@ struct MeasBufs {
     T *ktil;              // [W][N][n]      K[i][e] of the electron's spin block
     T *abar;              // [W][N][n]      dE_L / dA[e][i]
     double *gb;           // [W][N][6]      Jastrow gradient (0..2), det gradient (3..5)
-    double *dedr_part;    // [W][tiles][N][3]
+    double *dedr_part;    // [W][N][3]      dE_L/dr_e, determinant part
     double *tao;          // [W][M][6]      per-AO electron sums of t_k, s_k
 };
 
@@ -56,9 +65,6 @@ struct MeasBufsD {
     const double *gb, *dedr_part, *tao;
 };
 
-template <typename T>
-hipError_t launch_mo_rows(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
-                          const AoTiles &tiles, T *out, int nc, hipStream_t st);
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
                                const AoTiles &tiles16, T *out, int nc, hipStream_t st);
@@ -73,9 +79,11 @@ template <typename T>
 hipError_t launch_walker_dense(const SysDev &S, const double *R, const MeasBufs<T> &mb, const WalkerOut &out,
                                int *status, const DenseLayout &L, int W, hipStream_t st);
 template <typename T>
-hipError_t launch_adjoint_ao(const SysDev &S, const T *C, const double *R, const MeasBufs<T> &mb,
-                             const AoTiles &tiles, const WalkerOut &out, int W, hipStream_t st);
-hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb, int n_tiles,
+hipError_t launch_adjoint(const SysDev &S, const T *C, const double *R, const MeasBufs<T> &mb,
+                          const WalkerOut &out, const AdjLayout &L, int W, hipStream_t st);
+template <typename T>
+hipError_t configure_adjoint(size_t lds);
+hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb,
                            const WalkerOut &out, int warp, int W, hipStream_t st);
 hipError_t configure_pipeline(size_t dense_lds);
 template <typename T>
