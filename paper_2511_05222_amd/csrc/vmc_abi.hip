@@ -183,20 +183,19 @@ static AdjLayout adjoint_layout(const vmc_ctx *c, size_t ts) {
     return a;
 }
 
-// LDS layout of k_walker_dense.  Sizes are in doubles.
+// LDS layout of k_dense.
 static void layouts(vmc_ctx *c) {
-    const int N = c->N, n = c->n_occ;
-    int o = 0;
+    auto al = [](size_t b) { return (int)((b + 15) & ~(size_t)15); };
+    const int N = c->N, kn = vmcx::sweep_kn(c->n_occ);
     DenseLayout &d = c->dl;
-    d.p = o; o += 3 * N;
-    d.K0 = o; o += c->n_up * c->n_up;
-    d.K1 = o; o += c->n_dn * c->n_dn;
-    d.X = o; o += N * n;
-    d.U = o; o += std::max(64, n * n);
-    d.g = o; o += 3 * N;
-    d.red = o; o += 8;
-    d.perm = o; o += 32;
-    d.bytes = (size_t)o * sizeof(double);
+    d.ldk = kn + 1;
+    d.off_p = 0;
+    d.off_g = d.off_p + al((size_t)3 * N * 8);
+    d.off_k = d.off_g + al((size_t)3 * N * 8);
+    d.off_x = d.off_k + al((size_t)2 * kn * d.ldk * 8);
+    d.off_perm = d.off_x + al((size_t)kn * d.ldk * 8);
+    d.off_red = d.off_perm + al(128 * 4);
+    d.bytes = (size_t)d.off_red + 8 * 8;
 }
 
 // One measurement of `cw` walkers at positions pos0 (device [cw][N][3]):
@@ -214,7 +213,7 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     MeasBufs<double> mb{pos, pos0, c->mb_phi, full ? c->mb_ktil : nullptr, c->mb_abar, c->mb_gb, c->mb_dpart,
                         c->mb_tao};
     HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(S, C, R, pos, cw * c->N, c->tiles16, c->mb_phi, 5, st));
-    HIP_OK(c, vmcx::launch_walker_dense<double>(S, R, mb, o, c->status, c->dl, (int)cw, st));
+    HIP_OK(c, vmcx::launch_dense<double>(S, R, mb, o, c->status, c->dl, (int)cw, st));
     if (!full) return VMC_OK;
     HIP_OK(c, vmcx::launch_adjoint<double>(S, C, R, mb, o, c->al, (int)cw, st));
     MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
@@ -419,7 +418,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     if (c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024 || c->al.bytes > 160 * 1024)
         return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu / %zu / %zu bytes)",
                             c->swl.bytes, c->dl.bytes, c->al.bytes));
-    if (vmcx::configure_pipeline(c->dl.bytes) != hipSuccess ||
+    if (vmcx::configure_dense<double>(c->dl.bytes) != hipSuccess ||
         vmcx::configure_sweep<double>(c->swl.bytes) != hipSuccess ||
         vmcx::configure_adjoint<double>(c->al.bytes) != hipSuccess)
         return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the kernels"));

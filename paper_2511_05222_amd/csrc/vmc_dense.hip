@@ -1,0 +1,253 @@
+// vmc_dense.hip -- per-walker dense part of one measurement (gfx950).
+//
+// One block of four wavefronts per walker.
+//   phase A  waves 0 and 1: the inverse K of the up and down Slater blocks by
+//            in-register Gauss-Jordan (FP64, partial pivoting), log|det|;
+//            waves 2 and 3 at the same time: Jastrow gradient g_e, Laplacian
+//            and value, e-e and e-n potentials per electron.
+//   phase B  per spin block, one wavefront per electron row: the determinant
+//            gradient b_e = sum_i K[i][e] grad phi_i(r_e), lap D/D likewise,
+//            and (with the adjoint) X[e][i] = lap phi_i + 2 g_e . grad phi_i;
+//            then on 16x16x4 FP64 MFMA T = X K and
+//            Abar = 1/2 (K X K)^T = 1/2 T^T K^T, written with K~[e][i] = K[i][e].
+//   phase C  block sums: E_L, ln|Psi| = log|det up| + log|det dn| + J.
+// K, X and T stay FP64; K~ and Abar are stored in the arithmetic type T.
+#include "vmc_mfma.hpp"
+#include "vmc_pipeline.hpp"
+#include "vmc_regs.hpp"
+
+namespace vmcx {
+
+__device__ inline double block_sum4(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <typename T, int KN>
+__global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restrict__ R, MeasBufs<T> mb, WalkerOut out,
+                                               int *status, DenseLayout L) {
+    typedef Mfma<double> MF;
+    constexpr int RTS = KN / 16;                    // 16-row tiles of a spin block
+    constexpr int TPW = (RTS * RTS + 3) / 4;        // output tiles per wavefront
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int N = S.N, nu = S.n_up, nd = S.n_dn, n = S.n_occ, A = S.A;
+    const int ldk = L.ldk;
+    double *p = (double *)(smem + L.off_p);      // [N][3]
+    double *g = (double *)(smem + L.off_g);      // [N][3] Jastrow gradient
+    double *Ks = (double *)(smem + L.off_k);     // [2][KN][ldk]  K[i][e]
+    double *Xs = (double *)(smem + L.off_x);     // [KN][ldk]     X, then T
+    int *perm = (int *)(smem + L.off_perm);      // [2][64]
+    double *red = (double *)(smem + L.off_red);  // [8]
+    const T *ph = mb.phi + (size_t)w * N * 5 * n;
+    for (int i = tid; i < 3 * N; i += 256) p[i] = mb.pos[(size_t)w * N * 3 + i];
+    __syncthreads();
+    double el_part = 0.0, j_part = 0.0;
+    bool bad = false;
+    if (wave < 2) {
+        const int b = wave, off = b ? nu : 0, nb = b ? nd : nu;
+        // B = A^T of the block: lane c holds orbital c at the block's electrons
+        int lz = lane;
+        asm volatile("" : "+v"(lz));
+        double Br[KN];
+#pragma unroll
+        for (int r = 0; r < KN; ++r) {
+            double v = (lz == r && r >= nb) ? 1.0 : 0.0;   // identity padding
+            if (lz < nb && r < nb) v = (double)ph[(size_t)(off + r) * 5 * n + lz];
+            Br[r] = v;
+        }
+        int sig;
+        double la;
+        gj_regs<KN, true>(Br, sig, bad, la);
+        if (lane == 0) red[4 + b] = la;
+        // natural layout: lane p_k holds column k with register j = orbital p_j
+        if (lane < KN) perm[64 * b + sig] = lane;
+        wave_sync_s();
+        double *K = Ks + (size_t)b * KN * ldk;
+        if (lane < KN)
+#pragma unroll
+            for (int j = 0; j < KN; ++j) K[perm[64 * b + j] * ldk + sig] = Br[j];
+    } else {
+        for (int e = tid - 128; e < N; e += 128) {
+            const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
+            double gx = 0.0, gy = 0.0, gz = 0.0, hh = 0.0, vee = 0.0, jj = 0.0;
+            for (int k = 0; k < N; ++k) {
+                if (k == e) continue;
+                const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const PadeD pd = pade_all(r, S.ee_a, S.ee_F);
+                const double f = pd.u1 / r;
+                gx += f * dx;
+                gy += f * dy;
+                gz += f * dz;
+                hh += pd.u2 + 2.0 * f;
+                vee += 1.0 / r;
+                jj += pd.u;
+            }
+            double ven = 0.0;
+            for (int a = 0; a < A; ++a) {
+                const double dx = x - R[3 * a], dy = y - R[3 * a + 1], dz = z - R[3 * a + 2];
+                ven -= S.Z[a] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+            g[3 * e] = gx;
+            g[3 * e + 1] = gy;
+            g[3 * e + 2] = gz;
+            el_part += -0.5 * (hh + gx * gx + gy * gy + gz * gz) + ven + 0.5 * vee;
+            j_part += 0.5 * jj;
+        }
+    }
+    __syncthreads();
+    const double logdet = red[4] + red[5];
+    const bool full = mb.ktil != nullptr;
+    double *gb = mb.gb + (size_t)w * N * 6;
+    for (int b = 0; b < 2; ++b) {
+        const int nb = b ? nd : nu, off = b ? nu : 0;
+        const double *K = Ks + (size_t)b * KN * ldk;
+        // one wavefront per electron row j of the block (rows nb..KN-1: zeros)
+        for (int j = wave; j < KN; j += 4) {
+            if (j >= nb) {
+                if (lane < KN) Xs[j * ldk + lane] = 0.0;
+                continue;
+            }
+            const int e = off + j;
+            const T *row = ph + (size_t)e * 5 * n;
+            const double gx = g[3 * e], gy = g[3 * e + 1], gz = g[3 * e + 2];
+            double bx = 0.0, by = 0.0, bz = 0.0, lp = 0.0, xv = 0.0;
+            if (lane < n) {
+                const double Gx = (double)row[n + lane], Gy = (double)row[2 * n + lane],
+                             Gz = (double)row[3 * n + lane], Lp = (double)row[4 * n + lane];
+                xv = Lp + 2.0 * (gx * Gx + gy * Gy + gz * Gz);
+                if (lane < nb) {
+                    const double kk = K[lane * ldk + j];
+                    bx = kk * Gx;
+                    by = kk * Gy;
+                    bz = kk * Gz;
+                    lp = kk * Lp;
+                }
+            }
+            if (lane < KN) Xs[j * ldk + lane] = xv;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                bx += __shfl_xor(bx, o, 64);
+                by += __shfl_xor(by, o, 64);
+                bz += __shfl_xor(bz, o, 64);
+                lp += __shfl_xor(lp, o, 64);
+            }
+            if (lane == 0) {
+                gb[6 * e + 0] = gx;
+                gb[6 * e + 1] = gy;
+                gb[6 * e + 2] = gz;
+                gb[6 * e + 3] = bx;
+                gb[6 * e + 4] = by;
+                gb[6 * e + 5] = bz;
+                el_part += -0.5 * (lp + 2.0 * (bx * gx + by * gy + bz * gz));
+            }
+        }
+        if (!full) continue;
+        __syncthreads();
+        // T = X K  (rows e', columns e)
+        const int ml = lane & 15, kg = lane >> 4;
+        MF::acc_t tacc[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int t = wave + 4 * q;
+            tacc[q] = MF::zero();
+            if (t < RTS * RTS) {
+                const int rt = t / RTS, ct = t - (t / RTS) * RTS;
+                const double *xa = Xs + (16 * rt + ml) * ldk + kg;
+                const double *kb = K + kg * ldk + 16 * ct + ml;
+#pragma unroll
+                for (int ks = 0; ks < KN / 4; ++ks) tacc[q] = MF::fma(xa[4 * ks], kb[4 * ks * ldk], tacc[q]);
+            }
+        }
+        __syncthreads();   // every read of X is done: T replaces it
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int t = wave + 4 * q;
+            if (t < RTS * RTS) {
+                const int rt = t / RTS, ct = t - (t / RTS) * RTS;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Xs[(16 * rt + MF::row(lane, v)) * ldk + 16 * ct + ml] = tacc[q][v];
+            }
+        }
+        __syncthreads();
+        // Abar[e][i] = 1/2 sum_e' T[e'][e] K[i][e']
+        T *abw = mb.abar + ((size_t)w * N + off) * n;
+        T *ktw = mb.ktil + ((size_t)w * N + off) * n;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int t = wave + 4 * q;
+            if (t < RTS * RTS) {
+                const int rt = t / RTS, ct = t - (t / RTS) * RTS;
+                const double *ta = Xs + kg * ldk + 16 * rt + ml;
+                const double *kb = K + (16 * ct + ml) * ldk + kg;
+                MF::acc_t acc = MF::zero();
+#pragma unroll
+                for (int ks = 0; ks < KN / 4; ++ks) acc = MF::fma(ta[4 * ks * ldk], kb[4 * ks], acc);
+                const int i = 16 * ct + ml;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int e = 16 * rt + MF::row(lane, v);
+                    if (e < nb && i < n) {
+                        abw[(size_t)e * n + i] = (T)(0.5 * acc[v]);
+                        ktw[(size_t)e * n + i] = (T)K[i * ldk + e];
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the next block rewrites X
+    }
+    double vnn = 0.0;
+    if (tid == 0)
+        for (int a = 0; a < A; ++a)
+            for (int c = a + 1; c < A; ++c) {
+                const double dx = R[3 * a] - R[3 * c], dy = R[3 * a + 1] - R[3 * c + 1],
+                             dz = R[3 * a + 2] - R[3 * c + 2];
+                vnn += S.Z[a] * S.Z[c] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+    const double EL = block_sum4(el_part + vnn, red);
+    const double J = block_sum4(j_part, red);
+    const int anybad = __syncthreads_or(bad ? 1 : 0);
+    if (tid == 0) {
+        if (out.EL) out.EL[w] = EL;
+        if (out.lnpsi) out.lnpsi[w] = logdet + J;
+        if (anybad) atomicOr(status, STATUS_SINGULAR);
+        if (!isfinite(EL) || !isfinite(logdet + J)) atomicOr(status, STATUS_NONFINITE);
+    }
+}
+
+template <typename T>
+hipError_t launch_dense(const SysDev &S, const double *R, const MeasBufs<T> &mb, const WalkerOut &out, int *status,
+                        const DenseLayout &L, int W, hipStream_t st) {
+    const dim3 g((unsigned)W), b(256);
+    switch (sweep_kn(S.n_occ)) {
+        case 16: hipLaunchKernelGGL((k_dense<T, 16>), g, b, L.bytes, st, S, R, mb, out, status, L); break;
+        case 32: hipLaunchKernelGGL((k_dense<T, 32>), g, b, L.bytes, st, S, R, mb, out, status, L); break;
+        case 48: hipLaunchKernelGGL((k_dense<T, 48>), g, b, L.bytes, st, S, R, mb, out, status, L); break;
+        default: hipLaunchKernelGGL((k_dense<T, 64>), g, b, L.bytes, st, S, R, mb, out, status, L); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t configure_dense(size_t lds) {
+    const void *f[4] = {(const void *)k_dense<T, 16>, (const void *)k_dense<T, 32>, (const void *)k_dense<T, 48>,
+                        (const void *)k_dense<T, 64>};
+    for (const void *g : f) {
+        const hipError_t e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_dense<double>(const SysDev &, const double *, const MeasBufs<double> &, const WalkerOut &,
+                                         int *, const DenseLayout &, int, hipStream_t);
+template hipError_t configure_dense<double>(size_t);
+
+}  // namespace vmcx

@@ -32,9 +32,10 @@ struct SweepBasisLds {
     int *sha, *shb;
 };
 
-// LDS offsets (doubles) of k_walker_dense.
+// LDS layout of k_dense (bytes).
 struct DenseLayout {
-    int p, K0, K1, X, U, g, red, perm;
+    int ldk;                 // row stride (doubles, odd) of K, X and T
+    int off_p, off_g, off_k, off_x, off_perm, off_red;
     size_t bytes;
 };
 
@@ -76,8 +77,10 @@ hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *wa
 hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const double *pos0, double *posw,
                        double *lnjac, int W, hipStream_t st);
 template <typename T>
-hipError_t launch_walker_dense(const SysDev &S, const double *R, const MeasBufs<T> &mb, const WalkerOut &out,
-                               int *status, const DenseLayout &L, int W, hipStream_t st);
+hipError_t launch_dense(const SysDev &S, const double *R, const MeasBufs<T> &mb, const WalkerOut &out, int *status,
+                        const DenseLayout &L, int W, hipStream_t st);
+template <typename T>
+hipError_t configure_dense(size_t lds);
 template <typename T>
 hipError_t launch_adjoint(const SysDev &S, const T *C, const double *R, const MeasBufs<T> &mb,
                           const WalkerOut &out, const AdjLayout &L, int W, hipStream_t st);
@@ -85,7 +88,6 @@ template <typename T>
 hipError_t configure_adjoint(size_t lds);
 hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb,
                            const WalkerOut &out, int warp, int W, hipStream_t st);
-hipError_t configure_pipeline(size_t dense_lds);
 template <typename T>
 hipError_t configure_sweep(size_t lds);
 
