@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="9atom")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--pmc-probe", action="store_true",
@@ -94,7 +95,7 @@ def main():
     mol = spec.molecule
     W = args.walkers or spec.n_walkers
     dev = torch.device("cuda:0")
-    ctx = vmc.Context(mol, max_walkers=W, refresh_period=32)
+    ctx = vmc.Context(mol, max_walkers=W, refresh_period=32, precision=args.precision)
     walkers = torch.tensor(inputs.initial_walkers(mol, W, spec.seed), device=dev)
     if args.pmc_probe:
         ctx.sweep(walkers, 2, spec.seed, measure=False)

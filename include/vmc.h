@@ -57,6 +57,10 @@ extern "C" {
 
 /* ---- precision modes ------------------------------------------------------ */
 #define VMC_FP64   0         /* every step in FP64                              */
+#define VMC_MIXED  1         /* FP32 AO evaluation, MO products on FP32 MFMA,
+                                FP32 Sherman-Morrison and back-projection; FP64
+                                inverse refresh, determinants, E_L assembly,
+                                Jastrow and every sum over walkers            */
 
 /* ---- flags ---------------------------------------------------------------- */
 #define VMC_SWEEP_MEASURE   1u   /* measure + accumulate after every sweep      */
@@ -111,7 +115,7 @@ typedef struct {
 } vmc_jastrow;
 
 /* Run options.
- * precision      : VMC_FP64
+ * precision      : VMC_FP64 or VMC_MIXED
  * refresh_period : the Slater inverse is recomputed from scratch after every
  *                  refresh_period-th proposed move (counted per walker over
  *                  the global move index sweep*N + e) and at every sweep start;
@@ -120,7 +124,12 @@ typedef struct {
  * max_walkers    : largest n_walkers any call on this context will pass
  * staging_walkers: walkers measured per launch (per-walker staging buffers);
  *                  0 = as many as fit in 2 GiB of staging
- * step_sigma     : proposal r' = r + step_sigma * N(0, I_3)                   */
+ * step_sigma     : proposal r' = r + step_sigma * N(0, I_3)
+ * promote_cond   : VMC_MIXED only: a walker whose Slater blocks have
+ *                  max|K| * max|A| above this (K = A^-1, FP64 from the FP32
+ *                  orbital values) is measured again in FP64 and its FP64
+ *                  results replace the mixed ones; 0 disables.  Costs one
+ *                  host read of the promoted count per measurement launch. */
 typedef struct {
     int32_t precision;
     int32_t refresh_period;
@@ -128,6 +137,7 @@ typedef struct {
     int32_t max_walkers;
     int32_t staging_walkers;
     double  step_sigma;
+    double  promote_cond;
 } vmc_options;
 
 /* Per-walker outputs of one measurement (device arrays, any may be NULL).

@@ -1,8 +1,8 @@
 // vmc_abi.hip -- host side of the C ABI declared in include/vmc.h.
 //
 // Owns the context (validated inputs, folded GTO normalisation, device
-// buffers), sequences the kernels of vmc_kernels.hip on the caller's stream,
-// and finishes the estimators in FP64 on the host.
+// buffers), sequences the kernels of the vmc_*.hip sources on the caller's
+// stream, and finishes the estimators in FP64 on the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -65,13 +66,12 @@ struct vmc_ctx {
     double *d_ao_eta = nullptr, *d_prim_exp = nullptr, *d_prim_cp = nullptr, *d_C = nullptr, *d_R = nullptr,
            *d_Z = nullptr;
     int *d_shell_l = nullptr, *d_shell_mu0 = nullptr;
-    int *d_tile = nullptr;   // [4][n_tiles]: first shell, end shell, first AO, end AO (<= 32 AOs)
-    int *d_tile16 = nullptr; // same with <= 16 AOs per tile
-    AoTiles tiles{}, tiles16{};
+    int *d_tile16 = nullptr; // [4][n_tiles]: first shell, end shell, first AO, end AO (<= 16 AOs)
+    AoTiles tiles16{};
     SysDev sys{};
-    SweepLayout swl{};   // k_sweep_r, FP64
+    SweepLayout swl{};   // k_sweep_r in the arithmetic type of the precision
     DenseLayout dl{};
-    AdjLayout al{};      // k_adjoint_mfma, FP64
+    AdjLayout al{};      // k_adjoint_mfma in the arithmetic type of the precision
 
     int64_t chunk = 0;
     double *st_EL = nullptr, *st_lnpsi = nullptr, *st_lnjac = nullptr, *st_dEdR = nullptr, *st_dPdR = nullptr,
@@ -79,7 +79,15 @@ struct vmc_ctx {
     // measurement pipeline staging (chunk walkers)
     double *mb_phi = nullptr, *mb_ktil = nullptr, *mb_abar = nullptr, *mb_gb = nullptr, *mb_dpart = nullptr,
            *mb_tao = nullptr, *mb_posw = nullptr;
-    double *Amo = nullptr;   // [max_walkers][N][n] MO matrix maintained by the sweep
+    void *Amo = nullptr;     // [max_walkers][N][n] MO matrix maintained by the sweep (type T)
+    float *d_Cf = nullptr;   // C in FP32 (mixed precision)
+    float *d_Cm = nullptr;   // FP32 copy of a caller's C (mixed precision)
+    // FP64 re-measurement of ill-conditioned walkers (mixed precision)
+    AdjLayout al64{};
+    int *plist = nullptr, *pcount = nullptr;
+    int64_t pcap = 0;
+    double *cp_pos = nullptr, *cp_pos0 = nullptr, *cp_EL = nullptr, *cp_lnpsi = nullptr, *cp_dEdR = nullptr,
+           *cp_dPdR = nullptr, *cp_dJdR = nullptr, *cp_O = nullptr, *cp_G = nullptr;
 
     int64_t n_est = 0;
     double *acc = nullptr, *comp = nullptr, *partial = nullptr;
@@ -198,8 +206,30 @@ static void layouts(vmc_ctx *c) {
     d.bytes = (size_t)d.off_red + 8 * 8;
 }
 
-// One measurement of `cw` walkers at positions pos0 (device [cw][N][3]):
-// forward always; adjoint when `full`.  Outputs already offset to the chunk.
+// The measurement kernels on cw walkers at (possibly warped) positions pos
+// with sampling positions pos0.  plist: promotion list for the dense kernel.
+template <typename T>
+static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64_t cw, const T *C, const double *R,
+                        const double *R0, int warp, int full, const WalkerOut &o, const AdjLayout &al, int *plist,
+                        hipStream_t st) {
+    const SysDev &S = c->sys;
+    T *phi = (T *)c->mb_phi;
+    MeasBufs<T> mb{pos,         pos0,       phi,       full ? (T *)c->mb_ktil : nullptr, (T *)c->mb_abar, c->mb_gb,
+                   c->mb_dpart, c->mb_tao, plist,     c->pcount,                        c->opt.promote_cond};
+    HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, st));
+    HIP_OK(c, vmcx::launch_dense<T>(S, R, mb, o, c->status, c->dl, (int)cw, st));
+    if (!full) return VMC_OK;
+    HIP_OK(c, vmcx::launch_adjoint<T>(S, C, R, mb, o, al, (int)cw, st));
+    MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
+    HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, o, warp, (int)cw, st));
+    return VMC_OK;
+}
+
+// One measurement of `cw` walkers at positions pos0 (device [cw][N][3]) with
+// the caller's FP64 C: forward always; adjoint when `full`.  Outputs already
+// offset to the chunk.  In mixed precision C is rounded to FP32, and the
+// walkers the dense kernel flags as ill-conditioned are measured again in
+// FP64 (gathered, measured, scattered over their mixed results).
 static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double *C, const double *R,
                        const double *R0, int warp, int full, const WalkerOut &o, hipStream_t st) {
     const SysDev &S = c->sys;
@@ -210,14 +240,42 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     } else if (o.lnjac) {
         HIP_OK(c, hipMemsetAsync(o.lnjac, 0, cw * sizeof(double), st));
     }
-    MeasBufs<double> mb{pos, pos0, c->mb_phi, full ? c->mb_ktil : nullptr, c->mb_abar, c->mb_gb, c->mb_dpart,
-                        c->mb_tao};
-    HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(S, C, R, pos, cw * c->N, c->tiles16, c->mb_phi, 5, st));
-    HIP_OK(c, vmcx::launch_dense<double>(S, R, mb, o, c->status, c->dl, (int)cw, st));
-    if (!full) return VMC_OK;
-    HIP_OK(c, vmcx::launch_adjoint<double>(S, C, R, mb, o, c->al, (int)cw, st));
-    MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
-    HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, o, warp, (int)cw, st));
+    if (c->opt.precision != VMC_MIXED) return measure_core<double>(c, pos, pos0, cw, C, R, R0, warp, full, o, c->al,
+                                                                   nullptr, st);
+    const float *Cf = c->d_Cf;
+    if (C != c->d_C) {
+        HIP_OK(c, vmcx::launch_round_f32(C, c->d_Cm, (int64_t)c->M * c->n_occ, st));
+        Cf = c->d_Cm;
+    }
+    const bool promote = c->opt.promote_cond > 0.0;
+    if (promote) HIP_OK(c, hipMemsetAsync(c->pcount, 0, sizeof(int), st));
+    int rc = measure_core<float>(c, pos, pos0, cw, Cf, R, R0, warp, full, o, c->al, promote ? c->plist : nullptr,
+                                 st);
+    if (rc || !promote) return rc;
+    int cnt = 0;
+    HIP_OK(c, hipMemcpyAsync(&cnt, c->pcount, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+    const int64_t N3 = 3 * (int64_t)c->N, A3 = 3 * (int64_t)c->A, Mn = (int64_t)c->M * c->n_occ;
+    for (int64_t k0 = 0; k0 < cnt; k0 += c->pcap) {
+        const int64_t kc = std::min<int64_t>(c->pcap, cnt - k0);
+        const int *lst = c->plist + k0;
+        HIP_OK(c, vmcx::launch_gather_rows(pos, lst, kc, N3, c->cp_pos, st));
+        HIP_OK(c, vmcx::launch_gather_rows(pos0, lst, kc, N3, c->cp_pos0, st));
+        WalkerOut oc{o.EL ? c->cp_EL : nullptr,        o.lnpsi ? c->cp_lnpsi : nullptr,  nullptr,
+                     o.dEL_dR ? c->cp_dEdR : nullptr, o.dlnpsi_dR ? c->cp_dPdR : nullptr,
+                     o.dlnjac_dR ? c->cp_dJdR : nullptr, o.O ? c->cp_O : nullptr, o.G ? c->cp_G : nullptr};
+        if ((rc = measure_core<double>(c, c->cp_pos, c->cp_pos0, kc, C, R, R0, warp, full, oc, c->al64, nullptr,
+                                       st)))
+            return rc;
+        const std::pair<double *, double *> rows[] = {{oc.EL, o.EL},         {oc.lnpsi, o.lnpsi},
+                                                      {oc.dEL_dR, o.dEL_dR}, {oc.dlnpsi_dR, o.dlnpsi_dR},
+                                                      {oc.dlnjac_dR, o.dlnjac_dR}, {oc.O, o.O},
+                                                      {oc.G, o.G}};
+        const int64_t lens[] = {1, 1, A3, A3, A3, Mn, Mn};
+        for (int k = 0; k < 7; ++k)
+            if (rows[k].first && (full || k < 2))
+                HIP_OK(c, vmcx::launch_scatter_rows(rows[k].first, lst, kc, lens[k], rows[k].second, st));
+    }
     return VMC_OK;
 }
 
@@ -300,10 +358,10 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         return bail(c->fail(VMC_EINVAL, "non-finite nuclei or MO coefficients"));
     if (!std::isfinite(jas->ee_a) || !std::isfinite(jas->ee_F) || jas->ee_F < 0.0)
         return bail(c->fail(VMC_EINVAL, "bad Jastrow parameters"));
-    if (opt->precision != VMC_FP64)
-        return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 only)", opt->precision));
+    if (opt->precision != VMC_FP64 && opt->precision != VMC_MIXED)
+        return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 or VMC_MIXED)", opt->precision));
     if (opt->refresh_period < 1 || opt->block_sweeps < 1 || opt->max_walkers < 1 || opt->staging_walkers < 0 ||
-        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma))
+        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_cond >= 0.0))
         return bail(c->fail(VMC_EINVAL, "bad options"));
     double Zsum = 0.0;
     for (int a = 0; a < A; ++a) Zsum += nuclei->Z[a];
@@ -376,17 +434,15 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
             for (int k = 0; k < 4; ++k) soa[k * nt + t] = tl[4 * t + k];
         return soa;
     };
-    const std::vector<int> tile32 = make_tiles(32), tile16 = make_tiles(16);
-    const int n_tiles = (int)tile32.size() / 4, n_tiles16 = (int)tile16.size() / 4;
+    const std::vector<int> tile16 = make_tiles(16);
+    const int n_tiles16 = (int)tile16.size() / 4;
 
     int rc;
     if ((rc = set_device(c))) return bail(rc);
     if ((rc = c->upload(&c->d_shell_l, (const int *)basis->shell_l, S)) ||
         (rc = c->upload(&c->d_shell_mu0, shell_mu0.data(), S)) ||
-        (rc = c->upload(&c->d_tile, tile32.data(), 4 * n_tiles)) ||
         (rc = c->upload(&c->d_tile16, tile16.data(), 4 * n_tiles16)))
         return bail(rc);
-    c->tiles = AoTiles{c->d_tile, c->d_tile + n_tiles, c->d_tile + 2 * n_tiles, c->d_tile + 3 * n_tiles, n_tiles};
     c->tiles16 = AoTiles{c->d_tile16, c->d_tile16 + n_tiles16, c->d_tile16 + 2 * n_tiles16,
                          c->d_tile16 + 3 * n_tiles16, n_tiles16};
     if ((rc = c->upload(&c->d_ao_shell, ao_shell.data(), M)) || (rc = c->upload(&c->d_ao_pow, ao_pow.data(), M)) ||
@@ -398,6 +454,12 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->upload(&c->d_C, mo->C, (size_t)M * c->n_occ)) || (rc = c->upload(&c->d_R, nuclei->xyz, 3 * A)) ||
         (rc = c->upload(&c->d_Z, nuclei->Z, A)))
         return bail(rc);
+    if (opt->precision == VMC_MIXED) {
+        std::vector<float> cf((size_t)M * c->n_occ);
+        for (size_t k = 0; k < cf.size(); ++k) cf[k] = (float)mo->C[k];
+        if ((rc = c->upload(&c->d_Cf, cf.data(), cf.size())) || (rc = c->dalloc(&c->d_Cm, cf.size())))
+            return bail(rc);
+    }
 
     SysDev &sd = c->sys;
     sd.N = c->N;
@@ -413,14 +475,25 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
                               c->d_shell_l, c->d_shell_mu0};
     sd.Z = c->d_Z;
     layouts(c);
-    c->swl = sweep_layout(c, sizeof(double));
-    c->al = adjoint_layout(c, sizeof(double));
+    const bool mixed = opt->precision == VMC_MIXED;
+    const size_t ts = mixed ? sizeof(float) : sizeof(double);
+    c->swl = sweep_layout(c, ts);
+    c->al = adjoint_layout(c, ts);
     if (c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024 || c->al.bytes > 160 * 1024)
         return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu / %zu / %zu bytes)",
                             c->swl.bytes, c->dl.bytes, c->al.bytes));
-    if (vmcx::configure_dense<double>(c->dl.bytes) != hipSuccess ||
-        vmcx::configure_sweep<double>(c->swl.bytes) != hipSuccess ||
-        vmcx::configure_adjoint<double>(c->al.bytes) != hipSuccess)
+    c->al64 = adjoint_layout(c, sizeof(double));
+    if (c->al64.bytes > 160 * 1024)
+        return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu bytes)", c->al64.bytes));
+    // the FP64 kernels are also the fallback of the mixed path
+    bool cfg_ok = vmcx::configure_dense<double>(c->dl.bytes) == hipSuccess &&
+                  vmcx::configure_sweep<double>(sweep_layout(c, sizeof(double)).bytes) == hipSuccess &&
+                  vmcx::configure_adjoint<double>(c->al64.bytes) == hipSuccess;
+    if (mixed)
+        cfg_ok = cfg_ok && vmcx::configure_dense<float>(c->dl.bytes) == hipSuccess &&
+                 vmcx::configure_sweep<float>(c->swl.bytes) == hipSuccess &&
+                 vmcx::configure_adjoint<float>(c->al.bytes) == hipSuccess;
+    if (!cfg_ok)
         return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the kernels"));
 
     // ---- staging and accumulators -------------------------------------------
@@ -440,8 +513,19 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->mb_abar, chunk * Nn)) || (rc = c->dalloc(&c->mb_gb, chunk * 6 * c->N)) ||
         (rc = c->dalloc(&c->mb_dpart, chunk * 3 * (int64_t)c->N)) ||
         (rc = c->dalloc(&c->mb_tao, chunk * 6 * M)) || (rc = c->dalloc(&c->mb_posw, chunk * 3 * c->N)) ||
-        (rc = c->dalloc(&c->Amo, (size_t)opt->max_walkers * Nn)))
+        (rc = c->dalloc((double **)&c->Amo, (size_t)opt->max_walkers * Nn)))
         return bail(rc);
+    if (opt->precision == VMC_MIXED && opt->promote_cond > 0.0) {
+        c->pcap = std::max<int64_t>(1, chunk / 8);
+        const int64_t p = c->pcap;
+        if ((rc = c->dalloc(&c->plist, chunk)) || (rc = c->dalloc(&c->pcount, 1)) ||
+            (rc = c->dalloc(&c->cp_pos, p * 3 * c->N)) || (rc = c->dalloc(&c->cp_pos0, p * 3 * c->N)) ||
+            (rc = c->dalloc(&c->cp_EL, p)) || (rc = c->dalloc(&c->cp_lnpsi, p)) ||
+            (rc = c->dalloc(&c->cp_dEdR, p * A3)) || (rc = c->dalloc(&c->cp_dPdR, p * A3)) ||
+            (rc = c->dalloc(&c->cp_dJdR, p * A3)) || (rc = c->dalloc(&c->cp_O, p * Mn)) ||
+            (rc = c->dalloc(&c->cp_G, p * Mn)))
+            return bail(rc);
+    }
     c->n_est = 2 + 3 * A3 + 3 * Mn;
     const int64_t n_vjp = Mn + A3;
     if ((rc = c->dalloc(&c->acc, c->n_est)) || (rc = c->dalloc(&c->comp, c->n_est)) ||
@@ -475,12 +559,23 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
         uint8_t *acc_t = accept ? accept + (size_t)t * c->N * W : nullptr;
         // the MO matrix of every walker from the caller's positions; the
         // sweeps keep it current (row e rewritten on each accepted move)
-        if (t == 0)
-            HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
-                                                       c->Amo, 1, st));
-        HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, c->Amo, sidx, seed,
-                                             c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
-                                             st));
+        if (c->opt.precision == VMC_MIXED) {
+            float *Amo = (float *)c->Amo;
+            if (t == 0)
+                HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, walkers, W * c->N, c->tiles16,
+                                                          Amo, 1, st));
+            HIP_OK(c, vmcx::launch_sweep<float>(c->sys, c->d_Cf, c->d_R, walkers, (int)W, Amo, sidx, seed,
+                                                c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
+                                                st));
+        } else {
+            double *Amo = (double *)c->Amo;
+            if (t == 0)
+                HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
+                                                           Amo, 1, st));
+            HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, Amo, sidx, seed,
+                                                 c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status,
+                                                 c->swl, st));
+        }
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
         const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
         double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;

@@ -92,10 +92,11 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                 T psi = T(0), q = T(0);
                 double t6[6] = {0, 0, 0, 0, 0, 0};
                 if (e < N && vm) {
-                    const T x = (T)(sp[3 * e] - Rx), y = (T)(sp[3 * e + 1] - Ry), z = (T)(sp[3 * e + 2] - Rz);
-                    const T rho = x * x + y * y + z * z;
+                    const double dx = sp[3 * e] - Rx, dy = sp[3 * e + 1] - Ry, dz = sp[3 * e + 2] - Rz;
+                    const double rho_d = dx * dx + dy * dy + dz * dz;
+                    const T x = (T)dx, y = (T)dy, z = (T)dz, rho = (T)rho_d;
                     T R0, R1, R2, R3;
-                    shell_radial<14, T>(S.basis, s, rho, R0, R1, R2, R3);
+                    shell_radial<14, T>(S.basis, s, rho_d, R0, R1, R2, R3);
                     T d[14];
                     ao_components<14, T>(x, y, z, rho, R0, R1, R2, R3, pw, eta, d);
                     const T gx = (T)sg[3 * e], gy = (T)sg[3 * e + 1], gz = (T)sg[3 * e + 2];
@@ -201,5 +202,9 @@ hipError_t configure_adjoint(size_t lds) {
 template hipError_t launch_adjoint<double>(const SysDev &, const double *, const double *, const MeasBufs<double> &,
                                            const WalkerOut &, const AdjLayout &, int, hipStream_t);
 template hipError_t configure_adjoint<double>(size_t);
+
+template hipError_t launch_adjoint<float>(const SysDev &, const float *, const double *, const MeasBufs<float> &,
+                                          const WalkerOut &, const AdjLayout &, int, hipStream_t);
+template hipError_t configure_adjoint<float>(size_t);
 
 }  // namespace vmcx

@@ -10,7 +10,10 @@
 //            and (with the adjoint) X[e][i] = lap phi_i + 2 g_e . grad phi_i;
 //            then on 16x16x4 FP64 MFMA T = X K and
 //            Abar = 1/2 (K X K)^T = 1/2 T^T K^T, written with K~[e][i] = K[i][e].
-//   phase C  block sums: E_L, ln|Psi| = log|det up| + log|det dn| + J.
+//   phase C  block sums: E_L, ln|Psi| = log|det up| + log|det dn| + J; the
+//            walker joins the promotion list if max|K| max|A| of a block
+//            exceeds the threshold (its T-precision orbitals are then too
+//            coarse for E_L and the derivatives).
 // K, X and T stay FP64; K~ and Abar are stored in the arithmetic type T.
 #include "vmc_mfma.hpp"
 #include "vmc_pipeline.hpp"
@@ -62,10 +65,25 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
             if (lz < nb && r < nb) v = (double)ph[(size_t)(off + r) * 5 * n + lz];
             Br[r] = v;
         }
+        // condition indicator of the block: max |A| before, max |K| after
+        double amax = 0.0;
+#pragma unroll
+        for (int r = 0; r < KN; ++r) amax = fmax(amax, (lz < nb && r < nb) ? fabs(Br[r]) : 0.0);
         int sig;
         double la;
         gj_regs<KN, true>(Br, sig, bad, la);
-        if (lane == 0) red[4 + b] = la;
+        double kmax = 0.0;
+#pragma unroll
+        for (int r = 0; r < KN; ++r) kmax = fmax(kmax, (sig < nb && r < nb) ? fabs(Br[r]) : 0.0);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            amax = fmax(amax, __shfl_xor(amax, o, 64));
+            kmax = fmax(kmax, __shfl_xor(kmax, o, 64));
+        }
+        if (lane == 0) {
+            red[4 + b] = la;
+            red[6 + b] = amax * kmax;
+        }
         // natural layout: lane p_k holds column k with register j = orbital p_j
         if (lane < KN) perm[64 * b + sig] = lane;
         wave_sync_s();
@@ -215,6 +233,8 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
     const double J = block_sum4(j_part, red);
     const int anybad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0) {
+        if (mb.promote_list && fmax(red[6], red[7]) > mb.promote_cond)
+            mb.promote_list[atomicAdd(mb.promote_count, 1)] = w;
         if (out.EL) out.EL[w] = EL;
         if (out.lnpsi) out.lnpsi[w] = logdet + J;
         if (anybad) atomicOr(status, STATUS_SINGULAR);
@@ -249,5 +269,9 @@ hipError_t configure_dense(size_t lds) {
 template hipError_t launch_dense<double>(const SysDev &, const double *, const MeasBufs<double> &, const WalkerOut &,
                                          int *, const DenseLayout &, int, hipStream_t);
 template hipError_t configure_dense<double>(size_t);
+
+template hipError_t launch_dense<float>(const SysDev &, const double *, const MeasBufs<float> &, const WalkerOut &,
+                                        int *, const DenseLayout &, int, hipStream_t);
+template hipError_t configure_dense<float>(size_t);
 
 }  // namespace vmcx

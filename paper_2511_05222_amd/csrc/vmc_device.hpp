@@ -1,7 +1,7 @@
 // vmc_device.hpp -- device math of the VMC hot path (gfx950).
 //
 // Everything here is __host__ __device__ so that the same arithmetic can be
-// checked on the CPU.  Kernels live in vmc_kernels.hip.
+// checked on the CPU.  The kernels live in the vmc_*.hip sources.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,15 +98,28 @@ __host__ __device__ inline T tpow(T x, int k) {
     return k <= 0 ? (k == 0 ? T(1) : T(0)) : (k == 1 ? x : x * x);
 }
 
-// Radial sums of shell s at rho = |r - R_A|^2: R0 = sum c' e^{-a rho} and its
-// first three rho-derivatives (NC > 5 needs R3).
+// e^{-x} for x = a rho >= 0 in the arithmetic type T.  In FP32 the product
+// is formed in FP64 and split as x = xh + xl (xh = fp32(x)), and
+// e^{-x} = e^{-xh} (1 - xl): rounding x itself to FP32 would cost a relative
+// error of x 2^-24 in the result (1e-6 at x = 20).
+__host__ __device__ inline double exp_neg(double a, double rho, double) { return exp(-a * rho); }
+__host__ __device__ inline float exp_neg(double a, double rho, float) {
+    const double x = a * rho;
+    const float xh = (float)x;
+    const float xl = (float)(x - (double)xh);
+    return expf(-xh) * (1.0f - xl);
+}
+
+// Radial sums of shell s at rho = |r - R_A|^2 (formed in FP64):
+// R0 = sum c' e^{-a rho} and its first three rho-derivatives (NC > 5 needs R3).
 template <int NC, typename T>
-__host__ __device__ inline void shell_radial(const BasisDev &B, int s, T rho, T &R0, T &R1, T &R2, T &R3) {
+__host__ __device__ inline void shell_radial(const BasisDev &B, int s, double rho, T &R0, T &R1, T &R2, T &R3) {
     const int p0 = B.shell_p0[s], np = B.shell_np[s];
     R0 = R1 = R2 = R3 = T(0);
     for (int k = 0; k < np; ++k) {
-        const T al = (T)B.prim_exp[p0 + k];
-        const T e = (T)B.prim_cp[p0 + k] * exp(-al * rho);
+        const double ad = B.prim_exp[p0 + k];
+        const T al = (T)ad;
+        const T e = (T)B.prim_cp[p0 + k] * exp_neg(ad, rho, T(0));
         R0 += e;
         if (NC > 1) {
             R1 -= al * e;
@@ -163,26 +176,10 @@ __host__ __device__ inline void ao_components(T x, T y, T z, T rho, T R0, T R1, 
     out[13] = eta * ((two * z * lapP + c1 * Pz) * R1 + (c2 * z * P + four * rho * Pz) * R2 + eight * rho * z * P * R3);
 }
 
-// All cartesian components of shell s at electron (rx, ry, rz): out[q*NC + k].
-// The displacement is formed in FP64 and then rounded to T.  Returns the
-// number of components.
-template <int NC, typename T>
-__host__ __device__ inline int shell_eval(const BasisDev &B, const double *R, int s, double rx, double ry, double rz,
-                                          T *out) {
-    const int atom = B.shell_atom[s];
-    const T x = (T)(rx - R[3 * atom]), y = (T)(ry - R[3 * atom + 1]), z = (T)(rz - R[3 * atom + 2]);
-    const T rho = x * x + y * y + z * z;
-    T R0, R1, R2, R3;
-    shell_radial<NC, T>(B, s, rho, R0, R1, R2, R3);
-    const int l = B.shell_l[s], mu0 = B.shell_mu0[s], nc = n_cart(l);
-    for (int q = 0; q < nc; ++q)
-        ao_components<NC, T>(x, y, z, rho, R0, R1, R2, R3, cart_pow(l, q), (T)B.ao_eta[mu0 + q], out + q * NC);
-    return nc;
-}
-
-// shell_eval with the angular momentum fixed at compile time, so that every
-// component index is a constant and nothing lands in per-lane scratch:
-// components are stored straight to dst[q*NC + k] (LDS or registers).
+// All cartesian components of shell s at an electron, with the angular
+// momentum fixed at compile time so that every component index is a constant
+// and nothing lands in per-lane scratch: stored straight to dst[q*NC + k] (LDS
+// or registers).  The displacement is formed in FP64 and rounded to T.
 template <int NC, typename T, int L>
 __host__ __device__ inline void shell_components(const BasisDev &B, int mu0, T x, T y, T z, T rho, T R0, T R1,
                                                  T R2, T R3, T *dst) {
@@ -199,10 +196,12 @@ template <int NC, typename T>
 __host__ __device__ inline int shell_eval_to(const BasisDev &B, const double *R, int s, double rx, double ry,
                                              double rz, T *dst) {
     const int atom = B.shell_atom[s];
-    const T x = (T)(rx - R[3 * atom]), y = (T)(ry - R[3 * atom + 1]), z = (T)(rz - R[3 * atom + 2]);
-    const T rho = x * x + y * y + z * z;
+    const double dx = rx - R[3 * atom], dy = ry - R[3 * atom + 1], dz = rz - R[3 * atom + 2];
+    const double rho_d = dx * dx + dy * dy + dz * dz;
+    const T x = (T)dx, y = (T)dy, z = (T)dz;
+    const T rho = (T)rho_d;
     T R0, R1, R2, R3;
-    shell_radial<NC, T>(B, s, rho, R0, R1, R2, R3);
+    shell_radial<NC, T>(B, s, rho_d, R0, R1, R2, R3);
     const int l = B.shell_l[s], mu0 = B.shell_mu0[s];
     if (l == 0) {
         shell_components<NC, T, 0>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
@@ -214,77 +213,6 @@ __host__ __device__ inline int shell_eval_to(const BasisDev &B, const double *R,
     }
     shell_components<NC, T, 2>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
     return 6;
-}
-
-__host__ __device__ inline double ipow(double x, int k) {
-    // k in -2..2 for l <= 2 shells; negative powers only appear multiplied by 0
-    return k <= 0 ? (k == 0 ? 1.0 : 0.0) : (k == 1 ? x : x * x);
-}
-
-// Number of AO derivative components written by ao_eval<NC>:
-//   NC = 1  : value
-//   NC = 5  : value, d/dx, d/dy, d/dz, laplacian
-//   NC = 14 : + hessian xx,xy,xz,yy,yz,zz (5..10), d(lap)/dx,dy,dz (11..13)
-template <int NC>
-__host__ __device__ inline void ao_eval(const BasisDev &B, const double *R, int mu, double rx,
-                                        double ry, double rz, double *out) {
-    const int s = B.ao_shell[mu];
-    const int atom = B.shell_atom[s];
-    const double x = rx - R[3 * atom + 0];
-    const double y = ry - R[3 * atom + 1];
-    const double z = rz - R[3 * atom + 2];
-    const double rho = x * x + y * y + z * z;
-    const int p0 = B.shell_p0[s], np = B.shell_np[s];
-    double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0;
-    for (int k = 0; k < np; ++k) {
-        const double al = B.prim_exp[p0 + k];
-        const double e = B.prim_cp[p0 + k] * exp(-al * rho);
-        R0 += e;
-        if (NC > 1) {
-            R1 -= al * e;
-            R2 += al * al * e;
-            if (NC > 5) R3 -= al * al * al * e;
-        }
-    }
-    const int pw = B.ao_pow[mu];
-    const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15;
-    const int l = a + b + c;
-    const double eta = B.ao_eta[mu];
-    const double xa = ipow(x, a), yb = ipow(y, b), zc = ipow(z, c);
-    const double P = xa * yb * zc;
-    out[0] = eta * P * R0;
-    if (NC == 1) return;
-    // first derivatives of the monomial
-    const double Px = a * ipow(x, a - 1) * yb * zc;
-    const double Py = b * xa * ipow(y, b - 1) * zc;
-    const double Pz = c * xa * yb * ipow(z, c - 1);
-    // second derivatives of the monomial (l <= 2: constants or linear)
-    const double Pxx = a * (a - 1) * ipow(x, a - 2) * yb * zc;
-    const double Pyy = b * (b - 1) * xa * ipow(y, b - 2) * zc;
-    const double Pzz = c * (c - 1) * xa * yb * ipow(z, c - 2);
-    const double lapP = Pxx + Pyy + Pzz;
-    out[1] = eta * (Px * R0 + 2.0 * x * P * R1);
-    out[2] = eta * (Py * R0 + 2.0 * y * P * R1);
-    out[3] = eta * (Pz * R0 + 2.0 * z * P * R1);
-    // lap[P R(rho)] = lapP R + 4 (x.gradP) R' + P (6 R' + 4 rho R''), x.gradP = l P
-    out[4] = eta * (lapP * R0 + (4.0 * l + 6.0) * P * R1 + 4.0 * rho * P * R2);
-    if (NC == 5) return;
-    const double Pxy = a * b * ipow(x, a - 1) * ipow(y, b - 1) * zc;
-    const double Pxz = a * c * ipow(x, a - 1) * yb * ipow(z, c - 1);
-    const double Pyz = b * c * xa * ipow(y, b - 1) * ipow(z, c - 1);
-    // d_i d_j [P R] = P_ij R + 2 (x_j P_i + x_i P_j) R' + 2 delta_ij P R' + 4 x_i x_j P R''
-    out[5] = eta * (Pxx * R0 + 4.0 * x * Px * R1 + 2.0 * P * R1 + 4.0 * x * x * P * R2);
-    out[6] = eta * (Pxy * R0 + 2.0 * (y * Px + x * Py) * R1 + 4.0 * x * y * P * R2);
-    out[7] = eta * (Pxz * R0 + 2.0 * (z * Px + x * Pz) * R1 + 4.0 * x * z * P * R2);
-    out[8] = eta * (Pyy * R0 + 4.0 * y * Py * R1 + 2.0 * P * R1 + 4.0 * y * y * P * R2);
-    out[9] = eta * (Pyz * R0 + 2.0 * (z * Py + y * Pz) * R1 + 4.0 * y * z * P * R2);
-    out[10] = eta * (Pzz * R0 + 4.0 * z * Pz * R1 + 2.0 * P * R1 + 4.0 * z * z * P * R2);
-    // d_k lap[P R] with lapP constant for l <= 2:
-    //   (2 x_k lapP + (4l+6) P_k) R' + ((8l+20) x_k P + 4 rho P_k) R'' + 8 rho x_k P R'''
-    const double c1 = 4.0 * l + 6.0, c2 = 8.0 * l + 20.0;
-    out[11] = eta * ((2.0 * x * lapP + c1 * Px) * R1 + (c2 * x * P + 4.0 * rho * Px) * R2 + 8.0 * rho * x * P * R3);
-    out[12] = eta * ((2.0 * y * lapP + c1 * Py) * R1 + (c2 * y * P + 4.0 * rho * Py) * R2 + 8.0 * rho * y * P * R3);
-    out[13] = eta * ((2.0 * z * lapP + c1 * Pz) * R1 + (c2 * z * P + 4.0 * rho * Pz) * R2 + 8.0 * rho * z * P * R3);
 }
 
 // ---------------------------------------------------------------------------

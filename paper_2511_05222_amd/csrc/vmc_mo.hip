@@ -109,4 +109,7 @@ hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, con
 template hipError_t launch_mo_rows_mfma<double>(const SysDev &, const double *, const double *, const double *,
                                                 int64_t, const AoTiles &, double *, int, hipStream_t);
 
+template hipError_t launch_mo_rows_mfma<float>(const SysDev &, const float *, const double *, const double *,
+                                               int64_t, const AoTiles &, float *, int, hipStream_t);
+
 }  // namespace vmcx

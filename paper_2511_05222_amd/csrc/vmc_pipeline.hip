@@ -259,4 +259,45 @@ hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, c
     return hipGetLastError();
 }
 
+__global__ void k_round_f32(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+
+hipError_t launch_round_f32(const double *x, float *y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_round_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+// dst[k][j] = src[list[k]][j] and its inverse, rows of len doubles.
+__global__ void k_gather_rows(const double *__restrict__ src, const int *__restrict__ list, int64_t kc, int64_t len,
+                              double *__restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kc * len) return;
+    const int64_t k = t / len, j = t - (t / len) * len;
+    dst[t] = src[(int64_t)list[k] * len + j];
+}
+
+__global__ void k_scatter_rows(const double *__restrict__ src, const int *__restrict__ list, int64_t kc, int64_t len,
+                               double *__restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kc * len) return;
+    const int64_t k = t / len, j = t - (t / len) * len;
+    dst[(int64_t)list[k] * len + j] = src[t];
+}
+
+hipError_t launch_gather_rows(const double *src, const int *list, int64_t kc, int64_t len, double *dst,
+                              hipStream_t st) {
+    const int64_t n = kc * len;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, list, kc, len, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const double *src, const int *list, int64_t kc, int64_t len, double *dst,
+                               hipStream_t st) {
+    const int64_t n = kc * len;
+    hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, list, kc, len, dst);
+    return hipGetLastError();
+}
+
 }  // namespace vmcx

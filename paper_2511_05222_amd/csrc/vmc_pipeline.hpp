@@ -59,6 +59,12 @@ struct MeasBufs {
     double *gb;           // [W][N][6]      Jastrow gradient (0..2), det gradient (3..5)
     double *dedr_part;    // [W][N][3]      dE_L/dr_e, determinant part
     double *tao;          // [W][M][6]      per-AO electron sums of t_k, s_k
+    // walkers whose Slater blocks are ill-conditioned for the arithmetic type
+    // (max|K| max|A| > promote_cond) are appended to promote_list (order of
+    // arrival) and counted in promote_count; null = no promotion
+    int *promote_list;
+    int *promote_count;
+    double promote_cond;
 };
 
 struct MeasBufsD {
@@ -90,5 +96,12 @@ hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, c
                            const WalkerOut &out, int warp, int W, hipStream_t st);
 template <typename T>
 hipError_t configure_sweep(size_t lds);
+
+hipError_t launch_round_f32(const double *x, float *y, int64_t n, hipStream_t st);
+
+hipError_t launch_gather_rows(const double *src, const int *list, int64_t kc, int64_t len, double *dst,
+                              hipStream_t st);
+hipError_t launch_scatter_rows(const double *src, const int *list, int64_t kc, int64_t len, double *dst,
+                               hipStream_t st);
 
 }  // namespace vmcx

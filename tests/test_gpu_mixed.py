@@ -1,0 +1,155 @@
+"""Mixed precision (VMC_MIXED) against FP64 on the same configurations.
+
+The mixed path rounds the AO values, the MO products, the Sherman-Morrison
+inverse and the back-projection/outer products to FP32 (FP32 MFMA with FP32
+accumulation); the inverse refresh, determinants, E_L assembly, the Jastrow
+factor and every sum over walkers stay FP64.
+
+Bounds, on replayed configurations (identical positions for both precisions):
+  walker-averaged energy      |dE| < 1e-5 Ha         (16384 walkers)
+  every bare force component  |dF| < 1e-4 Ha/bohr    (16384 walkers)
+  dE/dC and <dE_L/dC>         max |d| < 1e-3 max |.|  (512 / 256 walkers,
+                                                      oracle accumulator)
+The per-walker error of E_L is FP32 round-off, about 1e-4 Ha at 21 atoms:
+the Laplacians of the tight Gaussians reach |lap psi| ~ 1e4 near the nuclei,
+so each MO Laplacian carries an absolute rounding of order 1e4 * 2^-24.  It
+is unbiased, so walker averages shrink as 1/sqrt(W); the energy and force
+bounds are therefore checked on 16384 walkers (a quarter of the production
+batch).  The dE/dC bound is derived from the arithmetic: each O and G entry
+is an FP32 sum of N products with a relative error of order sqrt(N) 2^-24
+per walker, and the covariance 2(<E O> - <E><O>) cancels the mean part of O,
+which is 1e2-1e3 times larger than the covariance for these inputs: 1e-3 of
+max |dE/dC| leaves a margin of about ten.
+
+The FP32 sweep: accept/reject agrees with FP64 on >= 99.9% of the moves of
+one sweep from identical starting points (a different decision needs u within
+FP32 rounding of q).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2511_05222_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_05222_amd import vmc
+    vmc.lib()
+    return torch.device("cuda:0")
+
+
+def estimators(out):
+    from oracle import estimators as est
+    W, A = out["dEL_dR"].shape[:2]
+    M, n = out["O"].shape[1:]
+    acc = est.Accumulator(A, M, n)
+    acc.add(dict(E_L=out["EL"], H=out["dEL_dR"], P=out["dlnpsi_dR"] + 0.5 * out["dlnjac_dR"], O=out["O"],
+                 G=out["G"]))
+    return acc.result()
+
+
+def replayed(dev, cfg, W, sweeps, seed, outputs):
+    from paper_2511_05222_amd import vmc
+    mol = inputs.make_config(cfg).molecule
+    tw = torch.tensor(inputs.initial_walkers(mol, W, seed), device=dev)
+    c64 = vmc.Context(mol, max_walkers=W, precision="fp64")
+    c64.sweep(tw, sweeps, seed, measure=False)
+    c32 = vmc.Context(mol, max_walkers=W, precision="mixed")
+    o64 = {k: v.cpu().numpy() for k, v in c64.measure(tw, outputs=outputs).items()}
+    o32 = {k: v.cpu().numpy() for k, v in c32.measure(tw, outputs=outputs).items()}
+    torch.cuda.synchronize()
+    return mol, o64, o32
+
+
+def energy_force(out):
+    """E and the bare force from per-walker outputs (shifted FP64 sums)."""
+    E = out["EL"]
+    H = out["dEL_dR"]
+    P = out["dlnpsi_dR"] + 0.5 * out["dlnjac_dR"]
+    s = E.mean()
+    e = E - s
+    eP = np.einsum("w,wak->ak", e, P) / E.shape[0]
+    return s + e.mean(), -H.mean(axis=0) - 2.0 * (eP - e.mean() * P.mean(axis=0))
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_mixed_energy_force(dev, cfg):
+    W = 16384
+    mol, o64, o32 = replayed(dev, cfg, W, 3, 31 + cfg,
+                             ("EL", "lnpsi", "lnjac", "dEL_dR", "dlnpsi_dR", "dlnjac_dR"))
+    E64, F64 = energy_force(o64)
+    E32, F32 = energy_force(o32)
+    dE = abs(E32 - E64)
+    dF = np.abs(F32 - F64).max()
+    el = o32["EL"] - o64["EL"]
+    print(f"\n[mixed vs fp64] cfg{cfg} W={W}: |dE|={dE:.2e} Ha, max|dF|={dF:.2e} Ha/bohr, per-walker dE_L "
+          f"mean {el.mean():.2e} median|.| {np.median(np.abs(el)):.2e} max|.| {np.abs(el).max():.2e}")
+    assert np.isfinite(o32["EL"]).all() and np.isfinite(o32["dEL_dR"]).all()
+    assert dE < 1e-5
+    assert dF < 1e-4
+    # ln|Psi| is assembled in FP64 from FP32 orbital values
+    assert np.abs(o32["lnpsi"] - o64["lnpsi"]).max() < 1e-3
+
+
+@pytest.mark.parametrize("cfg,W", [(1, 512), (2, 256)])
+def test_mixed_dE_dC(dev, cfg, W):
+    mol, o64, o32 = replayed(dev, cfg, W, 3, 41 + cfg, ("EL", "lnpsi", "lnjac", "dEL_dR", "dlnpsi_dR",
+                                                          "dlnjac_dR", "O", "G"))
+    r64, r32 = estimators(o64), estimators(o32)
+    dC = np.abs(r32["dE_dC"] - r64["dE_dC"]).max() / np.abs(r64["dE_dC"]).max()
+    dG = np.abs(r32["dEL_dC_mean"] - r64["dEL_dC_mean"]).max() / np.abs(r64["dEL_dC_mean"]).max()
+    print(f"\n[mixed vs fp64] cfg{cfg} W={W}: dE/dC rel {dC:.2e}, <dE_L/dC> rel {dG:.2e}")
+    assert np.isfinite(o32["O"]).all() and np.isfinite(o32["G"]).all()
+    assert dC < 1e-3
+    assert dG < 1e-3
+
+
+def test_mixed_sweep_agrees(dev):
+    from paper_2511_05222_amd import vmc
+    mol = inputs.make_config(2).molecule
+    W = 512
+    w0 = inputs.initial_walkers(mol, W, 5)
+    bits = {}
+    pos = {}
+    for prec in ("fp64", "mixed"):
+        ctx = vmc.Context(mol, max_walkers=W, precision=prec)
+        tw = torch.tensor(w0, device=dev)
+        acc = torch.zeros((1, mol.n_elec, W), dtype=torch.uint8, device=dev)
+        ctx.sweep(tw, 1, 99, measure=False, accept=acc)
+        torch.cuda.synchronize()
+        bits[prec] = acc.cpu().numpy()
+        pos[prec] = tw.cpu().numpy()
+    agree = np.mean(bits["fp64"] == bits["mixed"])
+    rate = bits["mixed"].mean()
+    print(f"\n[mixed sweep] accept-bit agreement {agree:.6f}, acceptance {rate:.3f}")
+    assert agree >= 0.999
+    assert 0.2 < rate < 0.95
+    same = np.all(bits["fp64"] == bits["mixed"], axis=(0, 1))
+    assert np.array_equal(pos["fp64"][same], pos["mixed"][same])
+
+
+def test_mixed_estimators_run(dev):
+    """The whole mixed path (sweeps with measurement, FP64 accumulation)
+    gives finite estimators close to the FP64 ones of the same chains."""
+    from paper_2511_05222_amd import vmc
+    mol = inputs.make_config(1).molecule
+    W = 256
+    w0 = inputs.initial_walkers(mol, W, 6)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        ctx = vmc.Context(mol, max_walkers=W, precision=prec, block_sweeps=2)
+        tw = torch.tensor(w0, device=dev)
+        ctx.sweep(tw, 4, 123)
+        res[prec] = ctx.accumulate()
+    a, b = res["fp64"], res["mixed"]
+    assert b["n_samples"] == W * 4
+    assert np.isfinite(b["E"]) and np.isfinite(b["F_bare"]).all() and np.isfinite(b["dE_dC"]).all()
+    # chains that diverge after a near-tie decision make this a statistical
+    # comparison: within a few error bars
+    assert abs(a["E"] - b["E"]) < 5 * max(a["E_sigma"], 1e-6)
