@@ -245,6 +245,22 @@ int zvector_solve(const double *H_dev, int64_t d, const double *b_dev, double *z
  * returns -1 for a NULL context. */
 int64_t vmc_staging_walkers(const vmc_ctx *ctx);
 
+/* ---- kernel timing --------------------------------------------------------
+ * vmc_profile(ctx, enable): while enabled, every launch of the kernels named
+ * below (in the context's own precision; not the FP64 re-measurement of
+ * promoted walkers) is bracketed by HIP events recorded on its launch stream,
+ * and their elapsed times accumulate.  Enabling clears the totals.
+ * vmc_profile_read(ctx, kernel, ms, launches, walkers): waits for the recorded
+ * events and returns the summed elapsed milliseconds, the number of launches
+ * and the walkers they processed (any output pointer may be NULL).
+ * Returns VMC_EINVAL for an unknown kernel, VMC_EDEVICE on HIP errors.     */
+#define VMC_K_ADJOINT   0    /* k_adjoint_mfma: back-projection, outer products */
+#define VMC_K_DENSE     1    /* k_dense: inverses, E_L, (K X K)^T / 2           */
+#define VMC_K_MO_ROWS   2    /* k_mo_rows_mfma (value, gradient, Laplacian)      */
+#define VMC_K_SWEEP     3    /* k_sweep_r: one sweep of all walkers              */
+int vmc_profile(vmc_ctx *ctx, int32_t enable);
+int vmc_profile_read(vmc_ctx *ctx, int32_t kernel, double *ms, int64_t *launches, int64_t *walkers);
+
 /* Release the context and its device memory (NULL is ignored). */
 void vmc_free(vmc_ctx *ctx);
 

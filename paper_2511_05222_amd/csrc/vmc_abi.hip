@@ -89,6 +89,14 @@ struct vmc_ctx {
     double *cp_pos = nullptr, *cp_pos0 = nullptr, *cp_EL = nullptr, *cp_lnpsi = nullptr, *cp_dEdR = nullptr,
            *cp_dPdR = nullptr, *cp_dJdR = nullptr, *cp_O = nullptr, *cp_G = nullptr;
 
+    // kernel timing (vmc_profile): event pairs per kernel id
+    struct ProfRec {
+        hipEvent_t a, b;
+        int64_t walkers;
+    };
+    bool prof = false;
+    std::vector<ProfRec> prof_recs[4];
+
     int64_t n_est = 0;
     double *acc = nullptr, *comp = nullptr, *partial = nullptr;
     double *shift = nullptr;
@@ -137,6 +145,35 @@ struct vmc_ctx {
         hipError_t e_ = (call);                                                                \
         if (e_ != hipSuccess) return (ctx)->fail(VMC_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
+
+// Kernel timing: prof_begin records the start event of kernel id k (or does
+// nothing when profiling is off or !on); prof_end the stop event.
+static void prof_clear(vmc_ctx *c) {
+    for (auto &v : c->prof_recs) {
+        for (auto &r : v) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        v.clear();
+    }
+}
+
+static int prof_begin(vmc_ctx *c, int k, bool on, int64_t walkers, hipStream_t st) {
+    if (!c->prof || !on) return -1;
+    vmc_ctx::ProfRec r{};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess ||
+        hipEventRecord(r.a, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    r.walkers = walkers;
+    c->prof_recs[k].push_back(r);
+    return (int)c->prof_recs[k].size() - 1;
+}
+
+static void prof_end(vmc_ctx *c, int k, int idx, hipStream_t st) {
+    if (idx >= 0 && hipEventRecord(c->prof_recs[k][idx].b, st) != hipSuccess) (void)hipGetLastError();
+}
 
 // LDS layout of the sweep for an arithmetic type of ts bytes.
 static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
@@ -211,15 +248,21 @@ static void layouts(vmc_ctx *c) {
 template <typename T>
 static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64_t cw, const T *C, const double *R,
                         const double *R0, int warp, int full, const WalkerOut &o, const AdjLayout &al, int *plist,
-                        hipStream_t st) {
+                        bool prof, hipStream_t st) {
     const SysDev &S = c->sys;
     T *phi = (T *)c->mb_phi;
     MeasBufs<T> mb{pos,         pos0,       phi,       full ? (T *)c->mb_ktil : nullptr, (T *)c->mb_abar, c->mb_gb,
                    c->mb_dpart, c->mb_tao, plist,     c->pcount,                        c->opt.promote_cond};
+    int pi = prof_begin(c, VMC_K_MO_ROWS, prof, cw, st);
     HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, st));
+    prof_end(c, VMC_K_MO_ROWS, pi, st);
+    pi = prof_begin(c, VMC_K_DENSE, prof, cw, st);
     HIP_OK(c, vmcx::launch_dense<T>(S, R, mb, o, c->status, c->dl, (int)cw, st));
+    prof_end(c, VMC_K_DENSE, pi, st);
     if (!full) return VMC_OK;
+    pi = prof_begin(c, VMC_K_ADJOINT, prof, cw, st);
     HIP_OK(c, vmcx::launch_adjoint<T>(S, C, R, mb, o, al, (int)cw, st));
+    prof_end(c, VMC_K_ADJOINT, pi, st);
     MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
     HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, o, warp, (int)cw, st));
     return VMC_OK;
@@ -240,8 +283,8 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     } else if (o.lnjac) {
         HIP_OK(c, hipMemsetAsync(o.lnjac, 0, cw * sizeof(double), st));
     }
-    if (c->opt.precision != VMC_MIXED) return measure_core<double>(c, pos, pos0, cw, C, R, R0, warp, full, o, c->al,
-                                                                   nullptr, st);
+    if (c->opt.precision != VMC_MIXED)
+        return measure_core<double>(c, pos, pos0, cw, C, R, R0, warp, full, o, c->al, nullptr, true, st);
     const float *Cf = c->d_Cf;
     if (C != c->d_C) {
         HIP_OK(c, vmcx::launch_round_f32(C, c->d_Cm, (int64_t)c->M * c->n_occ, st));
@@ -250,7 +293,7 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     const bool promote = c->opt.promote_cond > 0.0;
     if (promote) HIP_OK(c, hipMemsetAsync(c->pcount, 0, sizeof(int), st));
     int rc = measure_core<float>(c, pos, pos0, cw, Cf, R, R0, warp, full, o, c->al, promote ? c->plist : nullptr,
-                                 st);
+                                 true, st);
     if (rc || !promote) return rc;
     int cnt = 0;
     HIP_OK(c, hipMemcpyAsync(&cnt, c->pcount, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -265,7 +308,7 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
                      o.dEL_dR ? c->cp_dEdR : nullptr, o.dlnpsi_dR ? c->cp_dPdR : nullptr,
                      o.dlnjac_dR ? c->cp_dJdR : nullptr, o.O ? c->cp_O : nullptr, o.G ? c->cp_G : nullptr};
         if ((rc = measure_core<double>(c, c->cp_pos, c->cp_pos0, kc, C, R, R0, warp, full, oc, c->al64, nullptr,
-                                       st)))
+                                       false, st)))
             return rc;
         const std::pair<double *, double *> rows[] = {{oc.EL, o.EL},         {oc.lnpsi, o.lnpsi},
                                                       {oc.dEL_dR, o.dEL_dR}, {oc.dlnpsi_dR, o.dlnpsi_dR},
@@ -303,8 +346,9 @@ const char *vmc_last_error(const vmc_ctx *ctx) { return ctx ? ctx->err.c_str() :
 
 void vmc_free(vmc_ctx *ctx) {
     if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    prof_clear(ctx);
     if (!ctx->allocs.empty()) {
-        (void)hipSetDevice(ctx->device);
         for (void *p : ctx->allocs) (void)hipFree(p);
     }
     delete ctx;
@@ -564,17 +608,21 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
             if (t == 0)
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, walkers, W * c->N, c->tiles16,
                                                           Amo, 1, st));
+            const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
             HIP_OK(c, vmcx::launch_sweep<float>(c->sys, c->d_Cf, c->d_R, walkers, (int)W, Amo, sidx, seed,
                                                 c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
                                                 st));
+            prof_end(c, VMC_K_SWEEP, pi, st);
         } else {
             double *Amo = (double *)c->Amo;
             if (t == 0)
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
                                                            Amo, 1, st));
+            const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
             HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, Amo, sidx, seed,
                                                  c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status,
                                                  c->swl, st));
+            prof_end(c, VMC_K_SWEEP, pi, st);
         }
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
         const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
@@ -795,6 +843,35 @@ int zvector_solve(const double *H, int64_t d, const double *b, double *z, double
     if (iters) *iters = it;
     if (status != VMC_OK) return status;
     return conv ? VMC_OK : VMC_ENOTCONV;
+}
+
+int vmc_profile(vmc_ctx *c, int32_t enable) {
+    if (!c) return VMC_EINVAL;
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    prof_clear(c);
+    c->prof = enable != 0;
+    return VMC_OK;
+}
+
+int vmc_profile_read(vmc_ctx *c, int32_t kernel, double *ms, int64_t *launches, int64_t *walkers) {
+    if (!c) return VMC_EINVAL;
+    if (kernel < 0 || kernel > 3) return c->fail(VMC_EINVAL, "vmc_profile_read: unknown kernel %d", kernel);
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    double tot = 0.0;
+    int64_t nw = 0;
+    for (const auto &r : c->prof_recs[kernel]) {
+        float e = 0.f;
+        HIP_OK(c, hipEventSynchronize(r.b));
+        HIP_OK(c, hipEventElapsedTime(&e, r.a, r.b));
+        tot += e;
+        nw += r.walkers;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = (int64_t)c->prof_recs[kernel].size();
+    if (walkers) *walkers = nw;
+    return VMC_OK;
 }
 
 const char *vmc_init_error(void) { return g_init_err.c_str(); }

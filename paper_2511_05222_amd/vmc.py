@@ -27,7 +27,7 @@ VMC_ACCUM_RESET = 1
 
 EXPORTED = ["vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
             "vmc_adjoint", "zvector_solve", "vmc_staging_walkers", "vmc_free", "vmc_last_error", "vmc_init_error",
-            "vmc_strerror"]
+            "vmc_strerror", "vmc_profile", "vmc_profile_read"]
 
 
 class VmcError(RuntimeError):
@@ -86,6 +86,8 @@ def lib():
     L.vmc_energy_cotangents.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.zvector_solve.argtypes = [vp, i64, vp, vp, dbl, i32, ct.POINTER(i32), vp]
+    L.vmc_profile.argtypes = [vp, i32]
+    L.vmc_profile_read.argtypes = [vp, i32, vp, vp, vp]
     L.vmc_staging_walkers.argtypes = [vp]
     L.vmc_staging_walkers.restype = ct.c_int64
     L.vmc_free.argtypes = [vp]
@@ -97,7 +99,7 @@ def lib():
     L.vmc_strerror.argtypes = [ct.c_int]
     L.vmc_strerror.restype = ct.c_char_p
     for name in ("vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
-                 "vmc_adjoint", "zvector_solve"):
+                 "vmc_adjoint", "zvector_solve", "vmc_profile", "vmc_profile_read"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -195,6 +197,18 @@ class Context:
         self._rc(lib().vmc_accumulate(self._h, dpn(E), dpn(F), dpn(dEdC), dpn(dELdC), ct.byref(ns),
                                       VMC_ACCUM_RESET if reset else 0, _stream()))
         return dict(E=E[0], E_sigma=E[1], F_bare=F, dE_dC=dEdC, dEL_dC_mean=dELdC, n_samples=ns.value)
+
+    def profile(self, enable=True):
+        """Start (clearing the totals) or stop HIP-event timing of the kernels."""
+        self._rc(lib().vmc_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, kernel):
+        """(total ms, launches, walkers) of a kernel since profile(True);
+        kernel in ("adjoint", "dense", "mo_rows", "sweep")."""
+        k = {"adjoint": 0, "dense": 1, "mo_rows": 2, "sweep": 3}[kernel]
+        ms, nl, nw = ct.c_double(0), ct.c_int64(0), ct.c_int64(0)
+        self._rc(lib().vmc_profile_read(self._h, k, ct.byref(ms), ct.byref(nl), ct.byref(nw)))
+        return ms.value, nl.value, nw.value
 
     def chunk_walkers(self):
         return int(lib().vmc_staging_walkers(self._h))
