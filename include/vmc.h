@@ -116,10 +116,13 @@ typedef struct {
 
 /* Run options.
  * precision      : VMC_FP64 or VMC_MIXED
- * refresh_period : the Slater inverse is recomputed from scratch after every
- *                  refresh_period-th proposed move (counted per walker over
- *                  the global move index sweep*N + e) and at every sweep start;
- *                  Sherman-Morrison updates in between
+ * refresh_period : the inverse of the spin block being swept is rebuilt from
+ *                  scratch (FP64 Gauss-Jordan, partial pivoting) from the
+ *                  walker's MO matrix at the block's first electron in every
+ *                  sweep, after every refresh_period-th proposed move (global
+ *                  move index sweep*N + e) that is not the block's last, and
+ *                  after an accepted move with |ratio| < 1e-8; Sherman-Morrison
+ *                  updates in between
  * block_sweeps   : sweeps per block of the blocked energy error bar
  * max_walkers    : largest n_walkers any call on this context will pass
  * staging_walkers: walkers measured per launch (per-walker staging buffers);
@@ -172,7 +175,9 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
  * A sweep proposes r'_e = r_e + step_sigma z for e = 0..N-1 in order and
  * accepts iff u < |Psi'/Psi|^2; z and u come from Philox4x32-10 with key
  * `seed` and counter (walker id, sweep index, electron | purpose << 16, 0),
- * sweep index = sweep_offset + t, walker id = row of walkers_dev.
+ * sweep index = sweep_offset + t, walker id = row of walkers_dev.  The MO
+ * matrix of every walker is built from walkers_dev at the start of the call
+ * and kept current by the moves (row e rewritten on each accepted move).
  * flags & VMC_SWEEP_MEASURE: after every sweep measure every walker and add
  *   the samples to the context's accumulators (read by vmc_accumulate).
  * accept_dev   : optional device uint8 [nsteps][N][n_walkers], 1 = accepted.
