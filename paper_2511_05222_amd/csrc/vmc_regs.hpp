@@ -24,15 +24,32 @@ __device__ inline float readlane_t(float v, int src) {
 }
 __device__ inline double readlane_t(double v, int src) { return readlane_d(v, src); }
 
+// Maximum of an unsigned value over the wavefront (uniform result): DPP
+// within each row of 16 lanes (quad swaps, half-row and row mirrors), then the
+// four row results by lane reads.
+__device__ inline unsigned wave_max_u32(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));    // quad [1,0,3,2]
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));    // quad [2,3,0,1]
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));   // half-row mirror
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));   // row mirror
+    const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16),
+                   c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return max(max(a, b), max(c, d));
+}
+
 // In-register Gauss-Jordan inversion (FP64) with partial pivoting by implicit
 // row choice.  The matrix is B = A^T of the spin block, padded to KN x KN with
 // an identity block: on entry lane c holds row c of B in Br[0..KN) (lanes >=
 // KN hold zeros and never pivot).  Step k eliminates column k, which a
 // rotation keeps in Br[0]: after the step every register moves down by one and
 // the new column k enters at Br[KN-1], so after KN steps the registers are
-// back in order.  The pivot of step k is the unused lane with the largest
-// |B[.][k]| (ties: lowest lane).  With p_k the pivot lane of step k the result
-// is R[p_k][j] = B^-1[k][p_j], i.e. lane p_k holds column k of K = A^-1 with
+// back in order.  The pivot of step k is an unused lane with the largest
+// |B[.][k]| compared on a 32-bit key: |B| rounded to FP32 with its six low
+// mantissa bits replaced by (63 - lane), so that values within 2^-17 of each
+// other count as equal and the lowest such lane wins (any such pivot is a
+// partial-pivoting choice; NaN and 0 rank lowest among the unused lanes).
+// The pivot row is broadcast by lane reads.  With p_k the pivot lane of step k the result is
+// R[p_k][j] = B^-1[k][p_j], i.e. lane p_k holds column k of K = A^-1 with
 // register j holding orbital p_j.  On return sig = k on lane p_k (lanes >= KN:
 // sig = lane).  A pivot with |pivot| <= 1e-300 or NaN sets bad.  With LOGDET,
 // logabs = sum_k log|pivot_k| = log|det B| (the identity padding adds 0).
@@ -45,23 +62,17 @@ __device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &lo
     for (int k = 0; k < KN; ++k) {
         const double a0 = Br[0];
         const double fa = fabs(a0);
-        double best = used ? -1.0 : (fa == fa ? fa : -0.5);
-        int bi = lane;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
+        unsigned key = 0u;
+        if (!used) {
+            const unsigned fb = fa == fa ? __float_as_uint((float)fa) : 0u;
+            key = max(fb & ~63u, 64u) | (unsigned)(63 - lane);
         }
-        const int p = __builtin_amdgcn_readfirstlane(bi);
+        const int p = 63 - (int)(wave_max_u32(key) & 63u);
+        const bool me = lane == p;
         const double piv = readlane_d(a0, p);
         if (!(fabs(piv) > 1e-300)) bad = true;
         if (LOGDET) logabs += log(fabs(piv));
         const double inv = 1.0 / piv;
-        const bool me = lane == p;
         if (me) {
             used = true;
             sig = k;
@@ -70,10 +81,7 @@ __device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &lo
         const double g = me ? -inv : a0 * inv;
         const double h = me ? 0.0 : 1.0;
 #pragma unroll
-        for (int r = 0; r + 1 < KN; ++r) {
-            const double pr = readlane_d(Br[r + 1], p);
-            Br[r] = fma(-g, pr, h * Br[r + 1]);
-        }
+        for (int r = 0; r + 1 < KN; ++r) Br[r] = fma(-g, readlane_d(Br[r + 1], p), h * Br[r + 1]);
         Br[KN - 1] = me ? inv : -a0 * inv;
     }
 }
