@@ -180,7 +180,15 @@ static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
     SweepLayout s{};
     const int n = c->n_occ, M = c->M;
     auto al = [](size_t b) { return (int)((b + 15) & ~(size_t)15); };
-    s.ldc = M | 1;   // odd stride: lanes walking their own row hit distinct banks
+    // lane groups of the MO-row product (as in the kernel) and 16-byte vectors
+    const int npad = n <= 16 ? 16 : (n <= 32 ? 32 : 64), G = 64 / npad, vw = (int)(16 / ts);
+    s.mchunk = ((M + G - 1) / G + vw - 1) / vw * vw;
+    s.mpad = G * s.mchunk;
+    // row stride: a whole number of 16-byte vectors plus half a 32-byte bank
+    // group (4 floats or 2 doubles), so that the 16-byte reads of lanes walking
+    // their own rows spread over all banks
+    s.ldc = s.mpad;
+    while ((s.ldc * ts) % 32 != 16) s.ldc += vw;
     size_t o = al((size_t)n * s.ldc * ts);
     s.off_R = (int)o;
     o += al((size_t)3 * c->A * sizeof(double));
@@ -196,7 +204,7 @@ static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
     const int kn = vmcx::sweep_kn(n);
     size_t w = 0;
     s.off_psi = 0;
-    w += al((size_t)M * ts);
+    w += al((size_t)s.mpad * ts);
     s.off_phin = (int)w;
     w += al((size_t)kn * ts);
     s.off_colj = (int)w;

@@ -15,6 +15,7 @@ struct AoTiles {
 // odd row stride ldc, then the basis tables) followed by wpb wavefront regions.
 struct SweepLayout {
     int ldc;                                        // row stride of Ct (elements)
+    int mpad, mchunk;                               // AO range padded for the vector loop, per lane group
     int off_R, off_pexp, off_pcp, off_sha, off_shb;  // basis tables
     int block_bytes;                                // block-shared region
     int off_psi, off_phin, off_colj;                // within a wavefront region

@@ -76,6 +76,23 @@ __device__ inline void shell_values_lds(const SweepBasisLds &B, int s, double rx
     }
 }
 
+// 16-byte vectors of the MO-row product (four FP32 or two FP64 lanes of LDS
+// per load; the element-wise products are plain scalar FMAs).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int W = 4;
+    __device__ static float sum(type v) { return (v.x + v.y) + (v.z + v.w); }
+};
+template <>
+struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int W = 2;
+    __device__ static double sum(type v) { return v.x + v.y; }
+};
+
 template <typename T, int KN>
 __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__ Cg, const double *__restrict__ R,
                                                   double *walkers, int W, T *Amo, uint32_t sweep, uint64_t seed,
@@ -92,6 +109,11 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
     for (int k = threadIdx.x; k < M * n; k += blockDim.x) {
         const int mu = k / n, i = k - (k / n) * n;
         Ct[i * ldc + mu] = Cg[k];
+    }
+    // zero padding of the rows up to mpad (the vector loop reads it)
+    for (int k = threadIdx.x; k < n * (L.mpad - M); k += blockDim.x) {
+        const int i = k / (L.mpad - M), mu = M + k - (k / (L.mpad - M)) * (L.mpad - M);
+        Ct[i * ldc + mu] = T(0);
     }
     for (int k = threadIdx.x; k < 3 * S.A; k += blockDim.x) B.R[k] = R[k];
     for (int k = threadIdx.x; k < NS; k += blockDim.x) {
@@ -110,6 +132,7 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
     T *psi = (T *)(wbase + L.off_psi);
     T *phin = (T *)(wbase + L.off_phin);   // phin[r] = phi_{p_r}
     T *colj = (T *)(wbase + L.off_colj);   // column of the moved electron
+    for (int k = M + lane; k < L.mpad; k += 64) psi[k] = T(0);
     double *wp = walkers + (size_t)w * N * 3;
     T *Aw = Amo + (size_t)w * N * n;
     // positions and this sweep's draws: lane l holds electrons l and l + 64
@@ -130,9 +153,12 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
     const int npad = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
     const int G = 64 / npad;
     const int li = lane & (npad - 1), lg = lane / npad;
-    // lane group lg of the phi product covers AOs [m_lo, m_hi)
-    const int mchunk = (M + G - 1) / G;
-    const int m_lo = min(M, lg * mchunk), m_hi = min(M, m_lo + mchunk);
+    // lane group lg of the phi product covers AOs [lg*mchunk, (lg+1)*mchunk)
+    // of the zero-padded range [0, mpad), in 16-byte vectors
+    typedef typename Vec16<T>::type V;
+    const int nvec = L.mchunk / Vec16<T>::W;
+    const V *cvec = (const V *)(Ct + li * ldc + lg * L.mchunk);
+    const V *svec = (const V *)(psi + lg * L.mchunk);
     bool need = true;
     for (int e = 0; e < N; ++e) {
         const int b = e < nu ? 0 : 1;
@@ -172,23 +198,15 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
         // phi_i(r') = sum_mu psi_mu C[mu][i]; lane group lg sums its AO range
         T ph = T(0);
         if (li < nb) {
-            T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0);
-            const T *cp = Ct + li * ldc + m_lo;
-            const T *sp = psi + m_lo;
-            const int len = m_hi - m_lo;
+            V a0 = V(T(0)), a1 = V(T(0));
             int k = 0;
-            for (; k + 8 <= len; k += 8) {
-                p0 += sp[k] * cp[k];
-                p1 += sp[k + 1] * cp[k + 1];
-                p2 += sp[k + 2] * cp[k + 2];
-                p3 += sp[k + 3] * cp[k + 3];
-                p0 += sp[k + 4] * cp[k + 4];
-                p1 += sp[k + 5] * cp[k + 5];
-                p2 += sp[k + 6] * cp[k + 6];
-                p3 += sp[k + 7] * cp[k + 7];
+            for (; k + 2 <= nvec; k += 2) {
+                a0 += svec[k] * cvec[k];
+                a1 += svec[k + 1] * cvec[k + 1];
             }
-            for (; k < len; ++k) p0 += sp[k] * cp[k];
-            ph = (p0 + p1) + (p2 + p3);
+            if (k < nvec) a0 += svec[k] * cvec[k];
+            a0 += a1;
+            ph = Vec16<T>::sum(a0);
         }
         for (int o = npad; o < 64; o <<= 1) ph += __shfl_xor(ph, o, 64);
         // lane i < KN holds phi_i (zero from nb on): store it at the register
