@@ -201,28 +201,28 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
         Mi[8] = (M3[0] * M3[4] - M3[1] * M3[3]) * id;
     }
     __syncthreads();
-    for (int idx = tid; idx < 3 * A; idx += 128) {
-        const int a = idx / 3, k = idx - (idx / 3) * 3;
-        double sE = 0.0, sP = 0.0, sJ = 0.0;
-        for (int m = 0; m < M; ++m)
-            if (S.basis.shell_atom[S.basis.ao_shell[m]] == a) {
-                sE -= mb.tao[((size_t)w * M + m) * 6 + k];
-                sP -= mb.tao[((size_t)w * M + m) * 6 + 3 + k];
-            }
-        for (int e = 0; e < N; ++e) {
-            const double dx = p[3 * e] - R[3 * a], dy = p[3 * e + 1] - R[3 * a + 1], dz = p[3 * e + 2] - R[3 * a + 2];
+    // per-nucleus sums: thread (a, j) takes electrons and AOs congruent to j
+    // modulo tpa; the tpa partials of a nucleus are added in a fixed order
+    double *part = (double *)(wnear + N + (N & 1));   // [128][9], 8-byte aligned
+    const int tpa = 128 / A;
+    if (tid < tpa * A) {
+        const int a = tid / tpa, j = tid - (tid / tpa) * tpa;
+        double sE[3] = {0, 0, 0}, sP[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
+        for (int m = j; m < M; m += tpa)
+            if (S.basis.shell_atom[S.basis.ao_shell[m]] == a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    sE[k] -= mb.tao[((size_t)w * M + m) * 6 + k];
+                    sP[k] -= mb.tao[((size_t)w * M + m) * 6 + 3 + k];
+                }
+        const double Rx = R[3 * a], Ry = R[3 * a + 1], Rz = R[3 * a + 2], Za = S.Z[a];
+        for (int e = j; e < N; e += tpa) {
+            const double dx = p[3 * e] - Rx, dy = p[3 * e + 1] - Ry, dz = p[3 * e + 2] - Rz;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const double dk = k == 0 ? dx : (k == 1 ? dy : dz);
-            sE -= S.Z[a] * dk / (r2 * sqrt(r2));
-        }
-        for (int c = 0; c < A; ++c) {
-            if (c == a) continue;
-            const double dx = R[3 * a] - R[3 * c], dy = R[3 * a + 1] - R[3 * c + 1], dz = R[3 * a + 2] - R[3 * c + 2];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double dk = k == 0 ? dx : (k == 1 ? dy : dz);
-            sE -= S.Z[a] * S.Z[c] * dk / (r2 * sqrt(r2));
-        }
-        for (int e = 0; e < N; ++e) {
+            const double f = Za / (r2 * sqrt(r2));
+            sE[0] -= f * dx;
+            sE[1] -= f * dy;
+            sE[2] -= f * dz;
             WarpE we;
             we.invS = wS[4 * e];
             we.sg[0] = wS[4 * e + 1];
@@ -231,10 +231,40 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
             we.near = wnear[e];
             double g[3];
             const double om = warp_omega(we, R0, a, p0[3 * e], p0[3 * e + 1], p0[3 * e + 2], g);
-            sE += om * dEdr[3 * e + k];
-            sP += om * (gb[6 * e + 3 + k] + gb[6 * e + k]);
             const double *Mi = Minv + 9 * e;
-            sJ += Mi[k] * g[0] + Mi[3 + k] * g[1] + Mi[6 + k] * g[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                sE[k] += om * dEdr[3 * e + k];
+                sP[k] += om * (gb[6 * e + 3 + k] + gb[6 * e + k]);
+                sJ[k] += Mi[k] * g[0] + Mi[3 + k] * g[1] + Mi[6 + k] * g[2];
+            }
+        }
+        if (j == 0)
+            for (int c = 0; c < A; ++c) {
+                if (c == a) continue;
+                const double dx = Rx - R[3 * c], dy = Ry - R[3 * c + 1], dz = Rz - R[3 * c + 2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double f = Za * S.Z[c] / (r2 * sqrt(r2));
+                sE[0] -= f * dx;
+                sE[1] -= f * dy;
+                sE[2] -= f * dz;
+            }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            part[9 * tid + k] = sE[k];
+            part[9 * tid + 3 + k] = sP[k];
+            part[9 * tid + 6 + k] = sJ[k];
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 3 * A; idx += 128) {
+        const int a = idx / 3, k = idx - (idx / 3) * 3;
+        double sE = 0.0, sP = 0.0, sJ = 0.0;
+        for (int j = 0; j < tpa; ++j) {
+            const double *q = part + 9 * (a * tpa + j);
+            sE += q[k];
+            sP += q[3 + k];
+            sJ += q[6 + k];
         }
         const size_t o = (size_t)w * 3 * A + idx;
         if (out.dEL_dR) out.dEL_dR[o] = sE;
@@ -254,7 +284,8 @@ hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const
 
 hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb,
                            const WalkerOut &out, int warp, int W, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t)S.N * (3 + 3 + 6 + 3 + 9 + 4) + sizeof(int) * (size_t)S.N;
+    const size_t lds = sizeof(double) * (size_t)S.N * (3 + 3 + 6 + 3 + 9 + 4) + sizeof(int) * (size_t)(S.N + S.N % 2) +
+                       sizeof(double) * 128 * 9;
     hipLaunchKernelGGL(k_finalize, dim3(W), dim3(128), lds, st, S, R, R0, mb, out, warp);
     return hipGetLastError();
 }
