@@ -16,10 +16,11 @@ Two ratio modes:
   sm     the ratio phi(r')^T K[:, e] from a Sherman-Morrison-updated inverse
          K = A^-1; after an accepted move
              K <- K - K[:, e] (phi(r')^T K - e_e^T) / ratio.
+         The inverses of both spin blocks persist across sweeps.  A block's
          K is recomputed from scratch at the start of a run, after every
-         `refresh_period`-th proposed move of the run's global move counter
-         (move index = sweep * N + electron), after the last move of every
-         sweep, and after an accepted move whose |ratio| < 1e-8.
+         `refresh_period`-th proposed move of that block (its own move index
+         sweep * n_block + j, j the electron's index within the block), and
+         after an accepted move of that block whose |ratio| < 1e-8.
 """
 import numpy as np
 
@@ -52,16 +53,19 @@ class Chains:
         val, _, _ = gto.eval_aos(self.system.table, self.R, pts)
         return val @ self.system.C[:, :n]
 
-    def refresh(self, mask=None):
-        """Recompute K = A^-1 for both spins from the current positions."""
+    def refresh(self, mask=None, blocks=(0, 1)):
+        """Recompute K = A^-1 of the given spin blocks from the current
+        positions (for the walkers in mask, default all)."""
         s = self.system
         phi = self.orbitals_at(self.r, s.C.shape[1])
-        K = []
+        K = list(self.K) if self.K is not None else [None, None]
         for b, (sl, n) in enumerate(s.spin_blocks()):
+            if b not in blocks and self.K is not None:
+                continue
             Kn = np.linalg.inv(phi[:, sl, :n])
             if mask is not None and self.K is not None:
                 Kn = np.where(mask[:, None, None], Kn, self.K[b])
-            K.append(Kn)
+            K[b] = Kn
         self.K = K
 
     def jastrow_delta(self, e, r_new):
@@ -118,10 +122,10 @@ class Chains:
                 K[acc] -= upd[acc]
                 forced = acc & (np.abs(ratio) < FORCED_REFRESH_RATIO)
                 if np.any(forced):
-                    self.refresh(mask=forced)
-                m = sweep_index * s.N + e
-                if (m + 1) % refresh_period == 0 or e == s.N - 1:
-                    self.refresh()
+                    self.refresh(mask=forced, blocks=(b,))
+                m = sweep_index * n + j
+                if (m + 1) % refresh_period == 0:
+                    self.refresh(blocks=(b,))
         return acc_bits
 
 

@@ -80,6 +80,9 @@ struct vmc_ctx {
     double *mb_phi = nullptr, *mb_ktil = nullptr, *mb_abar = nullptr, *mb_gb = nullptr, *mb_dpart = nullptr,
            *mb_tao = nullptr, *mb_posw = nullptr;
     void *Amo = nullptr;     // [max_walkers][N][n] MO matrix maintained by the sweep (type T)
+    void *Kst = nullptr;     // [max_walkers][2][KN][KN] persistent inverses (type T)
+    uint8_t *Ksig = nullptr; // [max_walkers][2][KN]
+    int *Kstale = nullptr;   // [max_walkers][2]
     float *d_Cf = nullptr;   // C in FP32 (mixed precision)
     float *d_Cm = nullptr;   // FP32 copy of a caller's C (mixed precision)
     // FP64 re-measurement of ill-conditioned walkers (mixed precision)
@@ -565,7 +568,11 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->mb_abar, chunk * Nn)) || (rc = c->dalloc(&c->mb_gb, chunk * 6 * c->N)) ||
         (rc = c->dalloc(&c->mb_dpart, chunk * 3 * (int64_t)c->N)) ||
         (rc = c->dalloc(&c->mb_tao, chunk * 6 * M)) || (rc = c->dalloc(&c->mb_posw, chunk * 3 * c->N)) ||
-        (rc = c->dalloc((double **)&c->Amo, (size_t)opt->max_walkers * Nn)))
+        (rc = c->dalloc((double **)&c->Amo, (size_t)opt->max_walkers * Nn)) ||
+        (rc = c->dalloc((double **)&c->Kst, (size_t)opt->max_walkers * 2 * vmcx::sweep_kn(c->n_occ) *
+                                                vmcx::sweep_kn(c->n_occ))) ||
+        (rc = c->dalloc(&c->Ksig, (size_t)opt->max_walkers * 2 * vmcx::sweep_kn(c->n_occ))) ||
+        (rc = c->dalloc(&c->Kstale, (size_t)opt->max_walkers * 2)))
         return bail(rc);
     if (opt->precision == VMC_MIXED && opt->promote_cond > 0.0) {
         c->pcap = std::max<int64_t>(1, chunk / 8);
@@ -617,9 +624,10 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, walkers, W * c->N, c->tiles16,
                                                           Amo, 1, st));
             const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
-            HIP_OK(c, vmcx::launch_sweep<float>(c->sys, c->d_Cf, c->d_R, walkers, (int)W, Amo, sidx, seed,
-                                                c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status, c->swl,
-                                                st));
+            const vmcx::KState<float> ks{(float *)c->Kst, c->Ksig, c->Kstale};
+            HIP_OK(c, vmcx::launch_sweep<float>(c->sys, c->d_Cf, c->d_R, walkers, (int)W, Amo, ks, t == 0, sidx,
+                                                seed, c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status,
+                                                c->swl, st));
             prof_end(c, VMC_K_SWEEP, pi, st);
         } else {
             double *Amo = (double *)c->Amo;
@@ -627,8 +635,9 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
                                                            Amo, 1, st));
             const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
-            HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, Amo, sidx, seed,
-                                                 c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status,
+            const vmcx::KState<double> ks{(double *)c->Kst, c->Ksig, c->Kstale};
+            HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, Amo, ks, t == 0, sidx,
+                                                 seed, c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status,
                                                  c->swl, st));
             prof_end(c, VMC_K_SWEEP, pi, st);
         }

@@ -76,11 +76,21 @@ struct MeasBufsD {
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
                                const AoTiles &tiles16, T *out, int nc, hipStream_t st);
+// Persistent inverses of the two spin blocks of every walker, in the
+// register layout of the sweep: K[w][b][r][lane] (KN x KN, type T), the
+// permutation sig[w][b][lane] and stale[w][b] = a rebuild is due.
+template <typename T>
+struct KState {
+    T *K;
+    uint8_t *sig;
+    int *stale;
+};
+
 int sweep_kn(int n_occ);
 template <typename T>
-hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo, uint32_t sweep,
-                        uint64_t seed, double sigma, int refresh_period, uint8_t *accept, int *status,
-                        const SweepLayout &L, hipStream_t st);
+hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
+                        const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, double sigma,
+                        int refresh_period, uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st);
 hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const double *pos0, double *posw,
                        double *lnjac, int W, hipStream_t st);
 template <typename T>

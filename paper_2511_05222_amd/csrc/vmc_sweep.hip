@@ -12,11 +12,14 @@
 //     lane p_k holding column k (electron k of the block), register r holding
 //     orbital p_r, where p is the pivot order of the last rebuild (gj_regs).
 // The MO matrix A[e][i] = phi_i(r_e) of every walker lives in HBM (type T);
-// row e is rewritten on each accepted move of e.  K is rebuilt from A in FP64
-// at the block's first electron (no electron of the block has moved yet in
-// this sweep, so this equals an inverse built at the start of the sweep),
-// after every refresh_period-th proposed move that is not the block's last,
-// and after an accepted move with |ratio| < 1e-8.
+// row e is rewritten on each accepted move of e.  Both blocks' inverses
+// persist across sweeps: at the end of a block the registers go to HBM (Kst,
+// with the layout permutation and a flag for a rebuild still due), and at the
+// block's next start they come back.  A block's inverse is rebuilt from A in
+// FP64 at the first sweep of a call (fresh), after every refresh_period-th
+// proposed move of that block (its own move index sweep * nb + j), and after
+// an accepted move with |ratio| < 1e-8; a rebuild that falls due after the
+// block's last move is carried to its next start by the flag.
 #include "vmc_pipeline.hpp"
 #include "vmc_regs.hpp"
 
@@ -95,9 +98,9 @@ struct Vec16<double> {
 
 template <typename T, int KN>
 __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__ Cg, const double *__restrict__ R,
-                                                  double *walkers, int W, T *Amo, uint32_t sweep, uint64_t seed,
-                                                  double sigma, int refresh_period, uint8_t *accept, int *status,
-                                                  SweepLayout L) {
+                                                  double *walkers, int W, T *Amo, KState<T> ks, int fresh,
+                                                  uint32_t sweep, uint64_t seed, double sigma, int refresh_period,
+                                                  uint8_t *accept, int *status, SweepLayout L) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int N = S.N, nu = S.n_up, n = S.n_occ, M = S.M, NS = S.basis.n_shells;
@@ -165,7 +168,16 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
         const int off = b ? nu : 0;
         const int jj = e - off;
         const int nb = b ? S.n_dn : nu;
-        if (jj == 0) need = true;
+        T *kst = ks.K + ((size_t)w * 2 + b) * KN * KN;
+        if (jj == 0) {
+            // the block's inverse: rebuilt, or as left at its last move
+            need = fresh || ks.stale[2 * w + b] != 0;
+            if (!need) {
+#pragma unroll
+                for (int r = 0; r < KN; ++r) Kr[r] = lane < KN ? kst[r * KN + lane] : T(0);
+                sig = lane < KN ? (int)ks.sig[((size_t)w * 2 + b) * KN + lane] : lane;
+            }
+        }
         if (need) {
             rebuild<T, KN>(Aw, n, off, nb, Kr, sig, bad);
             need = false;
@@ -250,10 +262,18 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
             if (fabs(ratio) < FORCED_REFRESH_RATIO) need = true;
         }
         if (accept != nullptr && lane == 0) accept[(size_t)e * W + w] = acc ? 1 : 0;
-        const uint64_t m = (uint64_t)sweep * (uint64_t)N + (uint64_t)e;
-        // the next move of this spin block needs a fresh inverse; a block that
-        // has no further move in this sweep is rebuilt at the next sweep anyway
-        if (((m + 1) % (uint64_t)refresh_period) == 0 && jj < nb - 1) need = true;
+        // refresh_period-th move of this block: rebuild before its next move
+        const uint64_t m = (uint64_t)sweep * (uint64_t)nb + (uint64_t)jj;
+        if (((m + 1) % (uint64_t)refresh_period) == 0) need = true;
+        if (jj == nb - 1) {
+            // end of the block: keep its inverse (and a rebuild still due)
+#pragma unroll
+            for (int r = 0; r < KN; ++r)
+                if (lane < KN) kst[r * KN + lane] = Kr[r];
+            if (lane < KN) ks.sig[((size_t)w * 2 + b) * KN + lane] = (uint8_t)sig;
+            if (lane == 0) ks.stale[2 * w + b] = need ? 1 : 0;
+            need = false;
+        }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -269,32 +289,32 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
 
 template <typename T, int KN>
 static hipError_t launch_kn(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
-                            uint32_t sweep, uint64_t seed, double sigma, int refresh_period, uint8_t *accept,
-                            int *status, const SweepLayout &L, hipStream_t st) {
+                            const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, double sigma,
+                            int refresh_period, uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_r<T, KN>), dim3((unsigned)((W + L.wpb - 1) / L.wpb)), dim3(64 * L.wpb), L.bytes, st,
-                       S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L);
+                       S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept, status, L);
     return hipGetLastError();
 }
 
 int sweep_kn(int n_occ) { return n_occ <= 16 ? 16 : (n_occ <= 32 ? 32 : (n_occ <= 48 ? 48 : 64)); }
 
 template <typename T>
-hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo, uint32_t sweep,
-                        uint64_t seed, double sigma, int refresh_period, uint8_t *accept, int *status,
-                        const SweepLayout &L, hipStream_t st) {
+hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
+                        const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, double sigma,
+                        int refresh_period, uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
     switch (sweep_kn(S.n_occ)) {
         case 16:
-            return launch_kn<T, 16>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
-                                    st);
+            return launch_kn<T, 16>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+                                    status, L, st);
         case 32:
-            return launch_kn<T, 32>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
-                                    st);
+            return launch_kn<T, 32>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+                                    status, L, st);
         case 48:
-            return launch_kn<T, 48>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
-                                    st);
+            return launch_kn<T, 48>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+                                    status, L, st);
         default:
-            return launch_kn<T, 64>(S, C, R, walkers, W, Amo, sweep, seed, sigma, refresh_period, accept, status, L,
-                                    st);
+            return launch_kn<T, 64>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+                                    status, L, st);
     }
 }
 
@@ -310,11 +330,11 @@ hipError_t configure_sweep(size_t lds) {
 }
 
 template hipError_t launch_sweep<double>(const SysDev &, const double *, const double *, double *, int, double *,
-                                         uint32_t, uint64_t, double, int, uint8_t *, int *, const SweepLayout &,
-                                         hipStream_t);
+                                         const KState<double> &, int, uint32_t, uint64_t, double, int, uint8_t *,
+                                         int *, const SweepLayout &, hipStream_t);
 template hipError_t launch_sweep<float>(const SysDev &, const float *, const double *, double *, int, float *,
-                                        uint32_t, uint64_t, double, int, uint8_t *, int *, const SweepLayout &,
-                                        hipStream_t);
+                                        const KState<float> &, int, uint32_t, uint64_t, double, int, uint8_t *,
+                                        int *, const SweepLayout &, hipStream_t);
 template hipError_t configure_sweep<double>(size_t);
 template hipError_t configure_sweep<float>(size_t);
 
