@@ -251,19 +251,27 @@ static void layouts(vmc_ctx *c) {
     d.off_x = d.off_k + al((size_t)2 * kn * d.ldk * 8);
     d.off_perm = d.off_x + al((size_t)kn * d.ldk * 8);
     d.off_red = d.off_perm + al(128 * 4);
-    d.bytes = (size_t)d.off_red + 8 * 8;
+    d.bytes = (size_t)d.off_red + 16 * 8;
 }
 
 // The measurement kernels on cw walkers at (possibly warped) positions pos
 // with sampling positions pos0.  plist: promotion list for the dense kernel.
+// Chunk offsets into the sweep's persistent inverses (null: none).
+struct KStateRef {
+    const void *K = nullptr;
+    const uint8_t *sig = nullptr;
+    const int *stale = nullptr;
+};
+
 template <typename T>
 static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64_t cw, const T *C, const double *R,
                         const double *R0, int warp, int full, const WalkerOut &o, const AdjLayout &al, int *plist,
-                        bool prof, hipStream_t st) {
+                        bool prof, const KStateRef &ks, hipStream_t st) {
     const SysDev &S = c->sys;
     T *phi = (T *)c->mb_phi;
     MeasBufs<T> mb{pos,         pos0,       phi,       full ? (T *)c->mb_ktil : nullptr, (T *)c->mb_abar, c->mb_gb,
-                   c->mb_dpart, c->mb_tao, plist,     c->pcount,                        c->opt.promote_cond};
+                   c->mb_dpart, c->mb_tao, plist,     c->pcount,                        c->opt.promote_cond,
+                   (const T *)ks.K, ks.sig, ks.stale};
     int pi = prof_begin(c, VMC_K_MO_ROWS, prof, cw, st);
     HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, st));
     prof_end(c, VMC_K_MO_ROWS, pi, st);
@@ -285,7 +293,8 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
 // walkers the dense kernel flags as ill-conditioned are measured again in
 // FP64 (gathered, measured, scattered over their mixed results).
 static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double *C, const double *R,
-                       const double *R0, int warp, int full, const WalkerOut &o, hipStream_t st) {
+                       const double *R0, int warp, int full, const WalkerOut &o, hipStream_t st,
+                       const KStateRef &ks = KStateRef()) {
     const SysDev &S = c->sys;
     const double *pos = pos0;
     if (warp) {
@@ -295,7 +304,7 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
         HIP_OK(c, hipMemsetAsync(o.lnjac, 0, cw * sizeof(double), st));
     }
     if (c->opt.precision != VMC_MIXED)
-        return measure_core<double>(c, pos, pos0, cw, C, R, R0, warp, full, o, c->al, nullptr, true, st);
+        return measure_core<double>(c, pos, pos0, cw, C, R, R0, warp, full, o, c->al, nullptr, true, ks, st);
     const float *Cf = c->d_Cf;
     if (C != c->d_C) {
         HIP_OK(c, vmcx::launch_round_f32(C, c->d_Cm, (int64_t)c->M * c->n_occ, st));
@@ -304,7 +313,7 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     const bool promote = c->opt.promote_cond > 0.0;
     if (promote) HIP_OK(c, hipMemsetAsync(c->pcount, 0, sizeof(int), st));
     int rc = measure_core<float>(c, pos, pos0, cw, Cf, R, R0, warp, full, o, c->al, promote ? c->plist : nullptr,
-                                 true, st);
+                                 true, ks, st);
     if (rc || !promote) return rc;
     int cnt = 0;
     HIP_OK(c, hipMemcpyAsync(&cnt, c->pcount, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -319,7 +328,7 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
                      o.dEL_dR ? c->cp_dEdR : nullptr, o.dlnpsi_dR ? c->cp_dPdR : nullptr,
                      o.dlnjac_dR ? c->cp_dJdR : nullptr, o.O ? c->cp_O : nullptr, o.G ? c->cp_G : nullptr};
         if ((rc = measure_core<double>(c, c->cp_pos, c->cp_pos0, kc, C, R, R0, warp, full, oc, c->al64, nullptr,
-                                       false, st)))
+                                       false, KStateRef(), st)))
             return rc;
         const std::pair<double *, double *> rows[] = {{oc.EL, o.EL},         {oc.lnpsi, o.lnpsi},
                                                       {oc.dEL_dR, o.dEL_dR}, {oc.dlnpsi_dR, o.dlnpsi_dR},
@@ -646,8 +655,17 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
         double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;
         for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
             const int64_t cw = std::min(c->chunk, W - c0);
-            WalkerOut o{c->st_EL, c->st_lnpsi, nullptr, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
-            if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, c->d_C, c->d_R, c->d_R, 0, 1, o, st))) return rc;
+            // ln|Psi| is not an estimator input: the dense kernel may start
+            // from the sweep's inverses
+            WalkerOut o{c->st_EL, nullptr, nullptr, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
+            const int kn = vmcx::sweep_kn(c->n_occ);
+            const size_t tsz = c->opt.precision == VMC_MIXED ? sizeof(float) : sizeof(double);
+            KStateRef ks;
+            ks.K = (const char *)c->Kst + (size_t)c0 * 2 * kn * kn * tsz;
+            ks.sig = c->Ksig + (size_t)c0 * 2 * kn;
+            ks.stale = c->Kstale + 2 * c0;
+            if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, c->d_C, c->d_R, c->d_R, 0, 1, o, st, ks)))
+                return rc;
             HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
             EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
                       nullptr,  nullptr,    nullptr,    A3,         Mn};

@@ -2,7 +2,9 @@
 //
 // One block of four wavefronts per walker.
 //   phase A  waves 0 and 1: the inverse K of the up and down Slater blocks by
-//            in-register Gauss-Jordan (FP64, partial pivoting), log|det|;
+//            in-register Gauss-Jordan (FP64, partial pivoting), log|det|; or,
+//            after a sweep, the sweep's inverse of the block followed by one
+//            FP64 Newton step K + K (I - A K) on MFMA (then without log|det|);
 //            waves 2 and 3 at the same time: Jastrow gradient g_e, Laplacian
 //            and value, e-e and e-n potentials per electron.
 //   phase B  per spin block, one wavefront per electron row: the determinant
@@ -70,8 +72,17 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
 #pragma unroll
         for (int r = 0; r < KN; ++r) amax = fmax(amax, (lz < nb && r < nb) ? fabs(Br[r]) : 0.0);
         int sig;
-        double la;
-        gj_regs<KN, true>(Br, sig, bad, la);
+        double la = 0.0;
+        const bool from_state = mb.kst != nullptr && mb.kstale[2 * w + b] == 0;
+        if (from_state) {
+            // the sweep's inverse, in its register layout
+            const T *kk = mb.kst + ((size_t)w * 2 + b) * KN * KN;
+#pragma unroll
+            for (int r = 0; r < KN; ++r) Br[r] = lane < KN ? (double)kk[r * KN + lane] : 0.0;
+            sig = lane < KN ? (int)mb.ksig[((size_t)w * 2 + b) * KN + lane] : lane;
+        } else {
+            gj_regs<KN, true>(Br, sig, bad, la);
+        }
         double kmax = 0.0;
 #pragma unroll
         for (int r = 0; r < KN; ++r) kmax = fmax(kmax, (sig < nb && r < nb) ? fabs(Br[r]) : 0.0);
@@ -83,6 +94,7 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         if (lane == 0) {
             red[4 + b] = la;
             red[6 + b] = amax * kmax;
+            red[8 + b] = from_state ? 1.0 : 0.0;
         }
         // natural layout: lane p_k holds column k with register j = orbital p_j
         if (lane < KN) perm[64 * b + sig] = lane;
@@ -121,6 +133,70 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         }
     }
     __syncthreads();
+    const int ml = lane & 15, kg = lane >> 4;
+    // a block started from the sweep's inverse: one FP64 Newton step
+    // K <- K + K (I - A K) on the matrix cores (quadratic in the drift)
+    for (int b = 0; b < 2; ++b) {
+        if (red[8 + b] == 0.0) continue;
+        const int nb = b ? nd : nu, off = b ? nu : 0;
+        double *K = Ks + (size_t)b * KN * ldk;
+        for (int idx = tid; idx < KN * KN; idx += 256) {
+            const int e = idx / KN, i = idx - (idx / KN) * KN;
+            Xs[e * ldk + i] = (e < nb && i < nb) ? (double)ph[(size_t)(off + e) * 5 * n + i] : (e == i ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        MF::acc_t tacc[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int t = wave + 4 * q;
+            tacc[q] = MF::zero();
+            if (t < RTS * RTS) {
+                const int rt = t / RTS, ct = t - (t / RTS) * RTS;
+                const double *xa = Xs + (16 * rt + ml) * ldk + kg;
+                const double *kb = K + kg * ldk + 16 * ct + ml;
+#pragma unroll
+                for (int ks = 0; ks < KN / 4; ++ks) tacc[q] = MF::fma(xa[4 * ks], kb[4 * ks * ldk], tacc[q]);
+            }
+        }
+        __syncthreads();   // A is read: R = I - A K replaces it
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int t = wave + 4 * q;
+            if (t < RTS * RTS) {
+                const int rt = t / RTS, ct = t - (t / RTS) * RTS;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * rt + MF::row(lane, v), c = 16 * ct + ml;
+                    Xs[r * ldk + c] = (r == c ? 1.0 : 0.0) - tacc[q][v];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int t = wave + 4 * q;
+            tacc[q] = MF::zero();
+            if (t < RTS * RTS) {
+                const int rt = t / RTS, ct = t - (t / RTS) * RTS;
+                const double *ka = K + (16 * rt + ml) * ldk + kg;
+                const double *rb = Xs + kg * ldk + 16 * ct + ml;
+#pragma unroll
+                for (int ks = 0; ks < KN / 4; ++ks) tacc[q] = MF::fma(ka[4 * ks], rb[4 * ks * ldk], tacc[q]);
+            }
+        }
+        __syncthreads();   // K is read: add the correction
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int t = wave + 4 * q;
+            if (t < RTS * RTS) {
+                const int rt = t / RTS, ct = t - (t / RTS) * RTS;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) K[(16 * rt + MF::row(lane, v)) * ldk + 16 * ct + ml] += tacc[q][v];
+            }
+        }
+        __syncthreads();
+    }
+    const bool have_ld = red[8] == 0.0 && red[9] == 0.0;   // ln|det| known
     const double logdet = red[4] + red[5];
     const bool full = mb.ktil != nullptr;
     double *gb = mb.gb + (size_t)w * N * 6;
@@ -170,7 +246,6 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         if (!full) continue;
         __syncthreads();
         // T = X K  (rows e', columns e)
-        const int ml = lane & 15, kg = lane >> 4;
         MF::acc_t tacc[TPW];
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
@@ -221,14 +296,14 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         }
         __syncthreads();   // the next block rewrites X
     }
+    // nuclear repulsion: the A^2 ordered pairs spread over the block
     double vnn = 0.0;
-    if (tid == 0)
-        for (int a = 0; a < A; ++a)
-            for (int c = a + 1; c < A; ++c) {
-                const double dx = R[3 * a] - R[3 * c], dy = R[3 * a + 1] - R[3 * c + 1],
-                             dz = R[3 * a + 2] - R[3 * c + 2];
-                vnn += S.Z[a] * S.Z[c] / sqrt(dx * dx + dy * dy + dz * dz);
-            }
+    for (int q = tid; q < A * A; q += 256) {
+        const int a = q / A, c = q - (q / A) * A;
+        if (c <= a) continue;
+        const double dx = R[3 * a] - R[3 * c], dy = R[3 * a + 1] - R[3 * c + 1], dz = R[3 * a + 2] - R[3 * c + 2];
+        vnn += S.Z[a] * S.Z[c] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
     const double EL = block_sum4(el_part + vnn, red);
     const double J = block_sum4(j_part, red);
     const int anybad = __syncthreads_or(bad ? 1 : 0);
@@ -236,9 +311,9 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         if (mb.promote_list && fmax(red[6], red[7]) > mb.promote_cond)
             mb.promote_list[atomicAdd(mb.promote_count, 1)] = w;
         if (out.EL) out.EL[w] = EL;
-        if (out.lnpsi) out.lnpsi[w] = logdet + J;
+        if (out.lnpsi) out.lnpsi[w] = have_ld ? logdet + J : __builtin_nan("");
         if (anybad) atomicOr(status, STATUS_SINGULAR);
-        if (!isfinite(EL) || !isfinite(logdet + J)) atomicOr(status, STATUS_NONFINITE);
+        if (!isfinite(EL) || !isfinite(J) || (have_ld && !isfinite(logdet))) atomicOr(status, STATUS_NONFINITE);
     }
 }
 

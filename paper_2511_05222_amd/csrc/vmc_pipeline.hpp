@@ -66,6 +66,12 @@ struct MeasBufs {
     int *promote_list;
     int *promote_count;
     double promote_cond;
+    // the sweep's persistent inverses of these walkers (KState layout); when
+    // set, a block whose inverse is not stale starts from it and one FP64
+    // Newton step instead of a Gauss-Jordan inversion (no ln|det| then)
+    const T *kst;
+    const uint8_t *ksig;
+    const int *kstale;
 };
 
 struct MeasBufsD {
