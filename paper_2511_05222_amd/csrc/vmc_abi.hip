@@ -251,7 +251,8 @@ static void layouts(vmc_ctx *c) {
     d.off_x = d.off_k + al((size_t)2 * kn * d.ldk * 8);
     d.off_perm = d.off_x + al((size_t)kn * d.ldk * 8);
     d.off_red = d.off_perm + al(128 * 4);
-    d.bytes = (size_t)d.off_red + 16 * 8;
+    d.off_jas = d.off_red + al(16 * 8);
+    d.bytes = (size_t)d.off_jas + (size_t)2 * N * 6 * 8;
 }
 
 // The measurement kernels on cw walkers at (possibly warped) positions pos

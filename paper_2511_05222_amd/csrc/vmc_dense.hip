@@ -5,8 +5,9 @@
 //            in-register Gauss-Jordan (FP64, partial pivoting), log|det|; or,
 //            after a sweep, the sweep's inverse of the block followed by one
 //            FP64 Newton step K + K (I - A K) on MFMA (then without log|det|);
-//            waves 2 and 3 at the same time: Jastrow gradient g_e, Laplacian
-//            and value, e-e and e-n potentials per electron.
+//            every wave: Jastrow gradient g_e, Laplacian and value, e-e and
+//            e-n potentials, as (electron, half of the other electrons)
+//            items combined in a fixed order.
 //   phase B  per spin block, one wavefront per electron row: the determinant
 //            gradient b_e = sum_i K[i][e] grad phi_i(r_e), lap D/D likewise,
 //            and (with the adjoint) X[e][i] = lap phi_i + 2 g_e . grad phi_i;
@@ -23,6 +24,30 @@
 
 namespace vmcx {
 
+// 1/sqrt(x) and 1/x (x > 0) in FP64: the hardware estimate refined by two
+// Newton-Raphson steps, y <- y (3 - x y^2) / 2 and y <- y (2 - x y).
+__device__ inline double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y * (1.5 - 0.5 * x * y * y);
+}
+
+__device__ inline double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * (2.0 - x * y);
+    return y * (2.0 - x * y);
+}
+
+__device__ inline double block_max4(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 __device__ inline double block_sum4(double v, double *red) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -34,7 +59,7 @@ __device__ inline double block_sum4(double v, double *red) {
 }
 
 template <typename T, int KN>
-__global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restrict__ R, MeasBufs<T> mb, WalkerOut out,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dense(SysDev S, const double *__restrict__ R, MeasBufs<T> mb, WalkerOut out,
                                                int *status, DenseLayout L) {
     typedef Mfma<double> MF;
     constexpr int RTS = KN / 16;                    // 16-row tiles of a spin block
@@ -60,27 +85,32 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         // B = A^T of the block: lane c holds orbital c at the block's electrons
         int lz = lane;
         asm volatile("" : "+v"(lz));
-        double Br[KN];
-#pragma unroll
-        for (int r = 0; r < KN; ++r) {
-            double v = (lz == r && r >= nb) ? 1.0 : 0.0;   // identity padding
-            if (lz < nb && r < nb) v = (double)ph[(size_t)(off + r) * 5 * n + lz];
-            Br[r] = v;
-        }
-        // condition indicator of the block: max |A| before, max |K| after
-        double amax = 0.0;
-#pragma unroll
-        for (int r = 0; r < KN; ++r) amax = fmax(amax, (lz < nb && r < nb) ? fabs(Br[r]) : 0.0);
         int sig;
-        double la = 0.0;
+        double la = 0.0, amax = 0.0;
+        double Br[KN];
         const bool from_state = mb.kst != nullptr && mb.kstale[2 * w + b] == 0;
         if (from_state) {
             // the sweep's inverse, in its register layout
-            const T *kk = mb.kst + ((size_t)w * 2 + b) * KN * KN;
+            const T *kk = mb.kst + ((size_t)w * 2 + b) * KN * KN + min(lane, KN - 1);
 #pragma unroll
-            for (int r = 0; r < KN; ++r) Br[r] = lane < KN ? (double)kk[r * KN + lane] : 0.0;
-            sig = lane < KN ? (int)mb.ksig[((size_t)w * 2 + b) * KN + lane] : lane;
+            for (int r = 0; r < KN; ++r) {
+                const double v = (double)kk[r * KN];
+                Br[r] = lane < KN ? v : 0.0;
+            }
+            const int sg = (int)mb.ksig[((size_t)w * 2 + b) * KN + min(lane, KN - 1)];
+            sig = lane < KN ? sg : lane;
         } else {
+            // (clamped, unconditional loads: a guarded load per register would
+            // be issued and waited for one at a time)
+            const T *pa = ph + (size_t)off * 5 * n + min(lz, nb - 1);
+            T av[KN];
+#pragma unroll
+            for (int r = 0; r < KN; ++r) av[r] = pa[(size_t)min(r, nb - 1) * 5 * n];
+#pragma unroll
+            for (int r = 0; r < KN; ++r) {
+                Br[r] = (lz < nb && r < nb) ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // identity padding
+                amax = fmax(amax, (lz < nb && r < nb) ? fabs(Br[r]) : 0.0);
+            }
             gj_regs<KN, true>(Br, sig, bad, la);
         }
         double kmax = 0.0;
@@ -93,7 +123,7 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         }
         if (lane == 0) {
             red[4 + b] = la;
-            red[6 + b] = amax * kmax;
+            red[6 + b] = from_state ? kmax : amax * kmax;   // the state path adds max|A| later
             red[8 + b] = from_state ? 1.0 : 0.0;
         }
         // natural layout: lane p_k holds column k with register j = orbital p_j
@@ -103,34 +133,53 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         if (lane < KN)
 #pragma unroll
             for (int j = 0; j < KN; ++j) K[perm[64 * b + j] * ldk + sig] = Br[j];
-    } else {
-        for (int e = tid - 128; e < N; e += 128) {
-            const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
-            double gx = 0.0, gy = 0.0, gz = 0.0, hh = 0.0, vee = 0.0, jj = 0.0;
-            for (int k = 0; k < N; ++k) {
-                if (k == e) continue;
-                const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                const PadeD pd = pade_all(r, S.ee_a, S.ee_F);
-                const double f = pd.u1 / r;
-                gx += f * dx;
-                gy += f * dy;
-                gz += f * dz;
-                hh += pd.u2 + 2.0 * f;
-                vee += 1.0 / r;
-                jj += pd.u;
-            }
-            double ven = 0.0;
+    }
+    // Jastrow and potential: item t = (electron t / 2, half t % 2 of the other
+    // electrons); waves 2 and 3 take the first 128 items, waves 0 and 1 (after
+    // the inverses) the rest
+    double *jp = (double *)(smem + L.off_jas);   // [2N][6]
+    for (int t = (tid + 128) & 255; t < 2 * N; t += 256) {
+        const int e = t >> 1, hf = t & 1, kh = (N + 1) >> 1;
+        const int k0 = hf * kh, k1 = min(N, k0 + kh);
+        const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
+        double gx = 0.0, gy = 0.0, gz = 0.0, hh = 0.0, vee = 0.0, jj = 0.0;
+        for (int k = k0; k < k1; ++k) {
+            if (k == e) continue;
+            const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            const double ir = rsqrt_nr(d2), r = d2 * ir;
+            const double q = rcp_nr(1.0 + S.ee_F * r);
+            const double u1 = S.ee_a * q * q, u2 = -2.0 * S.ee_F * u1 * q;
+            const double f = u1 * ir;
+            gx += f * dx;
+            gy += f * dy;
+            gz += f * dz;
+            hh += u2 + 2.0 * f;
+            vee += ir;
+            jj += S.ee_a * r * q;
+        }
+        if (hf == 0)
             for (int a = 0; a < A; ++a) {
                 const double dx = x - R[3 * a], dy = y - R[3 * a + 1], dz = z - R[3 * a + 2];
-                ven -= S.Z[a] / sqrt(dx * dx + dy * dy + dz * dz);
+                vee -= 2.0 * S.Z[a] * rsqrt_nr(dx * dx + dy * dy + dz * dz);
             }
-            g[3 * e] = gx;
-            g[3 * e + 1] = gy;
-            g[3 * e + 2] = gz;
-            el_part += -0.5 * (hh + gx * gx + gy * gy + gz * gz) + ven + 0.5 * vee;
-            j_part += 0.5 * jj;
-        }
+        double *o = jp + 6 * t;
+        o[0] = gx;
+        o[1] = gy;
+        o[2] = gz;
+        o[3] = hh;
+        o[4] = vee;   // 2 (electron-electron + electron-nucleus) potential of e
+        o[5] = jj;
+    }
+    __syncthreads();
+    for (int e = tid; e < N; e += 256) {
+        const double *a0 = jp + 12 * e, *a1 = a0 + 6;
+        const double gx = a0[0] + a1[0], gy = a0[1] + a1[1], gz = a0[2] + a1[2];
+        g[3 * e] = gx;
+        g[3 * e + 1] = gy;
+        g[3 * e + 2] = gz;
+        el_part += -0.5 * ((a0[3] + a1[3]) + gx * gx + gy * gy + gz * gz) + 0.5 * (a0[4] + a1[4]);
+        j_part += 0.5 * (a0[5] + a1[5]);
     }
     __syncthreads();
     const int ml = lane & 15, kg = lane >> 4;
@@ -140,10 +189,17 @@ __global__ __launch_bounds__(256) void k_dense(SysDev S, const double *__restric
         if (red[8 + b] == 0.0) continue;
         const int nb = b ? nd : nu, off = b ? nu : 0;
         double *K = Ks + (size_t)b * KN * ldk;
+        double am = 0.0;
         for (int idx = tid; idx < KN * KN; idx += 256) {
             const int e = idx / KN, i = idx - (idx / KN) * KN;
-            Xs[e * ldk + i] = (e < nb && i < nb) ? (double)ph[(size_t)(off + e) * 5 * n + i] : (e == i ? 1.0 : 0.0);
+            const double v = (double)ph[(size_t)(off + min(e, nb - 1)) * 5 * n + min(i, nb - 1)];
+            const bool in = e < nb && i < nb;
+            Xs[e * ldk + i] = in ? v : (e == i ? 1.0 : 0.0);
+            am = fmax(am, in ? fabs(v) : 0.0);
         }
+        // red[6 + b] held max|K| alone: complete the condition indicator
+        am = block_max4(am, red + 12);
+        if (tid == 0) red[6 + b] *= am;
         __syncthreads();
         MF::acc_t tacc[TPW];
 #pragma unroll

@@ -36,7 +36,7 @@ struct SweepBasisLds {
 // LDS layout of k_dense (bytes).
 struct DenseLayout {
     int ldk;                 // row stride (doubles, odd) of K, X and T
-    int off_p, off_g, off_k, off_x, off_perm, off_red;
+    int off_p, off_g, off_k, off_x, off_perm, off_red, off_jas;
     size_t bytes;
 };
 

@@ -36,13 +36,15 @@ __device__ inline void rebuild(const T *Aw, int n, int off, int nb, T (&Kr)[KN],
     // hoisted out of the sweep loop (they would stay live in registers)
     int lz = lane;
     asm volatile("" : "+v"(lz));
+    // (clamped, unconditional loads: a guarded load per register would be
+    // issued and waited for one at a time)
+    const T *pa = Aw + (size_t)off * n + min(lz, nb - 1);
+    T av[KN];
+#pragma unroll
+    for (int r = 0; r < KN; ++r) av[r] = pa[(size_t)min(r, nb - 1) * n];
     double Br[KN];
 #pragma unroll
-    for (int r = 0; r < KN; ++r) {
-        double v = (lz == r && r >= nb) ? 1.0 : 0.0;   // identity padding
-        if (lz < nb && r < nb) v = (double)Aw[(size_t)(off + r) * n + lz];
-        Br[r] = v;
-    }
+    for (int r = 0; r < KN; ++r) Br[r] = (lz < nb && r < nb) ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // padding
     double la;
     gj_regs<KN, false>(Br, sig, bad, la);
 #pragma unroll
@@ -173,9 +175,14 @@ __global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__
             // the block's inverse: rebuilt, or as left at its last move
             need = fresh || ks.stale[2 * w + b] != 0;
             if (!need) {
+                const T *kk = kst + min(lane, KN - 1);
 #pragma unroll
-                for (int r = 0; r < KN; ++r) Kr[r] = lane < KN ? kst[r * KN + lane] : T(0);
-                sig = lane < KN ? (int)ks.sig[((size_t)w * 2 + b) * KN + lane] : lane;
+                for (int r = 0; r < KN; ++r) {
+                    const T v = kk[r * KN];
+                    Kr[r] = lane < KN ? v : T(0);
+                }
+                const int sg = (int)ks.sig[((size_t)w * 2 + b) * KN + min(lane, KN - 1)];
+                sig = lane < KN ? sg : lane;
             }
         }
         if (need) {
