@@ -233,7 +233,10 @@ static AdjLayout adjoint_layout(const vmc_ctx *c, size_t ts) {
     a.off_p = 2 * kb;
     a.off_g = a.off_p + al((size_t)3 * N * 8);
     a.off_d = a.off_g + al((size_t)3 * N * 8);
-    a.waves = 8;
+    // FP32 needs about 140 registers (three wavefronts per SIMD): blocks of
+    // four wavefronts let three walkers share a CU; FP64 (about 250) runs two
+    // per SIMD, one block of eight
+    a.waves = ts == sizeof(float) ? 4 : 8;
     while (a.waves > 1 && (size_t)a.off_d + (size_t)a.waves * 3 * N * 8 > 160 * 1024) a.waves /= 2;
     a.bytes = (size_t)a.off_d + (size_t)a.waves * 3 * N * 8;
     return a;
