@@ -178,8 +178,9 @@ static void prof_end(vmc_ctx *c, int k, int idx, hipStream_t st) {
     if (idx >= 0 && hipEventRecord(c->prof_recs[k][idx].b, st) != hipSuccess) (void)hipGetLastError();
 }
 
-// LDS layout of the sweep for an arithmetic type of ts bytes.
-static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
+// LDS layout of the sweep for an arithmetic type of ts bytes and blocks of
+// wpb walkers.
+static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts, int wpb) {
     SweepLayout s{};
     const int n = c->n_occ, M = c->M;
     auto al = [](size_t b) { return (int)((b + 15) & ~(size_t)15); };
@@ -213,11 +214,30 @@ static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
     s.off_colj = (int)w;
     w += al((size_t)kn * ts);
     s.wave_bytes = (int)w;
-    int wpb = 8;
-    while (wpb > 1 && o + (size_t)wpb * w > 160 * 1024) --wpb;
     s.wpb = wpb;
     s.bytes = o + (size_t)wpb * w;
     return s;
+}
+
+// The block size that keeps the most walkers resident on a CU.  Every block
+// holds its own copy of the shared tables, so small blocks repeat them; large
+// blocks leave wavefront slots empty when the registers would allow more
+// resident wavefronts than whole blocks fit in LDS.  Ties go to the larger
+// block.
+static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
+    SweepLayout best = sweep_layout(c, ts, 1);
+    int best_res = -1;
+    for (int wpb : {8, 4, 2}) {
+        const SweepLayout s = sweep_layout(c, ts, wpb);
+        if (s.bytes > 160 * 1024) continue;
+        const int nb = ts == sizeof(float) ? vmcx::sweep_blocks_per_cu<float>(c->n_occ, wpb, s.bytes)
+                                           : vmcx::sweep_blocks_per_cu<double>(c->n_occ, wpb, s.bytes);
+        if (nb * wpb > best_res) {
+            best = s;
+            best_res = nb * wpb;
+        }
+    }
+    return best;
 }
 
 // LDS layout of the adjoint for an arithmetic type of ts bytes.
@@ -545,6 +565,11 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     layouts(c);
     const bool mixed = opt->precision == VMC_MIXED;
     const size_t ts = mixed ? sizeof(float) : sizeof(double);
+    // the occupancy query behind the sweep's block size needs the LDS limit
+    // raised first
+    if (vmcx::configure_sweep<double>(160 * 1024) != hipSuccess ||
+        (mixed && vmcx::configure_sweep<float>(160 * 1024) != hipSuccess))
+        return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the sweep"));
     c->swl = sweep_layout(c, ts);
     c->al = adjoint_layout(c, ts);
     if (c->swl.bytes > 160 * 1024 || c->dl.bytes > 160 * 1024 || c->al.bytes > 160 * 1024)

@@ -113,6 +113,10 @@ hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, c
                            const WalkerOut &out, int warp, int W, hipStream_t st);
 template <typename T>
 hipError_t configure_sweep(size_t lds);
+// resident blocks of k_sweep_r per CU for blocks of wpb walkers and lds bytes
+// (0 when the runtime cannot tell)
+template <typename T>
+int sweep_blocks_per_cu(int n_occ, int wpb, size_t lds);
 
 hipError_t launch_round_f32(const double *x, float *y, int64_t n, hipStream_t st);
 

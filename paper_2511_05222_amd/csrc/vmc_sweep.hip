@@ -98,8 +98,15 @@ struct Vec16<double> {
     __device__ static double sum(type v) { return v.x + v.y; }
 };
 
+// FP32 with KN <= 48 fits three wavefronts per SIMD (spilling a little in the
+// FP64 rebuild); the rest runs two.
 template <typename T, int KN>
-__global__ __launch_bounds__(512) void k_sweep_r(SysDev S, const T *__restrict__ Cg, const double *__restrict__ R,
+constexpr int sweep_waves() {
+    return (sizeof(T) == 4 && KN <= 48) ? 3 : 2;
+}
+
+template <typename T, int KN>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves<T, KN>()))) void k_sweep_r(SysDev S, const T *__restrict__ Cg, const double *__restrict__ R,
                                                   double *walkers, int W, T *Amo, KState<T> ks, int fresh,
                                                   uint32_t sweep, uint64_t seed, double sigma, int refresh_period,
                                                   uint8_t *accept, int *status, SweepLayout L) {
@@ -342,6 +349,21 @@ template hipError_t launch_sweep<double>(const SysDev &, const double *, const d
 template hipError_t launch_sweep<float>(const SysDev &, const float *, const double *, double *, int, float *,
                                         const KState<float> &, int, uint32_t, uint64_t, double, int, uint8_t *,
                                         int *, const SweepLayout &, hipStream_t);
+template <typename T>
+int sweep_blocks_per_cu(int n_occ, int wpb, size_t lds) {
+    const void *f[4] = {(const void *)k_sweep_r<T, 16>, (const void *)k_sweep_r<T, 32>,
+                        (const void *)k_sweep_r<T, 48>, (const void *)k_sweep_r<T, 64>};
+    const int kn = sweep_kn(n_occ), k = kn == 16 ? 0 : (kn == 32 ? 1 : (kn == 48 ? 2 : 3));
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f[k], 64 * wpb, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return nb;
+}
+
+template int sweep_blocks_per_cu<double>(int, int, size_t);
+template int sweep_blocks_per_cu<float>(int, int, size_t);
 template hipError_t configure_sweep<double>(size_t);
 template hipError_t configure_sweep<float>(size_t);
 
