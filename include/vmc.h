@@ -237,14 +237,45 @@ int vmc_adjoint(vmc_ctx *ctx, const double *walkers_dev, int64_t n_walkers,
                 const double *gEL_dev, const double *gPsi_dev, const double *gJac_dev,
                 double *dC_dev, double *dR_dev, void *stream);
 
-/* Solve H z = -b (Z-vector equations A Z = -B, eq. AZ_eq_B_elements) by
- * conjugate gradients in FP64 from z = 0 until ||H z + b|| <= rtol ||b||.
- * H_dev[d][d] symmetric positive definite, b_dev[d], z_dev[d] (device).
- * Host outputs: *iters = iterations used.  Synchronises `stream`.
- * Errors: VMC_EINVAL (d < 1, rtol <= 0, maxit < 1), VMC_ENOTCONV (maxit
- * reached; z holds the last iterate), VMC_ENONFINITE, VMC_ENOMEM, VMC_EDEVICE. */
+/* ---- Z-vector step (Sec. II, eq. AZ_eq_B_elements: A Z = -B) ----------------
+ * The orbital rotation z lives in the virtual-occupied block: z[a][i], a over
+ * the n_virt virtual orbitals, i over the n_occ occupied ones, flattened
+ * row-major to d = n_virt * n_occ.  The orbital Hessian H over that index is
+ * the caller's (its CPKS integrals are outside this library).
+ *
+ * zvector_rhs: b[a][i] = sum_mu Cv[mu][a] dEdC[mu][i], the virtual-occupied
+ * block of C^T dE/dC (the occupied-occupied block C_occ^T dE/dC vanishes, so
+ * this is the whole projection of B onto orbital rotations).
+ *   Cv_dev[n_ao][n_virt]: the virtual MO coefficients (columns of the full,
+ *   S-orthonormal C after the occupied ones), row-major;
+ *   dEdC_dev[n_ao][n_occ]: dE/dC as vmc_accumulate returns it; b_dev[n_virt][n_occ].
+ * zvector_backmap: Z[mu][i] = sum_a Cv[mu][a] z[a][i], the AO-basis response
+ * (Z^T S C_occ = 0 follows from the S-orthonormality of C).
+ *   z_dev[n_virt][n_occ] in, Z_dev[n_ao][n_occ] out.
+ * Both are queued on `stream` (no synchronisation); all pointers are device
+ * memory owned by the caller; outputs are overwritten.  Errors: VMC_EINVAL
+ * (NULL pointer, a size < 1), VMC_EDEVICE (launch failure).
+ *
+ * zvector_solve: H z = -b by conjugate gradients in FP64 from z = 0
+ * (Hestenes-Stiefel; with flags & ZVECTOR_JACOBI, preconditioned by diag H)
+ * until ||H z + b|| <= rtol ||b|| (the true residual norm, not the
+ * preconditioned one), at most maxit iterations.
+ *   H_dev[d][d] symmetric positive definite, row-major; b_dev[d]; z_dev[d]
+ *   (device, caller-owned; z is overwritten).  The iteration state stays on
+ *   the device; the host reads it once every 8 iterations.  Host output:
+ *   *iters = iterations used (may be NULL).  Synchronises `stream`; allocates
+ *   about 4.2 d doubles of device scratch for the call.
+ * Errors: VMC_EINVAL (NULL pointer, d < 1, rtol <= 0, maxit < 1, unknown
+ * flag), VMC_ENOTCONV (maxit reached; z holds the last iterate),
+ * VMC_ENONFINITE (a non-finite residual or curvature; z unspecified),
+ * VMC_ENOMEM, VMC_EDEVICE. */
+#define ZVECTOR_JACOBI 1u
+int zvector_rhs(const double *Cv_dev, int64_t n_ao, int64_t n_virt, int64_t n_occ,
+                const double *dEdC_dev, double *b_dev, void *stream);
+int zvector_backmap(const double *Cv_dev, int64_t n_ao, int64_t n_virt, int64_t n_occ,
+                    const double *z_dev, double *Z_dev, void *stream);
 int zvector_solve(const double *H_dev, int64_t d, const double *b_dev, double *z_dev,
-                  double rtol, int32_t maxit, int32_t *iters, void *stream);
+                  double rtol, int32_t maxit, uint32_t flags, int32_t *iters, void *stream);
 
 /* Walkers processed per measurement launch (size of the per-walker staging);
  * returns -1 for a NULL context. */

@@ -7,7 +7,13 @@ positive definite H the solution is unique.
 
 Two solutions are given: a dense Cholesky solve (library routine) and
 conjugate gradients with the stopping rule of the GPU path,
-||r_k|| <= rtol ||b||, x_0 = 0 (Hestenes & Stiefel, 1952).
+||r_k|| <= rtol ||b||, x_0 = 0 (Hestenes & Stiefel, 1952), optionally
+preconditioned by diag H.
+
+The unknowns are rotations of the occupied orbitals into the virtual ones,
+C_occ -> C_occ + C_virt kappa (kappa[a][i], virtual a, occupied i): the
+right-hand side is the derivative of E along them and the solution maps back
+to a change of the occupied AO coefficients.
 """
 import numpy as np
 
@@ -43,3 +49,15 @@ def cg_solve(H, b, rtol=1e-12, maxit=10000, jacobi=False):
         rz = rz_new
     return x, maxit, False
 
+
+
+def rhs(C_virt, dE_dC):
+    """b[a][i] = dE/dkappa_ai = sum_mu C_virt[mu][a] dE/dC[mu][i] (chain rule
+    through C_occ + C_virt kappa; the virtual orbitals do not enter E)."""
+    return np.asarray(C_virt).T @ np.asarray(dE_dC)
+
+
+def backmap(C_virt, z):
+    """Z[mu][i] = sum_a C_virt[mu][a] z[a][i]: the rotation z as a change of the
+    occupied AO coefficients."""
+    return np.asarray(C_virt) @ np.asarray(z)

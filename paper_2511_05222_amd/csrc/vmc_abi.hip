@@ -854,59 +854,62 @@ int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
 }
 
 int zvector_solve(const double *H, int64_t d, const double *b, double *z, double rtol, int32_t maxit,
-                  int32_t *iters, void *stream) {
-    if (!H || !b || !z || d < 1 || !(rtol > 0.0) || maxit < 1) return VMC_EINVAL;
+                  uint32_t flags, int32_t *iters, void *stream) {
+    if (iters) *iters = 0;
+    if (!H || !b || !z || d < 1 || !(rtol > 0.0) || maxit < 1 || (flags & ~(uint32_t)ZVECTOR_JACOBI))
+        return VMC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    const int NPART = 64;
-    double *work = nullptr;
-    const size_t nwork = 3 * (size_t)d + NPART + 8;
-    if (hipMalloc(&work, nwork * sizeof(double)) != hipSuccess) {
+    const int nb = vmcx::cg_matvec_blocks(d);
+    // r, p, Hp, dinv, the matvec partials, then the iteration state
+    const size_t nwork = 4 * (size_t)d + (size_t)nb;
+    const size_t bytes = nwork * sizeof(double) + sizeof(vmcx::CgState);
+    void *work = nullptr;
+    if (hipMalloc(&work, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return VMC_ENOMEM;
     }
-    double *r = work, *p = work + d, *Hp = work + 2 * d, *part = work + 3 * d;
-    double *sc = part + NPART;   // [0] rr, [1] rr_new, [2] pHp, [3] bb
-    double *rr = sc, *rr_new = sc + 1, *pHp = sc + 2, *bb = sc + 3;
-    int status = VMC_OK;
-    int it = 0;
-    auto chk = [&](hipError_t e) {
-        if (e != hipSuccess && status == VMC_OK) status = VMC_EDEVICE;
-        return e == hipSuccess;
-    };
-    double h_bb = 0.0, h_rr = 0.0;
-    chk(vmcx::launch_cg_init(z, r, p, b, d, st));
-    chk(vmcx::launch_dot(r, r, d, part, NPART, rr, st));
-    chk(hipMemcpyAsync(bb, rr, 8, hipMemcpyDeviceToDevice, st));
-    chk(hipMemcpyAsync(&h_bb, bb, 8, hipMemcpyDeviceToHost, st));
-    chk(hipStreamSynchronize(st));
-    if (status == VMC_OK && !std::isfinite(h_bb)) status = VMC_ENONFINITE;
-    bool conv = (status == VMC_OK && h_bb == 0.0);
-    const double tol2 = rtol * rtol * h_bb;
-    while (status == VMC_OK && !conv && it < maxit) {
-        ++it;
-        chk(vmcx::launch_matvec(H, p, Hp, d, st));
-        chk(vmcx::launch_dot(p, Hp, d, part, NPART, pHp, st));
-        chk(vmcx::launch_cg_update_xr(z, r, p, Hp, d, rr, pHp, st));
-        chk(vmcx::launch_dot(r, r, d, part, NPART, rr_new, st));
-        chk(hipMemcpyAsync(&h_rr, rr_new, 8, hipMemcpyDeviceToHost, st));
-        chk(hipStreamSynchronize(st));
-        if (status != VMC_OK) break;
-        if (!std::isfinite(h_rr)) {
-            status = VMC_ENONFINITE;
-            break;
-        }
-        if (h_rr <= tol2) {
-            conv = true;
-            break;
-        }
-        chk(vmcx::launch_cg_update_p(p, r, d, rr_new, rr, st));
-        std::swap(rr, rr_new);
+    double *r = (double *)work, *p = r + d, *Hp = p + d, *dinv = Hp + d, *part = dinv + d;
+    vmcx::CgState *cs = (vmcx::CgState *)(part + nb);
+    vmcx::CgState hs{};
+    bool ok = vmcx::launch_cg_setup(H, b, d, (flags & ZVECTOR_JACOBI) ? 1 : 0, rtol, maxit, z, r, p, dinv, cs,
+                                    st) == hipSuccess;
+    // batches of iterations between reads of the device state (iterations
+    // queued after the end return at once)
+    const int batch = 8;
+    while (ok) {
+        ok = hipMemcpyAsync(&hs, cs, sizeof(hs), hipMemcpyDeviceToHost, st) == hipSuccess &&
+             hipStreamSynchronize(st) == hipSuccess;
+        if (!ok || hs.done) break;
+        for (int k = 0; ok && k < batch; ++k)
+            ok = vmcx::launch_cg_iteration(H, d, z, r, p, Hp, dinv, part, cs, st) == hipSuccess;
     }
-    chk(hipStreamSynchronize(st));
+    if (!ok) (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
     (void)hipFree(work);
-    if (iters) *iters = it;
-    if (status != VMC_OK) return status;
-    return conv ? VMC_OK : VMC_ENOTCONV;
+    if (!ok) return VMC_EDEVICE;
+    if (iters) *iters = hs.it;
+    if (hs.done == vmcx::CG_NONFINITE) return VMC_ENONFINITE;
+    return hs.done == vmcx::CG_CONVERGED ? VMC_OK : VMC_ENOTCONV;
+}
+
+int zvector_rhs(const double *Cv, int64_t n_ao, int64_t n_virt, int64_t n_occ, const double *dEdC, double *b,
+                void *stream) {
+    if (!Cv || !dEdC || !b || n_ao < 1 || n_virt < 1 || n_occ < 1) return VMC_EINVAL;
+    if (vmcx::launch_zv_rhs(Cv, dEdC, n_ao, n_virt, n_occ, b, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return VMC_EDEVICE;
+    }
+    return VMC_OK;
+}
+
+int zvector_backmap(const double *Cv, int64_t n_ao, int64_t n_virt, int64_t n_occ, const double *z, double *Z,
+                    void *stream) {
+    if (!Cv || !z || !Z || n_ao < 1 || n_virt < 1 || n_occ < 1) return VMC_EINVAL;
+    if (vmcx::launch_zv_backmap(Cv, z, n_ao, n_virt, n_occ, Z, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return VMC_EDEVICE;
+    }
+    return VMC_OK;
 }
 
 int vmc_profile(vmc_ctx *c, int32_t enable) {

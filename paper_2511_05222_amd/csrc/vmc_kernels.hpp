@@ -41,13 +41,23 @@ hipError_t launch_energy_cotangents(int64_t W, double gE, const double *EL, cons
                                     const double *Ehat, double *gEL, double *gPsi, double *gJac,
                                     hipStream_t st);
 hipError_t launch_combine(const double *acc, const double *comp, int64_t n, double *out, hipStream_t st);
-hipError_t launch_matvec(const double *H, const double *x, double *y, int64_t d, hipStream_t st);
-hipError_t launch_dot(const double *a, const double *b, int64_t d, double *part, int n_part, double *out,
-                      hipStream_t st);
-hipError_t launch_cg_init(double *x, double *r, double *p, const double *b, int64_t d, hipStream_t st);
-hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *Hp, int64_t d,
-                               const double *rr, const double *pHp, hipStream_t st);
-hipError_t launch_cg_update_p(double *p, const double *r, int64_t d, const double *rr_new, const double *rr,
-                              hipStream_t st);
+// device state of a conjugate-gradient solve
+enum { CG_CONVERGED = 1, CG_NONFINITE = 2, CG_MAXIT = 3 };
+struct CgState {
+    double rz;     // r . (M^-1 r) of the current residual
+    double tol2;   // (rtol ||b||)^2
+    int maxit;
+    int it;        // iterations done
+    int done;      // 0 while running, else CG_*
+};
+int cg_matvec_blocks(int64_t d);   // partial sums the iteration writes
+hipError_t launch_cg_setup(const double *H, const double *b, int64_t d, int jacobi, double rtol, int maxit,
+                           double *x, double *r, double *p, double *dinv, CgState *cs, hipStream_t st);
+hipError_t launch_cg_iteration(const double *H, int64_t d, double *x, double *r, double *p, double *Hp,
+                               const double *dinv, double *part, CgState *cs, hipStream_t st);
+hipError_t launch_zv_rhs(const double *Cv, const double *G, int64_t M, int64_t nv, int64_t n, double *b,
+                         hipStream_t st);
+hipError_t launch_zv_backmap(const double *Cv, const double *z, int64_t M, int64_t nv, int64_t n, double *Z,
+                             hipStream_t st);
 
 }  // namespace vmcx

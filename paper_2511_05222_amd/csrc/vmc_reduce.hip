@@ -151,65 +151,184 @@ __global__ void k_combine(const double *acc, const double *comp, int64_t n, doub
 }
 
 // ---------------------------------------------------------------------------
-// Conjugate gradients (FP64, HBM-bound matrix-vector products).
+// Conjugate gradients for H z = -b (FP64; Hestenes-Stiefel with an optional
+// Jacobi preconditioner M = diag H), stopping at ||r|| <= rtol ||b||.  The
+// iteration state lives on the device so that the host queues batches of
+// iterations and reads the state once per batch; every kernel returns at once
+// when the state says the solve has ended, so iterations queued after the end
+// change nothing.
 // ---------------------------------------------------------------------------
-// y = H x, one 256-thread block per row group: each wave owns one row.
-__global__ __launch_bounds__(256) void k_matvec(const double *__restrict__ H, const double *__restrict__ x,
-                                                double *__restrict__ y, int64_t d) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= d) return;
-    const double *h = H + row * d;
-    double s = 0.0;
-    for (int64_t c = lane; c < d; c += 64) s += h[c] * x[c];
+constexpr int CG_BS = 1024;   // threads of the single-block vector kernels
+constexpr int CG_RW = 2;      // matrix rows per matvec wavefront
+constexpr int CG_U = 8;       // column groups of 64 per row in flight
+constexpr int CG_ROWS = 4 * CG_RW;   // matrix rows per matvec block
+
+template <int BS>
+__device__ inline void block_sum2(double &a, double &b, double *red) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) y[row] = s;
-}
-
-// partial dot products (fixed order) of n_seg segments
-__global__ void k_dot_partial(const double *a, const double *b, int64_t d, double *part) {
-    __shared__ double red[4];
-    const int64_t seg = blockIdx.x;
-    const int64_t len = (d + gridDim.x - 1) / gridDim.x;
-    const int64_t k0 = seg * len, k1 = min(d, k0 + len);
-    double s = 0.0;
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += a[k] * b[k];
-    s = block_sum<256>(s, red);
-    if (threadIdx.x == 0) part[seg] = s;
-}
-
-__global__ void k_dot_final(const double *part, int n, double *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += part[i];
-        out[0] = s;
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[2 * wid] = a;
+        red[2 * wid + 1] = b;
+    }
+    __syncthreads();
+    a = b = 0.0;
+#pragma unroll
+    for (int i = 0; i < BS / 64; ++i) {
+        a += red[2 * i];
+        b += red[2 * i + 1];
     }
 }
 
-// CG vector updates with alpha = rr / pHp:  x += alpha p, r -= alpha Hp
-__global__ void k_cg_update_xr(double *x, double *r, const double *p, const double *Hp, int64_t d,
-                               const double *rr, const double *pHp) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d) return;
-    const double alpha = rr[0] / pHp[0];
-    x[k] += alpha * p[k];
-    r[k] -= alpha * Hp[k];
+// x = 0, r = -b, dinv = 1 / H_kk (or 1), p = dinv r; rz = r.(dinv r),
+// tol2 = rtol^2 ||b||^2.
+__global__ __launch_bounds__(CG_BS) void k_cg_setup(const double *__restrict__ H, const double *__restrict__ b,
+                                                    int64_t d, int jacobi, double rtol, int maxit, double *x,
+                                                    double *r, double *p, double *dinv, CgState *cs) {
+    __shared__ double red[2 * CG_BS / 64];
+    double rr = 0.0, rz = 0.0;
+    for (int64_t k = threadIdx.x; k < d; k += CG_BS) {
+        const double rk = -b[k];
+        const double di = jacobi ? 1.0 / H[k * d + k] : 1.0;
+        x[k] = 0.0;
+        r[k] = rk;
+        dinv[k] = di;
+        p[k] = di * rk;
+        rr += rk * rk;
+        rz += rk * (di * rk);
+    }
+    block_sum2<CG_BS>(rr, rz, red);
+    if (threadIdx.x == 0) {
+        cs->rz = rz;
+        cs->tol2 = rtol * rtol * rr;
+        cs->maxit = maxit;
+        cs->it = 0;
+        cs->done = !(std::isfinite(rr) && std::isfinite(rz)) ? CG_NONFINITE : (rr == 0.0 ? CG_CONVERGED : 0);
+    }
 }
 
-// p = r + beta p, beta = rr_new / rr
-__global__ void k_cg_update_p(double *p, const double *r, int64_t d, const double *rr_new, const double *rr) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d) return;
-    p[k] = r[k] + (rr_new[0] / rr[0]) * p[k];
+// Hp = H p, CG_RW rows per wavefront (each p element is loaded once for
+// them), CG_U column groups of 64 in flight per row, plus the block's partial
+// of p.Hp over its rows in row order.
+__global__ __launch_bounds__(256) void k_cg_matvec(const double *__restrict__ H, const double *__restrict__ p,
+                                                   double *__restrict__ Hp, double *__restrict__ part, int64_t d,
+                                                   const CgState *cs) {
+    if (cs->done) return;
+    __shared__ double rp[CG_ROWS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * CG_ROWS + wv * CG_RW;
+    const double *h[CG_RW];
+#pragma unroll
+    for (int i = 0; i < CG_RW; ++i) h[i] = H + min(r0 + i, d - 1) * d;   // rows past the end repeat the last
+    double s[CG_RW];
+#pragma unroll
+    for (int i = 0; i < CG_RW; ++i) s[i] = 0.0;
+    const int64_t dm = d - d % (64 * CG_U);
+    for (int64_t c = lane; c < dm; c += 64 * CG_U) {
+        double xv[CG_U], hv[CG_RW][CG_U];
+#pragma unroll
+        for (int u = 0; u < CG_U; ++u) xv[u] = p[c + 64 * u];
+#pragma unroll
+        for (int i = 0; i < CG_RW; ++i)
+#pragma unroll
+            for (int u = 0; u < CG_U; ++u) hv[i][u] = __builtin_nontemporal_load(h[i] + c + 64 * u);
+#pragma unroll
+        for (int i = 0; i < CG_RW; ++i)
+#pragma unroll
+            for (int u = 0; u < CG_U; ++u) s[i] = fma(hv[i][u], xv[u], s[i]);
+    }
+    for (int64_t c = dm + lane; c < d; c += 64) {
+        const double xv = p[c];
+#pragma unroll
+        for (int i = 0; i < CG_RW; ++i) s[i] = fma(h[i][c], xv, s[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < CG_RW; ++i)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s[i] += __shfl_down(s[i], off, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < CG_RW; ++i) {
+            const int64_t row = r0 + i;
+            const bool ok = row < d;
+            if (ok) Hp[row] = s[i];
+            rp[wv * CG_RW + i] = ok ? s[i] * p[min(row, d - 1)] : 0.0;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < CG_ROWS; ++i) t += rp[i];
+        part[blockIdx.x] = t;
+    }
 }
 
-__global__ void k_cg_init(double *x, double *r, double *p, const double *b, int64_t d) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d) return;
-    x[k] = 0.0;
-    r[k] = -b[k];
-    p[k] = -b[k];
+// alpha = rz / p.Hp; x += alpha p; r -= alpha Hp; stop test on ||r||^2; then
+// beta = rz_new / rz and p = dinv r + beta p.
+__global__ __launch_bounds__(CG_BS) void k_cg_update(double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ p, const double *__restrict__ Hp,
+                                                     const double *__restrict__ dinv,
+                                                     const double *__restrict__ part, int n_part, int64_t d,
+                                                     CgState *cs) {
+    if (cs->done) return;
+    __shared__ double red[2 * CG_BS / 64];
+    double pHp = 0.0, unused = 0.0;
+    for (int j = threadIdx.x; j < n_part; j += CG_BS) pHp += part[j];
+    block_sum2<CG_BS>(pHp, unused, red);
+    const double rz = cs->rz;
+    const double alpha = rz / pHp;
+    double rr = 0.0, rzn = 0.0;
+    for (int64_t k = threadIdx.x; k < d; k += CG_BS) {
+        x[k] += alpha * p[k];
+        const double rk = r[k] - alpha * Hp[k];
+        r[k] = rk;
+        rr += rk * rk;
+        rzn += rk * (dinv[k] * rk);
+    }
+    block_sum2<CG_BS>(rr, rzn, red);
+    const int it = cs->it + 1;
+    int done = 0;
+    if (!(std::isfinite(rr) && std::isfinite(rzn))) done = CG_NONFINITE;
+    else if (rr <= cs->tol2) done = CG_CONVERGED;
+    else if (it >= cs->maxit) done = CG_MAXIT;
+    if (!done) {
+        const double beta = rzn / rz;
+        for (int64_t k = threadIdx.x; k < d; k += CG_BS) p[k] = dinv[k] * r[k] + beta * p[k];
+    }
+    __syncthreads();   // every thread has read the state
+    if (threadIdx.x == 0) {
+        cs->rz = rzn;
+        cs->it = it;
+        cs->done = done;
+    }
+}
+
+// b[a][i] = sum_mu Cv[mu][a] G[mu][i] (the virtual-occupied block of C^T G)
+__global__ void k_zv_rhs(const double *__restrict__ Cv, const double *__restrict__ G, int64_t M, int64_t nv,
+                         int64_t n, double *__restrict__ b) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nv * n) return;
+    const int64_t a = o / n, i = o % n;
+    double s = 0.0;
+    for (int64_t mu = 0; mu < M; ++mu) s = fma(Cv[mu * nv + a], G[mu * n + i], s);
+    b[o] = s;
+}
+
+// Z[mu][i] = sum_a Cv[mu][a] z[a][i]
+__global__ void k_zv_backmap(const double *__restrict__ Cv, const double *__restrict__ z, int64_t M, int64_t nv,
+                             int64_t n, double *__restrict__ Z) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= M * n) return;
+    const int64_t mu = o / n, i = o % n;
+    double s = 0.0;
+    for (int64_t a = 0; a < nv; ++a) s = fma(Cv[mu * nv + a], z[a * n + i], s);
+    Z[o] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -251,33 +370,31 @@ hipError_t launch_combine(const double *acc, const double *comp, int64_t n, doub
     return hipGetLastError();
 }
 
-hipError_t launch_matvec(const double *H, const double *x, double *y, int64_t d, hipStream_t st) {
-    hipLaunchKernelGGL(k_matvec, dim3((unsigned)((d + 3) / 4)), dim3(256), 0, st, H, x, y, d);
+int cg_matvec_blocks(int64_t d) { return (int)((d + CG_ROWS - 1) / CG_ROWS); }
+
+hipError_t launch_cg_setup(const double *H, const double *b, int64_t d, int jacobi, double rtol, int maxit,
+                           double *x, double *r, double *p, double *dinv, CgState *cs, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(CG_BS), 0, st, H, b, d, jacobi, rtol, maxit, x, r, p, dinv, cs);
     return hipGetLastError();
 }
 
-hipError_t launch_dot(const double *a, const double *b, int64_t d, double *part, int n_part, double *out,
-                      hipStream_t st) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(n_part), dim3(256), 0, st, a, b, d, part);
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, st, part, n_part, out);
+hipError_t launch_cg_iteration(const double *H, int64_t d, double *x, double *r, double *p, double *Hp,
+                               const double *dinv, double *part, CgState *cs, hipStream_t st) {
+    const int nb = cg_matvec_blocks(d);
+    hipLaunchKernelGGL(k_cg_matvec, dim3((unsigned)nb), dim3(256), 0, st, H, p, Hp, part, d, cs);
+    hipLaunchKernelGGL(k_cg_update, dim3(1), dim3(CG_BS), 0, st, x, r, p, Hp, dinv, part, nb, d, cs);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_init(double *x, double *r, double *p, const double *b, int64_t d, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, x, r, p, b, d);
+hipError_t launch_zv_rhs(const double *Cv, const double *G, int64_t M, int64_t nv, int64_t n, double *b,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_zv_rhs, dim3((unsigned)((nv * n + 255) / 256)), dim3(256), 0, st, Cv, G, M, nv, n, b);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update_xr(double *x, double *r, const double *p, const double *Hp, int64_t d,
-                               const double *rr, const double *pHp, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_update_xr, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, x, r, p, Hp, d, rr,
-                       pHp);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update_p(double *p, const double *r, int64_t d, const double *rr_new, const double *rr,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_update_p, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, p, r, d, rr_new, rr);
+hipError_t launch_zv_backmap(const double *Cv, const double *z, int64_t M, int64_t nv, int64_t n, double *Z,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_zv_backmap, dim3((unsigned)((M * n + 255) / 256)), dim3(256), 0, st, Cv, z, M, nv, n, Z);
     return hipGetLastError();
 }
 

@@ -26,8 +26,8 @@ VMC_SWEEP_MEASURE = 1
 VMC_ACCUM_RESET = 1
 
 EXPORTED = ["vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
-            "vmc_adjoint", "zvector_solve", "vmc_staging_walkers", "vmc_free", "vmc_last_error", "vmc_init_error",
-            "vmc_strerror", "vmc_profile", "vmc_profile_read"]
+            "vmc_adjoint", "zvector_solve", "zvector_rhs", "zvector_backmap", "vmc_staging_walkers", "vmc_free",
+            "vmc_last_error", "vmc_init_error", "vmc_strerror", "vmc_profile", "vmc_profile_read"]
 
 
 class VmcError(RuntimeError):
@@ -85,7 +85,9 @@ def lib():
     L.vmc_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_energy_cotangents.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.zvector_solve.argtypes = [vp, i64, vp, vp, dbl, i32, ct.POINTER(i32), vp]
+    L.zvector_solve.argtypes = [vp, i64, vp, vp, dbl, i32, ct.c_uint32, ct.POINTER(i32), vp]
+    L.zvector_rhs.argtypes = [vp, i64, i64, i64, vp, vp, vp]
+    L.zvector_backmap.argtypes = [vp, i64, i64, i64, vp, vp, vp]
     L.vmc_profile.argtypes = [vp, i32]
     L.vmc_profile_read.argtypes = [vp, i32, vp, vp, vp]
     L.vmc_staging_walkers.argtypes = [vp]
@@ -99,7 +101,8 @@ def lib():
     L.vmc_strerror.argtypes = [ct.c_int]
     L.vmc_strerror.restype = ct.c_char_p
     for name in ("vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
-                 "vmc_adjoint", "zvector_solve", "vmc_profile", "vmc_profile_read"):
+                 "vmc_adjoint", "zvector_solve", "zvector_rhs", "zvector_backmap", "vmc_profile",
+                 "vmc_profile_read"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -289,18 +292,52 @@ class Context:
         return dC, dR
 
 
-def zvector_solve(H, b, rtol=1e-12, maxit=1000):
-    """Solve H z = -b by FP64 conjugate gradients on the GPU; returns (z, iterations)."""
-    import torch
-    d = b.shape[0]
-    _check_dev(H, (d, d))
-    _check_dev(b, (d,))
-    z = torch.empty_like(b)
-    it = ct.c_int32(0)
-    rc = lib().zvector_solve(_ptr(H), d, _ptr(b), _ptr(z), float(rtol), int(maxit), ct.byref(it), _stream())
+ZVECTOR_JACOBI = 1
+
+
+def _zv_check(rc):
     if rc != VMC_OK:
         raise VmcError(rc, lib().vmc_strerror(rc).decode())
+
+
+def zvector_solve(H, b, rtol=1e-12, maxit=1000, jacobi=False):
+    """Solve H z = -b by FP64 conjugate gradients on the GPU (optionally
+    Jacobi-preconditioned); returns (z, iterations)."""
+    import torch
+    d = b.numel()
+    _check_dev(H, (d, d))
+    _check_dev(b, tuple(b.shape))
+    z = torch.empty_like(b)
+    it = ct.c_int32(0)
+    rc = lib().zvector_solve(_ptr(H), d, _ptr(b), _ptr(z), float(rtol), int(maxit),
+                             ZVECTOR_JACOBI if jacobi else 0, ct.byref(it), _stream())
+    _zv_check(rc)
     return z, it.value
+
+
+def zvector_rhs(Cv, dE_dC):
+    """b = Cv^T dE/dC, shape (n_virt, n_occ): the right-hand side of the
+    Z-vector equations in the virtual-occupied rotation block."""
+    import torch
+    M, nv = Cv.shape
+    n = dE_dC.shape[1]
+    _check_dev(Cv, (M, nv))
+    _check_dev(dE_dC, (M, n))
+    b = torch.empty((nv, n), dtype=torch.float64, device=Cv.device)
+    _zv_check(lib().zvector_rhs(_ptr(Cv), M, nv, n, _ptr(dE_dC), _ptr(b), _stream()))
+    return b
+
+
+def zvector_backmap(Cv, z):
+    """Z = Cv z, shape (n_ao, n_occ): the response in the AO basis."""
+    import torch
+    M, nv = Cv.shape
+    n = z.shape[1]
+    _check_dev(Cv, (M, nv))
+    _check_dev(z, (nv, n))
+    Z = torch.empty((M, n), dtype=torch.float64, device=Cv.device)
+    _zv_check(lib().zvector_backmap(_ptr(Cv), M, nv, n, _ptr(z), _ptr(Z), _stream()))
+    return Z
 
 
 def _make_energy_function():

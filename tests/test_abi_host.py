@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "vmc.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(vmc_\w+|zvector_solve)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(vmc_\w+|zvector_\w+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -92,4 +92,6 @@ def test_zvector_rejects_bad_sizes():
     L = vmc.lib()
     import ctypes as ct
     it = ct.c_int32(0)
-    assert L.zvector_solve(None, 0, None, None, 1e-10, 10, ct.byref(it), None) == vmc.VMC_EINVAL
+    assert L.zvector_solve(None, 0, None, None, 1e-10, 10, 0, ct.byref(it), None) == vmc.VMC_EINVAL
+    assert L.zvector_rhs(None, 5, 3, 2, None, None, None) == vmc.VMC_EINVAL
+    assert L.zvector_backmap(None, 5, 3, 2, None, None, None) == vmc.VMC_EINVAL

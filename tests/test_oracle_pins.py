@@ -313,6 +313,49 @@ def test_zvector_cg():
     assert not ok1 and it1 == 1
 
 
+# Z-vector right-hand side and back-map.  b = C_virt^T (dE/dC) is the derivative
+# of the fixed-sample energy along the rotation C_occ -> C_occ + h C_virt e_a e_i^T
+# (central differences, as P7); the back-mapped response is S-orthogonal to the
+# occupied orbitals (Z^T S C_occ = 0) because the full C is S-orthonormal.
+def test_zvector_rhs_and_backmap(mol9):
+    s = wf.System(mol9)
+    w = inputs.initial_walkers(mol9, 12, 4)
+    ch, _ = sampler.run(s, w, 3, 4)
+    r = ch.r
+    R0 = s.xyz
+    m = dv.measure(s, R0, r)
+    acc = estimators.Accumulator(s.A, s.M, s.C.shape[1])
+    acc.add(m)
+    res = acc.result()
+    n = mol9.n_occ
+    Cv = mol9.C_full[:, n:]
+    b = zvector.rhs(Cv, res["dE_dC"] + res["dEL_dC_mean"])
+    assert b.shape == (Cv.shape[1], n)
+    h = 1e-4
+    for a, i in [(0, 0), (5, 3), (Cv.shape[1] - 1, n - 1)]:
+        D = np.zeros_like(s.C)
+        D[:, i] = Cv[:, a]
+        fd = (_ehat(s, R0, R0, r, m["lnpsi"], s.C + h * D) - _ehat(s, R0, R0, r, m["lnpsi"], s.C - h * D)) / (2 * h)
+        assert abs(fd - b[a, i]) < 1e-6 * max(1.0, abs(fd)), (a, i, fd, b[a, i])
+    S = inputs.overlap_matrix(mol9.xyz, mol9.basis)
+    z = np.random.default_rng(9).standard_normal((Cv.shape[1], n))
+    Z = zvector.backmap(Cv, z)
+    assert np.abs(Z.T @ S @ mol9.C).max() < 1e-10 * np.abs(Z).max()
+    assert np.abs(Z.T @ S @ Cv - z.T).max() < 1e-10 * np.abs(z).max()
+
+
+# P15 with the Jacobi preconditioner: same solution, no more iterations on a
+# system with a spread diagonal.
+def test_zvector_cg_jacobi():
+    H = inputs.seeded_spd(300, 6)
+    b = np.random.default_rng(6).standard_normal(300)
+    z_ref = zvector.cholesky_solve(H, b)
+    z, it, ok = zvector.cg_solve(H, b, rtol=1e-12, jacobi=True)
+    assert ok
+    assert np.linalg.norm(H @ z + b) <= 1e-12 * np.linalg.norm(b) * 1.0001
+    assert np.allclose(z, z_ref, rtol=1e-10, atol=1e-10 * np.abs(z_ref).max())
+
+
 # P16: chains depend only on (seed, walker id, sweep index): splitting a run,
 # or running a subset of walkers, gives bitwise identical positions.
 def test_resume_and_subsets(mol9):
