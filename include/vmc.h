@@ -126,13 +126,19 @@ typedef struct {
  * block_sweeps   : sweeps per block of the blocked energy error bar
  * max_walkers    : largest n_walkers any call on this context will pass
  * staging_walkers: walkers measured per launch (per-walker staging buffers);
- *                  0 = as many as fit in 2 GiB of staging
+ *                  0 = as many as fit in 16 GiB of staging
  * step_sigma     : proposal r' = r + step_sigma * N(0, I_3)
- * promote_cond   : VMC_MIXED only: a walker whose Slater blocks have
- *                  max|K| * max|A| above this (K = A^-1, FP64 from the FP32
- *                  orbital values) is measured again in FP64 and its FP64
- *                  results replace the mixed ones; 0 disables.  Costs one
- *                  host read of the promoted count per measurement launch. */
+ * promote_fraction: VMC_MIXED only, in [0, 1]: the share of each measurement
+ *                  launch's walkers that is measured again in FP64, its FP64
+ *                  results replacing the mixed ones (ceil(fraction * walkers)
+ *                  walkers; 0 disables).  The walkers taken are those with
+ *                  the largest max|Abar| (ties to the lower index), where
+ *                  Abar = (K X K)^T / 2 is formed per spin block in FP64
+ *                  (K = A^-1 from the FP32 orbital values; X[e][i] =
+ *                  lap phi_i(r_e) + 2 grad J . grad phi_i(r_e)): the
+ *                  sensitivity of E_L to errors in the orbital values, so
+ *                  the walkers whose FP32 rounding would dominate the
+ *                  walker-averaged error.  Non-finite keys rank first. */
 typedef struct {
     int32_t precision;
     int32_t refresh_period;
@@ -140,7 +146,7 @@ typedef struct {
     int32_t max_walkers;
     int32_t staging_walkers;
     double  step_sigma;
-    double  promote_cond;
+    double  promote_fraction;
 } vmc_options;
 
 /* Per-walker outputs of one measurement (device arrays, any may be NULL).

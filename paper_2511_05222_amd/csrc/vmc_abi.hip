@@ -34,7 +34,7 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 constexpr int64_t MAX_SEG = 64;
 constexpr int64_t MAX_BLOCKS = 1 << 16;
-constexpr size_t STAGING_BUDGET = size_t(1) << 31;   // bytes of per-walker staging
+constexpr size_t STAGING_BUDGET = size_t(1) << 34;   // bytes of per-walker staging (16 GiB)
 
 int dfact(int n) {
     int r = 1;
@@ -85,9 +85,11 @@ struct vmc_ctx {
     int *Kstale = nullptr;   // [max_walkers][2]
     float *d_Cf = nullptr;   // C in FP32 (mixed precision)
     float *d_Cm = nullptr;   // FP32 copy of a caller's C (mixed precision)
-    // FP64 re-measurement of ill-conditioned walkers (mixed precision)
+    // FP64 re-measurement of the walkers whose E_L is most sensitive to the
+    // FP32 orbital values (mixed precision)
     AdjLayout al64{};
-    int *plist = nullptr, *pcount = nullptr;
+    int *plist = nullptr;
+    double *pkey = nullptr;
     int64_t pcap = 0;
     double *cp_pos = nullptr, *cp_pos0 = nullptr, *cp_EL = nullptr, *cp_lnpsi = nullptr, *cp_dEdR = nullptr,
            *cp_dPdR = nullptr, *cp_dJdR = nullptr, *cp_O = nullptr, *cp_G = nullptr;
@@ -289,13 +291,13 @@ struct KStateRef {
 
 template <typename T>
 static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64_t cw, const T *C, const double *R,
-                        const double *R0, int warp, int full, const WalkerOut &o, const AdjLayout &al, int *plist,
+                        const double *R0, int warp, int full, const WalkerOut &o, const AdjLayout &al, double *pkey,
                         bool prof, const KStateRef &ks, hipStream_t st) {
     const SysDev &S = c->sys;
     T *phi = (T *)c->mb_phi;
     MeasBufs<T> mb{pos,         pos0,       phi,       full ? (T *)c->mb_ktil : nullptr, (T *)c->mb_abar, c->mb_gb,
-                   c->mb_dpart, c->mb_tao, plist,     c->pcount,                        c->opt.promote_cond,
-                   (const T *)ks.K, ks.sig, ks.stale};
+                   c->mb_dpart, c->mb_tao, pkey,      (const T *)ks.K,                  ks.sig,
+                   ks.stale};
     int pi = prof_begin(c, VMC_K_MO_ROWS, prof, cw, st);
     HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, st));
     prof_end(c, VMC_K_MO_ROWS, pi, st);
@@ -314,7 +316,7 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
 // One measurement of `cw` walkers at positions pos0 (device [cw][N][3]) with
 // the caller's FP64 C: forward always; adjoint when `full`.  Outputs already
 // offset to the chunk.  In mixed precision C is rounded to FP32, and the
-// walkers the dense kernel flags as ill-conditioned are measured again in
+// walkers the dense kernel flags as sensitive are measured again in
 // FP64 (gathered, measured, scattered over their mixed results).
 static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double *C, const double *R,
                        const double *R0, int warp, int full, const WalkerOut &o, hipStream_t st,
@@ -334,14 +336,15 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
         HIP_OK(c, vmcx::launch_round_f32(C, c->d_Cm, (int64_t)c->M * c->n_occ, st));
         Cf = c->d_Cm;
     }
-    const bool promote = c->opt.promote_cond > 0.0;
-    if (promote) HIP_OK(c, hipMemsetAsync(c->pcount, 0, sizeof(int), st));
-    int rc = measure_core<float>(c, pos, pos0, cw, Cf, R, R0, warp, full, o, c->al, promote ? c->plist : nullptr,
-                                 true, ks, st);
-    if (rc || !promote) return rc;
-    int cnt = 0;
-    HIP_OK(c, hipMemcpyAsync(&cnt, c->pcount, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_OK(c, hipStreamSynchronize(st));
+    // the walkers re-measured in FP64: a fixed share of the launch, those
+    // with the largest max|Abar| (known count: no host round trip)
+    const int64_t cnt = c->opt.promote_fraction > 0.0
+                            ? std::min<int64_t>(cw, (int64_t)std::ceil(c->opt.promote_fraction * (double)cw))
+                            : 0;
+    int rc = measure_core<float>(c, pos, pos0, cw, Cf, R, R0, warp, full, o, c->al, cnt ? c->pkey : nullptr, true,
+                                 ks, st);
+    if (rc || !cnt) return rc;
+    HIP_OK(c, vmcx::launch_promote_select(c->pkey, (int)cw, (int)cnt, c->plist, st));
     const int64_t N3 = 3 * (int64_t)c->N, A3 = 3 * (int64_t)c->A, Mn = (int64_t)c->M * c->n_occ;
     for (int64_t k0 = 0; k0 < cnt; k0 += c->pcap) {
         const int64_t kc = std::min<int64_t>(c->pcap, cnt - k0);
@@ -449,7 +452,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     if (opt->precision != VMC_FP64 && opt->precision != VMC_MIXED)
         return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 or VMC_MIXED)", opt->precision));
     if (opt->refresh_period < 1 || opt->block_sweeps < 1 || opt->max_walkers < 1 || opt->staging_walkers < 0 ||
-        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_cond >= 0.0))
+        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_fraction >= 0.0 && opt->promote_fraction <= 1.0))
         return bail(c->fail(VMC_EINVAL, "bad options"));
     double Zsum = 0.0;
     for (int a = 0; a < A; ++a) Zsum += nuclei->Z[a];
@@ -612,10 +615,10 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->Ksig, (size_t)opt->max_walkers * 2 * vmcx::sweep_kn(c->n_occ))) ||
         (rc = c->dalloc(&c->Kstale, (size_t)opt->max_walkers * 2)))
         return bail(rc);
-    if (opt->precision == VMC_MIXED && opt->promote_cond > 0.0) {
-        c->pcap = std::max<int64_t>(1, chunk / 8);
+    if (opt->precision == VMC_MIXED && opt->promote_fraction > 0.0) {
+        c->pcap = std::max<int64_t>(1, std::min<int64_t>(chunk, (int64_t)std::ceil(opt->promote_fraction * chunk)));
         const int64_t p = c->pcap;
-        if ((rc = c->dalloc(&c->plist, chunk)) || (rc = c->dalloc(&c->pcount, 1)) ||
+        if ((rc = c->dalloc(&c->plist, chunk)) || (rc = c->dalloc(&c->pkey, chunk)) ||
             (rc = c->dalloc(&c->cp_pos, p * 3 * c->N)) || (rc = c->dalloc(&c->cp_pos0, p * 3 * c->N)) ||
             (rc = c->dalloc(&c->cp_EL, p)) || (rc = c->dalloc(&c->cp_lnpsi, p)) ||
             (rc = c->dalloc(&c->cp_dEdR, p * A3)) || (rc = c->dalloc(&c->cp_dPdR, p * A3)) ||

@@ -13,11 +13,14 @@
 //            and (with the adjoint) X[e][i] = lap phi_i + 2 g_e . grad phi_i;
 //            then on 16x16x4 FP64 MFMA T = X K and
 //            Abar = 1/2 (K X K)^T = 1/2 T^T K^T, written with K~[e][i] = K[i][e].
-//   phase C  block sums: E_L, ln|Psi| = log|det up| + log|det dn| + J; the
-//            walker joins the promotion list if max|K| max|A| of a block
-//            exceeds the threshold (its T-precision orbitals are then too
-//            coarse for E_L and the derivatives).
+//            Abar is the sensitivity of E_L to the orbital values, so its
+//            largest magnitude is the key by which the mixed path picks the
+//            walkers it measures again in FP64 (formed, not stored, when
+//            only that key is wanted).
+//   phase C  block sums: E_L, ln|Psi| = log|det up| + log|det dn| + J.
 // K, X and T stay FP64; K~ and Abar are stored in the arithmetic type T.
+#include <cfloat>
+
 #include "vmc_mfma.hpp"
 #include "vmc_pipeline.hpp"
 #include "vmc_regs.hpp"
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         int lz = lane;
         asm volatile("" : "+v"(lz));
         int sig;
-        double la = 0.0, amax = 0.0;
+        double la = 0.0;
         double Br[KN];
         const bool from_state = mb.kst != nullptr && mb.kstale[2 * w + b] == 0;
         if (from_state) {
@@ -107,23 +110,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int r = 0; r < KN; ++r) av[r] = pa[(size_t)min(r, nb - 1) * 5 * n];
 #pragma unroll
-            for (int r = 0; r < KN; ++r) {
+            for (int r = 0; r < KN; ++r)
                 Br[r] = (lz < nb && r < nb) ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // identity padding
-                amax = fmax(amax, (lz < nb && r < nb) ? fabs(Br[r]) : 0.0);
-            }
             gj_regs<KN, true>(Br, sig, bad, la);
-        }
-        double kmax = 0.0;
-#pragma unroll
-        for (int r = 0; r < KN; ++r) kmax = fmax(kmax, (sig < nb && r < nb) ? fabs(Br[r]) : 0.0);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            amax = fmax(amax, __shfl_xor(amax, o, 64));
-            kmax = fmax(kmax, __shfl_xor(kmax, o, 64));
         }
         if (lane == 0) {
             red[4 + b] = la;
-            red[6 + b] = from_state ? kmax : amax * kmax;   // the state path adds max|A| later
             red[8 + b] = from_state ? 1.0 : 0.0;
         }
         // natural layout: lane p_k holds column k with register j = orbital p_j
@@ -189,17 +181,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (red[8 + b] == 0.0) continue;
         const int nb = b ? nd : nu, off = b ? nu : 0;
         double *K = Ks + (size_t)b * KN * ldk;
-        double am = 0.0;
         for (int idx = tid; idx < KN * KN; idx += 256) {
             const int e = idx / KN, i = idx - (idx / KN) * KN;
             const double v = (double)ph[(size_t)(off + min(e, nb - 1)) * 5 * n + min(i, nb - 1)];
             const bool in = e < nb && i < nb;
             Xs[e * ldk + i] = in ? v : (e == i ? 1.0 : 0.0);
-            am = fmax(am, in ? fabs(v) : 0.0);
         }
-        // red[6 + b] held max|K| alone: complete the condition indicator
-        am = block_max4(am, red + 12);
-        if (tid == 0) red[6 + b] *= am;
         __syncthreads();
         MF::acc_t tacc[TPW];
 #pragma unroll
@@ -255,6 +242,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const bool have_ld = red[8] == 0.0 && red[9] == 0.0;   // ln|det| known
     const double logdet = red[4] + red[5];
     const bool full = mb.ktil != nullptr;
+    // Abar is also formed, not stored, when it decides the FP64 re-measurement
+    const bool need_abar = full || mb.promote_key != nullptr;
+    double abar_max = 0.0;
     double *gb = mb.gb + (size_t)w * N * 6;
     for (int b = 0; b < 2; ++b) {
         const int nb = b ? nd : nu, off = b ? nu : 0;
@@ -299,7 +289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 el_part += -0.5 * (lp + 2.0 * (bx * gx + by * gy + bz * gz));
             }
         }
-        if (!full) continue;
+        if (!need_abar) continue;
         __syncthreads();
         // T = X K  (rows e', columns e)
         MF::acc_t tacc[TPW];
@@ -327,8 +317,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         __syncthreads();
         // Abar[e][i] = 1/2 sum_e' T[e'][e] K[i][e']
-        T *abw = mb.abar + ((size_t)w * N + off) * n;
-        T *ktw = mb.ktil + ((size_t)w * N + off) * n;
+        T *abw = full ? mb.abar + ((size_t)w * N + off) * n : nullptr;
+        T *ktw = full ? mb.ktil + ((size_t)w * N + off) * n : nullptr;
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int t = wave + 4 * q;
@@ -344,14 +334,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int v = 0; v < 4; ++v) {
                     const int e = 16 * rt + MF::row(lane, v);
                     if (e < nb && i < n) {
-                        abw[(size_t)e * n + i] = (T)(0.5 * acc[v]);
-                        ktw[(size_t)e * n + i] = (T)K[i * ldk + e];
+                        abar_max = fmax(abar_max, fabs(0.5 * acc[v]));
+                        if (full) {
+                            abw[(size_t)e * n + i] = (T)(0.5 * acc[v]);
+                            ktw[(size_t)e * n + i] = (T)K[i * ldk + e];
+                        }
                     }
                 }
             }
         }
         __syncthreads();   // the next block rewrites X
     }
+    if (mb.promote_key) abar_max = block_max4(abar_max, red + 12);
     // nuclear repulsion: the A^2 ordered pairs spread over the block
     double vnn = 0.0;
     for (int q = tid; q < A * A; q += 256) {
@@ -364,8 +358,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const double J = block_sum4(j_part, red);
     const int anybad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0) {
-        if (mb.promote_list && fmax(red[6], red[7]) > mb.promote_cond)
-            mb.promote_list[atomicAdd(mb.promote_count, 1)] = w;
+        if (mb.promote_key) mb.promote_key[w] = abar_max <= DBL_MAX ? abar_max : __builtin_inf();
         if (out.EL) out.EL[w] = EL;
         if (out.lnpsi) out.lnpsi[w] = have_ld ? logdet + J : __builtin_nan("");
         if (anybad) atomicOr(status, STATUS_SINGULAR);

@@ -300,6 +300,92 @@ hipError_t launch_round_f32(const double *x, float *y, int64_t n, hipStream_t st
     return hipGetLastError();
 }
 
+// The k walkers with the largest keys, by a most-significant-digit radix
+// select on the bit patterns of the keys (non-negative doubles order like
+// their bits; NaN counts as +inf), 8 bits per pass, then a pass over index
+// segments that lists the keys above the k-th largest and as many equal to
+// it as needed, lowest indices first, in index order.  One block.
+__device__ inline unsigned long long promote_bits(double x) {
+    return (unsigned long long)__double_as_longlong(x > 0.0 ? x : (x <= 0.0 ? 0.0 : __builtin_inf()));
+}
+
+template <int BS>
+__device__ inline int block_excl_scan(int v, int *buf, int &total) {
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < BS; o <<= 1) {
+        const int a = t >= o ? buf[t - o] : 0;
+        __syncthreads();
+        buf[t] += a;
+        __syncthreads();
+    }
+    const int incl = buf[t];
+    total = buf[BS - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+constexpr int SEL_BS = 1024;
+
+__global__ __launch_bounds__(SEL_BS) void k_promote_select(const double *__restrict__ key, int W, int k,
+                                                           int *__restrict__ list) {
+    __shared__ unsigned hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_rem;
+    __shared__ int buf[SEL_BS];
+    const int tid = threadIdx.x;
+    unsigned long long prefix = 0, mask = 0;
+    int rem = k;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        if (tid < 256) hist[tid] = 0;
+        __syncthreads();
+        for (int w = tid; w < W; w += SEL_BS) {
+            const unsigned long long u = promote_bits(key[w]);
+            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int cum = 0, b = 255;
+            for (; b > 0; --b) {
+                if (cum + (int)hist[b] >= rem) break;
+                cum += (int)hist[b];
+            }
+            s_rem = rem - cum;
+            s_prefix = prefix | ((unsigned long long)b << shift);
+        }
+        __syncthreads();
+        rem = s_rem;
+        prefix = s_prefix;
+        mask |= 255ull << shift;
+        __syncthreads();
+    }
+    // prefix: the k-th largest key; rem: how many keys equal to it to take
+    const int seg = (W + SEL_BS - 1) / SEL_BS;
+    const int w0 = min(W, tid * seg), w1 = min(W, w0 + seg);
+    int gt = 0, eq = 0;
+    for (int w = w0; w < w1; ++w) {
+        const unsigned long long u = promote_bits(key[w]);
+        gt += u > prefix;
+        eq += u == prefix;
+    }
+    int tot;
+    const int eq_before = block_excl_scan<SEL_BS>(eq, buf, tot);
+    const int take = max(0, min(eq, rem - eq_before));
+    int off = block_excl_scan<SEL_BS>(gt + take, buf, tot);
+    int taken = 0;
+    for (int w = w0; w < w1; ++w) {
+        const unsigned long long u = promote_bits(key[w]);
+        if (u > prefix || (u == prefix && taken++ < take)) list[off++] = w;
+    }
+}
+
+hipError_t launch_promote_select(const double *key, int W, int k, int *list, hipStream_t st) {
+    if (k <= 0 || W <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_promote_select, dim3(1), dim3(SEL_BS), 0, st, key, W, min(k, W), list);
+    return hipGetLastError();
+}
+
 // dst[k][j] = src[list[k]][j] and its inverse, rows of len doubles.
 __global__ void k_gather_rows(const double *__restrict__ src, const int *__restrict__ list, int64_t kc, int64_t len,
                               double *__restrict__ dst) {

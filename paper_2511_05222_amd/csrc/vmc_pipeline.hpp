@@ -60,12 +60,10 @@ struct MeasBufs {
     double *gb;           // [W][N][6]      Jastrow gradient (0..2), det gradient (3..5)
     double *dedr_part;    // [W][N][3]      dE_L/dr_e, determinant part
     double *tao;          // [W][M][6]      per-AO electron sums of t_k, s_k
-    // walkers whose Slater blocks are ill-conditioned for the arithmetic type
-    // (max|K| max|A| > promote_cond) are appended to promote_list (order of
-    // arrival) and counted in promote_count; null = no promotion
-    int *promote_list;
-    int *promote_count;
-    double promote_cond;
+    // per walker, max|Abar| over both spin blocks (Abar = (K X K)^T / 2, the
+    // sensitivity of E_L to the orbital values; +inf if not finite): the key
+    // that picks the walkers measured again in FP64; null = not needed
+    double *promote_key;
     // the sweep's persistent inverses of these walkers (KState layout); when
     // set, a block whose inverse is not stale starts from it and one FP64
     // Newton step instead of a Gauss-Jordan inversion (no ln|det| then)
@@ -118,6 +116,9 @@ hipError_t configure_sweep(size_t lds);
 template <typename T>
 int sweep_blocks_per_cu(int n_occ, int wpb, size_t lds);
 
+// list[0..k) = the k walkers of W with the largest keys (ties to the lower
+// index), in index order
+hipError_t launch_promote_select(const double *key, int W, int k, int *list, hipStream_t st);
 hipError_t launch_round_f32(const double *x, float *y, int64_t n, hipStream_t st);
 
 hipError_t launch_gather_rows(const double *src, const int *list, int64_t kc, int64_t len, double *dst,

@@ -298,11 +298,29 @@ def make_config(i: int) -> RunSpec:
         mol = make_molecule(composition(21), 2, 12, 102, "21-atom C9O4H8")
         return RunSpec(mol, 256, 50, 3)
     if i == 4:
-        rng = np.random.Generator(np.random.PCG64(4))
-        A = int(rng.integers(9, 22))
-        mol = make_molecule(composition(A), 1000, 2000, 3000, f"{A}-atom mixed-family g0")
-        return RunSpec(mol, 8192, 10, 4, precision="mixed")
+        return family_member(0)
     raise ValueError(i)
+
+
+FAMILY_SIZE = 64
+
+
+def family_sizes():
+    """Atom counts of the 64-geometry mixed-size family, A ~ U{9..21} (PCG64 seed 4)."""
+    rng = np.random.Generator(np.random.PCG64(4))
+    return [int(a) for a in rng.integers(9, 22, size=FAMILY_SIZE)]
+
+
+@lru_cache(maxsize=None)
+def family_member(g: int) -> RunSpec:
+    """Geometry g of the mixed-size family: composition of its atom count,
+    geometry / basis / C seeds 1000 + g, 2000 + g, 3000 + g; 8192 walkers,
+    mixed precision."""
+    if not 0 <= g < FAMILY_SIZE:
+        raise ValueError(g)
+    A = family_sizes()[g]
+    mol = make_molecule(composition(A), 1000 + g, 2000 + g, 3000 + g, f"{A}-atom mixed-family g{g}")
+    return RunSpec(mol, 8192, 10, 4, precision="mixed")
 
 
 def init_atom_of_electron(Z, n_up, n_dn):

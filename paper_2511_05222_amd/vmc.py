@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(HERE, "libvmcx.so")
 VMC_OK, VMC_EINVAL, VMC_ENOMEM, VMC_EDEVICE, VMC_ESINGULAR, VMC_ENOTCONV, VMC_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 VMC_FP64 = 0
 VMC_MIXED = 1
-# mixed precision: walkers with max|K| max|A| above this are measured again in
-# FP64 (the FP32 orbital rounding, amplified by the conditioning of the Slater
-# blocks, would otherwise dominate the walker-averaged error)
-PROMOTE_COND = 300.0
+# mixed precision: share of each measurement launch re-measured in FP64 (the
+# walkers with the largest max|Abar|, the sensitivity of E_L to the orbital
+# values); a few such walkers would otherwise dominate the walker-averaged error
+PROMOTE_FRACTION = 0.02
 VMC_SWEEP_MEASURE = 1
 VMC_ACCUM_RESET = 1
 
@@ -58,7 +58,7 @@ class _Jastrow(ct.Structure):
 class _Options(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("refresh_period", ct.c_int32), ("block_sweeps", ct.c_int32),
                 ("max_walkers", ct.c_int32), ("staging_walkers", ct.c_int32), ("step_sigma", ct.c_double),
-                ("promote_cond", ct.c_double)]
+                ("promote_fraction", ct.c_double)]
 
 
 class _WalkerOut(ct.Structure):
@@ -131,7 +131,7 @@ class Context:
     """A wavefunction on one GPU plus its estimator accumulators."""
 
     def __init__(self, mol, max_walkers, precision="fp64", refresh_period=32, block_sweeps=1,
-                 step_sigma=0.5, device=0, staging_walkers=0, promote_cond=PROMOTE_COND):
+                 step_sigma=0.5, device=0, staging_walkers=0, promote_fraction=PROMOTE_FRACTION):
         L = lib()
         b = mol.basis
         self._keep = [np.ascontiguousarray(b.shell_atom, np.int32), np.ascontiguousarray(b.shell_l, np.int32),
@@ -152,7 +152,7 @@ class Context:
         if prec is None:
             raise VmcError(VMC_EINVAL, f"precision {precision!r} is not available")
         opt = _Options(prec, refresh_period, block_sweeps, int(max_walkers), int(staging_walkers), step_sigma,
-                       float(promote_cond))
+                       float(promote_fraction))
         h = ct.c_void_p()
         rc = L.vmc_init(ct.byref(basis), ct.byref(nuc), ct.byref(mo), ct.byref(jas), ct.byref(opt), device,
                         ct.byref(h))
