@@ -137,7 +137,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed sweeps (with measurement) before the timed call: the chains leave their "
+                         "starting positions, so the timed sweeps see equilibrated walkers")
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="21atom")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
