@@ -138,7 +138,11 @@ typedef struct {
  *                  lap phi_i(r_e) + 2 grad J . grad phi_i(r_e)): the
  *                  sensitivity of E_L to errors in the orbital values, so
  *                  the walkers whose FP32 rounding would dominate the
- *                  walker-averaged error.  Non-finite keys rank first. */
+ *                  walker-averaged error.  Non-finite keys rank first.
+ * jackknife_blocks: number of blocks (of block_sweeps sweeps) whose sums of
+ *                  every estimator element are kept for vmc_jackknife
+ *                  (at most 65535; 0 = none; (2 + 9A + 3 M n_occ) doubles of
+ *                  device memory per block). */
 typedef struct {
     int32_t precision;
     int32_t refresh_period;
@@ -147,6 +151,7 @@ typedef struct {
     int32_t staging_walkers;
     double  step_sigma;
     double  promote_fraction;
+    int32_t jackknife_blocks;
 } vmc_options;
 
 /* Per-walker outputs of one measurement (device arrays, any may be NULL).
@@ -206,6 +211,22 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
 int vmc_accumulate(vmc_ctx *ctx, double *E, double *F_bare, double *dE_dC,
                    double *dEL_dC_mean, int64_t *n_samples, uint32_t flags, void *stream);
 
+/* Jackknife replicas of the estimators (Sec. II: the statistical error of B
+ * carried through the Z-vector equations by resampling; App. A blocking):
+ * for each of the nb complete blocks accumulated since the last reset (at
+ * most jackknife_blocks), the estimate from all other blocks,
+ *   E_jk_dev[nb]                 E^(-b)
+ *   F_jk_dev[nb][n_atoms][3]     F_bare^(-b)
+ *   dEdC_jk_dev[nb][n_ao][n_occ] dE/dC^(-b)
+ * (device, caller-owned, any may be NULL; all NULL = only report nb).  The
+ * jackknife mean and error of any quantity computed from the replicas follow
+ * from zvector_jackknife.  *n_blocks (host, may be NULL) = nb.  Call before
+ * the vmc_accumulate that resets.  Synchronises `stream`.
+ * Errors: VMC_EINVAL (jackknife_blocks = 0, or fewer than two complete
+ * blocks when an output is requested), VMC_EDEVICE. */
+int vmc_jackknife(vmc_ctx *ctx, double *E_jk_dev, double *F_jk_dev, double *dEdC_jk_dev, int64_t *n_blocks,
+                  void *stream);
+
 /* Per-walker measurement at fixed configurations for arbitrary MO
  * coefficients C_dev[n_ao][n_occ] and nuclei R_dev[A][3] (device): electrons
  * are warped r' = r + sum_a omega_a(r; R0) (R_a - R0_a) with weights taken at
@@ -247,40 +268,53 @@ int vmc_adjoint(vmc_ctx *ctx, const double *walkers_dev, int64_t n_walkers,
  * The orbital rotation z lives in the virtual-occupied block: z[a][i], a over
  * the n_virt virtual orbitals, i over the n_occ occupied ones, flattened
  * row-major to d = n_virt * n_occ.  The orbital Hessian H over that index is
- * the caller's (its CPKS integrals are outside this library).
+ * the caller's (its CPKS integrals are outside this library).  Every call
+ * takes a batch of right-hand sides (n_batch / n_rhs >= 1, stored one after
+ * another), e.g. the jackknife replicas of dE/dC.
  *
- * zvector_rhs: b[a][i] = sum_mu Cv[mu][a] dEdC[mu][i], the virtual-occupied
- * block of C^T dE/dC (the occupied-occupied block C_occ^T dE/dC vanishes, so
- * this is the whole projection of B onto orbital rotations).
+ * zvector_rhs: b[k][a][i] = sum_mu Cv[mu][a] dEdC[k][mu][i], the
+ * virtual-occupied block of C^T dE/dC (the occupied-occupied block
+ * C_occ^T dE/dC vanishes, so this is the whole projection of B onto orbital
+ * rotations).
  *   Cv_dev[n_ao][n_virt]: the virtual MO coefficients (columns of the full,
  *   S-orthonormal C after the occupied ones), row-major;
- *   dEdC_dev[n_ao][n_occ]: dE/dC as vmc_accumulate returns it; b_dev[n_virt][n_occ].
- * zvector_backmap: Z[mu][i] = sum_a Cv[mu][a] z[a][i], the AO-basis response
- * (Z^T S C_occ = 0 follows from the S-orthonormality of C).
- *   z_dev[n_virt][n_occ] in, Z_dev[n_ao][n_occ] out.
- * Both are queued on `stream` (no synchronisation); all pointers are device
- * memory owned by the caller; outputs are overwritten.  Errors: VMC_EINVAL
- * (NULL pointer, a size < 1), VMC_EDEVICE (launch failure).
+ *   dEdC_dev[n_batch][n_ao][n_occ]; b_dev[n_batch][n_virt][n_occ].
+ * zvector_backmap: Z[k][mu][i] = sum_a Cv[mu][a] z[k][a][i], the AO-basis
+ * response (Z^T S C_occ = 0 follows from the S-orthonormality of C).
+ *   z_dev[n_batch][n_virt][n_occ] in, Z_dev[n_batch][n_ao][n_occ] out.
+ * zvector_jackknife: over n_blocks replicas x_jk_dev[n_blocks][len], the
+ * jackknife mean[len] = sum_b x_b / nb and standard error
+ * sigma[len] = sqrt((nb - 1)/nb sum_b (x_b - mean)^2) (either may be NULL).
+ * These three are queued on `stream` (no synchronisation); all pointers are
+ * device memory owned by the caller; outputs are overwritten.  Errors:
+ * VMC_EINVAL (NULL pointer, a size < 1, n_batch > 65535, n_blocks < 2),
+ * VMC_EDEVICE (launch failure).
  *
- * zvector_solve: H z = -b by conjugate gradients in FP64 from z = 0
- * (Hestenes-Stiefel; with flags & ZVECTOR_JACOBI, preconditioned by diag H)
- * until ||H z + b|| <= rtol ||b|| (the true residual norm, not the
- * preconditioned one), at most maxit iterations.
- *   H_dev[d][d] symmetric positive definite, row-major; b_dev[d]; z_dev[d]
- *   (device, caller-owned; z is overwritten).  The iteration state stays on
- *   the device; the host reads it once every 8 iterations.  Host output:
- *   *iters = iterations used (may be NULL).  Synchronises `stream`; allocates
- *   about 4.2 d doubles of device scratch for the call.
- * Errors: VMC_EINVAL (NULL pointer, d < 1, rtol <= 0, maxit < 1, unknown
- * flag), VMC_ENOTCONV (maxit reached; z holds the last iterate),
- * VMC_ENONFINITE (a non-finite residual or curvature; z unspecified),
- * VMC_ENOMEM, VMC_EDEVICE. */
+ * zvector_solve: H z_k = -b_k for k < n_rhs by conjugate gradients in FP64
+ * from z = 0 (Hestenes-Stiefel; with flags & ZVECTOR_JACOBI, preconditioned
+ * by diag H) until ||H z + b|| <= rtol ||b|| (the true residual norm, not the
+ * preconditioned one), at most maxit iterations each.
+ *   H_dev[d][d] symmetric positive definite, row-major; b_dev[n_rhs][d];
+ *   z_dev[n_rhs][d] (device, caller-owned; z is overwritten).  The iteration
+ *   state stays on the device; the host reads it once every 8 iterations.
+ *   Several right-hand sides run in lockstep in groups of up to 64, every
+ *   read of H shared by the group (an FP64 matrix-core product); each keeps
+ *   its own step lengths and stopping test.  Host output: iters[n_rhs] =
+ *   iterations used (may be NULL).  Synchronises `stream`; allocates device
+ *   scratch for the call: about 4.2 d doubles for one right-hand side,
+ *   (3 + s) * g * d doubles for a group of g (s <= 16 column splits).
+ * Errors (the first failing right-hand side decides): VMC_EINVAL (NULL
+ * pointer, d < 1, n_rhs < 1, rtol <= 0, maxit < 1, unknown flag),
+ * VMC_ENOTCONV (maxit reached; z holds the last iterate), VMC_ENONFINITE (a
+ * non-finite residual or curvature; z unspecified), VMC_ENOMEM, VMC_EDEVICE. */
 #define ZVECTOR_JACOBI 1u
-int zvector_rhs(const double *Cv_dev, int64_t n_ao, int64_t n_virt, int64_t n_occ,
+int zvector_rhs(const double *Cv_dev, int64_t n_ao, int64_t n_virt, int64_t n_occ, int64_t n_batch,
                 const double *dEdC_dev, double *b_dev, void *stream);
-int zvector_backmap(const double *Cv_dev, int64_t n_ao, int64_t n_virt, int64_t n_occ,
+int zvector_backmap(const double *Cv_dev, int64_t n_ao, int64_t n_virt, int64_t n_occ, int64_t n_batch,
                     const double *z_dev, double *Z_dev, void *stream);
-int zvector_solve(const double *H_dev, int64_t d, const double *b_dev, double *z_dev,
+int zvector_jackknife(const double *x_jk_dev, int64_t n_blocks, int64_t len, double *mean_dev,
+                      double *sigma_dev, void *stream);
+int zvector_solve(const double *H_dev, int64_t d, int64_t n_rhs, const double *b_dev, double *z_dev,
                   double rtol, int32_t maxit, uint32_t flags, int32_t *iters, void *stream);
 
 /* Walkers processed per measurement launch (size of the per-walker staging);

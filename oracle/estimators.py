@@ -16,6 +16,12 @@ subtracted from E_L, so that the covariances do not cancel catastrophically
 (E_L is hundreds of hartree).  Batches are summed by numpy (pairwise) and
 accumulated across batches with Neumaier compensation.  Block sums of E_L - s
 per `block_sweeps` sweeps give the blocked error bar.
+
+Jackknife (the resampling the paper uses for the error of B and of what the
+Z-vector equations make of it, Sec. II): every complete block keeps its own
+sums of all estimator terms; replica b is the estimate from all blocks but b,
+and the jackknife error of any function of the replicas x_b is
+sqrt((nb - 1)/nb * sum_b (x_b - mean)^2).
 """
 import numpy as np
 
@@ -50,6 +56,8 @@ class Accumulator:
         self._sweeps_in_block = 0
         self.block_F = []
         self._blk = None
+        self.block_terms = []      # per complete block: dict of term sums and K
+        self._terms = None
 
     def _block_force(self, e, meas):
         """Per-block force estimate (for blocked error bars of F)."""
@@ -78,6 +86,10 @@ class Accumulator:
         sm["O"].add(np.sum(meas["O"], axis=0))
         sm["EO"].add(np.einsum("w,wmi->mi", e, meas["O"]))
         sm["G"].add(np.sum(meas["G"], axis=0))
+        t = dict(K=W, E=np.sum(e), H=np.sum(meas["H"], axis=0), P=np.sum(meas["P"], axis=0),
+                 EP=np.einsum("w,wak->ak", e, meas["P"]), O=np.sum(meas["O"], axis=0),
+                 EO=np.einsum("w,wmi->mi", e, meas["O"]))
+        self._terms = t if self._terms is None else {k: self._terms[k] + t[k] for k in t}
         self._cur_block[0] += float(np.sum(e))
         self._cur_block[1] += W
         self._block_force(e, meas)
@@ -87,6 +99,8 @@ class Accumulator:
             k = float(b["K"])
             self.block_F.append(-b["H"] / k - 2.0 * (b["EP"] / k - (b["E"] / k) * (b["P"] / k)))
             self._blk = None
+            self.block_terms.append(self._terms)
+            self._terms = None
             self.block_sums.append(self._cur_block[0])
             self.block_counts.append(self._cur_block[1])
             self._cur_block = [0.0, 0]
@@ -108,3 +122,25 @@ class Accumulator:
             F_sigma = np.full_like(F, np.nan)
         return dict(E=E, E_sigma=sigma, F_sigma=F_sigma, F_bare=F, dE_dC=dEdC, dEL_dC_mean=v["G"],
                     var_E=v["EE"] - v["E"] ** 2, K=self.K, shift=self.shift)
+
+    def jackknife(self):
+        """Leave-one-block-out replicas of E, F_bare and dE/dC over the complete
+        blocks: replica b sums the terms of every block except b."""
+        nb = len(self.block_terms)
+        out = dict(E=[], F_bare=[], dE_dC=[])
+        for b in range(nb):
+            rest = [self.block_terms[q] for q in range(nb) if q != b]
+            K = float(sum(r["K"] for r in rest))
+            v = {k: sum(r[k] for r in rest) / K for k in ("E", "H", "P", "EP", "O", "EO")}
+            out["E"].append(self.shift + v["E"])
+            out["F_bare"].append(-v["H"] - 2.0 * (v["EP"] - v["E"] * v["P"]))
+            out["dE_dC"].append(2.0 * (v["EO"] - v["E"] * v["O"]))
+        return {k: np.array(x) for k, x in out.items()}
+
+
+def jackknife_stats(x):
+    """Mean and jackknife standard error over the first axis of replicas x."""
+    x = np.asarray(x, dtype=np.float64)
+    nb = x.shape[0]
+    m = x.mean(axis=0)
+    return m, np.sqrt((nb - 1) / nb * ((x - m) ** 2).sum(axis=0))

@@ -36,6 +36,7 @@ def run(mol, walkers, n_sweeps, seed, sweep_offset=0, walker_ids=None, step_sigm
     out = dict(positions=ch.r, accept=bits, system=system)
     if measure:
         out.update(acc.result())
+        out["jackknife"] = acc.jackknife()
     if keep_samples:
         out["samples"] = samples
     return out

@@ -104,6 +104,10 @@ struct vmc_ctx {
 
     int64_t n_est = 0;
     double *acc = nullptr, *comp = nullptr, *partial = nullptr;
+    // per-block sums of every estimator element (jackknife), jk_cap blocks
+    double *blk_all = nullptr, *jk_cnt = nullptr;
+    int64_t jk_cap = 0;
+    std::vector<double> jk_cnt_host;
     double *shift = nullptr;
     int *shift_set = nullptr;
     int *status = nullptr;
@@ -452,7 +456,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     if (opt->precision != VMC_FP64 && opt->precision != VMC_MIXED)
         return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 or VMC_MIXED)", opt->precision));
     if (opt->refresh_period < 1 || opt->block_sweeps < 1 || opt->max_walkers < 1 || opt->staging_walkers < 0 ||
-        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_fraction >= 0.0 && opt->promote_fraction <= 1.0))
+        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_fraction >= 0.0 && opt->promote_fraction <= 1.0) || opt->jackknife_blocks < 0)
         return bail(c->fail(VMC_EINVAL, "bad options"));
     double Zsum = 0.0;
     for (int a = 0; a < A; ++a) Zsum += nuclei->Z[a];
@@ -634,6 +638,13 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->blocks, MAX_BLOCKS)) || (rc = c->dalloc(&c->vjp_acc, n_vjp)) ||
         (rc = c->dalloc(&c->vjp_comp, n_vjp)) || (rc = c->dalloc(&c->vjp_out, n_vjp)))
         return bail(rc);
+    if (opt->jackknife_blocks > 0) {
+        c->jk_cap = std::min<int64_t>(opt->jackknife_blocks, 65535);
+        if ((rc = c->dalloc(&c->blk_all, c->jk_cap * c->n_est)) || (rc = c->dalloc(&c->jk_cnt, c->jk_cap)))
+            return bail(rc);
+        if (hipMemset(c->blk_all, 0, c->jk_cap * c->n_est * 8) != hipSuccess)
+            return bail(c->fail(VMC_EDEVICE, "hipMemset failed"));
+    }
     if (hipMemset(c->acc, 0, c->n_est * 8) != hipSuccess || hipMemset(c->comp, 0, c->n_est * 8) != hipSuccess ||
         hipMemset(c->shift, 0, 8) != hipSuccess || hipMemset(c->shift_set, 0, 4) != hipSuccess ||
         hipMemset(c->status, 0, 4) != hipSuccess || hipMemset(c->blocks, 0, MAX_BLOCKS * 8) != hipSuccess)
@@ -685,6 +696,7 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
         const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
         double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;
+        double *blk_all = blk_idx < c->jk_cap ? c->blk_all + blk_idx * c->n_est : nullptr;
         for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
             const int64_t cw = std::min(c->chunk, W - c0);
             // ln|Psi| is not an estimator input: the dense kernel may start
@@ -701,7 +713,8 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
             HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
             EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
                       nullptr,  nullptr,    nullptr,    A3,         Mn};
-            HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, st));
+            HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, blk_all,
+                                          st));
         }
         if (blk_idx < MAX_BLOCKS) {
             if ((int64_t)c->block_counts.size() <= blk_idx) c->block_counts.resize(blk_idx + 1, 0);
@@ -772,6 +785,7 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
         HIP_OK(c, hipMemsetAsync(c->shift_set, 0, 4, st));
         HIP_OK(c, hipMemsetAsync(c->status, 0, 4, st));
         HIP_OK(c, hipMemsetAsync(c->blocks, 0, MAX_BLOCKS * 8, st));
+        if (c->jk_cap) HIP_OK(c, hipMemsetAsync(c->blk_all, 0, c->jk_cap * n * 8, st));
         HIP_OK(c, hipStreamSynchronize(st));
         c->block_counts.clear();
         c->n_samples = 0;
@@ -779,6 +793,25 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
     }
     if (status & vmcx::STATUS_SINGULAR) return c->fail(VMC_ESINGULAR, "a Slater matrix had a zero pivot");
     if (status & vmcx::STATUS_NONFINITE) return c->fail(VMC_ENONFINITE, "non-finite local energy or ln|Psi|");
+    return VMC_OK;
+}
+
+int vmc_jackknife(vmc_ctx *c, double *E_jk, double *F_jk, double *dEdC_jk, int64_t *n_blocks, void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (!c->jk_cap) return c->fail(VMC_EINVAL, "vmc_jackknife: the context keeps no block sums (jackknife_blocks = 0)");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t nb = std::min<int64_t>(c->sweeps_since_reset / c->opt.block_sweeps, c->jk_cap);
+    nb = std::min<int64_t>(nb, (int64_t)c->block_counts.size());
+    if (n_blocks) *n_blocks = nb;
+    if (!E_jk && !F_jk && !dEdC_jk) return VMC_OK;
+    if (nb < 2) return c->fail(VMC_EINVAL, "vmc_jackknife: %lld complete blocks (need 2)", (long long)nb);
+    c->jk_cnt_host.assign(c->block_counts.begin(), c->block_counts.begin() + nb);
+    HIP_OK(c, hipMemcpyAsync(c->jk_cnt, c->jk_cnt_host.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_OK(c, vmcx::launch_jackknife(c->blk_all, c->jk_cnt, (int)nb, c->n_est, 3 * c->A, (int64_t)c->M * c->n_occ,
+                                     c->shift, E_jk, F_jk, dEdC_jk, st));
+    HIP_OK(c, hipStreamSynchronize(st));
     return VMC_OK;
 }
 
@@ -848,7 +881,8 @@ int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
         if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, C, R, R0, warp, 1, o, st))) return rc;
         EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, nullptr,
                   gEL + c0, gPsi + c0,  gJac + c0,  A3,         Mn};
-        HIP_OK(c, vmcx::launch_reduce(a, 1, nv, cw, c->partial, MAX_SEG, c->vjp_acc, c->vjp_comp, nullptr, st));
+        HIP_OK(c, vmcx::launch_reduce(a, 1, nv, cw, c->partial, MAX_SEG, c->vjp_acc, c->vjp_comp, nullptr, nullptr,
+                                      st));
     }
     HIP_OK(c, vmcx::launch_combine(c->vjp_acc, c->vjp_comp, nv, c->vjp_out, st));
     HIP_OK(c, hipMemcpyAsync(dC, c->vjp_out, Mn * 8, hipMemcpyDeviceToDevice, st));
@@ -856,28 +890,15 @@ int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
     return VMC_OK;
 }
 
-int zvector_solve(const double *H, int64_t d, const double *b, double *z, double rtol, int32_t maxit,
-                  uint32_t flags, int32_t *iters, void *stream) {
-    if (iters) *iters = 0;
-    if (!H || !b || !z || d < 1 || !(rtol > 0.0) || maxit < 1 || (flags & ~(uint32_t)ZVECTOR_JACOBI))
-        return VMC_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
+// One CG solve (device state; batches of iterations between host reads).
+static int cg_one(const double *H, int64_t d, const double *b, double *z, double rtol, int32_t maxit, uint32_t flags,
+                  int32_t *iters, double *work, hipStream_t st) {
     const int nb = vmcx::cg_matvec_blocks(d);
-    // r, p, Hp, dinv, the matvec partials, then the iteration state
-    const size_t nwork = 4 * (size_t)d + (size_t)nb;
-    const size_t bytes = nwork * sizeof(double) + sizeof(vmcx::CgState);
-    void *work = nullptr;
-    if (hipMalloc(&work, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return VMC_ENOMEM;
-    }
-    double *r = (double *)work, *p = r + d, *Hp = p + d, *dinv = Hp + d, *part = dinv + d;
+    double *r = work, *p = r + d, *Hp = p + d, *dinv = Hp + d, *part = dinv + d;
     vmcx::CgState *cs = (vmcx::CgState *)(part + nb);
     vmcx::CgState hs{};
-    bool ok = vmcx::launch_cg_setup(H, b, d, (flags & ZVECTOR_JACOBI) ? 1 : 0, rtol, maxit, z, r, p, dinv, cs,
+    bool ok = vmcx::launch_cg_setup(H, b, d, 1, (flags & ZVECTOR_JACOBI) ? 1 : 0, rtol, maxit, z, r, p, dinv, cs,
                                     st) == hipSuccess;
-    // batches of iterations between reads of the device state (iterations
-    // queued after the end return at once)
     const int batch = 8;
     while (ok) {
         ok = hipMemcpyAsync(&hs, cs, sizeof(hs), hipMemcpyDeviceToHost, st) == hipSuccess &&
@@ -886,29 +907,120 @@ int zvector_solve(const double *H, int64_t d, const double *b, double *z, double
         for (int k = 0; ok && k < batch; ++k)
             ok = vmcx::launch_cg_iteration(H, d, z, r, p, Hp, dinv, part, cs, st) == hipSuccess;
     }
-    if (!ok) (void)hipGetLastError();
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(work);
-    if (!ok) return VMC_EDEVICE;
+    if (!ok) {
+        (void)hipGetLastError();
+        return VMC_EDEVICE;
+    }
     if (iters) *iters = hs.it;
     if (hs.done == vmcx::CG_NONFINITE) return VMC_ENONFINITE;
     return hs.done == vmcx::CG_CONVERGED ? VMC_OK : VMC_ENOTCONV;
 }
 
-int zvector_rhs(const double *Cv, int64_t n_ao, int64_t n_virt, int64_t n_occ, const double *dEdC, double *b,
-                void *stream) {
-    if (!Cv || !dEdC || !b || n_ao < 1 || n_virt < 1 || n_occ < 1) return VMC_EINVAL;
-    if (vmcx::launch_zv_rhs(Cv, dEdC, n_ao, n_virt, n_occ, b, (hipStream_t)stream) != hipSuccess) {
+// Up to 64 CG solves in lockstep, every read of H shared by all of them; each
+// right-hand side keeps its own step lengths and stopping test.
+static int cg_batch(const double *H, int64_t d, int nrhs, const double *b, double *z, double rtol, int32_t maxit,
+                    uint32_t flags, int32_t *iters, hipStream_t st) {
+    const size_t vec = (size_t)nrhs * d;
+    const size_t n = 3 * vec + (size_t)vmcx::cgb_ksplit(d) * vec;
+    void *work = nullptr;
+    if (hipMalloc(&work, n * sizeof(double) + nrhs * sizeof(vmcx::CgState)) != hipSuccess) {
+        (void)hipGetLastError();
+        return VMC_ENOMEM;
+    }
+    double *R = (double *)work, *P = R + vec, *Dinv = P + vec, *HPp = Dinv + vec;
+    vmcx::CgState *cs = (vmcx::CgState *)(HPp + (size_t)vmcx::cgb_ksplit(d) * vec);
+    std::vector<vmcx::CgState> hs(nrhs);
+    bool ok = vmcx::launch_cg_setup(H, b, d, nrhs, (flags & ZVECTOR_JACOBI) ? 1 : 0, rtol, maxit, z, R, P, Dinv, cs,
+                                    st) == hipSuccess;
+    const int batch = 8;
+    while (ok) {
+        ok = hipMemcpyAsync(hs.data(), cs, nrhs * sizeof(vmcx::CgState), hipMemcpyDeviceToHost, st) == hipSuccess &&
+             hipStreamSynchronize(st) == hipSuccess;
+        bool all = true;
+        for (const auto &h : hs) all = all && h.done;
+        if (!ok || all) break;
+        for (int k = 0; ok && k < batch; ++k)
+            ok = vmcx::launch_cgb_iteration(H, d, nrhs, z, R, P, HPp, Dinv, cs, st) == hipSuccess;
+    }
+    if (!ok) (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(work);
+    if (!ok) return VMC_EDEVICE;
+    int status = VMC_OK;
+    for (int k = 0; k < nrhs; ++k) {
+        if (iters) iters[k] = hs[k].it;
+        const int rc = hs[k].done == vmcx::CG_NONFINITE ? VMC_ENONFINITE
+                       : hs[k].done == vmcx::CG_CONVERGED ? VMC_OK
+                                                          : VMC_ENOTCONV;
+        if (rc != VMC_OK && status == VMC_OK) status = rc;
+    }
+    return status;
+}
+
+int zvector_solve(const double *H, int64_t d, int64_t n_rhs, const double *b, double *z, double rtol, int32_t maxit,
+                  uint32_t flags, int32_t *iters, void *stream) {
+    if (!H || !b || !z || d < 1 || n_rhs < 1 || !(rtol > 0.0) || maxit < 1 || (flags & ~(uint32_t)ZVECTOR_JACOBI))
+        return VMC_EINVAL;
+    if (iters)
+        for (int64_t k = 0; k < n_rhs; ++k) iters[k] = 0;
+    hipStream_t st = (hipStream_t)stream;
+    if (n_rhs > 1) {
+        // groups of up to 64 right-hand sides share the reads of H
+        int status = VMC_OK;
+        for (int64_t k0 = 0; k0 < n_rhs; k0 += 64) {
+            const int g = (int)std::min<int64_t>(64, n_rhs - k0);
+            const int rc = cg_batch(H, d, g, b + k0 * d, z + k0 * d, rtol, maxit, flags, iters ? iters + k0 : nullptr,
+                                    st);
+            if (rc != VMC_OK && status == VMC_OK) status = rc;
+            if (rc == VMC_EDEVICE || rc == VMC_ENOMEM) break;
+        }
+        return status;
+    }
+    // r, p, Hp, dinv, the matvec partials, then the iteration state
+    const size_t nwork = 4 * (size_t)d + (size_t)vmcx::cg_matvec_blocks(d);
+    void *work = nullptr;
+    if (hipMalloc(&work, nwork * sizeof(double) + sizeof(vmcx::CgState)) != hipSuccess) {
+        (void)hipGetLastError();
+        return VMC_ENOMEM;
+    }
+    int status = VMC_OK;
+    for (int64_t k = 0; k < n_rhs; ++k) {
+        const int rc = cg_one(H, d, b + k * d, z + k * d, rtol, maxit, flags, iters ? iters + k : nullptr,
+                              (double *)work, st);
+        // the first failure decides the status; a device error stops at once
+        if (rc != VMC_OK && status == VMC_OK) status = rc;
+        if (rc == VMC_EDEVICE) break;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(work);
+    return status;
+}
+
+int zvector_rhs(const double *Cv, int64_t n_ao, int64_t n_virt, int64_t n_occ, int64_t n_batch, const double *dEdC,
+                double *b, void *stream) {
+    if (!Cv || !dEdC || !b || n_ao < 1 || n_virt < 1 || n_occ < 1 || n_batch < 1 || n_batch > 65535)
+        return VMC_EINVAL;
+    if (vmcx::launch_zv_rhs(Cv, dEdC, n_ao, n_virt, n_occ, n_batch, b, (hipStream_t)stream) != hipSuccess) {
         (void)hipGetLastError();
         return VMC_EDEVICE;
     }
     return VMC_OK;
 }
 
-int zvector_backmap(const double *Cv, int64_t n_ao, int64_t n_virt, int64_t n_occ, const double *z, double *Z,
-                    void *stream) {
-    if (!Cv || !z || !Z || n_ao < 1 || n_virt < 1 || n_occ < 1) return VMC_EINVAL;
-    if (vmcx::launch_zv_backmap(Cv, z, n_ao, n_virt, n_occ, Z, (hipStream_t)stream) != hipSuccess) {
+int zvector_backmap(const double *Cv, int64_t n_ao, int64_t n_virt, int64_t n_occ, int64_t n_batch, const double *z,
+                    double *Z, void *stream) {
+    if (!Cv || !z || !Z || n_ao < 1 || n_virt < 1 || n_occ < 1 || n_batch < 1 || n_batch > 65535)
+        return VMC_EINVAL;
+    if (vmcx::launch_zv_backmap(Cv, z, n_ao, n_virt, n_occ, n_batch, Z, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return VMC_EDEVICE;
+    }
+    return VMC_OK;
+}
+
+int zvector_jackknife(const double *x_jk, int64_t n_blocks, int64_t len, double *mean, double *sigma, void *stream) {
+    if (!x_jk || n_blocks < 2 || len < 1 || (!mean && !sigma)) return VMC_EINVAL;
+    if (vmcx::launch_jackknife_stats(x_jk, n_blocks, len, mean, sigma, (hipStream_t)stream) != hipSuccess) {
         (void)hipGetLastError();
         return VMC_EDEVICE;
     }

@@ -117,9 +117,11 @@ __host__ __device__ inline void shell_radial(const BasisDev &B, int s, double rh
     const int p0 = B.shell_p0[s], np = B.shell_np[s];
     R0 = R1 = R2 = R3 = T(0);
     for (int k = 0; k < np; ++k) {
-        const double ad = B.prim_exp[p0 + k];
-        const T al = (T)ad;
-        const T e = (T)B.prim_cp[p0 + k] * exp_neg(ad, rho, T(0));
+        // the exponent in the arithmetic type, used alike in the exponential
+        // and in the derivative factors, so that value and derivatives belong
+        // to one function
+        const T al = (T)B.prim_exp[p0 + k];
+        const T e = (T)B.prim_cp[p0 + k] * exp_neg((double)al, rho, T(0));
         R0 += e;
         if (NC > 1) {
             R1 -= al * e;

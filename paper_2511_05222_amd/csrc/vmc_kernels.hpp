@@ -32,8 +32,16 @@ struct EstArgs {
     int64_t A3, Mn;
 };
 
+// blk: the running block's energy sum (element 0 only); blk_all: its sums of
+// every element (both nullable)
 hipError_t launch_reduce(const EstArgs &a, int mode, int64_t n_out, int64_t W, double *partial,
-                         int64_t max_seg, double *acc, double *comp, double *blk, hipStream_t st);
+                         int64_t max_seg, double *acc, double *comp, double *blk, double *blk_all, hipStream_t st);
+// leave-one-block-out replicas E_jk[nb], F_jk[nb][A3], dC_jk[nb][Mn] (nullable)
+// from per-block sums bs[nb][n_est] and per-block sample counts cnt[nb]
+hipError_t launch_jackknife(const double *bs, const double *cnt, int nb, int64_t n_est, int64_t A3, int64_t Mn,
+                            const double *shift, double *E_jk, double *F_jk, double *dC_jk, hipStream_t st);
+hipError_t launch_jackknife_stats(const double *x, int64_t nb, int64_t len, double *mean, double *sigma,
+                                  hipStream_t st);
 hipError_t launch_set_shift(const double *EL, int64_t W, double *shift, int *shift_set, hipStream_t st);
 hipError_t launch_eval_weights(const double *EL, const double *lnpsi, const double *lnjac,
                                const double *lnpsi0, int64_t W, double *wnorm, double *Ehat, hipStream_t st);
@@ -51,13 +59,19 @@ struct CgState {
     int done;      // 0 while running, else CG_*
 };
 int cg_matvec_blocks(int64_t d);   // partial sums the iteration writes
-hipError_t launch_cg_setup(const double *H, const double *b, int64_t d, int jacobi, double rtol, int maxit,
-                           double *x, double *r, double *p, double *dinv, CgState *cs, hipStream_t st);
+// nrhs right-hand sides, vectors stored one after another (states cs[nrhs])
+hipError_t launch_cg_setup(const double *H, const double *b, int64_t d, int nrhs, int jacobi, double rtol,
+                           int maxit, double *x, double *r, double *p, double *dinv, CgState *cs, hipStream_t st);
+// several right-hand sides (2..64) sharing the reads of H; HPp holds
+// cgb_ksplit(d) * nrhs * d doubles of partial products
+int cgb_ksplit(int64_t d);
+hipError_t launch_cgb_iteration(const double *H, int64_t d, int nrhs, double *X, double *R, double *P, double *HPp,
+                                const double *dinv, CgState *cs, hipStream_t st);
 hipError_t launch_cg_iteration(const double *H, int64_t d, double *x, double *r, double *p, double *Hp,
                                const double *dinv, double *part, CgState *cs, hipStream_t st);
-hipError_t launch_zv_rhs(const double *Cv, const double *G, int64_t M, int64_t nv, int64_t n, double *b,
-                         hipStream_t st);
-hipError_t launch_zv_backmap(const double *Cv, const double *z, int64_t M, int64_t nv, int64_t n, double *Z,
-                             hipStream_t st);
+hipError_t launch_zv_rhs(const double *Cv, const double *G, int64_t M, int64_t nv, int64_t n, int64_t nbat,
+                         double *b, hipStream_t st);
+hipError_t launch_zv_backmap(const double *Cv, const double *z, int64_t M, int64_t nv, int64_t n, int64_t nbat,
+                             double *Z, hipStream_t st);
 
 }  // namespace vmcx

@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "vmc_kernels.hpp"
+#include "vmc_mfma.hpp"
 
 namespace vmcx {
 
@@ -75,7 +76,7 @@ __global__ void k_partial_sums(EstArgs a, int mode, int64_t n_out, int64_t W, in
 // acc[o] (+ comp[o]) += sum_seg partial[seg][o]  (Neumaier, fixed order);
 // if blk != nullptr, element 0's chunk sum is also added to *blk.
 __global__ void k_accumulate(const double *partial, int64_t n_out, int64_t n_seg, double *acc,
-                             double *comp, double *blk) {
+                             double *comp, double *blk, double *blk_all) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n_out) return;
     double s = 0.0, c = 0.0;
@@ -91,6 +92,57 @@ __global__ void k_accumulate(const double *partial, int64_t n_out, int64_t n_seg
     comp[o] += (fabs(a0) >= fabs(x)) ? ((a0 - t) + x) : ((x - t) + a0);
     acc[o] = t;
     if (o == 0 && blk != nullptr) blk[0] += x;
+    if (blk_all != nullptr) blk_all[o] += x;
+}
+
+// Leave-one-block-out (jackknife) replicas of the estimators over nb complete
+// blocks with per-block sums bs[b][*] and counts cnt[b]:
+//   S^(-b) = sum_{b' != b} S_b' (formed as the fixed-order total minus S_b),
+//   dE/dC^(-b) = 2 (S_EO/K - (S_E/K)(S_O/K)),  F^(-b) = -S_H/K - 2 (S_EP/K - (S_E/K)(S_P/K)),
+//   E^(-b) = s + S_E/K,  K = K^(-b).
+__global__ void k_jackknife(const double *__restrict__ bs, const double *__restrict__ cnt, int nb, int64_t n_est,
+                            int64_t A3, int64_t Mn, const double *__restrict__ shift, double *E_jk, double *F_jk,
+                            double *dC_jk) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // output element of one replica
+    const int b = blockIdx.y;
+    const int64_t n_out = 1 + A3 + Mn;
+    if (o >= n_out) return;
+    double Kt = 0.0;
+    for (int q = 0; q < nb; ++q) Kt += cnt[q];
+    const double K = Kt - cnt[b];
+    auto loo = [&](int64_t i) {
+        double t = 0.0;
+        for (int q = 0; q < nb; ++q) t += bs[(size_t)q * n_est + i];
+        return (t - bs[(size_t)b * n_est + i]) / K;
+    };
+    const double vE = loo(0);
+    if (o == 0) {
+        if (E_jk) E_jk[b] = shift[0] + vE;
+    } else if (o <= A3) {
+        const int64_t i = o - 1;
+        if (F_jk) F_jk[(size_t)b * A3 + i] = -loo(2 + i) - 2.0 * (loo(2 + 2 * A3 + i) - vE * loo(2 + A3 + i));
+    } else {
+        const int64_t i = o - 1 - A3;
+        if (dC_jk) dC_jk[(size_t)b * Mn + i] = 2.0 * (loo(2 + 3 * A3 + Mn + i) - vE * loo(2 + 3 * A3 + i));
+    }
+}
+
+// Jackknife mean and standard error of nb replicas of len values:
+//   mean = sum_b x_b / nb,  sigma = sqrt((nb - 1)/nb * sum_b (x_b - mean)^2)
+__global__ void k_jackknife_stats(const double *__restrict__ x, int64_t nb, int64_t len, double *mean,
+                                  double *sigma) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double m = 0.0;
+    for (int64_t b = 0; b < nb; ++b) m += x[b * len + i];
+    m /= (double)nb;
+    double v = 0.0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const double d = x[b * len + i] - m;
+        v += d * d;
+    }
+    if (mean) mean[i] = m;
+    if (sigma) sigma[i] = sqrt((double)(nb - 1) / (double)nb * v);
 }
 
 // shift s = mean E_L of the first measured chunk (set once)
@@ -190,6 +242,12 @@ __device__ inline void block_sum2(double &a, double &b, double *red) {
 __global__ __launch_bounds__(CG_BS) void k_cg_setup(const double *__restrict__ H, const double *__restrict__ b,
                                                     int64_t d, int jacobi, double rtol, int maxit, double *x,
                                                     double *r, double *p, double *dinv, CgState *cs) {
+    // right-hand side blockIdx.x of a batch (vectors stored one after another)
+    {
+        const int64_t o = (int64_t)blockIdx.x * d;
+        b += o, x += o, r += o, p += o, dinv += o;
+        cs += blockIdx.x;
+    }
     __shared__ double red[2 * CG_BS / 64];
     double rr = 0.0, rz = 0.0;
     for (int64_t k = threadIdx.x; k < d; k += CG_BS) {
@@ -309,10 +367,134 @@ __global__ __launch_bounds__(CG_BS) void k_cg_update(double *__restrict__ x, dou
     }
 }
 
+// ---------------------------------------------------------------------------
+// Several right-hand sides at once (e.g. jackknife replicas): every read of H
+// serves up to 64 of them.  HP = H P^T is a tall-skinny FP64 product on the
+// matrix cores: a block stages 64 rows x 32 columns of H and the 16*NRT
+// right-hand sides' 32 columns in LDS, each wavefront accumulates 16 rows x
+// 16*NRT right-hand sides, and the columns are split over ksplit blocks whose
+// partial products the update kernel adds in a fixed order.  The per-RHS
+// vector work runs one block per right-hand side.
+// ---------------------------------------------------------------------------
+constexpr int CGB_ROWS = 64;          // rows of H per block (16 per wavefront)
+constexpr int CGB_KC = 32;            // columns per LDS stage
+constexpr int CGB_LD = CGB_KC + 1;    // padded LDS row stride (doubles)
+
+template <int NRT>
+__global__ __launch_bounds__(256) void k_cgb_matvec(const double *__restrict__ H, const double *__restrict__ P,
+                                                    double *__restrict__ HPp, int64_t d, int nrhs, int ksplit,
+                                                    const CgState *cs) {
+    typedef Mfma<double> MF;
+    __shared__ double Hs[CGB_ROWS * CGB_LD];
+    __shared__ double Ps[16 * NRT * CGB_LD];
+    int running = 0;
+    for (int k = 0; k < nrhs; ++k) running |= cs[k].done == 0;
+    if (!running) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ml = lane & 15, kg = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * CGB_ROWS;
+    const int split = blockIdx.y;
+    // this block's share of the columns, in whole stages
+    const int64_t nst = (d + CGB_KC - 1) / CGB_KC;
+    const int64_t s0 = nst * split / ksplit, s1 = nst * (split + 1) / ksplit;
+    MF::acc_t acc[NRT];
+#pragma unroll
+    for (int t = 0; t < NRT; ++t) acc[t] = MF::zero();
+    for (int64_t st = s0; st < s1; ++st) {
+        const int64_t c0 = st * CGB_KC;
+        // clamped, unconditional loads (selected afterwards)
+#pragma unroll
+        for (int q = 0; q < CGB_ROWS * CGB_KC / 256; ++q) {
+            const int i = tid + 256 * q, rr = i / CGB_KC, cc = i % CGB_KC;
+            const int64_t row = r0 + rr, col = c0 + cc;
+            const double v = H[min(row, d - 1) * d + min(col, d - 1)];
+            Hs[rr * CGB_LD + cc] = (row < d && col < d) ? v : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16 * NRT * CGB_KC / 256; ++q) {
+            const int i = tid + 256 * q, kk = i / CGB_KC, cc = i % CGB_KC;
+            const int64_t col = c0 + cc;
+            const double v = P[(int64_t)min(kk, nrhs - 1) * d + min(col, d - 1)];
+            Ps[kk * CGB_LD + cc] = (kk < nrhs && col < d) ? v : 0.0;
+        }
+        __syncthreads();
+        const double *ha = Hs + (16 * wv + ml) * CGB_LD + kg;
+#pragma unroll
+        for (int ks = 0; ks < CGB_KC / 4; ++ks) {
+            const double a = ha[4 * ks];
+#pragma unroll
+            for (int t = 0; t < NRT; ++t) acc[t] = MF::fma(a, Ps[(16 * t + ml) * CGB_LD + 4 * ks + kg], acc[t]);
+        }
+        __syncthreads();
+    }
+    // D[i][j] = sum_c H[row i][c] P[rhs j][c]: register v of lane l holds row
+    // l/16 + 4v, right-hand side l%16 of tile t
+#pragma unroll
+    for (int t = 0; t < NRT; ++t) {
+        const int j = 16 * t + ml;
+        if (j >= nrhs) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + 16 * wv + kg + 4 * v;
+            if (row < d) HPp[((int64_t)split * nrhs + j) * d + row] = acc[t][v];
+        }
+    }
+}
+
+// per right-hand side k (one block each): Hp = sum of the ksplit partials;
+// alpha = rz / p.Hp; x += alpha p; r -= alpha Hp; stop test; p = dinv r + beta p
+__global__ __launch_bounds__(CG_BS) void k_cgb_update(double *__restrict__ X, double *__restrict__ R,
+                                                      double *__restrict__ P, const double *__restrict__ HPp,
+                                                      const double *__restrict__ Dinv, int64_t d, int nrhs,
+                                                      int ksplit, CgState *css) {
+    const int k = blockIdx.x;
+    CgState *cs = css + k;
+    if (cs->done) return;
+    __shared__ double red[2 * CG_BS / 64];
+    double *x = X + (int64_t)k * d, *r = R + (int64_t)k * d, *p = P + (int64_t)k * d;
+    const double *dinv = Dinv + (int64_t)k * d;
+    auto hp = [&](int64_t i) {
+        double t = 0.0;
+        for (int s = 0; s < ksplit; ++s) t += HPp[((int64_t)s * nrhs + k) * d + i];
+        return t;
+    };
+    double pHp = 0.0, unused = 0.0;
+    for (int64_t i = threadIdx.x; i < d; i += CG_BS) pHp += p[i] * hp(i);
+    block_sum2<CG_BS>(pHp, unused, red);
+    const double rz = cs->rz;
+    const double alpha = rz / pHp;
+    double rr = 0.0, rzn = 0.0;
+    for (int64_t i = threadIdx.x; i < d; i += CG_BS) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * hp(i);
+        r[i] = ri;
+        rr += ri * ri;
+        rzn += ri * (dinv[i] * ri);
+    }
+    block_sum2<CG_BS>(rr, rzn, red);
+    const int it = cs->it + 1;
+    int done = 0;
+    if (!(std::isfinite(rr) && std::isfinite(rzn))) done = CG_NONFINITE;
+    else if (rr <= cs->tol2) done = CG_CONVERGED;
+    else if (it >= cs->maxit) done = CG_MAXIT;
+    if (!done) {
+        const double beta = rzn / rz;
+        for (int64_t i = threadIdx.x; i < d; i += CG_BS) p[i] = dinv[i] * r[i] + beta * p[i];
+    }
+    __syncthreads();   // every thread has read the state
+    if (threadIdx.x == 0) {
+        cs->rz = rzn;
+        cs->it = it;
+        cs->done = done;
+    }
+}
+
 // b[a][i] = sum_mu Cv[mu][a] G[mu][i] (the virtual-occupied block of C^T G)
 __global__ void k_zv_rhs(const double *__restrict__ Cv, const double *__restrict__ G, int64_t M, int64_t nv,
                          int64_t n, double *__restrict__ b) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    G += (size_t)blockIdx.y * M * n;   // batch item
+    b += (size_t)blockIdx.y * nv * n;
     if (o >= nv * n) return;
     const int64_t a = o / n, i = o % n;
     double s = 0.0;
@@ -324,6 +506,8 @@ __global__ void k_zv_rhs(const double *__restrict__ Cv, const double *__restrict
 __global__ void k_zv_backmap(const double *__restrict__ Cv, const double *__restrict__ z, int64_t M, int64_t nv,
                              int64_t n, double *__restrict__ Z) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    z += (size_t)blockIdx.y * nv * n;   // batch item
+    Z += (size_t)blockIdx.y * M * n;
     if (o >= M * n) return;
     const int64_t mu = o / n, i = o % n;
     double s = 0.0;
@@ -335,14 +519,29 @@ __global__ void k_zv_backmap(const double *__restrict__ Cv, const double *__rest
 // host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_reduce(const EstArgs &a, int mode, int64_t n_out, int64_t W, double *partial,
-                         int64_t max_seg, double *acc, double *comp, double *blk, hipStream_t st) {
+                         int64_t max_seg, double *acc, double *comp, double *blk, double *blk_all, hipStream_t st) {
     int64_t n_seg = std::min<int64_t>(max_seg, std::max<int64_t>(1, (W + 63) / 64));
     const int64_t seg_len = (W + n_seg - 1) / n_seg;
     n_seg = (W + seg_len - 1) / seg_len;
     dim3 g1((unsigned)((n_out + 255) / 256), (unsigned)n_seg);
     hipLaunchKernelGGL(k_partial_sums, g1, dim3(256), 0, st, a, mode, n_out, W, seg_len, partial);
     hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, partial, n_out,
-                       n_seg, acc, comp, blk);
+                       n_seg, acc, comp, blk, blk_all);
+    return hipGetLastError();
+}
+
+hipError_t launch_jackknife(const double *bs, const double *cnt, int nb, int64_t n_est, int64_t A3, int64_t Mn,
+                            const double *shift, double *E_jk, double *F_jk, double *dC_jk, hipStream_t st) {
+    const int64_t n_out = 1 + A3 + Mn;
+    hipLaunchKernelGGL(k_jackknife, dim3((unsigned)((n_out + 255) / 256), (unsigned)nb), dim3(256), 0, st, bs, cnt,
+                       nb, n_est, A3, Mn, shift, E_jk, F_jk, dC_jk);
+    return hipGetLastError();
+}
+
+hipError_t launch_jackknife_stats(const double *x, int64_t nb, int64_t len, double *mean, double *sigma,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(k_jackknife_stats, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, x, nb, len, mean,
+                       sigma);
     return hipGetLastError();
 }
 
@@ -372,9 +571,30 @@ hipError_t launch_combine(const double *acc, const double *comp, int64_t n, doub
 
 int cg_matvec_blocks(int64_t d) { return (int)((d + CG_ROWS - 1) / CG_ROWS); }
 
-hipError_t launch_cg_setup(const double *H, const double *b, int64_t d, int jacobi, double rtol, int maxit,
-                           double *x, double *r, double *p, double *dinv, CgState *cs, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(CG_BS), 0, st, H, b, d, jacobi, rtol, maxit, x, r, p, dinv, cs);
+hipError_t launch_cg_setup(const double *H, const double *b, int64_t d, int nrhs, int jacobi, double rtol,
+                           int maxit, double *x, double *r, double *p, double *dinv, CgState *cs, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_setup, dim3((unsigned)nrhs), dim3(CG_BS), 0, st, H, b, d, jacobi, rtol, maxit, x, r, p,
+                       dinv, cs);
+    return hipGetLastError();
+}
+
+int cgb_ksplit(int64_t d) {
+    const int64_t rb = (d + CGB_ROWS - 1) / CGB_ROWS, nst = (d + CGB_KC - 1) / CGB_KC;
+    int64_t ks = (512 + rb - 1) / rb;   // about 512 blocks in all
+    return (int)std::max<int64_t>(1, std::min<int64_t>({ks, 16, nst}));
+}
+
+hipError_t launch_cgb_iteration(const double *H, int64_t d, int nrhs, double *X, double *R, double *P, double *HPp,
+                                const double *dinv, CgState *cs, hipStream_t st) {
+    const int ks = cgb_ksplit(d);
+    const dim3 g((unsigned)((d + CGB_ROWS - 1) / CGB_ROWS), (unsigned)ks);
+    switch ((nrhs + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_cgb_matvec<1>, g, dim3(256), 0, st, H, P, HPp, d, nrhs, ks, cs); break;
+        case 2: hipLaunchKernelGGL(k_cgb_matvec<2>, g, dim3(256), 0, st, H, P, HPp, d, nrhs, ks, cs); break;
+        case 3: hipLaunchKernelGGL(k_cgb_matvec<3>, g, dim3(256), 0, st, H, P, HPp, d, nrhs, ks, cs); break;
+        default: hipLaunchKernelGGL(k_cgb_matvec<4>, g, dim3(256), 0, st, H, P, HPp, d, nrhs, ks, cs); break;
+    }
+    hipLaunchKernelGGL(k_cgb_update, dim3((unsigned)nrhs), dim3(CG_BS), 0, st, X, R, P, HPp, dinv, d, nrhs, ks, cs);
     return hipGetLastError();
 }
 
@@ -386,15 +606,17 @@ hipError_t launch_cg_iteration(const double *H, int64_t d, double *x, double *r,
     return hipGetLastError();
 }
 
-hipError_t launch_zv_rhs(const double *Cv, const double *G, int64_t M, int64_t nv, int64_t n, double *b,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_zv_rhs, dim3((unsigned)((nv * n + 255) / 256)), dim3(256), 0, st, Cv, G, M, nv, n, b);
+hipError_t launch_zv_rhs(const double *Cv, const double *G, int64_t M, int64_t nv, int64_t n, int64_t nbat,
+                         double *b, hipStream_t st) {
+    hipLaunchKernelGGL(k_zv_rhs, dim3((unsigned)((nv * n + 255) / 256), (unsigned)nbat), dim3(256), 0, st, Cv, G, M,
+                       nv, n, b);
     return hipGetLastError();
 }
 
-hipError_t launch_zv_backmap(const double *Cv, const double *z, int64_t M, int64_t nv, int64_t n, double *Z,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_zv_backmap, dim3((unsigned)((M * n + 255) / 256)), dim3(256), 0, st, Cv, z, M, nv, n, Z);
+hipError_t launch_zv_backmap(const double *Cv, const double *z, int64_t M, int64_t nv, int64_t n, int64_t nbat,
+                             double *Z, hipStream_t st) {
+    hipLaunchKernelGGL(k_zv_backmap, dim3((unsigned)((M * n + 255) / 256), (unsigned)nbat), dim3(256), 0, st, Cv, z,
+                       M, nv, n, Z);
     return hipGetLastError();
 }
 

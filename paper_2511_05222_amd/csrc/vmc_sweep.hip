@@ -62,7 +62,14 @@ __device__ inline void shell_values_lds(const SweepBasisLds &B, int s, double rx
     const T rho = x * x + y * y + z * z;
     const T *pe = (const T *)B.pexp + p0, *pc = (const T *)B.pcp + p0;
     T r0 = T(0);
-    for (int k = 0; k < np; ++k) r0 += pc[k] * exp(-pe[k] * rho);
+    // (FP32, ratios only: the hardware exponential, relative error of order
+    // |a rho| 2^-23, negligible on the terms that are not already tiny)
+    for (int k = 0; k < np; ++k) {
+        if constexpr (sizeof(T) == sizeof(float))
+            r0 += pc[k] * __expf(-pe[k] * rho);
+        else
+            r0 += pc[k] * exp(-pe[k] * rho);
+    }
     T *o = psi + mu0;
     if (l == 0) {
         o[0] = r0;
@@ -97,6 +104,49 @@ struct Vec16<double> {
     static constexpr int W = 2;
     __device__ static double sum(type v) { return v.x + v.y; }
 };
+
+// Sum over the pairs (e, k) of u(|r' - r_k|) - u(|r_e - r_k|), the lane's k
+// being lane and lane + 64, reduced over the wavefront.  FP64: exact sqrt and
+// division.  FP32 (the mixed sweep, where it only enters the acceptance
+// ratio): differences of FP64 positions rounded to FP32, hardware square root
+// and reciprocal (about one ulp each), so the sum carries a relative error of
+// order 1e-7, far below what moves a Metropolis decision.
+template <typename T>
+__device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, double rx, double ry, double rz,
+                                       double ex, double ey, double ez, const double *px, const double *py,
+                                       const double *pz) {
+    double dj;
+    if constexpr (sizeof(T) == sizeof(float)) {
+        const float a = (float)S.ee_a, F = (float)S.ee_F;
+        float d = 0.0f;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int k = lane + 64 * hh;
+            const float ax = (float)(rx - px[hh]), ay = (float)(ry - py[hh]), az = (float)(rz - pz[hh]);
+            const float bx = (float)(ex - px[hh]), by = (float)(ey - py[hh]), bz = (float)(ez - pz[hh]);
+            const float ra = __builtin_amdgcn_sqrtf(ax * ax + ay * ay + az * az);
+            const float rb = __builtin_amdgcn_sqrtf(bx * bx + by * by + bz * bz);
+            const float t = a * ra * __builtin_amdgcn_rcpf(1.0f + F * ra) - a * rb * __builtin_amdgcn_rcpf(1.0f + F * rb);
+            d += (k < N && k != e) ? t : 0.0f;
+        }
+        dj = (double)d;
+    } else {
+        dj = 0.0;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int k = lane + 64 * hh;
+            if (k < N && k != e) {
+                const double ax = rx - px[hh], ay = ry - py[hh], az = rz - pz[hh];
+                const double bx = ex - px[hh], by = ey - py[hh], bz = ez - pz[hh];
+                dj += pade_u(sqrt(ax * ax + ay * ay + az * az), S.ee_a, S.ee_F) -
+                      pade_u(sqrt(bx * bx + by * by + bz * bz), S.ee_a, S.ee_F);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dj += __shfl_xor(dj, o, 64);
+    return dj;
+}
 
 // FP32 with KN <= 48 fits three wavefronts per SIMD (spilling a little in the
 // FP64 rebuild); the rest runs two.
@@ -206,20 +256,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         const double ez = readlane_d(h ? pz[1] : pz[0], src);
         const double rx = ex + sigma * z0, ry = ey + sigma * z1, rz = ez + sigma * z2;
         for (int s = lane; s < NS; s += 64) shell_values_lds<T>(B, s, rx, ry, rz, psi);
-        // Jastrow difference over the pairs (e, k), k held by this lane
-        double dj = 0.0;
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            const int k = lane + 64 * hh;
-            if (k < N && k != e) {
-                const double ax = rx - px[hh], ay = ry - py[hh], az = rz - pz[hh];
-                const double bx = ex - px[hh], by = ey - py[hh], bz = ez - pz[hh];
-                dj += pade_u(sqrt(ax * ax + ay * ay + az * az), S.ee_a, S.ee_F) -
-                      pade_u(sqrt(bx * bx + by * by + bz * bz), S.ee_a, S.ee_F);
-            }
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) dj += __shfl_xor(dj, o, 64);
+        // Jastrow difference over the pairs (e, k), k held by this lane (in
+        // the arithmetic type: it only enters the acceptance ratio)
+        double dj = jastrow_delta<T>(S, N, e, lane, rx, ry, rz, ex, ey, ez, px, py, pz);
         wave_sync_s();
         // phi_i(r') = sum_mu psi_mu C[mu][i]; lane group lg sums its AO range
         T ph = T(0);

@@ -26,8 +26,9 @@ VMC_SWEEP_MEASURE = 1
 VMC_ACCUM_RESET = 1
 
 EXPORTED = ["vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
-            "vmc_adjoint", "zvector_solve", "zvector_rhs", "zvector_backmap", "vmc_staging_walkers", "vmc_free",
-            "vmc_last_error", "vmc_init_error", "vmc_strerror", "vmc_profile", "vmc_profile_read"]
+            "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap", "zvector_jackknife",
+            "vmc_staging_walkers", "vmc_free", "vmc_last_error", "vmc_init_error", "vmc_strerror", "vmc_profile",
+            "vmc_profile_read"]
 
 
 class VmcError(RuntimeError):
@@ -58,7 +59,7 @@ class _Jastrow(ct.Structure):
 class _Options(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("refresh_period", ct.c_int32), ("block_sweeps", ct.c_int32),
                 ("max_walkers", ct.c_int32), ("staging_walkers", ct.c_int32), ("step_sigma", ct.c_double),
-                ("promote_fraction", ct.c_double)]
+                ("promote_fraction", ct.c_double), ("jackknife_blocks", ct.c_int32)]
 
 
 class _WalkerOut(ct.Structure):
@@ -85,9 +86,11 @@ def lib():
     L.vmc_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_energy_cotangents.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-    L.zvector_solve.argtypes = [vp, i64, vp, vp, dbl, i32, ct.c_uint32, ct.POINTER(i32), vp]
-    L.zvector_rhs.argtypes = [vp, i64, i64, i64, vp, vp, vp]
-    L.zvector_backmap.argtypes = [vp, i64, i64, i64, vp, vp, vp]
+    L.vmc_jackknife.argtypes = [vp, vp, vp, vp, ct.POINTER(i64), vp]
+    L.zvector_solve.argtypes = [vp, i64, i64, vp, vp, dbl, i32, u32, vp, vp]
+    L.zvector_rhs.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
+    L.zvector_backmap.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
+    L.zvector_jackknife.argtypes = [vp, i64, i64, vp, vp, vp]
     L.vmc_profile.argtypes = [vp, i32]
     L.vmc_profile_read.argtypes = [vp, i32, vp, vp, vp]
     L.vmc_staging_walkers.argtypes = [vp]
@@ -101,8 +104,8 @@ def lib():
     L.vmc_strerror.argtypes = [ct.c_int]
     L.vmc_strerror.restype = ct.c_char_p
     for name in ("vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
-                 "vmc_adjoint", "zvector_solve", "zvector_rhs", "zvector_backmap", "vmc_profile",
-                 "vmc_profile_read"):
+                 "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap",
+                 "zvector_jackknife", "vmc_profile", "vmc_profile_read"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -131,7 +134,8 @@ class Context:
     """A wavefunction on one GPU plus its estimator accumulators."""
 
     def __init__(self, mol, max_walkers, precision="fp64", refresh_period=32, block_sweeps=1,
-                 step_sigma=0.5, device=0, staging_walkers=0, promote_fraction=PROMOTE_FRACTION):
+                 step_sigma=0.5, device=0, staging_walkers=0, promote_fraction=PROMOTE_FRACTION,
+                 jackknife_blocks=0):
         L = lib()
         b = mol.basis
         self._keep = [np.ascontiguousarray(b.shell_atom, np.int32), np.ascontiguousarray(b.shell_l, np.int32),
@@ -152,7 +156,7 @@ class Context:
         if prec is None:
             raise VmcError(VMC_EINVAL, f"precision {precision!r} is not available")
         opt = _Options(prec, refresh_period, block_sweeps, int(max_walkers), int(staging_walkers), step_sigma,
-                       float(promote_fraction))
+                       float(promote_fraction), int(jackknife_blocks))
         h = ct.c_void_p()
         rc = L.vmc_init(ct.byref(basis), ct.byref(nuc), ct.byref(mo), ct.byref(jas), ct.byref(opt), device,
                         ct.byref(h))
@@ -200,6 +204,19 @@ class Context:
         self._rc(lib().vmc_accumulate(self._h, dpn(E), dpn(F), dpn(dEdC), dpn(dELdC), ct.byref(ns),
                                       VMC_ACCUM_RESET if reset else 0, _stream()))
         return dict(E=E[0], E_sigma=E[1], F_bare=F, dE_dC=dEdC, dEL_dC_mean=dELdC, n_samples=ns.value)
+
+    def jackknife(self):
+        """Leave-one-block-out replicas (E [nb], F_bare [nb][A][3], dE_dC [nb][M][n])
+        over the complete blocks since the last reset (device tensors)."""
+        import torch
+        nb = ct.c_int64(0)
+        self._rc(lib().vmc_jackknife(self._h, None, None, None, ct.byref(nb), _stream()))
+        dev = torch.device("cuda", self.device)
+        E = torch.empty((nb.value,), dtype=torch.float64, device=dev)
+        F = torch.empty((nb.value, self.A, 3), dtype=torch.float64, device=dev)
+        C = torch.empty((nb.value, self.M, self.n_occ), dtype=torch.float64, device=dev)
+        self._rc(lib().vmc_jackknife(self._h, _ptr(E), _ptr(F), _ptr(C), ct.byref(nb), _stream()))
+        return dict(E=E, F_bare=F, dE_dC=C)
 
     def profile(self, enable=True):
         """Start (clearing the totals) or stop HIP-event timing of the kernels."""
@@ -302,42 +319,71 @@ def _zv_check(rc):
 
 def zvector_solve(H, b, rtol=1e-12, maxit=1000, jacobi=False):
     """Solve H z = -b by FP64 conjugate gradients on the GPU (optionally
-    Jacobi-preconditioned); returns (z, iterations)."""
+    Jacobi-preconditioned).  b holds one right-hand side of H.shape[0]
+    values, or a batch along its first dimension (then shape (n_rhs, ...)).
+    Returns (z shaped like b, iterations: an int, or a list for a batch)."""
     import torch
-    d = b.numel()
+    d = H.shape[0]
     _check_dev(H, (d, d))
     _check_dev(b, tuple(b.shape))
+    single = b.numel() == d
+    n_rhs = 1 if single else b.shape[0]
+    if b.numel() != n_rhs * d:
+        raise ValueError(f"b has {b.numel()} values, not a multiple {n_rhs} x {d}")
     z = torch.empty_like(b)
-    it = ct.c_int32(0)
-    rc = lib().zvector_solve(_ptr(H), d, _ptr(b), _ptr(z), float(rtol), int(maxit),
-                             ZVECTOR_JACOBI if jacobi else 0, ct.byref(it), _stream())
+    it = (ct.c_int32 * n_rhs)()
+    rc = lib().zvector_solve(_ptr(H), d, n_rhs, _ptr(b), _ptr(z), float(rtol), int(maxit),
+                             ZVECTOR_JACOBI if jacobi else 0, ct.cast(it, ct.c_void_p), _stream())
     _zv_check(rc)
-    return z, it.value
+    return z, (it[0] if single else list(it))
+
+
+def _batch(x, shape2):
+    if tuple(x.shape) == tuple(shape2):
+        return 1, False
+    if x.dim() == 3 and tuple(x.shape[1:]) == tuple(shape2):
+        return x.shape[0], True
+    raise ValueError(f"expected shape {tuple(shape2)} or (batch, {shape2[0]}, {shape2[1]}), got {tuple(x.shape)}")
 
 
 def zvector_rhs(Cv, dE_dC):
-    """b = Cv^T dE/dC, shape (n_virt, n_occ): the right-hand side of the
-    Z-vector equations in the virtual-occupied rotation block."""
+    """b = Cv^T dE/dC, shape (n_virt, n_occ) (or a batch of them): the
+    right-hand side of the Z-vector equations in the virtual-occupied block."""
     import torch
     M, nv = Cv.shape
-    n = dE_dC.shape[1]
+    n = dE_dC.shape[-1]
     _check_dev(Cv, (M, nv))
-    _check_dev(dE_dC, (M, n))
-    b = torch.empty((nv, n), dtype=torch.float64, device=Cv.device)
-    _zv_check(lib().zvector_rhs(_ptr(Cv), M, nv, n, _ptr(dE_dC), _ptr(b), _stream()))
+    nb, bat = _batch(dE_dC, (M, n))
+    _check_dev(dE_dC, tuple(dE_dC.shape))
+    b = torch.empty(((nb,) if bat else ()) + (nv, n), dtype=torch.float64, device=Cv.device)
+    _zv_check(lib().zvector_rhs(_ptr(Cv), M, nv, n, nb, _ptr(dE_dC), _ptr(b), _stream()))
     return b
 
 
 def zvector_backmap(Cv, z):
-    """Z = Cv z, shape (n_ao, n_occ): the response in the AO basis."""
+    """Z = Cv z, shape (n_ao, n_occ) (or a batch): the response in the AO basis."""
     import torch
     M, nv = Cv.shape
-    n = z.shape[1]
+    n = z.shape[-1]
     _check_dev(Cv, (M, nv))
-    _check_dev(z, (nv, n))
-    Z = torch.empty((M, n), dtype=torch.float64, device=Cv.device)
-    _zv_check(lib().zvector_backmap(_ptr(Cv), M, nv, n, _ptr(z), _ptr(Z), _stream()))
+    nb, bat = _batch(z, (nv, n))
+    _check_dev(z, tuple(z.shape))
+    Z = torch.empty(((nb,) if bat else ()) + (M, n), dtype=torch.float64, device=Cv.device)
+    _zv_check(lib().zvector_backmap(_ptr(Cv), M, nv, n, nb, _ptr(z), _ptr(Z), _stream()))
     return Z
+
+
+def jackknife_stats(x_jk):
+    """Jackknife mean and standard error over the first dimension of the
+    replicas x_jk (device, FP64): sqrt((nb - 1)/nb sum (x_b - mean)^2)."""
+    import torch
+    _check_dev(x_jk, tuple(x_jk.shape))
+    nb = x_jk.shape[0]
+    ln = x_jk[0].numel()
+    mean = torch.empty(x_jk.shape[1:], dtype=torch.float64, device=x_jk.device)
+    sigma = torch.empty_like(mean)
+    _zv_check(lib().zvector_jackknife(_ptr(x_jk), nb, ln, _ptr(mean), _ptr(sigma), _stream()))
+    return mean, sigma
 
 
 def _make_energy_function():

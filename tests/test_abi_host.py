@@ -92,6 +92,8 @@ def test_zvector_rejects_bad_sizes():
     L = vmc.lib()
     import ctypes as ct
     it = ct.c_int32(0)
-    assert L.zvector_solve(None, 0, None, None, 1e-10, 10, 0, ct.byref(it), None) == vmc.VMC_EINVAL
-    assert L.zvector_rhs(None, 5, 3, 2, None, None, None) == vmc.VMC_EINVAL
-    assert L.zvector_backmap(None, 5, 3, 2, None, None, None) == vmc.VMC_EINVAL
+    assert L.zvector_solve(None, 0, 1, None, None, 1e-10, 10, 0, ct.byref(it), None) == vmc.VMC_EINVAL
+    assert L.zvector_rhs(None, 5, 3, 2, 1, None, None, None) == vmc.VMC_EINVAL
+    assert L.zvector_backmap(None, 5, 3, 2, 1, None, None, None) == vmc.VMC_EINVAL
+    assert L.zvector_jackknife(None, 4, 3, None, None, None) == vmc.VMC_EINVAL
+    assert L.vmc_jackknife(None, None, None, None, None, None) == vmc.VMC_EINVAL

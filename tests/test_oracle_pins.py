@@ -356,6 +356,37 @@ def test_zvector_cg_jacobi():
     assert np.allclose(z, z_ref, rtol=1e-10, atol=1e-10 * np.abs(z_ref).max())
 
 
+# Jackknife (the paper's resampling for the error of B and of the Z-vector
+# solution, Sec. II).  (i) For a linear statistic with equal blocks the
+# jackknife error equals the blocked standard error exactly, and the replicas
+# average to the full estimate.  (ii) The solve is linear, so the jackknife
+# variance of z equals diag(H^-1 Cov_jk(b) H^-1), the analytic propagation the
+# paper describes as the alternative route.  (iii) Every replica is an
+# estimate over a sample set, so C^T dE/dC = 0 holds for each.
+def test_jackknife_identities(mol9):
+    w = inputs.initial_walkers(mol9, 16, 5)
+    res = vmc.run(mol9, w, 6, 5, block_sweeps=2)
+    jk = res["jackknife"]
+    assert jk["E"].shape == (3,) and jk["dE_dC"].shape == (3,) + mol9.C.shape
+    m, sE = estimators.jackknife_stats(jk["E"])
+    assert abs(sE - res["E_sigma"]) < 1e-12 * res["E_sigma"]
+    assert abs(m - res["E"]) < 1e-12 * abs(res["E"])
+    for g in jk["dE_dC"]:
+        assert np.abs(mol9.C.T @ g).max() < 1e-9 * np.abs(g).max()
+    n = mol9.n_occ
+    Cv = mol9.C_full[:, n:]
+    b_jk = np.array([zvector.rhs(Cv, g).ravel() for g in jk["dE_dC"]])
+    H = inputs.seeded_spd(b_jk.shape[1], 8)
+    z_jk = np.array([zvector.cholesky_solve(H, b) for b in b_jk])
+    _, sz = estimators.jackknife_stats(z_jk)
+    bm = b_jk.mean(axis=0)
+    nb = b_jk.shape[0]
+    cov_b = (nb - 1) / nb * (b_jk - bm).T @ (b_jk - bm)
+    Hi = np.linalg.inv(H)
+    var_prop = np.einsum("ij,jk,ik->i", Hi, cov_b, Hi)
+    assert np.allclose(sz ** 2, var_prop, rtol=1e-8, atol=1e-12 * var_prop.max())
+
+
 # P16: chains depend only on (seed, walker id, sweep index): splitting a run,
 # or running a subset of walkers, gives bitwise identical positions.
 def test_resume_and_subsets(mol9):
