@@ -163,10 +163,11 @@ def main():
     w0 = torch.tensor(inputs.initial_walkers(mol, W, spec.seed), device=dev)
     ctx = vmc.Context(mol, max_walkers=W, refresh_period=32, precision=args.precision)
     if args.pmc_probe:
+        # the measurement as the timed run launches it: one sweep with
+        # measurement after two without
         walkers = w0.clone()
         ctx.sweep(walkers, 2, spec.seed, measure=False)
-        outs = ctx.measure(walkers)
-        ctx.measure_into(walkers, outs)
+        ctx.sweep(walkers, 1, spec.seed, sweep_offset=2)
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):

@@ -128,7 +128,7 @@ class Accumulator:
         blocks: replica b sums the terms of every block except b."""
         nb = len(self.block_terms)
         out = dict(E=[], F_bare=[], dE_dC=[])
-        for b in range(nb):
+        for b in range(nb if nb >= 2 else 0):   # a replica needs another block
             rest = [self.block_terms[q] for q in range(nb) if q != b]
             K = float(sum(r["K"] for r in rest))
             v = {k: sum(r[k] for r in rest) / K for k in ("E", "H", "P", "EP", "O", "EO")}

@@ -357,7 +357,8 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
         HIP_OK(c, vmcx::launch_gather_rows(pos0, lst, kc, N3, c->cp_pos0, st));
         WalkerOut oc{o.EL ? c->cp_EL : nullptr,        o.lnpsi ? c->cp_lnpsi : nullptr,  nullptr,
                      o.dEL_dR ? c->cp_dEdR : nullptr, o.dlnpsi_dR ? c->cp_dPdR : nullptr,
-                     o.dlnjac_dR ? c->cp_dJdR : nullptr, o.O ? c->cp_O : nullptr, o.G ? c->cp_G : nullptr};
+                     o.dlnjac_dR ? c->cp_dJdR : nullptr, (o.O || o.Of) ? c->cp_O : nullptr,
+                     (o.G || o.Gf) ? c->cp_G : nullptr};
         if ((rc = measure_core<double>(c, c->cp_pos, c->cp_pos0, kc, C, R, R0, warp, full, oc, c->al64, nullptr,
                                        false, KStateRef(), st)))
             return rc;
@@ -367,8 +368,10 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
                                                       {oc.G, o.G}};
         const int64_t lens[] = {1, 1, A3, A3, A3, Mn, Mn};
         for (int k = 0; k < 7; ++k)
-            if (rows[k].first && (full || k < 2))
+            if (rows[k].first && rows[k].second && (full || k < 2))
                 HIP_OK(c, vmcx::launch_scatter_rows(rows[k].first, lst, kc, lens[k], rows[k].second, st));
+        if (full && o.Of) HIP_OK(c, vmcx::launch_scatter_rows_f32(oc.O, lst, kc, Mn, o.Of, st));
+        if (full && o.Gf) HIP_OK(c, vmcx::launch_scatter_rows_f32(oc.G, lst, kc, Mn, o.Gf, st));
     }
     return VMC_OK;
 }
@@ -701,7 +704,15 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
             const int64_t cw = std::min(c->chunk, W - c0);
             // ln|Psi| is not an estimator input: the dense kernel may start
             // from the sweep's inverses
-            WalkerOut o{c->st_EL, nullptr, nullptr, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
+            // (in mixed precision O and G are staged in FP32: the estimator
+            // reduction reads them once per launch)
+            const bool f32 = c->opt.precision == VMC_MIXED;
+            WalkerOut o{c->st_EL, nullptr, nullptr, c->st_dEdR, c->st_dPdR, c->st_dJdR, f32 ? nullptr : c->st_O,
+                        f32 ? nullptr : c->st_G};
+            if (f32) {
+                o.Of = (float *)c->st_O;
+                o.Gf = (float *)c->st_G;
+            }
             const int kn = vmcx::sweep_kn(c->n_occ);
             const size_t tsz = c->opt.precision == VMC_MIXED ? sizeof(float) : sizeof(double);
             KStateRef ks;
@@ -713,6 +724,10 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
             HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
             EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
                       nullptr,  nullptr,    nullptr,    A3,         Mn};
+            if (f32) {
+                a.Of = o.Of;
+                a.Gf = o.Gf;
+            }
             HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, blk_all,
                                           st));
         }

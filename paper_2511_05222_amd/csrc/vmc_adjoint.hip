@@ -152,6 +152,8 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                     const size_t o = ((size_t)w * M + mr) * n + i;
                     if (out.O) out.O[o] = (double)accO[it][v];
                     if (out.G) out.G[o] = (double)accG[it][v];
+                    if (out.Of) out.Of[o] = (float)accO[it][v];
+                    if (out.Gf) out.Gf[o] = (float)accG[it][v];
                 }
             }
         }

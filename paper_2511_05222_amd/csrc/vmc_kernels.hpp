@@ -23,6 +23,8 @@ struct SysDev {
 
 struct WalkerOut {
     double *EL, *lnpsi, *lnjac, *dEL_dR, *dlnpsi_dR, *dlnjac_dR, *O, *G;
+    // O and G kept in FP32 instead (internal staging of the mixed path)
+    float *Of = nullptr, *Gf = nullptr;
 };
 
 struct EstArgs {
@@ -30,6 +32,8 @@ struct EstArgs {
     const double *shift;
     const double *gE, *gP, *gJ;
     int64_t A3, Mn;
+    // when set, O and G are read from these FP32 arrays
+    const float *Of = nullptr, *Gf = nullptr;
 };
 
 // blk: the running block's energy sum (element 0 only); blk_all: its sums of

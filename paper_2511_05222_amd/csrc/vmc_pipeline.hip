@@ -403,6 +403,22 @@ __global__ void k_scatter_rows(const double *__restrict__ src, const int *__rest
     dst[(int64_t)list[k] * len + j] = src[t];
 }
 
+__global__ void k_scatter_rows_f32(const double *__restrict__ src, const int *__restrict__ list, int64_t kc,
+                                   int64_t len, float *__restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kc * len) return;
+    const int64_t k = t / len, j = t - (t / len) * len;
+    dst[(int64_t)list[k] * len + j] = (float)src[t];
+}
+
+hipError_t launch_scatter_rows_f32(const double *src, const int *list, int64_t kc, int64_t len, float *dst,
+                                   hipStream_t st) {
+    const int64_t n = kc * len;
+    hipLaunchKernelGGL(k_scatter_rows_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, list, kc, len,
+                       dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_rows(const double *src, const int *list, int64_t kc, int64_t len, double *dst,
                               hipStream_t st) {
     const int64_t n = kc * len;

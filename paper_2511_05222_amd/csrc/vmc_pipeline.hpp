@@ -125,5 +125,7 @@ hipError_t launch_gather_rows(const double *src, const int *list, int64_t kc, in
                               hipStream_t st);
 hipError_t launch_scatter_rows(const double *src, const int *list, int64_t kc, int64_t len, double *dst,
                                hipStream_t st);
+hipError_t launch_scatter_rows_f32(const double *src, const int *list, int64_t kc, int64_t len, float *dst,
+                                   hipStream_t st);
 
 }  // namespace vmcx

@@ -30,6 +30,9 @@ __device__ inline double block_sum(double v, double *red) {
 // Element space of the vector-Jacobian product:
 //   [0..Mn) dC = gE G + gPsi O, [Mn..Mn+3A) dR = gE dEdR + gPsi dPdR + gJ dJdR.
 // ---------------------------------------------------------------------------
+__device__ inline double est_O(const EstArgs &a, int64_t i) { return a.Of ? (double)a.Of[i] : a.O[i]; }
+__device__ inline double est_G(const EstArgs &a, int64_t i) { return a.Gf ? (double)a.Gf[i] : a.G[i]; }
+
 __device__ inline double est_term(const EstArgs &a, int64_t o, int64_t k) {
     const double e = a.EL[k] - a.shift[0];
     const int64_t A3 = a.A3, Mn = a.Mn;
@@ -42,11 +45,11 @@ __device__ inline double est_term(const EstArgs &a, int64_t o, int64_t k) {
     o -= A3;
     if (o < A3) return e * (a.dPdR[k * A3 + o] + 0.5 * a.dJdR[k * A3 + o]);
     o -= A3;
-    if (o < Mn) return a.O[k * Mn + o];
+    if (o < Mn) return est_O(a, k * Mn + o);
     o -= Mn;
-    if (o < Mn) return e * a.O[k * Mn + o];
+    if (o < Mn) return e * est_O(a, k * Mn + o);
     o -= Mn;
-    return a.G[k * Mn + o];
+    return est_G(a, k * Mn + o);
 }
 
 __device__ inline double vjp_term(const EstArgs &a, int64_t o, int64_t k) {
@@ -56,20 +59,59 @@ __device__ inline double vjp_term(const EstArgs &a, int64_t o, int64_t k) {
     return a.gE[k] * a.dEdR[k * A3 + o] + a.gP[k] * a.dPdR[k * A3 + o] + a.gJ[k] * a.dJdR[k * A3 + o];
 }
 
-// partial[seg][o] = sum over walkers of segment seg (Neumaier, fixed order)
+// Neumaier step: s + c accumulates x
+__device__ inline void neumaier(double &s, double &c, double x) {
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+}
+
+// partial[seg][o] = sum over walkers of segment seg (Neumaier, fixed order).
+// The O and G elements (most of the element space) load PS_U walkers ahead of
+// the accumulation; the thread of an O element also forms the e O element
+// from the same load (the e O threads return at once).
+constexpr int PS_U = 8;
+
 __global__ void k_partial_sums(EstArgs a, int mode, int64_t n_out, int64_t W, int64_t seg_len,
                                double *partial) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t seg = blockIdx.y;
     if (o >= n_out) return;
     const int64_t k0 = seg * seg_len, k1 = min(W, k0 + seg_len);
-    double s = 0.0, c = 0.0;
-    for (int64_t k = k0; k < k1; ++k) {
-        const double x = mode == 0 ? est_term(a, o, k) : vjp_term(a, o, k);
-        const double t = s + x;
-        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-        s = t;
+    if (mode == 0) {
+        const int64_t oO = 2 + 3 * a.A3, Mn = a.Mn;
+        if (o >= oO + Mn && o < oO + 2 * Mn) return;
+        if (o >= oO) {
+            const bool isO = o < oO + Mn;
+            const int64_t i = isO ? o - oO : o - oO - 2 * Mn;
+            const double sh = a.shift[0];
+            double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+            int64_t k = k0;
+            for (; k + PS_U <= k1; k += PS_U) {
+                double x[PS_U], e[PS_U];
+#pragma unroll
+                for (int u = 0; u < PS_U; ++u) {
+                    x[u] = isO ? est_O(a, (k + u) * Mn + i) : est_G(a, (k + u) * Mn + i);
+                    e[u] = a.EL[k + u] - sh;
+                }
+#pragma unroll
+                for (int u = 0; u < PS_U; ++u) {
+                    neumaier(s1, c1, x[u]);
+                    if (isO) neumaier(s2, c2, e[u] * x[u]);
+                }
+            }
+            for (; k < k1; ++k) {
+                const double x = isO ? est_O(a, k * Mn + i) : est_G(a, k * Mn + i);
+                neumaier(s1, c1, x);
+                if (isO) neumaier(s2, c2, (a.EL[k] - sh) * x);
+            }
+            partial[seg * n_out + o] = s1 + c1;
+            if (isO) partial[seg * n_out + o + Mn] = s2 + c2;
+            return;
+        }
     }
+    double s = 0.0, c = 0.0;
+    for (int64_t k = k0; k < k1; ++k) neumaier(s, c, mode == 0 ? est_term(a, o, k) : vjp_term(a, o, k));
     partial[seg * n_out + o] = s + c;
 }
 
