@@ -5,7 +5,8 @@
 //
 // A block owns 64 rows (one 16-row tile per wavefront) and all n orbitals
 // (NT tiles of 16 columns).  AO tiles of whole shells (<= 16 AOs) are
-// produced in LDS by a shell-major GTO evaluation and consumed in k-steps of
+// produced in LDS by a GTO evaluation that gives each wavefront one shell at
+// all 64 rows (uniform angular momentum) and consumed in k-steps of
 // 4 AOs by 16x16x4 MFMA (FP64: v_mfma_f64_16x16x4_f64; FP32:
 // v_mfma_f32_16x16x4_f32), accumulating in the arithmetic type T.
 #include "vmc_mfma.hpp"
@@ -39,8 +40,10 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
         const int s0 = tiles.s0[tile], s1 = tiles.s1[tile], mu0 = tiles.mu0[tile], mu1 = tiles.mu1[tile];
         const int nsh = s1 - s0, nmu = mu1 - mu0;
         __syncthreads();
+        // shell-major: a wavefront evaluates one shell at its 64 rows, so the
+        // angular momentum (and the shell's tables) are uniform over it
         for (int p = tid; p < RB * nsh; p += 256) {
-            const int r = p / nsh, s = s0 + (p - (p / nsh) * nsh);
+            const int s = s0 + p / RB, r = p % RB;
             shell_eval_to<NC, T>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
                                  aot + r * RS + (S.basis.shell_mu0[s] - mu0) * NC);
         }

@@ -111,7 +111,15 @@ __global__ void k_partial_sums(EstArgs a, int mode, int64_t n_out, int64_t W, in
         }
     }
     double s = 0.0, c = 0.0;
-    for (int64_t k = k0; k < k1; ++k) neumaier(s, c, mode == 0 ? est_term(a, o, k) : vjp_term(a, o, k));
+    int64_t k = k0;
+    for (; k + PS_U <= k1; k += PS_U) {
+        double x[PS_U];
+#pragma unroll
+        for (int u = 0; u < PS_U; ++u) x[u] = mode == 0 ? est_term(a, o, k + u) : vjp_term(a, o, k + u);
+#pragma unroll
+        for (int u = 0; u < PS_U; ++u) neumaier(s, c, x[u]);
+    }
+    for (; k < k1; ++k) neumaier(s, c, mode == 0 ? est_term(a, o, k) : vjp_term(a, o, k));
     partial[seg * n_out + o] = s + c;
 }
 
