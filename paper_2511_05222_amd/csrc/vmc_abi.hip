@@ -32,7 +32,7 @@ using vmcx::WalkerOut;
 namespace {
 
 constexpr double PI = 3.14159265358979323846;
-constexpr int64_t MAX_SEG = 64;
+constexpr int64_t MAX_SEG = 256;
 constexpr int64_t MAX_BLOCKS = 1 << 16;
 constexpr size_t STAGING_BUDGET = size_t(1) << 34;   // bytes of per-walker staging (16 GiB)
 

@@ -38,11 +38,27 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
     double *dpw = (double *)(smem + L.off_d);   // [nw][N][3] per-wave dE_L/dr_e partials
     const T *ktw = mb.ktil + (size_t)w * N * n;
     const T *abw = mb.abar + (size_t)w * N * n;
-    for (int k = tid; k < RT * 16 * ldk; k += blockDim.x) {
-        const int e = k / ldk, i = k - (k / ldk) * ldk;
-        const bool on = e < N && i < n;
-        Ks[k] = on ? ktw[(size_t)e * n + i] : T(0);
-        As[k] = on ? abw[(size_t)e * n + i] : T(0);
+    // K~ and Abar into LDS, eight elements per thread in flight (clamped,
+    // unconditional loads; the padding is selected afterwards)
+    for (int k0 = tid; k0 < RT * 16 * ldk; k0 += 8 * (int)blockDim.x) {
+        T kv[8], av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * (int)blockDim.x;
+            const int e = min(k / ldk, N - 1), i = min(k - (k / ldk) * ldk, n - 1);
+            kv[u] = ktw[(size_t)e * n + i];
+            av[u] = abw[(size_t)e * n + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * (int)blockDim.x;
+            if (k < RT * 16 * ldk) {
+                const int e = k / ldk, i = k - (k / ldk) * ldk;
+                const bool on = e < N && i < n;
+                Ks[k] = on ? kv[u] : T(0);
+                As[k] = on ? av[u] : T(0);
+            }
+        }
     }
     for (int k = tid; k < 3 * N; k += blockDim.x) {
         sp[k] = mb.pos[(size_t)w * N * 3 + k];

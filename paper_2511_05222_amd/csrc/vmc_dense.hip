@@ -181,11 +181,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (red[8 + b] == 0.0) continue;
         const int nb = b ? nd : nu, off = b ? nu : 0;
         double *K = Ks + (size_t)b * KN * ldk;
-        for (int idx = tid; idx < KN * KN; idx += 256) {
+        // (all of this thread's loads first: one latency, not one per element)
+        constexpr int PER = (KN * KN + 255) / 256;
+        T av[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = min(tid + 256 * q, KN * KN - 1);
             const int e = idx / KN, i = idx - (idx / KN) * KN;
-            const double v = (double)ph[(size_t)(off + min(e, nb - 1)) * 5 * n + min(i, nb - 1)];
-            const bool in = e < nb && i < nb;
-            Xs[e * ldk + i] = in ? v : (e == i ? 1.0 : 0.0);
+            av[q] = ph[(size_t)(off + min(e, nb - 1)) * 5 * n + min(i, nb - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + 256 * q;
+            if (idx < KN * KN) {
+                const int e = idx / KN, i = idx - (idx / KN) * KN;
+                const bool in = e < nb && i < nb;
+                Xs[e * ldk + i] = in ? (double)av[q] : (e == i ? 1.0 : 0.0);
+            }
         }
         __syncthreads();
         MF::acc_t tacc[TPW];
@@ -249,19 +261,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int b = 0; b < 2; ++b) {
         const int nb = b ? nd : nu, off = b ? nu : 0;
         const double *K = Ks + (size_t)b * KN * ldk;
-        // one wavefront per electron row j of the block (rows nb..KN-1: zeros)
-        for (int j = wave; j < KN; j += 4) {
+        // one wavefront per electron row j of the block (rows nb..KN-1:
+        // zeros).  The wavefront's gradient and Laplacian rows are loaded
+        // together first (clamped, unconditional loads), so that their
+        // latency is paid once rather than once per row.
+        constexpr int JPW = (KN + 3) / 4;
+        T rG[JPW][4];
+        const int lc = min(lane, n - 1);
+#pragma unroll
+        for (int q = 0; q < JPW; ++q) {
+            const T *row = ph + (size_t)(off + min(wave + 4 * q, nb - 1)) * 5 * n + lc;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rG[q][c] = row[(c + 1) * n];
+        }
+#pragma unroll
+        for (int q = 0; q < JPW; ++q) {
+            const int j = wave + 4 * q;
             if (j >= nb) {
                 if (lane < KN) Xs[j * ldk + lane] = 0.0;
                 continue;
             }
             const int e = off + j;
-            const T *row = ph + (size_t)e * 5 * n;
             const double gx = g[3 * e], gy = g[3 * e + 1], gz = g[3 * e + 2];
             double bx = 0.0, by = 0.0, bz = 0.0, lp = 0.0, xv = 0.0;
             if (lane < n) {
-                const double Gx = (double)row[n + lane], Gy = (double)row[2 * n + lane],
-                             Gz = (double)row[3 * n + lane], Lp = (double)row[4 * n + lane];
+                const double Gx = (double)rG[q][0], Gy = (double)rG[q][1], Gz = (double)rG[q][2],
+                             Lp = (double)rG[q][3];
                 xv = Lp + 2.0 * (gx * Gx + gy * Gy + gz * Gz);
                 if (lane < nb) {
                     const double kk = K[lane * ldk + j];
