@@ -65,7 +65,7 @@ struct vmc_ctx {
         *d_shell_np = nullptr;
     double *d_ao_eta = nullptr, *d_prim_exp = nullptr, *d_prim_cp = nullptr, *d_C = nullptr, *d_R = nullptr,
            *d_Z = nullptr;
-    int *d_shell_l = nullptr, *d_shell_mu0 = nullptr;
+    int *d_shell_l = nullptr, *d_shell_mu0 = nullptr, *d_atom_ao_ptr = nullptr, *d_atom_ao = nullptr;
     int *d_tile16 = nullptr; // [4][n_tiles]: first shell, end shell, first AO, end AO (<= 16 AOs)
     AoTiles tiles16{};
     SysDev sys{};
@@ -543,6 +543,17 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         return bail(rc);
     c->tiles16 = AoTiles{c->d_tile16, c->d_tile16 + n_tiles16, c->d_tile16 + 2 * n_tiles16,
                          c->d_tile16 + 3 * n_tiles16, n_tiles16};
+    // the AOs of each atom (any shell order), for per-nucleus sums
+    std::vector<int> atom_ao_ptr(A + 1, 0), atom_ao(M);
+    for (int m = 0; m < M; ++m) ++atom_ao_ptr[basis->shell_atom[ao_shell[m]] + 1];
+    for (int a = 0; a < A; ++a) atom_ao_ptr[a + 1] += atom_ao_ptr[a];
+    {
+        std::vector<int> fill(atom_ao_ptr.begin(), atom_ao_ptr.end() - 1);
+        for (int m = 0; m < M; ++m) atom_ao[fill[basis->shell_atom[ao_shell[m]]]++] = m;
+    }
+    if ((rc = c->upload(&c->d_atom_ao_ptr, atom_ao_ptr.data(), A + 1)) ||
+        (rc = c->upload(&c->d_atom_ao, atom_ao.data(), M)))
+        return bail(rc);
     if ((rc = c->upload(&c->d_ao_shell, ao_shell.data(), M)) || (rc = c->upload(&c->d_ao_pow, ao_pow.data(), M)) ||
         (rc = c->upload(&c->d_ao_eta, ao_eta.data(), M)) ||
         (rc = c->upload(&c->d_shell_atom, (const int *)basis->shell_atom, S)) ||
@@ -570,7 +581,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     sd.ee_F = c->ee_F;
     sd.basis = vmcx::BasisDev{M,          S,           c->d_ao_shell, c->d_ao_pow,   c->d_ao_eta,
                               c->d_shell_atom, c->d_shell_p0, c->d_shell_np, c->d_prim_exp, c->d_prim_cp,
-                              c->d_shell_l, c->d_shell_mu0};
+                              c->d_shell_l, c->d_shell_mu0, c->d_atom_ao_ptr, c->d_atom_ao};
     sd.Z = c->d_Z;
     layouts(c);
     const bool mixed = opt->precision == VMC_MIXED;

@@ -81,6 +81,8 @@ struct BasisDev {
     const double *prim_cp;   // radial coefficient incl. all norms
     const int *shell_l;
     const int *shell_mu0;    // first AO of the shell
+    const int *atom_ao_ptr;  // [A + 1]: the AOs of atom a are atom_ao[ptr[a] .. ptr[a + 1])
+    const int *atom_ao;      // [M]
 };
 
 // Monomial exponents of cartesian component q of a shell with angular

@@ -208,13 +208,16 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
     if (tid < tpa * A) {
         const int a = tid / tpa, j = tid - (tid / tpa) * tpa;
         double sE[3] = {0, 0, 0}, sP[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
-        for (int m = j; m < M; m += tpa)
-            if (S.basis.shell_atom[S.basis.ao_shell[m]] == a)
+        // this nucleus's AOs (congruent to j modulo tpa in its list)
+        const int q0 = S.basis.atom_ao_ptr[a], q1 = S.basis.atom_ao_ptr[a + 1];
+        for (int q = q0 + j; q < q1; q += tpa) {
+            const double *t = mb.tao + ((size_t)w * M + S.basis.atom_ao[q]) * 6;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    sE[k] -= mb.tao[((size_t)w * M + m) * 6 + k];
-                    sP[k] -= mb.tao[((size_t)w * M + m) * 6 + 3 + k];
-                }
+            for (int k = 0; k < 3; ++k) {
+                sE[k] -= t[k];
+                sP[k] -= t[3 + k];
+            }
+        }
         const double Rx = R[3 * a], Ry = R[3 * a + 1], Rz = R[3 * a + 2], Za = S.Z[a];
         for (int e = j; e < N; e += tpa) {
             const double dx = p[3 * e] - Rx, dy = p[3 * e + 1] - Ry, dz = p[3 * e + 2] - Rz;
