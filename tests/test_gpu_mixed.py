@@ -153,3 +153,29 @@ def test_mixed_estimators_run(dev):
     # chains that diverge after a near-tie decision make this a statistical
     # comparison: within a few error bars
     assert abs(a["E"] - b["E"]) < 5 * max(a["E_sigma"], 1e-6)
+
+
+def test_promotion_all_and_none(dev):
+    """The FP64 re-measurement machinery (selection, gather, scatter): with a
+    promoted share of 1 every walker's mixed results are replaced by FP64 ones,
+    so they equal the FP64 context's bit for bit; with 0 nothing is replaced
+    and the results differ from FP64 by FP32 round-off only."""
+    from paper_2511_05222_amd import vmc
+    mol = inputs.make_config(1).molecule
+    W = 300
+    tw = torch.tensor(inputs.initial_walkers(mol, W, 9), device=dev)
+    c64 = vmc.Context(mol, max_walkers=W, precision="fp64")
+    c64.sweep(tw, 2, 9, measure=False)
+    outs = ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G")
+    ref = {k: v.cpu().numpy() for k, v in c64.measure(tw, outputs=outs).items()}
+    for frac, staging in ((1.0, 128), (0.0, 0)):
+        c32 = vmc.Context(mol, max_walkers=W, precision="mixed", promote_fraction=frac, staging_walkers=staging)
+        got = {k: v.cpu().numpy() for k, v in c32.measure(tw, outputs=outs).items()}
+        torch.cuda.synchronize()
+        for k in outs:
+            if frac == 1.0:
+                assert np.array_equal(got[k], ref[k]), k
+            else:
+                scale = np.abs(ref[k]).max()
+                assert np.abs(got[k] - ref[k]).max() < 1e-2 * scale, k
+                assert not np.array_equal(got[k], ref[k]), k
