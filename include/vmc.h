@@ -190,7 +190,8 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
  * matrix of every walker is built from walkers_dev at the start of the call
  * and kept current by the moves (row e rewritten on each accepted move).
  * flags & VMC_SWEEP_MEASURE: after every sweep measure every walker and add
- *   the samples to the context's accumulators (read by vmc_accumulate).
+ *   the samples to the context's accumulators (read by vmc_accumulate) and,
+ *   with jackknife_blocks > 0, to the running block's sums (vmc_jackknife).
  * accept_dev   : optional device uint8 [nsteps][N][n_walkers], 1 = accepted.
  * Errors: VMC_EINVAL (n_walkers > max_walkers or < 1, nsteps < 0),
  * VMC_EDEVICE. */

@@ -450,24 +450,41 @@ __global__ __launch_bounds__(256) void k_cgb_matvec(const double *__restrict__ H
     MF::acc_t acc[NRT];
 #pragma unroll
     for (int t = 0; t < NRT; ++t) acc[t] = MF::zero();
-    for (int64_t st = s0; st < s1; ++st) {
+    // stage st+1 is loaded into registers while stage st is multiplied
+    constexpr int HQ = CGB_ROWS * CGB_KC / 256, PQ = 16 * NRT * CGB_KC / 256;
+    double hr[HQ], pr[PQ];
+    auto load = [&](int64_t st) {
         const int64_t c0 = st * CGB_KC;
         // clamped, unconditional loads (selected afterwards)
 #pragma unroll
-        for (int q = 0; q < CGB_ROWS * CGB_KC / 256; ++q) {
+        for (int q = 0; q < HQ; ++q) {
             const int i = tid + 256 * q, rr = i / CGB_KC, cc = i % CGB_KC;
             const int64_t row = r0 + rr, col = c0 + cc;
             const double v = H[min(row, d - 1) * d + min(col, d - 1)];
-            Hs[rr * CGB_LD + cc] = (row < d && col < d) ? v : 0.0;
+            hr[q] = (row < d && col < d) ? v : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 16 * NRT * CGB_KC / 256; ++q) {
+        for (int q = 0; q < PQ; ++q) {
             const int i = tid + 256 * q, kk = i / CGB_KC, cc = i % CGB_KC;
             const int64_t col = c0 + cc;
             const double v = P[(int64_t)min(kk, nrhs - 1) * d + min(col, d - 1)];
-            Ps[kk * CGB_LD + cc] = (kk < nrhs && col < d) ? v : 0.0;
+            pr[q] = (kk < nrhs && col < d) ? v : 0.0;
+        }
+    };
+    if (s0 < s1) load(s0);
+    for (int64_t st = s0; st < s1; ++st) {
+#pragma unroll
+        for (int q = 0; q < HQ; ++q) {
+            const int i = tid + 256 * q;
+            Hs[(i / CGB_KC) * CGB_LD + i % CGB_KC] = hr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int i = tid + 256 * q;
+            Ps[(i / CGB_KC) * CGB_LD + i % CGB_KC] = pr[q];
         }
         __syncthreads();
+        if (st + 1 < s1) load(st + 1);
         const double *ha = Hs + (16 * wv + ml) * CGB_LD + kg;
 #pragma unroll
         for (int ks = 0; ks < CGB_KC / 4; ++ks) {
@@ -491,23 +508,29 @@ __global__ __launch_bounds__(256) void k_cgb_matvec(const double *__restrict__ H
     }
 }
 
-// per right-hand side k (one block each): Hp = sum of the ksplit partials;
-// alpha = rz / p.Hp; x += alpha p; r -= alpha Hp; stop test; p = dinv r + beta p
+// HP[k][i] = the ksplit partial products added in a fixed order, written over
+// the first partial (all right-hand sides and rows in parallel)
+__global__ void k_cgb_sum(double *__restrict__ HPp, int64_t d, int nrhs, int ksplit, const CgState *cs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nrhs * d || cs[t / d].done) return;
+    double v = 0.0;
+    for (int s = 0; s < ksplit; ++s) v += HPp[(int64_t)s * nrhs * d + t];
+    HPp[t] = v;
+}
+
+// per right-hand side k (one block each): alpha = rz / p.Hp; x += alpha p;
+// r -= alpha Hp; stop test; p = dinv r + beta p
 __global__ __launch_bounds__(CG_BS) void k_cgb_update(double *__restrict__ X, double *__restrict__ R,
-                                                      double *__restrict__ P, const double *__restrict__ HPp,
-                                                      const double *__restrict__ Dinv, int64_t d, int nrhs,
-                                                      int ksplit, CgState *css) {
+                                                      double *__restrict__ P, const double *__restrict__ HP,
+                                                      const double *__restrict__ Dinv, int64_t d, CgState *css) {
     const int k = blockIdx.x;
     CgState *cs = css + k;
     if (cs->done) return;
     __shared__ double red[2 * CG_BS / 64];
     double *x = X + (int64_t)k * d, *r = R + (int64_t)k * d, *p = P + (int64_t)k * d;
     const double *dinv = Dinv + (int64_t)k * d;
-    auto hp = [&](int64_t i) {
-        double t = 0.0;
-        for (int s = 0; s < ksplit; ++s) t += HPp[((int64_t)s * nrhs + k) * d + i];
-        return t;
-    };
+    const double *hpk = HP + (int64_t)k * d;
+    auto hp = [&](int64_t i) { return hpk[i]; };
     double pHp = 0.0, unused = 0.0;
     for (int64_t i = threadIdx.x; i < d; i += CG_BS) pHp += p[i] * hp(i);
     block_sum2<CG_BS>(pHp, unused, red);
@@ -630,8 +653,8 @@ hipError_t launch_cg_setup(const double *H, const double *b, int64_t d, int nrhs
 
 int cgb_ksplit(int64_t d) {
     const int64_t rb = (d + CGB_ROWS - 1) / CGB_ROWS, nst = (d + CGB_KC - 1) / CGB_KC;
-    int64_t ks = (512 + rb - 1) / rb;   // about 512 blocks in all
-    return (int)std::max<int64_t>(1, std::min<int64_t>({ks, 16, nst}));
+    int64_t ks = (2048 + rb - 1) / rb;   // about 2048 blocks in all
+    return (int)std::max<int64_t>(1, std::min<int64_t>({ks, 32, nst}));
 }
 
 hipError_t launch_cgb_iteration(const double *H, int64_t d, int nrhs, double *X, double *R, double *P, double *HPp,
@@ -644,7 +667,9 @@ hipError_t launch_cgb_iteration(const double *H, int64_t d, int nrhs, double *X,
         case 3: hipLaunchKernelGGL(k_cgb_matvec<3>, g, dim3(256), 0, st, H, P, HPp, d, nrhs, ks, cs); break;
         default: hipLaunchKernelGGL(k_cgb_matvec<4>, g, dim3(256), 0, st, H, P, HPp, d, nrhs, ks, cs); break;
     }
-    hipLaunchKernelGGL(k_cgb_update, dim3((unsigned)nrhs), dim3(CG_BS), 0, st, X, R, P, HPp, dinv, d, nrhs, ks, cs);
+    hipLaunchKernelGGL(k_cgb_sum, dim3((unsigned)(((int64_t)nrhs * d + 255) / 256)), dim3(256), 0, st, HPp, d, nrhs,
+                       ks, cs);
+    hipLaunchKernelGGL(k_cgb_update, dim3((unsigned)nrhs), dim3(CG_BS), 0, st, X, R, P, HPp, dinv, d, cs);
     return hipGetLastError();
 }
 
