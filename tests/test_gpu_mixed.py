@@ -159,7 +159,8 @@ def test_promotion_all_and_none(dev):
     """The FP64 re-measurement machinery (selection, gather, scatter): with a
     promoted share of 1 every walker's mixed results are replaced by FP64 ones,
     so they equal the FP64 context's bit for bit; with 0 nothing is replaced
-    and the results differ from FP64 by FP32 round-off only."""
+    and the results differ from FP64 by FP32 round-off only; with 1/4, exactly
+    ceil(launch / 4) walkers of each measurement launch carry FP64 results."""
     from paper_2511_05222_amd import vmc
     mol = inputs.make_config(1).molecule
     W = 300
@@ -168,14 +169,22 @@ def test_promotion_all_and_none(dev):
     c64.sweep(tw, 2, 9, measure=False)
     outs = ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G")
     ref = {k: v.cpu().numpy() for k, v in c64.measure(tw, outputs=outs).items()}
-    for frac, staging in ((1.0, 128), (0.0, 0)):
+    for frac, staging in ((1.0, 128), (0.0, 0), (0.25, 128)):
         c32 = vmc.Context(mol, max_walkers=W, precision="mixed", promote_fraction=frac, staging_walkers=staging)
         got = {k: v.cpu().numpy() for k, v in c32.measure(tw, outputs=outs).items()}
         torch.cuda.synchronize()
-        for k in outs:
-            if frac == 1.0:
+        if frac == 1.0:
+            for k in outs:
                 assert np.array_equal(got[k], ref[k]), k
-            else:
+        elif frac == 0.0:
+            for k in outs:
                 scale = np.abs(ref[k]).max()
                 assert np.abs(got[k] - ref[k]).max() < 1e-2 * scale, k
                 assert not np.array_equal(got[k], ref[k]), k
+        else:
+            # launches of 128, 128 and 44 walkers: ceil(share x launch) of each
+            # carry the FP64 results exactly, in every output
+            same = np.all([np.all((got[k] == ref[k]).reshape(W, -1), axis=1) for k in outs], axis=0)
+            assert same.sum() == 32 + 32 + 11, same.sum()
+            for c0, c1, kk in ((0, 128, 32), (128, 256, 32), (256, 300, 11)):
+                assert same[c0:c1].sum() == kk
