@@ -22,7 +22,7 @@
  *     valid until the work queued on `stream` has completed.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Every call queues
  *     its kernels on that stream and returns without synchronising, except
- *     vmc_accumulate and zvector_solve, which synchronise the stream.
+ *     vmc_accumulate, vmc_jackknife and zvector_solve, which synchronise it.
  *   - Every function returns VMC_OK (0) or a negative status; none aborts,
  *     throws or prints.  vmc_last_error(ctx) gives a human-readable detail.
  *   - A context is not thread-safe; distinct contexts are independent.
@@ -116,13 +116,15 @@ typedef struct {
 
 /* Run options.
  * precision      : VMC_FP64 or VMC_MIXED
- * refresh_period : the inverse of the spin block being swept is rebuilt from
+ * refresh_period : each spin block's inverse (kept in device memory between
+ *                  its blocks of moves and between sweeps) is rebuilt from
  *                  scratch (FP64 Gauss-Jordan, partial pivoting) from the
- *                  walker's MO matrix at the block's first electron in every
- *                  sweep, after every refresh_period-th proposed move (global
- *                  move index sweep*N + e) that is not the block's last, and
- *                  after an accepted move with |ratio| < 1e-8; Sherman-Morrison
- *                  updates in between
+ *                  walker's MO matrix after every refresh_period-th proposed
+ *                  move of that block's electrons (block move index
+ *                  sweep * n_occ + j for its j-th electron), at the start of
+ *                  every vmc_sweep call, and after an accepted move of the
+ *                  block with |ratio| < 1e-8; Sherman-Morrison updates in
+ *                  between
  * block_sweeps   : sweeps per block of the blocked energy error bar
  * max_walkers    : largest n_walkers any call on this context will pass
  * staging_walkers: walkers measured per launch (per-walker staging buffers);

@@ -21,18 +21,24 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose=False):
+def build(verbose=False, jobs=None):
+    """Compile every source (in parallel, one hipcc per source) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
     tmp = os.path.join(HERE, "_build")
     os.makedirs(tmp, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(tmp, src.replace(".hip", ".o"))
-        cmd = [hipcc, *[f for f in HIPCC_FLAGS if f != "-shared"], "-c", os.path.join(CSRC, src), "-o", obj]
+    objs = [os.path.join(tmp, src.replace(".hip", ".o")) for src in SOURCES]
+
+    def compile_one(i):
+        cmd = [hipcc, *[f for f in HIPCC_FLAGS if f != "-shared"], "-c", os.path.join(CSRC, SOURCES[i]), "-o", objs[i]]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    jobs = jobs or min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(compile_one, i) for i in range(len(SOURCES))]:
+            f.result()
     out_tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out_tmp]
     if verbose:
