@@ -108,10 +108,18 @@ typedef struct {
     const double *C;
 } vmc_mo;
 
-/* Two-body Pade Jastrow u(r) = ee_a r / (1 + ee_F r), spin independent. */
+/* Two-body Jastrow exp(sum_{i<j} u(r_ij)), spin independent (Appendix A):
+ *   ee_form = VMC_JASTROW_PADE: u(r) = ee_a r / (1 + ee_F r)      (eq. twobody_v)
+ *   ee_form = VMC_JASTROW_EXP : u(r) = ee_a (1 - exp(-ee_F r)) / ee_F
+ *                                                         (eq. twobody_v_exp)
+ * (the paper's forms have ee_a = 1/2, the electron-electron cusp; the
+ * exponential form needs ee_F > 0). */
+#define VMC_JASTROW_PADE 0
+#define VMC_JASTROW_EXP  1
 typedef struct {
     double ee_a;
     double ee_F;
+    int32_t ee_form;
 } vmc_jastrow;
 
 /* Run options.

@@ -77,7 +77,7 @@ class Chains:
             ro = self.r[:, others, :]
             dn = np.sqrt(np.sum((r_new[:, None, :] - ro) ** 2, axis=-1))
             do = np.sqrt(np.sum((self.r[:, e, None, :] - ro) ** 2, axis=-1))
-            dJ += np.sum(wf.pade(dn, s.a, s.F)[0] - wf.pade(do, s.a, s.F)[0], axis=1)
+            dJ += np.sum(wf.ee_pair(s, dn)[0] - wf.ee_pair(s, do)[0], axis=1)
         if s.en_on:
             for al in range(s.A):
                 dn = np.linalg.norm(r_new - self.R[al], axis=-1)

@@ -41,6 +41,7 @@ class System:
         jas = mol.jastrow
         self.a = float(jas.ee_a)
         self.F = float(jas.ee_F)
+        self.ee_form = int(getattr(jas, "ee_form", 0))
         self.en_on = int(jas.en_on)
         self.en_b = float(jas.en_b)
         self.A = self.xyz.shape[0]
@@ -109,9 +110,21 @@ def mo_matrices(system, R, r, C=None):
 # --------------------------------------------------------------------------
 
 def pade(r, a, F):
-    """u, u', u'' of u(r) = a r / (1 + F r)."""
+    """u, u', u'' of u(r) = a r / (1 + F r)  (eq. twobody_v, a = 1/2)."""
     q = 1.0 / (1.0 + F * r)
     return a * r * q, a * q * q, -2.0 * a * F * q * q * q
+
+
+def expo(r, a, F):
+    """u, u', u'' of u(r) = a (1 - exp(-F r)) / F  (eq. twobody_v_exp, a = 1/2)."""
+    e = np.exp(-F * r)
+    return a * (1.0 - e) / F, a * e, -a * F * e
+
+
+def ee_pair(system, r):
+    """The electron-electron Jastrow function of the system and its first two
+    derivatives at distances r."""
+    return (expo if system.ee_form == 1 else pade)(r, system.a, system.F)
 
 
 def _pairs(r):
@@ -136,7 +149,7 @@ def jastrow_terms(system, R, r):
     h = np.zeros((W, N), dtype=dtype)
     if N > 1:
         d, rij, off = _pairs(r)                         # [W,N,N,3], [W,N,N], [N,N]
-        u, u1, u2 = pade(rij, system.a, system.F)
+        u, u1, u2 = ee_pair(system, rij)
         J = J + 0.5 * np.sum(u * off, axis=(1, 2))
         g = g + np.sum((off * u1 / rij)[..., None] * d, axis=2)
         h = h + np.sum(off * (u2 + 2.0 * u1 / rij), axis=2)

@@ -58,6 +58,7 @@ struct vmc_ctx {
     int N = 0, n_up = 0, n_dn = 0, n_occ = 0, M = 0, A = 0, S = 0, P = 0;
     vmc_options opt{};
     double ee_a = 0.5, ee_F = 1.0;
+    int ee_form = VMC_JASTROW_PADE;
     std::string err;
 
     std::vector<void *> allocs;
@@ -454,7 +455,9 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         return bail(c->fail(VMC_EINVAL, "n_occ = %d / N = %d exceed the limits", mo->n_occ, mo->n_up + mo->n_dn));
     if (!all_finite(nuclei->xyz, 3 * A) || !all_finite(nuclei->Z, A) || !all_finite(mo->C, (int64_t)M * mo->n_occ))
         return bail(c->fail(VMC_EINVAL, "non-finite nuclei or MO coefficients"));
-    if (!std::isfinite(jas->ee_a) || !std::isfinite(jas->ee_F) || jas->ee_F < 0.0)
+    if (!std::isfinite(jas->ee_a) || !std::isfinite(jas->ee_F) || jas->ee_F < 0.0 ||
+        (jas->ee_form != VMC_JASTROW_PADE && jas->ee_form != VMC_JASTROW_EXP) ||
+        (jas->ee_form == VMC_JASTROW_EXP && !(jas->ee_F > 0.0)))
         return bail(c->fail(VMC_EINVAL, "bad Jastrow parameters"));
     if (opt->precision != VMC_FP64 && opt->precision != VMC_MIXED)
         return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 or VMC_MIXED)", opt->precision));
@@ -473,6 +476,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     c->P = P;
     c->ee_a = jas->ee_a;
     c->ee_F = jas->ee_F;
+    c->ee_form = jas->ee_form;
     (void)Zsum;
 
     // ---- fold normalisation -------------------------------------------------
@@ -579,6 +583,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     sd.A = A;
     sd.ee_a = c->ee_a;
     sd.ee_F = c->ee_F;
+    sd.ee_form = c->ee_form;
     sd.basis = vmcx::BasisDev{M,          S,           c->d_ao_shell, c->d_ao_pow,   c->d_ao_eta,
                               c->d_shell_atom, c->d_shell_p0, c->d_shell_np, c->d_prim_exp, c->d_prim_cp,
                               c->d_shell_l, c->d_shell_mu0, c->d_atom_ao_ptr, c->d_atom_ao};

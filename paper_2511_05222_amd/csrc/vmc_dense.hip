@@ -140,15 +140,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
             const double d2 = dx * dx + dy * dy + dz * dz;
             const double ir = rsqrt_nr(d2), r = d2 * ir;
-            const double q = rcp_nr(1.0 + S.ee_F * r);
-            const double u1 = S.ee_a * q * q, u2 = -2.0 * S.ee_F * u1 * q;
+            double u, u1, u2;
+            if (S.ee_form == 1) {
+                const double ex = exp(-S.ee_F * r);
+                u1 = S.ee_a * ex;
+                u2 = -S.ee_F * u1;
+                u = S.ee_a * (1.0 - ex) / S.ee_F;
+            } else {
+                const double q = rcp_nr(1.0 + S.ee_F * r);
+                u1 = S.ee_a * q * q;
+                u2 = -2.0 * S.ee_F * u1 * q;
+                u = S.ee_a * r * q;
+            }
             const double f = u1 * ir;
             gx += f * dx;
             gy += f * dy;
             gz += f * dz;
             hh += u2 + 2.0 * f;
             vee += ir;
-            jj += S.ee_a * r * q;
+            jj += u;
         }
         if (hf == 0)
             for (int a = 0; a < A; ++a) {

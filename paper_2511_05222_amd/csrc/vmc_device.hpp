@@ -220,20 +220,26 @@ __host__ __device__ inline int shell_eval_to(const BasisDev &B, const double *R,
 }
 
 // ---------------------------------------------------------------------------
-// Pade two-body Jastrow u(r) = a r / (1 + F r) and derivatives.
+// Two-body Jastrow function u(r) and its derivatives:
+//   form 0 (Pade)       u = a r / (1 + F r)
+//   form 1 (exponential) u = a (1 - e^{-F r}) / F
 // ---------------------------------------------------------------------------
-__host__ __device__ inline double pade_u(double r, double a, double F) {
-    return a * r / (1.0 + F * r);
+__host__ __device__ inline double jas_u(double r, double a, double F, int form) {
+    return form == 1 ? a * (1.0 - exp(-F * r)) / F : a * r / (1.0 + F * r);
 }
 
-struct PadeD {
+struct JasD {
     double u, u1, u2, u3;
 };
 
-__host__ __device__ inline PadeD pade_all(double r, double a, double F) {
+__host__ __device__ inline JasD jas_all(double r, double a, double F, int form) {
+    if (form == 1) {
+        const double e = exp(-F * r), ae = a * e;
+        return JasD{a * (1.0 - e) / F, ae, -F * ae, F * F * ae};
+    }
     const double q = 1.0 / (1.0 + F * r);
     const double q2 = q * q;
-    return PadeD{a * r * q, a * q2, -2.0 * a * F * q2 * q, 6.0 * a * F * F * q2 * q2};
+    return JasD{a * r * q, a * q2, -2.0 * a * F * q2 * q, 6.0 * a * F * F * q2 * q2};
 }
 
 }  // namespace vmcx

@@ -17,6 +17,7 @@ constexpr int STATUS_NONFINITE = 2;
 struct SysDev {
     int N, n_up, n_dn, n_occ, M, A;
     double ee_a, ee_F;
+    int ee_form;   // 0: a r / (1 + F r); 1: a (1 - e^{-F r}) / F
     BasisDev basis;
     const double *Z;
 };

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
             const double r = sqrt(dx * dx + dy * dy + dz * dz);
             const double ir = 1.0 / r;
             const double ux = dx * ir, uy = dy * ir, uz = dz * ir;
-            const PadeD pd = pade_all(r, S.ee_a, S.ee_F);
+            const JasD pd = jas_all(r, S.ee_a, S.ee_F, S.ee_form);
             const double vx = ge[0] + (gb[6 * k + 3] + gb[6 * k]);
             const double vy = ge[1] + (gb[6 * k + 4] + gb[6 * k + 1]);
             const double vz = ge[2] + (gb[6 * k + 5] + gb[6 * k + 2]);

@@ -118,6 +118,7 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
     double dj;
     if constexpr (sizeof(T) == sizeof(float)) {
         const float a = (float)S.ee_a, F = (float)S.ee_F;
+        const float aF = S.ee_form == 1 ? (float)(S.ee_a / S.ee_F) : 0.0f;
         float d = 0.0f;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
@@ -126,7 +127,10 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
             const float bx = (float)(ex - px[hh]), by = (float)(ey - py[hh]), bz = (float)(ez - pz[hh]);
             const float ra = __builtin_amdgcn_sqrtf(ax * ax + ay * ay + az * az);
             const float rb = __builtin_amdgcn_sqrtf(bx * bx + by * by + bz * bz);
-            const float t = a * ra * __builtin_amdgcn_rcpf(1.0f + F * ra) - a * rb * __builtin_amdgcn_rcpf(1.0f + F * rb);
+            const float t = S.ee_form == 1
+                                ? aF * (__expf(-F * rb) - __expf(-F * ra))
+                                : a * ra * __builtin_amdgcn_rcpf(1.0f + F * ra) -
+                                      a * rb * __builtin_amdgcn_rcpf(1.0f + F * rb);
             d += (k < N && k != e) ? t : 0.0f;
         }
         dj = (double)d;
@@ -138,8 +142,8 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
             if (k < N && k != e) {
                 const double ax = rx - px[hh], ay = ry - py[hh], az = rz - pz[hh];
                 const double bx = ex - px[hh], by = ey - py[hh], bz = ez - pz[hh];
-                dj += pade_u(sqrt(ax * ax + ay * ay + az * az), S.ee_a, S.ee_F) -
-                      pade_u(sqrt(bx * bx + by * by + bz * bz), S.ee_a, S.ee_F);
+                dj += jas_u(sqrt(ax * ax + ay * ay + az * az), S.ee_a, S.ee_F, S.ee_form) -
+                      jas_u(sqrt(bx * bx + by * by + bz * bz), S.ee_a, S.ee_F, S.ee_form);
             }
         }
     }

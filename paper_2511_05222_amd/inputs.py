@@ -81,6 +81,7 @@ class Jastrow:
     ee_F: float = 1.0
     en_on: int = 0
     en_b: float = 0.0
+    ee_form: int = 0   # 0: a r / (1 + F r); 1: a (1 - exp(-F r)) / F
 
 
 @dataclass

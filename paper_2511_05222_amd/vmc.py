@@ -53,7 +53,7 @@ class _MO(ct.Structure):
 
 
 class _Jastrow(ct.Structure):
-    _fields_ = [("ee_a", ct.c_double), ("ee_F", ct.c_double)]
+    _fields_ = [("ee_a", ct.c_double), ("ee_F", ct.c_double), ("ee_form", ct.c_int32)]
 
 
 class _Options(ct.Structure):
@@ -149,7 +149,7 @@ class Context:
         nuc = _Nuclei(mol.n_atoms, dp(k[5]), dp(k[6]))
         n_ao = int(sum((int(l) + 1) * (int(l) + 2) // 2 for l in b.shell_l))
         mo = _MO(n_ao, mol.n_occ, mol.n_up, mol.n_dn, dp(k[7]))
-        jas = _Jastrow(mol.jastrow.ee_a, mol.jastrow.ee_F)
+        jas = _Jastrow(mol.jastrow.ee_a, mol.jastrow.ee_F, int(getattr(mol.jastrow, "ee_form", 0)))
         if getattr(mol.jastrow, "en_on", 0):
             raise VmcError(VMC_EINVAL, "the electron-nucleus Jastrow factor is not part of the HIP path")
         prec = {"fp64": VMC_FP64, "mixed": VMC_MIXED}.get(precision)

@@ -74,9 +74,19 @@ def test_rejects_bad_atom_index():
 
 
 def test_rejects_too_many_orbitals():
-    mol = copy.deepcopy(inputs.make_config(1).molecule)
-    with pytest.raises(vmc.VmcError):
-        vmc.Context(mol, 4, precision="mixed")
+    def m(mol):
+        mol.n_up = mol.n_dn = 65   # C_full has 75 columns; 65 occupied > VMC_MAX_OCC
+    e = _bad(m)
+    assert e.code == vmc.VMC_EINVAL and "exceed" in str(e)
+
+
+def test_rejects_bad_jastrow_form():
+    def form(f, F):
+        def m(mol):
+            mol.jastrow = inputs.Jastrow(0.5, F, 0, 0.0, ee_form=f)
+        return m
+    assert _bad(form(2, 1.0)).code == vmc.VMC_EINVAL
+    assert _bad(form(1, 0.0)).code == vmc.VMC_EINVAL   # the exponential form needs F > 0
 
 
 def test_rejects_bad_options():

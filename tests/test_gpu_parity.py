@@ -182,3 +182,49 @@ def test_zvector_cg(dev):
     with pytest.raises(vmc.VmcError) as ei:
         vmc.zvector_solve(torch.tensor(H, device=dev), torch.tensor(b, device=dev), rtol=1e-12, maxit=1)
     assert ei.value.code == vmc.VMC_ENOTCONV
+
+
+def test_exponential_jastrow(dev):
+    """The exponential two-body Jastrow (eq. twobody_v_exp, F = 1.3): FP64
+    accept bits and positions, per-walker measurement and estimators against
+    the oracle; the mixed sweep agrees with the FP64 one."""
+    import dataclasses
+    from oracle import sampler, vmc as ovmc, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    mol = dataclasses.replace(inputs.make_config(1).molecule,
+                              jastrow=inputs.Jastrow(0.5, 1.3, 0, 0.0, ee_form=1))
+    W = 12
+    w0 = inputs.initial_walkers(mol, W, 31)
+    ch, bits = sampler.run(wf.System(mol), w0, 2, 4321, refresh_period=32)
+    ctx = vmc.Context(mol, max_walkers=W)
+    tw = torch.tensor(w0, device=dev)
+    acc = torch.zeros((2, mol.n_elec, W), dtype=torch.uint8, device=dev)
+    ctx.sweep(tw, 2, 4321, measure=False, accept=acc)
+    torch.cuda.synchronize()
+    assert np.array_equal(acc.cpu().numpy().astype(bool), bits)
+    close(tw.cpu().numpy(), ch.r, tol=1e-13, what="positions")
+    r = ch.r[:4]
+    ref = per_walker_oracle(mol, r)
+    out = ctx.measure(torch.tensor(r, device=dev))
+    torch.cuda.synchronize()
+    for k in ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G"):
+        close(out[k].cpu().numpy(), ref[k], what=f"exp-Jastrow {k}")
+    est = ovmc.run(mol, w0, 3, 77, block_sweeps=1)
+    c2 = vmc.Context(mol, max_walkers=W, block_sweeps=1)
+    tw2 = torch.tensor(w0, device=dev)
+    c2.sweep(tw2, 3, 77)
+    res = c2.accumulate()
+    for k in ("E", "F_bare", "dE_dC"):
+        close(res[k], est[k], what=f"exp-Jastrow estimator {k}")
+    # mixed sweep against FP64 from the same starting points
+    Wm = 256
+    wm = inputs.initial_walkers(mol, Wm, 32)
+    b = {}
+    for prec in ("fp64", "mixed"):
+        c = vmc.Context(mol, max_walkers=Wm, precision=prec)
+        t = torch.tensor(wm, device=dev)
+        a = torch.zeros((1, mol.n_elec, Wm), dtype=torch.uint8, device=dev)
+        c.sweep(t, 1, 5, measure=False, accept=a)
+        torch.cuda.synchronize()
+        b[prec] = a.cpu().numpy()
+    assert np.mean(b["fp64"] == b["mixed"]) >= 0.999

@@ -195,6 +195,10 @@ def test_same_spin_swap_flips_sign(mol9):
 # complex-step divergence of that gradient; together they give the kinetic
 # energy independently of the determinant-Laplacian formula.
 def test_kinetic_identity(mol9):
+    _kinetic_identity(mol9)
+
+
+def _kinetic_identity(mol9):
     s = wf.System(mol9)
     r = inputs.initial_walkers(mol9, 3, 13)
     ev = wf.evaluate(s, s.xyz, r, keep=True)
@@ -211,6 +215,25 @@ def test_kinetic_identity(mol9):
             lap += (evc["b"] + evc["g"])[:, e, k].imag / hcs
     tot = lap + np.sum(grad * grad, axis=(1, 2))
     assert np.allclose(-0.5 * tot, kin, rtol=1e-10, atol=1e-10 * np.abs(kin).max())
+
+
+# The exponential two-body Jastrow (eq. twobody_v_exp): u = a (1 - e^{-F r})/F
+# has the electron-electron cusp u'(0) = a and tends to a/F; its derivatives
+# match central differences of u; and the wavefunction built with it obeys the
+# kinetic identity (complex-step derivatives of ln|Psi| against the analytic
+# gradient and Laplacian), which fixes u' and u'' inside E_L.
+def test_exponential_jastrow(mol9):
+    import dataclasses
+    a, F = 0.5, 1.3
+    r = np.linspace(0.05, 6.0, 40)
+    u, u1, u2 = wf.expo(r, a, F)
+    h = 1e-5
+    assert np.allclose((wf.expo(r + h, a, F)[0] - wf.expo(r - h, a, F)[0]) / (2 * h), u1, rtol=1e-8)
+    assert np.allclose((wf.expo(r + h, a, F)[1] - wf.expo(r - h, a, F)[1]) / (2 * h), u2, rtol=1e-8)
+    assert abs(wf.expo(np.array([0.0]), a, F)[1][0] - a) < 1e-15
+    assert abs(wf.expo(np.array([60.0]), a, F)[0][0] - a / F) < 1e-15
+    mol = dataclasses.replace(mol9, jastrow=inputs.Jastrow(0.5, 1.3, 0, 0.0, ee_form=1))
+    _kinetic_identity(mol)
 
 
 # P11: every cartesian AO has unit norm (spherical product quadrature of the
