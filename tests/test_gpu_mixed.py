@@ -188,3 +188,27 @@ def test_promotion_all_and_none(dev):
             assert same.sum() == 32 + 32 + 11, same.sum()
             for c0, c1, kk in ((0, 128, 32), (128, 256, 32), (256, 300, 11)):
                 assert same[c0:c1].sum() == kk
+
+
+def test_mixed_small_cases(dev):
+    """Degenerate sizes in mixed precision: H2 (one orbital per spin, the
+    smallest register class) and a single walker with one-walker launches."""
+    from paper_2511_05222_amd import vmc
+    for cfg, W, staging in ((0, 64, 0), (1, 1, 1)):
+        mol = inputs.make_config(cfg).molecule
+        w0 = inputs.initial_walkers(mol, W, 3)
+        res = {}
+        for prec in ("fp64", "mixed"):
+            ctx = vmc.Context(mol, max_walkers=W, precision=prec, staging_walkers=staging)
+            tw = torch.tensor(w0, device=dev)
+            acc = torch.zeros((2, mol.n_elec, W), dtype=torch.uint8, device=dev)
+            ctx.sweep(tw, 2, 17, measure=False, accept=acc)
+            out = ctx.measure(tw, outputs=("EL", "dEL_dR", "O"))
+            torch.cuda.synchronize()
+            res[prec] = (acc.cpu().numpy(), tw.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()})
+        a64, p64, o64 = res["fp64"]
+        a32, p32, o32 = res["mixed"]
+        assert np.array_equal(a64, a32) and np.array_equal(p64, p32), cfg
+        for k in ("EL", "dEL_dR", "O"):
+            scale = np.abs(o64[k]).max()
+            assert np.abs(o32[k] - o64[k]).max() < 1e-4 * scale, (cfg, k)
