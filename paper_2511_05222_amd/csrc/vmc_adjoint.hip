@@ -26,6 +26,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                                                       AdjLayout L) {
     typedef Mfma<T> MF;
     constexpr int KS = 4 * NT;        // k-steps over orbitals (4 per step)
+    constexpr int NPR = sizeof(T) == 4 ? 3 : 0;   // primitives held in registers (FP32)
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -72,15 +73,10 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
     for (int st = wave; st < n_sub; st += nw) {
         const int mu = 16 * st + ml;
         const bool vm = mu < M;
-        // this lane's AO
-        int s = 0, pw = 0, atom = 0;
-        T eta = T(0);
-        if (vm) {
-            s = S.basis.ao_shell[mu];
-            pw = S.basis.ao_pow[mu];
-            eta = (T)S.basis.ao_eta[mu];
-            atom = S.basis.shell_atom[s];
-        }
+        // this lane's AO: monomial and primitives in registers for the sub-tile
+        AoLane<T, NPR> al;
+        ao_lane_load<T, NPR>(S.basis, vm ? mu : M - 1, al);
+        const int atom = S.basis.shell_atom[S.basis.ao_shell[vm ? mu : M - 1]];
         const double Rx = R[3 * atom], Ry = R[3 * atom + 1], Rz = R[3 * atom + 2];
         T cB[KS];
 #pragma unroll
@@ -111,10 +107,10 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                     const double dx = sp[3 * e] - Rx, dy = sp[3 * e + 1] - Ry, dz = sp[3 * e + 2] - Rz;
                     const double rho_d = dx * dx + dy * dy + dz * dz;
                     const T x = (T)dx, y = (T)dy, z = (T)dz, rho = (T)rho_d;
-                    T R0, R1, R2, R3;
-                    shell_radial<14, T>(S.basis, s, rho_d, R0, R1, R2, R3);
+                    T R0, u1, u2, u3;
+                    ao_lane_radial<T, NPR>(al, S.basis, rho_d, R0, u1, u2, u3);
                     T d[14];
-                    ao_components<14, T>(x, y, z, rho, R0, R1, R2, R3, pw, eta, d);
+                    ao_lane_components<T, NPR>(al, x, y, z, rho, R0, u1, u2, u3, d);
                     const T gx = (T)sg[3 * e], gy = (T)sg[3 * e + 1], gz = (T)sg[3 * e + 2];
                     const T hgx = gx * d[5] + gy * d[6] + gz * d[7];
                     const T hgy = gx * d[6] + gy * d[8] + gz * d[9];
@@ -132,15 +128,10 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                 }
 #pragma unroll
                 for (int c = 0; c < 6; ++c) tl[c] += t6[c];
-                // AO sum of t_k for electron e over the 16 lanes of this row group
-                double d0 = t6[0], d1 = t6[1], d2 = t6[2];
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) {
-                    d0 += __shfl_xor(d0, off, 64);
-                    d1 += __shfl_xor(d1, off, 64);
-                    d2 += __shfl_xor(d2, off, 64);
-                }
-                if (ml == 0 && e < N) {
+                // AO sum of t_k for electron e over the 16 lanes of this row
+                // group (a DPP row), left in its last lane
+                const double d0 = row16_sum_last(t6[0]), d1 = row16_sum_last(t6[1]), d2 = row16_sum_last(t6[2]);
+                if (ml == 15 && e < N) {
                     dw[3 * e] += d0;
                     dw[3 * e + 1] += d1;
                     dw[3 * e + 2] += d2;

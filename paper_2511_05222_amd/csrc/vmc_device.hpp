@@ -1,7 +1,8 @@
 // vmc_device.hpp -- device math of the VMC hot path (gfx950).
 //
-// Everything here is __host__ __device__ so that the same arithmetic can be
-// checked on the CPU.  The kernels live in the vmc_*.hip sources.
+// Mostly __host__ __device__ (plain arithmetic); the per-lane AO helpers use
+// the hardware exponential and are device-only.  The kernels live in the
+// vmc_*.hip sources.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -178,6 +179,166 @@ __host__ __device__ inline void ao_components(T x, T y, T z, T rho, T R0, T R1, 
     out[11] = eta * ((two * x * lapP + c1 * Px) * R1 + (c2 * x * P + four * rho * Px) * R2 + eight * rho * x * P * R3);
     out[12] = eta * ((two * y * lapP + c1 * Py) * R1 + (c2 * y * P + four * rho * Py) * R2 + eight * rho * y * P * R3);
     out[13] = eta * ((two * z * lapP + c1 * Pz) * R1 + (c2 * z * P + four * rho * Pz) * R2 + eight * rho * z * P * R3);
+}
+
+// ---------------------------------------------------------------------------
+// One AO held by one lane across many electrons (the adjoint's layout): the
+// shell's primitives and the monomial are loaded once into registers.
+//
+// FP32 exponential of the primitives: t = a rho log2(e) is formed in FP64 and
+// split as t = th + tl (th = fp32(t)); 2^-t = 2^-th (1 - tl ln 2) up to
+// (tl ln 2)^2 / 2 < 1e-10 relative for t < 150, with 2^-th from the hardware
+// base-2 exponential.  The FP64 path calls exp.
+// ---------------------------------------------------------------------------
+__device__ inline float exp2_neg_split(double t) {
+    const float th = (float)t;
+    const float tl = (float)(t - (double)th);
+    return __builtin_amdgcn_exp2f(-th) * fmaf(-tl, 0.69314718055994531f, 1.0f);
+}
+
+template <typename T, int NPR>
+struct AoLane {
+    // monomial eta x^a y^b z^c as a product of per-axis quadratics
+    // f_q(t) = c0 + c1 t + c2 t^2 with one-hot coefficients (eta folded into
+    // the x axis), so that f, f' = c1 + 2 c2 t and f'' = 2 c2 need no branch
+    T c0[3], c1[3], c2[3];
+    T h46, h820;               // (4l + 6) / 2 and (8l + 20) / 4
+    int np, p0;                // primitives of the shell
+    T al[NPR], cp[NPR];        // first NPR exponents (in T) and coefficients
+    double alt[NPR];           // al * log2(e) in FP64 (FP32 exponential)
+};
+
+template <typename T, int NPR>
+__device__ inline void ao_lane_load(const BasisDev &B, int mu, AoLane<T, NPR> &L) {
+    const int s = B.ao_shell[mu], pw = B.ao_pow[mu];
+    const T eta = (T)B.ao_eta[mu];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int p = (pw >> (4 * q)) & 15;
+        const T sc = q == 0 ? eta : T(1);
+        L.c0[q] = p == 0 ? sc : T(0);
+        L.c1[q] = p == 1 ? sc : T(0);
+        L.c2[q] = p == 2 ? sc : T(0);
+    }
+    const int l = B.shell_l[s];
+    L.h46 = T(2 * l + 3);
+    L.h820 = T(2 * l + 5);
+    L.np = B.shell_np[s];
+    L.p0 = B.shell_p0[s];
+#pragma unroll
+    for (int k = 0; k < NPR; ++k) {
+        const int p = L.p0 + max(min(k, L.np - 1), 0);
+        L.al[k] = (T)B.prim_exp[p];
+        L.cp[k] = k < L.np ? (T)B.prim_cp[p] : T(0);
+        L.alt[k] = (double)L.al[k] * 1.4426950408889634;
+    }
+}
+
+template <typename T>
+__device__ inline T prim_exp_neg(T al, double alt, double rho);
+template <>
+__device__ inline float prim_exp_neg<float>(float, double alt, double rho) {
+    return exp2_neg_split(alt * rho);
+}
+template <>
+__device__ inline double prim_exp_neg<double>(double al, double, double rho) {
+    return exp(-al * rho);
+}
+
+// Radial sums of the lane's shell at rho (FP64): R0 = sum c' e^{-a rho} and
+// u1 = 2 R0', u2 = 4 R0'', u3 = 8 R0''' (derivatives in rho).
+template <typename T, int NPR>
+__device__ inline void ao_lane_radial(const AoLane<T, NPR> &L, const BasisDev &B, double rho, T &R0, T &u1,
+                                      T &u2, T &u3) {
+    T r0 = T(0), r1 = T(0), r2 = T(0), r3 = T(0);
+#pragma unroll
+    for (int k = 0; k < NPR; ++k) {
+        // padded primitives carry cp = 0
+        const T al = L.al[k];
+        const T e = L.cp[k] * prim_exp_neg<T>(al, L.alt[k], rho);
+        const T w1 = al * e, w2 = al * w1;
+        r0 += e;
+        r1 -= w1;
+        r2 += w2;
+        r3 -= al * w2;
+    }
+    for (int k = NPR; k < L.np; ++k) {
+        const T al = (T)B.prim_exp[L.p0 + k];
+        const T e = (T)B.prim_cp[L.p0 + k] * prim_exp_neg<T>(al, (double)al * 1.4426950408889634, rho);
+        const T w1 = al * e, w2 = al * w1;
+        r0 += e;
+        r1 -= w1;
+        r2 += w2;
+        r3 -= al * w2;
+    }
+    R0 = r0;
+    u1 = T(2) * r1;
+    u2 = T(4) * r2;
+    u3 = T(8) * r3;
+}
+
+// The 14 components of ao_components<14> for the lane's AO at displacement
+// (x, y, z), rho = x^2 + y^2 + z^2, from R0, u1, u2, u3 of ao_lane_radial.
+template <typename T, int NPR>
+__device__ inline void ao_lane_components(const AoLane<T, NPR> &L, T x, T y, T z, T rho, T R0, T u1, T u2, T u3,
+                                          T *d) {
+    const T r[3] = {x, y, z};
+    T f[3], f1[3], f2[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const T h = fma(L.c2[q], r[q], L.c1[q]);
+        f[q] = fma(h, r[q], L.c0[q]);
+        f1[q] = fma(L.c2[q], r[q], h);
+        f2[q] = L.c2[q] + L.c2[q];
+    }
+    const T fyz = f[1] * f[2], fxz = f[0] * f[2], fxy = f[0] * f[1];
+    const T P = f[0] * fyz;
+    const T Px = f1[0] * fyz, Py = f1[1] * fxz, Pz = f1[2] * fxy;
+    const T Pxx = f2[0] * fyz, Pyy = f2[1] * fxz, Pzz = f2[2] * fxy;
+    const T Pxy = f1[0] * f1[1] * f[2], Pxz = f1[0] * f1[2] * f[1], Pyz = f1[1] * f1[2] * f[0];
+    const T lapP = Pxx + Pyy + Pzz;
+    const T PR1 = P * u1, PR2 = P * u2;                   // 2 P R', 4 P R''
+    const T Pxu = Px * u1, Pyu = Py * u1, Pzu = Pz * u1;  // 2 P_k R'
+    d[0] = P * R0;
+    d[1] = fma(Px, R0, x * PR1);
+    d[2] = fma(Py, R0, y * PR1);
+    d[3] = fma(Pz, R0, z * PR1);
+    // lapP R + (4l + 6) P R' + 4 rho P R''
+    d[4] = fma(lapP, R0, fma(L.h46, PR1, rho * PR2));
+    // P_kk R + 4 x_k P_k R' + 2 P R' + 4 x_k^2 P R''
+    const T xP2 = x * PR2, yP2 = y * PR2, zP2 = z * PR2;
+    d[5] = fma(Pxx, R0, fma(x + x, Pxu, fma(x, xP2, PR1)));
+    d[8] = fma(Pyy, R0, fma(y + y, Pyu, fma(y, yP2, PR1)));
+    d[10] = fma(Pzz, R0, fma(z + z, Pzu, fma(z, zP2, PR1)));
+    // P_kj R + 2 (x_j P_k + x_k P_j) R' + 4 x_k x_j P R''
+    d[6] = fma(Pxy, R0, fma(y, Pxu, fma(x, Pyu, x * yP2)));
+    d[7] = fma(Pxz, R0, fma(z, Pxu, fma(x, Pzu, x * zP2)));
+    d[9] = fma(Pyz, R0, fma(z, Pyu, fma(y, Pzu, y * zP2)));
+    // d_k lap = x_k (2 lapP R' + (8l + 20) P R'' + 8 rho P R''') + P_k ((4l + 6) R' + 4 rho R'')
+    const T S1 = fma(lapP, u1, fma(L.h820, PR2, rho * P * u3));
+    const T S2 = fma(L.h46, u1, rho * u2);
+    d[11] = fma(x, S1, Px * S2);
+    d[12] = fma(y, S1, Py * S2);
+    d[13] = fma(z, S1, Pz * S2);
+}
+
+// Sum over the 16 lanes of each DPP row, left in the row's last lane (lane
+// 15 of the row; the other lanes hold partial sums): an inclusive scan with
+// row shifts 1, 2, 4, 8, lanes shifted in from outside the row reading 0.
+template <int K>
+__device__ inline double dpp_row_shr(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x110 + K, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x110 + K, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ inline double row16_sum_last(double v) {
+    v += dpp_row_shr<1>(v);
+    v += dpp_row_shr<2>(v);
+    v += dpp_row_shr<4>(v);
+    v += dpp_row_shr<8>(v);
+    return v;
 }
 
 // All cartesian components of shell s at an electron, with the angular
