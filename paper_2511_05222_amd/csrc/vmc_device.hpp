@@ -101,30 +101,35 @@ __host__ __device__ inline T tpow(T x, int k) {
     return k <= 0 ? (k == 0 ? T(1) : T(0)) : (k == 1 ? x : x * x);
 }
 
-// e^{-x} for x = a rho >= 0 in the arithmetic type T.  In FP32 the product
-// is formed in FP64 and split as x = xh + xl (xh = fp32(x)), and
-// e^{-x} = e^{-xh} (1 - xl): rounding x itself to FP32 would cost a relative
-// error of x 2^-24 in the result (1e-6 at x = 20).
+// e^{-x} for x = a rho >= 0 in the arithmetic type T.  In FP32 the exponent
+// is formed in FP64 and split into FP32 parts before the exponential
+// (exp2_neg_split): rounding x itself to FP32 would cost a relative error of
+// x 2^-24 in the result (1e-6 at x = 20).
+__device__ inline float exp2_neg_split(double t);
 __host__ __device__ inline double exp_neg(double a, double rho, double) { return exp(-a * rho); }
-__host__ __device__ inline float exp_neg(double a, double rho, float) {
-    const double x = a * rho;
-    const float xh = (float)x;
-    const float xl = (float)(x - (double)xh);
-    return expf(-xh) * (1.0f - xl);
+__device__ inline float exp_neg(double a, double rho, float) {
+    return exp2_neg_split(a * rho * 1.4426950408889634);
+}
+
+// Entry of a table that no kernel writes, read through the constant address
+// space: with a wavefront-uniform index it becomes a scalar load.
+template <typename T>
+__device__ inline T ldc(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
 }
 
 // Radial sums of shell s at rho = |r - R_A|^2 (formed in FP64):
 // R0 = sum c' e^{-a rho} and its first three rho-derivatives (NC > 5 needs R3).
 template <int NC, typename T>
-__host__ __device__ inline void shell_radial(const BasisDev &B, int s, double rho, T &R0, T &R1, T &R2, T &R3) {
-    const int p0 = B.shell_p0[s], np = B.shell_np[s];
+__device__ inline void shell_radial(const BasisDev &B, int s, double rho, T &R0, T &R1, T &R2, T &R3) {
+    const int p0 = ldc(B.shell_p0 + s), np = ldc(B.shell_np + s);
     R0 = R1 = R2 = R3 = T(0);
     for (int k = 0; k < np; ++k) {
         // the exponent in the arithmetic type, used alike in the exponential
         // and in the derivative factors, so that value and derivatives belong
         // to one function
-        const T al = (T)B.prim_exp[p0 + k];
-        const T e = (T)B.prim_cp[p0 + k] * exp_neg((double)al, rho, T(0));
+        const T al = (T)ldc(B.prim_exp + p0 + k);
+        const T e = (T)ldc(B.prim_cp + p0 + k) * exp_neg((double)al, rho, T(0));
         R0 += e;
         if (NC > 1) {
             R1 -= al * e;
@@ -346,28 +351,30 @@ __device__ inline double row16_sum_last(double v) {
 // and nothing lands in per-lane scratch: stored straight to dst[q*NC + k] (LDS
 // or registers).  The displacement is formed in FP64 and rounded to T.
 template <int NC, typename T, int L>
-__host__ __device__ inline void shell_components(const BasisDev &B, int mu0, T x, T y, T z, T rho, T R0, T R1,
-                                                 T R2, T R3, T *dst) {
+__device__ inline void shell_components(const BasisDev &B, int mu0, T x, T y, T z, T rho, T R0, T R1, T R2, T R3,
+                                        T *dst) {
 #pragma unroll
     for (int q = 0; q < (L + 1) * (L + 2) / 2; ++q) {
         T o[NC];
-        ao_components<NC, T>(x, y, z, rho, R0, R1, R2, R3, cart_pow(L, q), (T)B.ao_eta[mu0 + q], o);
+        ao_components<NC, T>(x, y, z, rho, R0, R1, R2, R3, cart_pow(L, q), (T)ldc(B.ao_eta + mu0 + q), o);
 #pragma unroll
         for (int k = 0; k < NC; ++k) dst[q * NC + k] = o[k];
     }
 }
 
+// Shell s (uniform over the wavefront in the callers) at one electron per
+// lane; the basis tables and R are read with ldc.
 template <int NC, typename T>
-__host__ __device__ inline int shell_eval_to(const BasisDev &B, const double *R, int s, double rx, double ry,
-                                             double rz, T *dst) {
-    const int atom = B.shell_atom[s];
-    const double dx = rx - R[3 * atom], dy = ry - R[3 * atom + 1], dz = rz - R[3 * atom + 2];
+__device__ inline int shell_eval_to(const BasisDev &B, const double *R, int s, double rx, double ry, double rz,
+                                    T *dst) {
+    const int atom = ldc(B.shell_atom + s);
+    const double dx = rx - ldc(R + 3 * atom), dy = ry - ldc(R + 3 * atom + 1), dz = rz - ldc(R + 3 * atom + 2);
     const double rho_d = dx * dx + dy * dy + dz * dz;
     const T x = (T)dx, y = (T)dy, z = (T)dz;
     const T rho = (T)rho_d;
     T R0, R1, R2, R3;
     shell_radial<NC, T>(B, s, rho_d, R0, R1, R2, R3);
-    const int l = B.shell_l[s], mu0 = B.shell_mu0[s];
+    const int l = ldc(B.shell_l + s), mu0 = ldc(B.shell_mu0 + s);
     if (l == 0) {
         shell_components<NC, T, 0>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
         return 1;

@@ -43,9 +43,10 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
         // shell-major: a wavefront evaluates one shell at its 64 rows, so the
         // angular momentum (and the shell's tables) are uniform over it
         for (int p = tid; p < RB * nsh; p += 256) {
-            const int s = s0 + p / RB, r = p % RB;
+            // p / RB is the same in every lane of a wavefront: scalar tables
+            const int s = __builtin_amdgcn_readfirstlane(s0 + p / RB), r = p % RB;
             shell_eval_to<NC, T>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
-                                 aot + r * RS + (S.basis.shell_mu0[s] - mu0) * NC);
+                                 aot + r * RS + (ldc(S.basis.shell_mu0 + s) - mu0) * NC);
         }
         // zero the padding AOs of the tile
         for (int p = tid; p < RB * (MT - nmu) * NC; p += 256) {
