@@ -27,20 +27,6 @@
 
 namespace vmcx {
 
-// 1/sqrt(x) and 1/x (x > 0) in FP64: the hardware estimate refined by two
-// Newton-Raphson steps, y <- y (3 - x y^2) / 2 and y <- y (2 - x y).
-__device__ inline double rsqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    return y * (1.5 - 0.5 * x * y * y);
-}
-
-__device__ inline double rcp_nr(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    y = y * (2.0 - x * y);
-    return y * (2.0 - x * y);
-}
-
 __device__ inline double block_max4(double v, double *red) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));

@@ -387,6 +387,20 @@ __device__ inline int shell_eval_to(const BasisDev &B, const double *R, int s, d
     return 6;
 }
 
+// 1/sqrt(x) and 1/x (x > 0) in FP64: the hardware estimate refined by two
+// Newton-Raphson steps, y <- y (3 - x y^2) / 2 and y <- y (2 - x y).
+__device__ inline double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y * (1.5 - 0.5 * x * y * y);
+}
+
+__device__ inline double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * (2.0 - x * y);
+    return y * (2.0 - x * y);
+}
+
 // ---------------------------------------------------------------------------
 // Two-body Jastrow function u(r) and its derivatives:
 //   form 0 (Pade)       u = a r / (1 + F r)
@@ -400,12 +414,12 @@ struct JasD {
     double u, u1, u2, u3;
 };
 
-__host__ __device__ inline JasD jas_all(double r, double a, double F, int form) {
+__device__ inline JasD jas_all(double r, double a, double F, int form) {
     if (form == 1) {
         const double e = exp(-F * r), ae = a * e;
         return JasD{a * (1.0 - e) / F, ae, -F * ae, F * F * ae};
     }
-    const double q = 1.0 / (1.0 + F * r);
+    const double q = rcp_nr(1.0 + F * r);
     const double q2 = q * q;
     return JasD{a * r * q, a * q2, -2.0 * a * F * q2 * q, 6.0 * a * F * F * q2 * q2};
 }

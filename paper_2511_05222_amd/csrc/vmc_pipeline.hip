@@ -15,7 +15,8 @@ namespace vmcx {
 // ---------------------------------------------------------------------------
 // Space-warp helpers: omega_a(r) = kappa_a / sum_b kappa_b, kappa = d^-4;
 // grad omega_a = omega_a (g_a - sum_b omega_b g_b), g_b = -4 (r - R_b)/d_b^2.
-// Within 1e-12 bohr of nucleus c: omega = delta_ac, gradient 0.
+// Within 1e-12 bohr of nucleus c: omega = delta_ac, gradient 0.  The
+// reciprocals 1/d^2 come from rcp_nr (a few ulp from the rounded quotient).
 // ---------------------------------------------------------------------------
 struct WarpE {
     double invS;      // 1 / sum_b d_b^-4
@@ -30,17 +31,21 @@ __device__ inline WarpE warp_electron(const double *R0, int A, double x, double 
     for (int b = 0; b < A; ++b) {
         const double dx = x - R0[3 * b], dy = y - R0[3 * b + 1], dz = z - R0[3 * b + 2];
         const double d2 = dx * dx + dy * dy + dz * dz;
-        if (d2 < 1e-24) o.near = b;
-        S += 1.0 / (d2 * d2);
+        double id2 = 0.0;
+        if (d2 < 1e-24)
+            o.near = b;
+        else
+            id2 = rcp_nr(d2);
+        S += id2 * id2;
     }
     o.invS = 1.0 / S;
     o.sg[0] = o.sg[1] = o.sg[2] = 0.0;
     if (o.near < 0)
         for (int b = 0; b < A; ++b) {
             const double dx = x - R0[3 * b], dy = y - R0[3 * b + 1], dz = z - R0[3 * b + 2];
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            const double om = o.invS / (d2 * d2);
-            const double f = -4.0 / d2;
+            const double id2 = rcp_nr(dx * dx + dy * dy + dz * dz);
+            const double om = o.invS * id2 * id2;
+            const double f = -4.0 * id2;
             o.sg[0] += om * f * dx;
             o.sg[1] += om * f * dy;
             o.sg[2] += om * f * dz;
@@ -55,9 +60,9 @@ __device__ inline double warp_omega(const WarpE &we, const double *R0, int a, do
         return we.near == a ? 1.0 : 0.0;
     }
     const double dx = x - R0[3 * a], dy = y - R0[3 * a + 1], dz = z - R0[3 * a + 2];
-    const double d2 = dx * dx + dy * dy + dz * dz;
-    const double om = we.invS / (d2 * d2);
-    const double f = -4.0 / d2;
+    const double id2 = rcp_nr(dx * dx + dy * dy + dz * dz);
+    const double om = we.invS * id2 * id2;
+    const double f = -4.0 * id2;
     g[0] = om * (f * dx - we.sg[0]);
     g[1] = om * (f * dy - we.sg[1]);
     g[2] = om * (f * dz - we.sg[2]);
@@ -136,8 +141,8 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
         for (int k = 0; k < N; ++k) {
             if (k == e) continue;
             const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            const double ir = 1.0 / r;
+            const double ir = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+            const double r = (dx * dx + dy * dy + dz * dz) * ir;
             const double ux = dx * ir, uy = dy * ir, uz = dz * ir;
             const JasD pd = jas_all(r, S.ee_a, S.ee_F, S.ee_form);
             const double vx = ge[0] + (gb[6 * k + 3] + gb[6 * k]);
@@ -159,8 +164,8 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
         }
         for (int a = 0; a < A; ++a) {
             const double dx = x - R[3 * a], dy = y - R[3 * a + 1], dz = z - R[3 * a + 2];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double f = S.Z[a] / (r2 * sqrt(r2));
+            const double ir = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+            const double f = S.Z[a] * ir * ir * ir;
             d0 += f * dx;
             d1 += f * dy;
             d2 += f * dz;
@@ -221,8 +226,8 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
         const double Rx = R[3 * a], Ry = R[3 * a + 1], Rz = R[3 * a + 2], Za = S.Z[a];
         for (int e = j; e < N; e += tpa) {
             const double dx = p[3 * e] - Rx, dy = p[3 * e + 1] - Ry, dz = p[3 * e + 2] - Rz;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double f = Za / (r2 * sqrt(r2));
+            const double ir = rsqrt_nr(dx * dx + dy * dy + dz * dz);
+            const double f = Za * ir * ir * ir;
             sE[0] -= f * dx;
             sE[1] -= f * dy;
             sE[2] -= f * dz;
