@@ -67,49 +67,17 @@ __device__ inline void neumaier(double &s, double &c, double x) {
 }
 
 // partial[seg][o] = sum over walkers of segment seg (Neumaier, fixed order).
-// The O and G elements (most of the element space) load PS_U walkers ahead of
-// the accumulation; the thread of an O element also forms the e O element
-// from the same load (the e O threads return at once).
+// Partial sums over one walker segment (blockIdx.y) of elements [0, n_elem)
+// of a partial row of n_out elements; in mode 0 only the leading elements
+// (everything before O), the O / e O / G elements going to k_partial_sums_og.
 constexpr int PS_U = 8;
 
-__global__ void k_partial_sums(EstArgs a, int mode, int64_t n_out, int64_t W, int64_t seg_len,
+__global__ void k_partial_sums(EstArgs a, int mode, int64_t n_elem, int64_t n_out, int64_t W, int64_t seg_len,
                                double *partial) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t seg = blockIdx.y;
-    if (o >= n_out) return;
+    if (o >= n_elem) return;
     const int64_t k0 = seg * seg_len, k1 = min(W, k0 + seg_len);
-    if (mode == 0) {
-        const int64_t oO = 2 + 3 * a.A3, Mn = a.Mn;
-        if (o >= oO + Mn && o < oO + 2 * Mn) return;
-        if (o >= oO) {
-            const bool isO = o < oO + Mn;
-            const int64_t i = isO ? o - oO : o - oO - 2 * Mn;
-            const double sh = a.shift[0];
-            double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
-            int64_t k = k0;
-            for (; k + PS_U <= k1; k += PS_U) {
-                double x[PS_U], e[PS_U];
-#pragma unroll
-                for (int u = 0; u < PS_U; ++u) {
-                    x[u] = isO ? est_O(a, (k + u) * Mn + i) : est_G(a, (k + u) * Mn + i);
-                    e[u] = a.EL[k + u] - sh;
-                }
-#pragma unroll
-                for (int u = 0; u < PS_U; ++u) {
-                    neumaier(s1, c1, x[u]);
-                    if (isO) neumaier(s2, c2, e[u] * x[u]);
-                }
-            }
-            for (; k < k1; ++k) {
-                const double x = isO ? est_O(a, k * Mn + i) : est_G(a, k * Mn + i);
-                neumaier(s1, c1, x);
-                if (isO) neumaier(s2, c2, (a.EL[k] - sh) * x);
-            }
-            partial[seg * n_out + o] = s1 + c1;
-            if (isO) partial[seg * n_out + o + Mn] = s2 + c2;
-            return;
-        }
-    }
     double s = 0.0, c = 0.0;
     int64_t k = k0;
     for (; k + PS_U <= k1; k += PS_U) {
@@ -121,6 +89,47 @@ __global__ void k_partial_sums(EstArgs a, int mode, int64_t n_out, int64_t W, in
     }
     for (; k < k1; ++k) neumaier(s, c, mode == 0 ? est_term(a, o, k) : vjp_term(a, o, k));
     partial[seg * n_out + o] = s + c;
+}
+
+// Mode 0, the O, e O and G elements (most of the element space): thread
+// t < Mn takes O element t and forms e O from the same load, Mn <= t < 2 Mn
+// takes G element t - Mn.  PS_OG walkers are loaded ahead; their energies are
+// the same in every lane (scalar loads).  Few registers, so that enough
+// wavefronts are resident to keep HBM busy.
+constexpr int PS_OG = 16;
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_partial_sums_og(const S *__restrict__ O, const S *__restrict__ G,
+                                                         EstArgs a, int64_t n_out, int64_t W, int64_t seg_len,
+                                                         double *partial) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Mn = a.Mn, oO = 2 + 3 * a.A3;
+    if (t >= 2 * Mn) return;
+    const bool isO = t < Mn;
+    const int64_t i = isO ? t : t - Mn;
+    const S *src = isO ? O : G;
+    const int64_t seg = blockIdx.y, k0 = seg * seg_len, k1 = min(W, k0 + seg_len);
+    const double sh = ldc(a.shift);
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    int64_t k = k0;
+    for (; k + PS_OG <= k1; k += PS_OG) {
+        S x[PS_OG];
+#pragma unroll
+        for (int u = 0; u < PS_OG; ++u) x[u] = src[(k + u) * Mn + i];
+#pragma unroll
+        for (int u = 0; u < PS_OG; ++u) {
+            const double xv = (double)x[u];
+            neumaier(s1, c1, xv);
+            if (isO) neumaier(s2, c2, (ldc(a.EL + k + u) - sh) * xv);
+        }
+    }
+    for (; k < k1; ++k) {
+        const double xv = (double)src[k * Mn + i];
+        neumaier(s1, c1, xv);
+        if (isO) neumaier(s2, c2, (ldc(a.EL + k) - sh) * xv);
+    }
+    partial[seg * n_out + oO + (isO ? i : 2 * Mn + i)] = s1 + c1;
+    if (isO) partial[seg * n_out + oO + Mn + i] = s2 + c2;
 }
 
 // acc[o] (+ comp[o]) += sum_seg partial[seg][o]  (Neumaier, fixed order);
@@ -596,8 +605,19 @@ hipError_t launch_reduce(const EstArgs &a, int mode, int64_t n_out, int64_t W, d
     int64_t n_seg = std::min<int64_t>(max_seg, std::max<int64_t>(1, (W + 63) / 64));
     const int64_t seg_len = (W + n_seg - 1) / n_seg;
     n_seg = (W + seg_len - 1) / seg_len;
-    dim3 g1((unsigned)((n_out + 255) / 256), (unsigned)n_seg);
-    hipLaunchKernelGGL(k_partial_sums, g1, dim3(256), 0, st, a, mode, n_out, W, seg_len, partial);
+    // mode 0: the leading elements here, O / e O / G in k_partial_sums_og
+    const int64_t n_elem = mode == 0 ? 2 + 3 * a.A3 : n_out;
+    dim3 g1((unsigned)((n_elem + 255) / 256), (unsigned)n_seg);
+    hipLaunchKernelGGL(k_partial_sums, g1, dim3(256), 0, st, a, mode, n_elem, n_out, W, seg_len, partial);
+    if (mode == 0) {
+        dim3 g2((unsigned)((2 * a.Mn + 255) / 256), (unsigned)n_seg);
+        if (a.Of != nullptr)
+            hipLaunchKernelGGL(k_partial_sums_og<float>, g2, dim3(256), 0, st, a.Of, a.Gf, a, n_out, W, seg_len,
+                               partial);
+        else
+            hipLaunchKernelGGL(k_partial_sums_og<double>, g2, dim3(256), 0, st, a.O, a.G, a, n_out, W, seg_len,
+                               partial);
+    }
     hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, partial, n_out,
                        n_seg, acc, comp, blk, blk_all);
     return hipGetLastError();
