@@ -87,7 +87,9 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
         typename MF::acc_t accO[NT], accG[NT];
 #pragma unroll
         for (int it = 0; it < NT; ++it) accO[it] = accG[it] = MF::zero();
-        double tl[6] = {0, 0, 0, 0, 0, 0};
+        // per-AO sums over this lane's 4 RT electrons in T, then over the
+        // four row groups in FP64
+        T tl[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         for (int rt = 0; rt < RT; ++rt) {
             typename MF::acc_t kap = MF::zero(), aa = MF::zero();
             const T *kr = Ks + (16 * rt + ml) * ldk + kg;
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
             for (int v = 0; v < 4; ++v) {
                 const int e = 16 * rt + MF::row(lane, v);
                 T psi = T(0), q = T(0);
-                double t6[6] = {0, 0, 0, 0, 0, 0};
+                T t6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
                 if (e < N && vm) {
                     const double dx = sp[3 * e] - Rx, dy = sp[3 * e + 1] - Ry, dz = sp[3 * e + 2] - Rz;
                     const double rho_d = dx * dx + dy * dy + dz * dz;
@@ -117,12 +119,12 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                     const T hgz = gx * d[7] + gy * d[9] + gz * d[10];
                     const T half = T(0.5);
                     const T kv = kap[v], av = aa[v];
-                    t6[0] = (double)(av * d[1] - kv * (hgx + half * d[11]));
-                    t6[1] = (double)(av * d[2] - kv * (hgy + half * d[12]));
-                    t6[2] = (double)(av * d[3] - kv * (hgz + half * d[13]));
-                    t6[3] = (double)(kv * d[1]);
-                    t6[4] = (double)(kv * d[2]);
-                    t6[5] = (double)(kv * d[3]);
+                    t6[0] = av * d[1] - kv * (hgx + half * d[11]);
+                    t6[1] = av * d[2] - kv * (hgy + half * d[12]);
+                    t6[2] = av * d[3] - kv * (hgz + half * d[13]);
+                    t6[3] = kv * d[1];
+                    t6[4] = kv * d[2];
+                    t6[5] = kv * d[3];
                     psi = d[0];
                     q = -(gx * d[1] + gy * d[2] + gz * d[3]) - half * d[4];
                 }
@@ -130,7 +132,8 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                 for (int c = 0; c < 6; ++c) tl[c] += t6[c];
                 // AO sum of t_k for electron e over the 16 lanes of this row
                 // group (a DPP row), left in its last lane
-                const double d0 = row16_sum_last(t6[0]), d1 = row16_sum_last(t6[1]), d2 = row16_sum_last(t6[2]);
+                const double d0 = (double)row16_sum_last<T>(t6[0]), d1 = (double)row16_sum_last<T>(t6[1]),
+                             d2 = (double)row16_sum_last<T>(t6[2]);
                 if (ml == 15 && e < N) {
                     dw[3 * e] += d0;
                     dw[3 * e + 1] += d1;
@@ -165,14 +168,16 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
             }
         }
         // electron sums per AO: add the four row groups
+        double td[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            tl[c] += __shfl_xor(tl[c], 16, 64);
-            tl[c] += __shfl_xor(tl[c], 32, 64);
+            td[c] = (double)tl[c];
+            td[c] += __shfl_xor(td[c], 16, 64);
+            td[c] += __shfl_xor(td[c], 32, 64);
         }
         if (kg == 0 && vm)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) mb.tao[((size_t)w * M + mu) * 6 + c] = tl[c];
+            for (int c = 0; c < 6; ++c) mb.tao[((size_t)w * M + mu) * 6 + c] = td[c];
     }
     __syncthreads();
     // dE_L/dr_e (determinant part): the wavefronts' partials in a fixed order

@@ -338,7 +338,13 @@ __device__ inline double dpp_row_shr(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ inline double row16_sum_last(double v) {
+template <int K>
+__device__ inline float dpp_row_shr(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x110 + K, 0xF, 0xF, true));
+}
+
+template <typename T>
+__device__ inline T row16_sum_last(T v) {
     v += dpp_row_shr<1>(v);
     v += dpp_row_shr<2>(v);
     v += dpp_row_shr<4>(v);
