@@ -86,6 +86,7 @@ struct vmc_ctx {
     int *Kstale = nullptr;   // [max_walkers][2]
     float *d_Cf = nullptr;   // C in FP32 (mixed precision)
     float *d_Cm = nullptr;   // FP32 copy of a caller's C (mixed precision)
+    double *d_cpad = nullptr;   // C padded for the MO-row kernel ((M + 16) x 64, either type)
     // FP64 re-measurement of the walkers whose E_L is most sensitive to the
     // FP32 orbital values (mixed precision)
     AdjLayout al64{};
@@ -304,7 +305,7 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
                    c->mb_dpart, c->mb_tao, pkey,      (const T *)ks.K,                  ks.sig,
                    ks.stale};
     int pi = prof_begin(c, VMC_K_MO_ROWS, prof, cw, st);
-    HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, st));
+    HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, (T *)c->d_cpad, st));
     prof_end(c, VMC_K_MO_ROWS, pi, st);
     pi = prof_begin(c, VMC_K_DENSE, prof, cw, st);
     HIP_OK(c, vmcx::launch_dense<T>(S, R, mb, o, c->status, c->dl, (int)cw, st));
@@ -573,6 +574,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         if ((rc = c->upload(&c->d_Cf, cf.data(), cf.size())) || (rc = c->dalloc(&c->d_Cm, cf.size())))
             return bail(rc);
     }
+    if ((rc = c->dalloc(&c->d_cpad, (size_t)(M + 16) * 64))) return bail(rc);
 
     SysDev &sd = c->sys;
     sd.N = c->N;
@@ -693,7 +695,7 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
             float *Amo = (float *)c->Amo;
             if (t == 0)
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, walkers, W * c->N, c->tiles16,
-                                                          Amo, 1, st));
+                                                          Amo, 1, (float *)c->d_cpad, st));
             const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
             const vmcx::KState<float> ks{(float *)c->Kst, c->Ksig, c->Kstale};
             HIP_OK(c, vmcx::launch_sweep<float>(c->sys, c->d_Cf, c->d_R, walkers, (int)W, Amo, ks, t == 0, sidx,
@@ -704,7 +706,7 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
             double *Amo = (double *)c->Amo;
             if (t == 0)
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
-                                                           Amo, 1, st));
+                                                           Amo, 1, c->d_cpad, st));
             const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
             const vmcx::KState<double> ks{(double *)c->Kst, c->Ksig, c->Kstale};
             HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, Amo, ks, t == 0, sidx,

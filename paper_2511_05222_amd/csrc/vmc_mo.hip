@@ -4,7 +4,10 @@
 //   (NC = 1: values;  NC = 5: value, gradient, Laplacian)
 //
 // A block owns 64 rows (one 16-row tile per wavefront) and all n orbitals
-// (NT tiles of 16 columns).  AO tiles of whole shells (<= 16 AOs) are
+// (NT tiles of 16 columns).  C is read from a copy padded to 64 columns and
+// 16 extra zero rows (k_pad_c), one 16-byte vector per thread and tile.  The
+// AO tile is zeroed once: its AOs past the tile's last one then hold finite
+// values of earlier tiles, which meet zero rows of the C tile.  AO tiles of whole shells (<= 16 AOs) are
 // produced in LDS by a GTO evaluation that gives each wavefront one shell at
 // all 64 rows (uniform angular momentum) and consumed in k-steps of
 // 4 AOs by 16x16x4 MFMA (FP64: v_mfma_f64_16x16x4_f64; FP32:
@@ -14,8 +17,17 @@
 
 namespace vmcx {
 
+// Cp[mu][i] = C[mu][i] for mu < M, i < n; zero elsewhere ([M + 16][64]).
+template <typename T>
+__global__ void k_pad_c(const T *__restrict__ C, int M, int n, T *__restrict__ Cp) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (M + 16) * 64) return;
+    const int mu = k >> 6, i = k & 63;
+    Cp[k] = (mu < M && i < n) ? C[(size_t)mu * n + i] : T(0);
+}
+
 template <typename T, int NC, int NT>
-__global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restrict__ C, const double *__restrict__ R,
+__global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restrict__ Cp, const double *__restrict__ R,
                                                       const double *__restrict__ pos, int64_t n_rows, AoTiles tiles,
                                                       T *__restrict__ out) {
     constexpr int RB = 64, MT = 16;
@@ -29,6 +41,7 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
     const int n = S.n_occ;
     const int64_t row0 = (int64_t)blockIdx.x * RB;
     for (int k = tid; k < RB * 3; k += 256) sp[k] = (row0 + k / 3) < n_rows ? pos[row0 * 3 + k] : 0.0;
+    for (int k = tid; k < RB * RS; k += 256) aot[k] = T(0);
     typename MF::acc_t acc[NC][NT];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -48,14 +61,13 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
             shell_eval_to<NC, T>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
                                  aot + r * RS + (ldc(S.basis.shell_mu0 + s) - mu0) * NC);
         }
-        // zero the padding AOs of the tile
-        for (int p = tid; p < RB * (MT - nmu) * NC; p += 256) {
-            const int r = p / ((MT - nmu) * NC), q = p - r * ((MT - nmu) * NC);
-            aot[r * RS + nmu * NC + q] = T(0);
-        }
-        for (int p = tid; p < MT * 64; p += 256) {
-            const int m = p >> 6, i = p & 63;
-            ct[m * CS + i] = (m < nmu && i < n) ? C[(size_t)(mu0 + m) * n + i] : T(0);
+        // C tile: rows of the tile's AOs, zero rows past its last AO
+        constexpr int VW = 16 / sizeof(T);
+        typedef T V __attribute__((ext_vector_type(VW)));
+        for (int p = tid; p < MT * 64 / VW; p += 256) {
+            const int m = p / (64 / VW), i = (p - m * (64 / VW)) * VW;
+            const V v = *(const V *)(Cp + (size_t)(mu0 + m) * 64 + i);
+            *(V *)(ct + m * CS + i) = m < nmu ? v : V(T(0));
         }
         __syncthreads();
         const int ksteps = (nmu + 3) >> 2;
@@ -90,6 +102,7 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
 template <typename T, int NC>
 static hipError_t launch_nc(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
                             const AoTiles &tiles, T *out, hipStream_t st) {
+    // (C here is the padded copy)
     const dim3 g((unsigned)((n_rows + 63) / 64));
     const int nt = (S.n_occ + 15) / 16;
     if (nt == 1)
@@ -105,15 +118,18 @@ static hipError_t launch_nc(const SysDev &S, const T *C, const double *R, const 
 
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
-                               const AoTiles &tiles16, T *out, int nc, hipStream_t st) {
-    return nc == 1 ? launch_nc<T, 1>(S, C, R, pos, n_rows, tiles16, out, st)
-                   : launch_nc<T, 5>(S, C, R, pos, n_rows, tiles16, out, st);
+                               const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st) {
+    if (S.n_occ > 64) return hipErrorInvalidValue;
+    const int np = (S.M + 16) * 64;
+    hipLaunchKernelGGL(k_pad_c<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, C, S.M, S.n_occ, cpad);
+    return nc == 1 ? launch_nc<T, 1>(S, cpad, R, pos, n_rows, tiles16, out, st)
+                   : launch_nc<T, 5>(S, cpad, R, pos, n_rows, tiles16, out, st);
 }
 
 template hipError_t launch_mo_rows_mfma<double>(const SysDev &, const double *, const double *, const double *,
-                                                int64_t, const AoTiles &, double *, int, hipStream_t);
+                                                int64_t, const AoTiles &, double *, int, double *, hipStream_t);
 
 template hipError_t launch_mo_rows_mfma<float>(const SysDev &, const float *, const double *, const double *,
-                                               int64_t, const AoTiles &, float *, int, hipStream_t);
+                                               int64_t, const AoTiles &, float *, int, float *, hipStream_t);
 
 }  // namespace vmcx

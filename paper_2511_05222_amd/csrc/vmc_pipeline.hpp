@@ -77,9 +77,10 @@ struct MeasBufsD {
     const double *gb, *dedr_part, *tao;
 };
 
+// cpad: scratch of (M + 16) * 64 elements for the padded copy of C (n_occ <= 64)
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
-                               const AoTiles &tiles16, T *out, int nc, hipStream_t st);
+                               const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st);
 // Persistent inverses of the two spin blocks of every walker, in the
 // register layout of the sweep: K[w][b][r][lane] (KN x KN, type T), the
 // permutation sig[w][b][lane] and stale[w][b] = a rebuild is due.
