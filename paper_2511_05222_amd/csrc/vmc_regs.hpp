@@ -77,11 +77,12 @@ __device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &lo
             used = true;
             sig = k;
         }
-        // pivot row: B[p][j] / piv;  other rows: B[i][j] - (B[i][k] / piv) B[p][j]
-        const double g = me ? -inv : a0 * inv;
-        const double h = me ? 0.0 : 1.0;
+        // other rows: B[i][j] - (B[i][k] / piv) B[p][j];  pivot row: B[p][j] / piv,
+        // formed by the same fma as B[p][j] - (1 - 1/piv) B[p][j] (its own
+        // row; relative error |piv - 1| 2^-53 from rounding 1 - 1/piv)
+        const double g = me ? 1.0 - inv : a0 * inv;
 #pragma unroll
-        for (int r = 0; r + 1 < KN; ++r) Br[r] = fma(-g, readlane_d(Br[r + 1], p), h * Br[r + 1]);
+        for (int r = 0; r + 1 < KN; ++r) Br[r] = fma(-g, readlane_d(Br[r + 1], p), Br[r + 1]);
         Br[KN - 1] = me ? inv : -a0 * inv;
     }
 }

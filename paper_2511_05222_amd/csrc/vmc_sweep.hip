@@ -115,7 +115,6 @@ template <typename T>
 __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, double rx, double ry, double rz,
                                        double ex, double ey, double ez, const double *px, const double *py,
                                        const double *pz) {
-    double dj;
     if constexpr (sizeof(T) == sizeof(float)) {
         const float a = (float)S.ee_a, F = (float)S.ee_F;
         const float aF = S.ee_form == 1 ? (float)(S.ee_a / S.ee_F) : 0.0f;
@@ -133,9 +132,15 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
                                       a * rb * __builtin_amdgcn_rcpf(1.0f + F * rb);
             d += (k < N && k != e) ? t : 0.0f;
         }
-        dj = (double)d;
+        // wavefront sum in FP32: DPP sums of the four rows, then their totals
+        d = row16_sum_last<float>(d);
+        const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), 15));
+        const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), 31));
+        const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), 47));
+        const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), 63));
+        return (double)((r0 + r1) + (r2 + r3));
     } else {
-        dj = 0.0;
+        double dj = 0.0;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             const int k = lane + 64 * hh;
@@ -146,10 +151,10 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
                       jas_u(sqrt(bx * bx + by * by + bz * bz), S.ee_a, S.ee_F, S.ee_form);
             }
         }
-    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dj += __shfl_xor(dj, o, 64);
-    return dj;
+        for (int o = 32; o > 0; o >>= 1) dj += __shfl_xor(dj, o, 64);
+        return dj;
+    }
 }
 
 // FP32 with KN <= 48 fits three wavefronts per SIMD (spilling a little in the
@@ -267,13 +272,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         // phi_i(r') = sum_mu psi_mu C[mu][i]; lane group lg sums its AO range
         T ph = T(0);
         if (li < nb) {
+            // FP64 up to KN = 48: four vectors per step (8 products per
+            // address increment); otherwise two (four would spill in the
+            // rebuild)
             V a0 = V(T(0)), a1 = V(T(0));
             int k = 0;
-            for (; k + 2 <= nvec; k += 2) {
-                a0 += svec[k] * cvec[k];
-                a1 += svec[k + 1] * cvec[k + 1];
+            if constexpr (sizeof(T) == 8 && KN <= 48) {
+                V a2 = V(T(0)), a3 = V(T(0));
+                for (; k + 4 <= nvec; k += 4) {
+                    a0 += svec[k] * cvec[k];
+                    a1 += svec[k + 1] * cvec[k + 1];
+                    a2 += svec[k + 2] * cvec[k + 2];
+                    a3 += svec[k + 3] * cvec[k + 3];
+                }
+                a0 += a2;
+                a1 += a3;
+            } else {
+                for (; k + 2 <= nvec; k += 2) {
+                    a0 += svec[k] * cvec[k];
+                    a1 += svec[k + 1] * cvec[k + 1];
+                }
             }
-            if (k < nvec) a0 += svec[k] * cvec[k];
+            for (; k < nvec; ++k) a0 += svec[k] * cvec[k];
             a0 += a1;
             ph = Vec16<T>::sum(a0);
         }
