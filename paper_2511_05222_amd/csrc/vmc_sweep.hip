@@ -313,7 +313,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         // the lane holding electron jj of the block
         const int pj = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(__ballot(sig == jj)));
         const double ratio = (double)readlane_t(v, pj);
-        const double qv = ratio * exp(dj);
+        // (FP32 sweep: the FP32 exponential, as accurate as its ratio)
+        const double qv = ratio * (sizeof(T) == sizeof(float) ? (double)expf((float)dj) : exp(dj));
         const bool acc = u < qv * qv;
         if (acc) {
             if (lane < nb && lg == 0) Aw[(size_t)e * n + lane] = ph;
