@@ -272,12 +272,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         // phi_i(r') = sum_mu psi_mu C[mu][i]; lane group lg sums its AO range
         T ph = T(0);
         if (li < nb) {
-            // FP64 up to KN = 48: four vectors per step (8 products per
-            // address increment); otherwise two (four would spill in the
-            // rebuild)
+            // up to KN = 48: four vectors per step (16 FP32 or 8 FP64
+            // products per address increment); otherwise two (four would
+            // spill in the rebuild)
             V a0 = V(T(0)), a1 = V(T(0));
             int k = 0;
-            if constexpr (sizeof(T) == 8 && KN <= 48) {
+            if constexpr (KN <= 48) {
                 V a2 = V(T(0)), a3 = V(T(0));
                 for (; k + 4 <= nvec; k += 4) {
                     a0 += svec[k] * cvec[k];
