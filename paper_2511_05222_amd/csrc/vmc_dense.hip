@@ -293,13 +293,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 }
             }
             if (lane < KN) Xs[j * ldk + lane] = xv;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                bx += __shfl_xor(bx, o, 64);
-                by += __shfl_xor(by, o, 64);
-                bz += __shfl_xor(bz, o, 64);
-                lp += __shfl_xor(lp, o, 64);
-            }
+            bx = wave_sum_dpp(bx);
+            by = wave_sum_dpp(by);
+            bz = wave_sum_dpp(bz);
+            lp = wave_sum_dpp(lp);
             if (lane == 0) {
                 gb[6 * e + 0] = gx;
                 gb[6 * e + 1] = gy;

@@ -352,6 +352,21 @@ __device__ inline T row16_sum_last(T v) {
     return v;
 }
 
+// Sum over the wavefront (all 64 lanes active), the same in every lane: the
+// four DPP row sums, then their totals by lane reads, in a fixed order.
+__device__ inline double wave_sum_dpp(double v) {
+    v = row16_sum_last<double>(v);
+    const long long b = __double_as_longlong(v);
+    double r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int lo = __builtin_amdgcn_readlane((int)b, 16 * q + 15);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * q + 15);
+        r[q] = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    }
+    return (r[0] + r[1]) + (r[2] + r[3]);
+}
+
 // All cartesian components of shell s at an electron, with the angular
 // momentum fixed at compile time so that every component index is a constant
 // and nothing lands in per-lane scratch: stored straight to dst[q*NC + k] (LDS
