@@ -38,8 +38,7 @@ __device__ inline double block_max4(double v, double *red) {
 }
 
 __device__ inline double block_sum4(double v, double *red) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum_dpp(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) red[wid] = v;

@@ -151,9 +151,7 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
                       jas_u(sqrt(bx * bx + by * by + bz * bz), S.ee_a, S.ee_F, S.ee_form);
             }
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) dj += __shfl_xor(dj, o, 64);
-        return dj;
+        return wave_sum_dpp(dj);
     }
 }
 
