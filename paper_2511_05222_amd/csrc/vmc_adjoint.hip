@@ -76,6 +76,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
         // this lane's AO: monomial and primitives in registers for the sub-tile
         AoLane<T, NPR> al;
         ao_lane_load<T, NPR>(S.basis, vm ? mu : M - 1, al);
+        if (!vm) al.c0[0] = al.c1[0] = al.c2[0] = al.c22[0] = T(0);   // no AO: every component 0
         const int atom = S.basis.shell_atom[S.basis.ao_shell[vm ? mu : M - 1]];
         const double Rx = R[3 * atom], Ry = R[3 * atom + 1], Rz = R[3 * atom + 2];
         T cB[KS];
@@ -99,35 +100,30 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                 kap = MF::fma(kr[4 * ks], cB[ks], kap);
                 aa = MF::fma(ar[4 * ks], cB[ks], aa);
             }
-            // one (e, mu) evaluation at a time: unrolled, four would be live
+            // one (e, mu) evaluation at a time: unrolled, four would be live.
+            // Every lane evaluates: past the last AO all components are 0,
+            // past the last electron (position of electron N - 1) kappa, a
+            // and the K~ / Abar rows are 0, so nothing of it reaches a sum.
 #pragma unroll 1
             for (int v = 0; v < 4; ++v) {
-                const int e = 16 * rt + MF::row(lane, v);
-                T psi = T(0), q = T(0);
-                T t6[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-                if (e < N && vm) {
-                    const double dx = sp[3 * e] - Rx, dy = sp[3 * e + 1] - Ry, dz = sp[3 * e + 2] - Rz;
-                    const double rho_d = dx * dx + dy * dy + dz * dz;
-                    const T x = (T)dx, y = (T)dy, z = (T)dz, rho = (T)rho_d;
-                    T R0, u1, u2, u3;
-                    ao_lane_radial<T, NPR>(al, S.basis, rho_d, R0, u1, u2, u3);
-                    T d[14];
-                    ao_lane_components<T, NPR>(al, x, y, z, rho, R0, u1, u2, u3, d);
-                    const T gx = (T)sg[3 * e], gy = (T)sg[3 * e + 1], gz = (T)sg[3 * e + 2];
-                    const T hgx = gx * d[5] + gy * d[6] + gz * d[7];
-                    const T hgy = gx * d[6] + gy * d[8] + gz * d[9];
-                    const T hgz = gx * d[7] + gy * d[9] + gz * d[10];
-                    const T half = T(0.5);
-                    const T kv = kap[v], av = aa[v];
-                    t6[0] = av * d[1] - kv * (hgx + half * d[11]);
-                    t6[1] = av * d[2] - kv * (hgy + half * d[12]);
-                    t6[2] = av * d[3] - kv * (hgz + half * d[13]);
-                    t6[3] = kv * d[1];
-                    t6[4] = kv * d[2];
-                    t6[5] = kv * d[3];
-                    psi = d[0];
-                    q = -(gx * d[1] + gy * d[2] + gz * d[3]) - half * d[4];
-                }
+                const int e = 16 * rt + MF::row(lane, v), ec = min(e, N - 1);
+                const double dx = sp[3 * ec] - Rx, dy = sp[3 * ec + 1] - Ry, dz = sp[3 * ec + 2] - Rz;
+                const double rho_d = dx * dx + dy * dy + dz * dz;
+                const T x = (T)dx, y = (T)dy, z = (T)dz, rho = (T)rho_d;
+                T R0, u1, u2, u3;
+                ao_lane_radial<T, NPR>(al, S.basis, rho_d, R0, u1, u2, u3);
+                T d[14];
+                ao_lane_components<T, NPR>(al, x, y, z, rho, R0, u1, u2, u3, d);
+                const T gx = (T)sg[3 * ec], gy = (T)sg[3 * ec + 1], gz = (T)sg[3 * ec + 2];
+                const T hgx = gx * d[5] + gy * d[6] + gz * d[7];
+                const T hgy = gx * d[6] + gy * d[8] + gz * d[9];
+                const T hgz = gx * d[7] + gy * d[9] + gz * d[10];
+                const T half = T(0.5);
+                const T kv = kap[v], av = aa[v];
+                const T t6[6] = {av * d[1] - kv * (hgx + half * d[11]), av * d[2] - kv * (hgy + half * d[12]),
+                                 av * d[3] - kv * (hgz + half * d[13]), kv * d[1], kv * d[2], kv * d[3]};
+                const T psi = d[0];
+                const T q = -(gx * d[1] + gy * d[2] + gz * d[3]) - half * d[4];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) tl[c] += t6[c];
                 // AO sum of t_k for electron e over the 16 lanes of this row

@@ -206,10 +206,10 @@ struct AoLane {
     // monomial eta x^a y^b z^c as a product of per-axis quadratics
     // f_q(t) = c0 + c1 t + c2 t^2 with one-hot coefficients (eta folded into
     // the x axis), so that f, f' = c1 + 2 c2 t and f'' = 2 c2 need no branch
-    T c0[3], c1[3], c2[3];
+    T c0[3], c1[3], c2[3], c22[3];   // c22 = 2 c2
     T h46, h820;               // (4l + 6) / 2 and (8l + 20) / 4
     int np, p0;                // primitives of the shell
-    T al[NPR], cp[NPR];        // first NPR exponents (in T) and coefficients
+    T al[NPR], al2[NPR], al3[NPR], cp[NPR];   // first NPR exponents (in T), their powers, coefficients
     double alt[NPR];           // al * log2(e) in FP64 (FP32 exponential)
 };
 
@@ -224,6 +224,7 @@ __device__ inline void ao_lane_load(const BasisDev &B, int mu, AoLane<T, NPR> &L
         L.c0[q] = p == 0 ? sc : T(0);
         L.c1[q] = p == 1 ? sc : T(0);
         L.c2[q] = p == 2 ? sc : T(0);
+        L.c22[q] = L.c2[q] + L.c2[q];
     }
     const int l = B.shell_l[s];
     L.h46 = T(2 * l + 3);
@@ -234,6 +235,8 @@ __device__ inline void ao_lane_load(const BasisDev &B, int mu, AoLane<T, NPR> &L
     for (int k = 0; k < NPR; ++k) {
         const int p = L.p0 + max(min(k, L.np - 1), 0);
         L.al[k] = (T)B.prim_exp[p];
+        L.al2[k] = L.al[k] * L.al[k];
+        L.al3[k] = L.al2[k] * L.al[k];
         L.cp[k] = k < L.np ? (T)B.prim_cp[p] : T(0);
         L.alt[k] = (double)L.al[k] * 1.4426950408889634;
     }
@@ -259,13 +262,11 @@ __device__ inline void ao_lane_radial(const AoLane<T, NPR> &L, const BasisDev &B
 #pragma unroll
     for (int k = 0; k < NPR; ++k) {
         // padded primitives carry cp = 0
-        const T al = L.al[k];
-        const T e = L.cp[k] * prim_exp_neg<T>(al, L.alt[k], rho);
-        const T w1 = al * e, w2 = al * w1;
+        const T e = L.cp[k] * prim_exp_neg<T>(L.al[k], L.alt[k], rho);
         r0 += e;
-        r1 -= w1;
-        r2 += w2;
-        r3 -= al * w2;
+        r1 = fma(-L.al[k], e, r1);
+        r2 = fma(L.al2[k], e, r2);
+        r3 = fma(-L.al3[k], e, r3);
     }
     for (int k = NPR; k < L.np; ++k) {
         const T al = (T)B.prim_exp[L.p0 + k];
@@ -294,7 +295,7 @@ __device__ inline void ao_lane_components(const AoLane<T, NPR> &L, T x, T y, T z
         const T h = fma(L.c2[q], r[q], L.c1[q]);
         f[q] = fma(h, r[q], L.c0[q]);
         f1[q] = fma(L.c2[q], r[q], h);
-        f2[q] = L.c2[q] + L.c2[q];
+        f2[q] = L.c22[q];
     }
     const T fyz = f[1] * f[2], fxz = f[0] * f[2], fxy = f[0] * f[1];
     const T P = f[0] * fyz;
