@@ -112,6 +112,10 @@ __global__ __launch_bounds__(128) void k_warp(SysDev S, const double *__restrict
 // ---------------------------------------------------------------------------
 // k_finalize: one block per walker.
 // ---------------------------------------------------------------------------
+// doubles of the region that holds Minv [N][9] and wS [N][4], then the
+// [128][9] partial sums of the per-nucleus phase
+__host__ __device__ inline int finalize_region(int N) { return 13 * N > 128 * 9 ? 13 * N : 128 * 9; }
+
 __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__restrict__ R,
                                                   const double *__restrict__ R0, MeasBufsD mb,
                                                   WalkerOut out, int warp) {
@@ -125,7 +129,8 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
     double *dEdr = gb + 6 * N;     // [N][3]
     double *Minv = dEdr + 3 * N;   // [N][9]
     double *wS = Minv + 9 * N;     // [N][4]: invS, sg
-    int *wnear = (int *)(wS + 4 * N);
+    // (Minv and wS, at least 128 x 9 doubles, later hold the partial sums)
+    int *wnear = (int *)(Minv + finalize_region(N));
     for (int i = tid; i < 3 * N; i += 128) {
         p[i] = mb.pos[(size_t)w * N * 3 + i];
         p0[i] = mb.pos0[(size_t)w * N * 3 + i];
@@ -208,11 +213,11 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
     __syncthreads();
     // per-nucleus sums: thread (a, j) takes electrons and AOs congruent to j
     // modulo tpa; the tpa partials of a nucleus are added in a fixed order
-    double *part = (double *)(wnear + N + (N & 1));   // [128][9], 8-byte aligned
+    double *part = Minv;   // [128][9] once Minv and wS are read
     const int tpa = 128 / A;
+    double sE[3] = {0, 0, 0}, sP[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
     if (tid < tpa * A) {
         const int a = tid / tpa, j = tid - (tid / tpa) * tpa;
-        double sE[3] = {0, 0, 0}, sP[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
         // this nucleus's AOs (congruent to j modulo tpa in its list)
         const int q0 = S.basis.atom_ao_ptr[a], q1 = S.basis.atom_ao_ptr[a + 1];
         for (int q = q0 + j; q < q1; q += tpa) {
@@ -257,6 +262,9 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
                 sE[1] -= f * dy;
                 sE[2] -= f * dz;
             }
+    }
+    __syncthreads();   // Minv and wS are read: the partials replace them
+    if (tid < tpa * A) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             part[9 * tid + k] = sE[k];
@@ -292,8 +300,8 @@ hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const
 
 hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb,
                            const WalkerOut &out, int warp, int W, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t)S.N * (3 + 3 + 6 + 3 + 9 + 4) + sizeof(int) * (size_t)(S.N + S.N % 2) +
-                       sizeof(double) * 128 * 9;
+    const size_t lds = sizeof(double) * ((size_t)S.N * (3 + 3 + 6 + 3) + (size_t)finalize_region(S.N)) +
+                       sizeof(int) * (size_t)S.N;
     hipLaunchKernelGGL(k_finalize, dim3(W), dim3(128), lds, st, S, R, R0, mb, out, warp);
     return hipGetLastError();
 }
