@@ -135,8 +135,10 @@ typedef struct {
  *                  between
  * block_sweeps   : sweeps per block of the blocked energy error bar
  * max_walkers    : largest n_walkers any call on this context will pass
- * staging_walkers: walkers measured per launch (per-walker staging buffers);
- *                  0 = as many as fit in 16 GiB of staging
+ * staging_walkers: most walkers measured per launch (per-walker staging
+ *                  buffers); 0 = as many as fit in 16 GiB of staging.  A
+ *                  call on n walkers measures them in the fewest launches
+ *                  of at most this many, of equal size (up to one walker)
  * step_sigma     : proposal r' = r + step_sigma * N(0, I_3)
  * promote_fraction: VMC_MIXED only, in [0, 1]: the share of each measurement
  *                  launch's walkers that is measured again in FP64, its FP64
@@ -328,8 +330,8 @@ int zvector_jackknife(const double *x_jk_dev, int64_t n_blocks, int64_t len, dou
 int zvector_solve(const double *H_dev, int64_t d, int64_t n_rhs, const double *b_dev, double *z_dev,
                   double rtol, int32_t maxit, uint32_t flags, int32_t *iters, void *stream);
 
-/* Walkers processed per measurement launch (size of the per-walker staging);
- * returns -1 for a NULL context. */
+/* Most walkers processed per measurement launch (size of the per-walker
+ * staging); returns -1 for a NULL context. */
 int64_t vmc_staging_walkers(const vmc_ctx *ctx);
 
 /* ---- kernel timing --------------------------------------------------------

@@ -286,6 +286,14 @@ static void layouts(vmc_ctx *c) {
     d.bytes = (size_t)d.off_jas + (size_t)2 * N * 6 * 8;
 }
 
+// Walkers per measurement launch: W split into the fewest chunks that fit
+// the staging, of equal length (up to one), so that no launch is a small
+// tail (the FP64 re-measurement of each launch included).
+static int64_t chunk_len(const vmc_ctx *c, int64_t W) {
+    const int64_t nch = (W + c->chunk - 1) / c->chunk;
+    return nch > 0 ? (W + nch - 1) / nch : c->chunk;
+}
+
 // The measurement kernels on cw walkers at (possibly warped) positions pos
 // with sampling positions pos0.  plist: promotion list for the dense kernel.
 // Chunk offsets into the sweep's persistent inverses (null: none).
@@ -718,8 +726,9 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
         const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
         double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;
         double *blk_all = blk_idx < c->jk_cap ? c->blk_all + blk_idx * c->n_est : nullptr;
-        for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
-            const int64_t cw = std::min(c->chunk, W - c0);
+        const int64_t step = chunk_len(c, W);
+        for (int64_t c0 = 0; c0 < W; c0 += step) {
+            const int64_t cw = std::min(step, W - c0);
             // ln|Psi| is not an estimator input: the dense kernel may start
             // from the sweep's inverses
             // (in mixed precision O and G are staged in FP32: the estimator
@@ -859,8 +868,9 @@ int vmc_measure(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
     const int full = (out->dEL_dR || out->dlnpsi_dR || out->dlnjac_dR || out->O || out->G) ? 1 : 0;
     const int warp = (R != R0) ? 1 : 0;
     const int64_t Mn = (int64_t)c->M * c->n_occ, A3 = 3 * c->A;
-    for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
-        const int64_t cw = std::min(c->chunk, W - c0);
+    const int64_t step = chunk_len(c, W);
+    for (int64_t c0 = 0; c0 < W; c0 += step) {
+        const int64_t cw = std::min(step, W - c0);
         auto off = [&](double *p, int64_t stride) { return p ? p + c0 * stride : nullptr; };
         WalkerOut o{off(out->EL, 1),      off(out->lnpsi, 1),  off(out->lnjac, 1),
                     off(out->dEL_dR, A3), off(out->dlnpsi_dR, A3), off(out->dlnjac_dR, A3),
@@ -908,8 +918,9 @@ int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
     HIP_OK(c, hipMemsetAsync(c->vjp_acc, 0, nv * 8, st));
     HIP_OK(c, hipMemsetAsync(c->vjp_comp, 0, nv * 8, st));
     const int warp = (R != R0) ? 1 : 0;
-    for (int64_t c0 = 0; c0 < W; c0 += c->chunk) {
-        const int64_t cw = std::min(c->chunk, W - c0);
+    const int64_t step = chunk_len(c, W);
+    for (int64_t c0 = 0; c0 < W; c0 += step) {
+        const int64_t cw = std::min(step, W - c0);
         WalkerOut o{c->st_EL, c->st_lnpsi, c->st_lnjac, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
         if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, C, R, R0, warp, 1, o, st))) return rc;
         EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, nullptr,

@@ -51,7 +51,9 @@ def full():
 
 
 def sample_ids(W, chunk):
-    ids = {0, 3, 4, W // 2 + 1, chunk - 1, chunk, W - 1}
+    # measurement launches split W into equal chunks of at most `chunk`
+    step = -(-W // -(-W // chunk))
+    ids = {0, 3, 4, W // 2 + 1, step - 1, step, W - 1}
     return sorted(i for i in ids if 0 <= i < W)
 
 

@@ -160,7 +160,8 @@ def test_promotion_all_and_none(dev):
     promoted share of 1 every walker's mixed results are replaced by FP64 ones,
     so they equal the FP64 context's bit for bit; with 0 nothing is replaced
     and the results differ from FP64 by FP32 round-off only; with 1/4, exactly
-    ceil(launch / 4) walkers of each measurement launch carry FP64 results."""
+    ceil(launch / 4) walkers of each measurement launch carry FP64 results
+    (launches: W split into equal chunks of at most the staging size)."""
     from paper_2511_05222_amd import vmc
     mol = inputs.make_config(1).molecule
     W = 300
@@ -182,11 +183,13 @@ def test_promotion_all_and_none(dev):
                 assert np.abs(got[k] - ref[k]).max() < 1e-2 * scale, k
                 assert not np.array_equal(got[k], ref[k]), k
         else:
-            # launches of 128, 128 and 44 walkers: ceil(share x launch) of each
-            # carry the FP64 results exactly, in every output
+            # staging of 128 walkers: three launches of 100 (equal chunks);
+            # ceil(share x launch) of each carry the FP64 results exactly, in
+            # every output
+            assert c32.chunk_walkers() == 128
             same = np.all([np.all((got[k] == ref[k]).reshape(W, -1), axis=1) for k in outs], axis=0)
-            assert same.sum() == 32 + 32 + 11, same.sum()
-            for c0, c1, kk in ((0, 128, 32), (128, 256, 32), (256, 300, 11)):
+            assert same.sum() == 25 + 25 + 25, same.sum()
+            for c0, c1, kk in ((0, 100, 25), (100, 200, 25), (200, 300, 25)):
                 assert same[c0:c1].sum() == kk
 
 
