@@ -1,8 +1,8 @@
 // vmc_device.hpp -- device math of the VMC hot path (gfx950).
 //
-// Mostly __host__ __device__ (plain arithmetic); the per-lane AO helpers use
-// the hardware exponential and are device-only.  The kernels live in the
-// vmc_*.hip sources.
+// The random numbers, tables and Jastrow value are __host__ __device__ (plain
+// arithmetic); the AO evaluation, reciprocals and wavefront sums use device
+// builtins and are device-only.  The kernels live in the vmc_*.hip sources.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -111,8 +111,9 @@ __device__ inline float exp_neg(double a, double rho, float) {
     return exp2_neg_split(a * rho * 1.4426950408889634);
 }
 
-// Entry of a table that no kernel writes, read through the constant address
-// space: with a wavefront-uniform index it becomes a scalar load.
+// Entry of an array that the running kernel does not write (tables, or data
+// of earlier kernels), read through the constant address space: with a
+// wavefront-uniform index it becomes a scalar load.
 template <typename T>
 __device__ inline T ldc(const T *p) {
     return *(const __attribute__((address_space(4))) T *)p;
@@ -271,11 +272,10 @@ __device__ inline void ao_lane_radial(const AoLane<T, NPR> &L, const BasisDev &B
     for (int k = NPR; k < L.np; ++k) {
         const T al = (T)B.prim_exp[L.p0 + k];
         const T e = (T)B.prim_cp[L.p0 + k] * prim_exp_neg<T>(al, (double)al * 1.4426950408889634, rho);
-        const T w1 = al * e, w2 = al * w1;
         r0 += e;
-        r1 -= w1;
-        r2 += w2;
-        r3 -= al * w2;
+        r1 = fma(-al, e, r1);
+        r2 = fma(al * al, e, r2);
+        r3 = fma(-(al * al * al), e, r3);
     }
     R0 = r0;
     u1 = T(2) * r1;
