@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "vmc_device.hpp"
+
 namespace vmcx {
 
 __device__ inline void wave_sync_s() {
@@ -72,7 +74,7 @@ __device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &lo
         const double piv = readlane_d(a0, p);
         if (!(fabs(piv) > 1e-300)) bad = true;
         if (LOGDET) logabs += log(fabs(piv));
-        const double inv = 1.0 / piv;
+        const double inv = rcp_nr(piv);   // a few ulp; a zero pivot is flagged above
         if (me) {
             used = true;
             sig = k;
