@@ -332,7 +332,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
                 for (int r = 0; r < KN; ++r) colj[r] = Kr[r];
             }
             wave_sync_s();
-            const T t = (v - (lane == pj ? T(1) : T(0))) * (T)(1.0 / ratio);
+            const T rr = sizeof(T) == sizeof(float) ? (T)__builtin_amdgcn_rcpf((float)ratio) : (T)rcp_nr(ratio);
+            const T t = (v - (lane == pj ? T(1) : T(0))) * rr;
 #pragma unroll
             for (int r = 0; r < KN; ++r) Kr[r] -= colj[r] * t;
             if (fabs(ratio) < FORCED_REFRESH_RATIO) need = true;
