@@ -58,9 +58,11 @@ extern "C" {
 /* ---- precision modes ------------------------------------------------------ */
 #define VMC_FP64   0         /* every step in FP64                              */
 #define VMC_MIXED  1         /* FP32 AO evaluation, MO products on FP32 MFMA,
-                                FP32 Sherman-Morrison and back-projection; FP64
-                                inverse refresh, determinants, E_L assembly,
-                                Jastrow and every sum over walkers            */
+                                FP32 Sherman-Morrison, acceptance ratio (its
+                                Jastrow difference included) and
+                                back-projection; FP64 inverse refresh,
+                                determinants, E_L assembly with its Jastrow
+                                terms and every sum over walkers              */
 
 /* ---- flags ---------------------------------------------------------------- */
 #define VMC_SWEEP_MEASURE   1u   /* measure + accumulate after every sweep      */
