@@ -130,21 +130,35 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
     double *Minv = dEdr + 3 * N;   // [N][9]
     double *wS = Minv + 9 * N;     // [N][4]: invS, sg
     // (Minv and wS, at least 128 x 9 doubles, later hold the partial sums)
-    int *wnear = (int *)(Minv + finalize_region(N));
+    double *bw = Minv + finalize_region(N);   // [2][N][3] pair terms gathered by each wavefront
+    int *wnear = (int *)(bw + 6 * N);
+    const int wave = tid >> 6;
     for (int i = tid; i < 3 * N; i += 128) {
         p[i] = mb.pos[(size_t)w * N * 3 + i];
         p0[i] = mb.pos0[(size_t)w * N * 3 + i];
     }
     for (int i = tid; i < 6 * N; i += 128) gb[i] = mb.gb[(size_t)w * N * 6 + i];
+    for (int i = tid; i < 6 * N; i += 128) bw[i] = 0.0;
     __syncthreads();
-    for (int e = tid; e < N; e += 128) {
-        const double *dp = mb.dedr_part + ((size_t)w * N + e) * 3;
-        double d0 = dp[0], d1 = dp[1], d2 = dp[2];
+    // Electron-electron terms of dE_L/dr, each pair once: the term of pair
+    // (e, k) is odd under the exchange of e and k (bit for bit: every
+    // difference and product in it changes sign exactly), so round s pairs
+    // thread e with k = (e + s) mod N, adds the term to e and subtracts it
+    // from k's slot in its wavefront's table (a permutation of the slots in
+    // every round, read and written in program order).  Rounds s = 1 .. N/2
+    // cover every pair once; in round N/2 of an even N only e < N/2 takes part.
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (tid < N) {
+        const int e = tid;
         const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
         const double ge[3] = {-(gb[6 * e + 3] + gb[6 * e]), -(gb[6 * e + 4] + gb[6 * e + 1]),
                               -(gb[6 * e + 5] + gb[6 * e + 2])};
-        for (int k = 0; k < N; ++k) {
-            if (k == e) continue;
+        double *bme = bw + (size_t)wave * 3 * N;
+        for (int s = 1; 2 * s <= N; ++s) {
+            if (2 * s == N && e >= s) break;
+            int k = e + s;
+            if (k >= N) k -= N;
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
             const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
             const double ir = rsqrt_nr(dx * dx + dy * dy + dz * dz);
             const double r = (dx * dx + dy * dy + dz * dz) * ir;
@@ -166,7 +180,22 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
             d0 -= dx * ir3;
             d1 -= dy * ir3;
             d2 -= dz * ir3;
+            a0 += d0;
+            a1 += d1;
+            a2 += d2;
+            bme[3 * k] -= d0;
+            bme[3 * k + 1] -= d1;
+            bme[3 * k + 2] -= d2;
         }
+    }
+    __syncthreads();
+    if (tid < N) {
+        const int e = tid;
+        const double *dp = mb.dedr_part + ((size_t)w * N + e) * 3;
+        double d0 = dp[0] + (a0 + (bw[3 * e] + bw[3 * N + 3 * e]));
+        double d1 = dp[1] + (a1 + (bw[3 * e + 1] + bw[3 * N + 3 * e + 1]));
+        double d2 = dp[2] + (a2 + (bw[3 * e + 2] + bw[3 * N + 3 * e + 2]));
+        const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
         for (int a = 0; a < A; ++a) {
             const double dx = x - R[3 * a], dy = y - R[3 * a + 1], dz = z - R[3 * a + 2];
             const double ir = rsqrt_nr(dx * dx + dy * dy + dz * dz);
@@ -300,7 +329,9 @@ hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const
 
 hipError_t launch_finalize(const SysDev &S, const double *R, const double *R0, const MeasBufsD &mb,
                            const WalkerOut &out, int warp, int W, hipStream_t st) {
-    const size_t lds = sizeof(double) * ((size_t)S.N * (3 + 3 + 6 + 3) + (size_t)finalize_region(S.N)) +
+    // one electron per thread of the 128 (the spin blocks hold at most 64 each)
+    if (S.N > 128) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * ((size_t)S.N * (3 + 3 + 6 + 3 + 6) + (size_t)finalize_region(S.N)) +
                        sizeof(int) * (size_t)S.N;
     hipLaunchKernelGGL(k_finalize, dim3(W), dim3(128), lds, st, S, R, R0, mb, out, warp);
     return hipGetLastError();
