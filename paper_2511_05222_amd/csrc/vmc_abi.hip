@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -283,7 +284,7 @@ static void layouts(vmc_ctx *c) {
     d.off_perm = d.off_x + al((size_t)kn * d.ldk * 8);
     d.off_red = d.off_perm + al(128 * 4);
     d.off_jas = d.off_red + al(16 * 8);
-    d.bytes = (size_t)d.off_jas + (size_t)2 * N * 6 * 8;
+    d.bytes = (size_t)d.off_jas + (size_t)(2 + 4) * N * 3 * 8;
 }
 
 // Walkers per measurement launch: W split into the fewest chunks that fit
@@ -614,14 +615,26 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     c->al64 = adjoint_layout(c, sizeof(double));
     if (c->al64.bytes > 160 * 1024)
         return bail(c->fail(VMC_EINVAL, "system too large for the LDS of one workgroup (%zu bytes)", c->al64.bytes));
-    // the FP64 kernels are also the fallback of the mixed path
-    bool cfg_ok = vmcx::configure_dense<double>(c->dl.bytes) == hipSuccess &&
-                  vmcx::configure_sweep<double>(sweep_layout(c, sizeof(double)).bytes) == hipSuccess &&
-                  vmcx::configure_adjoint<double>(c->al64.bytes) == hipSuccess;
-    if (mixed)
-        cfg_ok = cfg_ok && vmcx::configure_dense<float>(c->dl.bytes) == hipSuccess &&
-                 vmcx::configure_sweep<float>(c->swl.bytes) == hipSuccess &&
-                 vmcx::configure_adjoint<float>(c->al.bytes) == hipSuccess;
+    // the FP64 kernels are also the fallback of the mixed path.  Limits are
+    // only raised (the largest size any context of the process has asked for),
+    // so that contexts of different sizes in one process never lower each
+    // other's; every launch passes its own size.
+    bool cfg_ok;
+    {
+        static std::mutex mu;
+        static size_t lim[6] = {0, 0, 0, 0, 0, 0};
+        std::lock_guard<std::mutex> lock(mu);
+        const size_t need[6] = {c->dl.bytes, sweep_layout(c, sizeof(double)).bytes, c->al64.bytes,
+                                c->dl.bytes, c->swl.bytes, c->al.bytes};
+        for (int q = 0; q < 6; ++q) lim[q] = std::max(lim[q], need[q]);
+        cfg_ok = vmcx::configure_dense<double>(lim[0]) == hipSuccess &&
+                 vmcx::configure_sweep<double>(lim[1]) == hipSuccess &&
+                 vmcx::configure_adjoint<double>(lim[2]) == hipSuccess;
+        if (mixed)
+            cfg_ok = cfg_ok && vmcx::configure_dense<float>(lim[3]) == hipSuccess &&
+                     vmcx::configure_sweep<float>(lim[4]) == hipSuccess &&
+                     vmcx::configure_adjoint<float>(lim[5]) == hipSuccess;
+    }
     if (!cfg_ok)
         return bail(c->fail(VMC_EDEVICE, "cannot raise the LDS limit of the kernels"));
 

@@ -6,8 +6,9 @@
 //            after a sweep, the sweep's inverse of the block followed by one
 //            FP64 Newton step K + K (I - A K) on MFMA (then without log|det|);
 //            every wave: Jastrow gradient g_e, Laplacian and value, e-e and
-//            e-n potentials, as (electron, half of the other electrons)
-//            items combined in a fixed order.
+//            e-n potentials, each electron pair evaluated once (in rounds,
+//            the partner's gradient share gathered per wavefront) and
+//            combined in a fixed order.
 //   phase B  per spin block, one wavefront per electron row: the determinant
 //            gradient b_e = sum_i K[i][e] grad phi_i(r_e), lap D/D likewise,
 //            and (with the adjoint) X[e][i] = lap phi_i + 2 g_e . grad phi_i;
@@ -111,62 +112,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int j = 0; j < KN; ++j) K[perm[64 * b + j] * ldk + sig] = Br[j];
     }
-    // Jastrow and potential: item t = (electron t / 2, half t % 2 of the other
-    // electrons); waves 2 and 3 take the first 128 items, waves 0 and 1 (after
-    // the inverses) the rest
-    double *jp = (double *)(smem + L.off_jas);   // [2N][6]
-    for (int t = (tid + 128) & 255; t < 2 * N; t += 256) {
-        const int e = t >> 1, hf = t & 1, kh = (N + 1) >> 1;
-        const int k0 = hf * kh, k1 = min(N, k0 + kh);
-        const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
-        double gx = 0.0, gy = 0.0, gz = 0.0, hh = 0.0, vee = 0.0, jj = 0.0;
-        for (int k = k0; k < k1; ++k) {
-            if (k == e) continue;
-            const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            const double ir = rsqrt_nr(d2), r = d2 * ir;
-            double u, u1, u2;
-            if (S.ee_form == 1) {
-                const double ex = exp(-S.ee_F * r);
-                u1 = S.ee_a * ex;
-                u2 = -S.ee_F * u1;
-                u = S.ee_a * (1.0 - ex) / S.ee_F;
-            } else {
-                const double q = rcp_nr(1.0 + S.ee_F * r);
-                u1 = S.ee_a * q * q;
-                u2 = -2.0 * S.ee_F * u1 * q;
-                u = S.ee_a * r * q;
+    // Jastrow and potential, each electron pair once.  Round s pairs electron
+    // e with k = (e + s) mod N; rounds 1 .. N/2 cover every pair once (in
+    // round N/2 of an even N only e < N/2 takes part).  Threads 0-127 (waves 0
+    // and 1, after the inverses) take rounds 1 .. N/4, threads 128-255 the
+    // rest, electron e = tid % 128.  The pair's gradient term f (r_e - r_k) is
+    // odd under exchange, bit for bit: e keeps it, and k's share is gathered
+    // in the wavefront's own table (all lanes of a wavefront are in the same
+    // round, so their slots differ; reads and writes in program order).  The
+    // even terms (Laplacian, potential, J) enter the block sums once per pair
+    // with weight 2 relative to the per-electron form.
+    double *jp = (double *)(smem + L.off_jas);   // [2][N][3] own gradient partials
+    double *bw = jp + 6 * N;                     // [4][N][3] partners' gradient partials
+    {
+        double *bme = bw + (size_t)wave * 3 * N;
+        for (int i = lane; i < 3 * N; i += 64) bme[i] = 0.0;
+        wave_sync_s();
+        const int h = tid >> 7, e = tid & 127;
+        const int s0 = N / 4, sb = h ? s0 + 1 : 1, se = h ? N / 2 : s0;
+        if (e < N) {
+            const double x = p[3 * e], y = p[3 * e + 1], z = p[3 * e + 2];
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+            for (int s = sb; s <= se; ++s) {
+                if (2 * s == N && e >= s) break;
+                int k = e + s;
+                if (k >= N) k -= N;
+                const double dx = x - p[3 * k], dy = y - p[3 * k + 1], dz = z - p[3 * k + 2];
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                const double ir = rsqrt_nr(d2), r = d2 * ir;
+                double u, u1, u2;
+                if (S.ee_form == 1) {
+                    const double ex = exp(-S.ee_F * r);
+                    u1 = S.ee_a * ex;
+                    u2 = -S.ee_F * u1;
+                    u = S.ee_a * (1.0 - ex) / S.ee_F;
+                } else {
+                    const double q = rcp_nr(1.0 + S.ee_F * r);
+                    u1 = S.ee_a * q * q;
+                    u2 = -2.0 * S.ee_F * u1 * q;
+                    u = S.ee_a * r * q;
+                }
+                const double f = u1 * ir;
+                const double tx = f * dx, ty = f * dy, tz = f * dz;
+                gx += tx;
+                gy += ty;
+                gz += tz;
+                bme[3 * k] -= tx;
+                bme[3 * k + 1] -= ty;
+                bme[3 * k + 2] -= tz;
+                el_part += ir - (u2 + 2.0 * f);
+                j_part += u;
             }
-            const double f = u1 * ir;
-            gx += f * dx;
-            gy += f * dy;
-            gz += f * dz;
-            hh += u2 + 2.0 * f;
-            vee += ir;
-            jj += u;
+            if (h)
+                for (int a = 0; a < A; ++a) {
+                    const double ax = x - R[3 * a], ay = y - R[3 * a + 1], az = z - R[3 * a + 2];
+                    el_part -= S.Z[a] * rsqrt_nr(ax * ax + ay * ay + az * az);
+                }
+            double *o = jp + 3 * ((size_t)h * N + e);
+            o[0] = gx;
+            o[1] = gy;
+            o[2] = gz;
         }
-        if (hf == 0)
-            for (int a = 0; a < A; ++a) {
-                const double dx = x - R[3 * a], dy = y - R[3 * a + 1], dz = z - R[3 * a + 2];
-                vee -= 2.0 * S.Z[a] * rsqrt_nr(dx * dx + dy * dy + dz * dz);
-            }
-        double *o = jp + 6 * t;
-        o[0] = gx;
-        o[1] = gy;
-        o[2] = gz;
-        o[3] = hh;
-        o[4] = vee;   // 2 (electron-electron + electron-nucleus) potential of e
-        o[5] = jj;
     }
     __syncthreads();
     for (int e = tid; e < N; e += 256) {
-        const double *a0 = jp + 12 * e, *a1 = a0 + 6;
-        const double gx = a0[0] + a1[0], gy = a0[1] + a1[1], gz = a0[2] + a1[2];
-        g[3 * e] = gx;
-        g[3 * e + 1] = gy;
-        g[3 * e + 2] = gz;
-        el_part += -0.5 * ((a0[3] + a1[3]) + gx * gx + gy * gy + gz * gz) + 0.5 * (a0[4] + a1[4]);
-        j_part += 0.5 * (a0[5] + a1[5]);
+        double gq[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            gq[c] = (jp[3 * e + c] + jp[3 * N + 3 * e + c]) +
+                    ((bw[3 * e + c] + bw[3 * N + 3 * e + c]) + (bw[6 * N + 3 * e + c] + bw[9 * N + 3 * e + c]));
+        g[3 * e] = gq[0];
+        g[3 * e + 1] = gq[1];
+        g[3 * e + 2] = gq[2];
+        el_part += -0.5 * (gq[0] * gq[0] + gq[1] * gq[1] + gq[2] * gq[2]);
     }
     __syncthreads();
     const int ml = lane & 15, kg = lane >> 4;
