@@ -228,3 +228,28 @@ def test_exponential_jastrow(dev):
         torch.cuda.synchronize()
         b[prec] = a.cpu().numpy()
     assert np.mean(b["fp64"] == b["mixed"]) >= 0.999
+
+
+def test_contexts_of_different_sizes_share_a_process(dev):
+    """A small context created after a larger one leaves the larger one
+    working and its results unchanged (bit for bit): the kernels' LDS limits
+    are only ever raised, never lowered to the newest context's needs."""
+    from paper_2511_05222_amd import vmc
+
+    big = inputs.make_config(3).molecule       # 21 atoms: the largest LDS layouts here
+    small = inputs.make_config(0).molecule     # H2
+    W = 32
+    wb = torch.tensor(inputs.initial_walkers(big, W, 91), device=dev)
+    ws = torch.tensor(inputs.initial_walkers(small, W, 92), device=dev)
+    for prec in ("fp64", "mixed"):
+        ca = vmc.Context(big, max_walkers=W, precision=prec)
+        ca.sweep(wb.clone(), 1, 3, measure=False)
+        first = {k: v.cpu().numpy().copy() for k, v in ca.measure(wb).items()}
+        cb = vmc.Context(small, max_walkers=W, precision=prec)
+        cb.sweep(ws.clone(), 1, 4, measure=False)
+        cb.measure(ws)
+        ca.sweep(wb.clone(), 1, 3, measure=False)
+        again = {k: v.cpu().numpy() for k, v in ca.measure(wb).items()}
+        torch.cuda.synchronize()
+        for k in first:
+            assert np.array_equal(first[k], again[k]), (prec, k)
