@@ -323,6 +323,66 @@ def test_rng_moments():
     assert not np.any(a == b) and not np.any(a == c)
 
 
+# P13: Philox4x32-10 reproduces the generator's published known-answer
+# vectors (tests/golden/philox4x32_10_kat.txt): a wrong multiplier, Weyl
+# constant, round order or key schedule changes every output word.
+def test_philox_known_answers():
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for row in rows:
+        v = [int(x, 16) for x in row]
+        out = philox.philox4x32_10(*[np.uint64(x) for x in v[:6]])
+        assert [int(x) for x in out] == v[6:], row
+
+
+# P5 (warp weights): kappa(d) = d^-4 (App. A, space-warp force).  With two
+# nuclei at distances d1 = 1 and d2 = 2, omega_1 = 1 / (1 + (1/2)^4) = 16/17;
+# equidistant nuclei share the weight equally; an electron on a nucleus gets
+# all of it.  The weight gradient matches central differences of the weights.
+def test_swct_weights_closed_values():
+    R0 = np.array([[0.0, 0.0, 0.0], [3.0, 0.0, 0.0]])
+    r = np.array([[[1.0, 0.0, 0.0], [1.5, 0.0, 0.0], [3.0, 0.0, 0.0], [1.0, 2.0, 0.0]]])
+    with np.errstate(divide="ignore", invalid="ignore"):   # the electron on nucleus 1
+        om = dv.swct_weights(R0, r)[0]
+    assert abs(om[0, 0] - 16.0 / 17.0) < 1e-15 and abs(om[0, 1] - 1.0 / 17.0) < 1e-15
+    assert np.allclose(om[1], [0.5, 0.5], atol=1e-15)
+    assert om[2, 1] == 1.0 and om[2, 0] == 0.0
+    # (1, 2, 0): d1^2 = 5, d2^2 = 8, omega_1 = 64 / (64 + 25)
+    assert abs(om[3, 0] - 64.0 / 89.0) < 1e-15
+    # three nuclei on an equilateral triangle, electron at its centre
+    R3 = np.array([[1.0, 0.0, 0.0], [-0.5, np.sqrt(3) / 2, 0.0], [-0.5, -np.sqrt(3) / 2, 0.0]])
+    assert np.allclose(dv.swct_weights(R3, np.zeros((1, 1, 3)))[0, 0], 1.0 / 3.0, atol=1e-14)
+    # gradient vs central differences (away from the nuclei)
+    rng = np.random.default_rng(11)
+    rr = rng.uniform(-2, 5, size=(1, 6, 3))
+    g = dv.swct_weight_gradients(R0, rr)
+    h = 1e-5
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        fd = (dv.swct_weights(R0, rr + e) - dv.swct_weights(R0, rr - e)) / (2 * h)
+        assert np.allclose(fd, g[..., k], rtol=1e-7, atol=1e-9)
+
+
+# P10 (Jastrow form): the Pade function u(r) = a r / (1 + F r) (eq. twobody_v):
+# tabulated values, the electron-electron cusp u'(0) = a, the limit a/F, and
+# its derivatives by central differences.
+def test_pade_jastrow_values():
+    a, F = 0.5, 1.0
+    u, u1, u2 = wf.pade(np.array([0.0, 1.0, 3.0, 1e9]), a, F)
+    assert u[0] == 0.0 and abs(u[1] - 0.25) < 1e-16 and abs(u[2] - 0.375) < 1e-16
+    assert abs(u[3] - a / F) < 1e-9
+    assert abs(u1[0] - a) < 1e-16                      # cusp
+    a, F = 0.37, 2.3
+    assert abs(wf.pade(np.array([2.0]), a, F)[0][0] - 0.74 / 5.6) < 1e-16
+    r = np.linspace(0.05, 6.0, 40)
+    h = 1e-5
+    _, p1, p2 = wf.pade(r, a, F)
+    assert np.allclose((wf.pade(r + h, a, F)[0] - wf.pade(r - h, a, F)[0]) / (2 * h), p1, rtol=1e-8)
+    assert np.allclose((wf.pade(r + h, a, F)[1] - wf.pade(r - h, a, F)[1]) / (2 * h), p2, rtol=1e-8)
+
+
 # P15: CG against the Cholesky solution of the same SPD system.
 def test_zvector_cg():
     H = inputs.seeded_spd(300, 5)
