@@ -51,7 +51,7 @@ extern "C" {
 #define VMC_EINVAL      -1   /* invalid argument or unsupported size            */
 #define VMC_ENOMEM      -2   /* device or host allocation failed                */
 #define VMC_EDEVICE     -3   /* HIP runtime error                               */
-#define VMC_ESINGULAR   -4   /* a Slater matrix had a zero pivot                */
+#define VMC_ESINGULAR   -4   /* a Slater block singular to working precision    */
 #define VMC_ENOTCONV    -5   /* iterative solver hit maxit                      */
 #define VMC_ENONFINITE  -6   /* non-finite value in an input or a result        */
 
@@ -133,8 +133,8 @@ typedef struct {
  *                  move of that block's electrons (block move index
  *                  sweep * n_occ + j for its j-th electron), at the start of
  *                  every vmc_sweep call, and after an accepted move of the
- *                  block with |ratio| < 1e-8; Sherman-Morrison updates in
- *                  between
+ *                  block with |ratio| < forced_refresh_ratio; Sherman-Morrison
+ *                  updates in between
  * block_sweeps   : sweeps per block of the blocked energy error bar
  * max_walkers    : largest n_walkers any call on this context will pass
  * staging_walkers: most walkers measured per launch (per-walker staging
@@ -156,7 +156,12 @@ typedef struct {
  * jackknife_blocks: number of blocks (of block_sweeps sweeps) whose sums of
  *                  every estimator element are kept for vmc_jackknife
  *                  (at most 65535; 0 = none; (2 + 9A + 3 M n_occ) doubles of
- *                  device memory per block). */
+ *                  device memory per block).
+ * forced_refresh_ratio: an accepted move whose determinant ratio has
+ *                  |ratio| below this value rebuilds its block's inverse
+ *                  before the block's next move (the Sherman-Morrison update
+ *                  divides by the ratio); 0 selects the default 1e-8, larger
+ *                  values force more rebuilds (>= 0, finite). */
 typedef struct {
     int32_t precision;
     int32_t refresh_period;
@@ -166,6 +171,7 @@ typedef struct {
     double  step_sigma;
     double  promote_fraction;
     int32_t jackknife_blocks;
+    double  forced_refresh_ratio;
 } vmc_options;
 
 /* Per-walker outputs of one measurement (device arrays, any may be NULL).
@@ -185,9 +191,13 @@ typedef struct {
     double *G;
 } vmc_walker_out;
 
-/* Create a context on HIP device `device`: validates and deep-copies the host
- * inputs (the caller may free them on return), folds the GTO normalisation,
- * and allocates device state for opt->max_walkers walkers.
+/* Create a context on HIP device `device` for the Jastrow-Slater wavefunction
+ * of Appendix A, "Wavefunction Ansatz": the determinant part expanded over
+ * the occupied MOs of the frozen coefficients C (eq. agp_expansion with
+ * p = N/2 MOs, i.e. eq. restricted-C), the two-body Jastrow of eqs.
+ * twobody_jastrow / twobody_v / twobody_v_exp.  Validates and deep-copies the
+ * host inputs (the caller may free them on return), folds the GTO
+ * normalisation, and allocates device state for opt->max_walkers walkers.
  * Errors: VMC_EINVAL (l > 2, alpha <= 0, non-finite input, n_up != n_dn,
  * n_occ != n_up, sizes beyond the VMC_MAX_* limits), VMC_ENOMEM, VMC_EDEVICE. */
 int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
@@ -221,8 +231,15 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
  * All sums are FP64, shifted by the mean E_L of the first measured batch and
  * compensated (Neumaier).  Synchronises `stream`.
  * flags & VMC_ACCUM_RESET clears the accumulators afterwards.
- * Errors: VMC_EINVAL (no samples), VMC_ESINGULAR / VMC_ENONFINITE if any
- * measured walker had a singular Slater matrix / non-finite E_L. */
+ * Errors: VMC_EINVAL (no samples); VMC_ESINGULAR if, since the last reset,
+ * an inverse rebuild of the sweeps or of a measurement met a Slater block
+ * that is singular to working precision (a pivot of at most 2^-40 times the
+ * largest orbital value of its electron: e.g. two same-spin electrons at one
+ * point, or an electron where every orbital vanishes); otherwise
+ * VMC_ENONFINITE if a measured E_L, ln|Psi| or log|det| was not finite (e.g.
+ * a walker with a NaN coordinate).  On these two errors the outputs are
+ * still written (they include the offending samples) and VMC_ACCUM_RESET
+ * still clears the accumulators and the error state. */
 int vmc_accumulate(vmc_ctx *ctx, double *E, double *F_bare, double *dE_dC,
                    double *dEL_dC_mean, int64_t *n_samples, uint32_t flags, void *stream);
 
@@ -269,7 +286,10 @@ int vmc_energy_cotangents(vmc_ctx *ctx, int64_t n_walkers, double gE, const doub
                           double *gPsi_dev, double *gJac_dev, void *stream);
 
 /* Vector-Jacobian product of the per-walker map (C, R) -> (E_L, ln|Psi|, ln Jac)
- * with per-walker cotangents gEL, gPsi, gJac (device [W]):
+ * (the derivatives the paper takes by algorithmic differentiation, Appendix A
+ * "Computing derivatives": the dE_L/dC and O = dln|Psi|/dC of eq.
+ * fc-vmc-eval, and the space-warp force terms) with per-walker cotangents
+ * gEL, gPsi, gJac (device [W]):
  *   dC_dev[n_ao][n_occ] = sum_k gEL_k dE_L,k/dC + gPsi_k dln|Psi_k|/dC
  *   dR_dev[A][3]        = sum_k gEL_k dE_L,k/dR + gPsi_k dln|Psi_k|/dR + gJac_k dlnJac_k/dR
  * (hand-written reverse mode; forward intermediates are recomputed, not

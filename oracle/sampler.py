@@ -20,7 +20,8 @@ Two ratio modes:
          K is recomputed from scratch at the start of a run, after every
          `refresh_period`-th proposed move of that block (its own move index
          sweep * n_block + j, j the electron's index within the block), and
-         after an accepted move of that block whose |ratio| < 1e-8.
+         after an accepted move of that block whose |ratio| is below
+         forced_ratio (1e-8 unless given; the update divides by the ratio).
 """
 import numpy as np
 
@@ -41,6 +42,7 @@ class Chains:
         self.ids = np.arange(W, dtype=np.uint64) if walker_ids is None else np.asarray(walker_ids, np.uint64)
         self.R = system.xyz if R is None else np.asarray(R, np.float64)
         self.K = None
+        self.n_forced = 0          # forced refreshes so far (walker-moves)
 
     # ------------------------------------------------------------------
     def spin_of(self, e):
@@ -86,7 +88,8 @@ class Chains:
         return dJ
 
     # ------------------------------------------------------------------
-    def sweep(self, seed, sweep_index, step_sigma=0.5, mode="sm", refresh_period=32):
+    def sweep(self, seed, sweep_index, step_sigma=0.5, mode="sm", refresh_period=32,
+              forced_ratio=FORCED_REFRESH_RATIO):
         """One sweep of N single-electron moves; returns accept bits [N, W]."""
         s = self.system
         W = self.r.shape[0]
@@ -120,7 +123,8 @@ class Chains:
                 t[:, j] -= 1.0
                 upd = colj[:, :, None] * (t / ratio[:, None])[:, None, :]
                 K[acc] -= upd[acc]
-                forced = acc & (np.abs(ratio) < FORCED_REFRESH_RATIO)
+                forced = acc & (np.abs(ratio) < forced_ratio)
+                self.n_forced += int(np.count_nonzero(forced))
                 if np.any(forced):
                     self.refresh(mask=forced, blocks=(b,))
                 m = sweep_index * n + j
@@ -130,7 +134,7 @@ class Chains:
 
 
 def run(system, walkers, n_sweeps, seed, sweep_offset=0, walker_ids=None, step_sigma=0.5,
-        mode="sm", refresh_period=32, measure=None):
+        mode="sm", refresh_period=32, measure=None, forced_ratio=FORCED_REFRESH_RATIO):
     """Sample n_sweeps sweeps; call measure(chains, sweep_index) after each.
 
     Returns (chains, accept bits [n_sweeps, N, W]).
@@ -139,7 +143,7 @@ def run(system, walkers, n_sweeps, seed, sweep_offset=0, walker_ids=None, step_s
     bits = []
     for t in range(n_sweeps):
         sidx = sweep_offset + t
-        bits.append(ch.sweep(seed, sidx, step_sigma, mode, refresh_period))
+        bits.append(ch.sweep(seed, sidx, step_sigma, mode, refresh_period, forced_ratio))
         if measure is not None:
             measure(ch, sidx)
     return ch, np.array(bits)

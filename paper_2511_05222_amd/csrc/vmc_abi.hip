@@ -472,7 +472,8 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     if (opt->precision != VMC_FP64 && opt->precision != VMC_MIXED)
         return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 or VMC_MIXED)", opt->precision));
     if (opt->refresh_period < 1 || opt->block_sweeps < 1 || opt->max_walkers < 1 || opt->staging_walkers < 0 ||
-        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_fraction >= 0.0 && opt->promote_fraction <= 1.0) || opt->jackknife_blocks < 0)
+        !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_fraction >= 0.0 && opt->promote_fraction <= 1.0) || opt->jackknife_blocks < 0 ||
+        !(opt->forced_refresh_ratio >= 0.0) || !std::isfinite(opt->forced_refresh_ratio))
         return bail(c->fail(VMC_EINVAL, "bad options"));
     double Zsum = 0.0;
     for (int a = 0; a < A; ++a) Zsum += nuclei->Z[a];
@@ -595,6 +596,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     sd.ee_a = c->ee_a;
     sd.ee_F = c->ee_F;
     sd.ee_form = c->ee_form;
+    sd.forced_ratio = opt->forced_refresh_ratio > 0.0 ? opt->forced_refresh_ratio : vmcx::FORCED_REFRESH_RATIO;
     sd.basis = vmcx::BasisDev{M,          S,           c->d_ao_shell, c->d_ao_pow,   c->d_ao_eta,
                               c->d_shell_atom, c->d_shell_p0, c->d_shell_np, c->d_prim_exp, c->d_prim_cp,
                               c->d_shell_l, c->d_shell_mu0, c->d_atom_ao_ptr, c->d_atom_ao};
@@ -846,7 +848,7 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
         c->n_samples = 0;
         c->sweeps_since_reset = 0;
     }
-    if (status & vmcx::STATUS_SINGULAR) return c->fail(VMC_ESINGULAR, "a Slater matrix had a zero pivot");
+    if (status & vmcx::STATUS_SINGULAR) return c->fail(VMC_ESINGULAR, "a Slater block was singular to working precision");
     if (status & vmcx::STATUS_NONFINITE) return c->fail(VMC_ENONFINITE, "non-finite local energy or ln|Psi|");
     return VMC_OK;
 }

@@ -98,7 +98,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int r = 0; r < KN; ++r)
                 Br[r] = (lz < nb && r < nb) ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // identity padding
-            gj_regs<KN, true>(Br, sig, bad, la);
+            const double tol = row_tol<KN>(ph + (size_t)(off + min(lz, nb - 1)) * 5 * n, nb, lz < nb);
+            gj_regs<KN, true>(Br, sig, bad, la, tol);
         }
         if (lane == 0) {
             red[4 + b] = la;
@@ -162,6 +163,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 bme[3 * k + 2] -= tz;
                 el_part += ir - (u2 + 2.0 * f);
                 j_part += u;
+                // the next round's partner slot of lane e - 1 is this round's
+                // of lane e: keep the rounds' LDS accesses in order
+                wave_sync_s();
             }
             if (h)
                 for (int a = 0; a < A; ++a) {

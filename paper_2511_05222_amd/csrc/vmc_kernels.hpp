@@ -10,6 +10,7 @@
 
 namespace vmcx {
 
+// default threshold of the forced inverse refresh after an accepted move
 constexpr double FORCED_REFRESH_RATIO = 1e-8;
 constexpr int STATUS_SINGULAR = 1;
 constexpr int STATUS_NONFINITE = 2;
@@ -18,6 +19,7 @@ struct SysDev {
     int N, n_up, n_dn, n_occ, M, A;
     double ee_a, ee_F;
     int ee_form;   // 0: a r / (1 + F r); 1: a (1 - e^{-F r}) / F
+    double forced_ratio;   // an accepted move with |ratio| below it rebuilds the block's inverse
     BasisDev basis;
     const double *Z;
 };

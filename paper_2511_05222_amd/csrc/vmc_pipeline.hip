@@ -9,6 +9,7 @@
 #include <type_traits>
 
 #include "vmc_pipeline.hpp"
+#include "vmc_regs.hpp"
 
 namespace vmcx {
 
@@ -186,6 +187,9 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
             bme[3 * k] -= d0;
             bme[3 * k + 1] -= d1;
             bme[3 * k + 2] -= d2;
+            // the next round's partner slot of lane e - 1 is this round's of
+            // lane e: keep the rounds' LDS accesses in order
+            wave_sync_s();
         }
     }
     __syncthreads();

@@ -46,7 +46,8 @@ __device__ inline void rebuild(const T *Aw, int n, int off, int nb, T (&Kr)[KN],
 #pragma unroll
     for (int r = 0; r < KN; ++r) Br[r] = (lz < nb && r < nb) ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // padding
     double la;
-    gj_regs<KN, false>(Br, sig, bad, la);
+    const double tol = row_tol<KN>(Aw + (size_t)(off + min(lz, nb - 1)) * n, nb, lz < nb);
+    gj_regs<KN, false>(Br, sig, bad, la, tol);
 #pragma unroll
     for (int r = 0; r < KN; ++r) Kr[r] = (T)Br[r];
 }
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             const T t = (v - (lane == pj ? T(1) : T(0))) * rr;
 #pragma unroll
             for (int r = 0; r < KN; ++r) Kr[r] -= colj[r] * t;
-            if (fabs(ratio) < FORCED_REFRESH_RATIO) need = true;
+            if (fabs(ratio) < S.forced_ratio) need = true;
         }
         if (accept != nullptr && lane == 0) accept[(size_t)e * W + w] = acc ? 1 : 0;
         // refresh_period-th move of this block: rebuild before its next move

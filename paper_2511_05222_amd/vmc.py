@@ -59,7 +59,8 @@ class _Jastrow(ct.Structure):
 class _Options(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("refresh_period", ct.c_int32), ("block_sweeps", ct.c_int32),
                 ("max_walkers", ct.c_int32), ("staging_walkers", ct.c_int32), ("step_sigma", ct.c_double),
-                ("promote_fraction", ct.c_double), ("jackknife_blocks", ct.c_int32)]
+                ("promote_fraction", ct.c_double), ("jackknife_blocks", ct.c_int32),
+                ("forced_refresh_ratio", ct.c_double)]
 
 
 class _WalkerOut(ct.Structure):
@@ -135,7 +136,7 @@ class Context:
 
     def __init__(self, mol, max_walkers, precision="fp64", refresh_period=32, block_sweeps=1,
                  step_sigma=0.5, device=0, staging_walkers=0, promote_fraction=PROMOTE_FRACTION,
-                 jackknife_blocks=0):
+                 jackknife_blocks=0, forced_refresh_ratio=0.0):
         L = lib()
         b = mol.basis
         self._keep = [np.ascontiguousarray(b.shell_atom, np.int32), np.ascontiguousarray(b.shell_l, np.int32),
@@ -156,7 +157,7 @@ class Context:
         if prec is None:
             raise VmcError(VMC_EINVAL, f"precision {precision!r} is not available")
         opt = _Options(prec, refresh_period, block_sweeps, int(max_walkers), int(staging_walkers), step_sigma,
-                       float(promote_fraction), int(jackknife_blocks))
+                       float(promote_fraction), int(jackknife_blocks), float(forced_refresh_ratio))
         h = ct.c_void_p()
         rc = L.vmc_init(ct.byref(basis), ct.byref(nuc), ct.byref(mo), ct.byref(jas), ct.byref(opt), device,
                         ct.byref(h))
