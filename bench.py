@@ -12,19 +12,23 @@ precision.  The same workload also runs through the FP64 path, and the line
 reports both rates and their ratio, plus the mixed-vs-FP64 error table on
 replayed configurations (the mixed run's final walkers measured in both
 precisions): walker-averaged |dE|, max |dF| over the bare force components,
-and the relative max error of dE/dC on a subset.
+and the relative max error of dE/dC on a subset.  The 9-atom molecule with
+16384 walkers through the FP64 path is timed as well (`fp64_9atom`).
 
 Also in the line:
-  roofline     the dominant kernel (k_adjoint_mfma: back-projection and outer
-               products on the matrix cores), timed with HIP events that the
-               library records on its launch stream over the timed region;
-               algorithmic flops per walker 10 N M n (kappa = K~ C^T and
-               a = Abar C^T, 2 N M n each; O = psi^T K~, 2 N M n; G = psi^T
-               Abar + q^T K~, 4 N M n) against the dense MFMA peak of the
-               arithmetic type; traffic from the committed rocprofv3 counter
-               summary when it matches this kernel source and launch size;
-  cpu_baseline the FP64 oracle on a bounded sample of the same molecule on
-               the host cores (unless --no-cpu-baseline).
+  roofline       the kernel with the largest share of the step, timed with
+                 HIP events that the library records on its launch stream
+                 over the timed region, against the roof of its algorithmic
+                 work (work_model: matrix-core flops, vector-ALU flops and
+                 HBM bytes per unit; the bound is the resource whose work
+                 takes longest at its peak); traffic from the committed
+                 rocprofv3 counter summary when it matches the kernel source
+                 and launch size;
+  kernels        the same for every timed kernel;
+  step_roofline  the whole walker-step: the summed work of the step against
+                 the same peaks, T_roof / T_measured;
+  cpu_baseline   the FP64 oracle on a bounded sample of the same molecule on
+                 the host cores (unless --no-cpu-baseline).
 """
 import argparse
 import hashlib
@@ -39,28 +43,90 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "walker-steps/s (fwd+adjoint) mixed vs FP64 on 1 GPU; force err Ha/bohr"
-MFMA_PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}   # dense FP32 / FP64 matrix-core peaks
-KERNEL = "k_adjoint_mfma"
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2511_05222_amd", "csrc", f)
-               for f in ("vmc_adjoint.hip", "vmc_mfma.hpp", "vmc_device.hpp", "vmc_pipeline.hpp")]
+# MI355X peaks.  Matrix cores: dense FP32 157.3, FP64 78.6 TFLOP/s.  Vector
+# ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (one FMA) x 2.4 GHz = 78.6
+# TFLOP/s for FP32 and FP64 alike (the 157.3 TFLOP/s FP32 vector figure needs
+# packed FP32 instructions, which this library does not emit).  HBM 8 TB/s.
+PEAK_MFMA = {"mixed": 157.3, "fp64": 78.6}
+PEAK_ALU = 78.6
+PEAK_HBM = 8000.0
+KERNELS = {"sweep": "k_sweep_r", "mo_rows": "k_mo_rows_mfma", "dense": "k_dense", "adjoint": "k_adjoint_mfma"}
+KERNEL_SRCS = {
+    "sweep": ("vmc_sweep.hip", "vmc_regs.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
+    "mo_rows": ("vmc_mo.hip", "vmc_mfma.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
+    "dense": ("vmc_dense.hip", "vmc_mfma.hpp", "vmc_regs.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
+    "adjoint": ("vmc_adjoint.hip", "vmc_mfma.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
+}
 COPY_BYTES = 1 << 30   # plain device copy used to calibrate the HBM byte counters
 WORKLOADS = {"9atom": 1, "21atom": 2}
 
 
-def adjoint_flops_per_walker(N, M, n):
-    return 10.0 * N * M * n
+def work_model(mol, precision, p_acc):
+    """Algorithmic work per unit of each kernel: {"mfma": flops, "alu": flops,
+    "hbm": bytes}; the unit is a walker-sweep for the sweep, a walker for the
+    measurement kernels.  Counts are what the method computes (no padding,
+    no recomputation beyond the design's recompute-not-store rule), with
+    N electrons, n orbitals per spin, M AOs, P primitives, S shells, A
+    atoms, p the measured acceptance:
+      sweep    per move: AO values at r' (per primitive alpha*rho and c*e,
+               per shell rho, per AO monomial x radial: 3P + 6S + 3M), the
+               MO row psi^T C (2Mn), the ratio (2n), the Jastrow difference
+               (N - 1 pairs, old and new distance, 24 flops), on accept the
+               Sherman-Morrison update (2n^2); per block every 32 moves an
+               inverse (2n^3, FP64).  Bytes: positions in and out, both
+               blocks' inverses in and out (in the arithmetic type), MO
+               rows written on accept, read back at each rebuild.
+      mo_rows  AO value, gradient, Laplacian (10 flops per primitive, 15 per
+               AO) and the five products psi C (10 NMn on the matrix cores);
+               bytes: the 5Nn orbital values written.
+      dense    per block a Newton step of the inverse (4n^3), T = X K and
+               Abar = T^T K^T (4n^3) on the matrix cores; Jastrow pairs
+               (40 flops each), determinant gradients (8Nn).
+      adjoint  AO derivatives through third order (60 flops per AO, 12 per
+               primitive, per electron); kappa = K~ C^T, a = Abar C^T,
+               O = psi^T K~, G = psi^T Abar + q^T K~ (10 NMn).
+    """
+    b = mol.basis
+    N, n, M, P, S, A = mol.n_elec, mol.n_occ, b.n_ao, b.n_prim, b.n_shells, mol.n_atoms
+    ts = 4 if precision == "mixed" else 8
+    ao_val = 3 * P + 6 * S + 3 * M
+    sweep_alu = N * (ao_val + 2 * M * n + 2 * n + 24 * (N - 1) + p_acc * 2 * n * n) + (N / 32.0) * 2 * n ** 3
+    sweep_hbm = 2 * 24 * N + 2 * 2 * (n * n * ts) + p_acc * N * n * ts + (N / 32.0) * n * n * ts
+    return {
+        "sweep": {"mfma": 0.0, "alu": float(sweep_alu), "hbm": float(sweep_hbm)},
+        "mo_rows": {"mfma": 10.0 * N * M * n, "alu": float(N * (10 * P + 6 * S + 15 * M)),
+                    "hbm": float(24 * N + 5 * N * n * ts)},
+        "dense": {"mfma": 16.0 * n ** 3, "alu": float(40 * N * (N - 1) / 2 + 8 * N * n),
+                  "hbm": float(5 * N * n * ts + 2 * N * n * ts)},
+        "adjoint": {"mfma": 10.0 * N * M * n, "alu": float(N * (60 * M + 12 * P)),
+                    "hbm": float(24 * N + 2 * N * n * ts + 2 * M * n * ts)},
+    }
 
 
-def kernel_sha():
+def roof(work, precision, t_s):
+    """Roofline of `work` done in t_s seconds: bound, achieved, peak, frac."""
+    times = {"mfma": work["mfma"] / (PEAK_MFMA[precision] * 1e12), "alu": work["alu"] / (PEAK_ALU * 1e12),
+             "hbm": work["hbm"] / (PEAK_HBM * 1e9)}
+    bound = max(times, key=times.get)
+    if bound == "hbm":
+        ach, peak, unit = work["hbm"] / t_s / 1e9, PEAK_HBM, "GB/s"
+    else:
+        ach, peak = work[bound] / t_s / 1e12, (PEAK_MFMA[precision] if bound == "mfma" else PEAK_ALU)
+        unit = "TFLOP/s"
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "t_roof_ns": times[bound] * 1e9, "t_measured_ns": t_s * 1e9}
+
+
+def kernel_sha(kernel):
     h = hashlib.sha256()
-    for p in KERNEL_SRCS:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for f in KERNEL_SRCS[kernel]:
+        with open(os.path.join(ROOT, "paper_2511_05222_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_file(workload, precision):
-    return os.path.join(ROOT, "profiles", f"{KERNEL}_{workload}_{precision}_traffic.json")
+def traffic_file(kernel, workload, precision):
+    return os.path.join(ROOT, "profiles", f"{KERNELS[kernel]}_{workload}_{precision}_traffic.json")
 
 
 def cpu_baseline(spec, budget_s=12.0):
@@ -81,9 +147,16 @@ def cpu_baseline(spec, budget_s=12.0):
     dt = time.perf_counter() - t0
     c1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (c1.ru_utime - c0.ru_utime) + (c1.ru_stime - c0.ru_stime)
-    return {"value": done / dt, "unit": "walker-steps/s", "cores": max(1, int(round(cpu / dt))),
-            "kind": "oracle", "sample": f"{walkers.shape[0]} walkers x {sweeps} sweeps (sweep + measurement) of the "
-                                        f"same molecule, {dt:.1f} s wall, {cpu:.1f} s CPU"}
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": done / dt, "unit": "walker-steps/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle", "cpu_model": model, "threads_busy": round(cpu / dt, 2),
+            "sample": f"{walkers.shape[0]} walkers x {sweeps} sweeps (sweep + measurement) of the same molecule, "
+                      f"{dt:.1f} s wall, {cpu:.1f} s CPU; numpy with its BLAS threads over the host cores"}
 
 
 def run_steps(ctx, walkers, seed, warmup, steps):
@@ -100,7 +173,14 @@ def run_steps(ctx, walkers, seed, warmup, steps):
     dt = time.perf_counter() - t0
     prof = {k: ctx.profile_read(k) for k in ("adjoint", "dense", "mo_rows", "sweep")}
     ctx.profile(False)
-    return dt, ctx.accumulate(reset=True), prof
+    res = ctx.accumulate(reset=True)
+    # acceptance of one more sweep on a copy (untimed, not accumulated)
+    wc = walkers.clone()
+    acc = torch.zeros((1, wc.shape[1], wc.shape[0]), dtype=torch.uint8, device=wc.device)
+    ctx.sweep(wc, 1, seed, sweep_offset=warmup + steps, measure=False, accept=acc)
+    p_acc = acc.float().mean().item()
+    del wc, acc
+    return dt, res, prof, p_acc
 
 
 def error_table(mol, W_sub, walkers, ctx32, ctx64):
@@ -174,30 +254,40 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"pmc_probe": True, "walkers": W, "staging_walkers": ctx.chunk_walkers(),
-                          "copy_bytes": COPY_BYTES, "kernel_source_sha": kernel_sha()}), flush=True)
+                          "copy_bytes": COPY_BYTES,
+                          "kernel_source_sha": {k: kernel_sha(k) for k in KERNEL_SRCS}}), flush=True)
         return
 
     walkers = w0.clone()
-    dt, res, prof = run_steps(ctx, walkers, spec.seed, args.warmup, args.steps)
+    dt, res, prof, p_acc = run_steps(ctx, walkers, spec.seed, args.warmup, args.steps)
     value = W * args.steps / dt
-    print(f"# {args.precision}: {value:.4g} walker-steps/s, {dt / args.steps * 1e3:.2f} ms/step", file=sys.stderr,
-          flush=True)
+    step_ms = dt / args.steps * 1e3
+    print(f"# {args.precision}: {value:.4g} walker-steps/s, {step_ms:.2f} ms/step", file=sys.stderr, flush=True)
 
-    # the dominant kernel
-    k_ms, k_launches, k_walkers = prof["adjoint"]
-    avg_ms = k_ms / max(k_launches, 1)
-    wpl = k_walkers / max(k_launches, 1)
-    flops = adjoint_flops_per_walker(mol.n_elec, mol.basis.n_ao, mol.n_occ) * wpl
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    peak = MFMA_PEAK_TFLOPS[args.precision]
+    work = work_model(mol, args.precision, p_acc)
+    kern = {}
+    for k, (ms, nl, nw) in prof.items():
+        if nl < 1:
+            continue
+        # per unit: walker-sweeps for the sweep (one launch per sweep), walkers otherwise
+        t_unit = ms * 1e-3 / max(nw, 1)
+        r = roof(work[k], args.precision, t_unit)
+        r.update({"kernel": KERNELS[k], "share_of_step": ms / args.steps / step_ms, "avg_launch_ms": ms / nl,
+                  "units_per_launch": nw / nl, "work_per_unit": work[k]})
+        kern[k] = r
+    dom = max(kern, key=lambda k: kern[k]["share_of_step"])
+    d = kern[dom]
     traffic = None
-    tf = traffic_file(args.workload, args.precision)
+    tf = traffic_file(dom, args.workload, args.precision)
     if os.path.exists(tf):
         t = json.load(open(tf))
-        if t.get("kernel_source_sha") == kernel_sha() and abs(t.get("walkers_per_launch", -1) - wpl) < 0.5:
+        if t.get("kernel_source_sha") == kernel_sha(dom) and abs(t.get("walkers_per_launch", -1) -
+                                                                 d["units_per_launch"]) < 0.5:
             traffic = t["hbm_bytes_per_launch"]
-    step_ms = dt / args.steps * 1e3
-    shares = {k: v[0] / args.steps / step_ms for k, v in prof.items()}
+    # the whole walker-step: work of all kernels (finalize and the estimator
+    # reductions are small beside them and are timed only as part of the step)
+    tot = {r: sum(work[k][r] for k in work) for r in ("mfma", "alu", "hbm")}
+    step_roof = roof(tot, args.precision, step_ms * 1e-3 / W)
 
     line = {
         "metric": METRIC,
@@ -216,17 +306,18 @@ def main():
                                f"cartesian AOs, {mol.n_occ} occupied orbitals per spin, {W} walkers",
                    "walkers": W, "electrons": mol.n_elec, "n_ao": mol.basis.n_ao, "atoms": mol.n_atoms,
                    "precision": args.precision, "refresh_period": 32},
-        "roofline": {"bound": "mfma", "kernel": KERNEL, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": avg_ms,
-                     "walkers_per_launch": wpl, "flops_per_walker": adjoint_flops_per_walker(
-                         mol.n_elec, mol.basis.n_ao, mol.n_occ)},
-        "kernel_share_of_step": shares,
+        "roofline": {"bound": d["bound"], "kernel": d["kernel"], "achieved": d["achieved"], "peak": d["peak"],
+                     "unit": d["unit"], "frac": d["frac"], "traffic": traffic, "avg_launch_ms": d["avg_launch_ms"],
+                     "units_per_launch": d["units_per_launch"], "work_per_unit": d["work_per_unit"]},
+        "kernels": kern,
+        "step_roofline": step_roof,
+        "acceptance": p_acc,
         "estimates": {"E": res["E"], "E_sigma": res["E_sigma"], "n_samples": res["n_samples"]},
     }
     if args.precision == "mixed" and not args.no_fp64:
         ctx64 = vmc.Context(mol, max_walkers=W, refresh_period=32, precision="fp64")
         w64 = w0.clone()
-        dt64, _, _ = run_steps(ctx64, w64, spec.seed, args.warmup, args.steps)
+        dt64, _, _, _ = run_steps(ctx64, w64, spec.seed, args.warmup, args.steps)
         v64 = W * args.steps / dt64
         print(f"# fp64: {v64:.4g} walker-steps/s, {dt64 / args.steps * 1e3:.2f} ms/step", file=sys.stderr,
               flush=True)
@@ -235,6 +326,21 @@ def main():
         line["mixed_over_fp64"] = value / v64
         del w64
         line["errors"] = error_table(mol, min(W, 1024), walkers, ctx, ctx64)
+        del ctx64
+    if args.workload == "21atom" and not args.no_fp64:
+        # the 9-atom molecule, 16384 walkers, FP64 path
+        spec9 = inputs.make_config(1)
+        m9 = spec9.molecule
+        c9 = vmc.Context(m9, max_walkers=spec9.n_walkers, refresh_period=32, precision="fp64")
+        w9 = torch.tensor(inputs.initial_walkers(m9, spec9.n_walkers, spec9.seed), device=dev)
+        dt9, _, _, _ = run_steps(c9, w9, spec9.seed, args.warmup, args.steps)
+        v9 = spec9.n_walkers * args.steps / dt9
+        print(f"# 9-atom fp64: {v9:.4g} walker-steps/s, {dt9 / args.steps * 1e3:.2f} ms/step", file=sys.stderr,
+              flush=True)
+        line["fp64_9atom"] = {"workload": f"{m9.name}: {m9.n_atoms} atoms, {m9.n_elec} electrons, "
+                                          f"{m9.basis.n_ao} cartesian AOs, {spec9.n_walkers} walkers, FP64",
+                              "value": v9, "ms_per_step": dt9 / args.steps * 1e3}
+        del c9, w9
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(line), flush=True)

@@ -234,8 +234,8 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
  * Errors: VMC_EINVAL (no samples); VMC_ESINGULAR if, since the last reset,
  * an inverse rebuild of the sweeps or of a measurement met a Slater block
  * that is singular to working precision (a pivot of at most 2^-40 times the
- * largest orbital value of its electron: e.g. two same-spin electrons at one
- * point, or an electron where every orbital vanishes); otherwise
+ * block's largest orbital value: e.g. two same-spin electrons at one point,
+ * or an electron where every orbital vanishes); otherwise
  * VMC_ENONFINITE if a measured E_L, ln|Psi| or log|det| was not finite (e.g.
  * a walker with a NaN coordinate).  On these two errors the outputs are
  * still written (they include the offending samples) and VMC_ACCUM_RESET

@@ -95,11 +95,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             T av[KN];
 #pragma unroll
             for (int r = 0; r < KN; ++r) av[r] = pa[(size_t)min(r, nb - 1) * 5 * n];
+            double mx = 0.0;
 #pragma unroll
-            for (int r = 0; r < KN; ++r)
-                Br[r] = (lz < nb && r < nb) ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // identity padding
-            const double tol = row_tol<KN>(ph + (size_t)(off + min(lz, nb - 1)) * 5 * n, nb, lz < nb);
-            gj_regs<KN, true>(Br, sig, bad, la, tol);
+            for (int r = 0; r < KN; ++r) {
+                const bool in = lz < nb && r < nb;
+                Br[r] = in ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // identity padding
+                mx = fmax(mx, in ? fabs(Br[r]) : 0.0);
+            }
+            gj_regs<KN, true>(Br, sig, bad, la, gj_tol(mx));
         }
         if (lane == 0) {
             red[4 + b] = la;

@@ -54,14 +54,13 @@ __device__ inline unsigned wave_max_u32(unsigned v) {
 // R[p_k][j] = B^-1[k][p_j], i.e. lane p_k holds column k of K = A^-1 with
 // register j holding orbital p_j.  On return sig = k on lane p_k (lanes >= KN:
 // sig = lane).  The block counts as singular (bad set) when a pivot is no
-// larger than rowtol of its step: lane k holds in rowtol the threshold of the
-// electron of register k (row_tol below; 0 for padding), so a row that is a
-// linear combination of the others to working precision, an all-zero row or
-// two coincident same-spin electrons, is reported.  A NaN pivot is not: it
-// leaves non-finite results, reported as such.  With LOGDET,
+// larger than tol (gj_tol below: 2^-40 of the block's largest entry), so a
+// row that is a linear combination of the others to working precision, e.g.
+// two coincident same-spin electrons, or an all-zero row is reported.  A NaN
+// pivot is not: it leaves non-finite results, reported as such.  With LOGDET,
 // logabs = sum_k log|pivot_k| = log|det B| (the identity padding adds 0).
 template <int KN, bool LOGDET>
-__device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &logabs, double rowtol) {
+__device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &logabs, double tol) {
     const int lane = threadIdx.x & 63;
     bool used = lane >= KN;
     sig = lane;
@@ -77,7 +76,7 @@ __device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &lo
         const int p = 63 - (int)(wave_max_u32(key) & 63u);
         const bool me = lane == p;
         const double piv = readlane_d(a0, p);
-        if (fabs(piv) <= readlane_d(rowtol, k)) bad = true;
+        if (fabs(piv) <= tol) bad = true;
         if (LOGDET) logabs += log(fabs(piv));
         const double inv = rcp_nr(piv);   // a few ulp; a zero pivot is flagged above
         if (me) {
@@ -94,20 +93,14 @@ __device__ inline void gj_regs(double (&Br)[KN], int &sig, bool &bad, double &lo
     }
 }
 
-// Singularity threshold of row `row` of a spin block's Slater matrix (the
-// electron's orbital values, nb of them, row[i] for i < nb): 2^-40 of its
-// largest magnitude, i.e. a pivot that lost 40 of the 53 significant bits of
-// its row.  The loads are clamped and unconditional (issued together); NaN
-// entries are ignored by fmax.  Lanes with on == false return 0.
-template <int KN, typename T>
-__device__ inline double row_tol(const T *row, int nb, bool on) {
-    T v[KN];
-#pragma unroll
-    for (int i = 0; i < KN; ++i) v[i] = row[min(i, nb - 1)];
-    double m = 0.0;
-#pragma unroll
-    for (int i = 0; i < KN; ++i) m = fmax(m, fabs((double)v[i]));
-    return on ? m * 0x1p-40 : 0.0;
+// Singularity threshold of gj_regs from each lane's largest |entry| of the
+// block (padding excluded): 2^-40 of the block's largest entry, i.e. a pivot
+// that lost 40 of the 53 significant bits.  The wavefront maximum is taken
+// on the high words of the non-negative doubles (monotonic in the value),
+// rounded up; NaN entries must be left out by the caller (fmax does).
+__device__ inline double gj_tol(double lane_max) {
+    const unsigned hi = wave_max_u32((unsigned)__double2hiint(lane_max));
+    return __hiloint2double((int)hi, -1) * 0x1p-40;
 }
 
 }  // namespace vmcx

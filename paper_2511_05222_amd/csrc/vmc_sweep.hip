@@ -43,11 +43,15 @@ __device__ inline void rebuild(const T *Aw, int n, int off, int nb, T (&Kr)[KN],
 #pragma unroll
     for (int r = 0; r < KN; ++r) av[r] = pa[(size_t)min(r, nb - 1) * n];
     double Br[KN];
+    double mx = 0.0;
 #pragma unroll
-    for (int r = 0; r < KN; ++r) Br[r] = (lz < nb && r < nb) ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // padding
+    for (int r = 0; r < KN; ++r) {
+        const bool in = lz < nb && r < nb;
+        Br[r] = in ? (double)av[r] : ((lz == r) ? 1.0 : 0.0);   // padding
+        mx = fmax(mx, in ? fabs(Br[r]) : 0.0);
+    }
     double la;
-    const double tol = row_tol<KN>(Aw + (size_t)(off + min(lz, nb - 1)) * n, nb, lz < nb);
-    gj_regs<KN, false>(Br, sig, bad, la, tol);
+    gj_regs<KN, false>(Br, sig, bad, la, gj_tol(mx));
 #pragma unroll
     for (int r = 0; r < KN; ++r) Kr[r] = (T)Br[r];
 }
