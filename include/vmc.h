@@ -352,6 +352,24 @@ int zvector_jackknife(const double *x_jk_dev, int64_t n_blocks, int64_t len, dou
 int zvector_solve(const double *H_dev, int64_t d, int64_t n_rhs, const double *b_dev, double *z_dev,
                   double rtol, int32_t maxit, uint32_t flags, int32_t *iters, void *stream);
 
+/* zvector_solve_noalloc: zvector_solve with no device allocation, for
+ * callers that cannot allocate device memory (code between the steps of a
+ * captured or replayed sequence, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as zvector_solve, except
+ * that the right-hand sides are solved one after another (no batch shares
+ * the reads of H) and d <= ZVECTOR_NOALLOC_MAX_D (VMC_EINVAL beyond).  The
+ * CG state (about 4.1 d doubles) lives in a library-owned device array of
+ * 2.5 MiB on each GPU, taken on the first call on that GPU and kept until
+ * the process ends; it allocates nothing else (no hipMalloc, hipFree or
+ * allocating library call).  All calls on one GPU share that array: calls
+ * that overlap in time on one GPU (two host threads, or two streams without
+ * synchronisation between them) race and give undefined results.  Every
+ * value of the array is written before it is read, so what an earlier call
+ * left there does not matter.  Synchronises `stream`. */
+#define ZVECTOR_NOALLOC_MAX_D 65536
+int zvector_solve_noalloc(const double *H_dev, int64_t d, int64_t n_rhs, const double *b_dev, double *z_dev,
+                          double rtol, int32_t maxit, uint32_t flags, int32_t *iters, void *stream);
+
 /* Most walkers processed per measurement launch (size of the per-walker
  * staging); returns -1 for a NULL context. */
 int64_t vmc_staging_walkers(const vmc_ctx *ctx);

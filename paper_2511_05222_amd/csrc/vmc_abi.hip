@@ -387,6 +387,35 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
     return VMC_OK;
 }
 
+// Device scratch of zvector_solve_noalloc: one copy of this array per GPU,
+// held until the process ends.  Its name is a host-side stand-in; the device
+// address of each GPU's copy comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is used.
+constexpr int64_t NOALLOC_DOUBLES = int64_t(5) << 16;   // 2.5 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Address of the current device's copy of `scratch` (nullptr on failure).
+static double *noalloc_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 static int set_device(vmc_ctx *c) {
     HIP_OK(c, hipSetDevice(c->device));
     return VMC_OK;
@@ -1052,6 +1081,34 @@ int zvector_solve(const double *H, int64_t d, int64_t n_rhs, const double *b, do
     }
     (void)hipStreamSynchronize(st);
     (void)hipFree(work);
+    return status;
+}
+
+int zvector_solve_noalloc(const double *H, int64_t d, int64_t n_rhs, const double *b, double *z, double rtol,
+                          int32_t maxit, uint32_t flags, int32_t *iters, void *stream) {
+    if (!H || !b || !z || d < 1 || n_rhs < 1 || !(rtol > 0.0) || maxit < 1 || (flags & ~(uint32_t)ZVECTOR_JACOBI))
+        return VMC_EINVAL;
+    // r, p, Hp, dinv, the matvec partials, then the iteration state
+    const int64_t need = 4 * d + vmcx::cg_matvec_blocks(d) +
+                         (int64_t)((sizeof(vmcx::CgState) + sizeof(double) - 1) / sizeof(double));
+    if (d > ZVECTOR_NOALLOC_MAX_D || need > NOALLOC_DOUBLES) return VMC_EINVAL;
+    if (iters)
+        for (int64_t k = 0; k < n_rhs; ++k) iters[k] = 0;
+    double *work = noalloc_scratch();
+    if (!work) return VMC_EDEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    // every scratch value is written by the setup kernel before it is read,
+    // so what the last call left there does not matter
+    int status = VMC_OK;
+    for (int64_t k = 0; k < n_rhs; ++k) {
+        const int rc = cg_one(H, d, b + k * d, z + k * d, rtol, maxit, flags, iters ? iters + k : nullptr, work, st);
+        if (rc != VMC_OK && status == VMC_OK) status = rc;
+        if (rc == VMC_EDEVICE) break;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return VMC_EDEVICE;
+    }
     return status;
 }
 

@@ -28,7 +28,7 @@ VMC_ACCUM_RESET = 1
 EXPORTED = ["vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
             "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap", "zvector_jackknife",
             "vmc_staging_walkers", "vmc_free", "vmc_last_error", "vmc_init_error", "vmc_strerror", "vmc_profile",
-            "vmc_profile_read"]
+            "vmc_profile_read", "zvector_solve_noalloc"]
 
 
 class VmcError(RuntimeError):
@@ -89,6 +89,7 @@ def lib():
     L.vmc_adjoint.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_jackknife.argtypes = [vp, vp, vp, vp, ct.POINTER(i64), vp]
     L.zvector_solve.argtypes = [vp, i64, i64, vp, vp, dbl, i32, u32, vp, vp]
+    L.zvector_solve_noalloc.argtypes = [vp, i64, i64, vp, vp, dbl, i32, u32, vp, vp]
     L.zvector_rhs.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
     L.zvector_backmap.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp]
     L.zvector_jackknife.argtypes = [vp, i64, i64, vp, vp, vp]
@@ -106,7 +107,7 @@ def lib():
     L.vmc_strerror.restype = ct.c_char_p
     for name in ("vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
                  "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap",
-                 "zvector_jackknife", "vmc_profile", "vmc_profile_read"):
+                 "zvector_jackknife", "vmc_profile", "vmc_profile_read", "zvector_solve_noalloc"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -337,6 +338,29 @@ def zvector_solve(H, b, rtol=1e-12, maxit=1000, jacobi=False):
                              ZVECTOR_JACOBI if jacobi else 0, ct.cast(it, ct.c_void_p), _stream())
     _zv_check(rc)
     return z, (it[0] if single else list(it))
+
+
+ZVECTOR_NOALLOC_MAX_D = 65536
+
+
+def zvector_solve_noalloc(H, b, z, rtol=1e-12, maxit=1000, jacobi=False):
+    """zvector_solve into a caller-provided z (same shape as b), with no
+    device allocation by the library (its CG state lives in a fixed device
+    array; right-hand sides are solved one after another).  Returns the
+    iterations (an int, or a list for a batch)."""
+    d = H.shape[0]
+    _check_dev(H, (d, d))
+    _check_dev(b, tuple(b.shape))
+    _check_dev(z, tuple(b.shape))
+    single = b.numel() == d
+    n_rhs = 1 if single else b.shape[0]
+    if b.numel() != n_rhs * d:
+        raise ValueError(f"b has {b.numel()} values, not a multiple {n_rhs} x {d}")
+    it = (ct.c_int32 * n_rhs)()
+    rc = lib().zvector_solve_noalloc(_ptr(H), d, n_rhs, _ptr(b), _ptr(z), float(rtol), int(maxit),
+                                     ZVECTOR_JACOBI if jacobi else 0, ct.cast(it, ct.c_void_p), _stream())
+    _zv_check(rc)
+    return it[0] if single else list(it)
 
 
 def _batch(x, shape2):
