@@ -50,9 +50,11 @@ METRIC = "walker-steps/s (fwd+adjoint) mixed vs FP64 on 1 GPU; force err Ha/bohr
 PEAK_MFMA = {"mixed": 157.3, "fp64": 78.6}
 PEAK_ALU = 78.6
 PEAK_HBM = 8000.0
-KERNELS = {"sweep": "k_sweep_r", "mo_rows": "k_mo_rows_mfma", "dense": "k_dense", "adjoint": "k_adjoint_mfma"}
+KERNELS = {"sweep": "k_sweep_r", "proposals": "k_mo_rows_mfma (proposals)", "mo_rows": "k_mo_rows_mfma",
+           "dense": "k_dense", "adjoint": "k_adjoint_mfma"}
 KERNEL_SRCS = {
     "sweep": ("vmc_sweep.hip", "vmc_regs.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
+    "proposals": ("vmc_sweep.hip", "vmc_mo.hip", "vmc_mfma.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
     "mo_rows": ("vmc_mo.hip", "vmc_mfma.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
     "dense": ("vmc_dense.hip", "vmc_mfma.hpp", "vmc_regs.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
     "adjoint": ("vmc_adjoint.hip", "vmc_mfma.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
@@ -68,14 +70,18 @@ def work_model(mol, precision, p_acc):
     no recomputation beyond the design's recompute-not-store rule), with
     N electrons, n orbitals per spin, M AOs, P primitives, S shells, A
     atoms, p the measured acceptance:
-      sweep    per move: AO values at r' (per primitive alpha*rho and c*e,
-               per shell rho, per AO monomial x radial: 3P + 6S + 3M), the
-               MO row psi^T C (2Mn), the ratio (2n), the Jastrow difference
-               (N - 1 pairs, old and new distance, 24 flops), on accept the
+      proposals  per walker-sweep, the N proposals' AO values (per
+               primitive alpha*rho and c*e, per shell rho, per AO monomial
+               x radial: 3P + 6S + 3M each) and MO rows psi^T C (2NMn on the
+               matrix cores); bytes: positions read, proposals written and
+               read, the N n orbital values written.
+      sweep    per move: the ratio (2n), the Jastrow difference (N - 1
+               pairs, old and new distance, 24 flops), on accept the
                Sherman-Morrison update (2n^2); per block every 32 moves an
-               inverse (2n^3, FP64).  Bytes: positions in and out, both
-               blocks' inverses in and out (in the arithmetic type), MO
-               rows written on accept, read back at each rebuild.
+               inverse (2n^3, FP64).  Bytes: positions and proposals in,
+               positions out, the proposals' orbital rows in, both blocks'
+               inverses in and out (in the arithmetic type), MO rows
+               written on accept, read back at each rebuild.
       mo_rows  AO value, gradient, Laplacian (10 flops per primitive, 15 per
                AO) and the five products psi C (10 NMn on the matrix cores);
                bytes: the 5Nn orbital values written.
@@ -90,9 +96,10 @@ def work_model(mol, precision, p_acc):
     N, n, M, P, S, A = mol.n_elec, mol.n_occ, b.n_ao, b.n_prim, b.n_shells, mol.n_atoms
     ts = 4 if precision == "mixed" else 8
     ao_val = 3 * P + 6 * S + 3 * M
-    sweep_alu = N * (ao_val + 2 * M * n + 2 * n + 24 * (N - 1) + p_acc * 2 * n * n) + (N / 32.0) * 2 * n ** 3
-    sweep_hbm = 2 * 24 * N + 2 * 2 * (n * n * ts) + p_acc * N * n * ts + (N / 32.0) * n * n * ts
+    sweep_alu = N * (2 * n + 24 * (N - 1) + p_acc * 2 * n * n) + (N / 32.0) * 2 * n ** 3
+    sweep_hbm = 3 * 24 * N + N * n * ts + 2 * 2 * (n * n * ts) + p_acc * N * n * ts + (N / 32.0) * n * n * ts
     return {
+        "proposals": {"mfma": 2.0 * N * M * n, "alu": float(N * ao_val), "hbm": float(3 * 24 * N + N * n * ts)},
         "sweep": {"mfma": 0.0, "alu": float(sweep_alu), "hbm": float(sweep_hbm)},
         "mo_rows": {"mfma": 10.0 * N * M * n, "alu": float(N * (10 * P + 6 * S + 15 * M)),
                     "hbm": float(24 * N + 5 * N * n * ts)},
@@ -171,7 +178,7 @@ def run_steps(ctx, walkers, seed, warmup, steps):
     ctx.sweep(walkers, steps, seed, sweep_offset=warmup)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = {k: ctx.profile_read(k) for k in ("adjoint", "dense", "mo_rows", "sweep")}
+    prof = {k: ctx.profile_read(k) for k in ("adjoint", "dense", "mo_rows", "sweep", "proposals")}
     ctx.profile(False)
     res = ctx.accumulate(reset=True)
     # acceptance of one more sweep on a copy (untimed, not accumulated)

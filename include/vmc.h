@@ -386,7 +386,10 @@ int64_t vmc_staging_walkers(const vmc_ctx *ctx);
 #define VMC_K_ADJOINT   0    /* k_adjoint_mfma: back-projection, outer products */
 #define VMC_K_DENSE     1    /* k_dense: inverses, E_L, (K X K)^T / 2           */
 #define VMC_K_MO_ROWS   2    /* k_mo_rows_mfma (value, gradient, Laplacian)      */
-#define VMC_K_SWEEP     3    /* k_sweep_r: one sweep of all walkers              */
+#define VMC_K_SWEEP     3    /* k_sweep_r: the moves of one sweep of all walkers */
+#define VMC_K_PROPOSALS 4    /* k_propose + k_mo_rows_mfma (values): a sweep's
+                                proposals and their MO rows                      */
+#define VMC_N_PROFILED  5
 int vmc_profile(vmc_ctx *ctx, int32_t enable);
 int vmc_profile_read(vmc_ctx *ctx, int32_t kernel, double *ms, int64_t *launches, int64_t *walkers);
 

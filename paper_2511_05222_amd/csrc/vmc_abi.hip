@@ -82,6 +82,8 @@ struct vmc_ctx {
     double *mb_phi = nullptr, *mb_ktil = nullptr, *mb_abar = nullptr, *mb_gb = nullptr, *mb_dpart = nullptr,
            *mb_tao = nullptr, *mb_posw = nullptr;
     void *Amo = nullptr;     // [max_walkers][N][n] MO matrix maintained by the sweep (type T)
+    void *Phip = nullptr;    // [max_walkers][N][n] MO rows at the sweep's proposals (type T)
+    double *prop = nullptr;  // [max_walkers][N][3] the sweep's proposals
     void *Kst = nullptr;     // [max_walkers][2][KN][KN] persistent inverses (type T)
     uint8_t *Ksig = nullptr; // [max_walkers][2][KN]
     int *Kstale = nullptr;   // [max_walkers][2]
@@ -103,7 +105,7 @@ struct vmc_ctx {
         int64_t walkers;
     };
     bool prof = false;
-    std::vector<ProfRec> prof_recs[4];
+    std::vector<ProfRec> prof_recs[VMC_N_PROFILED];
 
     int64_t n_est = 0;
     double *acc = nullptr, *comp = nullptr, *partial = nullptr;
@@ -188,57 +190,29 @@ static void prof_end(vmc_ctx *c, int k, int idx, hipStream_t st) {
 }
 
 // LDS layout of the sweep for an arithmetic type of ts bytes and blocks of
-// wpb walkers.
+// wpb walkers: two broadcast vectors per wavefront.
 static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts, int wpb) {
     SweepLayout s{};
-    const int n = c->n_occ, M = c->M;
     auto al = [](size_t b) { return (int)((b + 15) & ~(size_t)15); };
-    // lane groups of the MO-row product (as in the kernel) and 16-byte vectors
-    const int npad = n <= 16 ? 16 : (n <= 32 ? 32 : 64), G = 64 / npad, vw = (int)(16 / ts);
-    s.mchunk = ((M + G - 1) / G + vw - 1) / vw * vw;
-    s.mpad = G * s.mchunk;
-    // row stride: a whole number of 16-byte vectors plus half a 32-byte bank
-    // group (4 floats or 2 doubles), so that the 16-byte reads of lanes walking
-    // their own rows spread over all banks
-    s.ldc = s.mpad;
-    while ((s.ldc * ts) % 32 != 16) s.ldc += vw;
-    size_t o = al((size_t)n * s.ldc * ts);
-    s.off_R = (int)o;
-    o += al((size_t)3 * c->A * sizeof(double));
-    s.off_pexp = (int)o;
-    o += al((size_t)c->P * ts);
-    s.off_pcp = (int)o;
-    o += al((size_t)c->P * ts);
-    s.off_sha = (int)o;
-    o += al((size_t)c->S * 4);
-    s.off_shb = (int)o;
-    o += al((size_t)c->S * 4);
-    s.block_bytes = (int)o;
-    const int kn = vmcx::sweep_kn(n);
+    const int kn = vmcx::sweep_kn(c->n_occ);
     size_t w = 0;
-    s.off_psi = 0;
-    w += al((size_t)s.mpad * ts);
     s.off_phin = (int)w;
     w += al((size_t)kn * ts);
     s.off_colj = (int)w;
     w += al((size_t)kn * ts);
     s.wave_bytes = (int)w;
     s.wpb = wpb;
-    s.bytes = o + (size_t)wpb * w;
+    s.bytes = (size_t)wpb * w;
     return s;
 }
 
-// The block size that keeps the most walkers resident on a CU.  Every block
-// holds its own copy of the shared tables, so small blocks repeat them; large
-// blocks leave wavefront slots empty when the registers would allow more
-// resident wavefronts than whole blocks fit in LDS.  Ties go to the larger
-// block.
+// The block size that keeps the most walkers resident on a CU (ties go to
+// the larger block).
 static SweepLayout sweep_layout(const vmc_ctx *c, size_t ts) {
     SweepLayout best = sweep_layout(c, ts, 1);
     int best_res = -1;
     for (int wpb : {8, 4, 2}) {
         const SweepLayout s = sweep_layout(c, ts, wpb);
-        if (s.bytes > 160 * 1024) continue;
         const int nb = ts == sizeof(float) ? vmcx::sweep_blocks_per_cu<float>(c->n_occ, wpb, s.bytes)
                                            : vmcx::sweep_blocks_per_cu<double>(c->n_occ, wpb, s.bytes);
         if (nb * wpb > best_res) {
@@ -687,6 +661,9 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->mb_dpart, chunk * 3 * (int64_t)c->N)) ||
         (rc = c->dalloc(&c->mb_tao, chunk * 6 * M)) || (rc = c->dalloc(&c->mb_posw, chunk * 3 * c->N)) ||
         (rc = c->dalloc((double **)&c->Amo, (size_t)opt->max_walkers * Nn)) ||
+        (rc = c->dalloc((double **)&c->Phip, (size_t)opt->max_walkers * Nn * (opt->precision == VMC_MIXED ? 4 : 8) /
+                                                 8 + 1)) ||
+        (rc = c->dalloc(&c->prop, (size_t)opt->max_walkers * 3 * c->N)) ||
         (rc = c->dalloc((double **)&c->Kst, (size_t)opt->max_walkers * 2 * vmcx::sweep_kn(c->n_occ) *
                                                 vmcx::sweep_kn(c->n_occ))) ||
         (rc = c->dalloc(&c->Ksig, (size_t)opt->max_walkers * 2 * vmcx::sweep_kn(c->n_occ))) ||
@@ -743,26 +720,36 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
         uint8_t *acc_t = accept ? accept + (size_t)t * c->N * W : nullptr;
         // the MO matrix of every walker from the caller's positions; the
         // sweeps keep it current (row e rewritten on each accepted move)
+        // the proposals of every electron and their MO rows (independent of
+        // the moves' outcomes), then the moves
+        const int pp = prof_begin(c, VMC_K_PROPOSALS, true, W, st);
+        HIP_OK(c, vmcx::launch_propose(walkers, W, c->N, sidx, seed, c->opt.step_sigma, c->prop, st));
         if (c->opt.precision == VMC_MIXED) {
             float *Amo = (float *)c->Amo;
+            HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, c->prop, W * c->N, c->tiles16,
+                                                      (float *)c->Phip, 1, (float *)c->d_cpad, st));
+            prof_end(c, VMC_K_PROPOSALS, pp, st);
             if (t == 0)
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, walkers, W * c->N, c->tiles16,
                                                           Amo, 1, (float *)c->d_cpad, st));
             const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
             const vmcx::KState<float> ks{(float *)c->Kst, c->Ksig, c->Kstale};
-            HIP_OK(c, vmcx::launch_sweep<float>(c->sys, c->d_Cf, c->d_R, walkers, (int)W, Amo, ks, t == 0, sidx,
-                                                seed, c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status,
-                                                c->swl, st));
+            HIP_OK(c, vmcx::launch_sweep<float>(c->sys, (const float *)c->Phip, c->prop, walkers, (int)W, Amo, ks,
+                                                t == 0, sidx, seed, c->opt.refresh_period, acc_t, c->status, c->swl,
+                                                st));
             prof_end(c, VMC_K_SWEEP, pi, st);
         } else {
             double *Amo = (double *)c->Amo;
+            HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, c->prop, W * c->N, c->tiles16,
+                                                       (double *)c->Phip, 1, c->d_cpad, st));
+            prof_end(c, VMC_K_PROPOSALS, pp, st);
             if (t == 0)
                 HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
                                                            Amo, 1, c->d_cpad, st));
             const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
             const vmcx::KState<double> ks{(double *)c->Kst, c->Ksig, c->Kstale};
-            HIP_OK(c, vmcx::launch_sweep<double>(c->sys, c->d_C, c->d_R, walkers, (int)W, Amo, ks, t == 0, sidx,
-                                                 seed, c->opt.step_sigma, c->opt.refresh_period, acc_t, c->status,
+            HIP_OK(c, vmcx::launch_sweep<double>(c->sys, (const double *)c->Phip, c->prop, walkers, (int)W, Amo, ks,
+                                                 t == 0, sidx, seed, c->opt.refresh_period, acc_t, c->status,
                                                  c->swl, st));
             prof_end(c, VMC_K_SWEEP, pi, st);
         }
@@ -1154,7 +1141,8 @@ int vmc_profile(vmc_ctx *c, int32_t enable) {
 
 int vmc_profile_read(vmc_ctx *c, int32_t kernel, double *ms, int64_t *launches, int64_t *walkers) {
     if (!c) return VMC_EINVAL;
-    if (kernel < 0 || kernel > 3) return c->fail(VMC_EINVAL, "vmc_profile_read: unknown kernel %d", kernel);
+    if (kernel < 0 || kernel >= VMC_N_PROFILED)
+        return c->fail(VMC_EINVAL, "vmc_profile_read: unknown kernel %d", kernel);
     int rc;
     if ((rc = set_device(c))) return rc;
     double tot = 0.0;

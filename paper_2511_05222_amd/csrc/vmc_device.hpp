@@ -53,15 +53,20 @@ __host__ __device__ inline void box_muller(uint32_t a, uint32_t b, double &z0, d
 }
 
 // Three proposal normals and the accept uniform of one move.
-__host__ __device__ inline void move_draws(uint64_t seed, uint32_t walker, uint32_t sweep,
-                                           uint32_t electron, double z[3], double &u) {
+// The proposal's three normals z of one move.
+__host__ __device__ inline void move_normals(uint64_t seed, uint32_t walker, uint32_t sweep,
+                                             uint32_t electron, double z[3]) {
     const U4 a = draw_words(seed, walker, sweep, electron, PURPOSE_NORMAL);
     double t;
     box_muller(a.x, a.y, z[0], z[1]);
     box_muller(a.z, a.w, z[2], t);
+}
+
+// The accept test's uniform u in [0, 1) of one move (53 random bits).
+__host__ __device__ inline double move_uniform(uint64_t seed, uint32_t walker, uint32_t sweep, uint32_t electron) {
     const U4 b = draw_words(seed, walker, sweep, electron, PURPOSE_UNIFORM);
     const uint64_t bits = ((uint64_t)b.x << 21) | ((uint64_t)b.y >> 11);
-    u = (double)bits * 1.1102230246251565e-16;                      // 2^-53
+    return (double)bits * 1.1102230246251565e-16;                   // 2^-53
 }
 
 // ---------------------------------------------------------------------------

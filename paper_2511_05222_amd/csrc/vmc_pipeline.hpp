@@ -11,26 +11,13 @@ struct AoTiles {
     int n_tiles;
 };
 
-// LDS layout of k_sweep_r (bytes): a block-shared region (C transposed with
-// odd row stride ldc, then the basis tables) followed by wpb wavefront regions.
+// LDS layout of k_sweep_r (bytes): wpb wavefront regions of two broadcast
+// vectors each.
 struct SweepLayout {
-    int ldc;                                        // row stride of Ct (elements)
-    int mpad, mchunk;                               // AO range padded for the vector loop, per lane group
-    int off_R, off_pexp, off_pcp, off_sha, off_shb;  // basis tables
-    int block_bytes;                                // block-shared region
-    int off_psi, off_phin, off_colj;                // within a wavefront region
+    int off_phin, off_colj;                         // within a wavefront region
     int wave_bytes;
     int wpb;                                        // walkers (wavefronts) per block
     size_t bytes;                                   // per block
-};
-
-// Basis tables of the sweep in LDS: atom centres [A][3]; primitive exponents
-// and folded coefficients (type T); per shell atom | l << 8 | nprim << 12 and
-// first AO | first primitive << 16.
-struct SweepBasisLds {
-    double *R;
-    void *pexp, *pcp;
-    int *sha, *shb;
 };
 
 // LDS layout of k_dense (bytes).
@@ -92,10 +79,15 @@ struct KState {
 };
 
 int sweep_kn(int n_occ);
+// prop[w][e] = walkers[w][e] + sigma z_e for the W walkers (Philox normals of
+// the sweep)
+hipError_t launch_propose(const double *walkers, int64_t W, int N, uint32_t sweep, uint64_t seed, double sigma,
+                          double *prop, hipStream_t st);
+// The moves of one sweep; Phip[w][e][n] = the MO row at the proposal prop[w][e]
 template <typename T>
-hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
-                        const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, double sigma,
-                        int refresh_period, uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st);
+hipError_t launch_sweep(const SysDev &S, const T *Phip, const double *prop, double *walkers, int W, T *Amo,
+                        const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period,
+                        uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st);
 hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const double *pos0, double *posw,
                        double *lnjac, int W, hipStream_t st);
 template <typename T>

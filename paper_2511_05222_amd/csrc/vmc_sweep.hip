@@ -1,25 +1,32 @@
 // vmc_sweep.hip -- single-electron Metropolis sweeps on gfx950.
 //
-// One wavefront per walker, L.wpb walkers per block.  Shared by the block in
-// LDS: the MO coefficients C (transposed, odd row stride; every proposed move
-// needs phi(r') = psi(r')^T C, i.e. all of C) and the basis tables (atom
-// centres, primitives, packed shell descriptors).  Per wavefront in LDS: the
-// AO values psi(r') and two broadcast vectors.  Everything else of the walker
+// Every electron moves once per sweep, from its position at the start of the
+// sweep, so all N proposals r'_e = r_e + sigma z_e of a sweep are known before
+// its first move and none depends on an earlier move's outcome.  A sweep is
+// therefore three launches:
+//   k_propose      the proposals of every (walker, electron) (Philox normals);
+//   k_mo_rows_mfma their MO rows phi(r'_e) = psi(r'_e)^T C, one product of
+//                  [W N x M] by [M x n] on the matrix cores (vmc_mo.hip);
+//   k_sweep_r      the moves in order, per walker: ratio, Jastrow difference,
+//                  accept, Sherman-Morrison update, refreshes.
+// k_sweep_r runs one wavefront per walker, L.wpb walkers per block.  Per
+// wavefront in LDS: two broadcast vectors.  Everything else of the walker
 // lives in registers:
-//   * positions: lane l holds electrons l and l + 64;
-//   * the draws of this sweep: lane l holds those of electrons l and l + 64;
+//   * positions and proposals: lane l holds electrons l and l + 64;
+//   * the uniforms of this sweep: lane l holds those of electrons l and l + 64;
 //   * the inverse K of the spin block being swept: KN registers per lane,
 //     lane p_k holding column k (electron k of the block), register r holding
 //     orbital p_r, where p is the pivot order of the last rebuild (gj_regs).
 // The MO matrix A[e][i] = phi_i(r_e) of every walker lives in HBM (type T);
-// row e is rewritten on each accepted move of e.  Both blocks' inverses
-// persist across sweeps: at the end of a block the registers go to HBM (Kst,
-// with the layout permutation and a flag for a rebuild still due), and at the
-// block's next start they come back.  A block's inverse is rebuilt from A in
-// FP64 at the first sweep of a call (fresh), after every refresh_period-th
-// proposed move of that block (its own move index sweep * nb + j), and after
-// an accepted move with |ratio| < 1e-8; a rebuild that falls due after the
-// block's last move is carried to its next start by the flag.
+// row e is rewritten (from the proposal's row) on each accepted move of e.
+// Both blocks' inverses persist across sweeps: at the end of a block the
+// registers go to HBM (Kst, with the layout permutation and a flag for a
+// rebuild still due), and at the block's next start they come back.  A
+// block's inverse is rebuilt from A in FP64 at the first sweep of a call
+// (fresh), after every refresh_period-th proposed move of that block (its own
+// move index sweep * nb + j), and after an accepted move with |ratio| below
+// the forced-refresh threshold; a rebuild that falls due after the block's
+// last move is carried to its next start by the flag.
 #include "vmc_pipeline.hpp"
 #include "vmc_regs.hpp"
 
@@ -56,59 +63,19 @@ __device__ inline void rebuild(const T *Aw, int n, int off, int nb, T (&Kr)[KN],
     for (int r = 0; r < KN; ++r) Kr[r] = (T)Br[r];
 }
 
-// Values of the AOs of shell s at (rx, ry, rz) into psi, from the basis tables
-// in LDS.  Component factors: 1/sqrt(3) for xx, yy, zz; 1 otherwise.
-template <typename T>
-__device__ inline void shell_values_lds(const SweepBasisLds &B, int s, double rx, double ry, double rz, T *psi) {
-    const int sa = B.sha[s], sb = B.shb[s];
-    const int atom = sa & 255, l = (sa >> 8) & 15, np = sa >> 12;
-    const int mu0 = sb & 0xFFFF, p0 = sb >> 16;
-    const T x = (T)(rx - B.R[3 * atom]), y = (T)(ry - B.R[3 * atom + 1]), z = (T)(rz - B.R[3 * atom + 2]);
-    const T rho = x * x + y * y + z * z;
-    const T *pe = (const T *)B.pexp + p0, *pc = (const T *)B.pcp + p0;
-    T r0 = T(0);
-    // (FP32, ratios only: the hardware exponential, relative error of order
-    // |a rho| 2^-23, negligible on the terms that are not already tiny)
-    for (int k = 0; k < np; ++k) {
-        if constexpr (sizeof(T) == sizeof(float))
-            r0 += pc[k] * __expf(-pe[k] * rho);
-        else
-            r0 += pc[k] * exp(-pe[k] * rho);
-    }
-    T *o = psi + mu0;
-    if (l == 0) {
-        o[0] = r0;
-    } else if (l == 1) {
-        o[0] = x * r0;
-        o[1] = y * r0;
-        o[2] = z * r0;
-    } else {
-        const T e3 = T(0.57735026918962576451);   // 1/sqrt(3)
-        o[0] = e3 * (x * x) * r0;
-        o[1] = (x * y) * r0;
-        o[2] = (x * z) * r0;
-        o[3] = e3 * (y * y) * r0;
-        o[4] = (y * z) * r0;
-        o[5] = e3 * (z * z) * r0;
-    }
+// Proposals of one sweep: prop[w][e] = r_e + sigma z_e, z_e the Philox
+// normals of (walker w, sweep, electron e).
+__global__ __launch_bounds__(256) void k_propose(const double *__restrict__ walkers, int64_t n_rows, int N,
+                                                 uint32_t sweep, uint64_t seed, double sigma,
+                                                 double *__restrict__ prop) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_rows) return;
+    const uint32_t w = (uint32_t)(k / N), e = (uint32_t)(k - (int64_t)w * N);
+    double z[3];
+    move_normals(seed, w, sweep, e, z);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) prop[3 * k + d] = fma(sigma, z[d], walkers[3 * k + d]);
 }
-
-// 16-byte vectors of the MO-row product (four FP32 or two FP64 lanes of LDS
-// per load; the element-wise products are plain scalar FMAs).
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<float> {
-    typedef float type __attribute__((ext_vector_type(4)));
-    static constexpr int W = 4;
-    __device__ static float sum(type v) { return (v.x + v.y) + (v.z + v.w); }
-};
-template <>
-struct Vec16<double> {
-    typedef double type __attribute__((ext_vector_type(2)));
-    static constexpr int W = 2;
-    __device__ static double sum(type v) { return v.x + v.y; }
-};
 
 // Sum over the pairs (e, k) of u(|r' - r_k|) - u(|r_e - r_k|), the lane's k
 // being lane and lane + 64, reduced over the wavefront.  FP64: exact sqrt and
@@ -168,71 +135,45 @@ constexpr int sweep_waves() {
 }
 
 template <typename T, int KN>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves<T, KN>()))) void k_sweep_r(SysDev S, const T *__restrict__ Cg, const double *__restrict__ R,
-                                                  double *walkers, int W, T *Amo, KState<T> ks, int fresh,
-                                                  uint32_t sweep, uint64_t seed, double sigma, int refresh_period,
-                                                  uint8_t *accept, int *status, SweepLayout L) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves<T, KN>()))) void k_sweep_r(
+    SysDev S, const T *__restrict__ Phip, const double *__restrict__ prop, double *walkers, int W, T *Amo,
+    KState<T> ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period, uint8_t *accept, int *status,
+    SweepLayout L) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int N = S.N, nu = S.n_up, n = S.n_occ, M = S.M, NS = S.basis.n_shells;
-    // block-shared: C transposed (Ct[i*ldc + mu] = C[mu][i]) and the basis
-    T *Ct = (T *)smem;
-    const int ldc = L.ldc;
-    SweepBasisLds B{(double *)(smem + L.off_R), smem + L.off_pexp, smem + L.off_pcp, (int *)(smem + L.off_sha),
-                    (int *)(smem + L.off_shb)};
-    for (int k = threadIdx.x; k < M * n; k += blockDim.x) {
-        const int mu = k / n, i = k - (k / n) * n;
-        Ct[i * ldc + mu] = Cg[k];
-    }
-    // zero padding of the rows up to mpad (the vector loop reads it)
-    for (int k = threadIdx.x; k < n * (L.mpad - M); k += blockDim.x) {
-        const int i = k / (L.mpad - M), mu = M + k - (k / (L.mpad - M)) * (L.mpad - M);
-        Ct[i * ldc + mu] = T(0);
-    }
-    for (int k = threadIdx.x; k < 3 * S.A; k += blockDim.x) B.R[k] = R[k];
-    for (int k = threadIdx.x; k < NS; k += blockDim.x) {
-        const int p0 = S.basis.shell_p0[k], np = S.basis.shell_np[k];
-        B.sha[k] = S.basis.shell_atom[k] | (S.basis.shell_l[k] << 8) | (np << 12);
-        B.shb[k] = S.basis.shell_mu0[k] | (p0 << 16);
-        for (int q = 0; q < np; ++q) {
-            ((T *)B.pexp)[p0 + q] = (T)S.basis.prim_exp[p0 + q];
-            ((T *)B.pcp)[p0 + q] = (T)S.basis.prim_cp[p0 + q];
-        }
-    }
-    __syncthreads();
+    const int N = S.N, nu = S.n_up, n = S.n_occ;
     const int w = blockIdx.x * (int)(blockDim.x >> 6) + wave;
-    if (w >= W) return;   // no block barrier follows
-    unsigned char *wbase = smem + L.block_bytes + (size_t)wave * L.wave_bytes;
-    T *psi = (T *)(wbase + L.off_psi);
+    if (w >= W) return;   // no block barrier in this kernel
+    unsigned char *wbase = smem + (size_t)wave * L.wave_bytes;
     T *phin = (T *)(wbase + L.off_phin);   // phin[r] = phi_{p_r}
     T *colj = (T *)(wbase + L.off_colj);   // column of the moved electron
-    for (int k = M + lane; k < L.mpad; k += 64) psi[k] = T(0);
     double *wp = walkers + (size_t)w * N * 3;
+    const double *pp = prop + (size_t)w * N * 3;
+    const T *phw = Phip + (size_t)w * N * n;
     T *Aw = Amo + (size_t)w * N * n;
-    // positions and this sweep's draws: lane l holds electrons l and l + 64
-    double px[2], py[2], pz[2], dz[2][3], du[2];
+    // positions, proposals and this sweep's uniforms: lane l holds electrons
+    // l and l + 64
+    double px[2], py[2], pz[2], qx[2], qy[2], qz[2], du[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int e = lane + 64 * h;
         const bool on = e < N;
+        const int ec = on ? e : 0;
         px[h] = on ? wp[3 * e] : 0.0;
         py[h] = on ? wp[3 * e + 1] : 0.0;
         pz[h] = on ? wp[3 * e + 2] : 0.0;
-        move_draws(seed, (uint32_t)w, sweep, (uint32_t)(on ? e : 0), dz[h], du[h]);
+        qx[h] = pp[3 * ec];
+        qy[h] = pp[3 * ec + 1];
+        qz[h] = pp[3 * ec + 2];
+        du[h] = move_uniform(seed, (uint32_t)w, sweep, (uint32_t)ec);
     }
     bool bad = false;
     T Kr[KN];
     int sig = lane;
 
-    const int npad = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
-    const int G = 64 / npad;
-    const int li = lane & (npad - 1), lg = lane / npad;
-    // lane group lg of the phi product covers AOs [lg*mchunk, (lg+1)*mchunk)
-    // of the zero-padded range [0, mpad), in 16-byte vectors
-    typedef typename Vec16<T>::type V;
-    const int nvec = L.mchunk / Vec16<T>::W;
-    const V *cvec = (const V *)(Ct + li * ldc + lg * L.mchunk);
-    const V *svec = (const V *)(psi + lg * L.mchunk);
+    // the proposal's MO row of the first move (later rows are loaded one move
+    // ahead, so that the load overlaps the move before)
+    T ph_next = lane < nu ? phw[lane] : T(0);
     bool need = true;
     for (int e = 0; e < N; ++e) {
         const int b = e < nu ? 0 : 1;
@@ -259,48 +200,22 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             need = false;
         }
         const int src = e & 63, h = e >> 6;
-        const double z0 = readlane_d(h ? dz[1][0] : dz[0][0], src);
-        const double z1 = readlane_d(h ? dz[1][1] : dz[0][1], src);
-        const double z2 = readlane_d(h ? dz[1][2] : dz[0][2], src);
         const double u = readlane_d(h ? du[1] : du[0], src);
         const double ex = readlane_d(h ? px[1] : px[0], src);
         const double ey = readlane_d(h ? py[1] : py[0], src);
         const double ez = readlane_d(h ? pz[1] : pz[0], src);
-        const double rx = ex + sigma * z0, ry = ey + sigma * z1, rz = ez + sigma * z2;
-        for (int s = lane; s < NS; s += 64) shell_values_lds<T>(B, s, rx, ry, rz, psi);
+        const double rx = readlane_d(h ? qx[1] : qx[0], src);
+        const double ry = readlane_d(h ? qy[1] : qy[0], src);
+        const double rz = readlane_d(h ? qz[1] : qz[0], src);
+        // phi_i(r') of lane i (zero from nb on); the next move's row in flight
+        const T ph = ph_next;
+        if (e + 1 < N) {
+            const int nb1 = e + 1 < nu ? nu : S.n_dn;
+            ph_next = lane < nb1 ? phw[(size_t)(e + 1) * n + lane] : T(0);
+        }
         // Jastrow difference over the pairs (e, k), k held by this lane (in
         // the arithmetic type: it only enters the acceptance ratio)
         double dj = jastrow_delta<T>(S, N, e, lane, rx, ry, rz, ex, ey, ez, px, py, pz);
-        wave_sync_s();
-        // phi_i(r') = sum_mu psi_mu C[mu][i]; lane group lg sums its AO range
-        T ph = T(0);
-        if (li < nb) {
-            // up to KN = 48: four vectors per step (16 FP32 or 8 FP64
-            // products per address increment); otherwise two (four would
-            // spill in the rebuild)
-            V a0 = V(T(0)), a1 = V(T(0));
-            int k = 0;
-            if constexpr (KN <= 48) {
-                V a2 = V(T(0)), a3 = V(T(0));
-                for (; k + 4 <= nvec; k += 4) {
-                    a0 += svec[k] * cvec[k];
-                    a1 += svec[k + 1] * cvec[k + 1];
-                    a2 += svec[k + 2] * cvec[k + 2];
-                    a3 += svec[k + 3] * cvec[k + 3];
-                }
-                a0 += a2;
-                a1 += a3;
-            } else {
-                for (; k + 2 <= nvec; k += 2) {
-                    a0 += svec[k] * cvec[k];
-                    a1 += svec[k + 1] * cvec[k + 1];
-                }
-            }
-            for (; k < nvec; ++k) a0 += svec[k] * cvec[k];
-            a0 += a1;
-            ph = Vec16<T>::sum(a0);
-        }
-        for (int o = npad; o < 64; o <<= 1) ph += __shfl_xor(ph, o, 64);
         // lane i < KN holds phi_i (zero from nb on): store it at the register
         // slot of orbital i
         if (lane < KN) phin[sig] = ph;
@@ -320,7 +235,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         const double qv = ratio * (sizeof(T) == sizeof(float) ? (double)expf((float)dj) : exp(dj));
         const bool acc = u < qv * qv;
         if (acc) {
-            if (lane < nb && lg == 0) Aw[(size_t)e * n + lane] = ph;
+            if (lane < nb) Aw[(size_t)e * n + lane] = ph;
             if (lane == src) {
                 if (h) {
                     px[1] = rx;
@@ -370,32 +285,40 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
 }
 
 template <typename T, int KN>
-static hipError_t launch_kn(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
-                            const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, double sigma,
-                            int refresh_period, uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
+static hipError_t launch_kn(const SysDev &S, const T *Phip, const double *prop, double *walkers, int W, T *Amo,
+                            const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period,
+                            uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_r<T, KN>), dim3((unsigned)((W + L.wpb - 1) / L.wpb)), dim3(64 * L.wpb), L.bytes, st,
-                       S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept, status, L);
+                       S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept, status, L);
     return hipGetLastError();
 }
 
 int sweep_kn(int n_occ) { return n_occ <= 16 ? 16 : (n_occ <= 32 ? 32 : (n_occ <= 48 ? 48 : 64)); }
 
+hipError_t launch_propose(const double *walkers, int64_t W, int N, uint32_t sweep, uint64_t seed, double sigma,
+                          double *prop, hipStream_t st) {
+    const int64_t rows = W * N;
+    hipLaunchKernelGGL(k_propose, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, walkers, rows, N, sweep,
+                       seed, sigma, prop);
+    return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_sweep(const SysDev &S, const T *C, const double *R, double *walkers, int W, T *Amo,
-                        const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, double sigma,
-                        int refresh_period, uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
+hipError_t launch_sweep(const SysDev &S, const T *Phip, const double *prop, double *walkers, int W, T *Amo,
+                        const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period,
+                        uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
     switch (sweep_kn(S.n_occ)) {
         case 16:
-            return launch_kn<T, 16>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+            return launch_kn<T, 16>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
                                     status, L, st);
         case 32:
-            return launch_kn<T, 32>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+            return launch_kn<T, 32>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
                                     status, L, st);
         case 48:
-            return launch_kn<T, 48>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+            return launch_kn<T, 48>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
                                     status, L, st);
         default:
-            return launch_kn<T, 64>(S, C, R, walkers, W, Amo, ks, fresh, sweep, seed, sigma, refresh_period, accept,
+            return launch_kn<T, 64>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
                                     status, L, st);
     }
 }
@@ -412,11 +335,11 @@ hipError_t configure_sweep(size_t lds) {
 }
 
 template hipError_t launch_sweep<double>(const SysDev &, const double *, const double *, double *, int, double *,
-                                         const KState<double> &, int, uint32_t, uint64_t, double, int, uint8_t *,
-                                         int *, const SweepLayout &, hipStream_t);
+                                         const KState<double> &, int, uint32_t, uint64_t, int, uint8_t *, int *,
+                                         const SweepLayout &, hipStream_t);
 template hipError_t launch_sweep<float>(const SysDev &, const float *, const double *, double *, int, float *,
-                                        const KState<float> &, int, uint32_t, uint64_t, double, int, uint8_t *,
-                                        int *, const SweepLayout &, hipStream_t);
+                                        const KState<float> &, int, uint32_t, uint64_t, int, uint8_t *, int *,
+                                        const SweepLayout &, hipStream_t);
 template <typename T>
 int sweep_blocks_per_cu(int n_occ, int wpb, size_t lds) {
     const void *f[4] = {(const void *)k_sweep_r<T, 16>, (const void *)k_sweep_r<T, 32>,
