@@ -229,7 +229,9 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
  *   B = dE/dC), dEL_dC_mean[n_ao][n_occ] = <dE_L/dC> (may be NULL),
  *   n_samples (may be NULL).
  * All sums are FP64, shifted by the mean E_L of the first measured batch and
- * compensated (Neumaier).  Synchronises `stream`.
+ * compensated (Neumaier); every sample carries its weight (1 for the sweeps'
+ * own measurements, see vmc_accumulate_walkers) and the averages divide by
+ * the sum of the weights.  Synchronises `stream`.
  * flags & VMC_ACCUM_RESET clears the accumulators afterwards.
  * Errors: VMC_EINVAL (no samples); VMC_ESINGULAR if, since the last reset,
  * an inverse rebuild of the sweeps or of a measurement met a Slater block
@@ -242,6 +244,23 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
  * still clears the accumulators and the error state. */
 int vmc_accumulate(vmc_ctx *ctx, double *E, double *F_bare, double *dE_dC,
                    double *dEL_dC_mean, int64_t *n_samples, uint32_t flags, void *stream);
+
+/* Measure n_walkers given configurations (device [n_walkers][N][3]) at the
+ * context's MO coefficients and nuclei and add them to the accumulators as
+ * one measured batch (one sweep of the blocking), each with the weight
+ * weights_dev[k] (device [n_walkers], NULL = all 1): the reweighting of
+ * Appendix A (reweighting equation), <O> = <O W> / <W> with
+ * W = |Psi / Psi_G|^2 for configurations drawn from a guiding distribution
+ * Psi_G^2 (the paper names the Attaccalite-Sorella guiding function without
+ * defining it, so the weights are the caller's; samples of Psi^2 itself have
+ * W = 1).  vmc_accumulate then normalises every sum by the sum of the
+ * weights and forms the blocked error bar from weighted block means;
+ * vmc_jackknife likewise.  Weights must be finite and >= 0 with a positive
+ * sum (else vmc_accumulate returns VMC_EINVAL).  Queued on `stream`.
+ * Errors: VMC_EINVAL (NULL walkers, n_walkers < 1 or > max_walkers),
+ * VMC_EDEVICE. */
+int vmc_accumulate_walkers(vmc_ctx *ctx, const double *walkers_dev, int64_t n_walkers, const double *weights_dev,
+                           void *stream);
 
 /* Jackknife replicas of the estimators (Sec. II: the statistical error of B
  * carried through the Z-vector equations by resampling; App. A blocking):

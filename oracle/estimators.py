@@ -17,6 +17,14 @@ subtracted from E_L, so that the covariances do not cancel catastrophically
 accumulated across batches with Neumaier compensation.  Block sums of E_L - s
 per `block_sweeps` sweeps give the blocked error bar.
 
+Reweighting (Appendix A, the reweighting equation): when the configurations
+x' come from a guiding distribution Psi_G^2 instead of Psi^2, every average
+above becomes <O W>/<W> with W = |Psi/Psi_G|^2.  The paper names the
+Attaccalite-Sorella guiding function but does not define it; the weights are
+therefore an input here (one per walker, W = 1 for samples of Psi^2, which
+reproduces the unweighted estimators exactly).  Every sum below carries the
+walker's weight and K is the sum of the weights.
+
 Jackknife (the resampling the paper uses for the error of B and of what the
 Z-vector equations make of it, Sec. II): every complete block keeps its own
 sums of all estimator terms; replica b is the estimate from all blocks but b,
@@ -46,53 +54,59 @@ class Accumulator:
     def __init__(self, n_atoms, n_ao, n_occ, block_sweeps=1):
         A, M, n = n_atoms, n_ao, n_occ
         self.shift = None
-        self.K = 0
+        self.K = 0.0
         self.sums = {k: _Neumaier(sh) for k, sh in dict(
             E=(), EE=(), H=(A, 3), P=(A, 3), EP=(A, 3), O=(M, n), EO=(M, n), G=(M, n)).items()}
         self.block_sweeps = block_sweeps
         self.block_sums = []
         self.block_counts = []
-        self._cur_block = [0.0, 0]
+        self._cur_block = [0.0, 0.0]
         self._sweeps_in_block = 0
         self.block_F = []
         self._blk = None
         self.block_terms = []      # per complete block: dict of term sums and K
         self._terms = None
 
-    def _block_force(self, e, meas):
+    def _block_force(self, e, wt, meas):
         """Per-block force estimate (for blocked error bars of F)."""
         if self._blk is None:
-            self._blk = dict(K=0, E=0.0, H=0.0, P=0.0, EP=0.0)
+            self._blk = dict(K=0.0, E=0.0, H=0.0, P=0.0, EP=0.0)
         b = self._blk
-        b["K"] += e.shape[0]
-        b["E"] += np.sum(e)
-        b["H"] = b["H"] + np.sum(meas["H"], axis=0)
-        b["P"] = b["P"] + np.sum(meas["P"], axis=0)
-        b["EP"] = b["EP"] + np.einsum("w,wak->ak", e, meas["P"])
+        b["K"] += float(np.sum(wt))
+        b["E"] += np.sum(wt * e)
+        b["H"] = b["H"] + np.einsum("w,wak->ak", wt, meas["H"])
+        b["P"] = b["P"] + np.einsum("w,wak->ak", wt, meas["P"])
+        b["EP"] = b["EP"] + np.einsum("w,wak->ak", wt * e, meas["P"])
 
-    def add(self, meas):
+    def add(self, meas, weights=None):
+        """Add a batch of measured walkers; weights[W] = |Psi/Psi_G|^2 of each
+        (None: all 1, samples of Psi^2).  The shift is the mean E_L of the
+        first batch (unweighted)."""
         E = np.asarray(meas["E_L"], dtype=np.float64)
         if self.shift is None:
             self.shift = float(np.mean(E))
         e = E - self.shift
         W = E.shape[0]
-        self.K += W
+        wt = np.ones(W) if weights is None else np.asarray(weights, dtype=np.float64)
+        Kb = float(np.sum(wt))
+        self.K += Kb
+        we = wt * e
         sm = self.sums
-        sm["E"].add(np.sum(e))
-        sm["EE"].add(np.sum(e * e))
-        sm["H"].add(np.sum(meas["H"], axis=0))
-        sm["P"].add(np.sum(meas["P"], axis=0))
-        sm["EP"].add(np.einsum("w,wak->ak", e, meas["P"]))
-        sm["O"].add(np.sum(meas["O"], axis=0))
-        sm["EO"].add(np.einsum("w,wmi->mi", e, meas["O"]))
-        sm["G"].add(np.sum(meas["G"], axis=0))
-        t = dict(K=W, E=np.sum(e), H=np.sum(meas["H"], axis=0), P=np.sum(meas["P"], axis=0),
-                 EP=np.einsum("w,wak->ak", e, meas["P"]), O=np.sum(meas["O"], axis=0),
-                 EO=np.einsum("w,wmi->mi", e, meas["O"]))
+        sm["E"].add(np.sum(we))
+        sm["EE"].add(np.sum(we * e))
+        sm["H"].add(np.einsum("w,wak->ak", wt, meas["H"]))
+        sm["P"].add(np.einsum("w,wak->ak", wt, meas["P"]))
+        sm["EP"].add(np.einsum("w,wak->ak", we, meas["P"]))
+        sm["O"].add(np.einsum("w,wmi->mi", wt, meas["O"]))
+        sm["EO"].add(np.einsum("w,wmi->mi", we, meas["O"]))
+        sm["G"].add(np.einsum("w,wmi->mi", wt, meas["G"]))
+        t = dict(K=Kb, E=np.sum(we), H=np.einsum("w,wak->ak", wt, meas["H"]),
+                 P=np.einsum("w,wak->ak", wt, meas["P"]), EP=np.einsum("w,wak->ak", we, meas["P"]),
+                 O=np.einsum("w,wmi->mi", wt, meas["O"]), EO=np.einsum("w,wmi->mi", we, meas["O"]))
         self._terms = t if self._terms is None else {k: self._terms[k] + t[k] for k in t}
-        self._cur_block[0] += float(np.sum(e))
-        self._cur_block[1] += W
-        self._block_force(e, meas)
+        self._cur_block[0] += float(np.sum(we))
+        self._cur_block[1] += Kb
+        self._block_force(e, wt, meas)
         self._sweeps_in_block += 1
         if self._sweeps_in_block == self.block_sweeps:
             b = self._blk
@@ -103,7 +117,7 @@ class Accumulator:
             self._terms = None
             self.block_sums.append(self._cur_block[0])
             self.block_counts.append(self._cur_block[1])
-            self._cur_block = [0.0, 0]
+            self._cur_block = [0.0, 0.0]
             self._sweeps_in_block = 0
 
     def result(self):

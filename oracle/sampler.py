@@ -80,6 +80,15 @@ class Chains:
             dn = np.sqrt(np.sum((r_new[:, None, :] - ro) ** 2, axis=-1))
             do = np.sqrt(np.sum((self.r[:, e, None, :] - ro) ** 2, axis=-1))
             dJ += np.sum(wf.ee_pair(s, dn)[0] - wf.ee_pair(s, do)[0], axis=1)
+        if s.jas_table is not None:
+            # one- and three/four-body terms: only the pairs (e, j) change
+            c_new, _, _ = gto.eval_aos(s.jas_table, self.R, r_new[:, None, :])
+            c_old, _, _ = gto.eval_aos(s.jas_table, self.R, self.r[:, e, None, :])
+            dchi = (c_new - c_old)[:, 0, :]                            # [W, MJ]
+            dJ += dchi @ s.xi1
+            if others:
+                c_oth, _, _ = gto.eval_aos(s.jas_table, self.R, self.r[:, others, :])
+                dJ += np.einsum("wm,mn,wjn->w", dchi, s.xi3, c_oth)
         if s.en_on:
             for al in range(s.A):
                 dn = np.linalg.norm(r_new - self.R[al], axis=-1)

@@ -8,6 +8,17 @@ Follows Appendix A of the paper:
     down, both spins use the same C (Sec. II, restricted case).
   * Two-body Pade Jastrow J2 = exp(sum_{i<j} v(r_ij)), v(r) = a r / (1 + F r)
     (eq. twobody_v with a = 1/2); spin independent.
+  * Optional one-body and three/four-body terms on a Jastrow GTO basis
+    psi^Jas_mu (Appendix A, eqs. onebody_J_inhom and threebody_jas):
+      J1 = exp(sum_i sum_mu xi1_mu psi^Jas_mu(r_i)),
+      J3 = exp(sum_{i<j} Xi(r_i, r_j)),
+      Xi(r_i, r_j) = sum_{mu,nu} xi3_mu,nu psi^Jas_mu(r_i) psi^Jas_nu(r_j).
+    Readings: the one-body factor, printed without an exponential, enters as
+    exp(.) like the two- and three-body ones (the total J = J1 J2 J3 is a
+    product of exponentials); xi3 is symmetric (a sum over i < j of a
+    non-symmetric Xi would depend on the electrons' labels); all atom pairs
+    are coupled (the four-body elements are kept, as in the paper's runs);
+    the Jastrow basis functions follow the GTO conventions of gto.py.
   * Optional electron-nucleus cusp factor exp(sum_{e,alpha} -Z r/(1 + b r)):
     the paper omits it because its ECPs remove the singularity; here it is used
     only for the hydrogen-atom check.
@@ -44,6 +55,10 @@ class System:
         self.ee_form = int(getattr(jas, "ee_form", 0))
         self.en_on = int(jas.en_on)
         self.en_b = float(jas.en_b)
+        jb = getattr(jas, "jas_basis", None)
+        self.jas_table = gto.ShellTable(jb) if jb is not None else None
+        self.xi1 = None if jb is None else np.array(jas.xi1, dtype=np.float64)
+        self.xi3 = None if jb is None else np.array(jas.xi3, dtype=np.float64)
         self.A = self.xyz.shape[0]
         self.M = self.table.n_ao
         assert self.C.shape == (self.M, max(self.n_up, self.n_dn))
@@ -153,6 +168,11 @@ def jastrow_terms(system, R, r):
         J = J + 0.5 * np.sum(u * off, axis=(1, 2))
         g = g + np.sum((off * u1 / rij)[..., None] * d, axis=2)
         h = h + np.sum(off * (u2 + 2.0 * u1 / rij), axis=2)
+    if system.jas_table is not None:
+        J1, g1, h1, J3, g3, h3 = body_jastrow_terms(system, R, r)
+        J = J + J1 + J3
+        g = g + g1 + g3
+        h = h + h1 + h3
     if system.en_on:
         for al in range(system.A):
             d = r - R[al]                                # [W, N, 3]
@@ -162,6 +182,33 @@ def jastrow_terms(system, R, r):
             g = g + (u1 / rr)[..., None] * d
             h = h + u2 + 2.0 * u1 / rr
     return J, g, h
+
+
+def body_jastrow_terms(system, R, r):
+    """One-body and three/four-body terms (eqs. onebody_J_inhom, threebody_jas):
+    J1 [W], grad_e J1 [W,N,3], lap_e J1 [W,N] and the same for J3.
+
+    J1 = sum_i sum_mu xi1_mu chi_mu(r_i); J3 = sum_{i<j} Xi(r_i, r_j) with the
+    pair matrix P[i, j] = Xi(r_i, r_j) = chi(r_i)^T xi3 chi(r_j) summed over
+    i < j.  r_e enters J3 through the pairs (e, j), j != e, so
+    grad_e J3 = sum_{j != e} grad chi(r_e)^T xi3 chi(r_j) and the Laplacian
+    likewise with lap chi(r_e).
+    """
+    chi, gchi, lchi = gto.eval_aos(system.jas_table, R, r)    # [W,N,MJ], [W,N,MJ,3], [W,N,MJ]
+    N = r.shape[1]
+    xi1, xi3 = system.xi1, system.xi3
+    J1 = np.einsum("wim,m->w", chi, xi1)
+    g1 = np.einsum("wimk,m->wik", gchi, xi1)
+    h1 = np.einsum("wim,m->wi", lchi, xi1)
+    T = np.einsum("wjn,mn->wjm", chi, xi3)                  # T[w, j] = xi3 chi(r_j)
+    P = np.einsum("wim,wjm->wij", chi, T)                   # P[w, i, j] = Xi(r_i, r_j)
+    upper = np.triu(np.ones((N, N)), k=1)
+    J3 = np.einsum("wij,ij->w", P, upper)
+    off = 1.0 - np.eye(N)
+    Tsum = np.einsum("wjm,ej->wem", T, off)                 # sum_{j != e} xi3 chi(r_j)
+    g3 = np.einsum("wemk,wem->wek", gchi, Tsum)
+    h3 = np.einsum("wem,wem->we", lchi, Tsum)
+    return J1, g1, h1, J3, g3, h3
 
 
 def potential(system, R, r):

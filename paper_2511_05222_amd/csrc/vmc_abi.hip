@@ -110,14 +110,14 @@ struct vmc_ctx {
     int64_t n_est = 0;
     double *acc = nullptr, *comp = nullptr, *partial = nullptr;
     // per-block sums of every estimator element (jackknife), jk_cap blocks
-    double *blk_all = nullptr, *jk_cnt = nullptr;
+    double *blk_all = nullptr;
     int64_t jk_cap = 0;
-    std::vector<double> jk_cnt_host;
     double *shift = nullptr;
     int *shift_set = nullptr;
     int *status = nullptr;
-    double *blocks = nullptr;
-    std::vector<int64_t> block_counts;
+    double *blocks = nullptr;    // [MAX_BLOCKS] per-block sums of w (E_L - s)
+    double *blocks_w = nullptr;  // [MAX_BLOCKS] per-block sums of w
+    std::vector<int64_t> block_counts;   // walkers per block
     int64_t n_samples = 0;
     int64_t sweeps_since_reset = 0;
     double *vjp_acc = nullptr, *vjp_comp = nullptr, *vjp_out = nullptr;
@@ -358,6 +358,61 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
         if (full && o.Of) HIP_OK(c, vmcx::launch_scatter_rows_f32(oc.O, lst, kc, Mn, o.Of, st));
         if (full && o.Gf) HIP_OK(c, vmcx::launch_scatter_rows_f32(oc.G, lst, kc, Mn, o.Gf, st));
     }
+    return VMC_OK;
+}
+
+// Measure W walkers at the context's C and nuclei and add them, with weights
+// wt (null: 1), to the accumulators as one measured batch (one sweep of the
+// blocking).  from_sweep: the walkers are those of the last sweep, whose
+// persistent inverses the measurement may start from.
+static int measure_accumulate(vmc_ctx *c, const double *walkers, int64_t W, const double *wt, bool from_sweep,
+                              hipStream_t st) {
+    int rc;
+    const int64_t Mn = (int64_t)c->M * c->n_occ, A3 = 3 * c->A;
+    const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
+    double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;
+    double *blkw = blk_idx < MAX_BLOCKS ? c->blocks_w + blk_idx : nullptr;
+    double *blk_all = blk_idx < c->jk_cap ? c->blk_all + blk_idx * c->n_est : nullptr;
+    const int64_t step = chunk_len(c, W);
+    for (int64_t c0 = 0; c0 < W; c0 += step) {
+        const int64_t cw = std::min(step, W - c0);
+        // ln|Psi| is not an estimator input: the dense kernel may start
+        // from the sweep's inverses
+        // (in mixed precision O and G are staged in FP32: the estimator
+        // reduction reads them once per launch)
+        const bool f32 = c->opt.precision == VMC_MIXED;
+        WalkerOut o{c->st_EL, nullptr, nullptr, c->st_dEdR, c->st_dPdR, c->st_dJdR, f32 ? nullptr : c->st_O,
+                    f32 ? nullptr : c->st_G};
+        if (f32) {
+            o.Of = (float *)c->st_O;
+            o.Gf = (float *)c->st_G;
+        }
+        KStateRef ks;
+        if (from_sweep) {
+            const int kn = vmcx::sweep_kn(c->n_occ);
+            const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+            ks.K = (const char *)c->Kst + (size_t)c0 * 2 * kn * kn * tsz;
+            ks.sig = c->Ksig + (size_t)c0 * 2 * kn;
+            ks.stale = c->Kstale + 2 * c0;
+        }
+        if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, c->d_C, c->d_R, c->d_R, 0, 1, o, st, ks))) return rc;
+        HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
+        EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
+                  nullptr,  nullptr,    nullptr,    A3,         Mn};
+        if (f32) {
+            a.Of = o.Of;
+            a.Gf = o.Gf;
+        }
+        a.wt = wt ? wt + c0 : nullptr;
+        HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, blkw, blk_all,
+                                      st));
+    }
+    if (blk_idx < MAX_BLOCKS) {
+        if ((int64_t)c->block_counts.size() <= blk_idx) c->block_counts.resize(blk_idx + 1, 0);
+        c->block_counts[blk_idx] += W;
+    }
+    c->n_samples += W;
+    c->sweeps_since_reset += 1;
     return VMC_OK;
 }
 
@@ -680,24 +735,25 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
             (rc = c->dalloc(&c->cp_G, p * Mn)))
             return bail(rc);
     }
-    c->n_est = 2 + 3 * A3 + 3 * Mn;
+    c->n_est = 3 + 3 * A3 + 3 * Mn;   // the last element: the sum of the weights
     const int64_t n_vjp = Mn + A3;
     if ((rc = c->dalloc(&c->acc, c->n_est)) || (rc = c->dalloc(&c->comp, c->n_est)) ||
         (rc = c->dalloc(&c->partial, MAX_SEG * std::max(c->n_est, n_vjp))) || (rc = c->dalloc(&c->shift, 1)) ||
         (rc = c->dalloc(&c->shift_set, 1)) || (rc = c->dalloc(&c->status, 1)) ||
-        (rc = c->dalloc(&c->blocks, MAX_BLOCKS)) || (rc = c->dalloc(&c->vjp_acc, n_vjp)) ||
+        (rc = c->dalloc(&c->blocks, MAX_BLOCKS)) || (rc = c->dalloc(&c->blocks_w, MAX_BLOCKS)) || (rc = c->dalloc(&c->vjp_acc, n_vjp)) ||
         (rc = c->dalloc(&c->vjp_comp, n_vjp)) || (rc = c->dalloc(&c->vjp_out, n_vjp)))
         return bail(rc);
     if (opt->jackknife_blocks > 0) {
         c->jk_cap = std::min<int64_t>(opt->jackknife_blocks, 65535);
-        if ((rc = c->dalloc(&c->blk_all, c->jk_cap * c->n_est)) || (rc = c->dalloc(&c->jk_cnt, c->jk_cap)))
+        if ((rc = c->dalloc(&c->blk_all, c->jk_cap * c->n_est)))
             return bail(rc);
         if (hipMemset(c->blk_all, 0, c->jk_cap * c->n_est * 8) != hipSuccess)
             return bail(c->fail(VMC_EDEVICE, "hipMemset failed"));
     }
     if (hipMemset(c->acc, 0, c->n_est * 8) != hipSuccess || hipMemset(c->comp, 0, c->n_est * 8) != hipSuccess ||
         hipMemset(c->shift, 0, 8) != hipSuccess || hipMemset(c->shift_set, 0, 4) != hipSuccess ||
-        hipMemset(c->status, 0, 4) != hipSuccess || hipMemset(c->blocks, 0, MAX_BLOCKS * 8) != hipSuccess)
+        hipMemset(c->status, 0, 4) != hipSuccess || hipMemset(c->blocks, 0, MAX_BLOCKS * 8) != hipSuccess ||
+        hipMemset(c->blocks_w, 0, MAX_BLOCKS * 8) != hipSuccess)
         return bail(c->fail(VMC_EDEVICE, "hipMemset failed"));
     *out = c;
     return VMC_OK;
@@ -754,47 +810,7 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
             prof_end(c, VMC_K_SWEEP, pi, st);
         }
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
-        const int64_t blk_idx = c->sweeps_since_reset / c->opt.block_sweeps;
-        double *blk = blk_idx < MAX_BLOCKS ? c->blocks + blk_idx : nullptr;
-        double *blk_all = blk_idx < c->jk_cap ? c->blk_all + blk_idx * c->n_est : nullptr;
-        const int64_t step = chunk_len(c, W);
-        for (int64_t c0 = 0; c0 < W; c0 += step) {
-            const int64_t cw = std::min(step, W - c0);
-            // ln|Psi| is not an estimator input: the dense kernel may start
-            // from the sweep's inverses
-            // (in mixed precision O and G are staged in FP32: the estimator
-            // reduction reads them once per launch)
-            const bool f32 = c->opt.precision == VMC_MIXED;
-            WalkerOut o{c->st_EL, nullptr, nullptr, c->st_dEdR, c->st_dPdR, c->st_dJdR, f32 ? nullptr : c->st_O,
-                        f32 ? nullptr : c->st_G};
-            if (f32) {
-                o.Of = (float *)c->st_O;
-                o.Gf = (float *)c->st_G;
-            }
-            const int kn = vmcx::sweep_kn(c->n_occ);
-            const size_t tsz = c->opt.precision == VMC_MIXED ? sizeof(float) : sizeof(double);
-            KStateRef ks;
-            ks.K = (const char *)c->Kst + (size_t)c0 * 2 * kn * kn * tsz;
-            ks.sig = c->Ksig + (size_t)c0 * 2 * kn;
-            ks.stale = c->Kstale + 2 * c0;
-            if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, c->d_C, c->d_R, c->d_R, 0, 1, o, st, ks)))
-                return rc;
-            HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
-            EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
-                      nullptr,  nullptr,    nullptr,    A3,         Mn};
-            if (f32) {
-                a.Of = o.Of;
-                a.Gf = o.Gf;
-            }
-            HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, blk_all,
-                                          st));
-        }
-        if (blk_idx < MAX_BLOCKS) {
-            if ((int64_t)c->block_counts.size() <= blk_idx) c->block_counts.resize(blk_idx + 1, 0);
-            c->block_counts[blk_idx] += W;
-        }
-        c->n_samples += W;
-        c->sweeps_since_reset += 1;
+        if ((rc = measure_accumulate(c, walkers, W, nullptr, true, st))) return rc;
     }
     return VMC_OK;
 }
@@ -811,14 +827,17 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
     double shift = 0.0;
     int status = 0;
     const int64_t nb = std::min<int64_t>((int64_t)c->block_counts.size(), MAX_BLOCKS);
-    std::vector<double> blocks(std::max<int64_t>(nb, 1));
+    std::vector<double> blocks(std::max<int64_t>(nb, 1)), blocks_w(std::max<int64_t>(nb, 1));
     HIP_OK(c, hipMemcpyAsync(acc.data(), c->acc, n * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(c, hipMemcpyAsync(comp.data(), c->comp, n * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(c, hipMemcpyAsync(&shift, c->shift, 8, hipMemcpyDeviceToHost, st));
     HIP_OK(c, hipMemcpyAsync(&status, c->status, 4, hipMemcpyDeviceToHost, st));
     if (nb > 0) HIP_OK(c, hipMemcpyAsync(blocks.data(), c->blocks, nb * 8, hipMemcpyDeviceToHost, st));
+    if (nb > 0) HIP_OK(c, hipMemcpyAsync(blocks_w.data(), c->blocks_w, nb * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(c, hipStreamSynchronize(st));
-    const double K = (double)c->n_samples;
+    // normalisation: the sum of the weights (the sample count when all are 1)
+    const double K = acc[n - 1] + comp[n - 1];
+    if (!(K > 0.0) || !std::isfinite(K)) return c->fail(VMC_EINVAL, "the sum of the weights is %g", K);
     std::vector<double> v(n);
     for (int64_t i = 0; i < n; ++i) v[i] = (acc[i] + comp[i]) / K;
     const double vE = v[0];
@@ -833,7 +852,7 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
             double mean = 0.0;
             std::vector<double> bm(full);
             for (int64_t b = 0; b < full; ++b) {
-                bm[b] = blocks[b] / (double)c->block_counts[b];
+                bm[b] = blocks[b] / blocks_w[b];
                 mean += bm[b];
             }
             mean /= (double)full;
@@ -858,6 +877,7 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
         HIP_OK(c, hipMemsetAsync(c->shift_set, 0, 4, st));
         HIP_OK(c, hipMemsetAsync(c->status, 0, 4, st));
         HIP_OK(c, hipMemsetAsync(c->blocks, 0, MAX_BLOCKS * 8, st));
+        HIP_OK(c, hipMemsetAsync(c->blocks_w, 0, MAX_BLOCKS * 8, st));
         if (c->jk_cap) HIP_OK(c, hipMemsetAsync(c->blk_all, 0, c->jk_cap * n * 8, st));
         HIP_OK(c, hipStreamSynchronize(st));
         c->block_counts.clear();
@@ -867,6 +887,16 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
     if (status & vmcx::STATUS_SINGULAR) return c->fail(VMC_ESINGULAR, "a Slater block was singular to working precision");
     if (status & vmcx::STATUS_NONFINITE) return c->fail(VMC_ENONFINITE, "non-finite local energy or ln|Psi|");
     return VMC_OK;
+}
+
+int vmc_accumulate_walkers(vmc_ctx *c, const double *walkers, int64_t W, const double *weights, void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (!walkers || W < 1 || W > c->opt.max_walkers)
+        return c->fail(VMC_EINVAL, "bad arguments: walkers=%p n_walkers=%lld (max %d)", (void *)walkers,
+                       (long long)W, c->opt.max_walkers);
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    return measure_accumulate(c, walkers, W, weights, false, (hipStream_t)stream);
 }
 
 int vmc_jackknife(vmc_ctx *c, double *E_jk, double *F_jk, double *dEdC_jk, int64_t *n_blocks, void *stream) {
@@ -880,10 +910,8 @@ int vmc_jackknife(vmc_ctx *c, double *E_jk, double *F_jk, double *dEdC_jk, int64
     if (n_blocks) *n_blocks = nb;
     if (!E_jk && !F_jk && !dEdC_jk) return VMC_OK;
     if (nb < 2) return c->fail(VMC_EINVAL, "vmc_jackknife: %lld complete blocks (need 2)", (long long)nb);
-    c->jk_cnt_host.assign(c->block_counts.begin(), c->block_counts.begin() + nb);
-    HIP_OK(c, hipMemcpyAsync(c->jk_cnt, c->jk_cnt_host.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
-    HIP_OK(c, vmcx::launch_jackknife(c->blk_all, c->jk_cnt, (int)nb, c->n_est, 3 * c->A, (int64_t)c->M * c->n_occ,
-                                     c->shift, E_jk, F_jk, dEdC_jk, st));
+    HIP_OK(c, vmcx::launch_jackknife(c->blk_all, (int)nb, c->n_est, 3 * c->A, (int64_t)c->M * c->n_occ, c->shift,
+                                     E_jk, F_jk, dEdC_jk, st));
     HIP_OK(c, hipStreamSynchronize(st));
     return VMC_OK;
 }
@@ -957,6 +985,7 @@ int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
         EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, nullptr,
                   gEL + c0, gPsi + c0,  gJac + c0,  A3,         Mn};
         HIP_OK(c, vmcx::launch_reduce(a, 1, nv, cw, c->partial, MAX_SEG, c->vjp_acc, c->vjp_comp, nullptr, nullptr,
+                                      nullptr,
                                       st));
     }
     HIP_OK(c, vmcx::launch_combine(c->vjp_acc, c->vjp_comp, nv, c->vjp_out, st));

@@ -37,16 +37,20 @@ struct EstArgs {
     int64_t A3, Mn;
     // when set, O and G are read from these FP32 arrays
     const float *Of = nullptr, *Gf = nullptr;
+    // per-walker weights |Psi/Psi_G|^2 of the estimator sums (null: all 1)
+    const double *wt = nullptr;
 };
 
-// blk: the running block's energy sum (element 0 only); blk_all: its sums of
-// every element (both nullable)
+// blk / blkw: the running block's energy and weight sums (elements 0 and
+// n_out - 1); blk_all: its sums of every element (all nullable)
 hipError_t launch_reduce(const EstArgs &a, int mode, int64_t n_out, int64_t W, double *partial,
-                         int64_t max_seg, double *acc, double *comp, double *blk, double *blk_all, hipStream_t st);
+                         int64_t max_seg, double *acc, double *comp, double *blk, double *blkw, double *blk_all,
+                         hipStream_t st);
 // leave-one-block-out replicas E_jk[nb], F_jk[nb][A3], dC_jk[nb][Mn] (nullable)
-// from per-block sums bs[nb][n_est] and per-block sample counts cnt[nb]
-hipError_t launch_jackknife(const double *bs, const double *cnt, int nb, int64_t n_est, int64_t A3, int64_t Mn,
-                            const double *shift, double *E_jk, double *F_jk, double *dC_jk, hipStream_t st);
+// from per-block sums bs[nb][n_est] (the last element of a block's sums is
+// its weight sum)
+hipError_t launch_jackknife(const double *bs, int nb, int64_t n_est, int64_t A3, int64_t Mn, const double *shift,
+                            double *E_jk, double *F_jk, double *dC_jk, hipStream_t st);
 hipError_t launch_jackknife_stats(const double *x, int64_t nb, int64_t len, double *mean, double *sigma,
                                   hipStream_t st);
 hipError_t launch_set_shift(const double *EL, int64_t W, double *shift, int *shift_set, hipStream_t st);

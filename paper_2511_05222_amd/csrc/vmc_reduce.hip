@@ -24,16 +24,17 @@ __device__ inline double block_sum(double v, double *red) {
 
 // ---------------------------------------------------------------------------
 // Reductions over walkers (deterministic two-level sums).
-// Element space of the estimator sums (per measured walker k, e_k = E_L - s):
+// Element space of the estimator sums (per measured walker k, e_k = E_L - s,
+// every term multiplied by the walker's weight w_k, 1 unless given):
 //   [0] e, [1] e^2, [2..) H (3A), P = dlnpsi + dlnjac/2 (3A), e P (3A),
-//   O (M n), e O (M n), G (M n).
+//   O (M n), e O (M n), G (M n), and last the weight w itself.
 // Element space of the vector-Jacobian product:
 //   [0..Mn) dC = gE G + gPsi O, [Mn..Mn+3A) dR = gE dEdR + gPsi dPdR + gJ dJdR.
 // ---------------------------------------------------------------------------
 __device__ inline double est_O(const EstArgs &a, int64_t i) { return a.Of ? (double)a.Of[i] : a.O[i]; }
 __device__ inline double est_G(const EstArgs &a, int64_t i) { return a.Gf ? (double)a.Gf[i] : a.G[i]; }
 
-__device__ inline double est_term(const EstArgs &a, int64_t o, int64_t k) {
+__device__ inline double est_term_1(const EstArgs &a, int64_t o, int64_t k) {
     const double e = a.EL[k] - a.shift[0];
     const int64_t A3 = a.A3, Mn = a.Mn;
     if (o == 0) return e;
@@ -49,7 +50,13 @@ __device__ inline double est_term(const EstArgs &a, int64_t o, int64_t k) {
     o -= Mn;
     if (o < Mn) return e * est_O(a, k * Mn + o);
     o -= Mn;
-    return est_G(a, k * Mn + o);
+    if (o < Mn) return est_G(a, k * Mn + o);
+    return 1.0;   // the weight element
+}
+
+__device__ inline double est_term(const EstArgs &a, int64_t o, int64_t k) {
+    const double t = est_term_1(a, o, k);
+    return a.wt ? a.wt[k] * t : t;
 }
 
 __device__ inline double vjp_term(const EstArgs &a, int64_t o, int64_t k) {
@@ -78,17 +85,19 @@ __global__ void k_partial_sums(EstArgs a, int mode, int64_t n_elem, int64_t n_ou
     const int64_t seg = blockIdx.y;
     if (o >= n_elem) return;
     const int64_t k0 = seg * seg_len, k1 = min(W, k0 + seg_len);
+    // estimator element of this thread: the leading ones, then the weight
+    const int64_t oe = (mode == 0 && o == n_elem - 1) ? n_out - 1 : o;
     double s = 0.0, c = 0.0;
     int64_t k = k0;
     for (; k + PS_U <= k1; k += PS_U) {
         double x[PS_U];
 #pragma unroll
-        for (int u = 0; u < PS_U; ++u) x[u] = mode == 0 ? est_term(a, o, k + u) : vjp_term(a, o, k + u);
+        for (int u = 0; u < PS_U; ++u) x[u] = mode == 0 ? est_term(a, oe, k + u) : vjp_term(a, o, k + u);
 #pragma unroll
         for (int u = 0; u < PS_U; ++u) neumaier(s, c, x[u]);
     }
-    for (; k < k1; ++k) neumaier(s, c, mode == 0 ? est_term(a, o, k) : vjp_term(a, o, k));
-    partial[seg * n_out + o] = s + c;
+    for (; k < k1; ++k) neumaier(s, c, mode == 0 ? est_term(a, oe, k) : vjp_term(a, o, k));
+    partial[seg * n_out + oe] = s + c;
 }
 
 // Mode 0, the O, e O and G elements (most of the element space): thread
@@ -112,19 +121,20 @@ __global__ __launch_bounds__(256) void k_partial_sums_og(const S *__restrict__ O
     const double sh = ldc(a.shift);
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
     int64_t k = k0;
+    const double *wt = a.wt;
     for (; k + PS_OG <= k1; k += PS_OG) {
         S x[PS_OG];
 #pragma unroll
         for (int u = 0; u < PS_OG; ++u) x[u] = src[(k + u) * Mn + i];
 #pragma unroll
         for (int u = 0; u < PS_OG; ++u) {
-            const double xv = (double)x[u];
+            const double xv = wt ? ldc(wt + k + u) * (double)x[u] : (double)x[u];
             neumaier(s1, c1, xv);
             if (isO) neumaier(s2, c2, (ldc(a.EL + k + u) - sh) * xv);
         }
     }
     for (; k < k1; ++k) {
-        const double xv = (double)src[k * Mn + i];
+        const double xv = wt ? ldc(wt + k) * (double)src[k * Mn + i] : (double)src[k * Mn + i];
         neumaier(s1, c1, xv);
         if (isO) neumaier(s2, c2, (ldc(a.EL + k) - sh) * xv);
     }
@@ -133,9 +143,10 @@ __global__ __launch_bounds__(256) void k_partial_sums_og(const S *__restrict__ O
 }
 
 // acc[o] (+ comp[o]) += sum_seg partial[seg][o]  (Neumaier, fixed order);
-// if blk != nullptr, element 0's chunk sum is also added to *blk.
+// if blk / blkw != nullptr, element 0's / the last element's chunk sum is
+// also added to *blk / *blkw.
 __global__ void k_accumulate(const double *partial, int64_t n_out, int64_t n_seg, double *acc,
-                             double *comp, double *blk, double *blk_all) {
+                             double *comp, double *blk, double *blkw, double *blk_all) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n_out) return;
     double s = 0.0, c = 0.0;
@@ -151,24 +162,24 @@ __global__ void k_accumulate(const double *partial, int64_t n_out, int64_t n_seg
     comp[o] += (fabs(a0) >= fabs(x)) ? ((a0 - t) + x) : ((x - t) + a0);
     acc[o] = t;
     if (o == 0 && blk != nullptr) blk[0] += x;
+    if (o == n_out - 1 && blkw != nullptr) blkw[0] += x;
     if (blk_all != nullptr) blk_all[o] += x;
 }
 
 // Leave-one-block-out (jackknife) replicas of the estimators over nb complete
-// blocks with per-block sums bs[b][*] and counts cnt[b]:
+// blocks with per-block sums bs[b][*] (weight sums cnt[b] = bs[b][n_est - 1]):
 //   S^(-b) = sum_{b' != b} S_b' (formed as the fixed-order total minus S_b),
 //   dE/dC^(-b) = 2 (S_EO/K - (S_E/K)(S_O/K)),  F^(-b) = -S_H/K - 2 (S_EP/K - (S_E/K)(S_P/K)),
 //   E^(-b) = s + S_E/K,  K = K^(-b).
-__global__ void k_jackknife(const double *__restrict__ bs, const double *__restrict__ cnt, int nb, int64_t n_est,
-                            int64_t A3, int64_t Mn, const double *__restrict__ shift, double *E_jk, double *F_jk,
-                            double *dC_jk) {
+__global__ void k_jackknife(const double *__restrict__ bs, int nb, int64_t n_est, int64_t A3, int64_t Mn,
+                            const double *__restrict__ shift, double *E_jk, double *F_jk, double *dC_jk) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // output element of one replica
     const int b = blockIdx.y;
     const int64_t n_out = 1 + A3 + Mn;
     if (o >= n_out) return;
     double Kt = 0.0;
-    for (int q = 0; q < nb; ++q) Kt += cnt[q];
-    const double K = Kt - cnt[b];
+    for (int q = 0; q < nb; ++q) Kt += bs[(size_t)q * n_est + n_est - 1];
+    const double K = Kt - bs[(size_t)b * n_est + n_est - 1];
     auto loo = [&](int64_t i) {
         double t = 0.0;
         for (int q = 0; q < nb; ++q) t += bs[(size_t)q * n_est + i];
@@ -601,12 +612,14 @@ __global__ void k_zv_backmap(const double *__restrict__ Cv, const double *__rest
 // host-side launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_reduce(const EstArgs &a, int mode, int64_t n_out, int64_t W, double *partial,
-                         int64_t max_seg, double *acc, double *comp, double *blk, double *blk_all, hipStream_t st) {
+                         int64_t max_seg, double *acc, double *comp, double *blk, double *blkw, double *blk_all,
+                         hipStream_t st) {
     int64_t n_seg = std::min<int64_t>(max_seg, std::max<int64_t>(1, (W + 63) / 64));
     const int64_t seg_len = (W + n_seg - 1) / n_seg;
     n_seg = (W + seg_len - 1) / seg_len;
-    // mode 0: the leading elements here, O / e O / G in k_partial_sums_og
-    const int64_t n_elem = mode == 0 ? 2 + 3 * a.A3 : n_out;
+    // mode 0: the leading elements and the weight (last) here, O / e O / G
+    // in k_partial_sums_og
+    const int64_t n_elem = mode == 0 ? 3 + 3 * a.A3 : n_out;
     dim3 g1((unsigned)((n_elem + 255) / 256), (unsigned)n_seg);
     hipLaunchKernelGGL(k_partial_sums, g1, dim3(256), 0, st, a, mode, n_elem, n_out, W, seg_len, partial);
     if (mode == 0) {
@@ -619,15 +632,15 @@ hipError_t launch_reduce(const EstArgs &a, int mode, int64_t n_out, int64_t W, d
                                partial);
     }
     hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, partial, n_out,
-                       n_seg, acc, comp, blk, blk_all);
+                       n_seg, acc, comp, blk, blkw, blk_all);
     return hipGetLastError();
 }
 
-hipError_t launch_jackknife(const double *bs, const double *cnt, int nb, int64_t n_est, int64_t A3, int64_t Mn,
-                            const double *shift, double *E_jk, double *F_jk, double *dC_jk, hipStream_t st) {
+hipError_t launch_jackknife(const double *bs, int nb, int64_t n_est, int64_t A3, int64_t Mn, const double *shift,
+                            double *E_jk, double *F_jk, double *dC_jk, hipStream_t st) {
     const int64_t n_out = 1 + A3 + Mn;
-    hipLaunchKernelGGL(k_jackknife, dim3((unsigned)((n_out + 255) / 256), (unsigned)nb), dim3(256), 0, st, bs, cnt,
-                       nb, n_est, A3, Mn, shift, E_jk, F_jk, dC_jk);
+    hipLaunchKernelGGL(k_jackknife, dim3((unsigned)((n_out + 255) / 256), (unsigned)nb), dim3(256), 0, st, bs, nb,
+                       n_est, A3, Mn, shift, E_jk, F_jk, dC_jk);
     return hipGetLastError();
 }
 

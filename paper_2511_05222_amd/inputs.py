@@ -19,7 +19,12 @@ Workload recipe (synthetic stand-ins for the paper's rMD17 molecules, Sec. IV):
     contraction coefficients uniform in [0.2, 1.0];
   * MO coefficients: X ~ N(0,1)^{M x M}, C = X L^-T with L L^T = X^T S X, the
     first n columns occupied;
-  * Jastrow: two-body Pade u(r) = a r / (1 + F r), a = 1/2, F = 1.
+  * Jastrow: two-body Pade u(r) = a r / (1 + F r), a = 1/2, F = 1; for the
+    one-/three-body terms (with_body_jastrow), a Jastrow basis of
+    uncontracted cartesian primitives, [3s1p] on H and [4s2p1d] on C and O
+    (the paper's basis sizes), exponents log-uniform in [0.2, 4] sorted
+    descending, and seeded parameters xi1 ~ N(0, s1^2), xi3 = (G + G^T) / 2
+    with G ~ N(0, s3^2).
 """
 from __future__ import annotations
 
@@ -82,6 +87,11 @@ class Jastrow:
     en_on: int = 0
     en_b: float = 0.0
     ee_form: int = 0   # 0: a r / (1 + F r); 1: a (1 - exp(-F r)) / F
+    # one- and three/four-body terms on a Jastrow GTO basis (None: absent):
+    # jas_basis has M_J functions, xi1[M_J], xi3[M_J][M_J] symmetric
+    jas_basis: "Basis | None" = None
+    xi1: "np.ndarray | None" = None
+    xi3: "np.ndarray | None" = None
 
 
 @dataclass
@@ -279,6 +289,48 @@ class RunSpec:
     seed: int
     step_sigma: float = 0.5
     precision: str = "fp64"
+
+
+JAS_SHELLS_OF = {
+    "H": [0, 0, 0, 1],
+    "C": [0, 0, 0, 0, 1, 1, 2],
+    "O": [0, 0, 0, 0, 1, 1, 2],
+}
+
+
+def make_jastrow_basis(symbols, seed: int) -> Basis:
+    """Uncontracted cartesian primitives on every atom ([3s1p] H, [4s2p1d]
+    C, O), exponents log-uniform in [0.2, 4] sorted descending per shell
+    type, coefficient 1 (unit-normalised primitives)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sa, sl, ex = [], [], []
+    for a, sym in enumerate(symbols):
+        ls = JAS_SHELLS_OF[sym]
+        for l in sorted(set(ls)):
+            k = ls.count(l)
+            e = np.sort(np.exp(rng.uniform(np.log(0.2), np.log(4.0), size=k)))[::-1]
+            for x in e:
+                sa.append(a)
+                sl.append(l)
+                ex.append(float(x))
+    n = len(sa)
+    return Basis(np.array(sa, np.int32), np.array(sl, np.int32), np.ones(n, np.int32), np.array(ex),
+                 np.ones(n))
+
+
+def with_body_jastrow(mol: Molecule, seed: int, s1: float = 0.05, s3: float = 0.004) -> Molecule:
+    """A copy of mol whose Jastrow has the one- and three/four-body terms:
+    a seeded Jastrow basis and seeded parameters (xi3 symmetric, all atom
+    pairs coupled)."""
+    import dataclasses
+    jb = make_jastrow_basis(mol.symbols, seed)
+    MJ = jb.n_ao
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    xi1 = rng.normal(0.0, s1, size=MJ)
+    G = rng.normal(0.0, s3, size=(MJ, MJ))
+    xi3 = 0.5 * (G + G.T)
+    jas = dataclasses.replace(mol.jastrow, jas_basis=jb, xi1=xi1, xi3=xi3)
+    return dataclasses.replace(mol, jastrow=jas, name=mol.name + " +J1J3")
 
 
 @lru_cache(maxsize=None)

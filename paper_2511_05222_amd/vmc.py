@@ -28,7 +28,7 @@ VMC_ACCUM_RESET = 1
 EXPORTED = ["vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
             "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap", "zvector_jackknife",
             "vmc_staging_walkers", "vmc_free", "vmc_last_error", "vmc_init_error", "vmc_strerror", "vmc_profile",
-            "vmc_profile_read", "zvector_solve_noalloc"]
+            "vmc_profile_read", "zvector_solve_noalloc", "vmc_accumulate_walkers"]
 
 
 class VmcError(RuntimeError):
@@ -83,6 +83,7 @@ def lib():
                            ct.POINTER(_Options), i32, ct.POINTER(vp)]
     L.vmc_sweep.argtypes = [vp, vp, i64, i32, u64, u64, u32, vp, vp]
     L.vmc_accumulate.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp]
+    L.vmc_accumulate_walkers.argtypes = [vp, vp, i64, vp, vp]
     L.vmc_measure.argtypes = [vp, vp, i64, vp, vp, vp, ct.POINTER(_WalkerOut), vp]
     L.vmc_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_energy_cotangents.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp]
@@ -107,7 +108,8 @@ def lib():
     L.vmc_strerror.restype = ct.c_char_p
     for name in ("vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
                  "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap",
-                 "zvector_jackknife", "vmc_profile", "vmc_profile_read", "zvector_solve_noalloc"):
+                 "zvector_jackknife", "vmc_profile", "vmc_profile_read", "zvector_solve_noalloc",
+                 "vmc_accumulate_walkers"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -195,6 +197,15 @@ class Context:
             _check_dev(accept, (nsteps, self.N, W), torch.uint8)
         self._rc(lib().vmc_sweep(self._h, _ptr(walkers), W, nsteps, ct.c_uint64(seed), ct.c_uint64(sweep_offset),
                                  VMC_SWEEP_MEASURE if measure else 0, _ptr(accept), _stream()))
+
+    def accumulate_walkers(self, walkers, weights=None):
+        """Measure the given configurations and add them to the accumulators
+        with per-walker weights |Psi/Psi_G|^2 (device FP64 [W]; None = 1)."""
+        W = walkers.shape[0]
+        _check_dev(walkers, (W, self.N, 3))
+        if weights is not None:
+            _check_dev(weights, (W,))
+        self._rc(lib().vmc_accumulate_walkers(self._h, _ptr(walkers), W, _ptr(weights), _stream()))
 
     def accumulate(self, reset=True):
         E = np.zeros(2)

@@ -147,6 +147,62 @@ def test_estimators_are_fixed_sample_derivatives(mol9):
         assert abs(fd - an) < 1e-6 * max(1.0, abs(fd)), (mu, i, fd, an)
 
 
+# Reweighting (App. A, the reweighting equation): averages <O W>/<W> with a
+# weight W = |Psi/Psi_G|^2 per walker.  W = 1 reproduces the unweighted
+# estimators exactly; a common factor of the weights cancels; integer weights
+# equal replicated walkers; and with non-uniform W0 the weighted estimators
+# are the exact derivatives of the fixed-sample energy
+# sum W0 w E_L / sum W0 w, w = exp(2 (ln|Psi(C,R)| - ln|Psi0|)) Jac(R).
+def _ehat_w(system, R, R0, r, lnpsi0, W0, C=None):
+    E, lp, lj = dv.warped_values(system, R, R0, r, C)
+    w = W0 * np.exp(2.0 * (lp - lnpsi0) + lj)
+    return float(np.sum(w * E) / np.sum(w))
+
+
+def test_reweighted_estimators(mol9):
+    s = wf.System(mol9)
+    W = 12
+    ch, _ = sampler.run(s, inputs.initial_walkers(mol9, W, 21), 3, 21)
+    r, R0 = ch.r, s.xyz
+    m = dv.measure(s, R0, r)
+
+    def est(meas, weights=None):
+        a = estimators.Accumulator(s.A, s.M, s.C.shape[1])
+        a.add(meas, weights)
+        return a.result()
+
+    keys = ("E", "F_bare", "dE_dC", "dEL_dC_mean")
+    ru, r1 = est(m), est(m, np.ones(W))
+    for k in keys:
+        assert np.array_equal(ru[k], r1[k]), k
+    rng = np.random.default_rng(22)
+    W0 = rng.uniform(0.2, 2.0, W)
+    rw, rs = est(m, W0), est(m, 3.7 * W0)
+    for k in keys:
+        assert np.allclose(rs[k], rw[k], rtol=1e-12, atol=1e-12 * np.abs(rw[k]).max()), k
+    # the weighted estimate differs from the unweighted one (weights matter)
+    assert abs(rw["E"] - ru["E"]) > 1e-6
+    reps = rng.integers(1, 4, W)
+    mrep = {k: np.repeat(v, reps, axis=0) for k, v in m.items() if isinstance(v, np.ndarray) and v.shape[:1] == (W,)}
+    rr, ri = est(mrep), est(m, reps.astype(float))
+    for k in keys:
+        assert np.allclose(ri[k], rr[k], rtol=1e-11, atol=1e-11 * np.abs(rr[k]).max()), k
+    lnpsi0 = m["lnpsi"]
+    h = 1e-4
+    for al, k in [(1, 0), (4, 2), (7, 1)]:
+        Rp = R0.copy(); Rp[al, k] += h
+        Rm = R0.copy(); Rm[al, k] -= h
+        fd = (_ehat_w(s, Rp, R0, r, lnpsi0, W0) - _ehat_w(s, Rm, R0, r, lnpsi0, W0)) / (2 * h)
+        assert abs(fd + rw["F_bare"][al, k]) < 1e-6 * max(1.0, abs(fd)), (al, k, fd, rw["F_bare"][al, k])
+    for _ in range(3):
+        mu, i = int(rng.integers(s.M)), int(rng.integers(s.C.shape[1]))
+        Cp = s.C.copy(); Cp[mu, i] += h
+        Cm = s.C.copy(); Cm[mu, i] -= h
+        fd = (_ehat_w(s, R0, R0, r, lnpsi0, W0, Cp) - _ehat_w(s, R0, R0, r, lnpsi0, W0, Cm)) / (2 * h)
+        an = rw["dE_dC"][mu, i] + rw["dEL_dC_mean"][mu, i]
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(fd)), (mu, i, fd, an)
+
+
 # P8: per-walker derivatives: complex step vs central differences; matrix
 # calculus dE_L/dC vs complex step along random directions.
 def test_per_walker_derivatives(mol9):
@@ -234,6 +290,62 @@ def test_exponential_jastrow(mol9):
     assert abs(wf.expo(np.array([60.0]), a, F)[0][0] - a / F) < 1e-15
     mol = dataclasses.replace(mol9, jastrow=inputs.Jastrow(0.5, 1.3, 0, 0.0, ee_form=1))
     _kinetic_identity(mol)
+
+
+# One-body and three/four-body Jastrow (eqs. onebody_J_inhom, threebody_jas).
+# Closed form: one H atom with a single normalised s primitive
+# chi(r) = (2 alpha/pi)^(3/4) exp(-alpha r^2) and two electrons gives
+# J1 = xi1 (chi(r1) + chi(r2)) and J3 = xi3 chi(r1) chi(r2).  The terms are
+# symmetric under any electron exchange; xi = 0 leaves the two-body result
+# unchanged; the sampler's move difference is the difference of the full
+# factor; and the wavefunction obeys the kinetic identity (complex-step
+# derivatives of ln|Psi| against the analytic gradient and Laplacian).
+def test_body_jastrow_closed_form():
+    import dataclasses
+    al, x1, x3 = 0.7, 0.3, -0.45
+    jb = inputs.Basis(np.array([0], np.int32), np.array([0], np.int32), np.array([1], np.int32),
+                      np.array([al]), np.array([1.0]))
+    b = inputs.Basis(np.array([0], np.int32), np.array([0], np.int32), np.array([1], np.int32),
+                     np.array([0.5]), np.array([1.0]))
+    jas = inputs.Jastrow(0.5, 1.0, 0, 0.0, jas_basis=jb, xi1=np.array([x1]), xi3=np.array([[x3]]))
+    mol = inputs.Molecule("H-", ["H"], np.zeros((1, 3)), np.array([1.0]), b, np.ones((1, 1)), 1, 1, jas)
+    s = wf.System(mol)
+    r = np.array([[[0.3, -0.2, 0.5], [-0.8, 0.4, 0.1]]])
+    chi = (2 * al / np.pi) ** 0.75 * np.exp(-al * np.sum(r[0] ** 2, axis=1))
+    J1, g1, h1, J3, g3, h3 = wf.body_jastrow_terms(s, s.xyz, r)
+    assert abs(J1[0] - x1 * (chi[0] + chi[1])) < 1e-15
+    assert abs(J3[0] - x3 * chi[0] * chi[1]) < 1e-15
+    # grad_1 J3 = xi3 chi(r2) grad chi(r1), grad chi = -2 alpha r chi
+    assert np.allclose(g3[0, 0], x3 * chi[1] * (-2 * al * r[0, 0] * chi[0]), atol=1e-15)
+    # lap chi = (4 alpha^2 r^2 - 6 alpha) chi
+    lap0 = (4 * al * al * np.sum(r[0, 0] ** 2) - 6 * al) * chi[0]
+    assert abs(h1[0, 0] - x1 * lap0) < 1e-14 and abs(h3[0, 0] - x3 * chi[1] * lap0) < 1e-14
+
+
+def test_body_jastrow_symmetry_and_limits(mol9):
+    import dataclasses
+    m = inputs.with_body_jastrow(mol9, 7)
+    s = wf.System(m)
+    r = inputs.initial_walkers(m, 4, 17)
+    J, g, h = wf.jastrow_terms(s, s.xyz, r)
+    for i, j in ((0, 1), (2, 20), (5, 25)):          # same spin and opposite spins
+        rs = r.copy()
+        rs[:, [i, j]] = rs[:, [j, i]]
+        Js, gs, hs = wf.jastrow_terms(s, s.xyz, rs)
+        assert np.allclose(Js, J, rtol=1e-13, atol=1e-13)
+        assert np.allclose(gs[:, [j, i]], g[:, [i, j]], atol=1e-13)
+    zero = dataclasses.replace(m.jastrow, xi1=np.zeros_like(m.jastrow.xi1), xi3=np.zeros_like(m.jastrow.xi3))
+    ev0 = wf.evaluate(wf.System(dataclasses.replace(m, jastrow=zero)), s.xyz, r)
+    ev2 = wf.evaluate(wf.System(mol9), s.xyz, r)
+    assert np.array_equal(ev0["E_L"], ev2["E_L"]) and np.array_equal(ev0["lnpsi"], ev2["lnpsi"])
+    # the sampler's Jastrow difference of one move
+    ch = sampler.Chains(s, r)
+    for e in (0, 13, 25):
+        rn = r.copy()
+        rn[:, e] += np.array([0.2, -0.35, 0.1])
+        Jn, _, _ = wf.jastrow_terms(s, s.xyz, rn)
+        assert np.allclose(ch.jastrow_delta(e, rn[:, e]), Jn - J, rtol=1e-12, atol=1e-12)
+    _kinetic_identity(m)
 
 
 # P11: every cartesian AO has unit norm (spherical product quadrature of the
