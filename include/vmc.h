@@ -110,18 +110,34 @@ typedef struct {
     const double *C;
 } vmc_mo;
 
-/* Two-body Jastrow exp(sum_{i<j} u(r_ij)), spin independent (Appendix A):
+/* Jastrow factor, spin independent (Appendix A, "Wavefunction Ansatz"),
+ * J = exp(U), U = sum_{i<j} u(r_ij) + U1 + U3:
+ * two-body term
  *   ee_form = VMC_JASTROW_PADE: u(r) = ee_a r / (1 + ee_F r)      (eq. twobody_v)
  *   ee_form = VMC_JASTROW_EXP : u(r) = ee_a (1 - exp(-ee_F r)) / ee_F
  *                                                         (eq. twobody_v_exp)
  * (the paper's forms have ee_a = 1/2, the electron-electron cusp; the
- * exponential form needs ee_F > 0). */
+ * exponential form needs ee_F > 0);
+ * optional one-body and three/four-body terms on a Jastrow GTO basis chi_mu
+ * (jas_basis, same conventions and limits as the determinant's basis, at
+ * most VMC_MAX_JAS cartesian functions, each atom of jas_basis->shell_atom
+ * an index into the nuclei):
+ *   U1 = sum_i sum_mu xi1[mu] chi_mu(r_i)                (eq. onebody_J_inhom)
+ *   U3 = sum_{i<j} sum_{mu,nu} xi3[mu][nu] chi_mu(r_i) chi_nu(r_j)
+ *                                                        (eq. threebody_jas)
+ * xi1[M_J], xi3[M_J][M_J] row-major and exactly symmetric (host arrays,
+ * copied; NULL = zero); all atom pairs may be coupled (four-body elements).
+ * jas_basis = NULL: two-body term only. */
 #define VMC_JASTROW_PADE 0
 #define VMC_JASTROW_EXP  1
+#define VMC_MAX_JAS    256       /* max Jastrow basis functions                  */
 typedef struct {
     double ee_a;
     double ee_F;
     int32_t ee_form;
+    const vmc_basis *jas_basis;
+    const double *xi1;
+    const double *xi3;
 } vmc_jastrow;
 
 /* Run options.

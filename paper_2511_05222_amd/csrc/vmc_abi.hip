@@ -63,13 +63,20 @@ struct vmc_ctx {
     std::string err;
 
     std::vector<void *> allocs;
-    int *d_ao_shell = nullptr, *d_ao_pow = nullptr, *d_shell_atom = nullptr, *d_shell_p0 = nullptr,
-        *d_shell_np = nullptr;
-    double *d_ao_eta = nullptr, *d_prim_exp = nullptr, *d_prim_cp = nullptr, *d_C = nullptr, *d_R = nullptr,
-           *d_Z = nullptr;
-    int *d_shell_l = nullptr, *d_shell_mu0 = nullptr, *d_atom_ao_ptr = nullptr, *d_atom_ao = nullptr;
-    int *d_tile16 = nullptr; // [4][n_tiles]: first shell, end shell, first AO, end AO (<= 16 AOs)
-    AoTiles tiles16{};
+    double *d_C = nullptr, *d_R = nullptr, *d_Z = nullptr;
+    vmcx::BasisDev bdev{};   // the determinant's basis tables
+    AoTiles tiles16{};       // its AO tiles: whole shells, <= 16 AOs
+    // one- and three/four-body Jastrow (MJ = 0: absent): the Jastrow basis,
+    // [xi3 | xi1] in column blocks of 64 ([nq][MJ][64], FP64 and FP32), xi1
+    int MJ = 0, nq = 0;
+    vmcx::BasisDev jdev{};
+    AoTiles jtiles16{};
+    double *d_xiblk = nullptr, *d_xi1 = nullptr;
+    float *d_xiblk_f = nullptr;
+    // staging of the Jastrow terms: sweeps ([W][N] rows) and measurements
+    // ([chunk][N] rows); element sizes of the arithmetic type
+    void *js_Xp = nullptr, *js_X0 = nullptr, *js_Pp = nullptr, *js_T0 = nullptr;
+    double *jm_X = nullptr, *jm_O = nullptr, *jm_g = nullptr, *jm_u = nullptr, *jm_tao = nullptr;
     SysDev sys{};
     SweepLayout swl{};   // k_sweep_r in the arithmetic type of the precision
     DenseLayout dl{};
@@ -272,6 +279,14 @@ static int64_t chunk_len(const vmc_ctx *c, int64_t W) {
 // The measurement kernels on cw walkers at (possibly warped) positions pos
 // with sampling positions pos0.  plist: promotion list for the dense kernel.
 // Chunk offsets into the sweep's persistent inverses (null: none).
+// [xi3 | xi1] column blocks in the arithmetic type
+template <typename T>
+static const T *xi_blocks(const vmc_ctx *c);
+template <>
+const float *xi_blocks<float>(const vmc_ctx *c) { return c->d_xiblk_f; }
+template <>
+const double *xi_blocks<double>(const vmc_ctx *c) { return c->d_xiblk; }
+
 struct KStateRef {
     const void *K = nullptr;
     const uint8_t *sig = nullptr;
@@ -290,6 +305,18 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     int pi = prof_begin(c, VMC_K_MO_ROWS, prof, cw, st);
     HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, (T *)c->d_cpad, st));
     prof_end(c, VMC_K_MO_ROWS, pi, st);
+    const int64_t jrows = cw * c->N;
+    T *jX = (T *)c->jm_X, *jO = (T *)c->jm_O;
+    if (c->MJ > 0) {
+        // one-/three-body Jastrow: chi, its [xi3 | xi1] products, gradient,
+        // Laplacian and value per walker (the dense kernel adds them)
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, R, pos, jrows, jX, st));
+        HIP_OK(c, vmcx::launch_jas_products<T>(S, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), R, pos, jrows, 5, jO,
+                                               (T *)c->d_cpad, st));
+        HIP_OK(c, vmcx::launch_jas_assemble<T>(c->N, c->MJ, c->nq, jrows, 0, (int)cw, jX, jO, c->jm_g, c->jm_u, st));
+        mb.jg = c->jm_g;
+        mb.ju = c->jm_u;
+    }
     pi = prof_begin(c, VMC_K_DENSE, prof, cw, st);
     HIP_OK(c, vmcx::launch_dense<T>(S, R, mb, o, c->status, c->dl, (int)cw, st));
     prof_end(c, VMC_K_DENSE, pi, st);
@@ -298,6 +325,12 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     HIP_OK(c, vmcx::launch_adjoint<T>(S, C, R, mb, o, al, (int)cw, st));
     prof_end(c, VMC_K_ADJOINT, pi, st);
     MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
+    if (c->MJ > 0) {
+        HIP_OK(c, vmcx::launch_jas_adjoint<T>(c->jdev, R, c->N, c->nq, jrows, 0, (int)cw, pos, jX, jO, c->mb_gb,
+                                              c->d_xi1, c->mb_dpart, c->jm_tao, st));
+        md.jtao = c->jm_tao;
+        md.jb = c->jdev;
+    }
     HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, o, warp, (int)cw, st));
     return VMC_OK;
 }
@@ -358,6 +391,48 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
         if (full && o.Of) HIP_OK(c, vmcx::launch_scatter_rows_f32(oc.O, lst, kc, Mn, o.Of, st));
         if (full && o.Gf) HIP_OK(c, vmcx::launch_scatter_rows_f32(oc.G, lst, kc, Mn, o.Gf, st));
     }
+    return VMC_OK;
+}
+
+// One sweep of W walkers: the proposals of every electron with their MO rows
+// (and Jastrow terms) -- independent of the moves' outcomes -- then the moves.
+template <typename T>
+static int sweep_once(vmc_ctx *c, double *walkers, int64_t W, int t, uint32_t sidx, uint64_t seed, uint8_t *acc_t,
+                      const T *C, hipStream_t st) {
+    const int64_t rows = W * c->N;
+    T *Amo = (T *)c->Amo;
+    const int pp = prof_begin(c, VMC_K_PROPOSALS, true, W, st);
+    HIP_OK(c, vmcx::launch_propose(walkers, W, c->N, sidx, seed, c->opt.step_sigma, c->prop, st));
+    HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(c->sys, C, c->d_R, c->prop, rows, c->tiles16, (T *)c->Phip, 1,
+                                          (T *)c->d_cpad, st));
+    vmcx::JasSweep<T> js;
+    if (c->MJ > 0) {
+        T *Xp = (T *)c->js_Xp, *X0 = (T *)c->js_X0, *Pp = (T *)c->js_Pp, *T0 = (T *)c->js_T0;
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->d_R, c->prop, rows, Xp, st));
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->d_R, walkers, rows, X0, st));
+        HIP_OK(c, vmcx::launch_jas_products<T>(c->sys, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), c->d_R, c->prop,
+                                               rows, 1, Pp, (T *)c->d_cpad, st));
+        HIP_OK(c, vmcx::launch_jas_products<T>(c->sys, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), c->d_R, walkers,
+                                               rows, 1, T0, (T *)c->d_cpad, st));
+        js.Xp = Xp;
+        js.X0 = X0;
+        js.Pp = Pp;
+        js.T0 = T0;
+        js.MJ = c->MJ;
+        js.nq = c->nq;
+        js.rows = rows;
+    }
+    prof_end(c, VMC_K_PROPOSALS, pp, st);
+    // the MO matrix of every walker from the caller's positions; the sweeps
+    // keep it current (row e rewritten on each accepted move)
+    if (t == 0)
+        HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(c->sys, C, c->d_R, walkers, rows, c->tiles16, Amo, 1, (T *)c->d_cpad,
+                                              st));
+    const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
+    const vmcx::KState<T> ks{(T *)c->Kst, c->Ksig, c->Kstale};
+    HIP_OK(c, vmcx::launch_sweep<T>(c->sys, (const T *)c->Phip, c->prop, walkers, (int)W, Amo, ks, t == 0, sidx, seed,
+                                    c->opt.refresh_period, acc_t, c->status, c->swl, js, st));
+    prof_end(c, VMC_K_SWEEP, pi, st);
     return VMC_OK;
 }
 
@@ -445,6 +520,153 @@ static double *noalloc_scratch() {
     return g_scratch_ptr[dev];
 }
 
+static size_t ts_of(int precision) { return precision == VMC_MIXED ? sizeof(float) : sizeof(double); }
+
+// Fold the GTO normalisation of a basis (coefficients of unit-normalised
+// primitives; every cartesian component renormalised to unit norm) and upload
+// its tables and AO tiles (whole shells of at most 16 AOs).  Shell counts,
+// angular momenta and exponents have been validated.
+static int upload_basis(vmc_ctx *c, const vmc_basis *basis, int A, vmcx::BasisDev &bd, AoTiles &tiles) {
+    const int S = basis->n_shells;
+    int P = 0;
+    for (int s = 0; s < S; ++s) P += basis->shell_nprim[s];
+    std::vector<int> ao_shell, ao_pow, shell_p0(S), shell_mu0(S);
+    std::vector<double> ao_eta, cp(P);
+    int p0 = 0;
+    for (int s = 0; s < S; ++s) {
+        const int l = basis->shell_l[s], np = basis->shell_nprim[s];
+        shell_p0[s] = p0;
+        shell_mu0[s] = (int)ao_shell.size();
+        std::vector<double> cn(np);
+        for (int k = 0; k < np; ++k) {
+            const double al = basis->prim_exp[p0 + k];
+            cn[k] = basis->prim_coef[p0 + k] * std::pow(2.0 * al / PI, 0.75) * std::pow(4.0 * al, 0.5 * l);
+        }
+        double ov = 0.0;
+        for (int k = 0; k < np; ++k)
+            for (int q = 0; q < np; ++q) {
+                const double pp = basis->prim_exp[p0 + k] + basis->prim_exp[p0 + q];
+                ov += cn[k] * cn[q] * std::pow(PI / pp, 1.5) / std::pow(2.0 * pp, l);
+            }
+        if (!(ov > 0.0)) return c->fail(VMC_EINVAL, "shell %d has zero norm", s);
+        for (int k = 0; k < np; ++k) cp[p0 + k] = cn[k] / std::sqrt(ov);
+        p0 += np;
+        // cartesian components in order s; x,y,z; xx,xy,xz,yy,yz,zz
+        static const int comps[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                                         {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
+        const int first = l == 0 ? 0 : (l == 1 ? 1 : 4);
+        const int cnt = (l + 1) * (l + 2) / 2;
+        for (int q = 0; q < cnt; ++q) {
+            const int *cc = comps[first + q];
+            ao_shell.push_back(s);
+            ao_pow.push_back(cc[0] | (cc[1] << 4) | (cc[2] << 8));
+            ao_eta.push_back(1.0 / std::sqrt((double)(dfact(2 * cc[0] - 1) * dfact(2 * cc[1] - 1) * dfact(2 * cc[2] - 1))));
+        }
+    }
+    const int M = (int)ao_shell.size();
+    // AO tiles: consecutive whole shells with at most 16 AOs, as four arrays
+    // (first shell, end shell, first AO, end AO)
+    std::vector<int> tl;
+    for (int s = 0; s < S;) {
+        int s1 = s, cnt = 0;
+        while (s1 < S && cnt + (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2 <= 16) {
+            cnt += (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2;
+            ++s1;
+        }
+        tl.push_back(s);
+        tl.push_back(s1);
+        tl.push_back(shell_mu0[s]);
+        tl.push_back(s1 < S ? shell_mu0[s1] : M);
+        s = s1;
+    }
+    const int nt = (int)tl.size() / 4;
+    std::vector<int> soa(4 * nt);
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 4; ++k) soa[k * nt + t] = tl[4 * t + k];
+    // the AOs of each atom (any shell order), for per-nucleus sums
+    std::vector<int> atom_ao_ptr(A + 1, 0), atom_ao(M);
+    for (int m = 0; m < M; ++m) ++atom_ao_ptr[basis->shell_atom[ao_shell[m]] + 1];
+    for (int a = 0; a < A; ++a) atom_ao_ptr[a + 1] += atom_ao_ptr[a];
+    {
+        std::vector<int> fill(atom_ao_ptr.begin(), atom_ao_ptr.end() - 1);
+        for (int m = 0; m < M; ++m) atom_ao[fill[basis->shell_atom[ao_shell[m]]]++] = m;
+    }
+    int *d_ao_shell, *d_ao_pow, *d_shell_atom, *d_shell_p0, *d_shell_np, *d_shell_l, *d_shell_mu0, *d_ptr, *d_aa,
+        *d_tiles;
+    double *d_eta, *d_exp, *d_cp;
+    int rc;
+    if ((rc = c->upload(&d_shell_l, (const int *)basis->shell_l, S)) ||
+        (rc = c->upload(&d_shell_mu0, shell_mu0.data(), S)) || (rc = c->upload(&d_tiles, soa.data(), 4 * nt)) ||
+        (rc = c->upload(&d_ptr, atom_ao_ptr.data(), A + 1)) || (rc = c->upload(&d_aa, atom_ao.data(), M)) ||
+        (rc = c->upload(&d_ao_shell, ao_shell.data(), M)) || (rc = c->upload(&d_ao_pow, ao_pow.data(), M)) ||
+        (rc = c->upload(&d_eta, ao_eta.data(), M)) ||
+        (rc = c->upload(&d_shell_atom, (const int *)basis->shell_atom, S)) ||
+        (rc = c->upload(&d_shell_p0, shell_p0.data(), S)) ||
+        (rc = c->upload(&d_shell_np, (const int *)basis->shell_nprim, S)) ||
+        (rc = c->upload(&d_exp, basis->prim_exp, P)) || (rc = c->upload(&d_cp, cp.data(), P)))
+        return rc;
+    bd = vmcx::BasisDev{M,           S,         d_ao_shell, d_ao_pow, d_eta,       d_shell_atom, d_shell_p0,
+                        d_shell_np, d_exp,     d_cp,       d_shell_l, d_shell_mu0, d_ptr,        d_aa};
+    tiles = AoTiles{d_tiles, d_tiles + nt, d_tiles + 2 * nt, d_tiles + 3 * nt, nt};
+    return VMC_OK;
+}
+
+// Validate a basis: shells on existing atoms, l <= VMC_MAX_L, >= 1
+// primitive, finite exponents > 0 and finite coefficients.  Returns the
+// number of cartesian functions (or a negative status).
+static int check_basis(vmc_ctx *c, const vmc_basis *basis, int A, const char *what) {
+    if (!basis || basis->n_shells < 1 || !basis->shell_atom || !basis->shell_l || !basis->shell_nprim ||
+        !basis->prim_exp || !basis->prim_coef)
+        return c->fail(VMC_EINVAL, "%s: missing arrays or no shells", what);
+    int P = 0, M = 0;
+    for (int s = 0; s < basis->n_shells; ++s) {
+        const int l = basis->shell_l[s], np = basis->shell_nprim[s], at = basis->shell_atom[s];
+        if (l < 0 || l > VMC_MAX_L) return c->fail(VMC_EINVAL, "%s shell %d: l = %d not supported", what, s, l);
+        if (np < 1) return c->fail(VMC_EINVAL, "%s shell %d: %d primitives", what, s, np);
+        if (at < 0 || at >= A) return c->fail(VMC_EINVAL, "%s shell %d: atom %d out of range", what, s, at);
+        P += np;
+        M += (l + 1) * (l + 2) / 2;
+    }
+    for (int k = 0; k < P; ++k) {
+        if (!(basis->prim_exp[k] > 0.0) || !std::isfinite(basis->prim_exp[k]))
+            return c->fail(VMC_EINVAL, "%s primitive %d: exponent %g must be finite and > 0", what, k,
+                           basis->prim_exp[k]);
+        if (!std::isfinite(basis->prim_coef[k]))
+            return c->fail(VMC_EINVAL, "%s primitive %d: non-finite coefficient", what, k);
+    }
+    if (P >= 32768) return c->fail(VMC_EINVAL, "%s: %d primitives exceed 32767", what, P);
+    return M;
+}
+
+// The one- and three/four-body Jastrow: its basis tables and [xi3 | xi1] in
+// column blocks of 64 (block q holds columns 64 q .. 64 q + 63 of the
+// MJ x (MJ + 1) matrix whose last column is xi1), FP64 and FP32.
+static int setup_body_jastrow(vmc_ctx *c, const vmc_jastrow *jas, int A) {
+    int rc;
+    if ((rc = upload_basis(c, jas->jas_basis, A, c->jdev, c->jtiles16))) return rc;
+    const int MJ = c->MJ, nq = c->nq;
+    std::vector<double> blk((size_t)nq * MJ * 64, 0.0);
+    for (int q = 0; q < nq; ++q)
+        for (int mu = 0; mu < MJ; ++mu)
+            for (int i = 0; i < 64; ++i) {
+                const int col = 64 * q + i;
+                double v = 0.0;
+                if (col < MJ)
+                    v = jas->xi3 ? jas->xi3[(size_t)mu * MJ + col] : 0.0;
+                else if (col == MJ)
+                    v = jas->xi1 ? jas->xi1[mu] : 0.0;
+                blk[((size_t)q * MJ + mu) * 64 + i] = v;
+            }
+    std::vector<float> blkf(blk.size());
+    for (size_t k = 0; k < blk.size(); ++k) blkf[k] = (float)blk[k];
+    std::vector<double> x1(MJ, 0.0);
+    for (int mu = 0; mu < MJ; ++mu) x1[mu] = jas->xi1 ? jas->xi1[mu] : 0.0;
+    if ((rc = c->upload(&c->d_xiblk, blk.data(), blk.size())) ||
+        (rc = c->upload(&c->d_xiblk_f, blkf.data(), blkf.size())) || (rc = c->upload(&c->d_xi1, x1.data(), MJ)))
+        return rc;
+    return VMC_OK;
+}
+
 static int set_device(vmc_ctx *c) {
     HIP_OK(c, hipSetDevice(c->device));
     return VMC_OK;
@@ -494,28 +716,15 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     };
     c->device = device;
     c->opt = *opt;
-    const int S = basis->n_shells, A = nuclei->n_atoms;
-    if (S < 1 || A < 1 || A > VMC_MAX_ATOMS || !basis->shell_atom || !basis->shell_l || !basis->shell_nprim ||
-        !basis->prim_exp || !basis->prim_coef || !nuclei->xyz || !nuclei->Z || !mo->C)
-        return bail(c->fail(VMC_EINVAL, "missing arrays or bad counts (shells %d, atoms %d)", S, A));
-    int P = 0, M = 0;
-    for (int s = 0; s < S; ++s) {
-        const int l = basis->shell_l[s], np = basis->shell_nprim[s], at = basis->shell_atom[s];
-        if (l < 0 || l > VMC_MAX_L) return bail(c->fail(VMC_EINVAL, "shell %d: l = %d not supported", s, l));
-        if (np < 1) return bail(c->fail(VMC_EINVAL, "shell %d: %d primitives", s, np));
-        if (at < 0 || at >= A) return bail(c->fail(VMC_EINVAL, "shell %d: atom %d out of range", s, at));
-        P += np;
-        M += (l + 1) * (l + 2) / 2;
-    }
-    for (int k = 0; k < P; ++k) {
-        if (!(basis->prim_exp[k] > 0.0) || !std::isfinite(basis->prim_exp[k]))
-            return bail(c->fail(VMC_EINVAL, "primitive %d: exponent %g must be finite and > 0", k, basis->prim_exp[k]));
-        if (!std::isfinite(basis->prim_coef[k]))
-            return bail(c->fail(VMC_EINVAL, "primitive %d: non-finite coefficient", k));
-    }
+    const int S = basis ? basis->n_shells : 0, A = nuclei->n_atoms;
+    if (A < 1 || A > VMC_MAX_ATOMS || !nuclei->xyz || !nuclei->Z || !mo->C)
+        return bail(c->fail(VMC_EINVAL, "missing arrays or bad counts (atoms %d)", A));
+    const int M = check_basis(c, basis, A, "basis");
+    if (M < 0) return bail(M);
+    int P = 0;
+    for (int s = 0; s < S; ++s) P += basis->shell_nprim[s];
     if (M != mo->n_ao) return bail(c->fail(VMC_EINVAL, "n_ao = %d but the shells give %d AOs", mo->n_ao, M));
     if (M > VMC_MAX_AO) return bail(c->fail(VMC_EINVAL, "n_ao = %d exceeds %d", M, VMC_MAX_AO));
-    if (P >= 32768) return bail(c->fail(VMC_EINVAL, "%d primitives exceed 32767", P));
     if (mo->n_up != mo->n_dn || mo->n_up < 1 || mo->n_occ != mo->n_up)
         return bail(c->fail(VMC_EINVAL, "need a closed shell with n_up = n_dn = n_occ >= 1 (got %d, %d, %d)",
                             mo->n_up, mo->n_dn, mo->n_occ));
@@ -527,6 +736,21 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (jas->ee_form != VMC_JASTROW_PADE && jas->ee_form != VMC_JASTROW_EXP) ||
         (jas->ee_form == VMC_JASTROW_EXP && !(jas->ee_F > 0.0)))
         return bail(c->fail(VMC_EINVAL, "bad Jastrow parameters"));
+    if (jas->jas_basis) {
+        const int MJ = check_basis(c, jas->jas_basis, A, "Jastrow basis");
+        if (MJ < 0) return bail(MJ);
+        if (MJ > VMC_MAX_JAS)
+            return bail(c->fail(VMC_EINVAL, "%d Jastrow basis functions exceed %d", MJ, VMC_MAX_JAS));
+        if ((jas->xi1 && !all_finite(jas->xi1, MJ)) || (jas->xi3 && !all_finite(jas->xi3, (int64_t)MJ * MJ)))
+            return bail(c->fail(VMC_EINVAL, "non-finite Jastrow parameters"));
+        if (jas->xi3)
+            for (int a = 0; a < MJ; ++a)
+                for (int b = 0; b < a; ++b)
+                    if (jas->xi3[(size_t)a * MJ + b] != jas->xi3[(size_t)b * MJ + a])
+                        return bail(c->fail(VMC_EINVAL, "xi3 is not symmetric (%d, %d)", a, b));
+        c->MJ = MJ;
+        c->nq = (MJ + 1 + 63) / 64;
+    }
     if (opt->precision != VMC_FP64 && opt->precision != VMC_MIXED)
         return bail(c->fail(VMC_EINVAL, "precision %d not available (VMC_FP64 or VMC_MIXED)", opt->precision));
     if (opt->refresh_period < 1 || opt->block_sweeps < 1 || opt->max_walkers < 1 || opt->staging_walkers < 0 ||
@@ -548,92 +772,11 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     c->ee_form = jas->ee_form;
     (void)Zsum;
 
-    // ---- fold normalisation -------------------------------------------------
-    std::vector<int> ao_shell, ao_pow, shell_p0(S), shell_mu0(S);
-    std::vector<double> ao_eta, cp(P);
-    int p0 = 0;
-    for (int s = 0; s < S; ++s) {
-        const int l = basis->shell_l[s], np = basis->shell_nprim[s];
-        shell_p0[s] = p0;
-        shell_mu0[s] = (int)ao_shell.size();
-        std::vector<double> cn(np);
-        for (int k = 0; k < np; ++k) {
-            const double al = basis->prim_exp[p0 + k];
-            cn[k] = basis->prim_coef[p0 + k] * std::pow(2.0 * al / PI, 0.75) * std::pow(4.0 * al, 0.5 * l);
-        }
-        double ov = 0.0;
-        for (int k = 0; k < np; ++k)
-            for (int q = 0; q < np; ++q) {
-                const double pp = basis->prim_exp[p0 + k] + basis->prim_exp[p0 + q];
-                ov += cn[k] * cn[q] * std::pow(PI / pp, 1.5) / std::pow(2.0 * pp, l);
-            }
-        if (!(ov > 0.0)) return bail(c->fail(VMC_EINVAL, "shell %d has zero norm", s));
-        for (int k = 0; k < np; ++k) cp[p0 + k] = cn[k] / std::sqrt(ov);
-        p0 += np;
-        // cartesian components in order s; x,y,z; xx,xy,xz,yy,yz,zz
-        static const int comps[10][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
-                                         {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
-        const int first = l == 0 ? 0 : (l == 1 ? 1 : 4);
-        const int cnt = (l + 1) * (l + 2) / 2;
-        for (int q = 0; q < cnt; ++q) {
-            const int *cc = comps[first + q];
-            ao_shell.push_back(s);
-            ao_pow.push_back(cc[0] | (cc[1] << 4) | (cc[2] << 8));
-            ao_eta.push_back(1.0 / std::sqrt((double)(dfact(2 * cc[0] - 1) * dfact(2 * cc[1] - 1) * dfact(2 * cc[2] - 1))));
-        }
-    }
-
-    // AO tiles: consecutive whole shells with at most `cap` AOs, as four
-    // arrays (first shell, end shell, first AO, end AO)
-    auto make_tiles = [&](int cap) {
-        std::vector<int> tl;
-        for (int s = 0; s < S;) {
-            int s1 = s, cnt = 0;
-            while (s1 < S && cnt + (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2 <= cap) {
-                cnt += (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2;
-                ++s1;
-            }
-            tl.push_back(s);
-            tl.push_back(s1);
-            tl.push_back(shell_mu0[s]);
-            tl.push_back(s1 < S ? shell_mu0[s1] : M);
-            s = s1;
-        }
-        const int nt = (int)tl.size() / 4;
-        std::vector<int> soa(4 * nt);
-        for (int t = 0; t < nt; ++t)
-            for (int k = 0; k < 4; ++k) soa[k * nt + t] = tl[4 * t + k];
-        return soa;
-    };
-    const std::vector<int> tile16 = make_tiles(16);
-    const int n_tiles16 = (int)tile16.size() / 4;
-
+    // ---- fold normalisation, upload the basis tables -----------------------
     int rc;
     if ((rc = set_device(c))) return bail(rc);
-    if ((rc = c->upload(&c->d_shell_l, (const int *)basis->shell_l, S)) ||
-        (rc = c->upload(&c->d_shell_mu0, shell_mu0.data(), S)) ||
-        (rc = c->upload(&c->d_tile16, tile16.data(), 4 * n_tiles16)))
-        return bail(rc);
-    c->tiles16 = AoTiles{c->d_tile16, c->d_tile16 + n_tiles16, c->d_tile16 + 2 * n_tiles16,
-                         c->d_tile16 + 3 * n_tiles16, n_tiles16};
-    // the AOs of each atom (any shell order), for per-nucleus sums
-    std::vector<int> atom_ao_ptr(A + 1, 0), atom_ao(M);
-    for (int m = 0; m < M; ++m) ++atom_ao_ptr[basis->shell_atom[ao_shell[m]] + 1];
-    for (int a = 0; a < A; ++a) atom_ao_ptr[a + 1] += atom_ao_ptr[a];
-    {
-        std::vector<int> fill(atom_ao_ptr.begin(), atom_ao_ptr.end() - 1);
-        for (int m = 0; m < M; ++m) atom_ao[fill[basis->shell_atom[ao_shell[m]]]++] = m;
-    }
-    if ((rc = c->upload(&c->d_atom_ao_ptr, atom_ao_ptr.data(), A + 1)) ||
-        (rc = c->upload(&c->d_atom_ao, atom_ao.data(), M)))
-        return bail(rc);
-    if ((rc = c->upload(&c->d_ao_shell, ao_shell.data(), M)) || (rc = c->upload(&c->d_ao_pow, ao_pow.data(), M)) ||
-        (rc = c->upload(&c->d_ao_eta, ao_eta.data(), M)) ||
-        (rc = c->upload(&c->d_shell_atom, (const int *)basis->shell_atom, S)) ||
-        (rc = c->upload(&c->d_shell_p0, shell_p0.data(), S)) ||
-        (rc = c->upload(&c->d_shell_np, (const int *)basis->shell_nprim, S)) ||
-        (rc = c->upload(&c->d_prim_exp, basis->prim_exp, P)) || (rc = c->upload(&c->d_prim_cp, cp.data(), P)) ||
-        (rc = c->upload(&c->d_C, mo->C, (size_t)M * c->n_occ)) || (rc = c->upload(&c->d_R, nuclei->xyz, 3 * A)) ||
+    if ((rc = upload_basis(c, basis, A, c->bdev, c->tiles16))) return bail(rc);
+    if ((rc = c->upload(&c->d_C, mo->C, (size_t)M * c->n_occ)) || (rc = c->upload(&c->d_R, nuclei->xyz, 3 * A)) ||
         (rc = c->upload(&c->d_Z, nuclei->Z, A)))
         return bail(rc);
     if (opt->precision == VMC_MIXED) {
@@ -642,7 +785,8 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         if ((rc = c->upload(&c->d_Cf, cf.data(), cf.size())) || (rc = c->dalloc(&c->d_Cm, cf.size())))
             return bail(rc);
     }
-    if ((rc = c->dalloc(&c->d_cpad, (size_t)(M + 16) * 64))) return bail(rc);
+    if ((rc = c->dalloc(&c->d_cpad, (size_t)(std::max(M, c->MJ) + 16) * 64))) return bail(rc);
+    if (c->MJ > 0 && (rc = setup_body_jastrow(c, jas, A))) return bail(rc);
 
     SysDev &sd = c->sys;
     sd.N = c->N;
@@ -655,9 +799,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     sd.ee_F = c->ee_F;
     sd.ee_form = c->ee_form;
     sd.forced_ratio = opt->forced_refresh_ratio > 0.0 ? opt->forced_refresh_ratio : vmcx::FORCED_REFRESH_RATIO;
-    sd.basis = vmcx::BasisDev{M,          S,           c->d_ao_shell, c->d_ao_pow,   c->d_ao_eta,
-                              c->d_shell_atom, c->d_shell_p0, c->d_shell_np, c->d_prim_exp, c->d_prim_cp,
-                              c->d_shell_l, c->d_shell_mu0, c->d_atom_ao_ptr, c->d_atom_ao};
+    sd.basis = c->bdev;
     sd.Z = c->d_Z;
     layouts(c);
     const bool mixed = opt->precision == VMC_MIXED;
@@ -701,8 +843,14 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     // ---- staging and accumulators -------------------------------------------
     const int64_t Mn = (int64_t)M * c->n_occ, A3 = 3 * A;
     const int64_t Nn = (int64_t)c->N * c->n_occ;
+    // (with the one-/three-body Jastrow: its basis values, the five
+    // [xi3 | xi1] products per electron, gradient + Laplacian, per-function
+    // sums)
+    const int64_t jas_pw = c->MJ > 0 ? (int64_t)c->N * c->MJ + (int64_t)c->nq * c->N * 5 * 64 + 4 * (int64_t)c->N +
+                                           1 + 6 * (int64_t)c->MJ
+                                     : 0;
     const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
-                                                        3 * (int64_t)c->N + 6 * M + 3 * c->N);
+                                                        3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw);
     int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, opt->max_walkers));
     if (opt->staging_walkers > 0) chunk = std::min<int64_t>(chunk, opt->staging_walkers);
@@ -724,6 +872,20 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->Ksig, (size_t)opt->max_walkers * 2 * vmcx::sweep_kn(c->n_occ))) ||
         (rc = c->dalloc(&c->Kstale, (size_t)opt->max_walkers * 2)))
         return bail(rc);
+    if (c->MJ > 0) {
+        // sweeps: values and [xi3 | xi1] products at the proposals and the
+        // current positions, in the arithmetic type; measurements: FP64
+        // sizes (the mixed path's FP64 re-measurement reuses them)
+        const size_t rows = (size_t)opt->max_walkers * c->N, tsz = ts_of(opt->precision);
+        const size_t nx = (rows * c->MJ * tsz + 7) / 8, np = (rows * c->nq * 64 * tsz + 7) / 8;
+        if ((rc = c->dalloc((double **)&c->js_Xp, nx)) || (rc = c->dalloc((double **)&c->js_X0, nx)) ||
+            (rc = c->dalloc((double **)&c->js_Pp, np)) || (rc = c->dalloc((double **)&c->js_T0, np)) ||
+            (rc = c->dalloc(&c->jm_X, (size_t)chunk * c->N * c->MJ)) ||
+            (rc = c->dalloc(&c->jm_O, (size_t)c->nq * chunk * c->N * 5 * 64)) ||
+            (rc = c->dalloc(&c->jm_g, (size_t)chunk * c->N * 4)) || (rc = c->dalloc(&c->jm_u, (size_t)chunk)) ||
+            (rc = c->dalloc(&c->jm_tao, (size_t)chunk * c->MJ * 6)))
+            return bail(rc);
+    }
     if (opt->precision == VMC_MIXED && opt->promote_fraction > 0.0) {
         c->pcap = std::max<int64_t>(1, std::min<int64_t>(chunk, (int64_t)std::ceil(opt->promote_fraction * chunk)));
         const int64_t p = c->pcap;
@@ -770,45 +932,13 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
     int rc;
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    const int64_t Mn = (int64_t)c->M * c->n_occ, A3 = 3 * c->A;
     for (int t = 0; t < nsteps; ++t) {
         const uint32_t sidx = (uint32_t)(sweep_offset + t);
         uint8_t *acc_t = accept ? accept + (size_t)t * c->N * W : nullptr;
-        // the MO matrix of every walker from the caller's positions; the
-        // sweeps keep it current (row e rewritten on each accepted move)
-        // the proposals of every electron and their MO rows (independent of
-        // the moves' outcomes), then the moves
-        const int pp = prof_begin(c, VMC_K_PROPOSALS, true, W, st);
-        HIP_OK(c, vmcx::launch_propose(walkers, W, c->N, sidx, seed, c->opt.step_sigma, c->prop, st));
-        if (c->opt.precision == VMC_MIXED) {
-            float *Amo = (float *)c->Amo;
-            HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, c->prop, W * c->N, c->tiles16,
-                                                      (float *)c->Phip, 1, (float *)c->d_cpad, st));
-            prof_end(c, VMC_K_PROPOSALS, pp, st);
-            if (t == 0)
-                HIP_OK(c, vmcx::launch_mo_rows_mfma<float>(c->sys, c->d_Cf, c->d_R, walkers, W * c->N, c->tiles16,
-                                                          Amo, 1, (float *)c->d_cpad, st));
-            const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
-            const vmcx::KState<float> ks{(float *)c->Kst, c->Ksig, c->Kstale};
-            HIP_OK(c, vmcx::launch_sweep<float>(c->sys, (const float *)c->Phip, c->prop, walkers, (int)W, Amo, ks,
-                                                t == 0, sidx, seed, c->opt.refresh_period, acc_t, c->status, c->swl,
-                                                st));
-            prof_end(c, VMC_K_SWEEP, pi, st);
-        } else {
-            double *Amo = (double *)c->Amo;
-            HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, c->prop, W * c->N, c->tiles16,
-                                                       (double *)c->Phip, 1, c->d_cpad, st));
-            prof_end(c, VMC_K_PROPOSALS, pp, st);
-            if (t == 0)
-                HIP_OK(c, vmcx::launch_mo_rows_mfma<double>(c->sys, c->d_C, c->d_R, walkers, W * c->N, c->tiles16,
-                                                           Amo, 1, c->d_cpad, st));
-            const int pi = prof_begin(c, VMC_K_SWEEP, true, W, st);
-            const vmcx::KState<double> ks{(double *)c->Kst, c->Ksig, c->Kstale};
-            HIP_OK(c, vmcx::launch_sweep<double>(c->sys, (const double *)c->Phip, c->prop, walkers, (int)W, Amo, ks,
-                                                 t == 0, sidx, seed, c->opt.refresh_period, acc_t, c->status,
-                                                 c->swl, st));
-            prof_end(c, VMC_K_SWEEP, pi, st);
-        }
+        if ((rc = c->opt.precision == VMC_MIXED
+                      ? sweep_once<float>(c, walkers, W, t, sidx, seed, acc_t, c->d_Cf, st)
+                      : sweep_once<double>(c, walkers, W, t, sidx, seed, acc_t, c->d_C, st)))
+            return rc;
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
         if ((rc = measure_accumulate(c, walkers, W, nullptr, true, st))) return rc;
     }

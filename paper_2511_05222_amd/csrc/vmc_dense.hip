@@ -188,6 +188,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int c = 0; c < 3; ++c)
             gq[c] = (jp[3 * e + c] + jp[3 * N + 3 * e + c]) +
                     ((bw[3 * e + c] + bw[3 * N + 3 * e + c]) + (bw[6 * N + 3 * e + c] + bw[9 * N + 3 * e + c]));
+        if (mb.jg) {
+            // one-/three-body terms: gradient into the total, Laplacian
+            const double *jg = mb.jg + ((size_t)w * N + e) * 4;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gq[c] += jg[c];
+            el_part += -0.5 * jg[3];
+        }
         g[3 * e] = gq[0];
         g[3 * e + 1] = gq[1];
         g[3 * e + 2] = gq[2];
@@ -397,7 +404,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         vnn += S.Z[a] * S.Z[c] / sqrt(dx * dx + dy * dy + dz * dz);
     }
     const double EL = block_sum4(el_part + vnn, red);
-    const double J = block_sum4(j_part, red);
+    const double J = block_sum4(j_part, red) + (mb.ju ? mb.ju[w] : 0.0);
     const int anybad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0) {
         if (mb.promote_key) mb.promote_key[w] = abar_max <= DBL_MAX ? abar_max : __builtin_inf();

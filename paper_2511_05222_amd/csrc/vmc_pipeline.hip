@@ -261,6 +261,18 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
                 sP[k] -= t[3 + k];
             }
         }
+        if (mb.jtao) {
+            // the one-/three-body Jastrow functions on this nucleus
+            const int MJ = mb.jb.n_ao, j0 = mb.jb.atom_ao_ptr[a], j1 = mb.jb.atom_ao_ptr[a + 1];
+            for (int q = j0 + j; q < j1; q += tpa) {
+                const double *t = mb.jtao + ((size_t)w * MJ + mb.jb.atom_ao[q]) * 6;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    sE[k] -= t[k];
+                    sP[k] -= t[3 + k];
+                }
+            }
+        }
         const double Rx = R[3 * a], Ry = R[3 * a + 1], Rz = R[3 * a + 2], Za = S.Z[a];
         for (int e = j; e < N; e += tpa) {
             const double dx = p[3 * e] - Rx, dy = p[3 * e + 1] - Ry, dz = p[3 * e + 2] - Rz;

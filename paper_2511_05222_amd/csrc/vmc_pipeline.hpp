@@ -57,17 +57,53 @@ struct MeasBufs {
     const T *kst;
     const uint8_t *ksig;
     const int *kstale;
+    // one-/three-body Jastrow terms (null: none): grad_e U, lap_e U per
+    // electron [W][N][4] and U [W], added to the two-body terms
+    const double *jg = nullptr, *ju = nullptr;
 };
 
 struct MeasBufsD {
     const double *pos, *pos0;
     const double *gb, *dedr_part, *tao;
+    // one-/three-body Jastrow (null: none): per-function electron sums
+    // jtao[W][MJ][6] of its dE_L/dr and dlnPsi/dr terms; jb its basis
+    const double *jtao = nullptr;
+    BasisDev jb{};
 };
 
 // cpad: scratch of (M + 16) * 64 elements for the padded copy of C (n_occ <= 64)
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
                                const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st);
+// One-/three-body Jastrow terms (vmc_jastrow.hip).  jas_values: out[row][mu]
+// = chi_mu(pos[row]).  jas_products: for each of the nq column blocks q of
+// [xi3 | xi1] ([nq][MJ][64] in xiblk) the nc derivative components' products,
+// out[q][row][nc][64].  jas_assemble: grad_e U, lap_e U, U.  jas_adjoint: its
+// terms of dE_L/dr_e (added to dedr) and the per-function sums jtao.
+template <typename T>
+hipError_t launch_jas_values(const BasisDev &JB, const double *R, const double *pos, int64_t rows, T *out,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_jas_products(const SysDev &S, const BasisDev &JB, const AoTiles &jt, int nq, const T *xiblk,
+                               const double *R, const double *pos, int64_t rows, int nc, T *out, T *cpad,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0, int W, const T *X, const T *O,
+                               double *jg, double *ju, hipStream_t st);
+template <typename T>
+hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int nq, int64_t rows, int64_t row0, int W,
+                              const double *pos, const T *X, const T *O, const double *gb, const double *xi1,
+                              double *dedr, double *jtao, hipStream_t st);
+// The sweep's one-/three-body terms (null Xp: none): chi at the proposals and
+// at the positions of the sweep's start ([W N][MJ]), their [xi3 | xi1]
+// products ([nq][W N][64]).
+template <typename T>
+struct JasSweep {
+    const T *Xp = nullptr, *X0 = nullptr, *Pp = nullptr, *T0 = nullptr;
+    int MJ = 0, nq = 0;
+    int64_t rows = 0;
+};
+
 // Persistent inverses of the two spin blocks of every walker, in the
 // register layout of the sweep: K[w][b][r][lane] (KN x KN, type T), the
 // permutation sig[w][b][lane] and stale[w][b] = a rebuild is due.
@@ -87,7 +123,7 @@ hipError_t launch_propose(const double *walkers, int64_t W, int N, uint32_t swee
 template <typename T>
 hipError_t launch_sweep(const SysDev &S, const T *Phip, const double *prop, double *walkers, int W, T *Amo,
                         const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period,
-                        uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st);
+                        uint8_t *accept, int *status, const SweepLayout &L, const JasSweep<T> &js, hipStream_t st);
 hipError_t launch_warp(const SysDev &S, const double *R, const double *R0, const double *pos0, double *posw,
                        double *lnjac, int W, hipStream_t st);
 template <typename T>

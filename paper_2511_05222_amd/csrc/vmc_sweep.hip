@@ -134,11 +134,15 @@ constexpr int sweep_waves() {
     return (sizeof(T) == 4 && KN <= 48) ? 3 : 2;
 }
 
-template <typename T, int KN>
+// The one-/three-body Jastrow slots of a lane: basis function 64 q + lane for
+// q < JQ (the last slot past the basis, 64 q + lane = MJ, is xi1's column).
+constexpr int JQ = 5;
+
+template <typename T, int KN, bool J13>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves<T, KN>()))) void k_sweep_r(
     SysDev S, const T *__restrict__ Phip, const double *__restrict__ prop, double *walkers, int W, T *Amo,
     KState<T> ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period, uint8_t *accept, int *status,
-    SweepLayout L) {
+    SweepLayout L, JasSweep<T> js) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int N = S.N, nu = S.n_up, n = S.n_occ;
@@ -170,6 +174,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
     bool bad = false;
     T Kr[KN];
     int sig = lane;
+    // one-/three-body Jastrow: t = xi3 s over this lane's basis slots, s the
+    // sum of chi over the electrons' current positions (kept current by the
+    // accepted moves; rebuilt from the start positions every sweep)
+    T tq[JQ];
+    if constexpr (J13) {
+#pragma unroll
+        for (int q = 0; q < JQ; ++q) {
+            T a = T(0);
+            if (q < js.nq && 64 * q + lane < js.MJ)
+                for (int e = 0; e < N; ++e) a += js.T0[((size_t)q * js.rows + (size_t)w * N + e) * 64 + lane];
+            tq[q] = a;
+        }
+    }
 
     // the proposal's MO row of the first move (later rows are loaded one move
     // ahead, so that the load overlaps the move before)
@@ -216,6 +233,29 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         // Jastrow difference over the pairs (e, k), k held by this lane (in
         // the arithmetic type: it only enters the acceptance ratio)
         double dj = jastrow_delta<T>(S, N, e, lane, rx, ry, rz, ex, ey, ez, px, py, pz);
+        // one-/three-body difference: (chi' - chi) . (t - xi3 chi) over the
+        // basis, plus xi1 . (chi' - chi) from the last column
+        T jp[JQ], jt0[JQ];
+        if constexpr (J13) {
+            const size_t row = (size_t)w * N + e;
+            T loc = T(0);
+#pragma unroll
+            for (int q = 0; q < JQ; ++q) {
+                jp[q] = jt0[q] = T(0);
+                const int mu = 64 * q + lane;
+                if (q < js.nq && mu <= js.MJ) {
+                    jp[q] = js.Pp[((size_t)q * js.rows + row) * 64 + lane];
+                    jt0[q] = js.T0[((size_t)q * js.rows + row) * 64 + lane];
+                    if (mu < js.MJ) {
+                        const T d = js.Xp[row * js.MJ + mu] - js.X0[row * js.MJ + mu];
+                        loc += d * (tq[q] - jt0[q]);
+                    } else {
+                        loc += jp[q] - jt0[q];
+                    }
+                }
+            }
+            dj += wave_sum_dpp((double)loc);
+        }
         // lane i < KN holds phi_i (zero from nb on): store it at the register
         // slot of orbital i
         if (lane < KN) phin[sig] = ph;
@@ -252,6 +292,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
                 for (int r = 0; r < KN; ++r) colj[r] = Kr[r];
             }
             wave_sync_s();
+            if constexpr (J13) {
+#pragma unroll
+                for (int q = 0; q < JQ; ++q)
+                    if (64 * q + lane < js.MJ) tq[q] += jp[q] - jt0[q];
+            }
             const T rr = sizeof(T) == sizeof(float) ? (T)__builtin_amdgcn_rcpf((float)ratio) : (T)rcp_nr(ratio);
             const T t = (v - (lane == pj ? T(1) : T(0))) * rr;
 #pragma unroll
@@ -287,9 +332,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
 template <typename T, int KN>
 static hipError_t launch_kn(const SysDev &S, const T *Phip, const double *prop, double *walkers, int W, T *Amo,
                             const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period,
-                            uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_r<T, KN>), dim3((unsigned)((W + L.wpb - 1) / L.wpb)), dim3(64 * L.wpb), L.bytes, st,
-                       S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept, status, L);
+                            uint8_t *accept, int *status, const SweepLayout &L, const JasSweep<T> &js,
+                            hipStream_t st) {
+    const dim3 g((unsigned)((W + L.wpb - 1) / L.wpb)), b(64 * L.wpb);
+    if (js.Xp)
+        hipLaunchKernelGGL((k_sweep_r<T, KN, true>), g, b, L.bytes, st, S, Phip, prop, walkers, W, Amo, ks, fresh,
+                           sweep, seed, refresh_period, accept, status, L, js);
+    else
+        hipLaunchKernelGGL((k_sweep_r<T, KN, false>), g, b, L.bytes, st, S, Phip, prop, walkers, W, Amo, ks, fresh,
+                           sweep, seed, refresh_period, accept, status, L, js);
     return hipGetLastError();
 }
 
@@ -306,27 +357,27 @@ hipError_t launch_propose(const double *walkers, int64_t W, int N, uint32_t swee
 template <typename T>
 hipError_t launch_sweep(const SysDev &S, const T *Phip, const double *prop, double *walkers, int W, T *Amo,
                         const KState<T> &ks, int fresh, uint32_t sweep, uint64_t seed, int refresh_period,
-                        uint8_t *accept, int *status, const SweepLayout &L, hipStream_t st) {
+                        uint8_t *accept, int *status, const SweepLayout &L, const JasSweep<T> &js, hipStream_t st) {
     switch (sweep_kn(S.n_occ)) {
         case 16:
             return launch_kn<T, 16>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
-                                    status, L, st);
+                                    status, L, js, st);
         case 32:
             return launch_kn<T, 32>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
-                                    status, L, st);
+                                    status, L, js, st);
         case 48:
             return launch_kn<T, 48>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
-                                    status, L, st);
+                                    status, L, js, st);
         default:
             return launch_kn<T, 64>(S, Phip, prop, walkers, W, Amo, ks, fresh, sweep, seed, refresh_period, accept,
-                                    status, L, st);
+                                    status, L, js, st);
     }
 }
 
 template <typename T>
 hipError_t configure_sweep(size_t lds) {
-    const void *f[4] = {(const void *)k_sweep_r<T, 16>, (const void *)k_sweep_r<T, 32>,
-                        (const void *)k_sweep_r<T, 48>, (const void *)k_sweep_r<T, 64>};
+    const void *f[4] = {(const void *)k_sweep_r<T, 16, false>, (const void *)k_sweep_r<T, 32, false>,
+                        (const void *)k_sweep_r<T, 48, false>, (const void *)k_sweep_r<T, 64, false>};
     for (const void *g : f) {
         const hipError_t e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -336,14 +387,14 @@ hipError_t configure_sweep(size_t lds) {
 
 template hipError_t launch_sweep<double>(const SysDev &, const double *, const double *, double *, int, double *,
                                          const KState<double> &, int, uint32_t, uint64_t, int, uint8_t *, int *,
-                                         const SweepLayout &, hipStream_t);
+                                         const SweepLayout &, const JasSweep<double> &, hipStream_t);
 template hipError_t launch_sweep<float>(const SysDev &, const float *, const double *, double *, int, float *,
                                         const KState<float> &, int, uint32_t, uint64_t, int, uint8_t *, int *,
-                                        const SweepLayout &, hipStream_t);
+                                        const SweepLayout &, const JasSweep<float> &, hipStream_t);
 template <typename T>
 int sweep_blocks_per_cu(int n_occ, int wpb, size_t lds) {
-    const void *f[4] = {(const void *)k_sweep_r<T, 16>, (const void *)k_sweep_r<T, 32>,
-                        (const void *)k_sweep_r<T, 48>, (const void *)k_sweep_r<T, 64>};
+    const void *f[4] = {(const void *)k_sweep_r<T, 16, false>, (const void *)k_sweep_r<T, 32, false>,
+                        (const void *)k_sweep_r<T, 48, false>, (const void *)k_sweep_r<T, 64, false>};
     const int kn = sweep_kn(n_occ), k = kn == 16 ? 0 : (kn == 32 ? 1 : (kn == 48 ? 2 : 3));
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f[k], 64 * wpb, lds) != hipSuccess) {

@@ -53,7 +53,9 @@ class _MO(ct.Structure):
 
 
 class _Jastrow(ct.Structure):
-    _fields_ = [("ee_a", ct.c_double), ("ee_F", ct.c_double), ("ee_form", ct.c_int32)]
+    _fields_ = [("ee_a", ct.c_double), ("ee_F", ct.c_double), ("ee_form", ct.c_int32),
+                ("jas_basis", ct.POINTER(_Basis)), ("xi1", ct.POINTER(ct.c_double)),
+                ("xi3", ct.POINTER(ct.c_double))]
 
 
 class _Options(ct.Structure):
@@ -154,6 +156,17 @@ class Context:
         n_ao = int(sum((int(l) + 1) * (int(l) + 2) // 2 for l in b.shell_l))
         mo = _MO(n_ao, mol.n_occ, mol.n_up, mol.n_dn, dp(k[7]))
         jas = _Jastrow(mol.jastrow.ee_a, mol.jastrow.ee_F, int(getattr(mol.jastrow, "ee_form", 0)))
+        jb = getattr(mol.jastrow, "jas_basis", None)
+        if jb is not None:
+            jk = [np.ascontiguousarray(jb.shell_atom, np.int32), np.ascontiguousarray(jb.shell_l, np.int32),
+                  np.ascontiguousarray(jb.shell_nprim, np.int32), np.ascontiguousarray(jb.prim_exp, np.float64),
+                  np.ascontiguousarray(jb.prim_coef, np.float64),
+                  np.ascontiguousarray(mol.jastrow.xi1, np.float64), np.ascontiguousarray(mol.jastrow.xi3, np.float64)]
+            self._keep += jk
+            self._jbasis = _Basis(jb.n_shells, ip(jk[0]), ip(jk[1]), ip(jk[2]), dp(jk[3]), dp(jk[4]))
+            jas.jas_basis = ct.pointer(self._jbasis)
+            jas.xi1 = dp(jk[5])
+            jas.xi3 = dp(jk[6])
         if getattr(mol.jastrow, "en_on", 0):
             raise VmcError(VMC_EINVAL, "the electron-nucleus Jastrow factor is not part of the HIP path")
         prec = {"fp64": VMC_FP64, "mixed": VMC_MIXED}.get(precision)

@@ -107,3 +107,23 @@ def test_zvector_rejects_bad_sizes():
     assert L.zvector_backmap(None, 5, 3, 2, 1, None, None, None) == vmc.VMC_EINVAL
     assert L.zvector_jackknife(None, 4, 3, None, None, None) == vmc.VMC_EINVAL
     assert L.vmc_jackknife(None, None, None, None, None, None) == vmc.VMC_EINVAL
+
+
+def test_rejects_bad_body_jastrow():
+    import dataclasses
+    mol = inputs.with_body_jastrow(inputs.make_config(1).molecule, 7)
+    xi3 = mol.jastrow.xi3.copy()
+    xi3[0, 1] += 1e-3                       # not symmetric
+    bad = dataclasses.replace(mol, jastrow=dataclasses.replace(mol.jastrow, xi3=xi3))
+    with pytest.raises(vmc.VmcError) as ei:
+        vmc.Context(bad, 4)
+    assert ei.value.code == vmc.VMC_EINVAL and "symmetric" in str(ei.value)
+    jb = mol.jastrow.jas_basis
+    big = inputs.Basis(np.tile(jb.shell_atom, 4), np.tile(jb.shell_l, 4), np.tile(jb.shell_nprim, 4),
+                       np.tile(jb.prim_exp, 4), np.tile(jb.prim_coef, 4))
+    M4 = big.n_ao
+    bad = dataclasses.replace(mol, jastrow=dataclasses.replace(mol.jastrow, jas_basis=big, xi1=np.zeros(M4),
+                                                               xi3=np.zeros((M4, M4))))
+    with pytest.raises(vmc.VmcError) as ei:
+        vmc.Context(bad, 4)
+    assert ei.value.code == vmc.VMC_EINVAL and "exceed" in str(ei.value)

@@ -1,0 +1,154 @@
+"""One-body and three/four-body Jastrow terms on a Jastrow GTO basis
+(Appendix A, eqs. onebody_J_inhom and threebody_jas) through the C ABI,
+against the FP64 oracle.
+
+The seeded Jastrow of inputs.with_body_jastrow: [3s1p] on H and [4s2p1d] on
+C and O (84 functions for the 9-atom molecule, 256 for the 21-atom one, the
+library's limit; [xi3 | xi1] then spans five column blocks of 64).
+
+FP64, 1e-10 of each array's scale (accept bits bit-exact): the sweep's
+accept/reject sequence with the Jastrow difference of every move; the
+per-walker measurement (E_L, ln|Psi|, dE_L/dR, dln|Psi|/dR, O = dln|Psi|/dC,
+G = dE_L/dC) at the sampling geometry and at displaced nuclei (the Jastrow
+functions move with their nuclei; electrons warped); the estimators after
+sweeps with measurement.  Mixed precision within the mixed-vs-FP64 bounds.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2511_05222_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def close(gpu, ref, tol=TOL, what=""):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape, (what, gpu.shape, ref.shape)
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(gpu - ref).max()
+    assert err <= tol * scale, f"{what}: max err {err:.3e} vs scale {scale:.3e} (rel {err / scale:.3e})"
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_05222_amd import vmc
+    vmc.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def mol9j():
+    return inputs.with_body_jastrow(inputs.make_config(1).molecule, 7)
+
+
+def per_walker_oracle(mol, r, R=None, R0=None):
+    from oracle import derivatives as dv, wavefunction as wf
+    s = wf.System(mol)
+    R0 = s.xyz if R0 is None else R0
+    R = R0 if R is None else R
+    dE, dP, dJ = dv.nuclear_derivatives(s, R, R0, r)
+    rp, lnjac = dv.warp(R, R0, r)
+    O, G, ev = dv.coefficient_derivatives(s, R, rp)
+    return dict(EL=ev["E_L"], lnpsi=ev["lnpsi"], lnjac=lnjac, dEL_dR=dE, dlnpsi_dR=dP, dlnjac_dR=dJ, O=O, G=G)
+
+
+def test_sweep_accept_bits(dev, mol9j):
+    from oracle import sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    W, sweeps, seed = 16, 3, 551
+    w0 = inputs.initial_walkers(mol9j, W, 3)
+    ch, bits = sampler.run(wf.System(mol9j), w0, sweeps, seed, sweep_offset=2)
+    ctx = vmc.Context(mol9j, max_walkers=W)
+    tw = torch.tensor(w0, device=dev)
+    acc = torch.zeros((sweeps, mol9j.n_elec, W), dtype=torch.uint8, device=dev)
+    print("case: 9-atom J1/J3 sweep", flush=True)
+    ctx.sweep(tw, sweeps, seed, sweep_offset=2, measure=False, accept=acc)
+    torch.cuda.synchronize()
+    assert np.array_equal(acc.cpu().numpy().astype(bool), bits)
+    close(tw.cpu().numpy(), ch.r, tol=1e-13, what="positions")
+
+
+def test_measure_parity(dev, mol9j):
+    from oracle import sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    W = 7
+    ch, _ = sampler.run(wf.System(mol9j), inputs.initial_walkers(mol9j, W, 5), 2, 61)
+    r = ch.r
+    ref = per_walker_oracle(mol9j, r)
+    ctx = vmc.Context(mol9j, max_walkers=W, staging_walkers=4)
+    print("case: 9-atom J1/J3 measurement", flush=True)
+    out = ctx.measure(torch.tensor(r, device=dev))
+    torch.cuda.synchronize()
+    for k in ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "dlnjac_dR", "O", "G"):
+        close(out[k].cpu().numpy(), ref[k], what=k)
+    # displaced nuclei: the Jastrow functions move with them
+    R0 = np.array(mol9j.xyz)
+    R = R0 + 0.03 * np.random.default_rng(4).standard_normal(R0.shape)
+    ref = per_walker_oracle(mol9j, r[:4], R, R0)
+    out = ctx.measure(torch.tensor(r[:4], device=dev), R=torch.tensor(R, device=dev),
+                      R0=torch.tensor(R0, device=dev))
+    torch.cuda.synchronize()
+    for k in ref:
+        close(out[k].cpu().numpy(), ref[k], what=f"warped {k}")
+
+
+def test_measure_parity_21atom(dev):
+    """256 Jastrow functions: [xi3 | xi1] in five column blocks."""
+    from paper_2511_05222_amd import vmc
+    mol = inputs.with_body_jastrow(inputs.make_config(2).molecule, 9)
+    assert mol.jastrow.jas_basis.n_ao == 256
+    r = inputs.initial_walkers(mol, 2, 15)
+    ref = per_walker_oracle(mol, r)
+    ctx = vmc.Context(mol, max_walkers=2)
+    print("case: 21-atom J1/J3 measurement", flush=True)
+    out = ctx.measure(torch.tensor(r, device=dev))
+    torch.cuda.synchronize()
+    for k in ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G"):
+        close(out[k].cpu().numpy(), ref[k], what=k)
+
+
+def test_estimators(dev, mol9j):
+    from oracle import vmc as ovmc
+    from paper_2511_05222_amd import vmc
+    W, sweeps = 9, 3
+    w0 = inputs.initial_walkers(mol9j, W, 8)
+    ref = ovmc.run(mol9j, w0, sweeps, 79, block_sweeps=1)
+    ctx = vmc.Context(mol9j, max_walkers=W, staging_walkers=5)
+    tw = torch.tensor(w0, device=dev)
+    print("case: 9-atom J1/J3 estimators", flush=True)
+    ctx.sweep(tw, sweeps, 79)
+    res = ctx.accumulate()
+    close(res["E"], ref["E"], what="E")
+    close(res["F_bare"], ref["F_bare"], what="F_bare")
+    close(res["dE_dC"], ref["dE_dC"], what="dE_dC")
+    close(res["dEL_dC_mean"], ref["dEL_dC_mean"], what="dEL_dC_mean")
+
+
+def test_mixed_within_bounds(dev, mol9j):
+    from oracle import sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    W = 64
+    w0 = torch.tensor(inputs.initial_walkers(mol9j, W, 12), device=dev)
+    ctx64 = vmc.Context(mol9j, max_walkers=W)
+    ctx32 = vmc.Context(mol9j, max_walkers=W, precision="mixed")
+    w = w0.clone()
+    acc32 = torch.zeros((4, mol9j.n_elec, W), dtype=torch.uint8, device=dev)
+    acc64 = torch.zeros_like(acc32)
+    w64 = w0.clone()
+    print("case: 9-atom J1/J3 mixed", flush=True)
+    ctx32.sweep(w, 4, 88, measure=False, accept=acc32)
+    ctx64.sweep(w64, 4, 88, measure=False, accept=acc64)
+    torch.cuda.synchronize()
+    agree = (acc32 == acc64).float().mean().item()
+    assert agree >= 0.999, agree
+    o32 = ctx32.measure(w, outputs=("EL", "dEL_dR"))
+    o64 = ctx64.measure(w, outputs=("EL", "dEL_dR"))
+    dE = abs((o32["EL"] - o64["EL"]).mean().item())
+    assert dE < 1e-5, dE
