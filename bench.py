@@ -50,7 +50,7 @@ METRIC = "walker-steps/s (fwd+adjoint) mixed vs FP64 on 1 GPU; force err Ha/bohr
 PEAK_MFMA = {"mixed": 157.3, "fp64": 78.6}
 PEAK_ALU = 78.6
 PEAK_HBM = 8000.0
-KERNELS = {"sweep": "k_sweep_r", "proposals": "k_mo_rows_mfma (proposals)", "mo_rows": "k_mo_rows_mfma",
+KERNELS = {"sweep": "k_sweep_r", "proposals": "k_mo_rows_mfma_proposals", "mo_rows": "k_mo_rows_mfma",
            "dense": "k_dense", "adjoint": "k_adjoint_mfma"}
 KERNEL_SRCS = {
     "sweep": ("vmc_sweep.hip", "vmc_regs.hpp", "vmc_device.hpp", "vmc_pipeline.hpp"),
