@@ -27,6 +27,7 @@ inverse K, d ln det A = tr(K dA) and dK = -K dA K.
 """
 import numpy as np
 
+from . import ecp as ecp_mod
 from . import wavefunction as wf
 
 H_CS = 1e-30
@@ -80,14 +81,14 @@ def warp(R, R0, r):
     return rp, lnjac
 
 
-def warped_values(system, R, R0, r, C=None):
+def warped_values(system, R, R0, r, C=None, frame=None):
     """E_L, ln|Psi| and ln Jac of the warped configuration (real or complex R)."""
     rp, lnjac = warp(R, R0, r)
-    out = wf.evaluate(system, R, rp, C)
+    out = wf.evaluate(system, R, rp, C, frame=frame)
     return out["E_L"], out["lnpsi"], lnjac
 
 
-def nuclear_derivatives(system, R, R0, r, C=None):
+def nuclear_derivatives(system, R, R0, r, C=None, frame=None):
     """d/dR of (E_L, ln|Psi|, ln Jac) of warped configurations.
 
     Returns dE [W,A,3], dlnpsi [W,A,3], dlnjac [W,A,3] (complex step,
@@ -104,14 +105,14 @@ def nuclear_derivatives(system, R, R0, r, C=None):
         for k in range(3):
             Rc = R.astype(np.complex128)
             Rc[al, k] += 1j * H_CS
-            e, p, j = warped_values(system, Rc, R0, r, C)
+            e, p, j = warped_values(system, Rc, R0, r, C, frame)
             dE[:, al, k] = e.imag / H_CS
             dP[:, al, k] = p.imag / H_CS
             dJ[:, al, k] = np.asarray(j).imag / H_CS
     return dE, dP, dJ
 
 
-def coefficient_derivatives(system, R, r, C=None):
+def coefficient_derivatives(system, R, r, C=None, frame=None):
     """O = d ln|Psi| / dC and G = dE_L / dC per walker, each [W, M, n_occ].
 
     With K = A^-1 per spin (K[i,e]), b_e = sum_i K[i,e] grad phi_i(r_e),
@@ -123,7 +124,7 @@ def coefficient_derivatives(system, R, r, C=None):
       d ln|Psi|/dA[e,i]  =  K[i,e]
     and each MO matrix is AO matrix times C, so dX/dC = AO^T dX/d(MO).
     """
-    ev = wf.evaluate(system, R, r, C, keep=True)
+    ev = wf.evaluate(system, R, r, C, keep=True, frame=frame)
     W, N, _ = r.shape
     n_occ = system.C.shape[1]
     O = np.zeros((W, system.M, n_occ), dtype=ev["phi"].dtype)
@@ -139,15 +140,18 @@ def coefficient_derivatives(system, R, r, C=None):
         G[:, :, :n] += (np.einsum("wem,wei->wmi", ev["ao_val"][:, sl], Abar)
                         + np.einsum("wemk,weki->wmi", ev["ao_grad"][:, sl], Gbar)
                         + np.einsum("wem,wei->wmi", ev["ao_lap"][:, sl], Lbar))
+    if system.pp is not None:
+        G = G + ecp_mod.coefficient_terms(system, ev["ecp"], ev["Kinv"], ev["ao_val"], C)
     return O, G, ev
 
 
-def measure(system, R0, r, C=None):
+def measure(system, R0, r, C=None, frame=None):
     """All per-walker quantities of one measurement at the sampling geometry.
 
     Returns dict: E_L, lnpsi [W]; H, P [W,A,3] (SWCT force terms); O, G [W,M,n].
+    frame: (walker ids, rotation index) of a pseudopotential's quadrature.
     """
-    dE, dP, dJ = nuclear_derivatives(system, R0, R0, r, C)
-    O, G, ev = coefficient_derivatives(system, R0, r, C)
+    dE, dP, dJ = nuclear_derivatives(system, R0, R0, r, C, frame)
+    O, G, ev = coefficient_derivatives(system, R0, r, C, frame)
     return dict(E_L=ev["E_L"], lnpsi=ev["lnpsi"], H=dE, P=dP + 0.5 * dJ,
                 dlnpsi_dR=dP, dlnjac_dR=dJ, O=O, G=G)

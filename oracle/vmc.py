@@ -22,7 +22,7 @@ def run(mol, walkers, n_sweeps, seed, sweep_offset=0, walker_ids=None, step_sigm
     samples = []
 
     def meas(ch, sidx):
-        m = derivatives.measure(system, system.xyz, ch.r, C)
+        m = derivatives.measure(system, system.xyz, ch.r, C, frame=(ch.ids, sidx))
         acc.add(m)
         if keep_samples:
             samples.append(dict(m, r=ch.r.copy(), sweep=sidx))

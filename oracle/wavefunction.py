@@ -35,6 +35,7 @@ can be taken by the complex-step method (Squire & Trapp, SIAM Rev. 1998).
 """
 import numpy as np
 
+from . import ecp as ecp_mod
 from . import gto
 
 
@@ -61,6 +62,8 @@ class System:
         self.xi3 = None if jb is None else np.array(jas.xi3, dtype=np.float64)
         self.A = self.xyz.shape[0]
         self.M = self.table.n_ao
+        e = getattr(mol, "ecp", None)
+        self.pp = ecp_mod.Pseudo(e, self.A) if e is not None else None
         assert self.C.shape == (self.M, max(self.n_up, self.n_dn))
 
     def spin_blocks(self):
@@ -232,10 +235,12 @@ def potential(system, R, r):
 # local energy
 # --------------------------------------------------------------------------
 
-def evaluate(system, R, r, C=None, keep=False):
+def evaluate(system, R, r, C=None, keep=False, frame=None):
     """Per-walker E_L, log|Psi| and sign at nuclei R [A,3], electrons r [W,N,3].
 
     With keep=True the intermediates needed for derivatives are returned too.
+    With a pseudopotential, E_L includes its local and non-local parts
+    (ecp.py); frame = (walker ids, rotation index) of its quadrature.
     """
     r = np.asarray(r)
     W, N, _ = r.shape
@@ -259,8 +264,14 @@ def evaluate(system, R, r, C=None, keep=False):
     kin_e = lapD + 2.0 * np.sum(b * g, axis=-1) + h + np.sum(g * g, axis=-1)
     E_kin = -0.5 * kin_e.sum(axis=1)
     V = potential(system, R, r)
-    out = dict(E_L=E_kin + V, lnpsi=logdet + J, sign=sign)
+    E_L = E_kin + V
+    t = None
+    if system.pp is not None:
+        t = ecp_mod.terms(system, R, r, C, Kinv, frame)
+        E_L = E_L + t["E_loc"] + t["E_nl"]
+    out = dict(E_L=E_L, lnpsi=logdet + J, sign=sign)
     if keep:
+        out["ecp"] = t
         out.update(mo)
         out.update(Kinv=Kinv, b=b, lapD=lapD, g=g, h=h, J=J, V=V)
     return out

@@ -24,7 +24,10 @@ Workload recipe (synthetic stand-ins for the paper's rMD17 molecules, Sec. IV):
     uncontracted cartesian primitives, [3s1p] on H and [4s2p1d] on C and O
     (the paper's basis sizes), exponents log-uniform in [0.2, 4] sorted
     descending, and seeded parameters xi1 ~ N(0, s1^2), xi3 = (G + G^T) / 2
-    with G ~ N(0, s3^2).
+    with G ~ N(0, s3^2);
+  * pseudopotential (with_ecp): a seeded semilocal potential on C and O
+    (local part and l = 0, 1 projectors of Gaussian radial terms), the two
+    core electrons of each removed.
 """
 from __future__ import annotations
 
@@ -95,16 +98,35 @@ class Jastrow:
 
 
 @dataclass
+class Ecp:
+    """Semilocal pseudopotential: one radial term per entry,
+    beta r^(n - 2) exp(-alpha r^2) on nucleus atom[t] in channel l[t]
+    (-1 = the local part, l >= 0 the projector on angular momentum l);
+    rcut[A] bohr: the non-local channels of nucleus a act on electrons
+    closer than rcut[a] (0: none); rot_seed keys the random orientation of
+    the quadrature on the sphere."""
+
+    term_atom: np.ndarray
+    term_l: np.ndarray
+    term_n: np.ndarray
+    term_exp: np.ndarray
+    term_coef: np.ndarray
+    rcut: np.ndarray
+    rot_seed: int = 0
+
+
+@dataclass
 class Molecule:
     name: str
     symbols: list
     xyz: np.ndarray          # [A][3] bohr
-    Z: np.ndarray            # [A]
+    Z: np.ndarray            # [A] (effective charges with a pseudopotential)
     basis: Basis
     C_full: np.ndarray       # [M][M]; first n_occ columns occupied
     n_up: int
     n_dn: int
     jastrow: Jastrow = field(default_factory=Jastrow)
+    ecp: "Ecp | None" = None
 
     @property
     def n_elec(self) -> int:
@@ -331,6 +353,66 @@ def with_body_jastrow(mol: Molecule, seed: int, s1: float = 0.05, s3: float = 0.
     xi3 = 0.5 * (G + G.T)
     jas = dataclasses.replace(mol.jastrow, jas_basis=jb, xi1=xi1, xi3=xi3)
     return dataclasses.replace(mol, jastrow=jas, name=mol.name + " +J1J3")
+
+
+ECP_CORE = {"C": 2, "O": 2}   # core electrons a pseudopotential removes
+
+
+def _ecp_radial(r, n, alpha, beta):
+    return sum(b * r ** (k - 2) * np.exp(-a * r * r) for k, a, b in zip(n, alpha, beta))
+
+
+def with_ecp(mol: Molecule, seed: int, tail: float = 1e-12) -> Molecule:
+    """A valence-only copy of mol with a seeded semilocal pseudopotential on
+    its C and O atoms (synthetic stand-in for the paper's ccECP, whose
+    parameters are not available here).  Each such atom loses ECP_CORE
+    electrons (its charge becomes Z_eff = Z - core; one electron of each spin
+    per atom); the MO coefficients keep their first n_occ columns.  Per
+    element, with exponents log-uniform in the ranges given:
+      local   Z_eff r^-1 e^{-a1 r^2} (cancels -Z_eff/r at the nucleus),
+              b2 e^{-a2 r^2},  a1 in [3, 8], a2 in [1.5, 4], b2 ~ U(-2, 2);
+      l = 0   b e^{-a r^2}, a in [2, 5], b ~ U(4, 12);
+      l = 1   b e^{-a r^2}, a in [2, 5], b ~ U(-6, 6).
+    rcut: the radius beyond which every non-local channel of the atom stays
+    below `tail` hartree."""
+    import dataclasses
+    rng = np.random.Generator(np.random.PCG64(seed))
+    par = {}
+    for el in sorted(ECP_CORE):
+        zeff = Z_OF[el] - ECP_CORE[el]
+        lu = lambda lo, hi: float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        a1, a2, b2 = lu(3.0, 8.0), lu(1.5, 4.0), float(rng.uniform(-2.0, 2.0))
+        s_a, s_b = lu(2.0, 5.0), float(rng.uniform(4.0, 12.0))
+        p_a, p_b = lu(2.0, 5.0), float(rng.uniform(-6.0, 6.0))
+        terms = [(-1, 1, a1, float(zeff)), (-1, 2, a2, b2), (0, 2, s_a, s_b), (1, 2, p_a, p_b)]
+        rg = np.arange(0.0, 20.0, 1e-3)
+        v = np.zeros_like(rg)
+        for l, n, a, b in terms:
+            if l >= 0:
+                v = np.maximum(v, np.abs(_ecp_radial(rg, [n], [a], [b])))
+        rc = float(rg[np.nonzero(v > tail)[0][-1] + 1])
+        par[el] = (terms, rc)
+    ta, tl, tn, te, tc = [], [], [], [], []
+    Z = np.array(mol.Z, dtype=np.float64).copy()
+    rcut = np.zeros(len(mol.symbols))
+    removed = 0
+    for a, sym in enumerate(mol.symbols):
+        if sym not in par:
+            continue
+        terms, rc = par[sym]
+        for l, n, ex, b in terms:
+            ta.append(a)
+            tl.append(l)
+            tn.append(n)
+            te.append(ex)
+            tc.append(b)
+        rcut[a] = rc
+        Z[a] -= ECP_CORE[sym]
+        removed += ECP_CORE[sym]
+    ecp = Ecp(np.array(ta, np.int32), np.array(tl, np.int32), np.array(tn, np.int32), np.array(te),
+              np.array(tc), rcut, rot_seed=seed + 17)
+    return dataclasses.replace(mol, Z=Z, n_up=mol.n_up - removed // 2, n_dn=mol.n_dn - removed // 2, ecp=ecp,
+                               name=mol.name + " +ECP")
 
 
 @lru_cache(maxsize=None)

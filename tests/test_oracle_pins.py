@@ -594,3 +594,104 @@ def test_resume_and_subsets(mol9):
     assert np.array_equal(bits, np.concatenate([bits_a, bits_b]))
     ch_s, bits_s = sampler.run(s, w[3:6], 4, 9, walker_ids=np.arange(3, 6))
     assert np.array_equal(ch_s.r, ch.r[3:6])
+
+
+# Pseudopotential (oracle/ecp.py).  The projector of channel l picks the
+# angular-momentum-l part of the wavefunction on the electron's sphere: with a
+# single electron in a pure s, p or d function centred on the nucleus, the
+# non-local energy is exactly V_l(d) of that function's l (the 12-point rule
+# integrates the degree <= 4 integrands exactly, in any orientation), and the
+# other channels give 0.
+def _one_electron_ecp(l_fn, comp):
+    nc = {0: 1, 1: 3, 2: 6}[l_fn]
+    b = inputs.Basis(np.array([0], np.int32), np.array([l_fn], np.int32), np.array([1], np.int32),
+                     np.array([0.8]), np.array([1.0]))
+    Cf = np.eye(nc)[:, [comp] + [k for k in range(nc) if k != comp]]
+    e = inputs.Ecp(np.array([0, 0, 0, 0], np.int32), np.array([-1, 0, 1, 2], np.int32),
+                   np.array([1, 2, 2, 2], np.int32), np.array([2.0, 1.1, 0.9, 1.3]),
+                   np.array([3.0, 2.0, -1.5, 0.7]), np.array([10.0]), rot_seed=5)
+    return inputs.Molecule("one", ["C"], np.zeros((1, 3)), np.array([4.0]), b, Cf, 1, 0, ecp=e)
+
+
+def test_ecp_projectors_are_exact():
+    r = np.array([[[0.3, 0.4, -0.2]]])
+    d = np.sqrt(0.29)
+    V = {0: 2.0 * np.exp(-1.1 * d * d), 1: -1.5 * np.exp(-0.9 * d * d), 2: 0.7 * np.exp(-1.3 * d * d)}
+    for l_fn, comp in ((0, 0), (1, 0), (1, 2), (2, 1), (2, 4)):
+        if l_fn == 2 and comp in (0, 3, 5):
+            continue   # xx, yy, zz carry an s part
+        s = wf.System(_one_electron_ecp(l_fn, comp))
+        for frame in ((np.array([0], np.uint64), 0), (np.array([7], np.uint64), 3)):
+            ev = wf.evaluate(s, s.xyz, r, keep=True, frame=frame)
+            assert abs(ev["ecp"]["E_nl"][0] - V[l_fn]) < 1e-14, (l_fn, comp, ev["ecp"]["E_nl"][0], V[l_fn])
+            assert abs(ev["ecp"]["E_loc"][0] - 3.0 / d * np.exp(-2.0 * d * d)) < 1e-13
+
+
+def test_ecp_ratio_is_wavefunction_ratio(mol9):
+    import dataclasses
+    m = inputs.with_ecp(mol9, 5)
+    s = wf.System(m)
+    plain = wf.System(dataclasses.replace(m, ecp=None))
+    r = inputs.initial_walkers(m, 2, 4)
+    ev = wf.evaluate(s, s.xyz, r, keep=True)
+    base = wf.evaluate(plain, s.xyz, r)
+    checked = 0
+    for a, p in ev["ecp"]["atoms"].items():
+        for w, e in ((w, e) for w in range(2) for e in range(0, s.N, 3)):
+            q = (5 * e + w) % 12
+            if p["mask"][w, e] == 0:
+                continue
+            rm = r[w:w + 1].copy()
+            rm[0, e] = p["pts"][w, e, q]
+            mv = wf.evaluate(plain, s.xyz, rm)
+            exact = mv["sign"][0] * base["sign"][w] * np.exp(mv["lnpsi"][0] - base["lnpsi"][w])
+            got = p["ratio"][w, e, q] * p["jratio"][w, e, q]
+            assert abs(got - exact) < 1e-11 * max(1.0, abs(exact)), (a, w, e, q, got, exact)
+            # the point lies on the electron's sphere around the nucleus
+            assert abs(np.linalg.norm(p["pts"][w, e, q] - s.xyz[a]) - np.linalg.norm(r[w, e] - s.xyz[a])) < 1e-13
+            checked += 1
+    assert checked >= 8
+
+
+def test_ecp_rotations_and_rule():
+    from oracle import ecp
+    v = ecp.icosahedron()
+    assert np.allclose(np.linalg.norm(v, axis=1), 1.0) and np.allclose(v.sum(0), 0.0)
+    # the rule integrates x^2 and x^4 exactly over the unit sphere (1/3, 1/5)
+    assert abs(np.mean(v[:, 0] ** 2) - 1 / 3) < 1e-15 and abs(np.mean(v[:, 0] ** 4) - 1 / 5) < 1e-15
+    Rm = ecp.rotations(11, np.arange(4096, dtype=np.uint64), 2, 1)[:, 0]
+    assert np.allclose(np.einsum("wki,wkj->wij", Rm, Rm), np.eye(3), atol=1e-14)
+    assert np.allclose(np.linalg.det(Rm), 1.0)
+    # uniform over rotations: E[R] = 0, E[R_ij^2] = 1/3
+    assert np.abs(Rm.mean(0)).max() < 0.04 and np.abs((Rm ** 2).mean(0) - 1 / 3).max() < 0.03
+
+
+def test_ecp_estimators_are_fixed_sample_derivatives(mol9):
+    m = inputs.with_ecp(mol9, 5)
+    s = wf.System(m)
+    ch, _ = sampler.run(s, inputs.initial_walkers(m, 6, 3), 3, 3)
+    r, R0 = ch.r, s.xyz
+    meas = dv.measure(s, R0, r)
+    acc = estimators.Accumulator(s.A, s.M, s.C.shape[1])
+    acc.add(meas)
+    res = acc.result()
+    lnpsi0 = meas["lnpsi"]
+    h = 1e-4
+    for al, k in [(0, 0), (2, 1), (5, 2)]:
+        Rp = R0.copy(); Rp[al, k] += h
+        Rm = R0.copy(); Rm[al, k] -= h
+        fd = (_ehat(s, Rp, R0, r, lnpsi0) - _ehat(s, Rm, R0, r, lnpsi0)) / (2 * h)
+        assert abs(fd + res["F_bare"][al, k]) < 1e-6 * max(1.0, abs(fd)), (al, k, fd, res["F_bare"][al, k])
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        mu, i = int(rng.integers(s.M)), int(rng.integers(s.C.shape[1]))
+        Cp = s.C.copy(); Cp[mu, i] += h
+        Cm = s.C.copy(); Cm[mu, i] -= h
+        fd = (_ehat(s, R0, R0, r, lnpsi0, Cp) - _ehat(s, R0, R0, r, lnpsi0, Cm)) / (2 * h)
+        an = res["dE_dC"][mu, i] + res["dEL_dC_mean"][mu, i]
+        assert abs(fd - an) < 1e-6 * max(1.0, abs(fd)), (mu, i, fd, an)
+    # per walker: the C derivative against the complex step
+    O, G, _ = dv.coefficient_derivatives(s, R0, r)
+    V = rng.standard_normal(s.C.shape)
+    ev = wf.evaluate(s, R0, r, s.C + 1e-30j * V)
+    assert np.allclose(ev["E_L"].imag / 1e-30, np.einsum("wmi,mi->w", G, V), rtol=1e-9, atol=1e-8)
