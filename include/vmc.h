@@ -54,6 +54,7 @@ extern "C" {
 #define VMC_ESINGULAR   -4   /* a Slater block singular to working precision    */
 #define VMC_ENOTCONV    -5   /* iterative solver hit maxit                      */
 #define VMC_ENONFINITE  -6   /* non-finite value in an input or a result        */
+#define VMC_ECAPACITY   -7   /* a per-walker capacity was exceeded              */
 
 /* ---- precision modes ------------------------------------------------------ */
 #define VMC_FP64   0         /* every step in FP64                              */
@@ -140,6 +141,45 @@ typedef struct {
     const double *xi3;
 } vmc_jastrow;
 
+/* Semilocal pseudopotential (the paper's VMC uses ccECP pseudopotentials,
+ * Sec. III and Sec. IV "computational details"; the paper does not restate
+ * their form, so the standard semilocal one is taken: Mitas, Shirley and
+ * Ceperley, J. Chem. Phys. 95, 3467 (1991)).  On nucleus a, for an electron
+ * at distance d = |r_i - R_a| with direction u_i:
+ *   V_loc(d) + sum_l V_l(d) sum_m |l m><l m|,
+ *   V(d) = sum_t term_coef[t] d^(term_n[t] - 2) exp(-term_exp[t] d^2)
+ * over the terms t of the channel (term_l[t] = -1: the local part; 0 ..
+ * VMC_MAX_ECP_L: the projector on l).  The projectors enter E_L as
+ *   sum_l V_l(d) (2l + 1) sum_q (1/12) P_l(u_i . v_q) Psi(.., R_a + d v_q, ..) / Psi
+ * over the 12 vertices v_q of an icosahedron, turned by one random rotation
+ * per (walker, electron): Shoemake's unit quaternion from the first three
+ * 32-bit words (u = w 2^-32) of Philox4x32-10 with key rot_seed and counter
+ * (walker id, rotation index, electron | 2 << 16, 0); the rotation index is
+ * the sweep index for the measurement after each sweep of vmc_sweep and 0
+ * for every other call; the walker id is the row of the positions passed.
+ * Only electrons with d < rcut[a] see the projectors of nucleus a; the local
+ * part acts at every distance.  The charges of vmc_nuclei are the effective
+ * ones (the removed core's charge subtracted).
+ * term_n in 1..4, term_exp > 0; rcut[n_atoms] >= 0 (host arrays, copied).
+ * max_pairs: per walker, the most (electron, nucleus) pairs inside the
+ * cutoffs a measurement can hold (0 = N times the number of nuclei with a
+ * projector, which cannot overflow); a walker with more reports
+ * VMC_ECAPACITY at vmc_accumulate.  Not combined with the one-/three-body
+ * Jastrow terms. */
+#define VMC_MAX_ECP_L      3
+#define VMC_MAX_ECP_TERMS  256
+typedef struct {
+    int32_t n_terms;
+    const int32_t *term_atom;
+    const int32_t *term_l;
+    const int32_t *term_n;
+    const double  *term_exp;
+    const double  *term_coef;
+    const double  *rcut;
+    uint64_t rot_seed;
+    int32_t max_pairs;
+} vmc_ecp;
+
 /* Run options.
  * precision      : VMC_FP64 or VMC_MIXED
  * refresh_period : each spin block's inverse (kept in device memory between
@@ -177,7 +217,9 @@ typedef struct {
  *                  |ratio| below this value rebuilds its block's inverse
  *                  before the block's next move (the Sherman-Morrison update
  *                  divides by the ratio); 0 selects the default 1e-8, larger
- *                  values force more rebuilds (>= 0, finite). */
+ *                  values force more rebuilds (>= 0, finite).
+ * ecp            : a semilocal pseudopotential in E_L (NULL = none; see
+ *                  vmc_ecp). */
 typedef struct {
     int32_t precision;
     int32_t refresh_period;
@@ -188,6 +230,7 @@ typedef struct {
     double  promote_fraction;
     int32_t jackknife_blocks;
     double  forced_refresh_ratio;
+    const vmc_ecp *ecp;
 } vmc_options;
 
 /* Per-walker outputs of one measurement (device arrays, any may be NULL).
@@ -255,7 +298,9 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
  * block's largest orbital value: e.g. two same-spin electrons at one point,
  * or an electron where every orbital vanishes); otherwise
  * VMC_ENONFINITE if a measured E_L, ln|Psi| or log|det| was not finite (e.g.
- * a walker with a NaN coordinate).  On these two errors the outputs are
+ * a walker with a NaN coordinate); otherwise VMC_ECAPACITY if a measured
+ * walker had more pseudopotential pairs than vmc_ecp.max_pairs (its pairs
+ * beyond the capacity were left out).  On these errors the outputs are
  * still written (they include the offending samples) and VMC_ACCUM_RESET
  * still clears the accumulators and the error state. */
 int vmc_accumulate(vmc_ctx *ctx, double *E, double *F_bare, double *dE_dC,

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvmcx.so")
-SOURCES = ["vmc_abi.hip", "vmc_pipeline.hip", "vmc_mo.hip", "vmc_adjoint.hip", "vmc_dense.hip", "vmc_sweep.hip", "vmc_reduce.hip", "vmc_jastrow.hip"]
+SOURCES = ["vmc_abi.hip", "vmc_pipeline.hip", "vmc_mo.hip", "vmc_adjoint.hip", "vmc_dense.hip", "vmc_sweep.hip", "vmc_reduce.hip", "vmc_jastrow.hip", "vmc_ecp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -77,6 +77,17 @@ struct vmc_ctx {
     // ([chunk][N] rows); element sizes of the arithmetic type
     void *js_Xp = nullptr, *js_X0 = nullptr, *js_Pp = nullptr, *js_T0 = nullptr;
     double *jm_X = nullptr, *jm_O = nullptr, *jm_g = nullptr, *jm_u = nullptr, *jm_tao = nullptr;
+    // semilocal pseudopotential (has_ecp false: none): device tables, the
+    // staging of one measurement launch (EcpBufs) and the frame of its
+    // quadrature rotations for the next measurement: walker id of the
+    // launch's first walker (or of the listed walkers) and rotation index
+    bool has_ecp = false;
+    vmcx::EcpDev edev{};
+    int *e_pairs = nullptr, *e_npairs = nullptr;
+    double *e_qpos = nullptr, *e_phiq = nullptr, *e_rows = nullptr, *e_dR = nullptr;
+    int64_t ecp_id0 = 0;
+    uint32_t ecp_rot = 0;
+    const int *ecp_idlist = nullptr;
     SysDev sys{};
     SweepLayout swl{};   // k_sweep_r in the arithmetic type of the precision
     DenseLayout dl{};
@@ -299,12 +310,23 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
                         bool prof, const KStateRef &ks, hipStream_t st) {
     const SysDev &S = c->sys;
     T *phi = (T *)c->mb_phi;
-    MeasBufs<T> mb{pos,         pos0,       phi,       full ? (T *)c->mb_ktil : nullptr, (T *)c->mb_abar, c->mb_gb,
-                   c->mb_dpart, c->mb_tao, pkey,      (const T *)ks.K,                  ks.sig,
+    MeasBufs<T> mb{pos,         pos0,       phi,       (full || c->has_ecp) ? (T *)c->mb_ktil : nullptr,
+                   (T *)c->mb_abar, c->mb_gb,   c->mb_dpart, c->mb_tao,
+                   pkey,      (const T *)ks.K,                  ks.sig,
                    ks.stale};
     int pi = prof_begin(c, VMC_K_MO_ROWS, prof, cw, st);
     HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, pos, cw * c->N, c->tiles16, phi, 5, (T *)c->d_cpad, st));
     prof_end(c, VMC_K_MO_ROWS, pi, st);
+    // pseudopotential: the pairs inside the cutoffs, their points and the
+    // MO rows there (values; with the adjoint also gradients)
+    const vmcx::EcpBufs<T> eb{c->e_pairs, c->e_npairs, c->e_qpos, (T *)c->e_phiq, c->e_rows, c->e_dR};
+    const int enc = full ? 5 : 1;
+    if (c->has_ecp) {
+        HIP_OK(c, vmcx::launch_ecp_pairs(S, c->edev, R, pos, (int)cw, c->ecp_id0, c->ecp_idlist, c->ecp_rot,
+                                         c->e_pairs, c->e_npairs, c->e_qpos, c->status, st));
+        HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, c->e_qpos, cw * c->edev.pcap * 12, c->tiles16,
+                                               (T *)c->e_phiq, enc, (T *)c->d_cpad, st));
+    }
     const int64_t jrows = cw * c->N;
     T *jX = (T *)c->jm_X, *jO = (T *)c->jm_O;
     if (c->MJ > 0) {
@@ -320,11 +342,19 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     pi = prof_begin(c, VMC_K_DENSE, prof, cw, st);
     HIP_OK(c, vmcx::launch_dense<T>(S, R, mb, o, c->status, c->dl, (int)cw, st));
     prof_end(c, VMC_K_DENSE, pi, st);
+    if (c->has_ecp)
+        HIP_OK(c, vmcx::launch_ecp_energy<T>(S, c->edev, R, pos, (int)cw, eb, enc, mb.ktil, full ? mb.abar : nullptr,
+                                             o.EL, c->status, st));
     if (!full) return VMC_OK;
     pi = prof_begin(c, VMC_K_ADJOINT, prof, cw, st);
     HIP_OK(c, vmcx::launch_adjoint<T>(S, C, R, mb, o, al, (int)cw, st));
     prof_end(c, VMC_K_ADJOINT, pi, st);
     MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
+    if (c->has_ecp) {
+        HIP_OK(c, vmcx::launch_ecp_adjoint<T>(S, c->edev, C, R, pos, (int)cw, eb, mb.ktil, o.G, o.Gf, c->mb_dpart,
+                                              st));
+        md.ecp_dR = c->e_dR;
+    }
     if (c->MJ > 0) {
         HIP_OK(c, vmcx::launch_jas_adjoint<T>(c->jdev, R, c->N, c->nq, jrows, 0, (int)cw, pos, jX, jO, c->mb_gb,
                                               c->d_xi1, c->mb_dpart, c->jm_tao, st));
@@ -377,9 +407,11 @@ static int run_measure(vmc_ctx *c, const double *pos0, int64_t cw, const double 
                      o.dEL_dR ? c->cp_dEdR : nullptr, o.dlnpsi_dR ? c->cp_dPdR : nullptr,
                      o.dlnjac_dR ? c->cp_dJdR : nullptr, (o.O || o.Of) ? c->cp_O : nullptr,
                      (o.G || o.Gf) ? c->cp_G : nullptr};
-        if ((rc = measure_core<double>(c, c->cp_pos, c->cp_pos0, kc, C, R, R0, warp, full, oc, c->al64, nullptr,
-                                       false, KStateRef(), st)))
-            return rc;
+        c->ecp_idlist = lst;
+        rc = measure_core<double>(c, c->cp_pos, c->cp_pos0, kc, C, R, R0, warp, full, oc, c->al64, nullptr, false,
+                                  KStateRef(), st);
+        c->ecp_idlist = nullptr;
+        if (rc) return rc;
         const std::pair<double *, double *> rows[] = {{oc.EL, o.EL},         {oc.lnpsi, o.lnpsi},
                                                       {oc.dEL_dR, o.dEL_dR}, {oc.dlnpsi_dR, o.dlnpsi_dR},
                                                       {oc.dlnjac_dR, o.dlnjac_dR}, {oc.O, o.O},
@@ -470,6 +502,7 @@ static int measure_accumulate(vmc_ctx *c, const double *walkers, int64_t W, cons
             ks.sig = c->Ksig + (size_t)c0 * 2 * kn;
             ks.stale = c->Kstale + 2 * c0;
         }
+        c->ecp_id0 = c0;
         if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, c->d_C, c->d_R, c->d_R, 0, 1, o, st, ks))) return rc;
         HIP_OK(c, vmcx::launch_set_shift(c->st_EL, cw, c->shift, c->shift_set, st));
         EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, c->shift,
@@ -641,6 +674,78 @@ static int check_basis(vmc_ctx *c, const vmc_basis *basis, int A, const char *wh
 // The one- and three/four-body Jastrow: its basis tables and [xi3 | xi1] in
 // column blocks of 64 (block q holds columns 64 q .. 64 q + 63 of the
 // MJ x (MJ + 1) matrix whose last column is xi1), FP64 and FP32.
+// Pseudopotential: validation (host only), then the terms sorted by nucleus
+// and uploaded (the staging is sized with the rest of the measurement's).
+static int check_ecp(vmc_ctx *c, const vmc_ecp *e, int A) {
+    const int T = e->n_terms;
+    if (T < 1 || T > VMC_MAX_ECP_TERMS || !e->term_atom || !e->term_l || !e->term_n || !e->term_exp ||
+        !e->term_coef || !e->rcut || e->max_pairs < 0)
+        return c->fail(VMC_EINVAL, "pseudopotential: bad counts or missing arrays (%d terms)", T);
+    if (c->MJ > 0) return c->fail(VMC_EINVAL, "a pseudopotential with the one-/three-body Jastrow is not supported");
+    for (int t = 0; t < T; ++t) {
+        const int a = e->term_atom[t], l = e->term_l[t], n = e->term_n[t];
+        if (a < 0 || a >= A || l < -1 || l > VMC_MAX_ECP_L || n < 1 || n > 4 || !(e->term_exp[t] > 0.0) ||
+            !std::isfinite(e->term_exp[t]) || !std::isfinite(e->term_coef[t]))
+            return c->fail(VMC_EINVAL, "pseudopotential term %d: nucleus %d, l %d, n %d, exponent %g", t, a, l, n,
+                           e->term_exp[t]);
+    }
+    for (int a = 0; a < A; ++a)
+        if (!(e->rcut[a] >= 0.0) || !std::isfinite(e->rcut[a]))
+            return c->fail(VMC_EINVAL, "pseudopotential: bad cutoff %g of nucleus %d", e->rcut[a], a);
+    return VMC_OK;
+}
+
+static int setup_ecp(vmc_ctx *c, const vmc_ecp *e, int A) {
+    const int T = e->n_terms;
+    int lmax = -1;
+    for (int t = 0; t < T; ++t) lmax = std::max(lmax, (int)e->term_l[t]);
+    std::vector<int> t0(A + 1, 0), tl, tn, nl;
+    std::vector<double> ta, tb;
+    for (int a = 0; a < A; ++a) {
+        t0[a] = (int)tl.size();
+        bool proj = false;
+        for (int t = 0; t < T; ++t)
+            if (e->term_atom[t] == a) {
+                tl.push_back(e->term_l[t]);
+                tn.push_back(e->term_n[t]);
+                ta.push_back(e->term_exp[t]);
+                tb.push_back(e->term_coef[t]);
+                proj = proj || e->term_l[t] >= 0;
+            }
+        if (proj && e->rcut[a] > 0.0) nl.push_back(a);
+    }
+    t0[A] = (int)tl.size();
+    if (nl.empty()) nl.push_back(0);   // (a valid pointer; n_nl below stays exact)
+    vmcx::EcpDev &E = c->edev;
+    int rc;
+    int *d_t0 = nullptr, *d_tl = nullptr, *d_tn = nullptr, *d_nl = nullptr;
+    double *d_ta = nullptr, *d_tb = nullptr, *d_rc = nullptr;
+    if ((rc = c->upload(&d_t0, t0.data(), t0.size())) || (rc = c->upload(&d_tl, tl.data(), tl.size())) ||
+        (rc = c->upload(&d_tn, tn.data(), tn.size())) || (rc = c->upload(&d_ta, ta.data(), ta.size())) ||
+        (rc = c->upload(&d_tb, tb.data(), tb.size())) || (rc = c->upload(&d_rc, e->rcut, (size_t)A)) ||
+        (rc = c->upload(&d_nl, nl.data(), nl.size())))
+        return rc;
+    int n_nl = 0;
+    for (int a = 0; a < A; ++a) {
+        bool proj = false;
+        for (int t = 0; t < T; ++t) proj = proj || (e->term_atom[t] == a && e->term_l[t] >= 0);
+        n_nl += (proj && e->rcut[a] > 0.0) ? 1 : 0;
+    }
+    E.n_nl = n_nl;
+    E.nl_atom = d_nl;
+    E.t0 = d_t0;
+    E.t_l = d_tl;
+    E.t_n = d_tn;
+    E.t_alpha = d_ta;
+    E.t_beta = d_tb;
+    E.rcut = d_rc;
+    E.lmax = lmax;
+    E.seed = e->rot_seed;
+    E.pcap = e->max_pairs > 0 ? e->max_pairs : std::max(1, c->N * n_nl);
+    c->has_ecp = true;
+    return VMC_OK;
+}
+
 static int setup_body_jastrow(vmc_ctx *c, const vmc_jastrow *jas, int A) {
     int rc;
     if ((rc = upload_basis(c, jas->jas_basis, A, c->jdev, c->jtiles16))) return rc;
@@ -683,6 +788,7 @@ const char *vmc_strerror(int s) {
         case VMC_ESINGULAR: return "VMC_ESINGULAR";
         case VMC_ENOTCONV: return "VMC_ENOTCONV";
         case VMC_ENONFINITE: return "VMC_ENONFINITE";
+        case VMC_ECAPACITY: return "VMC_ECAPACITY";
         default: return "VMC_UNKNOWN";
     }
 }
@@ -757,6 +863,10 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         !(opt->step_sigma > 0.0) || !std::isfinite(opt->step_sigma) || !(opt->promote_fraction >= 0.0 && opt->promote_fraction <= 1.0) || opt->jackknife_blocks < 0 ||
         !(opt->forced_refresh_ratio >= 0.0) || !std::isfinite(opt->forced_refresh_ratio))
         return bail(c->fail(VMC_EINVAL, "bad options"));
+    if (opt->ecp) {
+        const int rc0 = check_ecp(c, opt->ecp, A);
+        if (rc0) return bail(rc0);
+    }
     double Zsum = 0.0;
     for (int a = 0; a < A; ++a) Zsum += nuclei->Z[a];
     c->N = mo->n_up + mo->n_dn;
@@ -787,6 +897,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     }
     if ((rc = c->dalloc(&c->d_cpad, (size_t)(std::max(M, c->MJ) + 16) * 64))) return bail(rc);
     if (c->MJ > 0 && (rc = setup_body_jastrow(c, jas, A))) return bail(rc);
+    if (opt->ecp && (rc = setup_ecp(c, opt->ecp, A))) return bail(rc);
 
     SysDev &sd = c->sys;
     sd.N = c->N;
@@ -824,14 +935,16 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     bool cfg_ok;
     {
         static std::mutex mu;
-        static size_t lim[6] = {0, 0, 0, 0, 0, 0};
+        static size_t lim[7] = {0, 0, 0, 0, 0, 0, 0};
         std::lock_guard<std::mutex> lock(mu);
-        const size_t need[6] = {c->dl.bytes, sweep_layout(c, sizeof(double)).bytes, c->al64.bytes,
-                                c->dl.bytes, c->swl.bytes, c->al.bytes};
-        for (int q = 0; q < 6; ++q) lim[q] = std::max(lim[q], need[q]);
+        const size_t need[7] = {c->dl.bytes, sweep_layout(c, sizeof(double)).bytes, c->al64.bytes,
+                                c->dl.bytes, c->swl.bytes, c->al.bytes,
+                                c->has_ecp ? vmcx::ecp_energy_lds(c->N, c->n_occ) : 0};
+        for (int q = 0; q < 7; ++q) lim[q] = std::max(lim[q], need[q]);
         cfg_ok = vmcx::configure_dense<double>(lim[0]) == hipSuccess &&
                  vmcx::configure_sweep<double>(lim[1]) == hipSuccess &&
-                 vmcx::configure_adjoint<double>(lim[2]) == hipSuccess;
+                 vmcx::configure_adjoint<double>(lim[2]) == hipSuccess &&
+                 (lim[6] == 0 || vmcx::configure_ecp(lim[6]) == hipSuccess);
         if (mixed)
             cfg_ok = cfg_ok && vmcx::configure_dense<float>(lim[3]) == hipSuccess &&
                      vmcx::configure_sweep<float>(lim[4]) == hipSuccess &&
@@ -849,8 +962,12 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     const int64_t jas_pw = c->MJ > 0 ? (int64_t)c->N * c->MJ + (int64_t)c->nq * c->N * 5 * 64 + 4 * (int64_t)c->N +
                                            1 + 6 * (int64_t)c->MJ
                                      : 0;
+    // (with a pseudopotential: its pairs, points, the MO rows and values kept
+    // per point, and the per-nucleus derivative)
+    const int64_t eq = c->has_ecp ? (int64_t)c->edev.pcap * 12 : 0;
+    const int64_t ecp_pw = c->has_ecp ? eq * (3 + 5 * (int64_t)c->n_occ + vmcx::ECP_ROW) + A3 + c->edev.pcap + 1 : 0;
     const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
-                                                        3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw);
+                                                        3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw + ecp_pw);
     int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, opt->max_walkers));
     if (opt->staging_walkers > 0) chunk = std::min<int64_t>(chunk, opt->staging_walkers);
@@ -884,6 +1001,14 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
             (rc = c->dalloc(&c->jm_O, (size_t)c->nq * chunk * c->N * 5 * 64)) ||
             (rc = c->dalloc(&c->jm_g, (size_t)chunk * c->N * 4)) || (rc = c->dalloc(&c->jm_u, (size_t)chunk)) ||
             (rc = c->dalloc(&c->jm_tao, (size_t)chunk * c->MJ * 6)))
+            return bail(rc);
+    }
+    if (c->has_ecp) {
+        if ((rc = c->dalloc(&c->e_pairs, (size_t)chunk * c->edev.pcap)) ||
+            (rc = c->dalloc(&c->e_npairs, (size_t)chunk)) || (rc = c->dalloc(&c->e_qpos, (size_t)chunk * eq * 3)) ||
+            (rc = c->dalloc(&c->e_phiq, (size_t)chunk * eq * 5 * c->n_occ)) ||
+            (rc = c->dalloc(&c->e_rows, (size_t)chunk * eq * vmcx::ECP_ROW)) ||
+            (rc = c->dalloc(&c->e_dR, (size_t)chunk * A3)))
             return bail(rc);
     }
     if (opt->precision == VMC_MIXED && opt->promote_fraction > 0.0) {
@@ -940,7 +1065,10 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
                       : sweep_once<double>(c, walkers, W, t, sidx, seed, acc_t, c->d_C, st)))
             return rc;
         if (!(flags & VMC_SWEEP_MEASURE)) continue;
-        if ((rc = measure_accumulate(c, walkers, W, nullptr, true, st))) return rc;
+        c->ecp_rot = sidx;
+        rc = measure_accumulate(c, walkers, W, nullptr, true, st);
+        c->ecp_rot = 0;
+        if (rc) return rc;
     }
     return VMC_OK;
 }
@@ -1016,6 +1144,8 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
     }
     if (status & vmcx::STATUS_SINGULAR) return c->fail(VMC_ESINGULAR, "a Slater block was singular to working precision");
     if (status & vmcx::STATUS_NONFINITE) return c->fail(VMC_ENONFINITE, "non-finite local energy or ln|Psi|");
+    if (status & vmcx::STATUS_CAPACITY)
+        return c->fail(VMC_ECAPACITY, "a walker had more pseudopotential pairs than the capacity (%d)", c->edev.pcap);
     return VMC_OK;
 }
 
@@ -1064,6 +1194,7 @@ int vmc_measure(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
         WalkerOut o{off(out->EL, 1),      off(out->lnpsi, 1),  off(out->lnjac, 1),
                     off(out->dEL_dR, A3), off(out->dlnpsi_dR, A3), off(out->dlnjac_dR, A3),
                     off(out->O, Mn),      off(out->G, Mn)};
+        c->ecp_id0 = c0;
         if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, C, R, R0, warp, full, o, st))) return rc;
     }
     return VMC_OK;
@@ -1111,6 +1242,7 @@ int vmc_adjoint(vmc_ctx *c, const double *walkers, int64_t W, const double *C, c
     for (int64_t c0 = 0; c0 < W; c0 += step) {
         const int64_t cw = std::min(step, W - c0);
         WalkerOut o{c->st_EL, c->st_lnpsi, c->st_lnjac, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G};
+        c->ecp_id0 = c0;
         if ((rc = run_measure(c, walkers + c0 * c->N * 3, cw, C, R, R0, warp, 1, o, st))) return rc;
         EstArgs a{c->st_EL, c->st_dEdR, c->st_dPdR, c->st_dJdR, c->st_O, c->st_G, nullptr,
                   gEL + c0, gPsi + c0,  gJac + c0,  A3,         Mn};

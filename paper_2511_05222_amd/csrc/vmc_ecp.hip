@@ -1,0 +1,571 @@
+// vmc_ecp.hip -- semilocal pseudopotential in the local energy (gfx950).
+//
+// On nucleus a, an electron i at distance d = |r_i - R_a| (direction u) sees
+// the local potential V_loc(d) and, for d < rcut[a], the projectors of the
+// channels l, which enter E_L as
+//   E_nl = sum_(i,a) sum_q c_q rho_q,   c_q = sum_l (2l + 1)/12 V_l(d) P_l(u . v_q),
+//   rho_q = Psi(.., r_q, ..) / Psi(.., r_i, ..) = t_q exp(dJ_q),
+//   t_q = phi(r_q)^T K e_i (determinant lemma),  r_q = R_a + d v_q,
+// over the 12 icosahedron vertices v_q turned by one random rotation per
+// (walker, electron), dJ_q the change of the two-body Jastrow.  Three kernels
+// around the measurement:
+//   k_ecp_pairs    the (electron, nucleus) pairs inside the cutoffs and their
+//                  12 points each; the MO rows at the points are then one
+//                  k_mo_rows_mfma launch;
+//   k_ecp_energy   after k_dense: rho_q, E_loc + E_nl added to E_L; and, with
+//                  Z[j][i] = sum_q c'_q phi_q[j] (c'_q = c_q exp(dJ_q), the
+//                  points of electron i), the derivative through the inverses,
+//                  dE/dA_b = -(K~_b Z_b K~_b) with K~[e][j] = K[j][e], added to
+//                  Abar, which k_adjoint_mfma carries into G, dE_L/dr and the
+//                  AO centres like the kinetic energy's share;
+//   k_ecp_adjoint  after k_adjoint_mfma: the derivatives through the points.
+//                  With y_q = c'_q K~[i] (dE/dphi(r_q)):  G += sum_q psi(r_q) y_q^T;
+//                  g_q = dE/dr_q (orbitals and Jastrow at r_q) carried to r_i
+//                  and R_a through r_q = R_a + d v_q; c_q through d and u . v_q;
+//                  the Jastrow's dependence on the other electrons; the AOs
+//                  at the points moving with their nuclei; V_loc.
+#include "vmc.h"
+#include "vmc_pipeline.hpp"
+#include "vmc_regs.hpp"
+
+namespace vmcx {
+
+constexpr uint32_t PURPOSE_ROTATION = 2;
+
+// Quadrature direction q: (0, s1, s2 g), (s1, s2 g, 0), (s2 g, 0, s1) for
+// s1, s2 in (+1, -1) in that order (q = 6 i1 + 3 i2 + k), g the golden
+// ratio, normalised.
+__device__ inline void ico_dir(int q, double v[3]) {
+    const double g = 0.5 * (1.0 + sqrt(5.0)), nrm = sqrt(1.0 + g * g);
+    const int i1 = q / 6, i2 = (q / 3) & 1, k = q % 3;
+    const double s1 = i1 ? -1.0 : 1.0, s2 = i2 ? -g : g;
+    const double a[3] = {0.0, s1, s2}, b[3] = {s1, s2, 0.0}, c[3] = {s2, 0.0, s1};
+    const double *x = k == 0 ? a : (k == 1 ? b : c);
+    v[0] = x[0] / nrm;
+    v[1] = x[1] / nrm;
+    v[2] = x[2] / nrm;
+}
+
+// Rotation of the quadrature of (walker id, rotation index, electron):
+// Shoemake's uniform unit quaternion (x, y, z, s) from three uniforms
+// u = w 2^-32 of one Philox draw, as a row-major 3 x 3 matrix.
+__device__ inline void ecp_rotation(uint64_t seed, uint32_t wid, uint32_t rot, int e, double Rm[9]) {
+    const U4 wd = draw_words(seed, wid, rot, (uint32_t)e, PURPOSE_ROTATION);
+    const double u1 = (double)wd.x * 2.3283064365386963e-10, u2 = (double)wd.y * 2.3283064365386963e-10,
+                 u3 = (double)wd.z * 2.3283064365386963e-10;
+    const double a = sqrt(1.0 - u1), b = sqrt(u1);
+    const double x = a * sin(6.283185307179586 * u2), y = a * cos(6.283185307179586 * u2);
+    const double z = b * sin(6.283185307179586 * u3), s = b * cos(6.283185307179586 * u3);
+    Rm[0] = 1.0 - 2.0 * (y * y + z * z);
+    Rm[1] = 2.0 * (x * y - z * s);
+    Rm[2] = 2.0 * (x * z + y * s);
+    Rm[3] = 2.0 * (x * y + z * s);
+    Rm[4] = 1.0 - 2.0 * (x * x + z * z);
+    Rm[5] = 2.0 * (y * z - x * s);
+    Rm[6] = 2.0 * (x * z - y * s);
+    Rm[7] = 2.0 * (y * z + x * s);
+    Rm[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// V_l of nucleus a at d (l = -1: local) and its derivative in d.
+__device__ inline void ecp_radial(const EcpDev &E, int a, int l, double d, double &v, double &dv) {
+    v = dv = 0.0;
+    for (int t = E.t0[a]; t < E.t0[a + 1]; ++t) {
+        if (E.t_l[t] != l) continue;
+        const int n = E.t_n[t];
+        const double al = E.t_alpha[t], b = E.t_beta[t];
+        const double ex = exp(-al * d * d);
+        const double pw = n == 1 ? 1.0 / d : (n == 2 ? 1.0 : (n == 3 ? d : d * d));     // d^(n-2)
+        const double pm = n == 1 ? -1.0 / (d * d) : (n == 2 ? 0.0 : (n == 3 ? 1.0 : 2.0 * d));   // (n-2) d^(n-3)
+        v += b * pw * ex;
+        dv += b * ex * (pm - 2.0 * al * d * pw);
+    }
+}
+
+__device__ inline double legendre(int l, double x) {
+    return l == 0 ? 1.0 : (l == 1 ? x : (l == 2 ? 1.5 * x * x - 0.5 : (2.5 * x * x - 1.5) * x));
+}
+__device__ inline double legendre_d(int l, double x) {
+    return l == 0 ? 0.0 : (l == 1 ? 1.0 : (l == 2 ? 3.0 * x : 7.5 * x * x - 1.5));
+}
+
+// ---------------------------------------------------------------------------
+// Pairs inside the cutoffs (in electron order, then the order of the nuclei
+// with projectors) and their points; rows past a walker's pairs get its
+// first electron's position (finite, never used).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(128) void k_ecp_pairs(SysDev S, EcpDev E, const double *__restrict__ R,
+                                                   const double *__restrict__ pos, int64_t id0,
+                                                   const int *__restrict__ idlist, uint32_t rot, int *pairs,
+                                                   int *npairs, double *qpos, int *status) {
+    __shared__ int cnt[128];
+    __shared__ int tot;
+    const int w = blockIdx.x, tid = threadIdx.x, N = S.N, P = E.pcap;
+    const double *p = pos + (size_t)w * N * 3;
+    int c = 0;
+    if (tid < N)
+        for (int k = 0; k < E.n_nl; ++k) {
+            const int a = E.nl_atom[k];
+            const double dx = p[3 * tid] - R[3 * a], dy = p[3 * tid + 1] - R[3 * a + 1],
+                         dz = p[3 * tid + 2] - R[3 * a + 2];
+            if (sqrt(dx * dx + dy * dy + dz * dz) < E.rcut[a]) ++c;
+        }
+    cnt[tid] = c;
+    __syncthreads();
+    if (tid == 0) {
+        int s = 0;
+        for (int i = 0; i < 128; ++i) {
+            const int t = cnt[i];
+            cnt[i] = s;
+            s += t;
+        }
+        tot = s;
+        npairs[w] = min(s, P);
+        if (s > P) atomicOr(status, STATUS_CAPACITY);
+    }
+    __syncthreads();
+    int *pw = pairs + (size_t)w * P;
+    if (tid < N) {
+        int o = cnt[tid];
+        for (int k = 0; k < E.n_nl; ++k) {
+            const int a = E.nl_atom[k];
+            const double dx = p[3 * tid] - R[3 * a], dy = p[3 * tid + 1] - R[3 * a + 1],
+                         dz = p[3 * tid + 2] - R[3 * a + 2];
+            if (sqrt(dx * dx + dy * dy + dz * dz) < E.rcut[a]) {
+                if (o < P) pw[o] = tid | (a << 8);
+                ++o;
+            }
+        }
+    }
+    __syncthreads();
+    const int np = min(tot, P);
+    const uint32_t wid = (uint32_t)(id0 + (idlist ? idlist[w] : w));
+    double *qp = qpos + (size_t)w * P * 12 * 3;
+    for (int t = tid; t < P * 12; t += 128) {
+        const int pi = t / 12, q = t - 12 * (t / 12);
+        double o0 = p[0], o1 = p[1], o2 = p[2];
+        if (pi < np) {
+            const int pr = pw[pi], e = pr & 255, a = pr >> 8;
+            const double dx = p[3 * e] - R[3 * a], dy = p[3 * e + 1] - R[3 * a + 1], dz = p[3 * e + 2] - R[3 * a + 2];
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            double Rm[9], u[3];
+            ecp_rotation(E.seed, wid, rot, e, Rm);
+            ico_dir(q, u);
+            o0 = R[3 * a] + d * (Rm[0] * u[0] + Rm[1] * u[1] + Rm[2] * u[2]);
+            o1 = R[3 * a + 1] + d * (Rm[3] * u[0] + Rm[4] * u[1] + Rm[5] * u[2]);
+            o2 = R[3 * a + 2] + d * (Rm[6] * u[0] + Rm[7] * u[1] + Rm[8] * u[2]);
+        }
+        qp[3 * t] = o0;
+        qp[3 * t + 1] = o1;
+        qp[3 * t + 2] = o2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The energy and the derivative through the inverses.  One block per walker;
+// wavefront v takes the pairs of the electrons i = v mod 4 (so that Z[.][i]
+// has one writer), lanes run over orbitals (ratio) and electrons (Jastrow).
+// Per point it keeps rows[.] = (c'_q, t_q, exp(dJ_q), c_q).
+// ---------------------------------------------------------------------------
+size_t ecp_energy_lds(int N, int n) { return sizeof(double) * ((size_t)3 * N + (size_t)N * n + (size_t)n * n + 132); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const double *__restrict__ R,
+                                                    const double *__restrict__ pos, EcpBufs<T> eb, int nc,
+                                                    const T *__restrict__ ktil, T *abar, double *EL, int *status) {
+    extern __shared__ double sm[];
+    const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int N = S.N, n = S.n_occ, P = E.pcap;
+    double *sp = sm;               // [N][3]
+    double *sz = sp + 3 * N;       // [N][n]: Z^T, row i = sum over the points of electron i
+    double *sP = sz + N * n;       // [n][n]
+    double *red = sP + n * n;      // [128] local terms, [4] per-wave E_nl
+    for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
+    if (abar)
+        for (int i = tid; i < N * n; i += 256) sz[i] = 0.0;
+    __syncthreads();
+    const int np = eb.npairs[w];
+    const int *pw = eb.pairs + (size_t)w * P;
+    const T *ph = eb.phiq + (size_t)w * P * 12 * nc * n;
+    const T *kt = ktil + (size_t)w * N * n;
+    const double *qp = eb.qpos + (size_t)w * P * 12 * 3;
+    double *rw = eb.rows + (size_t)w * P * 12 * ECP_ROW;
+    double Ew = 0.0;
+    for (int pi = 0; pi < np; ++pi) {
+        const int pr = pw[pi], e = pr & 255, a = pr >> 8;
+        if ((e & 3) != wave) continue;
+        const double ex = sp[3 * e], ey = sp[3 * e + 1], ez = sp[3 * e + 2];
+        const double dx = ex - R[3 * a], dy = ey - R[3 * a + 1], dz = ez - R[3 * a + 2];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        const double ux = dx / d, uy = dy / d, uz = dz / d;
+        double Vl[VMC_MAX_ECP_L + 1];
+        for (int l = 0; l <= E.lmax; ++l) {
+            double dv;
+            ecp_radial(E, a, l, d, Vl[l], dv);
+        }
+        const double kte = lane < n ? (double)kt[(size_t)e * n + lane] : 0.0;
+        // the electron's own pair terms, sum_{j != e} u(|r_e - r_j|)
+        double uo = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * h;
+            if (j < N && j != e) {
+                const double qx = ex - sp[3 * j], qy = ey - sp[3 * j + 1], qz = ez - sp[3 * j + 2];
+                uo += jas_u(sqrt(qx * qx + qy * qy + qz * qz), S.ee_a, S.ee_F, S.ee_form);
+            }
+        }
+        uo = wave_sum_dpp(uo);
+        for (int q = 0; q < 12; ++q) {
+            const int row = 12 * pi + q;
+            const double px = qp[3 * row], py = qp[3 * row + 1], pz = qp[3 * row + 2];
+            const double cs = (ux * (px - R[3 * a]) + uy * (py - R[3 * a + 1]) + uz * (pz - R[3 * a + 2])) / d;
+            double c = 0.0;
+            for (int l = 0; l <= E.lmax; ++l) c += (double)(2 * l + 1) / 12.0 * Vl[l] * legendre(l, cs);
+            const double phj = lane < n ? (double)ph[(size_t)row * nc * n + lane] : 0.0;
+            const double t = wave_sum_dpp(phj * kte);
+            double un = 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = lane + 64 * h;
+                if (j < N && j != e) {
+                    const double qx = px - sp[3 * j], qy = py - sp[3 * j + 1], qz = pz - sp[3 * j + 2];
+                    un += jas_u(sqrt(qx * qx + qy * qy + qz * qz), S.ee_a, S.ee_F, S.ee_form);
+                }
+            }
+            const double jr = exp(wave_sum_dpp(un) - uo);
+            const double cq = c * jr;
+            Ew += cq * t;
+            if (abar && lane < n) sz[(size_t)e * n + lane] += cq * phj;
+            if (lane == 0) {
+                double *o = rw + (size_t)row * ECP_ROW;
+                o[0] = cq;
+                o[1] = t;
+                o[2] = jr;
+                o[3] = c;
+            }
+        }
+    }
+    // the local part, every electron and nucleus
+    double El = 0.0;
+    if (tid < N)
+        for (int a = 0; a < S.A; ++a) {
+            if (E.t0[a] == E.t0[a + 1]) continue;
+            const double dx = sp[3 * tid] - R[3 * a], dy = sp[3 * tid + 1] - R[3 * a + 1],
+                         dz = sp[3 * tid + 2] - R[3 * a + 2];
+            double v, dv;
+            ecp_radial(E, a, -1, sqrt(dx * dx + dy * dy + dz * dz), v, dv);
+            El += v;
+        }
+    if (tid < 128) red[tid] = El;
+    if (lane == 0) red[128 + wave] = Ew;
+    __syncthreads();
+    if (tid == 0 && EL) {
+        double s = 0.0;
+        for (int i = 0; i < N; ++i) s += red[i];
+        const double e_l = EL[w] + (s + ((red[128] + red[129]) + (red[130] + red[131])));
+        EL[w] = e_l;
+        if (!isfinite(e_l)) atomicOr(status, STATUS_NONFINITE);
+    }
+    if (!abar) return;
+    // dE/dA_b = -(K~_b Z_b K~_b): sP = Z_b K~_b, then Abar_b -= K~_b sP
+    for (int b = 0; b < 2; ++b) {
+        const int off = b ? S.n_up : 0, nb = b ? S.n_dn : S.n_up;
+        __syncthreads();
+        for (int idx = tid; idx < n * n; idx += 256) {
+            const int a = idx / n, j = idx - (idx / n) * n;
+            double s = 0.0;
+            for (int i = 0; i < nb; ++i) s += sz[(size_t)(off + i) * n + a] * (double)kt[(size_t)(off + i) * n + j];
+            sP[idx] = s;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nb * n; idx += 256) {
+            const int ei = idx / n, j = idx - (idx / n) * n;
+            double s = 0.0;
+            for (int a = 0; a < n; ++a) s += (double)kt[(size_t)(off + ei) * n + a] * sP[(size_t)a * n + j];
+            T *ab = abar + ((size_t)w * N + off + ei) * n + j;
+            *ab = (T)((double)*ab - s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The derivatives through the points.  One block per walker.
+//   phase 1 (threads over AOs mu): G[mu] += sum_q psi_mu(r_q) y_q and the
+//            per-AO sums tc[mu] = sum_q kappa_q,mu grad psi_mu(r_q),
+//            kappa_q = C y_q, over batches of 16 points staged in LDS;
+//   phase 2 (threads over points): the chain through r_q = R_a + d v_q, the
+//            weights c_q and the Jastrow at r_q and r_i, into rows[4..9];
+//   phase 3: per electron and per nucleus, fixed-order sums.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T *__restrict__ C,
+                                                     const double *__restrict__ R, const double *__restrict__ pos,
+                                                     EcpBufs<T> eb, const T *__restrict__ ktil, double *G, float *Gf,
+                                                     double *dedr) {
+    extern __shared__ double sm[];
+    const int w = blockIdx.x, tid = threadIdx.x;
+    const int N = S.N, n = S.n_occ, M = S.M, A = S.A, P = E.pcap;
+    const BasisDev &B = S.basis;
+    double *sp = sm;               // [N][3]
+    double *sy = sp + 3 * N;       // [16][n]
+    double *sq = sy + 16 * n;      // [16][3]
+    double *stc = sq + 48;         // [M][3]
+    for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
+    const int np = eb.npairs[w], nrow = 12 * np;
+    const int *pw = eb.pairs + (size_t)w * P;
+    const T *ph = eb.phiq + (size_t)w * P * 12 * 5 * n;
+    const T *kt = ktil + (size_t)w * N * n;
+    const double *qp = eb.qpos + (size_t)w * P * 12 * 3;
+    double *rw = eb.rows + (size_t)w * P * 12 * ECP_ROW;
+    // ---- phase 1 ----
+    for (int mu0 = 0; mu0 < M; mu0 += 256) {
+        const int mu = mu0 + tid;
+        const bool vm = mu < M;
+        const int mm = vm ? mu : M - 1;
+        const int s = B.ao_shell[mm], atom = B.shell_atom[s], pwr = B.ao_pow[mm];
+        const double eta = B.ao_eta[mm];
+        double g[VMC_MAX_OCC];
+#pragma unroll
+        for (int j = 0; j < VMC_MAX_OCC; ++j) g[j] = 0.0;
+        double tcx = 0.0, tcy = 0.0, tcz = 0.0;
+        for (int r0 = 0; r0 < nrow; r0 += 16) {
+            __syncthreads();
+            for (int idx = tid; idx < 16 * n; idx += 256) {
+                const int r = idx / n, j = idx - (idx / n) * n, row = r0 + r;
+                double y = 0.0;
+                if (row < nrow) {
+                    const int e = pw[row / 12] & 255;
+                    y = rw[(size_t)row * ECP_ROW] * (double)kt[(size_t)e * n + j];
+                }
+                sy[idx] = y;
+            }
+            for (int idx = tid; idx < 48; idx += 256) {
+                const int row = r0 + idx / 3;
+                sq[idx] = row < nrow ? qp[(size_t)3 * r0 + idx] : 0.0;
+            }
+            __syncthreads();
+            const int nr = min(16, nrow - r0);
+            if (!vm) continue;
+            for (int r = 0; r < nr; ++r) {
+                const double dx = sq[3 * r] - R[3 * atom], dy = sq[3 * r + 1] - R[3 * atom + 1],
+                             dz = sq[3 * r + 2] - R[3 * atom + 2];
+                const double rho = dx * dx + dy * dy + dz * dz;
+                double R0, R1, R2, R3, o[5];
+                shell_radial<5, double>(B, s, rho, R0, R1, R2, R3);
+                ao_components<5, double>(dx, dy, dz, rho, R0, R1, R2, R3, pwr, eta, o);
+                double kap = 0.0;
+                const double *y = sy + (size_t)r * n;
+#pragma unroll
+                for (int j = 0; j < VMC_MAX_OCC; ++j)
+                    if (j < n) {
+                        kap += (double)C[(size_t)mu * n + j] * y[j];
+                        g[j] += o[0] * y[j];
+                    }
+                tcx += kap * o[1];
+                tcy += kap * o[2];
+                tcz += kap * o[3];
+            }
+        }
+        if (vm) {
+#pragma unroll
+            for (int j = 0; j < VMC_MAX_OCC; ++j)
+                if (j < n) {
+                    const size_t o = ((size_t)w * M + mu) * n + j;
+                    if (G)
+                        G[o] += g[j];
+                    else if (Gf)
+                        Gf[o] = (float)((double)Gf[o] + g[j]);
+                }
+            stc[3 * mu] = tcx;
+            stc[3 * mu + 1] = tcy;
+            stc[3 * mu + 2] = tcz;
+        }
+    }
+    __syncthreads();
+    // ---- phase 2 ----
+    for (int row = tid; row < nrow; row += 256) {
+        const int pr = pw[row / 12], e = pr & 255, a = pr >> 8;
+        const double ex = sp[3 * e], ey = sp[3 * e + 1], ez = sp[3 * e + 2];
+        const double dx = ex - R[3 * a], dy = ey - R[3 * a + 1], dz = ez - R[3 * a + 2];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        const double u[3] = {dx / d, dy / d, dz / d};
+        const double px = qp[3 * row], py = qp[3 * row + 1], pz = qp[3 * row + 2];
+        const double v[3] = {(px - R[3 * a]) / d, (py - R[3 * a + 1]) / d, (pz - R[3 * a + 2]) / d};
+        const double cs = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+        double *o = rw + (size_t)row * ECP_ROW;
+        const double cq = o[0], t = o[1], jr = o[2];
+        const double Eq = cq * t, hq = jr * t;
+        // dE/dr_q through the orbitals: cq sum_j K~[e][j] grad phi_j(r_q)
+        double g[3] = {0.0, 0.0, 0.0};
+        const T *pr5 = ph + (size_t)row * 5 * n;
+        for (int j = 0; j < n; ++j) {
+            const double kj = (double)kt[(size_t)e * n + j];
+            g[0] += kj * (double)pr5[n + j];
+            g[1] += kj * (double)pr5[2 * n + j];
+            g[2] += kj * (double)pr5[3 * n + j];
+        }
+        // through the Jastrow at r_q, and its pair terms at r_e
+        double gj[3] = {0.0, 0.0, 0.0}, jo[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < N; ++j) {
+            if (j == e) continue;
+            const double qx = px - sp[3 * j], qy = py - sp[3 * j + 1], qz = pz - sp[3 * j + 2];
+            const double rq = sqrt(qx * qx + qy * qy + qz * qz);
+            const double fq = jas_all(rq, S.ee_a, S.ee_F, S.ee_form).u1 / rq;
+            gj[0] += fq * qx;
+            gj[1] += fq * qy;
+            gj[2] += fq * qz;
+            const double sx = ex - sp[3 * j], sy_ = ey - sp[3 * j + 1], sz_ = ez - sp[3 * j + 2];
+            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
+            const double fe = jas_all(re, S.ee_a, S.ee_F, S.ee_form).u1 / re;
+            jo[0] += fe * sx;
+            jo[1] += fe * sy_;
+            jo[2] += fe * sz_;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] = cq * g[k] + Eq * gj[k];
+        // c_q through d and u . v
+        double dc[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l <= E.lmax; ++l) {
+            double V, dV;
+            ecp_radial(E, a, l, d, V, dV);
+            const double wl = (double)(2 * l + 1) / 12.0;
+            const double f1 = wl * dV * legendre(l, cs), f2 = wl * V * legendre_d(l, cs) / d;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dc[k] += f1 * u[k] + f2 * (v[k] - cs * u[k]);
+        }
+        const double gv = g[0] * v[0] + g[1] * v[1] + g[2] * v[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            o[4 + k] = gv * u[k] + hq * dc[k] - Eq * jo[k];     // to r_e
+            o[7 + k] = g[k] - gv * u[k] - hq * dc[k];           // to R_a
+        }
+    }
+    __syncthreads();
+    // ---- phase 3 ----
+    if (tid < N) {
+        const int j = tid;
+        const double xj = sp[3 * j], yj = sp[3 * j + 1], zj = sp[3 * j + 2];
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int row = 0; row < nrow; ++row) {
+            const double *o = rw + (size_t)row * ECP_ROW;
+            const int e = pw[row / 12] & 255;
+            if (e == j) {
+                s[0] += o[4];
+                s[1] += o[5];
+                s[2] += o[6];
+                continue;
+            }
+            // the Jastrow change of e's point depends on r_j through two pair terms
+            const double Eq = o[0] * o[1];
+            const double qx = qp[3 * row] - xj, qy = qp[3 * row + 1] - yj, qz = qp[3 * row + 2] - zj;
+            const double rq = sqrt(qx * qx + qy * qy + qz * qz);
+            const double fq = jas_all(rq, S.ee_a, S.ee_F, S.ee_form).u1 / rq;
+            const double sx = sp[3 * e] - xj, sy_ = sp[3 * e + 1] - yj, sz_ = sp[3 * e + 2] - zj;
+            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
+            const double fe = jas_all(re, S.ee_a, S.ee_F, S.ee_form).u1 / re;
+            s[0] += Eq * (fe * sx - fq * qx);
+            s[1] += Eq * (fe * sy_ - fq * qy);
+            s[2] += Eq * (fe * sz_ - fq * qz);
+        }
+        for (int a = 0; a < A; ++a) {
+            if (E.t0[a] == E.t0[a + 1]) continue;
+            const double dx = xj - R[3 * a], dy = yj - R[3 * a + 1], dz = zj - R[3 * a + 2];
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            double v, dv;
+            ecp_radial(E, a, -1, d, v, dv);
+            s[0] += dv * dx / d;
+            s[1] += dv * dy / d;
+            s[2] += dv * dz / d;
+        }
+        double *de = dedr + ((size_t)w * N + j) * 3;
+        de[0] += s[0];
+        de[1] += s[1];
+        de[2] += s[2];
+    }
+    if (tid < A) {
+        const int a = tid;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int row = 0; row < nrow; ++row) {
+            if ((pw[row / 12] >> 8) != a) continue;
+            const double *o = rw + (size_t)row * ECP_ROW;
+            s[0] += o[7];
+            s[1] += o[8];
+            s[2] += o[9];
+        }
+        if (E.t0[a] != E.t0[a + 1])
+            for (int j = 0; j < N; ++j) {
+                const double dx = sp[3 * j] - R[3 * a], dy = sp[3 * j + 1] - R[3 * a + 1], dz = sp[3 * j + 2] - R[3 * a + 2];
+                const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                double v, dv;
+                ecp_radial(E, a, -1, d, v, dv);
+                s[0] -= dv * dx / d;
+                s[1] -= dv * dy / d;
+                s[2] -= dv * dz / d;
+            }
+        // the AOs at the points move with their nuclei
+        for (int q = B.atom_ao_ptr[a]; q < B.atom_ao_ptr[a + 1]; ++q) {
+            const int mu = B.atom_ao[q];
+            s[0] -= stc[3 * mu];
+            s[1] -= stc[3 * mu + 1];
+            s[2] -= stc[3 * mu + 2];
+        }
+        double *o = eb.ecp_dR + ((size_t)w * A + a) * 3;
+        o[0] = s[0];
+        o[1] = s[1];
+        o[2] = s[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
+                            int64_t id0, const int *idlist, uint32_t rot, int *pairs, int *npairs, double *qpos,
+                            int *status, hipStream_t st) {
+    if (S.N > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ecp_pairs, dim3(W), dim3(128), 0, st, S, E, R, pos, id0, idlist, rot, pairs, npairs, qpos,
+                       status);
+    return hipGetLastError();
+}
+
+static size_t ecp_adjoint_lds(int N, int n, int M) {
+    return sizeof(double) * ((size_t)3 * N + (size_t)16 * n + 48 + (size_t)3 * M);
+}
+
+hipError_t configure_ecp(size_t lds) {
+    const void *f[2] = {(const void *)k_ecp_energy<double>, (const void *)k_ecp_energy<float>};
+    for (const void *g : f) {
+        const hipError_t e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_ecp_energy(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
+                             const EcpBufs<T> &eb, int nc, const T *ktil, T *abar, double *EL, int *status,
+                             hipStream_t st) {
+    hipLaunchKernelGGL((k_ecp_energy<T>), dim3(W), dim3(256), ecp_energy_lds(S.N, S.n_occ), st, S, E, R, pos, eb,
+                       nc, ktil, abar, EL, status);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, const double *R, const double *pos,
+                              int W, const EcpBufs<T> &eb, const T *ktil, double *G, float *Gf, double *dedr,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_ecp_adjoint<T>), dim3(W), dim3(256), ecp_adjoint_lds(S.N, S.n_occ, S.M), st, S, E, C, R,
+                       pos, eb, ktil, G, Gf, dedr);
+    return hipGetLastError();
+}
+
+#define ECP_INST(T)                                                                                                \
+    template hipError_t launch_ecp_energy<T>(const SysDev &, const EcpDev &, const double *, const double *, int,     \
+                                             const EcpBufs<T> &, int, const T *, T *, double *, int *, hipStream_t); \
+    template hipError_t launch_ecp_adjoint<T>(const SysDev &, const EcpDev &, const T *, const double *,             \
+                                              const double *, int, const EcpBufs<T> &, const T *, double *, float *, \
+                                              double *, hipStream_t);
+ECP_INST(double)
+ECP_INST(float)
+
+}  // namespace vmcx

@@ -14,6 +14,7 @@ namespace vmcx {
 constexpr double FORCED_REFRESH_RATIO = 1e-8;
 constexpr int STATUS_SINGULAR = 1;
 constexpr int STATUS_NONFINITE = 2;
+constexpr int STATUS_CAPACITY = 4;   // a walker had more pseudopotential pairs than the capacity
 
 struct SysDev {
     int N, n_up, n_dn, n_occ, M, A;

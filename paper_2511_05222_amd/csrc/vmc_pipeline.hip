@@ -297,6 +297,13 @@ __global__ __launch_bounds__(128) void k_finalize(SysDev S, const double *__rest
                 sJ[k] += Mi[k] * g[0] + Mi[3 + k] * g[1] + Mi[6 + k] * g[2];
             }
         }
+        if (j == 0 && mb.ecp_dR) {
+            // the pseudopotential's explicit derivative in this nucleus
+            const double *q = mb.ecp_dR + ((size_t)w * A + a) * 3;
+            sE[0] += q[0];
+            sE[1] += q[1];
+            sE[2] += q[2];
+        }
         if (j == 0)
             for (int c = 0; c < A; ++c) {
                 if (c == a) continue;

@@ -69,7 +69,56 @@ struct MeasBufsD {
     // jtao[W][MJ][6] of its dE_L/dr and dlnPsi/dr terms; jb its basis
     const double *jtao = nullptr;
     BasisDev jb{};
+    // pseudopotential (null: none): its explicit derivative in each nucleus,
+    // ecp_dR[W][A][3]
+    const double *ecp_dR = nullptr;
 };
+
+// Semilocal pseudopotential (vmc_ecp.hip): radial terms sorted by nucleus,
+// beta d^(n - 2) e^{-alpha d^2} in channel l (-1: local).
+struct EcpDev {
+    int n_nl;                  // nuclei with projectors
+    const int *nl_atom;        // [n_nl]
+    const int *t0;             // [A + 1]: the terms of nucleus a are t0[a] .. t0[a + 1]
+    const int *t_l, *t_n;
+    const double *t_alpha, *t_beta;
+    const double *rcut;        // [A]
+    int lmax;                  // largest projector l
+    uint64_t seed;             // key of the quadrature rotations
+    int pcap;                  // (electron, nucleus) pairs per walker
+};
+
+// Staging of the pseudopotential terms of one measurement launch (W walkers):
+// pairs[W][pcap] = electron | nucleus << 8, npairs[W], the points
+// qpos[W][pcap * 12][3], the MO rows there phiq[W][pcap * 12][nc][n] (type
+// T), per point rows[W][pcap * 12][ECP_ROW] and ecp_dR[W][A][3].
+constexpr int ECP_ROW = 10;
+template <typename T>
+struct EcpBufs {
+    int *pairs, *npairs;
+    double *qpos;
+    T *phiq;
+    double *rows;
+    double *ecp_dR;
+};
+// Pairs and points of walker w (walker id id0 + w, or id0 + idlist[w]).
+hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
+                            int64_t id0, const int *idlist, uint32_t rot, int *pairs, int *npairs, double *qpos,
+                            int *status, hipStream_t st);
+// LDS the energy kernel needs (bytes), and raising the limits to it
+size_t ecp_energy_lds(int N, int n);
+hipError_t configure_ecp(size_t lds);
+// E_loc + E_nl added to EL[w]; with abar: dE/dA through the inverses added.
+template <typename T>
+hipError_t launch_ecp_energy(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
+                             const EcpBufs<T> &eb, int nc, const T *ktil, T *abar, double *EL, int *status,
+                             hipStream_t st);
+// The derivatives through the points: G (or Gf) += sum psi(r_q) y_q^T,
+// dedr[w][e] += ..., ecp_dR[w][a] = ...
+template <typename T>
+hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, const double *R, const double *pos,
+                              int W, const EcpBufs<T> &eb, const T *ktil, double *G, float *Gf, double *dedr,
+                              hipStream_t st);
 
 // cpad: scratch of (M + 16) * 64 elements for the padded copy of C (n_occ <= 64)
 template <typename T>

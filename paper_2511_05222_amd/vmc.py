@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvmcx.so")
 
 VMC_OK, VMC_EINVAL, VMC_ENOMEM, VMC_EDEVICE, VMC_ESINGULAR, VMC_ENOTCONV, VMC_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+VMC_ECAPACITY = -7
 VMC_FP64 = 0
 VMC_MIXED = 1
 # mixed precision: share of each measurement launch re-measured in FP64 (the
@@ -58,11 +59,18 @@ class _Jastrow(ct.Structure):
                 ("xi3", ct.POINTER(ct.c_double))]
 
 
+class _Ecp(ct.Structure):
+    _fields_ = [("n_terms", ct.c_int32), ("term_atom", ct.POINTER(ct.c_int32)), ("term_l", ct.POINTER(ct.c_int32)),
+                ("term_n", ct.POINTER(ct.c_int32)), ("term_exp", ct.POINTER(ct.c_double)),
+                ("term_coef", ct.POINTER(ct.c_double)), ("rcut", ct.POINTER(ct.c_double)),
+                ("rot_seed", ct.c_uint64), ("max_pairs", ct.c_int32)]
+
+
 class _Options(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("refresh_period", ct.c_int32), ("block_sweeps", ct.c_int32),
                 ("max_walkers", ct.c_int32), ("staging_walkers", ct.c_int32), ("step_sigma", ct.c_double),
                 ("promote_fraction", ct.c_double), ("jackknife_blocks", ct.c_int32),
-                ("forced_refresh_ratio", ct.c_double)]
+                ("forced_refresh_ratio", ct.c_double), ("ecp", ct.POINTER(_Ecp))]
 
 
 class _WalkerOut(ct.Structure):
@@ -141,7 +149,7 @@ class Context:
 
     def __init__(self, mol, max_walkers, precision="fp64", refresh_period=32, block_sweeps=1,
                  step_sigma=0.5, device=0, staging_walkers=0, promote_fraction=PROMOTE_FRACTION,
-                 jackknife_blocks=0, forced_refresh_ratio=0.0):
+                 jackknife_blocks=0, forced_refresh_ratio=0.0, ecp_max_pairs=0):
         L = lib()
         b = mol.basis
         self._keep = [np.ascontiguousarray(b.shell_atom, np.int32), np.ascontiguousarray(b.shell_l, np.int32),
@@ -174,6 +182,15 @@ class Context:
             raise VmcError(VMC_EINVAL, f"precision {precision!r} is not available")
         opt = _Options(prec, refresh_period, block_sweeps, int(max_walkers), int(staging_walkers), step_sigma,
                        float(promote_fraction), int(jackknife_blocks), float(forced_refresh_ratio))
+        e = getattr(mol, "ecp", None)
+        if e is not None:
+            ek = [np.ascontiguousarray(e.term_atom, np.int32), np.ascontiguousarray(e.term_l, np.int32),
+                  np.ascontiguousarray(e.term_n, np.int32), np.ascontiguousarray(e.term_exp, np.float64),
+                  np.ascontiguousarray(e.term_coef, np.float64), np.ascontiguousarray(e.rcut, np.float64)]
+            self._keep += ek
+            self._ecp = _Ecp(len(ek[0]), ip(ek[0]), ip(ek[1]), ip(ek[2]), dp(ek[3]), dp(ek[4]), dp(ek[5]),
+                             ct.c_uint64(int(e.rot_seed)), int(ecp_max_pairs))
+            opt.ecp = ct.pointer(self._ecp)
         h = ct.c_void_p()
         rc = L.vmc_init(ct.byref(basis), ct.byref(nuc), ct.byref(mo), ct.byref(jas), ct.byref(opt), device,
                         ct.byref(h))

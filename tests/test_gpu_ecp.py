@@ -1,0 +1,141 @@
+"""Semilocal pseudopotential in E_L through the C ABI, against the FP64
+oracle (oracle/ecp.py).
+
+The seeded valence-only 9-atom molecule of inputs.with_ecp: C and O lose two
+core electrons each (20 electrons), with a local part and s and p
+projectors; the projectors' 12-point quadrature is turned per (walker,
+electron) by the counter-based rotation both sides draw.
+
+FP64, 1e-10 of each array's scale: the per-walker measurement (E_L, ln|Psi|,
+dE_L/dR with the space warp, dln|Psi|/dR, O, G = dE_L/dC) at the sampling
+geometry and at displaced nuclei; the estimators after sweeps with
+measurement (the quadrature turned by the sweep index), over several
+measurement launches.  Mixed precision within the mixed-vs-FP64 bounds, and
+its FP64 re-measurement of every walker equal to the FP64 path.  A capacity
+of pairs below a walker's need reports VMC_ECAPACITY.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2511_05222_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def close(gpu, ref, tol=TOL, what=""):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape, (what, gpu.shape, ref.shape)
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(gpu - ref).max()
+    assert err <= tol * scale, f"{what}: max err {err:.3e} vs scale {scale:.3e} (rel {err / scale:.3e})"
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_05222_amd import vmc
+    vmc.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def mol9e():
+    return inputs.with_ecp(inputs.make_config(1).molecule, 5)
+
+
+def per_walker_oracle(mol, r, R=None, R0=None):
+    from oracle import derivatives as dv, wavefunction as wf
+    s = wf.System(mol)
+    R0 = s.xyz if R0 is None else R0
+    R = R0 if R is None else R
+    dE, dP, dJ = dv.nuclear_derivatives(s, R, R0, r)
+    rp, lnjac = dv.warp(R, R0, r)
+    O, G, ev = dv.coefficient_derivatives(s, R, rp)
+    return dict(EL=ev["E_L"], lnpsi=ev["lnpsi"], lnjac=lnjac, dEL_dR=dE, dlnpsi_dR=dP, dlnjac_dR=dJ, O=O, G=G)
+
+
+def test_measure_parity(dev, mol9e):
+    from oracle import sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    W = 6
+    ch, _ = sampler.run(wf.System(mol9e), inputs.initial_walkers(mol9e, W, 5), 2, 61)
+    r = ch.r
+    ref = per_walker_oracle(mol9e, r)
+    ctx = vmc.Context(mol9e, max_walkers=W, staging_walkers=4)
+    print("case: 9-atom pseudopotential measurement", flush=True)
+    out = ctx.measure(torch.tensor(r, device=dev))
+    torch.cuda.synchronize()
+    for k in ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "dlnjac_dR", "O", "G"):
+        close(out[k].cpu().numpy(), ref[k], what=k)
+    # displaced nuclei (electrons warped; the points move with their nucleus)
+    R0 = np.array(mol9e.xyz)
+    R = R0 + 0.03 * np.random.default_rng(4).standard_normal(R0.shape)
+    ref = per_walker_oracle(mol9e, r[:3], R, R0)
+    out = ctx.measure(torch.tensor(r[:3], device=dev), R=torch.tensor(R, device=dev),
+                      R0=torch.tensor(R0, device=dev))
+    torch.cuda.synchronize()
+    for k in ref:
+        close(out[k].cpu().numpy(), ref[k], what=f"warped {k}")
+
+
+def test_estimators(dev, mol9e):
+    from oracle import vmc as ovmc
+    from paper_2511_05222_amd import vmc
+    W, sweeps = 7, 3
+    w0 = inputs.initial_walkers(mol9e, W, 8)
+    ref = ovmc.run(mol9e, w0, sweeps, 79, block_sweeps=1)
+    ctx = vmc.Context(mol9e, max_walkers=W, staging_walkers=3)
+    tw = torch.tensor(w0, device=dev)
+    print("case: 9-atom pseudopotential estimators", flush=True)
+    ctx.sweep(tw, sweeps, 79)
+    res = ctx.accumulate()
+    close(res["E"], ref["E"], what="E")
+    close(res["F_bare"], ref["F_bare"], what="F_bare")
+    close(res["dE_dC"], ref["dE_dC"], what="dE_dC")
+    close(res["dEL_dC_mean"], ref["dEL_dC_mean"], what="dEL_dC_mean")
+
+
+def test_mixed_within_bounds(dev, mol9e):
+    from paper_2511_05222_amd import vmc
+    W = 256
+    w = torch.tensor(inputs.initial_walkers(mol9e, W, 12), device=dev)
+    ctx64 = vmc.Context(mol9e, max_walkers=W)
+    ctx64.sweep(w, 4, 88, measure=False)
+    ctx32 = vmc.Context(mol9e, max_walkers=W, precision="mixed")
+    print("case: 9-atom pseudopotential mixed", flush=True)
+    o32 = ctx32.measure(w, outputs=("EL", "dEL_dR", "dlnpsi_dR"))
+    o64 = ctx64.measure(w, outputs=("EL", "dEL_dR", "dlnpsi_dR"))
+    torch.cuda.synchronize()
+    dE = abs((o32["EL"] - o64["EL"]).mean().item())
+    assert dE < 1e-5, dE
+
+    def force(o):
+        E, H, P = o["EL"], o["dEL_dR"], o["dlnpsi_dR"]
+        e = E - E.mean()
+        return -H.mean(0) - 2.0 * ((e[:, None, None] * P).mean(0) - e.mean() * P.mean(0))
+
+    dF = (force(o32) - force(o64)).abs().max().item()
+    assert dF < 1e-4, dF
+    # every walker re-measured in FP64 (the listed walkers keep their ids)
+    ctxp = vmc.Context(mol9e, max_walkers=W, precision="mixed", promote_fraction=1.0)
+    op = ctxp.measure(w, outputs=("EL", "dEL_dR"))
+    torch.cuda.synchronize()
+    assert torch.equal(op["EL"], o64["EL"]) and torch.equal(op["dEL_dR"], o64["dEL_dR"])
+
+
+def test_capacity(dev, mol9e):
+    from paper_2511_05222_amd import vmc
+    W = 4
+    ctx = vmc.Context(mol9e, max_walkers=W, ecp_max_pairs=1)
+    tw = torch.tensor(inputs.initial_walkers(mol9e, W, 3), device=dev)
+    print("case: 9-atom pseudopotential capacity", flush=True)
+    ctx.sweep(tw, 1, 5)
+    with pytest.raises(vmc.VmcError) as ei:
+        ctx.accumulate()
+    assert ei.value.code == vmc.VMC_ECAPACITY
