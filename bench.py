@@ -27,6 +27,9 @@ Also in the line:
   kernels        the same for every timed kernel;
   step_roofline  the whole walker-step: the summed work of the step against
                  the same peaks, T_roof / T_measured;
+  ecp_9atom      the pseudopotential workload (the 9-atom molecule made
+                 valence-only with a seeded semilocal pseudopotential, 16384
+                 walkers, both precisions) with its kernels' rooflines;
   cpu_baseline   the FP64 oracle on a bounded sample of the same molecule on
                  the host cores (unless --no-cpu-baseline).
 """
@@ -190,6 +193,90 @@ def run_steps(ctx, walkers, seed, warmup, steps):
     return dt, res, prof, p_acc
 
 
+ECP_KERNELS = {"ecp_points": "k_ecp_count/scan/place + k_mo_rows_mfma (points)", "ecp_energy": "k_ecp_energy",
+               "ecp_adjoint": "k_ecp_adjoint"}
+
+
+def ecp_work(mol, precision, pairs):
+    """Algorithmic work per walker of the pseudopotential kernels, with
+    `pairs` (electron, nucleus) pairs inside the cutoffs per walker, Q = 12
+    pairs quadrature points:
+      ecp_points   the AOs and their gradients at the points (10 flops per
+                   primitive, 6 per shell, 15 per AO) and psi C for the five
+                   components (10 Q M n on the matrix cores); bytes: the
+                   points and their MO rows written;
+      ecp_energy   per point the ratio (2n), the Jastrow difference (N pairs,
+                   about 30 flops each) and Z (2n); per spin block
+                   K~ Z K~ (4 n^3); bytes: the points' values, K~ and Abar;
+      ecp_adjoint  per point and AO the value and gradient (~30 flops),
+                   kappa = C y and G += psi y (4n), the chain (6n + 60 N);
+                   bytes: the points' gradients, K~, G read and written."""
+    b = mol.basis
+    N, n, M, P, S = mol.n_elec, mol.n_occ, b.n_ao, b.n_prim, b.n_shells
+    ts = 4 if precision == "mixed" else 8
+    Q = 12.0 * pairs
+    return {
+        "ecp_points": {"mfma": 10.0 * Q * M * n, "alu": Q * (10 * P + 6 * S + 15 * M),
+                       "hbm": Q * (24 + 5 * n * ts)},
+        "ecp_energy": {"mfma": 0.0, "alu": Q * (4 * n + 30 * N) + 2 * 4.0 * n ** 3,
+                       "hbm": Q * n * ts + 3.0 * N * n * ts},
+        "ecp_adjoint": {"mfma": 0.0, "alu": Q * (M * (30 + 4 * n) + 6 * n + 60 * N),
+                        "hbm": Q * (3 * n * ts + 24) + N * n * ts + 2.0 * M * n * 8},
+    }
+
+
+def ecp_entry(args, dev):
+    """The pseudopotential workload: the 9-atom molecule made valence-only
+    with the seeded semilocal pseudopotential (20 electrons), 16384 walkers,
+    both precisions; walker-steps/s and the pseudopotential kernels'
+    rooflines."""
+    import torch
+    from paper_2511_05222_amd import inputs, vmc
+    spec9 = inputs.make_config(1)
+    m = inputs.with_ecp(spec9.molecule, 5)
+    W = spec9.n_walkers
+    out = {"workload": f"{m.name}: {m.n_atoms} atoms, {m.n_elec} valence electrons, {m.basis.n_ao} cartesian AOs, "
+                       f"s and p projectors on C and O, 12-point quadrature, {W} walkers"}
+    for prec in ("mixed", "fp64"):
+        ctx = vmc.Context(m, max_walkers=W, refresh_period=32, precision=prec)
+        w = torch.tensor(inputs.initial_walkers(m, W, spec9.seed), device=dev)
+        ctx.sweep(w, args.warmup, spec9.seed, sweep_offset=0)
+        torch.cuda.synchronize()
+        ctx.accumulate(reset=True)
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.sweep(w, args.steps, spec9.seed, sweep_offset=args.warmup)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = {k: ctx.profile_read(k) for k in ECP_KERNELS}
+        ctx.profile(False)
+        ctx.accumulate(reset=True)
+        # pairs inside the cutoffs per walker, from the final positions
+        r = w.cpu().numpy()
+        e = m.ecp
+        nl = [a for a in range(m.n_atoms) if e.rcut[a] > 0]
+        d = np.linalg.norm(r[:, :, None, :] - np.asarray(m.xyz)[None, None, nl, :], axis=-1)
+        pairs = float((d < np.asarray(e.rcut)[nl][None, None, :]).sum(axis=(1, 2)).mean())
+        work = ecp_work(m, prec, pairs)
+        kern = {}
+        step_ms = dt / args.steps * 1e3
+        for k, (ms, nl_, nw) in prof.items():
+            if nl_ < 1:
+                continue
+            rf = roof(work[k], prec, ms * 1e-3 / max(nw, 1))
+            rf.update({"kernel": ECP_KERNELS[k], "share_of_step": ms / args.steps / step_ms,
+                       "avg_launch_ms": ms / nl_, "units_per_launch": nw / nl_, "work_per_unit": work[k]})
+            kern[k] = rf
+        out[prec] = {"value": W * args.steps / dt, "ms_per_step": step_ms, "pairs_per_walker": pairs,
+                     "kernels": kern}
+        print(f"# ecp 9-atom {prec}: {W * args.steps / dt:.4g} walker-steps/s, {step_ms:.2f} ms/step",
+              file=sys.stderr, flush=True)
+        del ctx, w
+    out["mixed_over_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    return out
+
+
 def error_table(mol, W_sub, walkers, ctx32, ctx64):
     """Mixed vs FP64 on the same configurations."""
     import torch
@@ -232,6 +319,7 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference run and the error table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ecp", action="store_true", help="skip the pseudopotential workload")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the measurement and a plain copy of known size (for counter runs)")
     args = ap.parse_args()
@@ -348,6 +436,8 @@ def main():
                                           f"{m9.basis.n_ao} cartesian AOs, {spec9.n_walkers} walkers, FP64",
                               "value": v9, "ms_per_step": dt9 / args.steps * 1e3}
         del c9, w9
+    if args.workload == "21atom" and not args.no_ecp:
+        line["ecp_9atom"] = ecp_entry(args, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(line), flush=True)

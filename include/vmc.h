@@ -161,11 +161,13 @@ typedef struct {
  * part acts at every distance.  The charges of vmc_nuclei are the effective
  * ones (the removed core's charge subtracted).
  * term_n in 1..4, term_exp > 0; rcut[n_atoms] >= 0 (host arrays, copied).
- * max_pairs: per walker, the most (electron, nucleus) pairs inside the
- * cutoffs a measurement can hold (0 = N times the number of nuclei with a
- * projector, which cannot overflow); a walker with more reports
- * VMC_ECAPACITY at vmc_accumulate.  Not combined with the one-/three-body
- * Jastrow terms. */
+ * max_pairs: (electron, nucleus) pairs inside the cutoffs a measurement
+ * launch holds, per walker of the launch (the pairs of a launch's walkers are
+ * packed together, so it bounds their average; 0 = N times the number of
+ * nuclei with a projector, which cannot overflow; smaller values allow more
+ * walkers per launch); a launch with more pairs drops those past the
+ * capacity and reports VMC_ECAPACITY at vmc_accumulate.  Not combined with
+ * the one-/three-body Jastrow terms. */
 #define VMC_MAX_ECP_L      3
 #define VMC_MAX_ECP_TERMS  256
 typedef struct {
@@ -298,9 +300,9 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
  * block's largest orbital value: e.g. two same-spin electrons at one point,
  * or an electron where every orbital vanishes); otherwise
  * VMC_ENONFINITE if a measured E_L, ln|Psi| or log|det| was not finite (e.g.
- * a walker with a NaN coordinate); otherwise VMC_ECAPACITY if a measured
- * walker had more pseudopotential pairs than vmc_ecp.max_pairs (its pairs
- * beyond the capacity were left out).  On these errors the outputs are
+ * a walker with a NaN coordinate); otherwise VMC_ECAPACITY if a measurement
+ * launch had more pseudopotential pairs than its capacity (vmc_ecp.max_pairs;
+ * the pairs beyond it were left out).  On these errors the outputs are
  * still written (they include the offending samples) and VMC_ACCUM_RESET
  * still clears the accumulators and the error state. */
 int vmc_accumulate(vmc_ctx *ctx, double *E, double *F_bare, double *dE_dC,
@@ -469,7 +471,11 @@ int64_t vmc_staging_walkers(const vmc_ctx *ctx);
 #define VMC_K_SWEEP     3    /* k_sweep_r: the moves of one sweep of all walkers */
 #define VMC_K_PROPOSALS 4    /* k_propose + k_mo_rows_mfma (values): a sweep's
                                 proposals and their MO rows                      */
-#define VMC_N_PROFILED  5
+#define VMC_K_ECP_POINTS  5  /* k_ecp_pairs + k_mo_rows_mfma at the quadrature
+                                points of the pseudopotential                    */
+#define VMC_K_ECP_ENERGY  6  /* k_ecp_energy                                     */
+#define VMC_K_ECP_ADJOINT 7  /* k_ecp_adjoint                                    */
+#define VMC_N_PROFILED  8
 int vmc_profile(vmc_ctx *ctx, int32_t enable);
 int vmc_profile_read(vmc_ctx *ctx, int32_t kernel, double *ms, int64_t *launches, int64_t *walkers);
 

@@ -83,7 +83,7 @@ struct vmc_ctx {
     // launch's first walker (or of the listed walkers) and rotation index
     bool has_ecp = false;
     vmcx::EcpDev edev{};
-    int *e_pairs = nullptr, *e_npairs = nullptr;
+    int *e_pairs = nullptr, *e_npairs = nullptr, *e_off = nullptr, *e_nrows = nullptr;
     double *e_qpos = nullptr, *e_phiq = nullptr, *e_rows = nullptr, *e_dR = nullptr;
     int64_t ecp_id0 = 0;
     uint32_t ecp_rot = 0;
@@ -319,13 +319,16 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     prof_end(c, VMC_K_MO_ROWS, pi, st);
     // pseudopotential: the pairs inside the cutoffs, their points and the
     // MO rows there (values; with the adjoint also gradients)
-    const vmcx::EcpBufs<T> eb{c->e_pairs, c->e_npairs, c->e_qpos, (T *)c->e_phiq, c->e_rows, c->e_dR};
+    const vmcx::EcpBufs<T> eb{c->e_pairs, c->e_npairs, c->e_off,  c->e_nrows,
+                              c->e_qpos,  (T *)c->e_phiq, c->e_rows, c->e_dR};
     const int enc = full ? 5 : 1;
     if (c->has_ecp) {
+        pi = prof_begin(c, VMC_K_ECP_POINTS, prof, cw, st);
         HIP_OK(c, vmcx::launch_ecp_pairs(S, c->edev, R, pos, (int)cw, c->ecp_id0, c->ecp_idlist, c->ecp_rot,
-                                         c->e_pairs, c->e_npairs, c->e_qpos, c->status, st));
+                                         c->e_pairs, c->e_npairs, c->e_off, c->e_nrows, c->e_qpos, c->status, st));
         HIP_OK(c, vmcx::launch_mo_rows_mfma<T>(S, C, R, c->e_qpos, cw * c->edev.pcap * 12, c->tiles16,
-                                               (T *)c->e_phiq, enc, (T *)c->d_cpad, st));
+                                               (T *)c->e_phiq, enc, (T *)c->d_cpad, st, c->e_nrows));
+        prof_end(c, VMC_K_ECP_POINTS, pi, st);
     }
     const int64_t jrows = cw * c->N;
     T *jX = (T *)c->jm_X, *jO = (T *)c->jm_O;
@@ -342,17 +345,22 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     pi = prof_begin(c, VMC_K_DENSE, prof, cw, st);
     HIP_OK(c, vmcx::launch_dense<T>(S, R, mb, o, c->status, c->dl, (int)cw, st));
     prof_end(c, VMC_K_DENSE, pi, st);
-    if (c->has_ecp)
+    if (c->has_ecp) {
+        pi = prof_begin(c, VMC_K_ECP_ENERGY, prof, cw, st);
         HIP_OK(c, vmcx::launch_ecp_energy<T>(S, c->edev, R, pos, (int)cw, eb, enc, mb.ktil, full ? mb.abar : nullptr,
                                              o.EL, c->status, st));
+        prof_end(c, VMC_K_ECP_ENERGY, pi, st);
+    }
     if (!full) return VMC_OK;
     pi = prof_begin(c, VMC_K_ADJOINT, prof, cw, st);
     HIP_OK(c, vmcx::launch_adjoint<T>(S, C, R, mb, o, al, (int)cw, st));
     prof_end(c, VMC_K_ADJOINT, pi, st);
     MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
     if (c->has_ecp) {
+        pi = prof_begin(c, VMC_K_ECP_ADJOINT, prof, cw, st);
         HIP_OK(c, vmcx::launch_ecp_adjoint<T>(S, c->edev, C, R, pos, (int)cw, eb, mb.ktil, o.G, o.Gf, c->mb_dpart,
                                               st));
+        prof_end(c, VMC_K_ECP_ADJOINT, pi, st);
         md.ecp_dR = c->e_dR;
     }
     if (c->MJ > 0) {
@@ -965,7 +973,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     // (with a pseudopotential: its pairs, points, the MO rows and values kept
     // per point, and the per-nucleus derivative)
     const int64_t eq = c->has_ecp ? (int64_t)c->edev.pcap * 12 : 0;
-    const int64_t ecp_pw = c->has_ecp ? eq * (3 + 5 * (int64_t)c->n_occ + vmcx::ECP_ROW) + A3 + c->edev.pcap + 1 : 0;
+    const int64_t ecp_pw = c->has_ecp ? eq * (3 + 5 * (int64_t)c->n_occ + vmcx::ECP_ROW) + A3 + c->edev.pcap + 2 : 0;
     const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
                                                         3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw + ecp_pw);
     int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
@@ -1005,7 +1013,8 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     }
     if (c->has_ecp) {
         if ((rc = c->dalloc(&c->e_pairs, (size_t)chunk * c->edev.pcap)) ||
-            (rc = c->dalloc(&c->e_npairs, (size_t)chunk)) || (rc = c->dalloc(&c->e_qpos, (size_t)chunk * eq * 3)) ||
+            (rc = c->dalloc(&c->e_npairs, (size_t)chunk)) || (rc = c->dalloc(&c->e_off, (size_t)chunk)) ||
+            (rc = c->dalloc(&c->e_nrows, 1)) || (rc = c->dalloc(&c->e_qpos, (size_t)chunk * eq * 3)) ||
             (rc = c->dalloc(&c->e_phiq, (size_t)chunk * eq * 5 * c->n_occ)) ||
             (rc = c->dalloc(&c->e_rows, (size_t)chunk * eq * vmcx::ECP_ROW)) ||
             (rc = c->dalloc(&c->e_dR, (size_t)chunk * A3)))
@@ -1145,7 +1154,8 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
     if (status & vmcx::STATUS_SINGULAR) return c->fail(VMC_ESINGULAR, "a Slater block was singular to working precision");
     if (status & vmcx::STATUS_NONFINITE) return c->fail(VMC_ENONFINITE, "non-finite local energy or ln|Psi|");
     if (status & vmcx::STATUS_CAPACITY)
-        return c->fail(VMC_ECAPACITY, "a walker had more pseudopotential pairs than the capacity (%d)", c->edev.pcap);
+        return c->fail(VMC_ECAPACITY, "a measurement launch had more pseudopotential pairs than its capacity (%d per "
+                                      "walker)", c->edev.pcap);
     return VMC_OK;
 }
 

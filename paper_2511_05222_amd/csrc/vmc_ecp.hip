@@ -9,9 +9,11 @@
 // over the 12 icosahedron vertices v_q turned by one random rotation per
 // (walker, electron), dJ_q the change of the two-body Jastrow.  Three kernels
 // around the measurement:
-//   k_ecp_pairs    the (electron, nucleus) pairs inside the cutoffs and their
-//                  12 points each; the MO rows at the points are then one
-//                  k_mo_rows_mfma launch;
+//   k_ecp_count / k_ecp_scan / k_ecp_place
+//                  the (electron, nucleus) pairs inside the cutoffs, packed
+//                  over the walkers of a launch, and their 12 points each;
+//                  the MO rows at the points are then one k_mo_rows_mfma
+//                  launch over the packed rows;
 //   k_ecp_energy   after k_dense: rho_q, E_loc + E_nl added to E_L; and, with
 //                  Z[j][i] = sum_q c'_q phi_q[j] (c'_q = c_q exp(dJ_q), the
 //                  points of electron i), the derivative through the inverses,
@@ -90,26 +92,75 @@ __device__ inline double legendre_d(int l, double x) {
 }
 
 // ---------------------------------------------------------------------------
-// Pairs inside the cutoffs (in electron order, then the order of the nuclei
-// with projectors) and their points; rows past a walker's pairs get its
-// first electron's position (finite, never used).
+// Pairs inside the cutoffs, packed over the walkers of a launch: the count
+// per walker, the offsets (one block, in walker order), then the pairs (in
+// electron order, then the order of the nuclei with projectors) and their
+// points.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(128) void k_ecp_pairs(SysDev S, EcpDev E, const double *__restrict__ R,
-                                                   const double *__restrict__ pos, int64_t id0,
-                                                   const int *__restrict__ idlist, uint32_t rot, int *pairs,
-                                                   int *npairs, double *qpos, int *status) {
+__device__ inline int ecp_inside(const EcpDev &E, const double *R, int a, double x, double y, double z) {
+    const double dx = x - R[3 * a], dy = y - R[3 * a + 1], dz = z - R[3 * a + 2];
+    return sqrt(dx * dx + dy * dy + dz * dz) < E.rcut[a] ? 1 : 0;
+}
+
+__global__ __launch_bounds__(128) void k_ecp_count(SysDev S, EcpDev E, const double *__restrict__ R,
+                                                   const double *__restrict__ pos, int *npairs) {
     __shared__ int cnt[128];
-    __shared__ int tot;
-    const int w = blockIdx.x, tid = threadIdx.x, N = S.N, P = E.pcap;
+    const int w = blockIdx.x, tid = threadIdx.x, N = S.N;
     const double *p = pos + (size_t)w * N * 3;
     int c = 0;
     if (tid < N)
-        for (int k = 0; k < E.n_nl; ++k) {
-            const int a = E.nl_atom[k];
-            const double dx = p[3 * tid] - R[3 * a], dy = p[3 * tid + 1] - R[3 * a + 1],
-                         dz = p[3 * tid + 2] - R[3 * a + 2];
-            if (sqrt(dx * dx + dy * dy + dz * dz) < E.rcut[a]) ++c;
+        for (int k = 0; k < E.n_nl; ++k) c += ecp_inside(E, R, E.nl_atom[k], p[3 * tid], p[3 * tid + 1], p[3 * tid + 2]);
+    cnt[tid] = c;
+    __syncthreads();
+    if (tid == 0) {
+        int s = 0;
+        for (int i = 0; i < N; ++i) s += cnt[i];
+        npairs[w] = s;
+    }
+}
+
+// off[w] = pairs of the walkers before w; a walker's pairs past the
+// launch's capacity are dropped (and flagged); *nrows = 12 * the pairs kept.
+__global__ __launch_bounds__(1024) void k_ecp_scan(int W, int64_t cap, int *npairs, int *off, int *nrows,
+                                                   int *status) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int seg = (W + 1023) / 1024, w0 = tid * seg, w1 = min(W, w0 + seg);
+    int64_t s = 0;
+    for (int w = w0; w < w1; ++w) s += npairs[w];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t t = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const int64_t v = part[i];
+            part[i] = t;
+            t += v;
         }
+        *nrows = (int)(12 * min(t, cap));
+        if (t > cap) atomicOr(status, STATUS_CAPACITY);
+    }
+    __syncthreads();
+    int64_t o = part[tid];
+    for (int w = w0; w < w1; ++w) {
+        const int c = npairs[w];
+        off[w] = (int)min(o, cap);
+        npairs[w] = (int)max((int64_t)0, min((int64_t)c, cap - o));
+        o += c;
+    }
+}
+
+__global__ __launch_bounds__(128) void k_ecp_place(SysDev S, EcpDev E, const double *__restrict__ R,
+                                                   const double *__restrict__ pos, int64_t id0,
+                                                   const int *__restrict__ idlist, uint32_t rot,
+                                                   const int *__restrict__ npairs, const int *__restrict__ off,
+                                                   int *pairs, double *qpos) {
+    __shared__ int cnt[128];
+    const int w = blockIdx.x, tid = threadIdx.x, N = S.N;
+    const double *p = pos + (size_t)w * N * 3;
+    int c = 0;
+    if (tid < N)
+        for (int k = 0; k < E.n_nl; ++k) c += ecp_inside(E, R, E.nl_atom[k], p[3 * tid], p[3 * tid + 1], p[3 * tid + 2]);
     cnt[tid] = c;
     __syncthreads();
     if (tid == 0) {
@@ -119,45 +170,34 @@ __global__ __launch_bounds__(128) void k_ecp_pairs(SysDev S, EcpDev E, const dou
             cnt[i] = s;
             s += t;
         }
-        tot = s;
-        npairs[w] = min(s, P);
-        if (s > P) atomicOr(status, STATUS_CAPACITY);
     }
     __syncthreads();
-    int *pw = pairs + (size_t)w * P;
+    const int np = npairs[w], o0 = off[w];
+    int *pw = pairs + o0;
     if (tid < N) {
         int o = cnt[tid];
         for (int k = 0; k < E.n_nl; ++k) {
             const int a = E.nl_atom[k];
-            const double dx = p[3 * tid] - R[3 * a], dy = p[3 * tid + 1] - R[3 * a + 1],
-                         dz = p[3 * tid + 2] - R[3 * a + 2];
-            if (sqrt(dx * dx + dy * dy + dz * dz) < E.rcut[a]) {
-                if (o < P) pw[o] = tid | (a << 8);
+            if (ecp_inside(E, R, a, p[3 * tid], p[3 * tid + 1], p[3 * tid + 2])) {
+                if (o < np) pw[o] = tid | (a << 8);
                 ++o;
             }
         }
     }
     __syncthreads();
-    const int np = min(tot, P);
     const uint32_t wid = (uint32_t)(id0 + (idlist ? idlist[w] : w));
-    double *qp = qpos + (size_t)w * P * 12 * 3;
-    for (int t = tid; t < P * 12; t += 128) {
+    double *qp = qpos + (size_t)o0 * 12 * 3;
+    for (int t = tid; t < np * 12; t += 128) {
         const int pi = t / 12, q = t - 12 * (t / 12);
-        double o0 = p[0], o1 = p[1], o2 = p[2];
-        if (pi < np) {
-            const int pr = pw[pi], e = pr & 255, a = pr >> 8;
-            const double dx = p[3 * e] - R[3 * a], dy = p[3 * e + 1] - R[3 * a + 1], dz = p[3 * e + 2] - R[3 * a + 2];
-            const double d = sqrt(dx * dx + dy * dy + dz * dz);
-            double Rm[9], u[3];
-            ecp_rotation(E.seed, wid, rot, e, Rm);
-            ico_dir(q, u);
-            o0 = R[3 * a] + d * (Rm[0] * u[0] + Rm[1] * u[1] + Rm[2] * u[2]);
-            o1 = R[3 * a + 1] + d * (Rm[3] * u[0] + Rm[4] * u[1] + Rm[5] * u[2]);
-            o2 = R[3 * a + 2] + d * (Rm[6] * u[0] + Rm[7] * u[1] + Rm[8] * u[2]);
-        }
-        qp[3 * t] = o0;
-        qp[3 * t + 1] = o1;
-        qp[3 * t + 2] = o2;
+        const int pr = pw[pi], e = pr & 255, a = pr >> 8;
+        const double dx = p[3 * e] - R[3 * a], dy = p[3 * e + 1] - R[3 * a + 1], dz = p[3 * e + 2] - R[3 * a + 2];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        double Rm[9], u[3];
+        ecp_rotation(E.seed, wid, rot, e, Rm);
+        ico_dir(q, u);
+        qp[3 * t] = R[3 * a] + d * (Rm[0] * u[0] + Rm[1] * u[1] + Rm[2] * u[2]);
+        qp[3 * t + 1] = R[3 * a + 1] + d * (Rm[3] * u[0] + Rm[4] * u[1] + Rm[5] * u[2]);
+        qp[3 * t + 2] = R[3 * a + 2] + d * (Rm[6] * u[0] + Rm[7] * u[1] + Rm[8] * u[2]);
     }
 }
 
@@ -175,7 +215,7 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
                                                     const T *__restrict__ ktil, T *abar, double *EL, int *status) {
     extern __shared__ double sm[];
     const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int N = S.N, n = S.n_occ, P = E.pcap;
+    const int N = S.N, n = S.n_occ;
     double *sp = sm;               // [N][3]
     double *sz = sp + 3 * N;       // [N][n]: Z^T, row i = sum over the points of electron i
     double *sP = sz + N * n;       // [n][n]
@@ -185,11 +225,12 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
         for (int i = tid; i < N * n; i += 256) sz[i] = 0.0;
     __syncthreads();
     const int np = eb.npairs[w];
-    const int *pw = eb.pairs + (size_t)w * P;
-    const T *ph = eb.phiq + (size_t)w * P * 12 * nc * n;
+    const size_t o0 = (size_t)eb.off[w];
+    const int *pw = eb.pairs + o0;
+    const T *ph = eb.phiq + o0 * 12 * nc * n;
     const T *kt = ktil + (size_t)w * N * n;
-    const double *qp = eb.qpos + (size_t)w * P * 12 * 3;
-    double *rw = eb.rows + (size_t)w * P * 12 * ECP_ROW;
+    const double *qp = eb.qpos + o0 * 12 * 3;
+    double *rw = eb.rows + o0 * 12 * ECP_ROW;
     double Ew = 0.0;
     for (int pi = 0; pi < np; ++pi) {
         const int pr = pw[pi], e = pr & 255, a = pr >> 8;
@@ -290,43 +331,93 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
 
 // ---------------------------------------------------------------------------
 // The derivatives through the points.  One block per walker.
-//   phase 1 (threads over AOs mu): G[mu] += sum_q psi_mu(r_q) y_q and the
-//            per-AO sums tc[mu] = sum_q kappa_q,mu grad psi_mu(r_q),
-//            kappa_q = C y_q, over batches of 16 points staged in LDS;
+//   phase 0 (threads over electrons): jo[e] = sum_{j != e} u'(r_ej) (r_e - r_j)/r_ej
+//            and es[e] = the sum of E_q = c'_q t_q over e's points;
+//   phase 1 (threads over (AO mu, slot), the slots splitting the points when
+//            the AOs are fewer than the threads): G[mu] += sum_q psi_mu(r_q) y_q
+//            and tc[mu] = sum_q kappa_q,mu grad psi_mu(r_q), kappa_q = C y_q,
+//            over batches of 16 points staged in LDS; the slots' partials
+//            added in slot order;
 //   phase 2 (threads over points): the chain through r_q = R_a + d v_q, the
-//            weights c_q and the Jastrow at r_q and r_i, into rows[4..9];
-//   phase 3: per electron and per nucleus, fixed-order sums.
+//            weights c_q and the Jastrow at r_q, into rows[4..9];
+//   phase 3 (threads over (electron, slot)): per electron its own points'
+//            terms and the other points' Jastrow terms; per nucleus its
+//            points' terms, V_loc and the AOs at the points (fixed order).
 // ---------------------------------------------------------------------------
-template <typename T>
+__device__ inline double jas_u1(double r, double a, double F, int form) {
+    if (form == 1) return a * exp(-F * r);
+    const double q = 1.0 / (1.0 + F * r);
+    return a * q * q;
+}
+
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T *__restrict__ C,
                                                      const double *__restrict__ R, const double *__restrict__ pos,
                                                      EcpBufs<T> eb, const T *__restrict__ ktil, double *G, float *Gf,
                                                      double *dedr) {
+    constexpr int NW = 16 * NT;
     extern __shared__ double sm[];
     const int w = blockIdx.x, tid = threadIdx.x;
-    const int N = S.N, n = S.n_occ, M = S.M, A = S.A, P = E.pcap;
+    const int N = S.N, n = S.n_occ, M = S.M, A = S.A;
     const BasisDev &B = S.basis;
     double *sp = sm;               // [N][3]
-    double *sy = sp + 3 * N;       // [16][n]
+    double *sjo = sp + 3 * N;      // [N][3]
+    double *ses = sjo + 3 * N;     // [N]
+    double *sy = ses + N;          // [16][n]
     double *sq = sy + 16 * n;      // [16][3]
     double *stc = sq + 48;         // [M][3]
+    double *part = stc + 3 * M;    // [256][16]
     for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
     const int np = eb.npairs[w], nrow = 12 * np;
-    const int *pw = eb.pairs + (size_t)w * P;
-    const T *ph = eb.phiq + (size_t)w * P * 12 * 5 * n;
+    const size_t o0 = (size_t)eb.off[w];
+    const int *pw = eb.pairs + o0;
+    const T *ph = eb.phiq + o0 * 12 * 5 * n;
     const T *kt = ktil + (size_t)w * N * n;
-    const double *qp = eb.qpos + (size_t)w * P * 12 * 3;
-    double *rw = eb.rows + (size_t)w * P * 12 * ECP_ROW;
+    const double *qp = eb.qpos + o0 * 12 * 3;
+    double *rw = eb.rows + o0 * 12 * ECP_ROW;
+    __syncthreads();
+    // ---- phase 0 ----
+    if (tid < N) {
+        const int e = tid;
+        double jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int j = 0; j < N; ++j) {
+            if (j == e) continue;
+            const double sx = sp[3 * e] - sp[3 * j], sy_ = sp[3 * e + 1] - sp[3 * j + 1],
+                         sz_ = sp[3 * e + 2] - sp[3 * j + 2];
+            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
+            const double f = jas_u1(re, S.ee_a, S.ee_F, S.ee_form) / re;
+            jx += f * sx;
+            jy += f * sy_;
+            jz += f * sz_;
+        }
+        sjo[3 * e] = jx;
+        sjo[3 * e + 1] = jy;
+        sjo[3 * e + 2] = jz;
+        double es = 0.0;
+        for (int pi = 0; pi < np; ++pi)
+            if ((pw[pi] & 255) == e)
+                for (int q = 0; q < 12; ++q) {
+                    const double *o = rw + (size_t)(12 * pi + q) * ECP_ROW;
+                    es += o[0] * o[1];
+                }
+        ses[e] = es;
+    }
     // ---- phase 1 ----
-    for (int mu0 = 0; mu0 < M; mu0 += 256) {
-        const int mu = mu0 + tid;
-        const bool vm = mu < M;
+    const int nsl = M < 256 ? 256 / M : 1;
+    const int per = 256 / nsl;
+    for (int mu0 = 0; mu0 < M; mu0 += per) {
+        const int mu = mu0 + tid / nsl, slot = tid - (tid / nsl) * nsl;
+        const bool vm = tid < per * nsl && mu < M;
         const int mm = vm ? mu : M - 1;
         const int s = B.ao_shell[mm], atom = B.shell_atom[s], pwr = B.ao_pow[mm];
         const double eta = B.ao_eta[mm];
-        double g[VMC_MAX_OCC];
+        const double Rx = R[3 * atom], Ry = R[3 * atom + 1], Rz = R[3 * atom + 2];
+        double cr[NW], g[NW];
 #pragma unroll
-        for (int j = 0; j < VMC_MAX_OCC; ++j) g[j] = 0.0;
+        for (int j = 0; j < NW; ++j) {
+            cr[j] = j < n ? (double)C[(size_t)mm * n + j] : 0.0;
+            g[j] = 0.0;
+        }
         double tcx = 0.0, tcy = 0.0, tcz = 0.0;
         for (int r0 = 0; r0 < nrow; r0 += 16) {
             __syncthreads();
@@ -346,9 +437,8 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
             __syncthreads();
             const int nr = min(16, nrow - r0);
             if (!vm) continue;
-            for (int r = 0; r < nr; ++r) {
-                const double dx = sq[3 * r] - R[3 * atom], dy = sq[3 * r + 1] - R[3 * atom + 1],
-                             dz = sq[3 * r + 2] - R[3 * atom + 2];
+            for (int r = slot; r < nr; r += nsl) {
+                const double dx = sq[3 * r] - Rx, dy = sq[3 * r + 1] - Ry, dz = sq[3 * r + 2] - Rz;
                 const double rho = dx * dx + dy * dy + dz * dz;
                 double R0, R1, R2, R3, o[5];
                 shell_radial<5, double>(B, s, rho, R0, R1, R2, R3);
@@ -356,30 +446,45 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
                 double kap = 0.0;
                 const double *y = sy + (size_t)r * n;
 #pragma unroll
-                for (int j = 0; j < VMC_MAX_OCC; ++j)
-                    if (j < n) {
-                        kap += (double)C[(size_t)mu * n + j] * y[j];
-                        g[j] += o[0] * y[j];
-                    }
+                for (int j = 0; j < NW; ++j) {
+                    const double yj = j < n ? y[j] : 0.0;
+                    kap += cr[j] * yj;
+                    g[j] += o[0] * yj;
+                }
                 tcx += kap * o[1];
                 tcy += kap * o[2];
                 tcz += kap * o[3];
             }
         }
-        if (vm) {
+        // the slots' partials, added in slot order (16 columns at a time)
 #pragma unroll
-            for (int j = 0; j < VMC_MAX_OCC; ++j)
-                if (j < n) {
+        for (int c0 = 0; c0 < NW; c0 += 16) {
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; ++j) part[tid * 16 + j] = g[c0 + j];
+            __syncthreads();
+            if (vm && slot == 0)
+                for (int j = c0; j < min(n, c0 + 16); ++j) {
+                    double t = 0.0;
+                    for (int q = 0; q < nsl; ++q) t += part[(tid + q) * 16 + (j - c0)];
                     const size_t o = ((size_t)w * M + mu) * n + j;
                     if (G)
-                        G[o] += g[j];
+                        G[o] += t;
                     else if (Gf)
-                        Gf[o] = (float)((double)Gf[o] + g[j]);
+                        Gf[o] = (float)((double)Gf[o] + t);
                 }
-            stc[3 * mu] = tcx;
-            stc[3 * mu + 1] = tcy;
-            stc[3 * mu + 2] = tcz;
         }
+        __syncthreads();
+        part[3 * tid] = tcx;
+        part[3 * tid + 1] = tcy;
+        part[3 * tid + 2] = tcz;
+        __syncthreads();
+        if (vm && slot == 0)
+            for (int k = 0; k < 3; ++k) {
+                double t = 0.0;
+                for (int q = 0; q < nsl; ++q) t += part[3 * (tid + q) + k];
+                stc[3 * mu + k] = t;
+            }
     }
     __syncthreads();
     // ---- phase 2 ----
@@ -404,22 +509,16 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
             g[1] += kj * (double)pr5[2 * n + j];
             g[2] += kj * (double)pr5[3 * n + j];
         }
-        // through the Jastrow at r_q, and its pair terms at r_e
-        double gj[3] = {0.0, 0.0, 0.0}, jo[3] = {0.0, 0.0, 0.0};
+        // through the Jastrow at r_q
+        double gj[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j < N; ++j) {
             if (j == e) continue;
             const double qx = px - sp[3 * j], qy = py - sp[3 * j + 1], qz = pz - sp[3 * j + 2];
             const double rq = sqrt(qx * qx + qy * qy + qz * qz);
-            const double fq = jas_all(rq, S.ee_a, S.ee_F, S.ee_form).u1 / rq;
+            const double fq = jas_u1(rq, S.ee_a, S.ee_F, S.ee_form) / rq;
             gj[0] += fq * qx;
             gj[1] += fq * qy;
             gj[2] += fq * qz;
-            const double sx = ex - sp[3 * j], sy_ = ey - sp[3 * j + 1], sz_ = ez - sp[3 * j + 2];
-            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
-            const double fe = jas_all(re, S.ee_a, S.ee_F, S.ee_form).u1 / re;
-            jo[0] += fe * sx;
-            jo[1] += fe * sy_;
-            jo[2] += fe * sz_;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) g[k] = cq * g[k] + Eq * gj[k];
@@ -436,36 +535,56 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
         const double gv = g[0] * v[0] + g[1] * v[1] + g[2] * v[2];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            o[4 + k] = gv * u[k] + hq * dc[k] - Eq * jo[k];     // to r_e
-            o[7 + k] = g[k] - gv * u[k] - hq * dc[k];           // to R_a
+            o[4 + k] = gv * u[k] + hq * dc[k] - Eq * sjo[3 * e + k];   // to r_e
+            o[7 + k] = g[k] - gv * u[k] - hq * dc[k];                  // to R_a
         }
     }
     __syncthreads();
-    // ---- phase 3 ----
+    // ---- phase 3: electrons, (electron, slot) over the points ----
+    const int esl = 256 / N;
+    {
+        const int j = tid / esl, slot = tid - (tid / esl) * esl;
+        double s3[3] = {0.0, 0.0, 0.0};
+        if (j < N) {
+            const double xj = sp[3 * j], yj = sp[3 * j + 1], zj = sp[3 * j + 2];
+            for (int row = slot; row < nrow; row += esl) {
+                const double *o = rw + (size_t)row * ECP_ROW;
+                if ((pw[row / 12] & 255) == j) {
+                    s3[0] += o[4];
+                    s3[1] += o[5];
+                    s3[2] += o[6];
+                    continue;
+                }
+                // the Jastrow change of another electron's point, through r_j
+                const double Eq = o[0] * o[1];
+                const double qx = qp[3 * row] - xj, qy = qp[3 * row + 1] - yj, qz = qp[3 * row + 2] - zj;
+                const double rq = sqrt(qx * qx + qy * qy + qz * qz);
+                const double fq = Eq * jas_u1(rq, S.ee_a, S.ee_F, S.ee_form) / rq;
+                s3[0] -= fq * qx;
+                s3[1] -= fq * qy;
+                s3[2] -= fq * qz;
+            }
+        }
+        part[3 * tid] = s3[0];
+        part[3 * tid + 1] = s3[1];
+        part[3 * tid + 2] = s3[2];
+    }
+    __syncthreads();
     if (tid < N) {
         const int j = tid;
+        double s3[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < esl; ++q)
+            for (int k = 0; k < 3; ++k) s3[k] += part[3 * (j * esl + q) + k];
         const double xj = sp[3 * j], yj = sp[3 * j + 1], zj = sp[3 * j + 2];
-        double s[3] = {0.0, 0.0, 0.0};
-        for (int row = 0; row < nrow; ++row) {
-            const double *o = rw + (size_t)row * ECP_ROW;
-            const int e = pw[row / 12] & 255;
-            if (e == j) {
-                s[0] += o[4];
-                s[1] += o[5];
-                s[2] += o[6];
-                continue;
-            }
-            // the Jastrow change of e's point depends on r_j through two pair terms
-            const double Eq = o[0] * o[1];
-            const double qx = qp[3 * row] - xj, qy = qp[3 * row + 1] - yj, qz = qp[3 * row + 2] - zj;
-            const double rq = sqrt(qx * qx + qy * qy + qz * qz);
-            const double fq = jas_all(rq, S.ee_a, S.ee_F, S.ee_form).u1 / rq;
+        // ... and through r_j in the pair terms at the other electrons' own positions
+        for (int e = 0; e < N; ++e) {
+            if (e == j || ses[e] == 0.0) continue;
             const double sx = sp[3 * e] - xj, sy_ = sp[3 * e + 1] - yj, sz_ = sp[3 * e + 2] - zj;
             const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
-            const double fe = jas_all(re, S.ee_a, S.ee_F, S.ee_form).u1 / re;
-            s[0] += Eq * (fe * sx - fq * qx);
-            s[1] += Eq * (fe * sy_ - fq * qy);
-            s[2] += Eq * (fe * sz_ - fq * qz);
+            const double fe = ses[e] * jas_u1(re, S.ee_a, S.ee_F, S.ee_form) / re;
+            s3[0] += fe * sx;
+            s3[1] += fe * sy_;
+            s3[2] += fe * sz_;
         }
         for (int a = 0; a < A; ++a) {
             if (E.t0[a] == E.t0[a + 1]) continue;
@@ -473,24 +592,26 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
             const double d = sqrt(dx * dx + dy * dy + dz * dz);
             double v, dv;
             ecp_radial(E, a, -1, d, v, dv);
-            s[0] += dv * dx / d;
-            s[1] += dv * dy / d;
-            s[2] += dv * dz / d;
+            s3[0] += dv * dx / d;
+            s3[1] += dv * dy / d;
+            s3[2] += dv * dz / d;
         }
         double *de = dedr + ((size_t)w * N + j) * 3;
-        de[0] += s[0];
-        de[1] += s[1];
-        de[2] += s[2];
+        de[0] += s3[0];
+        de[1] += s3[1];
+        de[2] += s3[2];
     }
     if (tid < A) {
         const int a = tid;
-        double s[3] = {0.0, 0.0, 0.0};
-        for (int row = 0; row < nrow; ++row) {
-            if ((pw[row / 12] >> 8) != a) continue;
-            const double *o = rw + (size_t)row * ECP_ROW;
-            s[0] += o[7];
-            s[1] += o[8];
-            s[2] += o[9];
+        double s3[3] = {0.0, 0.0, 0.0};
+        for (int pi = 0; pi < np; ++pi) {
+            if ((pw[pi] >> 8) != a) continue;
+            for (int q = 0; q < 12; ++q) {
+                const double *o = rw + (size_t)(12 * pi + q) * ECP_ROW;
+                s3[0] += o[7];
+                s3[1] += o[8];
+                s3[2] += o[9];
+            }
         }
         if (E.t0[a] != E.t0[a + 1])
             for (int j = 0; j < N; ++j) {
@@ -498,21 +619,21 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
                 const double d = sqrt(dx * dx + dy * dy + dz * dz);
                 double v, dv;
                 ecp_radial(E, a, -1, d, v, dv);
-                s[0] -= dv * dx / d;
-                s[1] -= dv * dy / d;
-                s[2] -= dv * dz / d;
+                s3[0] -= dv * dx / d;
+                s3[1] -= dv * dy / d;
+                s3[2] -= dv * dz / d;
             }
         // the AOs at the points move with their nuclei
         for (int q = B.atom_ao_ptr[a]; q < B.atom_ao_ptr[a + 1]; ++q) {
             const int mu = B.atom_ao[q];
-            s[0] -= stc[3 * mu];
-            s[1] -= stc[3 * mu + 1];
-            s[2] -= stc[3 * mu + 2];
+            s3[0] -= stc[3 * mu];
+            s3[1] -= stc[3 * mu + 1];
+            s3[2] -= stc[3 * mu + 2];
         }
         double *o = eb.ecp_dR + ((size_t)w * A + a) * 3;
-        o[0] = s[0];
-        o[1] = s[1];
-        o[2] = s[2];
+        o[0] = s3[0];
+        o[1] = s3[1];
+        o[2] = s3[2];
     }
 }
 
@@ -520,16 +641,18 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
-                            int64_t id0, const int *idlist, uint32_t rot, int *pairs, int *npairs, double *qpos,
-                            int *status, hipStream_t st) {
+                            int64_t id0, const int *idlist, uint32_t rot, int *pairs, int *npairs, int *off,
+                            int *nrows, double *qpos, int *status, hipStream_t st) {
     if (S.N > 128) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_ecp_pairs, dim3(W), dim3(128), 0, st, S, E, R, pos, id0, idlist, rot, pairs, npairs, qpos,
-                       status);
+    hipLaunchKernelGGL(k_ecp_count, dim3(W), dim3(128), 0, st, S, E, R, pos, npairs);
+    hipLaunchKernelGGL(k_ecp_scan, dim3(1), dim3(1024), 0, st, W, (int64_t)W * E.pcap, npairs, off, nrows, status);
+    hipLaunchKernelGGL(k_ecp_place, dim3(W), dim3(128), 0, st, S, E, R, pos, id0, idlist, rot, npairs, off, pairs,
+                       qpos);
     return hipGetLastError();
 }
 
 static size_t ecp_adjoint_lds(int N, int n, int M) {
-    return sizeof(double) * ((size_t)3 * N + (size_t)16 * n + 48 + (size_t)3 * M);
+    return sizeof(double) * ((size_t)7 * N + (size_t)16 * n + 48 + (size_t)3 * M + 256 * 16);
 }
 
 hipError_t configure_ecp(size_t lds) {
@@ -554,8 +677,16 @@ template <typename T>
 hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, const double *R, const double *pos,
                               int W, const EcpBufs<T> &eb, const T *ktil, double *G, float *Gf, double *dedr,
                               hipStream_t st) {
-    hipLaunchKernelGGL((k_ecp_adjoint<T>), dim3(W), dim3(256), ecp_adjoint_lds(S.N, S.n_occ, S.M), st, S, E, C, R,
-                       pos, eb, ktil, G, Gf, dedr);
+    const size_t lds = ecp_adjoint_lds(S.N, S.n_occ, S.M);
+    const int nt = (S.n_occ + 15) / 16;
+    if (nt == 1)
+        hipLaunchKernelGGL((k_ecp_adjoint<T, 1>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
+    else if (nt == 2)
+        hipLaunchKernelGGL((k_ecp_adjoint<T, 2>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
+    else if (nt == 3)
+        hipLaunchKernelGGL((k_ecp_adjoint<T, 3>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
+    else
+        hipLaunchKernelGGL((k_ecp_adjoint<T, 4>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
     return hipGetLastError();
 }
 

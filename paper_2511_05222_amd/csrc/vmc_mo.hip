@@ -29,7 +29,7 @@ __global__ void k_pad_c(const T *__restrict__ C, int M, int n, T *__restrict__ C
 template <typename T, int NC, int NT>
 __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restrict__ Cp, const double *__restrict__ R,
                                                       const double *__restrict__ pos, int64_t n_rows, AoTiles tiles,
-                                                      T *__restrict__ out) {
+                                                      T *__restrict__ out, const int *__restrict__ rows_dev) {
     constexpr int RB = 64, MT = 16;
     constexpr int RS = MT * NC + 1;    // odd row stride of the AO tile
     constexpr int CS = 80;             // row stride of the C tile (lane groups hit disjoint banks)
@@ -40,6 +40,9 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = S.n_occ;
     const int64_t row0 = (int64_t)blockIdx.x * RB;
+    // (a row count known only on the device: the blocks past it leave)
+    if (rows_dev) n_rows = min(n_rows, (int64_t)*rows_dev);
+    if (row0 >= n_rows) return;
     for (int k = tid; k < RB * 3; k += 256) sp[k] = (row0 + k / 3) < n_rows ? pos[row0 * 3 + k] : 0.0;
     for (int k = tid; k < RB * RS; k += 256) aot[k] = T(0);
     typename MF::acc_t acc[NC][NT];
@@ -101,35 +104,42 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
 
 template <typename T, int NC>
 static hipError_t launch_nc(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
-                            const AoTiles &tiles, T *out, hipStream_t st) {
+                            const AoTiles &tiles, T *out, const int *rows_dev, hipStream_t st) {
     // (C here is the padded copy)
     const dim3 g((unsigned)((n_rows + 63) / 64));
     const int nt = (S.n_occ + 15) / 16;
     if (nt == 1)
-        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 1>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 1>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out,
+                           rows_dev);
     else if (nt == 2)
-        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 2>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 2>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out,
+                           rows_dev);
     else if (nt == 3)
-        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 3>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 3>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out,
+                           rows_dev);
     else
-        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 4>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out);
+        hipLaunchKernelGGL((k_mo_rows_mfma<T, NC, 4>), g, dim3(256), 0, st, S, C, R, pos, n_rows, tiles, out,
+                           rows_dev);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
-                               const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st) {
+                               const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st,
+                               const int *rows_dev) {
     if (S.n_occ > 64) return hipErrorInvalidValue;
     const int np = (S.M + 16) * 64;
     hipLaunchKernelGGL(k_pad_c<T>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, C, S.M, S.n_occ, cpad);
-    return nc == 1 ? launch_nc<T, 1>(S, cpad, R, pos, n_rows, tiles16, out, st)
-                   : launch_nc<T, 5>(S, cpad, R, pos, n_rows, tiles16, out, st);
+    return nc == 1 ? launch_nc<T, 1>(S, cpad, R, pos, n_rows, tiles16, out, rows_dev, st)
+                   : launch_nc<T, 5>(S, cpad, R, pos, n_rows, tiles16, out, rows_dev, st);
 }
 
 template hipError_t launch_mo_rows_mfma<double>(const SysDev &, const double *, const double *, const double *,
-                                                int64_t, const AoTiles &, double *, int, double *, hipStream_t);
+                                                int64_t, const AoTiles &, double *, int, double *, hipStream_t,
+                                                const int *);
 
 template hipError_t launch_mo_rows_mfma<float>(const SysDev &, const float *, const double *, const double *,
-                                               int64_t, const AoTiles &, float *, int, float *, hipStream_t);
+                                               int64_t, const AoTiles &, float *, int, float *, hipStream_t,
+                                               const int *);
 
 }  // namespace vmcx

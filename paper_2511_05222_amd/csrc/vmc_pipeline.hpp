@@ -88,23 +88,25 @@ struct EcpDev {
     int pcap;                  // (electron, nucleus) pairs per walker
 };
 
-// Staging of the pseudopotential terms of one measurement launch (W walkers):
-// pairs[W][pcap] = electron | nucleus << 8, npairs[W], the points
-// qpos[W][pcap * 12][3], the MO rows there phiq[W][pcap * 12][nc][n] (type
-// T), per point rows[W][pcap * 12][ECP_ROW] and ecp_dR[W][A][3].
+// Staging of the pseudopotential terms of one measurement launch of W
+// walkers, packed over the walkers (capacity W * pcap pairs): walker w's
+// pairs are pairs[off[w] .. off[w] + npairs[w]) (electron | nucleus << 8),
+// its points qpos[12 off[w] ..][3], the MO rows there phiq[12 off[w] ..][nc][n]
+// (type T) and per point rows[12 off[w] ..][ECP_ROW]; *nrows = 12 * the
+// pairs of the launch; ecp_dR[W][A][3].
 constexpr int ECP_ROW = 10;
 template <typename T>
 struct EcpBufs {
-    int *pairs, *npairs;
+    int *pairs, *npairs, *off, *nrows;
     double *qpos;
     T *phiq;
     double *rows;
     double *ecp_dR;
 };
-// Pairs and points of walker w (walker id id0 + w, or id0 + idlist[w]).
+// Pairs and points of the W walkers (walker id id0 + w, or id0 + idlist[w]).
 hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
-                            int64_t id0, const int *idlist, uint32_t rot, int *pairs, int *npairs, double *qpos,
-                            int *status, hipStream_t st);
+                            int64_t id0, const int *idlist, uint32_t rot, int *pairs, int *npairs, int *off,
+                            int *nrows, double *qpos, int *status, hipStream_t st);
 // LDS the energy kernel needs (bytes), and raising the limits to it
 size_t ecp_energy_lds(int N, int n);
 hipError_t configure_ecp(size_t lds);
@@ -120,10 +122,12 @@ hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, cons
                               int W, const EcpBufs<T> &eb, const T *ktil, double *G, float *Gf, double *dedr,
                               hipStream_t st);
 
-// cpad: scratch of (M + 16) * 64 elements for the padded copy of C (n_occ <= 64)
+// cpad: scratch of (M + 16) * 64 elements for the padded copy of C (n_occ <= 64);
+// rows_dev (optional): a device count that caps n_rows
 template <typename T>
 hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, const double *pos, int64_t n_rows,
-                               const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st);
+                               const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st,
+                               const int *rows_dev = nullptr);
 // One-/three-body Jastrow terms (vmc_jastrow.hip).  jas_values: out[row][mu]
 // = chi_mu(pos[row]).  jas_products: for each of the nq column blocks q of
 // [xi3 | xi1] ([nq][MJ][64] in xiblk) the nc derivative components' products,
