@@ -30,6 +30,9 @@ Also in the line:
   ecp_9atom      the pseudopotential workload (the 9-atom molecule made
                  valence-only with a seeded semilocal pseudopotential, 16384
                  walkers, both precisions) with its kernels' rooflines;
+  family_64      the 64-geometry mixed-size family (9-21 atoms, 8192 walkers
+                 each, mixed precision), one context per geometry, their
+                 sweeps on four streams (and on one, for comparison);
   cpu_baseline   the FP64 oracle on a bounded sample of the same molecule on
                  the host cores (unless --no-cpu-baseline).
 """
@@ -277,6 +280,54 @@ def ecp_entry(args, dev):
     return out
 
 
+def family_entry(args, dev, n_streams=4):
+    """The mixed-size family: 64 seeded geometries of 9-21 atoms, 8192
+    walkers each, mixed precision, one context per geometry.  Every context
+    runs its sweeps (with measurement) on one of n_streams streams in turn,
+    so that the small members' launches overlap; the same with one stream
+    for comparison.  value = 64 x 8192 x steps / seconds."""
+    import torch
+    from paper_2511_05222_amd import inputs, vmc
+    G = inputs.FAMILY_SIZE
+    specs = [inputs.family_member(g) for g in range(G)]
+    ctxs, ws = [], []
+    for sp in specs:
+        ctxs.append(vmc.Context(sp.molecule, max_walkers=sp.n_walkers, refresh_period=32, precision="mixed",
+                                staging_walkers=4096))
+        ws.append(torch.tensor(inputs.initial_walkers(sp.molecule, sp.n_walkers, sp.seed), device=dev))
+    walkers = sum(sp.n_walkers for sp in specs)
+    out = {"workload": f"{G} seeded geometries of {min(inputs.family_sizes())}-{max(inputs.family_sizes())} atoms, "
+                       f"8192 walkers each ({walkers} in all), mixed precision, one context per geometry"}
+    off = 0
+    for ns in (n_streams, 1):
+        streams = [torch.cuda.Stream() for _ in range(ns)]
+
+        def run(nsteps, offset):
+            for g, (c, w) in enumerate(zip(ctxs, ws)):
+                with torch.cuda.stream(streams[g % ns]):
+                    c.sweep(w, nsteps, specs[g].seed + g, sweep_offset=offset)
+
+        run(2, off)
+        torch.cuda.synchronize()
+        for c in ctxs:
+            c.accumulate(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(args.steps, off + 2)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        off += 2 + args.steps
+        for c in ctxs:
+            c.accumulate(reset=True)
+        out[f"streams_{ns}"] = {"value": walkers * args.steps / dt, "ms_per_step": dt / args.steps * 1e3}
+        print(f"# family, {ns} streams: {walkers * args.steps / dt:.4g} walker-steps/s, "
+              f"{dt / args.steps * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    out["value"] = out[f"streams_{n_streams}"]["value"]
+    out["unit"] = "walker-steps/s"
+    del ctxs, ws
+    return out
+
+
 def error_table(mol, W_sub, walkers, ctx32, ctx64):
     """Mixed vs FP64 on the same configurations."""
     import torch
@@ -320,6 +371,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference run and the error table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ecp", action="store_true", help="skip the pseudopotential workload")
+    ap.add_argument("--no-family", action="store_true", help="skip the 64-geometry mixed-size family")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the measurement and a plain copy of known size (for counter runs)")
     args = ap.parse_args()
@@ -438,6 +490,9 @@ def main():
         del c9, w9
     if args.workload == "21atom" and not args.no_ecp:
         line["ecp_9atom"] = ecp_entry(args, dev)
+    if args.workload == "21atom" and not args.no_family:
+        del ctx
+        line["family_64"] = family_entry(args, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(line), flush=True)
