@@ -12,10 +12,15 @@ Bounds, on replayed configurations (identical positions for both precisions):
                                                       oracle accumulator)
 The per-walker error of E_L is FP32 round-off, about 1e-4 Ha at 21 atoms:
 the Laplacians of the tight Gaussians reach |lap psi| ~ 1e4 near the nuclei,
-so each MO Laplacian carries an absolute rounding of order 1e4 * 2^-24.  It
-is unbiased, so walker averages shrink as 1/sqrt(W); the energy and force
-bounds are therefore checked on 16384 walkers (a quarter of the production
-batch).  The dE/dC bound is derived from the arithmetic: each O and G entry
+so each MO Laplacian carries an absolute rounding of order 1e4 * 2^-24.  Its
+random part averages away as 1/sqrt(W), but the walker average also carries
+a systematic shift: the mixed E_L is lower by about 4e-6 to 7e-6 Ha on
+equilibrated 21-atom walkers (second order in the orbital values' rounding,
+through the inverse), which does not shrink with W.  It comes from the FP32
+evaluation of the AO derivative components: summing the AO-to-MO products in
+FP64 instead of FP32 leaves it unchanged.  The bounds are checked on 16384
+walkers (a quarter of the production batch), and the shift (the mean of the
+per-walker differences) is printed for every case.  The dE/dC bound is derived from the arithmetic: each O and G entry
 is an FP32 sum of N products with a relative error of order sqrt(N) 2^-24
 per walker, and the covariance 2(<E O> - <E><O>) cancels the mean part of O,
 which is 1e2-1e3 times larger than the covariance for these inputs: 1e-3 of
