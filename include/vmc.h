@@ -58,8 +58,11 @@ extern "C" {
 
 /* ---- precision modes ------------------------------------------------------ */
 #define VMC_FP64   0         /* every step in FP64                              */
-#define VMC_MIXED  1         /* FP32 AO evaluation, MO products on FP32 MFMA,
-                                FP32 Sherman-Morrison, acceptance ratio (its
+#define VMC_MIXED  1         /* FP32 AO values (the measurement's value,
+                                gradient and Laplacian components formed in
+                                FP64 around an FP32 exponential and rounded
+                                once), MO products on FP32 MFMA, FP32
+                                Sherman-Morrison, acceptance ratio (its
                                 Jastrow difference included) and
                                 back-projection; FP64 inverse refresh,
                                 determinants, E_L assembly with its Jastrow

@@ -26,6 +26,50 @@ __global__ void k_pad_c(const T *__restrict__ C, int M, int n, T *__restrict__ C
     Cp[k] = (mu < M && i < n) ? C[(size_t)mu * n + i] : T(0);
 }
 
+// All cartesian components of shell s at one position, evaluated in FP64 and
+// rounded once to FP32 (the angular momentum fixed at compile time per
+// branch, so that the FP64 values stay in registers).  For the FP32
+// measurement rows: components formed in FP32 from FP32 radial sums lose
+// digits to cancellation (the Laplacian near its radial nodes), and that
+// rounding, second order through the inverse, shifts the walker-averaged
+// E_L by several 1e-6 Ha; formed in FP64 and rounded once they leave a few
+// 1e-7 Ha.
+template <int NC, int L>
+__device__ inline void shell_round_l(const BasisDev &B, int mu0, double x, double y, double z, double rho, double R0,
+                                     double R1, double R2, double R3, float *dst) {
+    double t[(L + 1) * (L + 2) / 2 * NC];
+    shell_components<NC, double, L>(B, mu0, x, y, z, rho, R0, R1, R2, R3, t);
+#pragma unroll
+    for (int i = 0; i < (L + 1) * (L + 2) / 2 * NC; ++i) dst[i] = (float)t[i];
+}
+
+template <int NC>
+__device__ inline void shell_eval_rounded(const BasisDev &B, const double *R, int s, double rx, double ry, double rz,
+                                          float *dst) {
+    const int atom = ldc(B.shell_atom + s);
+    const double x = rx - ldc(R + 3 * atom), y = ry - ldc(R + 3 * atom + 1), z = rz - ldc(R + 3 * atom + 2);
+    const double rho = x * x + y * y + z * z;
+    // radial sums in FP64 around the FP32 exponential of the split argument
+    // (its relative error, ~1e-7, is the one the FP32 path has; the
+    // derivative combinations below are where FP32 would lose digits)
+    double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0;
+    const int p0 = ldc(B.shell_p0 + s), np = ldc(B.shell_np + s);
+    for (int k = 0; k < np; ++k) {
+        const double al = ldc(B.prim_exp + p0 + k);
+        const double e = ldc(B.prim_cp + p0 + k) * (double)exp_neg(al, rho, 0.0f);
+        R0 += e;
+        R1 -= al * e;
+        R2 += al * al * e;
+    }
+    const int l = ldc(B.shell_l + s), mu0 = ldc(B.shell_mu0 + s);
+    if (l == 0)
+        shell_round_l<NC, 0>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
+    else if (l == 1)
+        shell_round_l<NC, 1>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
+    else
+        shell_round_l<NC, 2>(B, mu0, x, y, z, rho, R0, R1, R2, R3, dst);
+}
+
 template <typename T, int NC, int NT>
 __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restrict__ Cp, const double *__restrict__ R,
                                                       const double *__restrict__ pos, int64_t n_rows, AoTiles tiles,
@@ -61,8 +105,13 @@ __global__ __launch_bounds__(256) void k_mo_rows_mfma(SysDev S, const T *__restr
         for (int p = tid; p < RB * nsh; p += 256) {
             // p / RB is the same in every lane of a wavefront: scalar tables
             const int s = __builtin_amdgcn_readfirstlane(s0 + p / RB), r = p % RB;
-            shell_eval_to<NC, T>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
-                                 aot + r * RS + (ldc(S.basis.shell_mu0 + s) - mu0) * NC);
+            T *dst = aot + r * RS + (ldc(S.basis.shell_mu0 + s) - mu0) * NC;
+            if constexpr (sizeof(T) == 4 && NC == 5) {
+                // FP32 measurement rows: the AO components in FP64, rounded once
+                shell_eval_rounded<NC>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2], dst);
+            } else {
+                shell_eval_to<NC, T>(S.basis, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2], dst);
+            }
         }
         // C tile: rows of the tile's AOs, zero rows past its last AO
         constexpr int VW = 16 / sizeof(T);
