@@ -84,7 +84,7 @@ struct vmc_ctx {
     bool has_ecp = false;
     vmcx::EcpDev edev{};
     int *e_pairs = nullptr, *e_npairs = nullptr, *e_off = nullptr, *e_nrows = nullptr;
-    double *e_qpos = nullptr, *e_phiq = nullptr, *e_rows = nullptr, *e_dR = nullptr;
+    double *e_qpos = nullptr, *e_phiq = nullptr, *e_rows = nullptr, *e_dR = nullptr, *e_tc = nullptr;
     int64_t ecp_id0 = 0;
     uint32_t ecp_rot = 0;
     const int *ecp_idlist = nullptr;
@@ -319,8 +319,8 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     prof_end(c, VMC_K_MO_ROWS, pi, st);
     // pseudopotential: the pairs inside the cutoffs, their points and the
     // MO rows there (values; with the adjoint also gradients)
-    const vmcx::EcpBufs<T> eb{c->e_pairs, c->e_npairs, c->e_off,  c->e_nrows,
-                              c->e_qpos,  (T *)c->e_phiq, c->e_rows, c->e_dR};
+    const vmcx::EcpBufs<T> eb{c->e_pairs, c->e_npairs, c->e_off,  c->e_nrows, c->e_qpos,
+                              (T *)c->e_phiq, c->e_rows, c->e_dR,    c->e_tc};
     const int enc = full ? 5 : 1;
     if (c->has_ecp) {
         pi = prof_begin(c, VMC_K_ECP_POINTS, prof, cw, st);
@@ -973,7 +973,8 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     // (with a pseudopotential: its pairs, points, the MO rows and values kept
     // per point, and the per-nucleus derivative)
     const int64_t eq = c->has_ecp ? (int64_t)c->edev.pcap * 12 : 0;
-    const int64_t ecp_pw = c->has_ecp ? eq * (3 + 5 * (int64_t)c->n_occ + vmcx::ECP_ROW) + A3 + c->edev.pcap + 2 : 0;
+    const int64_t ecp_pw = c->has_ecp ? eq * (3 + 5 * (int64_t)c->n_occ + vmcx::ECP_ROW) + A3 + 3 * M + c->edev.pcap + 2
+                                      : 0;
     const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
                                                         3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw + ecp_pw);
     int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
@@ -1017,7 +1018,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
             (rc = c->dalloc(&c->e_nrows, 1)) || (rc = c->dalloc(&c->e_qpos, (size_t)chunk * eq * 3)) ||
             (rc = c->dalloc(&c->e_phiq, (size_t)chunk * eq * 5 * c->n_occ)) ||
             (rc = c->dalloc(&c->e_rows, (size_t)chunk * eq * vmcx::ECP_ROW)) ||
-            (rc = c->dalloc(&c->e_dR, (size_t)chunk * A3)))
+            (rc = c->dalloc(&c->e_dR, (size_t)chunk * A3)) || (rc = c->dalloc(&c->e_tc, (size_t)chunk * 3 * M)))
             return bail(rc);
     }
     if (opt->precision == VMC_MIXED && opt->promote_fraction > 0.0) {

@@ -330,19 +330,20 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
 }
 
 // ---------------------------------------------------------------------------
-// The derivatives through the points.  One block per walker.
+// The derivatives through the points, two kernels with one block per walker.
+// k_ecp_points_ao (threads over (AO mu, slot), the slots splitting the
+//   points when the AOs are fewer than the threads): G[mu] += sum_q
+//   psi_mu(r_q) y_q and tc[mu] = sum_q kappa_q,mu grad psi_mu(r_q),
+//   kappa_q = C y_q, over batches of 16 points staged in LDS; the slots'
+//   partials added in slot order.
+// k_ecp_chain:
 //   phase 0 (threads over electrons): jo[e] = sum_{j != e} u'(r_ej) (r_e - r_j)/r_ej
 //            and es[e] = the sum of E_q = c'_q t_q over e's points;
-//   phase 1 (threads over (AO mu, slot), the slots splitting the points when
-//            the AOs are fewer than the threads): G[mu] += sum_q psi_mu(r_q) y_q
-//            and tc[mu] = sum_q kappa_q,mu grad psi_mu(r_q), kappa_q = C y_q,
-//            over batches of 16 points staged in LDS; the slots' partials
-//            added in slot order;
 //   phase 2 (threads over points): the chain through r_q = R_a + d v_q, the
 //            weights c_q and the Jastrow at r_q, into rows[4..9];
 //   phase 3 (threads over (electron, slot)): per electron its own points'
 //            terms and the other points' Jastrow terms; per nucleus its
-//            points' terms, V_loc and the AOs at the points (fixed order).
+//            points' terms, V_loc and the AOs at the points (tc; fixed order).
 // ---------------------------------------------------------------------------
 __device__ inline double jas_u1(double r, double a, double F, int form) {
     if (form == 1) return a * exp(-F * r);
@@ -351,58 +352,24 @@ __device__ inline double jas_u1(double r, double a, double F, int form) {
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T *__restrict__ C,
-                                                     const double *__restrict__ R, const double *__restrict__ pos,
-                                                     EcpBufs<T> eb, const T *__restrict__ ktil, double *G, float *Gf,
-                                                     double *dedr) {
+__global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__restrict__ C,
+                                                       const double *__restrict__ R, EcpBufs<T> eb,
+                                                       const T *__restrict__ ktil, double *G, float *Gf) {
     constexpr int NW = 16 * NT;
     extern __shared__ double sm[];
     const int w = blockIdx.x, tid = threadIdx.x;
-    const int N = S.N, n = S.n_occ, M = S.M, A = S.A;
+    const int N = S.N, n = S.n_occ, M = S.M;
     const BasisDev &B = S.basis;
-    double *sp = sm;               // [N][3]
-    double *sjo = sp + 3 * N;      // [N][3]
-    double *ses = sjo + 3 * N;     // [N]
-    double *sy = ses + N;          // [16][n]
+    double *sy = sm;               // [16][n]
     double *sq = sy + 16 * n;      // [16][3]
-    double *stc = sq + 48;         // [M][3]
-    double *part = stc + 3 * M;    // [256][16]
-    for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
+    double *part = sq + 48;        // [256][16]
     const int np = eb.npairs[w], nrow = 12 * np;
     const size_t o0 = (size_t)eb.off[w];
     const int *pw = eb.pairs + o0;
-    const T *ph = eb.phiq + o0 * 12 * 5 * n;
     const T *kt = ktil + (size_t)w * N * n;
     const double *qp = eb.qpos + o0 * 12 * 3;
-    double *rw = eb.rows + o0 * 12 * ECP_ROW;
-    __syncthreads();
-    // ---- phase 0 ----
-    if (tid < N) {
-        const int e = tid;
-        double jx = 0.0, jy = 0.0, jz = 0.0;
-        for (int j = 0; j < N; ++j) {
-            if (j == e) continue;
-            const double sx = sp[3 * e] - sp[3 * j], sy_ = sp[3 * e + 1] - sp[3 * j + 1],
-                         sz_ = sp[3 * e + 2] - sp[3 * j + 2];
-            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
-            const double f = jas_u1(re, S.ee_a, S.ee_F, S.ee_form) / re;
-            jx += f * sx;
-            jy += f * sy_;
-            jz += f * sz_;
-        }
-        sjo[3 * e] = jx;
-        sjo[3 * e + 1] = jy;
-        sjo[3 * e + 2] = jz;
-        double es = 0.0;
-        for (int pi = 0; pi < np; ++pi)
-            if ((pw[pi] & 255) == e)
-                for (int q = 0; q < 12; ++q) {
-                    const double *o = rw + (size_t)(12 * pi + q) * ECP_ROW;
-                    es += o[0] * o[1];
-                }
-        ses[e] = es;
-    }
-    // ---- phase 1 ----
+    const double *rw = eb.rows + o0 * 12 * ECP_ROW;
+    double *stc = eb.tc + (size_t)w * M * 3;
     const int nsl = M < 256 ? 256 / M : 1;
     const int per = 256 / nsl;
     for (int mu0 = 0; mu0 < M; mu0 += per) {
@@ -485,6 +452,56 @@ __global__ __launch_bounds__(256) void k_ecp_adjoint(SysDev S, EcpDev E, const T
                 for (int q = 0; q < nsl; ++q) t += part[3 * (tid + q) + k];
                 stc[3 * mu + k] = t;
             }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const double *__restrict__ R,
+                                                   const double *__restrict__ pos, EcpBufs<T> eb,
+                                                   const T *__restrict__ ktil, double *dedr) {
+    extern __shared__ double sm[];
+    const int w = blockIdx.x, tid = threadIdx.x;
+    const int N = S.N, n = S.n_occ, M = S.M, A = S.A;
+    const BasisDev &B = S.basis;
+    double *sp = sm;               // [N][3]
+    double *sjo = sp + 3 * N;      // [N][3]
+    double *ses = sjo + 3 * N;     // [N]
+    double *part = ses + N;        // [256][3]
+    const double *stc = eb.tc + (size_t)w * M * 3;
+    for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
+    const int np = eb.npairs[w], nrow = 12 * np;
+    const size_t o0 = (size_t)eb.off[w];
+    const int *pw = eb.pairs + o0;
+    const T *ph = eb.phiq + o0 * 12 * 5 * n;
+    const T *kt = ktil + (size_t)w * N * n;
+    const double *qp = eb.qpos + o0 * 12 * 3;
+    double *rw = eb.rows + o0 * 12 * ECP_ROW;
+    __syncthreads();
+    // ---- phase 0 ----
+    if (tid < N) {
+        const int e = tid;
+        double jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int j = 0; j < N; ++j) {
+            if (j == e) continue;
+            const double sx = sp[3 * e] - sp[3 * j], sy_ = sp[3 * e + 1] - sp[3 * j + 1],
+                         sz_ = sp[3 * e + 2] - sp[3 * j + 2];
+            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
+            const double f = jas_u1(re, S.ee_a, S.ee_F, S.ee_form) / re;
+            jx += f * sx;
+            jy += f * sy_;
+            jz += f * sz_;
+        }
+        sjo[3 * e] = jx;
+        sjo[3 * e + 1] = jy;
+        sjo[3 * e + 2] = jz;
+        double es = 0.0;
+        for (int pi = 0; pi < np; ++pi)
+            if ((pw[pi] & 255) == e)
+                for (int q = 0; q < 12; ++q) {
+                    const double *o = rw + (size_t)(12 * pi + q) * ECP_ROW;
+                    es += o[0] * o[1];
+                }
+        ses[e] = es;
     }
     __syncthreads();
     // ---- phase 2 ----
@@ -651,9 +668,8 @@ hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, c
     return hipGetLastError();
 }
 
-static size_t ecp_adjoint_lds(int N, int n, int M) {
-    return sizeof(double) * ((size_t)7 * N + (size_t)16 * n + 48 + (size_t)3 * M + 256 * 16);
-}
+static size_t ecp_points_ao_lds(int n) { return sizeof(double) * ((size_t)16 * n + 48 + 256 * 16); }
+static size_t ecp_chain_lds(int N) { return sizeof(double) * ((size_t)7 * N + 256 * 3); }
 
 hipError_t configure_ecp(size_t lds) {
     const void *f[2] = {(const void *)k_ecp_energy<double>, (const void *)k_ecp_energy<float>};
@@ -677,16 +693,17 @@ template <typename T>
 hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, const double *R, const double *pos,
                               int W, const EcpBufs<T> &eb, const T *ktil, double *G, float *Gf, double *dedr,
                               hipStream_t st) {
-    const size_t lds = ecp_adjoint_lds(S.N, S.n_occ, S.M);
+    const size_t lds = ecp_points_ao_lds(S.n_occ);
     const int nt = (S.n_occ + 15) / 16;
     if (nt == 1)
-        hipLaunchKernelGGL((k_ecp_adjoint<T, 1>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
+        hipLaunchKernelGGL((k_ecp_points_ao<T, 1>), dim3(W), dim3(256), lds, st, S, C, R, eb, ktil, G, Gf);
     else if (nt == 2)
-        hipLaunchKernelGGL((k_ecp_adjoint<T, 2>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
+        hipLaunchKernelGGL((k_ecp_points_ao<T, 2>), dim3(W), dim3(256), lds, st, S, C, R, eb, ktil, G, Gf);
     else if (nt == 3)
-        hipLaunchKernelGGL((k_ecp_adjoint<T, 3>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
+        hipLaunchKernelGGL((k_ecp_points_ao<T, 3>), dim3(W), dim3(256), lds, st, S, C, R, eb, ktil, G, Gf);
     else
-        hipLaunchKernelGGL((k_ecp_adjoint<T, 4>), dim3(W), dim3(256), lds, st, S, E, C, R, pos, eb, ktil, G, Gf, dedr);
+        hipLaunchKernelGGL((k_ecp_points_ao<T, 4>), dim3(W), dim3(256), lds, st, S, C, R, eb, ktil, G, Gf);
+    hipLaunchKernelGGL((k_ecp_chain<T>), dim3(W), dim3(256), ecp_chain_lds(S.N), st, S, E, R, pos, eb, ktil, dedr);
     return hipGetLastError();
 }
 

@@ -93,7 +93,8 @@ struct EcpDev {
 // pairs are pairs[off[w] .. off[w] + npairs[w]) (electron | nucleus << 8),
 // its points qpos[12 off[w] ..][3], the MO rows there phiq[12 off[w] ..][nc][n]
 // (type T) and per point rows[12 off[w] ..][ECP_ROW]; *nrows = 12 * the
-// pairs of the launch; ecp_dR[W][A][3].
+// pairs of the launch; ecp_dR[W][A][3]; per AO the sums over the points
+// tc[W][M][3] of kappa grad psi.
 constexpr int ECP_ROW = 10;
 template <typename T>
 struct EcpBufs {
@@ -102,6 +103,7 @@ struct EcpBufs {
     T *phiq;
     double *rows;
     double *ecp_dR;
+    double *tc;
 };
 // Pairs and points of the W walkers (walker id id0 + w, or id0 + idlist[w]).
 hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
