@@ -148,10 +148,15 @@ def coefficient_derivatives(system, R, r, C=None, frame=None):
 def measure(system, R0, r, C=None, frame=None):
     """All per-walker quantities of one measurement at the sampling geometry.
 
-    Returns dict: E_L, lnpsi [W]; H, P [W,A,3] (SWCT force terms); O, G [W,M,n].
-    frame: (walker ids, rotation index) of a pseudopotential's quadrature.
+    Returns dict: E_L, lnpsi [W]; H, P [W,A,3] (SWCT force terms); O, G [W,M,n];
+    with one-/three-body Jastrow terms also Oxi1 [W,MJ], Oxi3 [W,MJ,MJ]
+    (dln|Psi| / dxi).  frame: (walker ids, rotation index) of a
+    pseudopotential's quadrature.
     """
     dE, dP, dJ = nuclear_derivatives(system, R0, R0, r, C, frame)
     O, G, ev = coefficient_derivatives(system, R0, r, C, frame)
-    return dict(E_L=ev["E_L"], lnpsi=ev["lnpsi"], H=dE, P=dP + 0.5 * dJ,
-                dlnpsi_dR=dP, dlnjac_dR=dJ, O=O, G=G)
+    out = dict(E_L=ev["E_L"], lnpsi=ev["lnpsi"], H=dE, P=dP + 0.5 * dJ,
+               dlnpsi_dR=dP, dlnjac_dR=dJ, O=O, G=G)
+    if system.jas_table is not None:
+        out["Oxi1"], out["Oxi3"] = wf.jastrow_parameter_derivatives(system, R0, r)
+    return out

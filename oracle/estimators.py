@@ -10,6 +10,11 @@
            finite-difference check confirms)
   <dE_L/dC> is reported separately; its expectation vanishes and the
   covariance form drops it, as the paper does.
+  dE/dxi = 2 (<E_L O_xi> - <E_L><O_xi>), O_xi = dln|Psi|/dxi of the one- and
+           three/four-body Jastrow parameters (xi1, and xi3 as a symmetric
+           matrix), the same covariance form (the gradient the paper's
+           stochastic reconfiguration of the Jastrow works with); present
+           when the measurements carry Oxi1 and Oxi3.
 
 All sums are FP64 with a shift s (the mean E_L of the first measured batch)
 subtracted from E_L, so that the covariances do not cancel catastrophically
@@ -66,6 +71,7 @@ class Accumulator:
         self._blk = None
         self.block_terms = []      # per complete block: dict of term sums and K
         self._terms = None
+        self.xi = None             # Jastrow-parameter sums (Oxi1, EOxi1, Oxi3, EOxi3)
 
     def _block_force(self, e, wt, meas):
         """Per-block force estimate (for blocked error bars of F)."""
@@ -100,6 +106,13 @@ class Accumulator:
         sm["O"].add(np.einsum("w,wmi->mi", wt, meas["O"]))
         sm["EO"].add(np.einsum("w,wmi->mi", we, meas["O"]))
         sm["G"].add(np.einsum("w,wmi->mi", wt, meas["G"]))
+        if "Oxi1" in meas:
+            if self.xi is None:
+                self.xi = {k: _Neumaier(np.shape(meas[k.lstrip("E")])[1:]) for k in ("Oxi1", "EOxi1", "Oxi3", "EOxi3")}
+            self.xi["Oxi1"].add(np.einsum("w,wm->m", wt, meas["Oxi1"]))
+            self.xi["EOxi1"].add(np.einsum("w,wm->m", we, meas["Oxi1"]))
+            self.xi["Oxi3"].add(np.einsum("w,wmn->mn", wt, meas["Oxi3"]))
+            self.xi["EOxi3"].add(np.einsum("w,wmn->mn", we, meas["Oxi3"]))
         t = dict(K=Kb, E=np.sum(we), H=np.einsum("w,wak->ak", wt, meas["H"]),
                  P=np.einsum("w,wak->ak", wt, meas["P"]), EP=np.einsum("w,wak->ak", we, meas["P"]),
                  O=np.einsum("w,wmi->mi", wt, meas["O"]), EO=np.einsum("w,wmi->mi", we, meas["O"]))
@@ -134,8 +147,13 @@ class Accumulator:
         else:
             sigma = float("nan")
             F_sigma = np.full_like(F, np.nan)
-        return dict(E=E, E_sigma=sigma, F_sigma=F_sigma, F_bare=F, dE_dC=dEdC, dEL_dC_mean=v["G"],
-                    var_E=v["EE"] - v["E"] ** 2, K=self.K, shift=self.shift)
+        out = dict(E=E, E_sigma=sigma, F_sigma=F_sigma, F_bare=F, dE_dC=dEdC, dEL_dC_mean=v["G"],
+                   var_E=v["EE"] - v["E"] ** 2, K=self.K, shift=self.shift)
+        if self.xi is not None:
+            x = {k: a.value / K for k, a in self.xi.items()}
+            out["dE_dxi1"] = 2.0 * (x["EOxi1"] - v["E"] * x["Oxi1"])
+            out["dE_dxi3"] = 2.0 * (x["EOxi3"] - v["E"] * x["Oxi3"])
+        return out
 
     def jackknife(self):
         """Leave-one-block-out replicas of E, F_bare and dE/dC over the complete

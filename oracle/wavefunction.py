@@ -214,6 +214,18 @@ def body_jastrow_terms(system, R, r):
     return J1, g1, h1, J3, g3, h3
 
 
+def jastrow_parameter_derivatives(system, R, r):
+    """O_xi = dln|Psi|/dxi of the one- and three/four-body parameters:
+    O_xi1 [W, MJ] = s = sum_i chi(r_i) (eq. onebody_J_inhom is linear in xi1);
+    O_xi3 [W, MJ, MJ] = (s s^T - sum_i chi(r_i) chi(r_i)^T) / 2, the gradient
+    of U3 = sum_{i<j} chi(r_i)^T xi3 chi(r_j) (eq. threebody_jas) with respect
+    to the symmetric matrix xi3: for a symmetric change D,
+    dU3 = sum_{mu,nu} O_xi3[mu, nu] D[mu, nu]."""
+    chi, _, _ = gto.eval_aos(system.jas_table, R, r)            # [W, N, MJ]
+    s = chi.sum(axis=1)
+    return s, 0.5 * (s[:, :, None] * s[:, None, :] - np.einsum("wim,win->wmn", chi, chi))
+
+
 def potential(system, R, r):
     """V = -sum Z/|r-R| + sum_{i<j} 1/r_ij + sum_{a<b} Z_a Z_b / R_ab  [W]."""
     W, N, _ = r.shape

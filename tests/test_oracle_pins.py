@@ -695,3 +695,49 @@ def test_ecp_estimators_are_fixed_sample_derivatives(mol9):
     V = rng.standard_normal(s.C.shape)
     ev = wf.evaluate(s, R0, r, s.C + 1e-30j * V)
     assert np.allclose(ev["E_L"].imag / 1e-30, np.einsum("wmi,mi->w", G, V), rtol=1e-9, atol=1e-8)
+
+
+# Jastrow-parameter derivatives: O_xi = dln|Psi|/dxi against the complex step
+# of ln|Psi| along random directions (xi3 along symmetric ones), and the
+# covariance estimator dE/dxi against the fixed-sample finite difference of
+# E_hat(xi) = sum w E_L / sum w, w = exp(2 (ln|Psi(xi)| - ln|Psi0|)), whose
+# exact derivative is the covariance form plus <dE_L/dxi> (complex step).
+def test_jastrow_parameter_derivatives(mol9):
+    m = inputs.with_body_jastrow(mol9, 7)
+    s = wf.System(m)
+    ch, _ = sampler.run(s, inputs.initial_walkers(m, 6, 31), 2, 31)
+    r, R0 = ch.r, s.xyz
+    O1, O3 = wf.jastrow_parameter_derivatives(s, R0, r)
+    rng = np.random.default_rng(12)
+    MJ = s.xi1.shape[0]
+    d1 = rng.standard_normal(MJ)
+    G = rng.standard_normal((MJ, MJ))
+    d3 = 0.5 * (G + G.T)
+    xi1, xi3 = s.xi1.copy(), s.xi3.copy()
+
+    def at(t1, t3):
+        s.xi1, s.xi3 = xi1 + t1 * d1, xi3 + t3 * d3
+        ev = wf.evaluate(s, R0, r)
+        s.xi1, s.xi3 = xi1, xi3
+        return ev
+
+    e1 = at(1e-30j, 0.0)
+    e3 = at(0.0, 1e-30j)
+    assert np.allclose(e1["lnpsi"].imag / 1e-30, O1 @ d1, rtol=1e-12, atol=1e-12)
+    assert np.allclose(e3["lnpsi"].imag / 1e-30, np.einsum("wmn,mn->w", O3, d3), rtol=1e-12, atol=1e-12)
+    meas = dv.measure(s, R0, r)
+    acc = estimators.Accumulator(s.A, s.M, s.C.shape[1])
+    acc.add(meas)
+    res = acc.result()
+    lnpsi0 = meas["lnpsi"]
+    for t1, t3, an, dl in ((1.0, 0.0, res["dE_dxi1"] @ d1, e1), (0.0, 1.0, np.sum(res["dE_dxi3"] * d3), e3)):
+        h = 1e-5
+
+        def ehat(t):
+            ev = at(t * t1, t * t3)
+            w = np.exp(2.0 * (ev["lnpsi"] - lnpsi0))
+            return float(np.sum(w * ev["E_L"]) / np.sum(w))
+
+        fd = (ehat(h) - ehat(-h)) / (2 * h)
+        dEL = float(np.mean(dl["E_L"].imag / 1e-30))
+        assert abs(fd - (an + dEL)) < 1e-6 * max(1.0, abs(fd)), (t1, t3, fd, an, dEL)
