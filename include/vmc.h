@@ -224,7 +224,10 @@ typedef struct {
  *                  divides by the ratio); 0 selects the default 1e-8, larger
  *                  values force more rebuilds (>= 0, finite).
  * ecp            : a semilocal pseudopotential in E_L (NULL = none; see
- *                  vmc_ecp). */
+ *                  vmc_ecp).
+ * jastrow_gradient: with the one-/three-body Jastrow terms, nonzero adds to
+ *                  every accumulated batch the sums that vmc_jastrow_gradient
+ *                  reads (their cost grows as M_J^2 N per walker). */
 typedef struct {
     int32_t precision;
     int32_t refresh_period;
@@ -236,6 +239,7 @@ typedef struct {
     int32_t jackknife_blocks;
     double  forced_refresh_ratio;
     const vmc_ecp *ecp;
+    int32_t jastrow_gradient;
 } vmc_options;
 
 /* Per-walker outputs of one measurement (device arrays, any may be NULL).
@@ -310,6 +314,22 @@ int vmc_sweep(vmc_ctx *ctx, double *walkers_dev, int64_t n_walkers, int32_t nste
  * still clears the accumulators and the error state. */
 int vmc_accumulate(vmc_ctx *ctx, double *E, double *F_bare, double *dE_dC,
                    double *dEL_dC_mean, int64_t *n_samples, uint32_t flags, void *stream);
+
+/* Gradient of the energy in the one- and three/four-body Jastrow parameters
+ * over the samples accumulated since the last reset (the covariance form of
+ * eq. fc-vmc-eval applied to the Jastrow parameters of App. A, eqs.
+ * onebody_J_inhom and threebody_jas; the gradient the paper's stochastic
+ * reconfiguration of the Jastrow works with):
+ *   dE/dxi = 2 (<E_L O_xi> - <E_L><O_xi>),  O_xi = dln|Psi|/dxi,
+ *   O_xi1 = sum_i chi(r_i),  O_xi3 = (s s^T - sum_i chi(r_i) chi(r_i)^T) / 2
+ * (s = sum_i chi(r_i); xi3 as a symmetric matrix: for a symmetric change D
+ * the energy changes by sum_{mu,nu} dE_dxi3[mu][nu] D[mu][nu]), with the
+ * weights and shifted FP64 sums of vmc_accumulate.  Host outputs
+ * dE_dxi1[M_J], dE_dxi3[M_J][M_J]; read before vmc_accumulate resets.
+ * Synchronises `stream`.
+ * Errors: VMC_EINVAL (no one-/three-body terms, options.jastrow_gradient
+ * off, or no samples), VMC_EDEVICE. */
+int vmc_jastrow_gradient(vmc_ctx *ctx, double *dE_dxi1, double *dE_dxi3, void *stream);
 
 /* Measure n_walkers given configurations (device [n_walkers][N][3]) at the
  * context's MO coefficients and nuclei and add them to the accumulators as

@@ -72,6 +72,11 @@ struct vmc_ctx {
     vmcx::BasisDev jdev{};
     AoTiles jtiles16{};
     double *d_xiblk = nullptr, *d_xi1 = nullptr;
+    // the Jastrow-parameter gradient's sums (jastrow_gradient): per launch
+    // the FP64 basis values at the electrons and the partial sums, and the
+    // compensated accumulators [s | (E-s) s | O3 | (E-s) O3]
+    double *xg_X = nullptr, *xg_part = nullptr, *xg_acc = nullptr, *xg_comp = nullptr;
+    int64_t xg_n = 0;
     float *d_xiblk_f = nullptr;
     // staging of the Jastrow terms: sweeps ([W][N] rows) and measurements
     // ([chunk][N] rows); element sizes of the arithmetic type
@@ -520,6 +525,14 @@ static int measure_accumulate(vmc_ctx *c, const double *walkers, int64_t W, cons
             a.Gf = o.Gf;
         }
         a.wt = wt ? wt + c0 : nullptr;
+        if (c->xg_n > 0) {
+            // the Jastrow-parameter sums of this launch (basis values again in
+            // FP64: the measurement's may have been replaced by a promoted subset)
+            HIP_OK(c, vmcx::launch_jas_values<double>(c->jdev, c->d_R, walkers + c0 * c->N * 3, cw * c->N, c->xg_X,
+                                                      st));
+            HIP_OK(c, vmcx::launch_xi_sums(c->xg_X, c->N, c->MJ, (int)cw, c->st_EL, c->shift, a.wt, c->xg_part,
+                                           c->xg_acc, c->xg_comp, st));
+        }
         HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, blkw, blk_all,
                                       st));
     }
@@ -975,8 +988,10 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     const int64_t eq = c->has_ecp ? (int64_t)c->edev.pcap * 12 : 0;
     const int64_t ecp_pw = c->has_ecp ? eq * (3 + 5 * (int64_t)c->n_occ + vmcx::ECP_ROW) + A3 + 3 * M + c->edev.pcap + 2
                                       : 0;
+    const int64_t xg_pw = (opt->jastrow_gradient && c->MJ > 0) ? (int64_t)c->N * c->MJ : 0;
     const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
-                                                        3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw + ecp_pw);
+                                                        3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw + ecp_pw +
+                                                        xg_pw);
     int64_t chunk = (int64_t)(STAGING_BUDGET / per_walker);
     chunk = std::max<int64_t>(1, std::min<int64_t>(chunk, opt->max_walkers));
     if (opt->staging_walkers > 0) chunk = std::min<int64_t>(chunk, opt->staging_walkers);
@@ -1011,6 +1026,14 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
             (rc = c->dalloc(&c->jm_g, (size_t)chunk * c->N * 4)) || (rc = c->dalloc(&c->jm_u, (size_t)chunk)) ||
             (rc = c->dalloc(&c->jm_tao, (size_t)chunk * c->MJ * 6)))
             return bail(rc);
+    }
+    if (opt->jastrow_gradient && c->MJ > 0) {
+        c->xg_n = 2 * (int64_t)c->MJ + 2 * (int64_t)c->MJ * c->MJ;
+        if ((rc = c->dalloc(&c->xg_X, (size_t)chunk * c->N * c->MJ)) || (rc = c->dalloc(&c->xg_part, c->xg_n)) ||
+            (rc = c->dalloc(&c->xg_acc, c->xg_n)) || (rc = c->dalloc(&c->xg_comp, c->xg_n)))
+            return bail(rc);
+        if (hipMemset(c->xg_acc, 0, c->xg_n * 8) != hipSuccess || hipMemset(c->xg_comp, 0, c->xg_n * 8) != hipSuccess)
+            return bail(c->fail(VMC_EDEVICE, "hipMemset failed"));
     }
     if (c->has_ecp) {
         if ((rc = c->dalloc(&c->e_pairs, (size_t)chunk * c->edev.pcap)) ||
@@ -1083,6 +1106,37 @@ int vmc_sweep(vmc_ctx *c, double *walkers, int64_t W, int32_t nsteps, uint64_t s
     return VMC_OK;
 }
 
+int vmc_jastrow_gradient(vmc_ctx *c, double *dE_dxi1, double *dE_dxi3, void *stream) {
+    if (!c) return VMC_EINVAL;
+    if (c->xg_n == 0)
+        return c->fail(VMC_EINVAL, "no one-/three-body Jastrow terms, or options.jastrow_gradient off");
+    if (c->n_samples < 1) return c->fail(VMC_EINVAL, "no samples accumulated");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = c->n_est, m = c->xg_n, MJ = c->MJ;
+    std::vector<double> a(m), q(m);
+    double e[2], ec[2], K[2];
+    HIP_OK(c, hipMemcpyAsync(a.data(), c->xg_acc, m * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(q.data(), c->xg_comp, m * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(e, c->acc, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(ec, c->comp, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(K, c->acc + n - 1, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipMemcpyAsync(K + 1, c->comp + n - 1, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(c, hipStreamSynchronize(st));
+    // (element 0 of the estimator vector: the weighted sum of E_L - shift;
+    // the last: the sum of the weights)
+    const double W = K[0] + K[1];
+    if (!(W > 0.0) || !std::isfinite(W)) return c->fail(VMC_EINVAL, "the sum of the weights is %g", W);
+    const double vE = (e[0] + ec[0]) / W;
+    auto v = [&](int64_t k) { return (a[k] + q[k]) / W; };
+    if (dE_dxi1)
+        for (int64_t mu = 0; mu < MJ; ++mu) dE_dxi1[mu] = 2.0 * (v(MJ + mu) - vE * v(mu));
+    if (dE_dxi3)
+        for (int64_t k = 0; k < MJ * MJ; ++k) dE_dxi3[k] = 2.0 * (v(2 * MJ + MJ * MJ + k) - vE * v(2 * MJ + k));
+    return VMC_OK;
+}
+
 int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC, int64_t *n_samples,
                    uint32_t flags, void *stream) {
     if (!c) return VMC_EINVAL;
@@ -1147,6 +1201,10 @@ int vmc_accumulate(vmc_ctx *c, double *E, double *F, double *dEdC, double *dELdC
         HIP_OK(c, hipMemsetAsync(c->blocks, 0, MAX_BLOCKS * 8, st));
         HIP_OK(c, hipMemsetAsync(c->blocks_w, 0, MAX_BLOCKS * 8, st));
         if (c->jk_cap) HIP_OK(c, hipMemsetAsync(c->blk_all, 0, c->jk_cap * n * 8, st));
+        if (c->xg_n) {
+            HIP_OK(c, hipMemsetAsync(c->xg_acc, 0, c->xg_n * 8, st));
+            HIP_OK(c, hipMemsetAsync(c->xg_comp, 0, c->xg_n * 8, st));
+        }
         HIP_OK(c, hipStreamSynchronize(st));
         c->block_counts.clear();
         c->n_samples = 0;

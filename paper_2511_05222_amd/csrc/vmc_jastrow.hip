@@ -284,3 +284,79 @@ JAS_INST(float)
 JAS_INST(double)
 
 }  // namespace vmcx
+
+namespace vmcx {
+
+// ---------------------------------------------------------------------------
+// Sums of the Jastrow-parameter log-derivatives over one measurement launch,
+// for dE/dxi = 2 (<E_L O_xi> - <E_L><O_xi>):
+//   O_xi1 = s = sum_i chi(r_i),  O_xi3 = (s s^T - sum_i chi(r_i) chi(r_i)^T) / 2
+// (the gradient of U3 with respect to the symmetric xi3).  With a_w the
+// walker's weight and b_w = a_w (E_L,w - shift), the launch's partial sums
+//   part = [sum a s | sum b s | sum a O_xi3 | sum b O_xi3]   (MJ, MJ, MJ^2, MJ^2)
+// one block per 16 x 16 tile (mu, nu) of O_xi3, walkers in order; the tiles
+// of the first column also form the O_xi1 sums.  X[w][i][mu] = chi_mu(r_i) in
+// FP64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_xi_sums(const double *__restrict__ X, int N, int MJ, int W,
+                                                 const double *__restrict__ EL, const double *__restrict__ shift,
+                                                 const double *__restrict__ wt, double *part) {
+    __shared__ double xm[128 * 16], xn[128 * 16];
+    const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+    const int mu0 = 16 * blockIdx.x, nu0 = 16 * blockIdx.y;
+    const int mu = mu0 + ti, nu = nu0 + tj;
+    double s3a = 0.0, s3b = 0.0, s1a = 0.0, s1b = 0.0;
+    const double sh = *shift;
+    for (int w = 0; w < W; ++w) {
+        __syncthreads();
+        const double *xw = X + (size_t)w * N * MJ;
+        for (int k = tid; k < N * 16; k += 256) {
+            const int i = k >> 4, q = k & 15;
+            xm[k] = mu0 + q < MJ ? xw[(size_t)i * MJ + mu0 + q] : 0.0;
+            xn[k] = nu0 + q < MJ ? xw[(size_t)i * MJ + nu0 + q] : 0.0;
+        }
+        __syncthreads();
+        double sm = 0.0, sn = 0.0, p = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const double a = xm[16 * i + ti], b = xn[16 * i + tj];
+            sm += a;
+            sn += b;
+            p += a * b;
+        }
+        const double aw = wt ? wt[w] : 1.0, bw = aw * (EL[w] - sh);
+        const double o3 = 0.5 * (sm * sn - p);
+        s3a += aw * o3;
+        s3b += bw * o3;
+        s1a += aw * sm;
+        s1b += bw * sm;
+    }
+    if (mu < MJ && nu < MJ) {
+        part[2 * MJ + (size_t)mu * MJ + nu] = s3a;
+        part[2 * MJ + (size_t)MJ * MJ + (size_t)mu * MJ + nu] = s3b;
+        if (blockIdx.y == 0 && tj == 0) {
+            part[mu] = s1a;
+            part[MJ + mu] = s1b;
+        }
+    }
+}
+
+// acc + comp += part (Neumaier), element by element.
+__global__ void k_add_compensated(const double *__restrict__ part, int64_t n, double *acc, double *comp) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double s = acc[k], x = part[k], t = s + x;
+    comp[k] += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+    acc[k] = t;
+}
+
+hipError_t launch_xi_sums(const double *X, int N, int MJ, int W, const double *EL, const double *shift,
+                          const double *wt, double *part, double *acc, double *comp, hipStream_t st) {
+    if (N > 128) return hipErrorInvalidValue;
+    const int nt = (MJ + 15) / 16;
+    hipLaunchKernelGGL(k_xi_sums, dim3(nt, nt), dim3(256), 0, st, X, N, MJ, W, EL, shift, wt, part);
+    const int64_t n = 2 * (int64_t)MJ + 2 * (int64_t)MJ * MJ;
+    hipLaunchKernelGGL(k_add_compensated, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, n, acc, comp);
+    return hipGetLastError();
+}
+
+}  // namespace vmcx

@@ -29,7 +29,7 @@ VMC_ACCUM_RESET = 1
 EXPORTED = ["vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
             "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap", "zvector_jackknife",
             "vmc_staging_walkers", "vmc_free", "vmc_last_error", "vmc_init_error", "vmc_strerror", "vmc_profile",
-            "vmc_profile_read", "zvector_solve_noalloc", "vmc_accumulate_walkers"]
+            "vmc_profile_read", "zvector_solve_noalloc", "vmc_accumulate_walkers", "vmc_jastrow_gradient"]
 
 
 class VmcError(RuntimeError):
@@ -70,7 +70,7 @@ class _Options(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("refresh_period", ct.c_int32), ("block_sweeps", ct.c_int32),
                 ("max_walkers", ct.c_int32), ("staging_walkers", ct.c_int32), ("step_sigma", ct.c_double),
                 ("promote_fraction", ct.c_double), ("jackknife_blocks", ct.c_int32),
-                ("forced_refresh_ratio", ct.c_double), ("ecp", ct.POINTER(_Ecp))]
+                ("forced_refresh_ratio", ct.c_double), ("ecp", ct.POINTER(_Ecp)), ("jastrow_gradient", ct.c_int32)]
 
 
 class _WalkerOut(ct.Structure):
@@ -94,6 +94,7 @@ def lib():
     L.vmc_sweep.argtypes = [vp, vp, i64, i32, u64, u64, u32, vp, vp]
     L.vmc_accumulate.argtypes = [vp, vp, vp, vp, vp, vp, u32, vp]
     L.vmc_accumulate_walkers.argtypes = [vp, vp, i64, vp, vp]
+    L.vmc_jastrow_gradient.argtypes = [vp, vp, vp, vp]
     L.vmc_measure.argtypes = [vp, vp, i64, vp, vp, vp, ct.POINTER(_WalkerOut), vp]
     L.vmc_eval.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.vmc_energy_cotangents.argtypes = [vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp]
@@ -119,7 +120,7 @@ def lib():
     for name in ("vmc_init", "vmc_sweep", "vmc_accumulate", "vmc_measure", "vmc_eval", "vmc_energy_cotangents",
                  "vmc_adjoint", "vmc_jackknife", "zvector_solve", "zvector_rhs", "zvector_backmap",
                  "zvector_jackknife", "vmc_profile", "vmc_profile_read", "zvector_solve_noalloc",
-                 "vmc_accumulate_walkers"):
+                 "vmc_accumulate_walkers", "vmc_jastrow_gradient"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -149,7 +150,7 @@ class Context:
 
     def __init__(self, mol, max_walkers, precision="fp64", refresh_period=32, block_sweeps=1,
                  step_sigma=0.5, device=0, staging_walkers=0, promote_fraction=PROMOTE_FRACTION,
-                 jackknife_blocks=0, forced_refresh_ratio=0.0, ecp_max_pairs=0):
+                 jackknife_blocks=0, forced_refresh_ratio=0.0, ecp_max_pairs=0, jastrow_gradient=False):
         L = lib()
         b = mol.basis
         self._keep = [np.ascontiguousarray(b.shell_atom, np.int32), np.ascontiguousarray(b.shell_l, np.int32),
@@ -182,6 +183,7 @@ class Context:
             raise VmcError(VMC_EINVAL, f"precision {precision!r} is not available")
         opt = _Options(prec, refresh_period, block_sweeps, int(max_walkers), int(staging_walkers), step_sigma,
                        float(promote_fraction), int(jackknife_blocks), float(forced_refresh_ratio))
+        opt.jastrow_gradient = 1 if jastrow_gradient else 0
         e = getattr(mol, "ecp", None)
         if e is not None:
             ek = [np.ascontiguousarray(e.term_atom, np.int32), np.ascontiguousarray(e.term_l, np.int32),
@@ -236,6 +238,16 @@ class Context:
         if weights is not None:
             _check_dev(weights, (W,))
         self._rc(lib().vmc_accumulate_walkers(self._h, _ptr(walkers), W, _ptr(weights), _stream()))
+
+    def jastrow_gradient(self):
+        """dE/dxi1 [MJ] and dE/dxi3 [MJ][MJ] over the samples since the last
+        reset (read before accumulate(reset=True))."""
+        MJ = self.mol.jastrow.jas_basis.n_ao
+        g1 = np.zeros(MJ)
+        g3 = np.zeros((MJ, MJ))
+        dpn = lambda a: a.ctypes.data_as(ct.c_void_p)
+        self._rc(lib().vmc_jastrow_gradient(self._h, dpn(g1), dpn(g3), _stream()))
+        return g1, g3
 
     def accumulate(self, reset=True):
         E = np.zeros(2)

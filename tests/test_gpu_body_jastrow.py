@@ -152,3 +152,35 @@ def test_mixed_within_bounds(dev, mol9j):
     o64 = ctx64.measure(w, outputs=("EL", "dEL_dR"))
     dE = abs((o32["EL"] - o64["EL"]).mean().item())
     assert dE < 1e-5, dE
+
+
+def test_jastrow_parameter_gradient(dev, mol9j):
+    """dE/dxi = 2 (<E_L O_xi> - <E_L><O_xi>) over sweeps with measurement
+    (several measurement launches) and over reweighted configurations,
+    against the oracle's accumulator (1e-10 of the largest element)."""
+    from oracle import derivatives as dv, estimators, vmc as ovmc, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    W, sweeps = 9, 3
+    w0 = inputs.initial_walkers(mol9j, W, 8)
+    ref = ovmc.run(mol9j, w0, sweeps, 79, block_sweeps=1)
+    ctx = vmc.Context(mol9j, max_walkers=W, staging_walkers=5, jastrow_gradient=True)
+    tw = torch.tensor(w0, device=dev)
+    print("case: 9-atom J1/J3 dE/dxi", flush=True)
+    ctx.sweep(tw, sweeps, 79)
+    g1, g3 = ctx.jastrow_gradient()
+    res = ctx.accumulate()
+    close(res["E"], ref["E"], what="E")
+    close(g1, ref["dE_dxi1"], what="dE_dxi1")
+    close(g3, ref["dE_dxi3"], what="dE_dxi3")
+    # reweighted samples (weights given per walker)
+    r = ref["positions"]
+    wts = np.exp(np.random.default_rng(5).normal(0.0, 0.5, size=W))
+    s = wf.System(mol9j)
+    acc = estimators.Accumulator(s.A, s.M, s.C.shape[1])
+    acc.add(dv.measure(s, s.xyz, r), wts)
+    rw = acc.result()
+    ctx.accumulate_walkers(torch.tensor(r, device=dev), torch.tensor(wts, device=dev))
+    g1, g3 = ctx.jastrow_gradient()
+    ctx.accumulate()
+    close(g1, rw["dE_dxi1"], what="weighted dE_dxi1")
+    close(g3, rw["dE_dxi3"], what="weighted dE_dxi3")
