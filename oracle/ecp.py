@@ -24,7 +24,9 @@ Readings (the paper gives none of this):
     d < rcut[a] (the input recipe puts rcut where every channel is below
     1e-12 hartree); the local part acts everywhere;
   * Psi'/Psi = [phi(r')^T K e_i] exp(J(r') - J(r)) (determinant lemma, the
-    ratio a single-electron move uses), with the two-body Jastrow.
+    ratio a single-electron move uses), with the whole Jastrow: the two-body
+    change sum_{j != i} u(|r' - r_j|) - u(|r_i - r_j|) and, with the one- and
+    three/four-body terms, (chi(r') - chi(r_i))^T (xi1 + xi3 sum_{j != i} chi(r_j)).
 
 Every routine stays complex-analytic in R, r and C (the cutoff is tested on
 the real part), so the complex-step derivatives of the local energy include
@@ -118,8 +120,6 @@ def terms(system, R, r, C, Kinv, frame=None):
     values at the points).
     """
     pp = system.pp
-    if system.jas_table is not None:
-        raise NotImplementedError("pseudopotential with one-/three-body Jastrow terms")
     W, N, _ = r.shape
     C = system.C if C is None else C
     ids, rot_index = frame if frame is not None else (np.arange(W, dtype=np.uint64), 0)
@@ -132,6 +132,11 @@ def terms(system, R, r, C, Kinv, frame=None):
     dij = r[:, :, None, :] - r[:, None, :, :]
     rij = np.sqrt(np.sum(dij * dij, axis=-1) + np.eye(N))
     u_old = _u(system, rij) * (1.0 - np.eye(N))                     # [W, i, j]
+    if system.jas_table is not None:
+        chi, _, _ = gto.eval_aos(system.jas_table, R, r)                # [W, N, MJ]
+        # h_i = xi1 + xi3 sum_{j != i} chi(r_j): the one-/three-body change
+        # of a move of electron i from r_i to r' is (chi(r') - chi(r_i)) . h_i
+        h13 = system.xi1 + np.einsum("mn,win->wim", system.xi3, chi.sum(axis=1)[:, None, :] - chi)
     per_atom = {}
     for a in range(pp.A):
         if not np.any(pp.atom == a):
@@ -159,6 +164,10 @@ def terms(system, R, r, C, Kinv, frame=None):
         self_ = np.eye(N)[None, :, None, :]
         rq = np.sqrt(np.sum(dq * dq, axis=-1) + self_)
         dJ = np.sum(_u(system, rq) * (1.0 - self_), axis=-1) - np.sum(u_old, axis=-1)[:, :, None]
+        if system.jas_table is not None:
+            chq, _, _ = gto.eval_aos(system.jas_table, R, pts.reshape(W, N * 12, 3))
+            chq = chq.reshape(W, N, 12, -1)
+            dJ = dJ + np.einsum("wiqm,wim->wiq", chq - chi[:, :, None, :], h13)
         jr = np.exp(dJ)
         cq = mask[..., None] * c * jr
         E_nl = E_nl + np.einsum("wnq,wnq->w", cq, ratio)

@@ -347,13 +347,26 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
         mb.jg = c->jm_g;
         mb.ju = c->jm_u;
     }
+    // the same terms in the pseudopotential's ratios
+    vmcx::EcpJas<T> ej;
+    if (c->MJ > 0) {
+        ej.jb = c->jdev;
+        ej.MJ = c->MJ;
+        ej.rows = jrows;
+        ej.X = jX;
+        ej.O = jO;
+        ej.xi1 = c->d_xi1;
+        ej.xiblk = c->d_xiblk;
+        ej.jg = c->jm_g;
+        ej.jtao = c->jm_tao;
+    }
     pi = prof_begin(c, VMC_K_DENSE, prof, cw, st);
     HIP_OK(c, vmcx::launch_dense<T>(S, R, mb, o, c->status, c->dl, (int)cw, st));
     prof_end(c, VMC_K_DENSE, pi, st);
     if (c->has_ecp) {
         pi = prof_begin(c, VMC_K_ECP_ENERGY, prof, cw, st);
         HIP_OK(c, vmcx::launch_ecp_energy<T>(S, c->edev, R, pos, (int)cw, eb, enc, mb.ktil, full ? mb.abar : nullptr,
-                                             o.EL, c->status, st));
+                                             o.EL, c->status, ej, st));
         prof_end(c, VMC_K_ECP_ENERGY, pi, st);
     }
     if (!full) return VMC_OK;
@@ -361,18 +374,20 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     HIP_OK(c, vmcx::launch_adjoint<T>(S, C, R, mb, o, al, (int)cw, st));
     prof_end(c, VMC_K_ADJOINT, pi, st);
     MeasBufsD md{pos, pos0, c->mb_gb, c->mb_dpart, c->mb_tao};
-    if (c->has_ecp) {
-        pi = prof_begin(c, VMC_K_ECP_ADJOINT, prof, cw, st);
-        HIP_OK(c, vmcx::launch_ecp_adjoint<T>(S, c->edev, C, R, pos, (int)cw, eb, mb.ktil, o.G, o.Gf, c->mb_dpart,
-                                              st));
-        prof_end(c, VMC_K_ECP_ADJOINT, pi, st);
-        md.ecp_dR = c->e_dR;
-    }
     if (c->MJ > 0) {
+        // (writes the per-function sums jtao that the pseudopotential's
+        // one-/three-body terms then add to)
         HIP_OK(c, vmcx::launch_jas_adjoint<T>(c->jdev, R, c->N, c->nq, jrows, 0, (int)cw, pos, jX, jO, c->mb_gb,
                                               c->d_xi1, c->mb_dpart, c->jm_tao, st));
         md.jtao = c->jm_tao;
         md.jb = c->jdev;
+    }
+    if (c->has_ecp) {
+        pi = prof_begin(c, VMC_K_ECP_ADJOINT, prof, cw, st);
+        HIP_OK(c, vmcx::launch_ecp_adjoint<T>(S, c->edev, C, R, pos, (int)cw, eb, mb.ktil, o.G, o.Gf, c->mb_dpart,
+                                              ej, st));
+        prof_end(c, VMC_K_ECP_ADJOINT, pi, st);
+        md.ecp_dR = c->e_dR;
     }
     HIP_OK(c, vmcx::launch_finalize(S, R, R0, md, o, warp, (int)cw, st));
     return VMC_OK;
@@ -702,7 +717,6 @@ static int check_ecp(vmc_ctx *c, const vmc_ecp *e, int A) {
     if (T < 1 || T > VMC_MAX_ECP_TERMS || !e->term_atom || !e->term_l || !e->term_n || !e->term_exp ||
         !e->term_coef || !e->rcut || e->max_pairs < 0)
         return c->fail(VMC_EINVAL, "pseudopotential: bad counts or missing arrays (%d terms)", T);
-    if (c->MJ > 0) return c->fail(VMC_EINVAL, "a pseudopotential with the one-/three-body Jastrow is not supported");
     for (int t = 0; t < T; ++t) {
         const int a = e->term_atom[t], l = e->term_l[t], n = e->term_n[t];
         if (a < 0 || a >= A || l < -1 || l > VMC_MAX_ECP_L || n < 1 || n > 4 || !(e->term_exp[t] > 0.0) ||
@@ -960,7 +974,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         std::lock_guard<std::mutex> lock(mu);
         const size_t need[7] = {c->dl.bytes, sweep_layout(c, sizeof(double)).bytes, c->al64.bytes,
                                 c->dl.bytes, c->swl.bytes, c->al.bytes,
-                                c->has_ecp ? vmcx::ecp_energy_lds(c->N, c->n_occ) : 0};
+                                c->has_ecp ? vmcx::ecp_energy_lds(c->N, c->n_occ, c->MJ) : 0};
         for (int q = 0; q < 7; ++q) lim[q] = std::max(lim[q], need[q]);
         cfg_ok = vmcx::configure_dense<double>(lim[0]) == hipSuccess &&
                  vmcx::configure_sweep<double>(lim[1]) == hipSuccess &&

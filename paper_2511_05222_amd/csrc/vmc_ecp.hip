@@ -7,8 +7,10 @@
 //   rho_q = Psi(.., r_q, ..) / Psi(.., r_i, ..) = t_q exp(dJ_q),
 //   t_q = phi(r_q)^T K e_i (determinant lemma),  r_q = R_a + d v_q,
 // over the 12 icosahedron vertices v_q turned by one random rotation per
-// (walker, electron), dJ_q the change of the two-body Jastrow.  Three kernels
-// around the measurement:
+// (walker, electron), dJ_q the change of the Jastrow: the two-body pair terms
+// of electron i and, with the one- and three/four-body terms,
+//   (chi(r_q) - chi(r_i)) . h_i,   h_i = xi1 + xi3 sum_{j != i} chi(r_j).
+// The kernels around the measurement:
 //   k_ecp_count / k_ecp_scan / k_ecp_place
 //                  the (electron, nucleus) pairs inside the cutoffs, packed
 //                  over the walkers of a launch, and their 12 points each;
@@ -25,7 +27,10 @@
 //                  g_q = dE/dr_q (orbitals and Jastrow at r_q) carried to r_i
 //                  and R_a through r_q = R_a + d v_q; c_q through d and u . v_q;
 //                  the Jastrow's dependence on the other electrons; the AOs
-//                  at the points moving with their nuclei; V_loc.
+//                  at the points moving with their nuclei; V_loc.  With the
+//                  one-/three-body terms k_ecp_jas first forms their share:
+//                  the gradient at each point, the electrons' terms through
+//                  the h_j, and the Jastrow functions' per-nucleus sums.
 #include "vmc.h"
 #include "vmc_pipeline.hpp"
 #include "vmc_regs.hpp"
@@ -82,6 +87,25 @@ __device__ inline void ecp_radial(const EcpDev &E, int a, int l, double d, doubl
         v += b * pw * ex;
         dv += b * ex * (pm - 2.0 * al * d * pw);
     }
+}
+
+// Components (NC = 1: value; 5: value, gradient, Laplacian) of Jastrow
+// function mu at (x, y, z), FP64.
+template <int NC>
+__device__ inline void jas_fn(const BasisDev &JB, const double *R, int mu, double x, double y, double z, double *c) {
+    const int s = JB.ao_shell[mu], atom = JB.shell_atom[s];
+    const double dx = x - R[3 * atom], dy = y - R[3 * atom + 1], dz = z - R[3 * atom + 2];
+    const double rho = dx * dx + dy * dy + dz * dz;
+    double R0, R1, R2, R3;
+    shell_radial<NC, double>(JB, s, rho, R0, R1, R2, R3);
+    ao_components<NC, double>(dx, dy, dz, rho, R0, R1, R2, R3, JB.ao_pow[mu], JB.ao_eta[mu], c);
+}
+
+// The value product of electron e with column mu of [xi3 | xi1]:
+// (xi3 chi(r_e))_mu for mu < MJ.
+template <typename T>
+__device__ inline double ecp_jas_oval(const EcpJas<T> &J, int64_t row, int mu) {
+    return (double)J.O[(((size_t)(mu >> 6) * J.rows + row) * 5) * 64 + (mu & 63)];
 }
 
 __device__ inline double legendre(int l, double x) {
@@ -207,22 +231,31 @@ __global__ __launch_bounds__(128) void k_ecp_place(SysDev S, EcpDev E, const dou
 // has one writer), lanes run over orbitals (ratio) and electrons (Jastrow).
 // Per point it keeps rows[.] = (c'_q, t_q, exp(dJ_q), c_q).
 // ---------------------------------------------------------------------------
-size_t ecp_energy_lds(int N, int n) { return sizeof(double) * ((size_t)3 * N + (size_t)N * n + (size_t)n * n + 132); }
+size_t ecp_energy_lds(int N, int n, int MJ) {
+    return sizeof(double) * ((size_t)3 * N + (size_t)N * n + (size_t)n * n + 132 + (size_t)MJ);
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const double *__restrict__ R,
                                                     const double *__restrict__ pos, EcpBufs<T> eb, int nc,
-                                                    const T *__restrict__ ktil, T *abar, double *EL, int *status) {
+                                                    const T *__restrict__ ktil, T *abar, double *EL, int *status,
+                                                    EcpJas<T> J) {
     extern __shared__ double sm[];
     const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int N = S.N, n = S.n_occ;
+    const int N = S.N, n = S.n_occ, MJ = J.X ? J.MJ : 0;
     double *sp = sm;               // [N][3]
     double *sz = sp + 3 * N;       // [N][n]: Z^T, row i = sum over the points of electron i
     double *sP = sz + N * n;       // [n][n]
     double *red = sP + n * n;      // [128] local terms, [4] per-wave E_nl
+    double *tv = red + 132;        // [MJ] xi3 s (one-/three-body terms)
     for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
     if (abar)
         for (int i = tid; i < N * n; i += 256) sz[i] = 0.0;
+    for (int mu = tid; mu < MJ; mu += 256) {
+        double t = 0.0;
+        for (int e = 0; e < N; ++e) t += ecp_jas_oval(J, (int64_t)w * N + e, mu);
+        tv[mu] = t;
+    }
     __syncthreads();
     const int np = eb.npairs[w];
     const size_t o0 = (size_t)eb.off[w];
@@ -256,6 +289,15 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
             }
         }
         uo = wave_sum_dpp(uo);
+        // one-/three-body: h_e and chi(r_e) of the lane's functions
+        double hj[4], xe[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int mu = lane + 64 * k;
+            const bool v = mu < MJ;
+            hj[k] = v ? J.xi1[mu] + tv[mu] - ecp_jas_oval(J, (int64_t)w * N + e, mu) : 0.0;
+            xe[k] = v ? (double)J.X[((size_t)w * N + e) * MJ + mu] : 0.0;
+        }
         for (int q = 0; q < 12; ++q) {
             const int row = 12 * pi + q;
             const double px = qp[3 * row], py = qp[3 * row + 1], pz = qp[3 * row + 2];
@@ -273,7 +315,20 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
                     un += jas_u(sqrt(qx * qx + qy * qy + qz * qz), S.ee_a, S.ee_F, S.ee_form);
                 }
             }
-            const double jr = exp(wave_sum_dpp(un) - uo);
+            double d13 = 0.0;
+            if (MJ > 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int mu = lane + 64 * k;
+                    if (mu < MJ) {
+                        double cv;
+                        jas_fn<1>(J.jb, R, mu, px, py, pz, &cv);
+                        d13 += (cv - xe[k]) * hj[k];
+                    }
+                }
+                d13 = wave_sum_dpp(d13);
+            }
+            const double jr = exp(wave_sum_dpp(un) - uo + d13);
             const double cq = c * jr;
             Ew += cq * t;
             if (abar && lane < n) sz[(size_t)e * n + lane] += cq * phj;
@@ -455,10 +510,187 @@ __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__rest
     }
 }
 
+// ---------------------------------------------------------------------------
+// The one-/three-body share of the derivatives through the ratios, one block
+// per walker.  With E_q = c'_q t_q, h_e = xi1 + xi3 (s - chi(r_e)) and
+// D_e = sum over e's points E_q (chi(r_q) - chi(r_e)), D = sum_e D_e:
+//   at each point       g13_q = grad chi(r_q)^T h_e           (rows[10..12]);
+//   at electron j       grad chi(r_j)^T xi3 (D - D_j)          (dedr; the
+//                       -grad chi(r_e)^T h_e of e's own points is the
+//                       electron's Jastrow gradient, taken by k_ecp_chain);
+//   per function mu     P_mu = sum_q E_q h_e,mu (grad chi_mu(r_q) - grad chi_mu(r_e))
+//                              + sum_j grad chi_mu(r_j) (xi3 (D - D_j))_mu,
+//                       added to jtao (the nucleus of mu gets -P_mu).
+// Wavefront v takes the electrons e = v mod 4 (e's points are consecutive
+// rows), lanes the functions mu = lane + 64 k; the wavefronts' per-function
+// partials are added in wavefront order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ecp_jas(int N, EcpJas<T> J, const double *__restrict__ R,
+                                                 const double *__restrict__ pos, EcpBufs<T> eb, double *dedr) {
+    __shared__ double tv[256], sDs[256];
+    __shared__ double sD[4][256], sDt[4][256];
+    __shared__ double sPp[4][3][256];
+    __shared__ double sel[128 * 3];
+    const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, MJ = J.MJ;
+    const double *p = pos + (size_t)w * N * 3;
+    const int np = eb.npairs[w];
+    const size_t o0 = (size_t)eb.off[w];
+    const int *pw = eb.pairs + o0;
+    const double *qp = eb.qpos + o0 * 12 * 3;
+    double *rw = eb.rows + o0 * 12 * ECP_ROW;
+    for (int mu = tid; mu < MJ; mu += 256) {
+        double t = 0.0;
+        for (int e = 0; e < N; ++e) t += ecp_jas_oval(J, (int64_t)w * N + e, mu);
+        tv[mu] = t;
+    }
+    for (int i = tid; i < 3 * N; i += 256) sel[i] = 0.0;
+    __syncthreads();
+    double Pk[4][3], Dt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Dt[k] = 0.0;
+        Pk[k][0] = Pk[k][1] = Pk[k][2] = 0.0;
+    }
+    int pi = 0;
+    for (int e = wave; e < N; e += 4) {
+        while (pi < np && (pw[pi] & 255) < e) ++pi;
+        int pe = pi;
+        while (pe < np && (pw[pe] & 255) == e) ++pe;
+        if (pe == pi) continue;
+        double hj[4], xe[4], Da[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int mu = lane + 64 * k;
+            const bool v = mu < MJ;
+            hj[k] = v ? J.xi1[mu] + tv[mu] - ecp_jas_oval(J, (int64_t)w * N + e, mu) : 0.0;
+            xe[k] = v ? (double)J.X[((size_t)w * N + e) * MJ + mu] : 0.0;
+            Da[k] = 0.0;
+        }
+        double es = 0.0;
+        for (int row = 12 * pi; row < 12 * pe; ++row) {
+            double *o = rw + (size_t)row * ECP_ROW;
+            const double Eq = o[0] * o[1];
+            const double px = qp[3 * row], py = qp[3 * row + 1], pz = qp[3 * row + 2];
+            double g3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int mu = lane + 64 * k;
+                if (mu < MJ) {
+                    double c5[5];
+                    jas_fn<5>(J.jb, R, mu, px, py, pz, c5);
+                    Da[k] += Eq * (c5[0] - xe[k]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        g3[d] += c5[1 + d] * hj[k];
+                        Pk[k][d] += Eq * hj[k] * c5[1 + d];
+                    }
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g3[d] = wave_sum_dpp(g3[d]);
+            if (lane == 0) {
+                o[10] = g3[0];
+                o[11] = g3[1];
+                o[12] = g3[2];
+            }
+            es += Eq;
+        }
+        // the electron's own functions, D_e staged for xi3 D_e
+        double ge[4][3];
+        wave_sync_s();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int mu = lane + 64 * k;
+            ge[k][0] = ge[k][1] = ge[k][2] = 0.0;
+            if (mu < MJ) {
+                double c5[5];
+                jas_fn<5>(J.jb, R, mu, p[3 * e], p[3 * e + 1], p[3 * e + 2], c5);
+                ge[k][0] = c5[1];
+                ge[k][1] = c5[2];
+                ge[k][2] = c5[3];
+                sD[wave][mu] = Da[k];
+            }
+            Dt[k] += Da[k];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Pk[k][d] -= es * hj[k] * ge[k][d];
+        }
+        wave_sync_s();
+        double el[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int mu = lane + 64 * k;
+            if (mu >= MJ) continue;
+            // (xi3 D_e)_mu; xi3 symmetric: row nu of column block k
+            const double *xb = J.xiblk + (size_t)k * MJ * 64 + lane;
+            double x3 = 0.0;
+            for (int nu = 0; nu < MJ; ++nu) x3 += xb[(size_t)nu * 64] * sD[wave][nu];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Pk[k][d] -= ge[k][d] * x3;
+                el[d] -= ge[k][d] * x3;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) el[d] = wave_sum_dpp(el[d]);
+        if (lane == 0) {
+            sel[3 * e] = el[0];
+            sel[3 * e + 1] = el[1];
+            sel[3 * e + 2] = el[2];
+        }
+        pi = pe;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int mu = lane + 64 * k;
+        if (mu < MJ) {
+            sDt[wave][mu] = Dt[k];
+            for (int d = 0; d < 3; ++d) sPp[wave][d][mu] = Pk[k][d];
+        }
+    }
+    __syncthreads();
+    for (int mu = tid; mu < MJ; mu += 256) sDs[mu] = (sDt[0][mu] + sDt[1][mu]) + (sDt[2][mu] + sDt[3][mu]);
+    __syncthreads();
+    // per function: the partials, and (xi3 D)_mu sum_j grad chi_mu(r_j)
+    for (int mu = tid; mu < MJ; mu += 256) {
+        const double *xb = J.xiblk + (size_t)(mu >> 6) * MJ * 64 + (mu & 63);
+        double x3 = 0.0;
+        for (int nu = 0; nu < MJ; ++nu) x3 += xb[(size_t)nu * 64] * sDs[nu];
+        double gs[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < N; ++j) {
+            double c5[5];
+            jas_fn<5>(J.jb, R, mu, p[3 * j], p[3 * j + 1], p[3 * j + 2], c5);
+            gs[0] += c5[1];
+            gs[1] += c5[2];
+            gs[2] += c5[3];
+        }
+        double *jt = J.jtao + ((size_t)w * MJ + mu) * 6;
+        for (int d = 0; d < 3; ++d)
+            jt[d] += ((sPp[0][d][mu] + sPp[1][d][mu]) + (sPp[2][d][mu] + sPp[3][d][mu])) + x3 * gs[d];
+    }
+    // per electron: grad chi(r_j)^T xi3 D = sum_mu O_grad[j][mu] D_mu, and -grad chi(r_j)^T xi3 D_j
+    if (tid < N) {
+        const int j = tid;
+        double s3[3] = {sel[3 * j], sel[3 * j + 1], sel[3 * j + 2]};
+        for (int mu = 0; mu < MJ; ++mu) {
+            const T *o = J.O + (((size_t)(mu >> 6) * J.rows + (size_t)w * N + j) * 5) * 64 + (mu & 63);
+            const double D = sDs[mu];
+            s3[0] += (double)o[64] * D;
+            s3[1] += (double)o[128] * D;
+            s3[2] += (double)o[192] * D;
+        }
+        double *de = dedr + ((size_t)w * N + j) * 3;
+        de[0] += s3[0];
+        de[1] += s3[1];
+        de[2] += s3[2];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const double *__restrict__ R,
                                                    const double *__restrict__ pos, EcpBufs<T> eb,
-                                                   const T *__restrict__ ktil, double *dedr) {
+                                                   const T *__restrict__ ktil, double *dedr,
+                                                   const double *__restrict__ jg) {
     extern __shared__ double sm[];
     const int w = blockIdx.x, tid = threadIdx.x;
     const int N = S.N, n = S.n_occ, M = S.M, A = S.A;
@@ -490,6 +722,13 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
             jx += f * sx;
             jy += f * sy_;
             jz += f * sz_;
+        }
+        if (jg) {
+            // the one-/three-body terms: grad_e (U1 + U3) = grad chi(r_e)^T h_e
+            const double *g = jg + ((size_t)w * N + e) * 4;
+            jx += g[0];
+            jy += g[1];
+            jz += g[2];
         }
         sjo[3 * e] = jx;
         sjo[3 * e + 1] = jy;
@@ -537,6 +776,9 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
             gj[1] += fq * qy;
             gj[2] += fq * qz;
         }
+        if (jg)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gj[k] += o[10 + k];
 #pragma unroll
         for (int k = 0; k < 3; ++k) g[k] = cq * g[k] + Eq * gj[k];
         // c_q through d and u . v
@@ -683,16 +925,21 @@ hipError_t configure_ecp(size_t lds) {
 template <typename T>
 hipError_t launch_ecp_energy(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
                              const EcpBufs<T> &eb, int nc, const T *ktil, T *abar, double *EL, int *status,
-                             hipStream_t st) {
-    hipLaunchKernelGGL((k_ecp_energy<T>), dim3(W), dim3(256), ecp_energy_lds(S.N, S.n_occ), st, S, E, R, pos, eb,
-                       nc, ktil, abar, EL, status);
+                             const EcpJas<T> &J, hipStream_t st) {
+    if (J.X && (J.MJ > 256 || S.N > 128)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_ecp_energy<T>), dim3(W), dim3(256), ecp_energy_lds(S.N, S.n_occ, J.X ? J.MJ : 0), st, S,
+                       E, R, pos, eb, nc, ktil, abar, EL, status, J);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, const double *R, const double *pos,
                               int W, const EcpBufs<T> &eb, const T *ktil, double *G, float *Gf, double *dedr,
-                              hipStream_t st) {
+                              const EcpJas<T> &J, hipStream_t st) {
+    if (J.X) {
+        if (J.MJ > 256 || S.N > 128) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_ecp_jas<T>), dim3(W), dim3(256), 0, st, S.N, J, R, pos, eb, dedr);
+    }
     const size_t lds = ecp_points_ao_lds(S.n_occ);
     const int nt = (S.n_occ + 15) / 16;
     if (nt == 1)
@@ -703,16 +950,18 @@ hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, cons
         hipLaunchKernelGGL((k_ecp_points_ao<T, 3>), dim3(W), dim3(256), lds, st, S, C, R, eb, ktil, G, Gf);
     else
         hipLaunchKernelGGL((k_ecp_points_ao<T, 4>), dim3(W), dim3(256), lds, st, S, C, R, eb, ktil, G, Gf);
-    hipLaunchKernelGGL((k_ecp_chain<T>), dim3(W), dim3(256), ecp_chain_lds(S.N), st, S, E, R, pos, eb, ktil, dedr);
+    hipLaunchKernelGGL((k_ecp_chain<T>), dim3(W), dim3(256), ecp_chain_lds(S.N), st, S, E, R, pos, eb, ktil, dedr,
+                       J.X ? J.jg : nullptr);
     return hipGetLastError();
 }
 
 #define ECP_INST(T)                                                                                                \
     template hipError_t launch_ecp_energy<T>(const SysDev &, const EcpDev &, const double *, const double *, int,     \
-                                             const EcpBufs<T> &, int, const T *, T *, double *, int *, hipStream_t); \
+                                             const EcpBufs<T> &, int, const T *, T *, double *, int *,               \
+                                             const EcpJas<T> &, hipStream_t);                                        \
     template hipError_t launch_ecp_adjoint<T>(const SysDev &, const EcpDev &, const T *, const double *,             \
                                               const double *, int, const EcpBufs<T> &, const T *, double *, float *, \
-                                              double *, hipStream_t);
+                                              double *, const EcpJas<T> &, hipStream_t);
 ECP_INST(double)
 ECP_INST(float)
 

@@ -94,8 +94,9 @@ struct EcpDev {
 // its points qpos[12 off[w] ..][3], the MO rows there phiq[12 off[w] ..][nc][n]
 // (type T) and per point rows[12 off[w] ..][ECP_ROW]; *nrows = 12 * the
 // pairs of the launch; ecp_dR[W][A][3]; per AO the sums over the points
-// tc[W][M][3] of kappa grad psi.
-constexpr int ECP_ROW = 10;
+// tc[W][M][3] of kappa grad psi.  rows[10..12]: the gradient at the point of
+// the one-/three-body Jastrow change (with those terms).
+constexpr int ECP_ROW = 13;
 template <typename T>
 struct EcpBufs {
     int *pairs, *npairs, *off, *nrows;
@@ -105,24 +106,38 @@ struct EcpBufs {
     double *ecp_dR;
     double *tc;
 };
+// The one-/three-body Jastrow in the pseudopotential's ratios (X null:
+// none): chi at the electrons X[W N][MJ] and the [xi3 | xi1] products O (the
+// measurement's, nq blocks of [W N][5][64]), xi1 and the FP64 column blocks
+// of [xi3 | xi1]; jg[W][N][4] the electrons' gradients of U1 + U3; jtao the
+// per-function sums the measurement subtracts per nucleus.
+template <typename T>
+struct EcpJas {
+    BasisDev jb{};
+    int MJ = 0;
+    int64_t rows = 0;
+    const T *X = nullptr, *O = nullptr;
+    const double *xi1 = nullptr, *xiblk = nullptr, *jg = nullptr;
+    double *jtao = nullptr;
+};
 // Pairs and points of the W walkers (walker id id0 + w, or id0 + idlist[w]).
 hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
                             int64_t id0, const int *idlist, uint32_t rot, int *pairs, int *npairs, int *off,
                             int *nrows, double *qpos, int *status, hipStream_t st);
 // LDS the energy kernel needs (bytes), and raising the limits to it
-size_t ecp_energy_lds(int N, int n);
+size_t ecp_energy_lds(int N, int n, int MJ);
 hipError_t configure_ecp(size_t lds);
 // E_loc + E_nl added to EL[w]; with abar: dE/dA through the inverses added.
 template <typename T>
 hipError_t launch_ecp_energy(const SysDev &S, const EcpDev &E, const double *R, const double *pos, int W,
                              const EcpBufs<T> &eb, int nc, const T *ktil, T *abar, double *EL, int *status,
-                             hipStream_t st);
+                             const EcpJas<T> &J, hipStream_t st);
 // The derivatives through the points: G (or Gf) += sum psi(r_q) y_q^T,
 // dedr[w][e] += ..., ecp_dR[w][a] = ...
 template <typename T>
 hipError_t launch_ecp_adjoint(const SysDev &S, const EcpDev &E, const T *C, const double *R, const double *pos,
                               int W, const EcpBufs<T> &eb, const T *ktil, double *G, float *Gf, double *dedr,
-                              hipStream_t st);
+                              const EcpJas<T> &J, hipStream_t st);
 
 // cpad: scratch of (M + 16) * 64 elements for the padded copy of C (n_occ <= 64);
 // rows_dev (optional): a device count that caps n_rows

@@ -136,12 +136,9 @@ def test_rejects_bad_pseudopotential():
     for field, value, word in (("term_l", np.where(e.term_l == 1, 4, e.term_l), "term"),
                                ("term_n", np.where(e.term_n == 2, 0, e.term_n), "term"),
                                ("term_exp", -e.term_exp, "term"),
-                               ("rcut", np.full_like(e.rcut, np.nan), "cutoff")):
+                               ("rcut", np.full_like(e.rcut, np.nan), "cutoff"),
+                              ("term_atom", np.where(e.term_atom == 0, 99, e.term_atom), "term")):
         bad = dataclasses.replace(mol, ecp=dataclasses.replace(e, **{field: value}))
         with pytest.raises(vmc.VmcError) as ei:
             vmc.Context(bad, 4)
         assert ei.value.code == vmc.VMC_EINVAL and word in str(ei.value), (field, str(ei.value))
-    both = inputs.with_body_jastrow(mol, 7)
-    with pytest.raises(vmc.VmcError) as ei:
-        vmc.Context(both, 4)
-    assert ei.value.code == vmc.VMC_EINVAL and "not supported" in str(ei.value)

@@ -12,7 +12,8 @@ geometry and at displaced nuclei; the estimators after sweeps with
 measurement (the quadrature turned by the sweep index), over several
 measurement launches.  Mixed precision within the mixed-vs-FP64 bounds, and
 its FP64 re-measurement of every walker equal to the FP64 path.  A capacity
-of pairs below a walker's need reports VMC_ECAPACITY.
+of pairs below a walker's need reports VMC_ECAPACITY.  The same with the
+one- and three/four-body Jastrow terms in the ratios (and dE/dxi).
 """
 import numpy as np
 import pytest
@@ -47,6 +48,11 @@ def dev():
 @pytest.fixture(scope="module")
 def mol9e():
     return inputs.with_ecp(inputs.make_config(1).molecule, 5)
+
+
+@pytest.fixture(scope="module")
+def mol9ej(mol9e):
+    return inputs.with_body_jastrow(mol9e, 7)
 
 
 def per_walker_oracle(mol, r, R=None, R0=None):
@@ -193,3 +199,74 @@ def test_fullsize_sampled(dev, mol9e):
     dEm, dFm = abs(E32 - E64), (F32 - F64).abs().max().item()
     print(f"[pseudopotential full size mixed vs fp64] |dE| = {dEm:.2e} Ha, max |dF| = {dFm:.2e} Ha/bohr")
     assert dEm < 1e-5 and dFm < 1e-4
+
+
+def test_body_jastrow_measure_parity(dev, mol9ej):
+    """Ratios with the one-/three-body change: the per-walker measurement at
+    the sampling geometry and at displaced nuclei (the Jastrow functions and
+    the points moving with their nuclei)."""
+    from oracle import sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    W = 5
+    ch, _ = sampler.run(wf.System(mol9ej), inputs.initial_walkers(mol9ej, W, 5), 2, 61)
+    r = ch.r
+    ref = per_walker_oracle(mol9ej, r)
+    ctx = vmc.Context(mol9ej, max_walkers=W, staging_walkers=3)
+    print("case: 9-atom pseudopotential with J1/J3, measurement", flush=True)
+    out = ctx.measure(torch.tensor(r, device=dev))
+    torch.cuda.synchronize()
+    for k in ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "dlnjac_dR", "O", "G"):
+        close(out[k].cpu().numpy(), ref[k], what=k)
+    R0 = np.array(mol9ej.xyz)
+    R = R0 + 0.03 * np.random.default_rng(4).standard_normal(R0.shape)
+    ref = per_walker_oracle(mol9ej, r[:3], R, R0)
+    out = ctx.measure(torch.tensor(r[:3], device=dev), R=torch.tensor(R, device=dev),
+                      R0=torch.tensor(R0, device=dev))
+    torch.cuda.synchronize()
+    for k in ref:
+        close(out[k].cpu().numpy(), ref[k], what=f"warped {k}")
+
+
+def test_body_jastrow_estimators(dev, mol9ej):
+    from oracle import vmc as ovmc
+    from paper_2511_05222_amd import vmc
+    W, sweeps = 6, 2
+    w0 = inputs.initial_walkers(mol9ej, W, 8)
+    ref = ovmc.run(mol9ej, w0, sweeps, 79, block_sweeps=1)
+    ctx = vmc.Context(mol9ej, max_walkers=W, staging_walkers=4, jastrow_gradient=True)
+    tw = torch.tensor(w0, device=dev)
+    print("case: 9-atom pseudopotential with J1/J3, estimators", flush=True)
+    ctx.sweep(tw, sweeps, 79)
+    g1, g3 = ctx.jastrow_gradient()
+    res = ctx.accumulate()
+    for k in ("E", "F_bare", "dE_dC"):
+        close(res[k], ref[k], what=k)
+    close(g1, ref["dE_dxi1"], what="dE_dxi1")
+    close(g3, ref["dE_dxi3"], what="dE_dxi3")
+
+
+def test_body_jastrow_mixed(dev, mol9ej):
+    from paper_2511_05222_amd import vmc
+    W = 256
+    w = torch.tensor(inputs.initial_walkers(mol9ej, W, 12), device=dev)
+    ctx64 = vmc.Context(mol9ej, max_walkers=W)
+    ctx64.sweep(w, 4, 88, measure=False)
+    ctx32 = vmc.Context(mol9ej, max_walkers=W, precision="mixed")
+    print("case: 9-atom pseudopotential with J1/J3, mixed", flush=True)
+    o32 = ctx32.measure(w, outputs=("EL", "dEL_dR", "dlnpsi_dR"))
+    o64 = ctx64.measure(w, outputs=("EL", "dEL_dR", "dlnpsi_dR"))
+    torch.cuda.synchronize()
+    dE = abs((o32["EL"] - o64["EL"]).mean().item())
+    assert dE < 1e-5, dE
+
+    def force(o):
+        E, H, P = o["EL"], o["dEL_dR"], o["dlnpsi_dR"]
+        e = E - E.mean()
+        return -H.mean(0) - 2.0 * ((e[:, None, None] * P).mean(0) - e.mean() * P.mean(0))
+
+    dF = (force(o32) - force(o64)).abs().max().item()
+    assert dF < 1e-4, dF
+    ctxp = vmc.Context(mol9ej, max_walkers=W, precision="mixed", promote_fraction=1.0)
+    op = ctxp.measure(w, outputs=("EL", "dEL_dR"))
+    torch.cuda.synchronize()
+    assert torch.equal(op["EL"], o64["EL"]) and torch.equal(op["dEL_dR"], o64["dEL_dR"])

@@ -741,3 +741,42 @@ def test_jastrow_parameter_derivatives(mol9):
         fd = (ehat(h) - ehat(-h)) / (2 * h)
         dEL = float(np.mean(dl["E_L"].imag / 1e-30))
         assert abs(fd - (an + dEL)) < 1e-6 * max(1.0, abs(fd)), (t1, t3, fd, an, dEL)
+
+
+def test_ecp_with_body_jastrow(mol9):
+    """The pseudopotential's ratio with the one- and three/four-body terms
+    equals Psi(r')/Psi(r) by full re-evaluation, and the fixed-sample energy
+    derivatives hold with both."""
+    import dataclasses
+    m = inputs.with_body_jastrow(inputs.with_ecp(mol9, 5), 7)
+    s = wf.System(m)
+    plain = wf.System(dataclasses.replace(m, ecp=None))
+    r = inputs.initial_walkers(m, 2, 4)
+    ev = wf.evaluate(s, s.xyz, r, keep=True)
+    base = wf.evaluate(plain, s.xyz, r)
+    checked = 0
+    for a, p in ev["ecp"]["atoms"].items():
+        for w, e in ((w, e) for w in range(2) for e in range(0, s.N, 4)):
+            q = (7 * e + w) % 12
+            if p["mask"][w, e] == 0:
+                continue
+            rm = r[w:w + 1].copy()
+            rm[0, e] = p["pts"][w, e, q]
+            mv = wf.evaluate(plain, s.xyz, rm)
+            exact = mv["sign"][0] * base["sign"][w] * np.exp(mv["lnpsi"][0] - base["lnpsi"][w])
+            got = p["ratio"][w, e, q] * p["jratio"][w, e, q]
+            assert abs(got - exact) < 1e-11 * max(1.0, abs(exact)), (a, w, e, q, got, exact)
+            checked += 1
+    assert checked >= 6
+    ch, _ = sampler.run(s, inputs.initial_walkers(m, 5, 3), 2, 3)
+    r, R0 = ch.r, s.xyz
+    meas = dv.measure(s, R0, r)
+    acc = estimators.Accumulator(s.A, s.M, s.C.shape[1])
+    acc.add(meas)
+    res = acc.result()
+    h = 1e-4
+    for al, k in [(0, 1), (4, 2)]:
+        Rp = R0.copy(); Rp[al, k] += h
+        Rm = R0.copy(); Rm[al, k] -= h
+        fd = (_ehat(s, Rp, R0, r, meas["lnpsi"]) - _ehat(s, Rm, R0, r, meas["lnpsi"])) / (2 * h)
+        assert abs(fd + res["F_bare"][al, k]) < 1e-6 * max(1.0, abs(fd)), (al, k, fd, res["F_bare"][al, k])
