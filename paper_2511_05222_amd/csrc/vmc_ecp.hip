@@ -108,6 +108,20 @@ __device__ inline double ecp_jas_oval(const EcpJas<T> &J, int64_t row, int mu) {
     return (double)J.O[(((size_t)(mu >> 6) * J.rows + row) * 5) * 64 + (mu & 63)];
 }
 
+// The two-body pair term u(r) and u'(r) / r from r^2 > 0, the reciprocal and
+// inverse square root from the hardware estimates and Newton steps.
+__device__ inline double ecp_u(double r2, const SysDev &S) {
+    const double r = r2 * rsqrt_nr(r2);
+    if (S.ee_form == 1) return S.ee_a * (1.0 - exp(-S.ee_F * r)) / S.ee_F;
+    return S.ee_a * r * rcp_nr(1.0 + S.ee_F * r);
+}
+__device__ inline double ecp_u1r(double r2, const SysDev &S) {
+    const double ir = rsqrt_nr(r2), r = r2 * ir;
+    if (S.ee_form == 1) return S.ee_a * exp(-S.ee_F * r) * ir;
+    const double q = rcp_nr(1.0 + S.ee_F * r);
+    return S.ee_a * q * q * ir;
+}
+
 __device__ inline double legendre(int l, double x) {
     return l == 0 ? 1.0 : (l == 1 ? x : (l == 2 ? 1.5 * x * x - 0.5 : (2.5 * x * x - 1.5) * x));
 }
@@ -235,14 +249,14 @@ size_t ecp_energy_lds(int N, int n, int MJ) {
     return sizeof(double) * ((size_t)3 * N + (size_t)N * n + (size_t)n * n + 132 + (size_t)MJ);
 }
 
-template <typename T>
+template <typename T, bool J13>
 __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const double *__restrict__ R,
                                                     const double *__restrict__ pos, EcpBufs<T> eb, int nc,
                                                     const T *__restrict__ ktil, T *abar, double *EL, int *status,
                                                     EcpJas<T> J) {
     extern __shared__ double sm[];
     const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int N = S.N, n = S.n_occ, MJ = J.X ? J.MJ : 0;
+    const int N = S.N, n = S.n_occ, MJ = J13 ? J.MJ : 0;
     double *sp = sm;               // [N][3]
     double *sz = sp + 3 * N;       // [N][n]: Z^T, row i = sum over the points of electron i
     double *sP = sz + N * n;       // [n][n]
@@ -251,11 +265,12 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
     for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
     if (abar)
         for (int i = tid; i < N * n; i += 256) sz[i] = 0.0;
-    for (int mu = tid; mu < MJ; mu += 256) {
-        double t = 0.0;
-        for (int e = 0; e < N; ++e) t += ecp_jas_oval(J, (int64_t)w * N + e, mu);
-        tv[mu] = t;
-    }
+    if constexpr (J13)
+        for (int mu = tid; mu < MJ; mu += 256) {
+            double t = 0.0;
+            for (int e = 0; e < N; ++e) t += ecp_jas_oval(J, (int64_t)w * N + e, mu);
+            tv[mu] = t;
+        }
     __syncthreads();
     const int np = eb.npairs[w];
     const size_t o0 = (size_t)eb.off[w];
@@ -285,18 +300,20 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
             const int j = lane + 64 * h;
             if (j < N && j != e) {
                 const double qx = ex - sp[3 * j], qy = ey - sp[3 * j + 1], qz = ez - sp[3 * j + 2];
-                uo += jas_u(sqrt(qx * qx + qy * qy + qz * qz), S.ee_a, S.ee_F, S.ee_form);
+                uo += ecp_u(qx * qx + qy * qy + qz * qz, S);
             }
         }
         uo = wave_sum_dpp(uo);
         // one-/three-body: h_e and chi(r_e) of the lane's functions
         double hj[4], xe[4];
+        if constexpr (J13) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int mu = lane + 64 * k;
-            const bool v = mu < MJ;
-            hj[k] = v ? J.xi1[mu] + tv[mu] - ecp_jas_oval(J, (int64_t)w * N + e, mu) : 0.0;
-            xe[k] = v ? (double)J.X[((size_t)w * N + e) * MJ + mu] : 0.0;
+            for (int k = 0; k < 4; ++k) {
+                const int mu = lane + 64 * k;
+                const bool v = mu < MJ;
+                hj[k] = v ? J.xi1[mu] + tv[mu] - ecp_jas_oval(J, (int64_t)w * N + e, mu) : 0.0;
+                xe[k] = v ? (double)J.X[((size_t)w * N + e) * MJ + mu] : 0.0;
+            }
         }
         for (int q = 0; q < 12; ++q) {
             const int row = 12 * pi + q;
@@ -312,11 +329,11 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
                 const int j = lane + 64 * h;
                 if (j < N && j != e) {
                     const double qx = px - sp[3 * j], qy = py - sp[3 * j + 1], qz = pz - sp[3 * j + 2];
-                    un += jas_u(sqrt(qx * qx + qy * qy + qz * qz), S.ee_a, S.ee_F, S.ee_form);
+                    un += ecp_u(qx * qx + qy * qy + qz * qz, S);
                 }
             }
             double d13 = 0.0;
-            if (MJ > 0) {
+            if constexpr (J13) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int mu = lane + 64 * k;
@@ -389,35 +406,35 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
 // k_ecp_points_ao (threads over (AO mu, slot), the slots splitting the
 //   points when the AOs are fewer than the threads): G[mu] += sum_q
 //   psi_mu(r_q) y_q and tc[mu] = sum_q kappa_q,mu grad psi_mu(r_q),
-//   kappa_q = C y_q, over batches of 16 points staged in LDS; the slots'
+//   kappa_q = C y_q, over batches of 32 points staged in LDS; the slots'
 //   partials added in slot order.
 // k_ecp_chain:
-//   phase 0 (threads over electrons): jo[e] = sum_{j != e} u'(r_ej) (r_e - r_j)/r_ej
-//            and es[e] = the sum of E_q = c'_q t_q over e's points;
+//   phase 0 (threads over electrons): jo[e] = sum_{j != e} u'(r_ej) (r_e - r_j)/r_ej;
+//            (threads over pairs) es[e] = the sum of E_q = c'_q t_q over e's
+//            points, by pair sums added in pair order;
 //   phase 2 (threads over points): the chain through r_q = R_a + d v_q, the
 //            weights c_q and the Jastrow at r_q, into rows[4..9];
 //   phase 3 (threads over (electron, slot)): per electron its own points'
-//            terms and the other points' Jastrow terms; per nucleus its
-//            points' terms, V_loc and the AOs at the points (tc; fixed order).
+//            terms and the other points' Jastrow terms; (threads over pairs)
+//            per nucleus its pairs' point terms in pair order, then V_loc and
+//            the AOs at the points (tc; fixed order).
+// The pair sums go through LDS in chunks of 256 pairs.
 // ---------------------------------------------------------------------------
-__device__ inline double jas_u1(double r, double a, double F, int form) {
-    if (form == 1) return a * exp(-F * r);
-    const double q = 1.0 / (1.0 + F * r);
-    return a * q * q;
-}
+
+constexpr int ECP_AO_ROWS = 32;   // points staged per batch
 
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__restrict__ C,
                                                        const double *__restrict__ R, EcpBufs<T> eb,
                                                        const T *__restrict__ ktil, double *G, float *Gf) {
-    constexpr int NW = 16 * NT;
+    constexpr int NW = 16 * NT, RB = ECP_AO_ROWS;
     extern __shared__ double sm[];
     const int w = blockIdx.x, tid = threadIdx.x;
     const int N = S.N, n = S.n_occ, M = S.M;
     const BasisDev &B = S.basis;
-    double *sy = sm;               // [16][n]
-    double *sq = sy + 16 * n;      // [16][3]
-    double *part = sq + 48;        // [256][16]
+    double *sq = sm;               // [RB][3]
+    double *part = sq + 3 * RB;    // [256][16]
+    T *sy = (T *)(part + 256 * 16);   // [RB][n]
     const int np = eb.npairs[w], nrow = 12 * np;
     const size_t o0 = (size_t)eb.off[w];
     const int *pw = eb.pairs + o0;
@@ -434,42 +451,46 @@ __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__rest
         const int s = B.ao_shell[mm], atom = B.shell_atom[s], pwr = B.ao_pow[mm];
         const double eta = B.ao_eta[mm];
         const double Rx = R[3 * atom], Ry = R[3 * atom + 1], Rz = R[3 * atom + 2];
-        double cr[NW], g[NW];
+        // (sums over the points in the arithmetic type: in FP32 the mixed
+        // measurement's G rows are FP32 too)
+        T cr[NW], g[NW];
 #pragma unroll
         for (int j = 0; j < NW; ++j) {
-            cr[j] = j < n ? (double)C[(size_t)mm * n + j] : 0.0;
-            g[j] = 0.0;
+            cr[j] = j < n ? C[(size_t)mm * n + j] : T(0);
+            g[j] = T(0);
         }
-        double tcx = 0.0, tcy = 0.0, tcz = 0.0;
-        for (int r0 = 0; r0 < nrow; r0 += 16) {
+        T tcx = T(0), tcy = T(0), tcz = T(0);
+        for (int r0 = 0; r0 < nrow; r0 += RB) {
             __syncthreads();
-            for (int idx = tid; idx < 16 * n; idx += 256) {
+            for (int idx = tid; idx < RB * n; idx += 256) {
                 const int r = idx / n, j = idx - (idx / n) * n, row = r0 + r;
                 double y = 0.0;
                 if (row < nrow) {
                     const int e = pw[row / 12] & 255;
                     y = rw[(size_t)row * ECP_ROW] * (double)kt[(size_t)e * n + j];
                 }
-                sy[idx] = y;
+                sy[idx] = (T)y;
             }
-            for (int idx = tid; idx < 48; idx += 256) {
+            for (int idx = tid; idx < 3 * RB; idx += 256) {
                 const int row = r0 + idx / 3;
                 sq[idx] = row < nrow ? qp[(size_t)3 * r0 + idx] : 0.0;
             }
             __syncthreads();
-            const int nr = min(16, nrow - r0);
+            const int nr = min(RB, nrow - r0);
             if (!vm) continue;
             for (int r = slot; r < nr; r += nsl) {
                 const double dx = sq[3 * r] - Rx, dy = sq[3 * r + 1] - Ry, dz = sq[3 * r + 2] - Rz;
                 const double rho = dx * dx + dy * dy + dz * dz;
-                double R0, R1, R2, R3, o[5];
-                shell_radial<5, double>(B, s, rho, R0, R1, R2, R3);
-                ao_components<5, double>(dx, dy, dz, rho, R0, R1, R2, R3, pwr, eta, o);
-                double kap = 0.0;
-                const double *y = sy + (size_t)r * n;
+                // the AO and its gradient in the arithmetic type (FP32: the
+                // split exponential, as in the measurement's adjoint)
+                T R0, R1, R2, R3, o[5];
+                shell_radial<5, T>(B, s, rho, R0, R1, R2, R3);
+                ao_components<5, T>((T)dx, (T)dy, (T)dz, (T)rho, R0, R1, R2, R3, pwr, (T)eta, o);
+                T kap = T(0);
+                const T *y = sy + (size_t)r * n;
 #pragma unroll
                 for (int j = 0; j < NW; ++j) {
-                    const double yj = j < n ? y[j] : 0.0;
+                    const T yj = j < n ? y[j] : T(0);
                     kap += cr[j] * yj;
                     g[j] += o[0] * yj;
                 }
@@ -483,7 +504,7 @@ __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__rest
         for (int c0 = 0; c0 < NW; c0 += 16) {
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 16; ++j) part[tid * 16 + j] = g[c0 + j];
+            for (int j = 0; j < 16; ++j) part[tid * 16 + j] = (double)g[c0 + j];
             __syncthreads();
             if (vm && slot == 0)
                 for (int j = c0; j < min(n, c0 + 16); ++j) {
@@ -497,9 +518,9 @@ __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__rest
                 }
         }
         __syncthreads();
-        part[3 * tid] = tcx;
-        part[3 * tid + 1] = tcy;
-        part[3 * tid + 2] = tcz;
+        part[3 * tid] = (double)tcx;
+        part[3 * tid + 1] = (double)tcy;
+        part[3 * tid + 2] = (double)tcz;
         __syncthreads();
         if (vm && slot == 0)
             for (int k = 0; k < 3; ++k) {
@@ -692,13 +713,14 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
                                                    const T *__restrict__ ktil, double *dedr,
                                                    const double *__restrict__ jg) {
     extern __shared__ double sm[];
+    __shared__ int cpi[256];       // a chunk's pairs: electron or nucleus (-1: none)
     const int w = blockIdx.x, tid = threadIdx.x;
     const int N = S.N, n = S.n_occ, M = S.M, A = S.A;
     const BasisDev &B = S.basis;
     double *sp = sm;               // [N][3]
     double *sjo = sp + 3 * N;      // [N][3]
     double *ses = sjo + 3 * N;     // [N]
-    double *part = ses + N;        // [256][3]
+    double *part = ses + N;        // [256][3] (also a chunk's pair sums)
     const double *stc = eb.tc + (size_t)w * M * 3;
     for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
     const int np = eb.npairs[w], nrow = 12 * np;
@@ -717,8 +739,7 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
             if (j == e) continue;
             const double sx = sp[3 * e] - sp[3 * j], sy_ = sp[3 * e + 1] - sp[3 * j + 1],
                          sz_ = sp[3 * e + 2] - sp[3 * j + 2];
-            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
-            const double f = jas_u1(re, S.ee_a, S.ee_F, S.ee_form) / re;
+            const double f = ecp_u1r(sx * sx + sy_ * sy_ + sz_ * sz_, S);
             jx += f * sx;
             jy += f * sy_;
             jz += f * sz_;
@@ -733,14 +754,26 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
         sjo[3 * e] = jx;
         sjo[3 * e + 1] = jy;
         sjo[3 * e + 2] = jz;
-        double es = 0.0;
-        for (int pi = 0; pi < np; ++pi)
-            if ((pw[pi] & 255) == e)
-                for (int q = 0; q < 12; ++q) {
-                    const double *o = rw + (size_t)(12 * pi + q) * ECP_ROW;
-                    es += o[0] * o[1];
-                }
-        ses[e] = es;
+        ses[e] = 0.0;
+    }
+    for (int p0 = 0; p0 < np; p0 += 256) {
+        __syncthreads();
+        const int pi = p0 + tid;
+        double sq = 0.0;
+        if (pi < np)
+            for (int q = 0; q < 12; ++q) {
+                const double *o = rw + (size_t)(12 * pi + q) * ECP_ROW;
+                sq += o[0] * o[1];
+            }
+        part[tid] = sq;
+        cpi[tid] = pi < np ? (pw[pi] & 255) : -1;
+        __syncthreads();
+        if (tid < N) {
+            double es = ses[tid];
+            for (int k = 0; k < min(256, np - p0); ++k)
+                if (cpi[k] == tid) es += part[k];
+            ses[tid] = es;
+        }
     }
     __syncthreads();
     // ---- phase 2 ----
@@ -770,8 +803,7 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
         for (int j = 0; j < N; ++j) {
             if (j == e) continue;
             const double qx = px - sp[3 * j], qy = py - sp[3 * j + 1], qz = pz - sp[3 * j + 2];
-            const double rq = sqrt(qx * qx + qy * qy + qz * qz);
-            const double fq = jas_u1(rq, S.ee_a, S.ee_F, S.ee_form) / rq;
+            const double fq = ecp_u1r(qx * qx + qy * qy + qz * qz, S);
             gj[0] += fq * qx;
             gj[1] += fq * qy;
             gj[2] += fq * qz;
@@ -817,8 +849,7 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
                 // the Jastrow change of another electron's point, through r_j
                 const double Eq = o[0] * o[1];
                 const double qx = qp[3 * row] - xj, qy = qp[3 * row + 1] - yj, qz = qp[3 * row + 2] - zj;
-                const double rq = sqrt(qx * qx + qy * qy + qz * qz);
-                const double fq = Eq * jas_u1(rq, S.ee_a, S.ee_F, S.ee_form) / rq;
+                const double fq = Eq * ecp_u1r(qx * qx + qy * qy + qz * qz, S);
                 s3[0] -= fq * qx;
                 s3[1] -= fq * qy;
                 s3[2] -= fq * qz;
@@ -839,8 +870,7 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
         for (int e = 0; e < N; ++e) {
             if (e == j || ses[e] == 0.0) continue;
             const double sx = sp[3 * e] - xj, sy_ = sp[3 * e + 1] - yj, sz_ = sp[3 * e + 2] - zj;
-            const double re = sqrt(sx * sx + sy_ * sy_ + sz_ * sz_);
-            const double fe = ses[e] * jas_u1(re, S.ee_a, S.ee_F, S.ee_form) / re;
+            const double fe = ses[e] * ecp_u1r(sx * sx + sy_ * sy_ + sz_ * sz_, S);
             s3[0] += fe * sx;
             s3[1] += fe * sy_;
             s3[2] += fe * sz_;
@@ -860,18 +890,35 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
         de[1] += s3[1];
         de[2] += s3[2];
     }
-    if (tid < A) {
-        const int a = tid;
+    // per nucleus: its pairs' point terms
+    double sa[3] = {0.0, 0.0, 0.0};
+    for (int p0 = 0; p0 < np; p0 += 256) {
+        __syncthreads();
+        const int pi = p0 + tid;
         double s3[3] = {0.0, 0.0, 0.0};
-        for (int pi = 0; pi < np; ++pi) {
-            if ((pw[pi] >> 8) != a) continue;
+        if (pi < np)
             for (int q = 0; q < 12; ++q) {
                 const double *o = rw + (size_t)(12 * pi + q) * ECP_ROW;
                 s3[0] += o[7];
                 s3[1] += o[8];
                 s3[2] += o[9];
             }
-        }
+        part[3 * tid] = s3[0];
+        part[3 * tid + 1] = s3[1];
+        part[3 * tid + 2] = s3[2];
+        cpi[tid] = pi < np ? (pw[pi] >> 8) : -1;
+        __syncthreads();
+        if (tid < A)
+            for (int k = 0; k < min(256, np - p0); ++k)
+                if (cpi[k] == tid) {
+                    sa[0] += part[3 * k];
+                    sa[1] += part[3 * k + 1];
+                    sa[2] += part[3 * k + 2];
+                }
+    }
+    if (tid < A) {
+        const int a = tid;
+        double s3[3] = {sa[0], sa[1], sa[2]};
         if (E.t0[a] != E.t0[a + 1])
             for (int j = 0; j < N; ++j) {
                 const double dx = sp[3 * j] - R[3 * a], dy = sp[3 * j + 1] - R[3 * a + 1], dz = sp[3 * j + 2] - R[3 * a + 2];
@@ -910,11 +957,12 @@ hipError_t launch_ecp_pairs(const SysDev &S, const EcpDev &E, const double *R, c
     return hipGetLastError();
 }
 
-static size_t ecp_points_ao_lds(int n) { return sizeof(double) * ((size_t)16 * n + 48 + 256 * 16); }
+static size_t ecp_points_ao_lds(int n) { return sizeof(double) * ((size_t)ECP_AO_ROWS * n + 3 * ECP_AO_ROWS + 256 * 16); }
 static size_t ecp_chain_lds(int N) { return sizeof(double) * ((size_t)7 * N + 256 * 3); }
 
 hipError_t configure_ecp(size_t lds) {
-    const void *f[2] = {(const void *)k_ecp_energy<double>, (const void *)k_ecp_energy<float>};
+    const void *f[4] = {(const void *)k_ecp_energy<double, false>, (const void *)k_ecp_energy<float, false>,
+                        (const void *)k_ecp_energy<double, true>, (const void *)k_ecp_energy<float, true>};
     for (const void *g : f) {
         const hipError_t e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -927,8 +975,13 @@ hipError_t launch_ecp_energy(const SysDev &S, const EcpDev &E, const double *R, 
                              const EcpBufs<T> &eb, int nc, const T *ktil, T *abar, double *EL, int *status,
                              const EcpJas<T> &J, hipStream_t st) {
     if (J.X && (J.MJ > 256 || S.N > 128)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ecp_energy<T>), dim3(W), dim3(256), ecp_energy_lds(S.N, S.n_occ, J.X ? J.MJ : 0), st, S,
-                       E, R, pos, eb, nc, ktil, abar, EL, status, J);
+    const size_t lds = ecp_energy_lds(S.N, S.n_occ, J.X ? J.MJ : 0);
+    if (J.X)
+        hipLaunchKernelGGL((k_ecp_energy<T, true>), dim3(W), dim3(256), lds, st, S, E, R, pos, eb, nc, ktil, abar, EL,
+                           status, J);
+    else
+        hipLaunchKernelGGL((k_ecp_energy<T, false>), dim3(W), dim3(256), lds, st, S, E, R, pos, eb, nc, ktil, abar,
+                           EL, status, J);
     return hipGetLastError();
 }
 
