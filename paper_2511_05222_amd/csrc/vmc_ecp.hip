@@ -31,6 +31,8 @@
 //                  one-/three-body terms k_ecp_jas first forms their share:
 //                  the gradient at each point, the electrons' terms through
 //                  the h_j, and the Jastrow functions' per-nucleus sums.
+#include <algorithm>
+
 #include "vmc.h"
 #include "vmc_pipeline.hpp"
 #include "vmc_regs.hpp"
@@ -245,8 +247,11 @@ __global__ __launch_bounds__(128) void k_ecp_place(SysDev S, EcpDev E, const dou
 // has one writer), lanes run over orbitals (ratio) and electrons (Jastrow).
 // Per point it keeps rows[.] = (c'_q, t_q, exp(dJ_q), c_q).
 // ---------------------------------------------------------------------------
+size_t ecp_energy_pts_lds(int N, int n);
+// (the larger of the two energy kernels' needs)
 size_t ecp_energy_lds(int N, int n, int MJ) {
-    return sizeof(double) * ((size_t)3 * N + (size_t)N * n + (size_t)n * n + 132 + (size_t)MJ);
+    return std::max(sizeof(double) * ((size_t)3 * N + (size_t)N * n + (size_t)n * n + 132 + (size_t)MJ),
+                    ecp_energy_pts_lds(N, n));
 }
 
 template <typename T, bool J13>
@@ -380,6 +385,144 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
         if (!isfinite(e_l)) atomicOr(status, STATUS_NONFINITE);
     }
     if (!abar) return;
+    // dE/dA_b = -(K~_b Z_b K~_b): sP = Z_b K~_b, then Abar_b -= K~_b sP
+    for (int b = 0; b < 2; ++b) {
+        const int off = b ? S.n_up : 0, nb = b ? S.n_dn : S.n_up;
+        __syncthreads();
+        for (int idx = tid; idx < n * n; idx += 256) {
+            const int a = idx / n, j = idx - (idx / n) * n;
+            double s = 0.0;
+            for (int i = 0; i < nb; ++i) s += sz[(size_t)(off + i) * n + a] * (double)kt[(size_t)(off + i) * n + j];
+            sP[idx] = s;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nb * n; idx += 256) {
+            const int ei = idx / n, j = idx - (idx / n) * n;
+            double s = 0.0;
+            for (int a = 0; a < n; ++a) s += (double)kt[(size_t)(off + ei) * n + a] * sP[(size_t)a * n + j];
+            T *ab = abar + ((size_t)w * N + off + ei) * n + j;
+            *ab = (T)((double)*ab - s);
+        }
+    }
+}
+
+// The same without the one-/three-body terms, threads over the points (one
+// block per walker): per electron its own pair sum; per point t_q, the pair
+// terms at r_q and c_q; E_nl summed over the threads in a fixed order; with
+// abar, Z^T[e][j] by threads over (electron, orbital) from the points' rows,
+// then dE/dA as above.
+size_t ecp_energy_pts_lds(int N, int n) {
+    return sizeof(double) * ((size_t)4 * N + (size_t)N * n + (size_t)n * n + 256 + 4);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ecp_energy_pts(SysDev S, EcpDev E, const double *__restrict__ R,
+                                                        const double *__restrict__ pos, EcpBufs<T> eb, int nc,
+                                                        const T *__restrict__ ktil, T *abar, double *EL,
+                                                        int *status) {
+    extern __shared__ double sm[];
+    const int w = blockIdx.x, tid = threadIdx.x;
+    const int N = S.N, n = S.n_occ;
+    double *sp = sm;               // [N][3]
+    double *suo = sp + 3 * N;      // [N] sum_{j != e} u(r_ej)
+    double *sz = suo + N;          // [N][n]: Z^T
+    double *sP = sz + N * n;       // [n][n]
+    double *red = sP + n * n;      // [256] E_nl partials, then the local terms
+    for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
+    __syncthreads();
+    for (int e = tid; e < N; e += 256) {
+        double uo = 0.0;
+        for (int j = 0; j < N; ++j)
+            if (j != e) {
+                const double qx = sp[3 * e] - sp[3 * j], qy = sp[3 * e + 1] - sp[3 * j + 1],
+                             qz = sp[3 * e + 2] - sp[3 * j + 2];
+                uo += ecp_u(qx * qx + qy * qy + qz * qz, S);
+            }
+        suo[e] = uo;
+    }
+    __syncthreads();
+    const int np = eb.npairs[w], nrow = 12 * np;
+    const size_t o0 = (size_t)eb.off[w];
+    const int *pw = eb.pairs + o0;
+    const T *ph = eb.phiq + o0 * 12 * nc * n;
+    const T *kt = ktil + (size_t)w * N * n;
+    const double *qp = eb.qpos + o0 * 12 * 3;
+    double *rw = eb.rows + o0 * 12 * ECP_ROW;
+    double Ew = 0.0;
+    for (int row = tid; row < nrow; row += 256) {
+        const int pr = pw[row / 12], e = pr & 255, a = pr >> 8;
+        const double ex = sp[3 * e], ey = sp[3 * e + 1], ez = sp[3 * e + 2];
+        const double dx = ex - R[3 * a], dy = ey - R[3 * a + 1], dz = ez - R[3 * a + 2];
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        const double px = qp[3 * row], py = qp[3 * row + 1], pz = qp[3 * row + 2];
+        const double cs = (dx * (px - R[3 * a]) + dy * (py - R[3 * a + 1]) + dz * (pz - R[3 * a + 2])) / (d * d);
+        double c = 0.0;
+        for (int l = 0; l <= E.lmax; ++l) {
+            double V, dV;
+            ecp_radial(E, a, l, d, V, dV);
+            c += (double)(2 * l + 1) / 12.0 * V * legendre(l, cs);
+        }
+        const T *phr = ph + (size_t)row * nc * n;
+        const T *ke = kt + (size_t)e * n;
+        double t = 0.0;
+        for (int j = 0; j < n; ++j) t += (double)phr[j] * (double)ke[j];
+        double un = 0.0;
+        for (int j = 0; j < N; ++j)
+            if (j != e) {
+                const double qx = px - sp[3 * j], qy = py - sp[3 * j + 1], qz = pz - sp[3 * j + 2];
+                un += ecp_u(qx * qx + qy * qy + qz * qz, S);
+            }
+        const double jr = exp(un - suo[e]);
+        const double cq = c * jr;
+        Ew += cq * t;
+        double *o = rw + (size_t)row * ECP_ROW;
+        o[0] = cq;
+        o[1] = t;
+        o[2] = jr;
+        o[3] = c;
+    }
+    red[tid] = Ew;
+    __syncthreads();
+    // the local part, every electron and nucleus
+    double El = 0.0;
+    for (int i = tid; i < N; i += 256)
+        for (int a = 0; a < S.A; ++a) {
+            if (E.t0[a] == E.t0[a + 1]) continue;
+            const double dx = sp[3 * i] - R[3 * a], dy = sp[3 * i + 1] - R[3 * a + 1], dz = sp[3 * i + 2] - R[3 * a + 2];
+            double v, dv;
+            ecp_radial(E, a, -1, sqrt(dx * dx + dy * dy + dz * dz), v, dv);
+            El += v;
+        }
+    if (tid == 0 && EL) {
+        double enl = 0.0;
+        for (int k = 0; k < 256; ++k) enl += red[k];
+        red[256] = enl;
+    }
+    __syncthreads();
+    red[tid] = El;
+    __syncthreads();
+    if (tid == 0 && EL) {
+        double s = 0.0;
+        for (int k = 0; k < 256; ++k) s += red[k];
+        const double e_l = EL[w] + (s + red[256]);
+        EL[w] = e_l;
+        if (!isfinite(e_l)) atomicOr(status, STATUS_NONFINITE);
+    }
+    if (!abar) return;
+    // Z^T[e][j] = sum over e's points c'_q phi_q[j] (the rows written above)
+    __syncthreads();
+    for (int idx = tid; idx < N * n; idx += 256) {
+        const int e = idx / n, j = idx - (idx / n) * n;
+        double z = 0.0;
+        for (int pi = 0; pi < np; ++pi) {
+            if ((pw[pi] & 255) != e) continue;
+            for (int q = 0; q < 12; ++q) {
+                const int row = 12 * pi + q;
+                z += rw[(size_t)row * ECP_ROW] * (double)ph[(size_t)row * nc * n + j];
+            }
+        }
+        sz[idx] = z;
+    }
     // dE/dA_b = -(K~_b Z_b K~_b): sP = Z_b K~_b, then Abar_b -= K~_b sP
     for (int b = 0; b < 2; ++b) {
         const int off = b ? S.n_up : 0, nb = b ? S.n_dn : S.n_up;
@@ -961,7 +1104,7 @@ static size_t ecp_points_ao_lds(int n) { return sizeof(double) * ((size_t)ECP_AO
 static size_t ecp_chain_lds(int N) { return sizeof(double) * ((size_t)7 * N + 256 * 3); }
 
 hipError_t configure_ecp(size_t lds) {
-    const void *f[4] = {(const void *)k_ecp_energy<double, false>, (const void *)k_ecp_energy<float, false>,
+    const void *f[4] = {(const void *)k_ecp_energy_pts<double>, (const void *)k_ecp_energy_pts<float>,
                         (const void *)k_ecp_energy<double, true>, (const void *)k_ecp_energy<float, true>};
     for (const void *g : f) {
         const hipError_t e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -975,13 +1118,15 @@ hipError_t launch_ecp_energy(const SysDev &S, const EcpDev &E, const double *R, 
                              const EcpBufs<T> &eb, int nc, const T *ktil, T *abar, double *EL, int *status,
                              const EcpJas<T> &J, hipStream_t st) {
     if (J.X && (J.MJ > 256 || S.N > 128)) return hipErrorInvalidValue;
-    const size_t lds = ecp_energy_lds(S.N, S.n_occ, J.X ? J.MJ : 0);
     if (J.X)
-        hipLaunchKernelGGL((k_ecp_energy<T, true>), dim3(W), dim3(256), lds, st, S, E, R, pos, eb, nc, ktil, abar, EL,
-                           status, J);
+        hipLaunchKernelGGL((k_ecp_energy<T, true>), dim3(W), dim3(256),
+                           sizeof(double) * ((size_t)3 * S.N + (size_t)S.N * S.n_occ + (size_t)S.n_occ * S.n_occ +
+                                             132 + (size_t)J.MJ),
+                           st, S, E,
+                           R, pos, eb, nc, ktil, abar, EL, status, J);
     else
-        hipLaunchKernelGGL((k_ecp_energy<T, false>), dim3(W), dim3(256), lds, st, S, E, R, pos, eb, nc, ktil, abar,
-                           EL, status, J);
+        hipLaunchKernelGGL((k_ecp_energy_pts<T>), dim3(W), dim3(256), ecp_energy_pts_lds(S.N, S.n_occ), st, S, E, R,
+                           pos, eb, nc, ktil, abar, EL, status);
     return hipGetLastError();
 }
 
