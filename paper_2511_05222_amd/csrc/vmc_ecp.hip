@@ -16,7 +16,9 @@
 //                  over the walkers of a launch, and their 12 points each;
 //                  the MO rows at the points are then one k_mo_rows_mfma
 //                  launch over the packed rows;
-//   k_ecp_energy   after k_dense: rho_q, E_loc + E_nl added to E_L; and, with
+//   k_ecp_energy_pts (threads over the points; with the one-/three-body
+//   terms k_ecp_energy, a wavefront per electron)
+//                  after k_dense: rho_q, E_loc + E_nl added to E_L; and, with
 //                  Z[j][i] = sum_q c'_q phi_q[j] (c'_q = c_q exp(dJ_q), the
 //                  points of electron i), the derivative through the inverses,
 //                  dE/dA_b = -(K~_b Z_b K~_b) with K~[e][j] = K[j][e], added to
