@@ -260,12 +260,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         // slot of orbital i
         if (lane < KN) phin[sig] = ph;
         wave_sync_s();
-        // v = phi^T K for the column this lane holds
+        // v = phi^T K for the column this lane holds (the broadcast vector
+        // read 16 bytes at a time: the regions are 16-byte aligned)
+        typedef T V16 __attribute__((ext_vector_type(16 / sizeof(T))));
+        constexpr int VL = 16 / sizeof(T);
         T v0 = T(0), v1 = T(0);
 #pragma unroll
-        for (int r = 0; r < KN; r += 2) {
-            v0 += phin[r] * Kr[r];
-            v1 += phin[r + 1] * Kr[r + 1];
+        for (int r = 0; r < KN; r += VL) {
+            const V16 a = *(const V16 *)(phin + r);
+#pragma unroll
+            for (int u = 0; u < VL; u += 2) {
+                v0 += a[u] * Kr[r + u];
+                v1 += a[u + 1] * Kr[r + u + 1];
+            }
         }
         const T v = v0 + v1;
         // the lane holding electron jj of the block
@@ -289,7 +296,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             }
             if (lane == pj) {
 #pragma unroll
-                for (int r = 0; r < KN; ++r) colj[r] = Kr[r];
+                for (int r = 0; r < KN; r += VL) {
+                    V16 c;
+#pragma unroll
+                    for (int u = 0; u < VL; ++u) c[u] = Kr[r + u];
+                    *(V16 *)(colj + r) = c;
+                }
             }
             wave_sync_s();
             if constexpr (J13) {
@@ -300,7 +312,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             const T rr = sizeof(T) == sizeof(float) ? (T)__builtin_amdgcn_rcpf((float)ratio) : (T)rcp_nr(ratio);
             const T t = (v - (lane == pj ? T(1) : T(0))) * rr;
 #pragma unroll
-            for (int r = 0; r < KN; ++r) Kr[r] -= colj[r] * t;
+            for (int r = 0; r < KN; r += VL) {
+                const V16 c = *(const V16 *)(colj + r);
+#pragma unroll
+                for (int u = 0; u < VL; ++u) Kr[r + u] -= c[u] * t;
+            }
             if (fabs(ratio) < S.forced_ratio) need = true;
         }
         if (accept != nullptr && lane == 0) accept[(size_t)e * W + w] = acc ? 1 : 0;
