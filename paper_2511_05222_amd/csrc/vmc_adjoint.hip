@@ -35,7 +35,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
     T *Ks = (T *)(smem + L.off_k);    // [RT*16][ldk]  K~[e][i]
     T *As = (T *)(smem + L.off_a);    // [RT*16][ldk]  Abar[e][i]
     double *sp = (double *)(smem + L.off_p);    // [N][3]
-    double *sg = (double *)(smem + L.off_g);    // [N][3] Jastrow gradient
+    T *sg = (T *)(smem + L.off_g);              // [N][3] Jastrow gradient (arithmetic type)
     double *dpw = (double *)(smem + L.off_d);   // [nw][N][3] per-wave dE_L/dr_e partials
     const T *ktw = mb.ktil + (size_t)w * N * n;
     const T *abw = mb.abar + (size_t)w * N * n;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
     }
     for (int k = tid; k < 3 * N; k += blockDim.x) {
         sp[k] = mb.pos[(size_t)w * N * 3 + k];
-        sg[k] = mb.gb[(size_t)w * N * 6 + 6 * (k / 3) + (k - (k / 3) * 3)];
+        sg[k] = (T)mb.gb[(size_t)w * N * 6 + 6 * (k / 3) + (k - (k / 3) * 3)];
     }
     for (int k = tid; k < nw * 3 * N; k += blockDim.x) dpw[k] = 0.0;
     __syncthreads();
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(512) void k_adjoint_mfma(SysDev S, const T *__restr
                 ao_lane_radial<T, NPR>(al, S.basis, rho_d, R0, u1, u2, u3);
                 T d[14];
                 ao_lane_components<T, NPR>(al, x, y, z, rho, R0, u1, u2, u3, d);
-                const T gx = (T)sg[3 * ec], gy = (T)sg[3 * ec + 1], gz = (T)sg[3 * ec + 2];
+                const T gx = sg[3 * ec], gy = sg[3 * ec + 1], gz = sg[3 * ec + 2];
                 const T hgx = gx * d[5] + gy * d[6] + gz * d[7];
                 const T hgy = gx * d[6] + gy * d[8] + gz * d[9];
                 const T hgz = gx * d[7] + gy * d[9] + gz * d[10];
