@@ -13,7 +13,8 @@ measurement (the quadrature turned by the sweep index), over several
 measurement launches.  Mixed precision within the mixed-vs-FP64 bounds, and
 its FP64 re-measurement of every walker equal to the FP64 path.  A capacity
 of pairs below a walker's need reports VMC_ECAPACITY.  The same with the
-one- and three/four-body Jastrow terms in the ratios (and dE/dxi).
+one- and three/four-body Jastrow terms in the ratios (and dE/dxi).  More
+than 256 pairs per walker on the 21-atom valence molecule.
 """
 import numpy as np
 import pytest
@@ -270,3 +271,60 @@ def test_body_jastrow_mixed(dev, mol9ej):
     op = ctxp.measure(w, outputs=("EL", "dEL_dR"))
     torch.cuda.synchronize()
     assert torch.equal(op["EL"], o64["EL"]) and torch.equal(op["dEL_dR"], o64["dEL_dR"])
+
+
+def test_many_pairs_21atom(dev):
+    """More than 256 pairs per walker (the kernels' pair sums run in chunks of
+    256): the 21-atom valence molecule (68 electrons) with cutoffs of 10 bohr
+    around its 13 C and O nuclei.  E_L, ln|Psi|, O and G against the oracle at
+    1e-10; per walker, dE_L/dR summed over the nuclei vanishes (translations
+    move electrons, nuclei and points together); the fixed-sample energy's
+    central differences (Richardson, h = 1e-4) in nuclear coordinates match
+    the adjoint to 1e-6."""
+    import dataclasses
+    from oracle import derivatives as dv, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    m = inputs.with_ecp(inputs.make_config(2).molecule, 5)
+    rc = np.where(np.asarray(m.ecp.rcut) > 0, 10.0, 0.0)
+    mol = dataclasses.replace(m, ecp=dataclasses.replace(m.ecp, rcut=rc))
+    W = 8
+    r = inputs.initial_walkers(mol, W, 3)
+    R0n = np.asarray(mol.xyz)
+    d = np.linalg.norm(r[:, :, None, :] - R0n[None, None, :, :], axis=-1)
+    pairs = (d < rc[None, None, :]).sum(axis=(1, 2))
+    assert pairs.max() > 256, pairs
+    ctx = vmc.Context(mol, max_walkers=W)
+    tw = torch.tensor(r, device=dev)
+    print(f"case: 21-atom pseudopotential, {pairs.min()}..{pairs.max()} pairs per walker", flush=True)
+    out = ctx.measure(tw)
+    torch.cuda.synchronize()
+    s = wf.System(mol)
+    O, G, ev = dv.coefficient_derivatives(s, s.xyz, r[:2])
+    close(out["EL"][:2].cpu().numpy(), ev["E_L"], what="EL")
+    close(out["lnpsi"][:2].cpu().numpy(), ev["lnpsi"], what="lnpsi")
+    close(out["O"][:2].cpu().numpy(), O, what="O")
+    close(out["G"][:2].cpu().numpy(), G, what="G")
+    H = out["dEL_dR"].cpu().numpy()
+    assert np.abs(H.sum(axis=1)).max() <= 1e-9 * np.abs(H).max(), np.abs(H.sum(axis=1)).max()
+    # the fixed-sample energy through the autograd function
+    R0 = torch.tensor(R0n, device=dev)
+    C0 = torch.tensor(mol.C, device=dev)
+    lnpsi0 = out["lnpsi"]
+    R = R0.clone().requires_grad_(True)
+    E = vmc.vmc_energy(C0, R, ctx, tw, R0, lnpsi0)
+    E.backward()
+    gR = R.grad.cpu().numpy()
+
+    def ehat(Rv):
+        return vmc.vmc_energy(C0, Rv, ctx, tw, R0, lnpsi0).item()
+
+    for a, k in [(0, 0), (4, 2), (9, 1), (12, 0), (15, 2)]:
+        def at(t):
+            Rt = R0.clone()
+            Rt[a, k] += t
+            return ehat(Rt)
+        h = 1e-4
+        d1 = (at(h) - at(-h)) / (2 * h)
+        d2 = (at(h / 2) - at(-h / 2)) / h
+        f = (4.0 * d2 - d1) / 3.0
+        assert abs(f - gR[a, k]) <= 1e-6 * max(1.0, abs(f)), (a, k, f, gR[a, k])
