@@ -328,3 +328,20 @@ def test_many_pairs_21atom(dev):
         d2 = (at(h / 2) - at(-h / 2)) / h
         f = (4.0 * d2 - d1) / 3.0
         assert abs(f - gR[a, k]) <= 1e-6 * max(1.0, abs(f)), (a, k, f, gR[a, k])
+
+
+def test_exponential_jastrow(dev, mol9e):
+    """The pseudopotential's ratios with the exponential two-body Jastrow
+    (eq. twobody_v_exp, F = 1.3): the per-walker measurement against the
+    oracle at 1e-10."""
+    import dataclasses
+    from paper_2511_05222_amd import vmc
+    mol = dataclasses.replace(mol9e, jastrow=dataclasses.replace(mol9e.jastrow, ee_F=1.3, ee_form=1))
+    r = inputs.initial_walkers(mol, 4, 17)
+    ref = per_walker_oracle(mol, r)
+    ctx = vmc.Context(mol, max_walkers=4)
+    print("case: 9-atom pseudopotential, exponential Jastrow", flush=True)
+    out = ctx.measure(torch.tensor(r, device=dev))
+    torch.cuda.synchronize()
+    for k in ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G"):
+        close(out[k].cpu().numpy(), ref[k], what=f"exp-Jastrow {k}")
