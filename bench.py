@@ -30,6 +30,11 @@ Also in the line:
   ecp_9atom      the pseudopotential workload (the 9-atom molecule made
                  valence-only with a seeded semilocal pseudopotential, 16384
                  walkers, both precisions) with its kernels' rooflines;
+  next_rows      on the 21-atom molecule with 16384 walkers: the one- and
+                 three/four-body Jastrow (mixed, FP64, and mixed with the
+                 Jastrow-parameter gradient sums), the exponential two-body
+                 Jastrow (mixed), reweighted accumulation of given walkers,
+                 and the jackknife error pipeline through the Z-vector solve;
   family_64      the 64-geometry mixed-size family (9-21 atoms, 8192 walkers
                  each, mixed precision), one context per geometry, their
                  sweeps on four streams (and on one, for comparison);
@@ -280,6 +285,81 @@ def ecp_entry(args, dev):
     return out
 
 
+def next_rows_entry(args, dev, W=16384, warmup=5, steps=3):
+    """The rows beyond the headline path, each on the 21-atom molecule:
+    the one- and three/four-body Jastrow (mixed and FP64, and mixed with the
+    Jastrow-parameter gradient sums), the exponential two-body form (mixed),
+    reweighted accumulation of given walkers with weights, and the jackknife
+    error pipeline through the Z-vector solve (4 replicas)."""
+    import dataclasses
+    import torch
+    from paper_2511_05222_amd import inputs, vmc
+    spec = inputs.make_config(2)
+    mol = spec.molecule
+    out = {}
+
+    def rate(m, prec, **kw):
+        ctx = vmc.Context(m, max_walkers=W, refresh_period=32, precision=prec, **kw)
+        w = torch.tensor(inputs.initial_walkers(m, W, spec.seed), device=dev)
+        dt, _, _, _ = run_steps(ctx, w, spec.seed, warmup, steps)
+        del ctx, w
+        return {"value": W * steps / dt, "ms_per_step": dt / steps * 1e3}
+
+    mj = inputs.with_body_jastrow(mol, 7)
+    out["body_jastrow"] = {
+        "workload": f"{mol.name} + one-/three-body Jastrow on {mj.jastrow.jas_basis.n_ao} Jastrow basis functions, "
+                    f"{W} walkers",
+        "mixed": rate(mj, "mixed"), "fp64": rate(mj, "fp64"),
+        "mixed_with_xi_gradient": rate(mj, "mixed", jastrow_gradient=True)}
+    out["body_jastrow"]["mixed_over_fp64"] = out["body_jastrow"]["mixed"]["value"] / out["body_jastrow"]["fp64"][
+        "value"]
+    me = dataclasses.replace(mol, jastrow=dataclasses.replace(mol.jastrow, ee_form=1))
+    out["exp_jastrow"] = {"workload": f"{mol.name}, exponential two-body Jastrow, {W} walkers",
+                          "mixed": rate(me, "mixed")}
+    # reweighted accumulation: measurement + weighted estimator sums of W
+    # given walkers (the weights from the caller)
+    ctx = vmc.Context(mol, max_walkers=W, refresh_period=32, precision="mixed")
+    w = torch.tensor(inputs.initial_walkers(mol, W, spec.seed), device=dev)
+    ctx.sweep(w, warmup, spec.seed, measure=False)
+    wt = torch.exp(torch.randn(W, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev)
+                               .manual_seed(5)) * 0.5)
+    ctx.accumulate_walkers(w, wt)
+    torch.cuda.synchronize()
+    ctx.accumulate(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.accumulate_walkers(w, wt)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.accumulate(reset=True)
+    out["reweighted"] = {"workload": f"{mol.name}, {W} given walkers with weights, mixed",
+                         "walkers_per_s": W * steps / dt, "ms_per_call": dt / steps * 1e3}
+    del ctx, w, wt
+    # jackknife error pipeline: replicas of dE/dC, their right-hand sides,
+    # one batched Jacobi-CG solve at d = 188 n, jackknife statistics
+    ctx = vmc.Context(mol, max_walkers=W, precision="mixed", block_sweeps=1, jackknife_blocks=4)
+    w = torch.tensor(inputs.initial_walkers(mol, W, spec.seed), device=dev)
+    ctx.sweep(w, 4, spec.seed)
+    n = mol.n_occ
+    Cv = torch.tensor(np.ascontiguousarray(mol.C_full[:, n:]), device=dev)
+    H = torch.tensor(inputs.seeded_spd(188 * n, 13), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    jk = ctx.jackknife()
+    b = vmc.zvector_rhs(Cv, jk["dE_dC"])
+    z, its = vmc.zvector_solve(H, b.reshape(b.shape[0], -1), rtol=1e-12, maxit=2000, jacobi=True)
+    vmc.jackknife_stats(z)
+    vmc.jackknife_stats(jk["F_bare"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["jackknife"] = {"workload": f"{mol.name}, {W} walkers x 4 sweeps in 4 blocks; Z-vector d = {188 * n}",
+                        "replicas": int(b.shape[0]), "ms": dt * 1e3, "cg_iterations": its}
+    del ctx, w, H
+    for k, v in out.items():
+        print(f"# next row {k}: {json.dumps(v)}", file=sys.stderr, flush=True)
+    return out
+
+
 def family_entry(args, dev, n_streams=4):
     """The mixed-size family: 64 seeded geometries of 9-21 atoms, 8192
     walkers each, mixed precision, one context per geometry.  Every context
@@ -372,6 +452,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ecp", action="store_true", help="skip the pseudopotential workload")
     ap.add_argument("--no-family", action="store_true", help="skip the 64-geometry mixed-size family")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the Jastrow, reweighting and jackknife entries")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the measurement and a plain copy of known size (for counter runs)")
     args = ap.parse_args()
@@ -490,6 +572,8 @@ def main():
         del c9, w9
     if args.workload == "21atom" and not args.no_ecp:
         line["ecp_9atom"] = ecp_entry(args, dev)
+    if args.workload == "21atom" and not args.no_next:
+        line["next_rows"] = next_rows_entry(args, dev)
     if args.workload == "21atom" and not args.no_family:
         del ctx
         line["family_64"] = family_entry(args, dev)

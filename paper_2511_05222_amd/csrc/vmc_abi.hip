@@ -75,7 +75,7 @@ struct vmc_ctx {
     // the Jastrow-parameter gradient's sums (jastrow_gradient): per launch
     // the FP64 basis values at the electrons and the partial sums, and the
     // compensated accumulators [s | (E-s) s | O3 | (E-s) O3]
-    double *xg_X = nullptr, *xg_part = nullptr, *xg_acc = nullptr, *xg_comp = nullptr;
+    double *xg_X = nullptr, *xg_part = nullptr, *xg_acc = nullptr, *xg_comp = nullptr, *xg_scr = nullptr;
     int64_t xg_n = 0;
     float *d_xiblk_f = nullptr;
     // staging of the Jastrow terms: sweeps ([W][N] rows) and measurements
@@ -546,7 +546,7 @@ static int measure_accumulate(vmc_ctx *c, const double *walkers, int64_t W, cons
             HIP_OK(c, vmcx::launch_jas_values<double>(c->jdev, c->d_R, walkers + c0 * c->N * 3, cw * c->N, c->xg_X,
                                                       st));
             HIP_OK(c, vmcx::launch_xi_sums(c->xg_X, c->N, c->MJ, (int)cw, c->st_EL, c->shift, a.wt, c->xg_part,
-                                           c->xg_acc, c->xg_comp, st));
+                                           c->xg_scr, c->xg_acc, c->xg_comp, st));
         }
         HIP_OK(c, vmcx::launch_reduce(a, 0, c->n_est, cw, c->partial, MAX_SEG, c->acc, c->comp, blk, blkw, blk_all,
                                       st));
@@ -1002,7 +1002,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     const int64_t eq = c->has_ecp ? (int64_t)c->edev.pcap * 12 : 0;
     const int64_t ecp_pw = c->has_ecp ? eq * (3 + 5 * (int64_t)c->n_occ + vmcx::ECP_ROW) + A3 + 3 * M + c->edev.pcap + 2
                                       : 0;
-    const int64_t xg_pw = (opt->jastrow_gradient && c->MJ > 0) ? (int64_t)c->N * c->MJ : 0;
+    const int64_t xg_pw = (opt->jastrow_gradient && c->MJ > 0) ? (int64_t)(c->N + 1) * c->MJ : 0;
     const size_t per_walker = sizeof(double) * (size_t)(3 + 3 * A3 + 2 * Mn + 5 * Nn + 2 * Nn + 6 * c->N +
                                                         3 * (int64_t)c->N + 6 * M + 3 * c->N + jas_pw + ecp_pw +
                                                         xg_pw);
@@ -1044,6 +1044,7 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     if (opt->jastrow_gradient && c->MJ > 0) {
         c->xg_n = 2 * (int64_t)c->MJ + 2 * (int64_t)c->MJ * c->MJ;
         if ((rc = c->dalloc(&c->xg_X, (size_t)chunk * c->N * c->MJ)) || (rc = c->dalloc(&c->xg_part, c->xg_n)) ||
+            (rc = c->dalloc(&c->xg_scr, vmcx::xi_scratch_doubles((int)chunk, c->MJ))) ||
             (rc = c->dalloc(&c->xg_acc, c->xg_n)) || (rc = c->dalloc(&c->xg_comp, c->xg_n)))
             return bail(rc);
         if (hipMemset(c->xg_acc, 0, c->xg_n * 8) != hipSuccess || hipMemset(c->xg_comp, 0, c->xg_n * 8) != hipSuccess)

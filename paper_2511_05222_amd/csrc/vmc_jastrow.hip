@@ -27,6 +27,7 @@
 // and a function centred on nucleus alpha moves with it, so its terms enter
 // dE_L/dR_alpha and dlnPsi/dR_alpha with the opposite sign (per-function
 // sums over electrons, added per nucleus by k_finalize).
+#include "vmc_mfma.hpp"
 #include "vmc_pipeline.hpp"
 
 namespace vmcx {
@@ -148,7 +149,10 @@ __device__ inline JasTerm jas_term(const BasisDev &JB, const double *R, int mu, 
 // Per walker: adds the Jastrow terms' dE_L/dr_e to dedr[w][e] and writes the
 // per-function electron sums jtao[w][mu] = (sum_e f, sum_e p).  pos: the
 // evaluation positions; gb[w][e]: total Jastrow gradient (0..2) and
-// determinant gradient (3..5).
+// determinant gradient (3..5).  Each (electron, function) term is evaluated
+// once: wavefront v takes the electrons e = v mod 4, lanes the functions
+// mu = lane + 64 k; per electron the sum over functions by a wavefront sum,
+// per function the wavefronts' partial sums added in wavefront order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *__restrict__ R, int N, int MJ, int nq,
                                                      int64_t rows, int64_t row0, const double *__restrict__ pos,
@@ -156,10 +160,11 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
                                                      const double *__restrict__ gb, const double *__restrict__ xi1,
                                                      double *__restrict__ dedr, double *__restrict__ jtao) {
     __shared__ double tv[JAS_MAX], xh[JAS_MAX];
-    __shared__ double ab[JAS_ELEC * 3], pe[JAS_ELEC * 3];
-    __shared__ double half0[JAS_ELEC * 3], half1[JAS_ELEC * 3];
-    const int w = blockIdx.x, tid = threadIdx.x;
-    const T *Xw = X + (size_t)w * N * MJ;
+    __shared__ double ab[JAS_ELEC * 3], pe[JAS_ELEC * 3], fe[JAS_ELEC * 3];
+    __shared__ double fp[JAS_MAX * 6];
+    const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    (void)X;
+    (void)nq;
     // element (e, c, mu) of the products
     auto Oat = [&](int e, int c, int mu) -> double {
         const int q = mu >> 6;
@@ -171,7 +176,6 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
         pe[i] = pos[(size_t)w * N * 3 + i];
     }
     __syncthreads();
-    (void)Xw;
     // t = xi3 s (the value products summed over electrons) and xi3 H
     for (int mu = tid; mu < MJ; mu += 256) {
         double t = 0.0, h = 0.0;
@@ -184,49 +188,53 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
         xh[mu] = h;
     }
     __syncthreads();
-    (void)nq;
-    // per function: sums over electrons
-    for (int mu = tid; mu < MJ; mu += 256) {
-        double f[3] = {0.0, 0.0, 0.0}, p[3] = {0.0, 0.0, 0.0};
-        const double x1 = xi1[mu];
-        for (int e = 0; e < N; ++e) {
-            const double *a = ab + 3 * e;
-            const double g = x1 + tv[mu] - Oat(e, 0, mu);
-            const double hq = a[0] * Oat(e, 1, mu) + a[1] * Oat(e, 2, mu) + a[2] * Oat(e, 3, mu) - 0.5 * Oat(e, 4, mu);
-            const JasTerm o = jas_term<T>(JB, R, mu, pe + 3 * e, a, g, xh[mu] - hq);
+    double F[4][3], P[4][3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                f[k] += o.f[k];
-                p[k] += o.p[k];
-            }
-        }
-        double *jt = jtao + ((size_t)w * MJ + mu) * 6;
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            jt[k] = f[k];
-            jt[3 + k] = p[k];
-        }
-    }
-    // per electron: sums over functions, in two halves (threads e and e + 128)
-    for (int i = tid; i < 2 * JAS_ELEC; i += 256) {
-        const int e = i & (JAS_ELEC - 1), hh = i >> 7;
-        if (e >= N) continue;
+        for (int d = 0; d < 3; ++d) F[k][d] = P[k][d] = 0.0;
+    for (int e = wave; e < N; e += 4) {
         const double *a = ab + 3 * e;
-        double f[3] = {0.0, 0.0, 0.0};
-        const int m0 = hh ? MJ / 2 : 0, m1 = hh ? MJ : MJ / 2;
-        for (int mu = m0; mu < m1; ++mu) {
+        double f3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int mu = lane + 64 * k;
+            if (mu >= MJ) continue;
             const double g = xi1[mu] + tv[mu] - Oat(e, 0, mu);
             const double hq = a[0] * Oat(e, 1, mu) + a[1] * Oat(e, 2, mu) + a[2] * Oat(e, 3, mu) - 0.5 * Oat(e, 4, mu);
             const JasTerm o = jas_term<T>(JB, R, mu, pe + 3 * e, a, g, xh[mu] - hq);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) f[k] += o.f[k];
+            for (int d = 0; d < 3; ++d) {
+                F[k][d] += o.f[d];
+                P[k][d] += o.p[d];
+                f3[d] += o.f[d];
+            }
         }
-        double *hv = hh ? half1 : half0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) hv[3 * e + k] = f[k];
+        for (int d = 0; d < 3; ++d) f3[d] = wave_sum_dpp(f3[d]);
+        if (lane == 0) {
+            fe[3 * e] = f3[0];
+            fe[3 * e + 1] = f3[1];
+            fe[3 * e + 2] = f3[2];
+        }
     }
-    __syncthreads();
-    for (int i = tid; i < 3 * N; i += 256) dedr[(size_t)w * N * 3 + i] += half0[i] + half1[i];
+    // per function: the wavefronts' partials, in wavefront order
+    for (int v = 0; v < 4; ++v) {
+        if (wave == v)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int mu = lane + 64 * k;
+                if (mu >= MJ) continue;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    fp[6 * mu + d] = (v ? fp[6 * mu + d] : 0.0) + F[k][d];
+                    fp[6 * mu + 3 + d] = (v ? fp[6 * mu + 3 + d] : 0.0) + P[k][d];
+                }
+            }
+        __syncthreads();
+    }
+    for (int i = tid; i < 6 * MJ; i += 256) jtao[(size_t)w * MJ * 6 + i] = fp[i];
+    for (int i = tid; i < 3 * N; i += 256) dedr[(size_t)w * N * 3 + i] += fe[i];
 }
 
 template <typename T>
@@ -293,50 +301,136 @@ namespace vmcx {
 //   O_xi1 = s = sum_i chi(r_i),  O_xi3 = (s s^T - sum_i chi(r_i) chi(r_i)^T) / 2
 // (the gradient of U3 with respect to the symmetric xi3).  With a_w the
 // walker's weight and b_w = a_w (E_L,w - shift), the launch's partial sums
-//   part = [sum a s | sum b s | sum a O_xi3 | sum b O_xi3]   (MJ, MJ, MJ^2, MJ^2)
-// one block per 16 x 16 tile (mu, nu) of O_xi3, walkers in order; the tiles
-// of the first column also form the O_xi1 sums.  X[w][i][mu] = chi_mu(r_i) in
-// FP64.
+//   part = [sum a s | sum b s | sum a O_xi3 | sum b O_xi3]   (MJ, MJ, MJ^2, MJ^2).
+// The O_xi3 sums are weighted Gram matrices, (S^T D S - Y^T D' Y) / 2 with
+// Y = [W N x MJ] the basis values of every electron, S = [W x MJ] their
+// walker sums and D, D' the walker weights (repeated over the electrons for
+// D'), formed on FP64 MFMA: k_wgram computes a 64 x 64 block-tile of both
+// weightings over a range of rows; the row ranges' partials are added in
+// order by k_xi_finish.  X[w][i][mu] = chi_mu(r_i) in FP64.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_xi_sums(const double *__restrict__ X, int N, int MJ, int W,
-                                                 const double *__restrict__ EL, const double *__restrict__ shift,
-                                                 const double *__restrict__ wt, double *part) {
-    __shared__ double xm[128 * 16], xn[128 * 16];
-    const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
-    const int mu0 = 16 * blockIdx.x, nu0 = 16 * blockIdx.y;
-    const int mu = mu0 + ti, nu = nu0 + tj;
-    double s3a = 0.0, s3b = 0.0, s1a = 0.0, s1b = 0.0;
-    const double sh = *shift;
-    for (int w = 0; w < W; ++w) {
-        __syncthreads();
-        const double *xw = X + (size_t)w * N * MJ;
-        for (int k = tid; k < N * 16; k += 256) {
-            const int i = k >> 4, q = k & 15;
-            xm[k] = mu0 + q < MJ ? xw[(size_t)i * MJ + mu0 + q] : 0.0;
-            xn[k] = nu0 + q < MJ ? xw[(size_t)i * MJ + nu0 + q] : 0.0;
-        }
-        __syncthreads();
-        double sm = 0.0, sn = 0.0, p = 0.0;
-        for (int i = 0; i < N; ++i) {
-            const double a = xm[16 * i + ti], b = xn[16 * i + tj];
-            sm += a;
-            sn += b;
-            p += a * b;
-        }
-        const double aw = wt ? wt[w] : 1.0, bw = aw * (EL[w] - sh);
-        const double o3 = 0.5 * (sm * sn - p);
-        s3a += aw * o3;
-        s3b += bw * o3;
-        s1a += aw * sm;
-        s1b += bw * sm;
+constexpr int XI_SPLIT_Y = 32, XI_SPLIT_S = 8;   // row ranges of the two products
+
+size_t xi_scratch_doubles(int W, int MJ) {
+    return (size_t)W * MJ + (size_t)(XI_SPLIT_Y + XI_SPLIT_S) * 2 * MJ * MJ;
+}
+
+// S[w][mu] = sum_i X[w][i][mu]
+__global__ __launch_bounds__(256) void k_xi_walker_sums(const double *__restrict__ X, int N, int MJ, int W,
+                                                        double *__restrict__ Sm) {
+    const int w = blockIdx.x;
+    for (int mu = threadIdx.x; mu < MJ; mu += 256) {
+        double a = 0.0;
+        for (int i = 0; i < N; ++i) a += X[((size_t)w * N + i) * MJ + mu];
+        Sm[(size_t)w * MJ + mu] = a;
     }
-    if (mu < MJ && nu < MJ) {
-        part[2 * MJ + (size_t)mu * MJ + nu] = s3a;
-        part[2 * MJ + (size_t)MJ * MJ + (size_t)mu * MJ + nu] = s3b;
-        if (blockIdx.y == 0 && tj == 0) {
-            part[mu] = s1a;
-            part[MJ + mu] = s1b;
+}
+
+// Block (tile, range): rows [k0, k1) of Z [K][MJ], row k belonging to walker
+// k / rpw; alpha_k = wt[w] (1 without weights), beta_k = alpha_k (EL[w] - shift).
+// part[range][0 / 1][mu][nu] = sum_k alpha_k / beta_k z_k[mu] z_k[nu] over the
+// block-tile's 64 x 64 entries.  Wavefront v takes the 16 rows mu of sub-tile
+// v and all four nu sub-tiles.
+__global__ __launch_bounds__(256) void k_wgram(const double *__restrict__ Z, int64_t K, int MJ, int rpw,
+                                               const double *__restrict__ wt, const double *__restrict__ EL,
+                                               const double *__restrict__ shift, int64_t per, double *part) {
+    typedef Mfma<double> MF;
+    __shared__ double zm[16][64], zn[16][64], al[16], be[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ml = lane & 15, kg = lane >> 4;
+    const int nbt = (MJ + 63) / 64, bi = blockIdx.x / nbt, bj = blockIdx.x - (blockIdx.x / nbt) * nbt;
+    const int64_t k0 = (int64_t)blockIdx.y * per, k1 = min(K, k0 + per);
+    const double sh = *shift;
+    MF::acc_t ga[4], gb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ga[j] = gb[j] = MF::zero();
+    for (int64_t kb = k0; kb < k1; kb += 16) {
+        __syncthreads();
+        for (int idx = tid; idx < 16 * 64; idx += 256) {
+            const int r = idx >> 6, c = idx & 63;
+            const int64_t k = kb + r;
+            const bool in = k < k1;
+            const int cm = 64 * bi + c, cn = 64 * bj + c;
+            zm[r][c] = (in && cm < MJ) ? Z[k * MJ + cm] : 0.0;
+            zn[r][c] = (in && cn < MJ) ? Z[k * MJ + cn] : 0.0;
         }
+        if (tid < 16) {
+            const int64_t k = kb + tid;
+            double a = 0.0, b = 0.0;
+            if (k < k1) {
+                const int64_t w = k / rpw;
+                a = wt ? wt[w] : 1.0;
+                b = a * (EL[w] - sh);
+            }
+            al[tid] = a;
+            be[tid] = b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int r = 4 * ks + kg;
+            const double am = zm[r][16 * wave + ml], wa = al[r], wb = be[r];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double z = zn[r][16 * j + ml];
+                ga[j] = MF::fma(am, wa * z, ga[j]);
+                gb[j] = MF::fma(am, wb * z, gb[j]);
+            }
+        }
+    }
+    double *pa = part + (size_t)blockIdx.y * 2 * MJ * MJ, *pb = pa + (size_t)MJ * MJ;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int mu = 64 * bi + 16 * wave + MF::row(lane, v), nu = 64 * bj + 16 * j + ml;
+            if (mu < MJ && nu < MJ) {
+                pa[(size_t)mu * MJ + nu] = ga[j][v];
+                pb[(size_t)mu * MJ + nu] = gb[j][v];
+            }
+        }
+}
+
+// part[mu] = sum_w a_w s_w[mu], part[MJ + mu] = sum_w b_w s_w[mu]: block mu,
+// threads over walkers, a fixed-order block sum.
+__global__ __launch_bounds__(256) void k_xi_s1(const double *__restrict__ Sm, int W, int MJ,
+                                               const double *__restrict__ EL, const double *__restrict__ shift,
+                                               const double *__restrict__ wt, double *part) {
+    __shared__ double ra[256], rb[256];
+    const int mu = blockIdx.x, tid = threadIdx.x;
+    const double sh = *shift;
+    double a1 = 0.0, b1 = 0.0;
+    for (int w = tid; w < W; w += 256) {
+        const double aw = wt ? wt[w] : 1.0, sv = Sm[(size_t)w * MJ + mu];
+        a1 += aw * sv;
+        b1 += aw * (EL[w] - sh) * sv;
+    }
+    ra[tid] = a1;
+    rb[tid] = b1;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+            ra[tid] += ra[tid + h];
+            rb[tid] += rb[tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[mu] = ra[0];
+        part[MJ + mu] = rb[0];
+    }
+}
+
+// part[2 MJ ..] = [(G_S - G_Y)_a / 2 | (G_S - G_Y)_b / 2], the ranges'
+// partials added in order.
+__global__ void k_xi_finish(int MJ, const double *__restrict__ pY, int nY, const double *__restrict__ pS, int nS,
+                            double *part) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m2 = (int64_t)MJ * MJ;
+    if (t < 2 * m2) {
+        double y = 0.0, q = 0.0;
+        for (int g = 0; g < nY; ++g) y += pY[(size_t)g * 2 * m2 + t];
+        for (int g = 0; g < nS; ++g) q += pS[(size_t)g * 2 * m2 + t];
+        part[2 * MJ + t] = 0.5 * (q - y);
     }
 }
 
@@ -350,11 +444,23 @@ __global__ void k_add_compensated(const double *__restrict__ part, int64_t n, do
 }
 
 hipError_t launch_xi_sums(const double *X, int N, int MJ, int W, const double *EL, const double *shift,
-                          const double *wt, double *part, double *acc, double *comp, hipStream_t st) {
-    if (N > 128) return hipErrorInvalidValue;
-    const int nt = (MJ + 15) / 16;
-    hipLaunchKernelGGL(k_xi_sums, dim3(nt, nt), dim3(256), 0, st, X, N, MJ, W, EL, shift, wt, part);
-    const int64_t n = 2 * (int64_t)MJ + 2 * (int64_t)MJ * MJ;
+                          const double *wt, double *part, double *scratch, double *acc, double *comp,
+                          hipStream_t st) {
+    if (W < 1 || MJ < 1) return hipSuccess;
+    const size_t m2 = (size_t)MJ * MJ;
+    double *Sm = scratch, *pY = Sm + (size_t)W * MJ, *pS = pY + (size_t)XI_SPLIT_Y * 2 * m2;
+    hipLaunchKernelGGL(k_xi_walker_sums, dim3((unsigned)W), dim3(256), 0, st, X, N, MJ, W, Sm);
+    const int nbt = (MJ + 63) / 64;
+    const int64_t KY = (int64_t)W * N, perY = (KY + XI_SPLIT_Y - 1) / XI_SPLIT_Y;
+    const int64_t perS = ((int64_t)W + XI_SPLIT_S - 1) / XI_SPLIT_S;
+    hipLaunchKernelGGL(k_wgram, dim3((unsigned)(nbt * nbt), XI_SPLIT_Y), dim3(256), 0, st, X, KY, MJ, N, wt, EL,
+                       shift, perY, pY);
+    hipLaunchKernelGGL(k_wgram, dim3((unsigned)(nbt * nbt), XI_SPLIT_S), dim3(256), 0, st, Sm, (int64_t)W, MJ, 1,
+                       wt, EL, shift, perS, pS);
+    const int64_t n = 2 * (int64_t)MJ + 2 * (int64_t)m2;
+    hipLaunchKernelGGL(k_xi_s1, dim3((unsigned)MJ), dim3(256), 0, st, Sm, W, MJ, EL, shift, wt, part);
+    hipLaunchKernelGGL(k_xi_finish, dim3((unsigned)((2 * m2 + 255) / 256)), dim3(256), 0, st, MJ, pY, XI_SPLIT_Y,
+                       pS, XI_SPLIT_S, part);
     hipLaunchKernelGGL(k_add_compensated, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, n, acc, comp);
     return hipGetLastError();
 }

@@ -165,9 +165,12 @@ hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int nq
                               const double *pos, const T *X, const T *O, const double *gb, const double *xi1,
                               double *dedr, double *jtao, hipStream_t st);
 // The launch's sums of the Jastrow-parameter log-derivatives (weights wt,
-// null = 1; E_L - shift) added into acc/comp: [s | (E-s) s | O3 | (E-s) O3].
+// null = 1; E_L - shift) added into acc/comp: [s | (E-s) s | O3 | (E-s) O3];
+// scratch of xi_scratch_doubles(W, MJ) doubles.
+size_t xi_scratch_doubles(int W, int MJ);
 hipError_t launch_xi_sums(const double *X, int N, int MJ, int W, const double *EL, const double *shift,
-                          const double *wt, double *part, double *acc, double *comp, hipStream_t st);
+                          const double *wt, double *part, double *scratch, double *acc, double *comp,
+                          hipStream_t st);
 // The sweep's one-/three-body terms (null Xp: none): chi at the proposals and
 // at the positions of the sweep's start ([W N][MJ]), their [xi3 | xi1]
 // products ([nq][W N][64]).
