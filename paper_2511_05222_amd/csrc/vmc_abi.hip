@@ -340,7 +340,7 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     if (c->MJ > 0) {
         // one-/three-body Jastrow: chi, its [xi3 | xi1] products, gradient,
         // Laplacian and value per walker (the dense kernel adds them)
-        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, R, pos, jrows, jX, st));
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, R, pos, jrows, jX, st));
         HIP_OK(c, vmcx::launch_jas_products<T>(S, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), R, pos, jrows, 5, jO,
                                                (T *)c->d_cpad, st));
         HIP_OK(c, vmcx::launch_jas_assemble<T>(c->N, c->MJ, c->nq, jrows, 0, (int)cw, jX, jO, c->jm_g, c->jm_u, st));
@@ -468,8 +468,8 @@ static int sweep_once(vmc_ctx *c, double *walkers, int64_t W, int t, uint32_t si
     vmcx::JasSweep<T> js;
     if (c->MJ > 0) {
         T *Xp = (T *)c->js_Xp, *X0 = (T *)c->js_X0, *Pp = (T *)c->js_Pp, *T0 = (T *)c->js_T0;
-        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->d_R, c->prop, rows, Xp, st));
-        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->d_R, walkers, rows, X0, st));
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, c->d_R, c->prop, rows, Xp, st));
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, c->d_R, walkers, rows, X0, st));
         HIP_OK(c, vmcx::launch_jas_products<T>(c->sys, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), c->d_R, c->prop,
                                                rows, 1, Pp, (T *)c->d_cpad, st));
         HIP_OK(c, vmcx::launch_jas_products<T>(c->sys, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), c->d_R, walkers,
@@ -543,8 +543,8 @@ static int measure_accumulate(vmc_ctx *c, const double *walkers, int64_t W, cons
         if (c->xg_n > 0) {
             // the Jastrow-parameter sums of this launch (basis values again in
             // FP64: the measurement's may have been replaced by a promoted subset)
-            HIP_OK(c, vmcx::launch_jas_values<double>(c->jdev, c->d_R, walkers + c0 * c->N * 3, cw * c->N, c->xg_X,
-                                                      st));
+            HIP_OK(c, vmcx::launch_jas_values<double>(c->jdev, c->jtiles16, c->d_R, walkers + c0 * c->N * 3,
+                                                      cw * c->N, c->xg_X, st));
             HIP_OK(c, vmcx::launch_xi_sums(c->xg_X, c->N, c->MJ, (int)cw, c->st_EL, c->shift, a.wt, c->xg_part,
                                            c->xg_scr, c->xg_acc, c->xg_comp, st));
         }

@@ -35,20 +35,34 @@ namespace vmcx {
 constexpr int JAS_MAX = 256;   // Jastrow basis functions
 constexpr int JAS_ELEC = 128;  // electrons
 
-// out[row][mu] = chi_mu(pos[row]) for the rows' positions; one block per
-// (64 rows, shell): the shell index is uniform over the block.
+// out[row][mu] = chi_mu(pos[row]) for the rows' positions; one block per 64
+// rows.  Per tile of whole shells (<= 16 functions) a wavefront evaluates one
+// shell at 64 rows (uniform angular momentum) into an LDS tile, which the
+// block then writes row by row (consecutive threads, consecutive functions).
 template <typename T>
-__global__ __launch_bounds__(64) void k_jas_values(BasisDev JB, const double *__restrict__ R,
-                                                   const double *__restrict__ pos, int64_t rows,
-                                                   T *__restrict__ out) {
-    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const int s = blockIdx.y;
-    if (row >= rows) return;
-    const double *p = pos + 3 * row;
-    T v[6];
-    const int cnt = shell_eval_to<1, T>(JB, R, s, p[0], p[1], p[2], v);
-    T *o = out + row * JB.n_ao + ldc(JB.shell_mu0 + s);
-    for (int q = 0; q < cnt; ++q) o[q] = v[q];
+__global__ __launch_bounds__(256) void k_jas_values(BasisDev JB, AoTiles tiles, const double *__restrict__ R,
+                                                    const double *__restrict__ pos, int64_t rows,
+                                                    T *__restrict__ out) {
+    constexpr int RB = 64, TS = 17;
+    __shared__ double sp[RB * 3];
+    __shared__ T tv[RB * TS];
+    const int tid = threadIdx.x, MJ = JB.n_ao;
+    const int64_t row0 = (int64_t)blockIdx.x * RB;
+    for (int k = tid; k < RB * 3; k += 256) sp[k] = (row0 + k / 3) < rows ? pos[row0 * 3 + k] : 0.0;
+    for (int tile = 0; tile < tiles.n_tiles; ++tile) {
+        const int s0 = tiles.s0[tile], s1 = tiles.s1[tile], mu0 = tiles.mu0[tile], nmu = tiles.mu1[tile] - mu0;
+        __syncthreads();
+        for (int p = tid; p < RB * (s1 - s0); p += 256) {
+            const int s = __builtin_amdgcn_readfirstlane(s0 + p / RB), r = p % RB;
+            shell_eval_to<1, T>(JB, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
+                                tv + r * TS + (ldc(JB.shell_mu0 + s) - mu0));
+        }
+        __syncthreads();
+        for (int p = tid; p < RB * nmu; p += 256) {
+            const int r = p / nmu, c = p - (p / nmu) * nmu;
+            if (row0 + r < rows) out[(row0 + r) * MJ + mu0 + c] = tv[r * TS + c];
+        }
+    }
 }
 
 // Per walker: grad_e U, lap_e U (jg[w][e][0..3]) and U (ju[w]), FP64 sums.
@@ -238,10 +252,11 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
 }
 
 template <typename T>
-hipError_t launch_jas_values(const BasisDev &JB, const double *R, const double *pos, int64_t rows, T *out,
-                             hipStream_t st) {
-    const dim3 g((unsigned)((rows + 63) / 64), (unsigned)JB.n_shells);
-    hipLaunchKernelGGL(k_jas_values<T>, g, dim3(64), 0, st, JB, R, pos, rows, out);
+hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double *R, const double *pos, int64_t rows,
+                             T *out, hipStream_t st) {
+    if (rows < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_jas_values<T>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, st, JB, jt, R, pos, rows,
+                       out);
     return hipGetLastError();
 }
 
@@ -278,8 +293,8 @@ hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int nq
 }
 
 #define JAS_INST(T)                                                                                               \
-    template hipError_t launch_jas_values<T>(const BasisDev &, const double *, const double *, int64_t, T *,       \
-                                             hipStream_t);                                                         \
+    template hipError_t launch_jas_values<T>(const BasisDev &, const AoTiles &, const double *, const double *,   \
+                                             int64_t, T *, hipStream_t);                                           \
     template hipError_t launch_jas_products<T>(const SysDev &, const BasisDev &, const AoTiles &, int, const T *, \
                                                const double *, const double *, int64_t, int, T *, T *,            \
                                                hipStream_t);                                                       \

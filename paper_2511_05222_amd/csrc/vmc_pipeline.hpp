@@ -151,8 +151,8 @@ hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, con
 // out[q][row][nc][64].  jas_assemble: grad_e U, lap_e U, U.  jas_adjoint: its
 // terms of dE_L/dr_e (added to dedr) and the per-function sums jtao.
 template <typename T>
-hipError_t launch_jas_values(const BasisDev &JB, const double *R, const double *pos, int64_t rows, T *out,
-                             hipStream_t st);
+hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double *R, const double *pos, int64_t rows,
+                             T *out, hipStream_t st);
 template <typename T>
 hipError_t launch_jas_products(const SysDev &S, const BasisDev &JB, const AoTiles &jt, int nq, const T *xiblk,
                                const double *R, const double *pos, int64_t rows, int nc, T *out, T *cpad,
