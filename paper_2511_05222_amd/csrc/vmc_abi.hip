@@ -81,7 +81,8 @@ struct vmc_ctx {
     // staging of the Jastrow terms: sweeps ([W][N] rows) and measurements
     // ([chunk][N] rows); element sizes of the arithmetic type
     void *js_Xp = nullptr, *js_X0 = nullptr, *js_Pp = nullptr, *js_T0 = nullptr;
-    double *jm_X = nullptr, *jm_O = nullptr, *jm_g = nullptr, *jm_u = nullptr, *jm_tao = nullptr;
+    double *jm_X = nullptr, *jm_D = nullptr, *jm_V = nullptr, *jm_Q = nullptr, *jm_g = nullptr, *jm_u = nullptr,
+           *jm_tao = nullptr;
     // semilocal pseudopotential (has_ecp false: none): device tables, the
     // staging of one measurement launch (EcpBufs) and the frame of its
     // quadrature rotations for the next measurement: walker id of the
@@ -336,14 +337,16 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
         prof_end(c, VMC_K_ECP_POINTS, pi, st);
     }
     const int64_t jrows = cw * c->N;
-    T *jX = (T *)c->jm_X, *jO = (T *)c->jm_O;
+    T *jX = (T *)c->jm_X, *jD = (T *)c->jm_D, *jV = (T *)c->jm_V, *jQ = (T *)c->jm_Q;
     if (c->MJ > 0) {
-        // one-/three-body Jastrow: chi, its [xi3 | xi1] products, gradient,
-        // Laplacian and value per walker (the dense kernel adds them)
-        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, R, pos, jrows, jX, st));
-        HIP_OK(c, vmcx::launch_jas_products<T>(S, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), R, pos, jrows, 5, jO,
+        // one-/three-body Jastrow: chi with its gradients and Laplacians, the
+        // value products with [xi3 | xi1]; gradient, Laplacian and value per
+        // walker (the dense kernel adds them)
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, R, pos, jrows, jX, st, jD));
+        HIP_OK(c, vmcx::launch_jas_products<T>(S, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), R, pos, jrows, 1, jV,
                                                (T *)c->d_cpad, st));
-        HIP_OK(c, vmcx::launch_jas_assemble<T>(c->N, c->MJ, c->nq, jrows, 0, (int)cw, jX, jO, c->jm_g, c->jm_u, st));
+        HIP_OK(c, vmcx::launch_jas_assemble<T>(c->N, c->MJ, c->nq, jrows, 0, (int)cw, jX, jD, jV, c->d_xi1, c->jm_g,
+                                               c->jm_u, st));
         mb.jg = c->jm_g;
         mb.ju = c->jm_u;
     }
@@ -354,7 +357,8 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
         ej.MJ = c->MJ;
         ej.rows = jrows;
         ej.X = jX;
-        ej.O = jO;
+        ej.D = jD;
+        ej.V = jV;
         ej.xi1 = c->d_xi1;
         ej.xiblk = c->d_xiblk;
         ej.jg = c->jm_g;
@@ -377,8 +381,9 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     if (c->MJ > 0) {
         // (writes the per-function sums jtao that the pseudopotential's
         // one-/three-body terms then add to)
-        HIP_OK(c, vmcx::launch_jas_adjoint<T>(c->jdev, R, c->N, c->nq, jrows, 0, (int)cw, pos, jX, jO, c->mb_gb,
-                                              c->d_xi1, c->mb_dpart, c->jm_tao, st));
+        HIP_OK(c, vmcx::launch_jas_hxi<T>(c->MJ, c->nq, jrows, jD, c->mb_gb, xi_blocks<T>(c), jQ, st));
+        HIP_OK(c, vmcx::launch_jas_adjoint<T>(c->jdev, R, c->N, jrows, 0, (int)cw, pos, jV, jQ, c->mb_gb, c->d_xi1,
+                                              c->mb_dpart, c->jm_tao, st));
         md.jtao = c->jm_tao;
         md.jb = c->jdev;
     }
@@ -991,10 +996,10 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
     // ---- staging and accumulators -------------------------------------------
     const int64_t Mn = (int64_t)M * c->n_occ, A3 = 3 * A;
     const int64_t Nn = (int64_t)c->N * c->n_occ;
-    // (with the one-/three-body Jastrow: its basis values, the five
-    // [xi3 | xi1] products per electron, gradient + Laplacian, per-function
-    // sums)
-    const int64_t jas_pw = c->MJ > 0 ? (int64_t)c->N * c->MJ + (int64_t)c->nq * c->N * 5 * 64 + 4 * (int64_t)c->N +
+    // (with the one-/three-body Jastrow: its basis values with their
+    // gradients and Laplacians, the value products with [xi3 | xi1], xi3 h,
+    // gradient + Laplacian, per-function sums)
+    const int64_t jas_pw = c->MJ > 0 ? 6 * (int64_t)c->N * c->MJ + (int64_t)c->nq * c->N * 64 + 4 * (int64_t)c->N +
                                            1 + 6 * (int64_t)c->MJ
                                      : 0;
     // (with a pseudopotential: its pairs, points, the MO rows and values kept
@@ -1036,7 +1041,9 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         if ((rc = c->dalloc((double **)&c->js_Xp, nx)) || (rc = c->dalloc((double **)&c->js_X0, nx)) ||
             (rc = c->dalloc((double **)&c->js_Pp, np)) || (rc = c->dalloc((double **)&c->js_T0, np)) ||
             (rc = c->dalloc(&c->jm_X, (size_t)chunk * c->N * c->MJ)) ||
-            (rc = c->dalloc(&c->jm_O, (size_t)c->nq * chunk * c->N * 5 * 64)) ||
+            (rc = c->dalloc(&c->jm_D, (size_t)chunk * c->N * 4 * c->MJ)) ||
+            (rc = c->dalloc(&c->jm_V, (size_t)c->nq * chunk * c->N * 64)) ||
+            (rc = c->dalloc(&c->jm_Q, (size_t)chunk * c->N * c->MJ)) ||
             (rc = c->dalloc(&c->jm_g, (size_t)chunk * c->N * 4)) || (rc = c->dalloc(&c->jm_u, (size_t)chunk)) ||
             (rc = c->dalloc(&c->jm_tao, (size_t)chunk * c->MJ * 6)))
             return bail(rc);

@@ -109,7 +109,7 @@ __device__ inline void jas_fn(const BasisDev &JB, const double *R, int mu, doubl
 // (xi3 chi(r_e))_mu for mu < MJ.
 template <typename T>
 __device__ inline double ecp_jas_oval(const EcpJas<T> &J, int64_t row, int mu) {
-    return (double)J.O[(((size_t)(mu >> 6) * J.rows + row) * 5) * 64 + (mu & 63)];
+    return (double)J.V[((size_t)(mu >> 6) * J.rows + row) * 64 + (mu & 63)];
 }
 
 // The two-body pair term u(r) and u'(r) / r from r^2 > 0, the reciprocal and
@@ -818,32 +818,28 @@ __global__ __launch_bounds__(256) void k_ecp_jas(int N, EcpJas<T> J, const doubl
     for (int mu = tid; mu < MJ; mu += 256) sDs[mu] = (sDt[0][mu] + sDt[1][mu]) + (sDt[2][mu] + sDt[3][mu]);
     __syncthreads();
     // per function: the partials, and (xi3 D)_mu sum_j grad chi_mu(r_j)
+    // (x3 = (xi3 D)_mu kept in sDt[0] for the electrons' terms)
+    const T *Dw = J.D + (size_t)w * N * 4 * MJ;
     for (int mu = tid; mu < MJ; mu += 256) {
         const double *xb = J.xiblk + (size_t)(mu >> 6) * MJ * 64 + (mu & 63);
         double x3 = 0.0;
         for (int nu = 0; nu < MJ; ++nu) x3 += xb[(size_t)nu * 64] * sDs[nu];
         double gs[3] = {0.0, 0.0, 0.0};
-        for (int j = 0; j < N; ++j) {
-            double c5[5];
-            jas_fn<5>(J.jb, R, mu, p[3 * j], p[3 * j + 1], p[3 * j + 2], c5);
-            gs[0] += c5[1];
-            gs[1] += c5[2];
-            gs[2] += c5[3];
-        }
+        for (int j = 0; j < N; ++j)
+            for (int d = 0; d < 3; ++d) gs[d] += (double)Dw[((size_t)j * 4 + d) * MJ + mu];
         double *jt = J.jtao + ((size_t)w * MJ + mu) * 6;
         for (int d = 0; d < 3; ++d)
             jt[d] += ((sPp[0][d][mu] + sPp[1][d][mu]) + (sPp[2][d][mu] + sPp[3][d][mu])) + x3 * gs[d];
+        sDt[0][mu] = x3;
     }
-    // per electron: grad chi(r_j)^T xi3 D = sum_mu O_grad[j][mu] D_mu, and -grad chi(r_j)^T xi3 D_j
+    __syncthreads();
+    // per electron: grad chi(r_j)^T xi3 D, and -grad chi(r_j)^T xi3 D_j
     if (tid < N) {
         const int j = tid;
         double s3[3] = {sel[3 * j], sel[3 * j + 1], sel[3 * j + 2]};
         for (int mu = 0; mu < MJ; ++mu) {
-            const T *o = J.O + (((size_t)(mu >> 6) * J.rows + (size_t)w * N + j) * 5) * 64 + (mu & 63);
-            const double D = sDs[mu];
-            s3[0] += (double)o[64] * D;
-            s3[1] += (double)o[128] * D;
-            s3[2] += (double)o[192] * D;
+            const double x3 = sDt[0][mu];
+            for (int d = 0; d < 3; ++d) s3[d] += (double)Dw[((size_t)j * 4 + d) * MJ + mu] * x3;
         }
         double *de = dedr + ((size_t)w * N + j) * 3;
         de[0] += s3[0];

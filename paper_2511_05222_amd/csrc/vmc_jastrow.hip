@@ -4,23 +4,22 @@
 //   U1 = sum_i xi1 . chi(r_i)                            (eq. onebody_J_inhom)
 //   U3 = sum_{i<j} chi(r_i)^T xi3 chi(r_j)               (eq. threebody_jas)
 //
-// With s = sum_i chi(r_i) and the [xi3 | xi1] products of the derivative
-// components D_c of chi at each electron, O_c[e] = D_c chi(r_e)^T [xi3 | xi1]
+// With s = sum_i chi(r_i), the value products V[e] = chi(r_e)^T [xi3 | xi1]
 // (MJ + 1 columns, formed on the matrix cores by k_mo_rows_mfma with the
-// Jastrow basis in column blocks of 64; xi3 is symmetric):
-//   grad_e U = O_grad[e] . (s - chi_e)  + O_grad[e][MJ],
-//   lap_e U  = O_lap[e]  . (s - chi_e)  + O_lap[e][MJ],
-//   U        = sum_e [ O_val[e] . (s - chi_e) / 2 + O_val[e][MJ] ],
-// where a . b runs over the MJ basis functions.
+// Jastrow basis in column blocks of 64; xi3 is symmetric), t = xi3 s =
+// sum_e V[e] and the coefficient vector of electron e
+//   g_e = xi1 + xi3 (s - chi_e) = xi1 + t - V[e]          (first MJ columns),
+// the terms of E_L are dot products with the basis derivatives at r_e:
+//   grad_e U = grad chi(r_e) . g_e,   lap_e U = lap chi(r_e) . g_e,
+//   U = sum_e [ V[e] . (s - chi_e) / 2 + V[e][MJ] ].
 //
 // Reverse mode (forces): with the total Jastrow gradient G_e and the
 // determinant gradient b_e, E_L depends on grad_e U through
 // abar_e = -(G_e + b_e) and on lap_e U through -1/2.  With
-//   g_e = xi1 + xi3 (s - chi_e)               (the coefficient vector of e),
 //   h_e = grad chi_e abar_e - lap chi_e / 2   (dE_L / dg_e),
-//   q_e = xi3 (sum_j h_j - h_e)               (dE_L / dchi_e through the g_j),
-// where xi3 h_e = sum_d abar_e,d O_d[e] - O_lap[e] / 2 comes from the same
-// products, the explicit dependence on r_e is
+//   Q[e] = xi3 h_e                            (one more product, k_jas_hxi),
+//   q_e = xi3 (sum_j h_j - h_e) = sum_j Q[j] - Q[e]   (dE_L / dchi_e through the g_j),
+// the explicit dependence on r_e is
 //   dE_L/dr_e = sum_mu [ q_e,mu grad chi_mu + g_e,mu (hess chi_mu) abar_e
 //                        - g_e,mu grad(lap chi_mu) / 2 ](r_e),
 //   dlnPsi/dr_e (Jastrow) = sum_mu g_e,mu grad chi_mu(r_e),
@@ -35,15 +34,17 @@ namespace vmcx {
 constexpr int JAS_MAX = 256;   // Jastrow basis functions
 constexpr int JAS_ELEC = 128;  // electrons
 
-// out[row][mu] = chi_mu(pos[row]) for the rows' positions; one block per 64
-// rows.  Per tile of whole shells (<= 16 functions) a wavefront evaluates one
-// shell at 64 rows (uniform angular momentum) into an LDS tile, which the
-// block then writes row by row (consecutive threads, consecutive functions).
-template <typename T>
+// out[row][mu] = chi_mu(pos[row]) for the rows' positions and, with NC = 5,
+// der[row][c][mu] = (d/dx, d/dy, d/dz, Laplacian)_c chi_mu(pos[row]); one
+// block per 64 rows.  Per tile of whole shells (<= 16 functions) a wavefront
+// evaluates one shell at 64 rows (uniform angular momentum) into an LDS
+// tile, which the block then writes row by row (consecutive threads,
+// consecutive functions).
+template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_jas_values(BasisDev JB, AoTiles tiles, const double *__restrict__ R,
                                                     const double *__restrict__ pos, int64_t rows,
-                                                    T *__restrict__ out) {
-    constexpr int RB = 64, TS = 17;
+                                                    T *__restrict__ out, T *__restrict__ der) {
+    constexpr int RB = 64, TS = 16 * NC + 1;
     __shared__ double sp[RB * 3];
     __shared__ T tv[RB * TS];
     const int tid = threadIdx.x, MJ = JB.n_ao;
@@ -54,47 +55,61 @@ __global__ __launch_bounds__(256) void k_jas_values(BasisDev JB, AoTiles tiles, 
         __syncthreads();
         for (int p = tid; p < RB * (s1 - s0); p += 256) {
             const int s = __builtin_amdgcn_readfirstlane(s0 + p / RB), r = p % RB;
-            shell_eval_to<1, T>(JB, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
-                                tv + r * TS + (ldc(JB.shell_mu0 + s) - mu0));
+            shell_eval_to<NC, T>(JB, R, s, sp[3 * r], sp[3 * r + 1], sp[3 * r + 2],
+                                 tv + r * TS + (ldc(JB.shell_mu0 + s) - mu0) * NC);
         }
         __syncthreads();
         for (int p = tid; p < RB * nmu; p += 256) {
             const int r = p / nmu, c = p - (p / nmu) * nmu;
-            if (row0 + r < rows) out[(row0 + r) * MJ + mu0 + c] = tv[r * TS + c];
+            if (row0 + r >= rows) continue;
+            const T *t = tv + r * TS + c * NC;
+            out[(row0 + r) * MJ + mu0 + c] = t[0];
+            if constexpr (NC == 5)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) der[((row0 + r) * 4 + k) * MJ + mu0 + c] = t[1 + k];
         }
     }
 }
 
 // Per walker: grad_e U, lap_e U (jg[w][e][0..3]) and U (ju[w]), FP64 sums.
-// X[row][MJ]: chi values; O: nq blocks of [rows][5][64] (value, gradient,
-// Laplacian products with [xi3 | xi1]).
+// X[row][MJ]: chi values; D[row][4][MJ]: their gradients and Laplacians;
+// V: nq blocks of [rows][64] (value products with [xi3 | xi1]).
 template <typename T>
 __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0,
-                                                      const T *__restrict__ X, const T *__restrict__ O,
+                                                      const T *__restrict__ X, const T *__restrict__ D,
+                                                      const T *__restrict__ V, const double *__restrict__ xi1,
                                                       double *__restrict__ jg, double *__restrict__ ju) {
-    __shared__ double sv[JAS_MAX];
+    __shared__ double sv[JAS_MAX], tv[JAS_MAX];
     __shared__ double ue[JAS_ELEC];
     const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const T *Xw = X + (size_t)w * N * MJ;
+    auto Vat = [&](int e, int mu) -> double {
+        return (double)V[((size_t)(mu >> 6) * rows + row0 + (size_t)w * N + e) * 64 + (mu & 63)];
+    };
     for (int mu = tid; mu < MJ; mu += 256) {
-        double a = 0.0;
-        for (int e = 0; e < N; ++e) a += (double)Xw[(size_t)e * MJ + mu];
+        double a = 0.0, t = 0.0;
+        for (int e = 0; e < N; ++e) {
+            a += (double)Xw[(size_t)e * MJ + mu];
+            t += Vat(e, mu);
+        }
         sv[mu] = a;
+        tv[mu] = t;
     }
     __syncthreads();
     for (int e = wave; e < N; e += 4) {
-        const int64_t row = row0 + (int64_t)w * N + e;
+        const size_t row = row0 + (size_t)w * N + e;
+        const T *de = D + row * 4 * MJ;
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int q = 0; q < nq; ++q) {
-            const int mu = 64 * q + lane;
-            // weights of the products: s - chi_e for the xi3 columns, 1 for
-            // the xi1 column, 0 past it (zero columns of the block)
-            const double d = mu < MJ ? sv[mu] - (double)Xw[(size_t)e * MJ + mu] : (mu == MJ ? 1.0 : 0.0);
-            const double dv = mu < MJ ? 0.5 * d : d;
-            const T *o = O + ((size_t)q * rows + row) * 5 * 64 + lane;
-            acc[0] += (double)o[0] * dv;
+        for (int mu = lane; mu <= MJ; mu += 64) {
+            const double v = Vat(e, mu);
+            if (mu == MJ) {
+                acc[0] += v;   // xi1 . chi_e
+                continue;
+            }
+            const double g = xi1[mu] + tv[mu] - v;
+            acc[0] += 0.5 * v * (sv[mu] - (double)Xw[(size_t)e * MJ + mu]);
 #pragma unroll
-            for (int c = 1; c < 5; ++c) acc[c] += (double)o[c * 64] * d;
+            for (int c = 0; c < 4; ++c) acc[1 + c] += (double)de[(size_t)c * MJ + mu] * g;
         }
 #pragma unroll
         for (int c = 0; c < 5; ++c) acc[c] = wave_sum_dpp(acc[c]);
@@ -112,6 +127,71 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
         double u = 0.0;
         for (int e = 0; e < N; ++e) u += ue[e];
         ju[w] = u;
+    }
+}
+
+// Q[row][mu] = (xi3 h_row)[mu], h_row = grad chi abar_row - lap chi / 2 at the
+// row's electron (abar = -(Jastrow + determinant gradient), from gb), on the
+// matrix cores: 64 rows per block (16 per wavefront), the columns in groups of
+// 64 QB (QB column blocks of [xi3 | xi1]; the accumulators of a group stay in
+// registers), the k dimension in chunks of 16 whose h and xi3 tiles are
+// staged in LDS.
+template <typename T, int QB>
+__global__ __launch_bounds__(256) void k_jas_hxi(int MJ, int nq, int64_t rows, const T *__restrict__ D,
+                                                 const double *__restrict__ gb, const T *__restrict__ xiblk,
+                                                 T *__restrict__ Q) {
+    typedef Mfma<T> MF;
+    constexpr int NTL = 4 * QB, CG = 64 * QB, HS = 17, XS = CG + 4;
+    __shared__ T hs[64 * HS];
+    __shared__ T xs[16 * XS];
+    __shared__ double ab[64 * 3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ml = lane & 15, kg = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    for (int i = tid; i < 64 * 3; i += 256) {
+        const int r = i / 3, d = i - 3 * (i / 3);
+        const int64_t row = row0 + r;
+        ab[i] = row < rows ? -(gb[row * 6 + d] + gb[row * 6 + 3 + d]) : 0.0;
+    }
+    const int nqm = (MJ + 63) / 64;   // column blocks holding xi3 columns
+    for (int q0 = 0; q0 < nqm; q0 += QB) {
+        typename MF::acc_t acc[NTL];
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) acc[t] = MF::zero();
+        for (int k0 = 0; k0 < MJ; k0 += 16) {
+            __syncthreads();
+            for (int i = tid; i < 64 * 16; i += 256) {
+                const int r = i >> 4, kk = i & 15, k = k0 + kk;
+                const int64_t row = row0 + r;
+                double h = 0.0;
+                if (row < rows && k < MJ) {
+                    const T *d = D + row * 4 * MJ + k;
+                    h = ab[3 * r] * (double)d[0] + ab[3 * r + 1] * (double)d[MJ] + ab[3 * r + 2] * (double)d[2 * MJ] -
+                        0.5 * (double)d[3 * MJ];
+                }
+                hs[r * HS + kk] = (T)h;
+            }
+            for (int i = tid; i < 16 * CG; i += 256) {
+                const int kk = i / CG, c = i - (i / CG) * CG, k = k0 + kk, q = q0 + c / 64;
+                xs[kk * XS + c] = (k < MJ && q < nq) ? xiblk[((size_t)q * MJ + k) * 64 + (c & 63)] : T(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const T a = hs[(16 * wave + ml) * HS + 4 * ks + kg];
+#pragma unroll
+                for (int t = 0; t < NTL; ++t) acc[t] = MF::fma(a, xs[(4 * ks + kg) * XS + 16 * t + ml], acc[t]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = row0 + 16 * wave + MF::row(lane, v);
+            if (row >= rows) continue;
+#pragma unroll
+            for (int t = 0; t < NTL; ++t) {
+                const int mu = 64 * q0 + 16 * t + ml;
+                if (mu < MJ) Q[row * MJ + mu] = acc[t][v];
+            }
+        }
     }
 }
 
@@ -168,22 +248,20 @@ __device__ inline JasTerm jas_term(const BasisDev &JB, const double *R, int mu, 
 // mu = lane + 64 k; per electron the sum over functions by a wavefront sum,
 // per function the wavefronts' partial sums added in wavefront order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *__restrict__ R, int N, int MJ, int nq,
+__global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *__restrict__ R, int N, int MJ,
                                                      int64_t rows, int64_t row0, const double *__restrict__ pos,
-                                                     const T *__restrict__ X, const T *__restrict__ O,
+                                                     const T *__restrict__ V, const T *__restrict__ Q,
                                                      const double *__restrict__ gb, const double *__restrict__ xi1,
                                                      double *__restrict__ dedr, double *__restrict__ jtao) {
     __shared__ double tv[JAS_MAX], xh[JAS_MAX];
     __shared__ double ab[JAS_ELEC * 3], pe[JAS_ELEC * 3], fe[JAS_ELEC * 3];
     __shared__ double fp[JAS_MAX * 6];
     const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    (void)X;
-    (void)nq;
-    // element (e, c, mu) of the products
-    auto Oat = [&](int e, int c, int mu) -> double {
-        const int q = mu >> 6;
-        return (double)O[(((size_t)q * rows + row0 + (size_t)w * N + e) * 5 + c) * 64 + (mu & 63)];
+    // the value products and Q = xi3 h of electron e
+    auto Vat = [&](int e, int mu) -> double {
+        return (double)V[((size_t)(mu >> 6) * rows + row0 + (size_t)w * N + e) * 64 + (mu & 63)];
     };
+    auto Qat = [&](int e, int mu) -> double { return (double)Q[(row0 + (size_t)w * N + e) * MJ + mu]; };
     for (int i = tid; i < 3 * N; i += 256) {
         const int e = i / 3, d = i - 3 * (i / 3);
         ab[i] = -(gb[((size_t)w * N + e) * 6 + d] + gb[((size_t)w * N + e) * 6 + 3 + d]);
@@ -194,9 +272,8 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
     for (int mu = tid; mu < MJ; mu += 256) {
         double t = 0.0, h = 0.0;
         for (int e = 0; e < N; ++e) {
-            t += Oat(e, 0, mu);
-            h += ab[3 * e] * Oat(e, 1, mu) + ab[3 * e + 1] * Oat(e, 2, mu) + ab[3 * e + 2] * Oat(e, 3, mu) -
-                 0.5 * Oat(e, 4, mu);
+            t += Vat(e, mu);
+            h += Qat(e, mu);
         }
         tv[mu] = t;
         xh[mu] = h;
@@ -214,9 +291,8 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
         for (int k = 0; k < 4; ++k) {
             const int mu = lane + 64 * k;
             if (mu >= MJ) continue;
-            const double g = xi1[mu] + tv[mu] - Oat(e, 0, mu);
-            const double hq = a[0] * Oat(e, 1, mu) + a[1] * Oat(e, 2, mu) + a[2] * Oat(e, 3, mu) - 0.5 * Oat(e, 4, mu);
-            const JasTerm o = jas_term<T>(JB, R, mu, pe + 3 * e, a, g, xh[mu] - hq);
+            const double g = xi1[mu] + tv[mu] - Vat(e, mu);
+            const JasTerm o = jas_term<T>(JB, R, mu, pe + 3 * e, a, g, xh[mu] - Qat(e, mu));
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 F[k][d] += o.f[d];
@@ -253,10 +329,13 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
 
 template <typename T>
 hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double *R, const double *pos, int64_t rows,
-                             T *out, hipStream_t st) {
+                             T *out, hipStream_t st, T *der) {
     if (rows < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_jas_values<T>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, st, JB, jt, R, pos, rows,
-                       out);
+    const dim3 g((unsigned)((rows + 63) / 64));
+    if (der)
+        hipLaunchKernelGGL((k_jas_values<T, 5>), g, dim3(256), 0, st, JB, jt, R, pos, rows, out, der);
+    else
+        hipLaunchKernelGGL((k_jas_values<T, 1>), g, dim3(256), 0, st, JB, jt, R, pos, rows, out, der);
     return hipGetLastError();
 }
 
@@ -277,30 +356,44 @@ hipError_t launch_jas_products(const SysDev &S, const BasisDev &JB, const AoTile
 }
 
 template <typename T>
-hipError_t launch_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0, int W, const T *X, const T *O,
-                               double *jg, double *ju, hipStream_t st) {
-    hipLaunchKernelGGL(k_jas_assemble<T>, dim3((unsigned)W), dim3(256), 0, st, N, MJ, nq, rows, row0, X, O, jg, ju);
+hipError_t launch_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0, int W, const T *X, const T *D,
+                               const T *V, const double *xi1, double *jg, double *ju, hipStream_t st) {
+    hipLaunchKernelGGL(k_jas_assemble<T>, dim3((unsigned)W), dim3(256), 0, st, N, MJ, nq, rows, row0, X, D, V, xi1,
+                       jg, ju);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int nq, int64_t rows, int64_t row0, int W,
-                              const double *pos, const T *X, const T *O, const double *gb, const double *xi1,
+hipError_t launch_jas_hxi(int MJ, int nq, int64_t rows, const T *D, const double *gb, const T *xiblk, T *Q,
+                          hipStream_t st) {
+    if (rows < 1) return hipSuccess;
+    // (a column group's accumulators: 64 VGPRs in either type)
+    constexpr int QB = sizeof(T) == sizeof(float) ? 4 : 2;
+    hipLaunchKernelGGL((k_jas_hxi<T, QB>), dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, st, MJ, nq, rows, D, gb,
+                       xiblk, Q);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int64_t rows, int64_t row0, int W,
+                              const double *pos, const T *V, const T *Q, const double *gb, const double *xi1,
                               double *dedr, double *jtao, hipStream_t st) {
-    hipLaunchKernelGGL(k_jas_adjoint<T>, dim3((unsigned)W), dim3(256), 0, st, JB, R, N, JB.n_ao, nq, rows, row0, pos,
-                       X, O, gb, xi1, dedr, jtao);
+    hipLaunchKernelGGL(k_jas_adjoint<T>, dim3((unsigned)W), dim3(256), 0, st, JB, R, N, JB.n_ao, rows, row0, pos, V,
+                       Q, gb, xi1, dedr, jtao);
     return hipGetLastError();
 }
 
 #define JAS_INST(T)                                                                                               \
     template hipError_t launch_jas_values<T>(const BasisDev &, const AoTiles &, const double *, const double *,   \
-                                             int64_t, T *, hipStream_t);                                           \
+                                             int64_t, T *, hipStream_t, T *);                                      \
     template hipError_t launch_jas_products<T>(const SysDev &, const BasisDev &, const AoTiles &, int, const T *, \
                                                const double *, const double *, int64_t, int, T *, T *,            \
                                                hipStream_t);                                                       \
     template hipError_t launch_jas_assemble<T>(int, int, int, int64_t, int64_t, int, const T *, const T *,        \
-                                               double *, double *, hipStream_t);                                   \
-    template hipError_t launch_jas_adjoint<T>(const BasisDev &, const double *, int, int, int64_t, int64_t, int,  \
+                                               const T *, const double *, double *, double *, hipStream_t);        \
+    template hipError_t launch_jas_hxi<T>(int, int, int64_t, const T *, const double *, const T *, T *,           \
+                                          hipStream_t);                                                            \
+    template hipError_t launch_jas_adjoint<T>(const BasisDev &, const double *, int, int64_t, int64_t, int,       \
                                               const double *, const T *, const T *, const double *,               \
                                               const double *, double *, double *, hipStream_t);
 JAS_INST(float)

@@ -107,16 +107,17 @@ struct EcpBufs {
     double *tc;
 };
 // The one-/three-body Jastrow in the pseudopotential's ratios (X null:
-// none): chi at the electrons X[W N][MJ] and the [xi3 | xi1] products O (the
-// measurement's, nq blocks of [W N][5][64]), xi1 and the FP64 column blocks
-// of [xi3 | xi1]; jg[W][N][4] the electrons' gradients of U1 + U3; jtao the
+// none): chi at the electrons X[W N][MJ], their gradients and Laplacians
+// D[W N][4][MJ] and the value products V with [xi3 | xi1] (the
+// measurement's, nq blocks of [W N][64]), xi1 and the FP64 column blocks of
+// [xi3 | xi1]; jg[W][N][4] the electrons' gradients of U1 + U3; jtao the
 // per-function sums the measurement subtracts per nucleus.
 template <typename T>
 struct EcpJas {
     BasisDev jb{};
     int MJ = 0;
     int64_t rows = 0;
-    const T *X = nullptr, *O = nullptr;
+    const T *X = nullptr, *D = nullptr, *V = nullptr;
     const double *xi1 = nullptr, *xiblk = nullptr, *jg = nullptr;
     double *jtao = nullptr;
 };
@@ -146,23 +147,30 @@ hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, con
                                const AoTiles &tiles16, T *out, int nc, T *cpad, hipStream_t st,
                                const int *rows_dev = nullptr);
 // One-/three-body Jastrow terms (vmc_jastrow.hip).  jas_values: out[row][mu]
-// = chi_mu(pos[row]).  jas_products: for each of the nq column blocks q of
-// [xi3 | xi1] ([nq][MJ][64] in xiblk) the nc derivative components' products,
-// out[q][row][nc][64].  jas_assemble: grad_e U, lap_e U, U.  jas_adjoint: its
-// terms of dE_L/dr_e (added to dedr) and the per-function sums jtao.
+// = chi_mu(pos[row]) and, with der, der[row][c][mu] its gradient (c < 3) and
+// Laplacian (c = 3).  jas_products: for each of the nq column blocks q of
+// [xi3 | xi1] ([nq][MJ][64] in xiblk) the nc derivative components'
+// products, out[q][row][nc][64] (the measurement uses nc = 1, the values).
+// jas_assemble: grad_e U, lap_e U, U from the values, their derivatives and
+// the value products.  jas_hxi: Q[row] = xi3 h_row (h = grad chi abar -
+// lap chi / 2, abar from gb).  jas_adjoint: its terms of dE_L/dr_e (added to
+// dedr) and the per-function sums jtao.
 template <typename T>
 hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double *R, const double *pos, int64_t rows,
-                             T *out, hipStream_t st);
+                             T *out, hipStream_t st, T *der = nullptr);
 template <typename T>
 hipError_t launch_jas_products(const SysDev &S, const BasisDev &JB, const AoTiles &jt, int nq, const T *xiblk,
                                const double *R, const double *pos, int64_t rows, int nc, T *out, T *cpad,
                                hipStream_t st);
 template <typename T>
-hipError_t launch_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0, int W, const T *X, const T *O,
-                               double *jg, double *ju, hipStream_t st);
+hipError_t launch_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0, int W, const T *X, const T *D,
+                               const T *V, const double *xi1, double *jg, double *ju, hipStream_t st);
 template <typename T>
-hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int nq, int64_t rows, int64_t row0, int W,
-                              const double *pos, const T *X, const T *O, const double *gb, const double *xi1,
+hipError_t launch_jas_hxi(int MJ, int nq, int64_t rows, const T *D, const double *gb, const T *xiblk, T *Q,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int64_t rows, int64_t row0, int W,
+                              const double *pos, const T *V, const T *Q, const double *gb, const double *xi1,
                               double *dedr, double *jtao, hipStream_t st);
 // The launch's sums of the Jastrow-parameter log-derivatives (weights wt,
 // null = 1; E_L - shift) added into acc/comp: [s | (E-s) s | O3 | (E-s) O3];
