@@ -80,7 +80,7 @@ struct vmc_ctx {
     float *d_xiblk_f = nullptr;
     // staging of the Jastrow terms: sweeps ([W][N] rows) and measurements
     // ([chunk][N] rows); element sizes of the arithmetic type
-    void *js_Xp = nullptr, *js_X0 = nullptr, *js_Pp = nullptr, *js_T0 = nullptr;
+    void *js_Xp = nullptr, *js_X0 = nullptr, *js_Pd = nullptr;
     double *jm_X = nullptr, *jm_D = nullptr, *jm_V = nullptr, *jm_Q = nullptr, *jm_g = nullptr, *jm_u = nullptr,
            *jm_tao = nullptr;
     // semilocal pseudopotential (has_ecp false: none): device tables, the
@@ -343,8 +343,7 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
         // value products with [xi3 | xi1]; gradient, Laplacian and value per
         // walker (the dense kernel adds them)
         HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, R, pos, jrows, jX, st, jD));
-        HIP_OK(c, vmcx::launch_jas_products<T>(S, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), R, pos, jrows, 1, jV,
-                                               (T *)c->d_cpad, st));
+        HIP_OK(c, vmcx::launch_jas_vprod<T>(c->MJ, c->nq, jrows, jX, (const T *)nullptr, xi_blocks<T>(c), jV, st));
         HIP_OK(c, vmcx::launch_jas_assemble<T>(c->N, c->MJ, c->nq, jrows, 0, (int)cw, jX, jD, jV, c->d_xi1, c->jm_g,
                                                c->jm_u, st));
         mb.jg = c->jm_g;
@@ -472,17 +471,13 @@ static int sweep_once(vmc_ctx *c, double *walkers, int64_t W, int t, uint32_t si
                                           (T *)c->d_cpad, st));
     vmcx::JasSweep<T> js;
     if (c->MJ > 0) {
-        T *Xp = (T *)c->js_Xp, *X0 = (T *)c->js_X0, *Pp = (T *)c->js_Pp, *T0 = (T *)c->js_T0;
+        T *Xp = (T *)c->js_Xp, *X0 = (T *)c->js_X0, *Pd = (T *)c->js_Pd;
         HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, c->d_R, c->prop, rows, Xp, st));
         HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, c->d_R, walkers, rows, X0, st));
-        HIP_OK(c, vmcx::launch_jas_products<T>(c->sys, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), c->d_R, c->prop,
-                                               rows, 1, Pp, (T *)c->d_cpad, st));
-        HIP_OK(c, vmcx::launch_jas_products<T>(c->sys, c->jdev, c->jtiles16, c->nq, xi_blocks<T>(c), c->d_R, walkers,
-                                               rows, 1, T0, (T *)c->d_cpad, st));
+        HIP_OK(c, vmcx::launch_jas_vprod<T>(c->MJ, c->nq, rows, Xp, X0, xi_blocks<T>(c), Pd, st));
         js.Xp = Xp;
         js.X0 = X0;
-        js.Pp = Pp;
-        js.T0 = T0;
+        js.Pd = Pd;
         js.MJ = c->MJ;
         js.nq = c->nq;
         js.rows = rows;
@@ -1033,13 +1028,14 @@ int vmc_init(const vmc_basis *basis, const vmc_nuclei *nuclei, const vmc_mo *mo,
         (rc = c->dalloc(&c->Kstale, (size_t)opt->max_walkers * 2)))
         return bail(rc);
     if (c->MJ > 0) {
-        // sweeps: values and [xi3 | xi1] products at the proposals and the
-        // current positions, in the arithmetic type; measurements: FP64
-        // sizes (the mixed path's FP64 re-measurement reuses them)
+        // sweeps: values at the proposals and the current positions and the
+        // [xi3 | xi1] products of their difference, in the arithmetic type;
+        // measurements: FP64 sizes (the mixed path's FP64 re-measurement
+        // reuses them)
         const size_t rows = (size_t)opt->max_walkers * c->N, tsz = ts_of(opt->precision);
         const size_t nx = (rows * c->MJ * tsz + 7) / 8, np = (rows * c->nq * 64 * tsz + 7) / 8;
         if ((rc = c->dalloc((double **)&c->js_Xp, nx)) || (rc = c->dalloc((double **)&c->js_X0, nx)) ||
-            (rc = c->dalloc((double **)&c->js_Pp, np)) || (rc = c->dalloc((double **)&c->js_T0, np)) ||
+            (rc = c->dalloc((double **)&c->js_Pd, np)) ||
             (rc = c->dalloc(&c->jm_X, (size_t)chunk * c->N * c->MJ)) ||
             (rc = c->dalloc(&c->jm_D, (size_t)chunk * c->N * 4 * c->MJ)) ||
             (rc = c->dalloc(&c->jm_V, (size_t)c->nq * chunk * c->N * 64)) ||

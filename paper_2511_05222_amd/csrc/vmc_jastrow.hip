@@ -5,19 +5,21 @@
 //   U3 = sum_{i<j} chi(r_i)^T xi3 chi(r_j)               (eq. threebody_jas)
 //
 // With s = sum_i chi(r_i), the value products V[e] = chi(r_e)^T [xi3 | xi1]
-// (MJ + 1 columns, formed on the matrix cores by k_mo_rows_mfma with the
-// Jastrow basis in column blocks of 64; xi3 is symmetric), t = xi3 s =
-// sum_e V[e] and the coefficient vector of electron e
+// (MJ + 1 columns, formed on the matrix cores by k_jas_gemm; xi3 is
+// symmetric), t = xi3 s = sum_e V[e] and the coefficient vector of electron e
 //   g_e = xi1 + xi3 (s - chi_e) = xi1 + t - V[e]          (first MJ columns),
 // the terms of E_L are dot products with the basis derivatives at r_e:
 //   grad_e U = grad chi(r_e) . g_e,   lap_e U = lap chi(r_e) . g_e,
 //   U = sum_e [ V[e] . (s - chi_e) / 2 + V[e][MJ] ].
+// A move of electron e to r' changes U by (xi3 d) . (s - chi_e) + xi1 . d,
+// d = chi(r') - chi_e; a sweep's proposals start from the positions of its
+// start, so their d rows form one product (k_sweep_r adds the terms).
 //
 // Reverse mode (forces): with the total Jastrow gradient G_e and the
 // determinant gradient b_e, E_L depends on grad_e U through
 // abar_e = -(G_e + b_e) and on lap_e U through -1/2.  With
 //   h_e = grad chi_e abar_e - lap chi_e / 2   (dE_L / dg_e),
-//   Q[e] = xi3 h_e                            (one more product, k_jas_hxi),
+//   Q[e] = xi3 h_e                            (one more product, k_jas_gemm),
 //   q_e = xi3 (sum_j h_j - h_e) = sum_j Q[j] - Q[e]   (dE_L / dchi_e through the g_j),
 // the explicit dependence on r_e is
 //   dE_L/dr_e = sum_mu [ q_e,mu grad chi_mu + g_e,mu (hess chi_mu) abar_e
@@ -26,7 +28,10 @@
 // and a function centred on nucleus alpha moves with it, so its terms enter
 // dE_L/dR_alpha and dlnPsi/dR_alpha with the opposite sign (per-function
 // sums over electrons, added per nucleus by k_finalize).
+#include <type_traits>
+
 #include "vmc_mfma.hpp"
+
 #include "vmc_pipeline.hpp"
 
 namespace vmcx {
@@ -130,67 +135,171 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
     }
 }
 
-// Q[row][mu] = (xi3 h_row)[mu], h_row = grad chi abar_row - lap chi / 2 at the
-// row's electron (abar = -(Jastrow + determinant gradient), from gb), on the
-// matrix cores: 64 rows per block (16 per wavefront), the columns in groups of
-// 64 QB (QB column blocks of [xi3 | xi1]; the accumulators of a group stay in
-// registers), the k dimension in chunks of 16 whose h and xi3 tiles are
-// staged in LDS.
-template <typename T, int QB>
-__global__ __launch_bounds__(256) void k_jas_hxi(int MJ, int nq, int64_t rows, const T *__restrict__ D,
-                                                 const double *__restrict__ gb, const T *__restrict__ xiblk,
-                                                 T *__restrict__ Q) {
+// out = A [xi3 | xi1] over the Jastrow basis (k < MJ), for three kinds of
+// rows of A:
+//   AM = 0: A = X                   (chi at the rows' positions),
+//   AM = 1: A = X - X0              (a proposal's change chi(r') - chi(r)),
+//   AM = 2: A = h = grad chi abar - lap chi / 2 at the row's electron, from
+//           D = [rows][4][MJ] (gradient, Laplacian) and abar = -(Jastrow +
+//           determinant gradient) from gb.
+// AM 0 and 1 write the MJ + 1 columns in blocks of 64 ([nq][rows][64]); AM 2
+// writes xi3 h, MJ columns row by row ([rows][MJ]).  The xi3 columns on the
+// matrix cores: 64 rows per block, 16 per wavefront; the columns in groups of
+// NTL tiles of 16 whose accumulators stay in registers; k in chunks of 16
+// with the chunk of xi3 staged in LDS (two buffers, one barrier per chunk;
+// thread i stages column i mod 16 NTL) and each lane's A entries read from
+// memory directly, both loaded one chunk ahead.  In a chunk, lane (m, g) of
+// the 16x16x4 product takes k = 4 g + j at step j: a permutation of k that
+// the A entries and the LDS reads share.  The LDS chunk is laid out
+// [k][m][tile] (rows of NTL + 16 bytes), so that a lane reads its NTL B
+// entries of a step as 16-byte vectors without bank conflicts.  The xi1 column (AM 0, 1) is a dot
+// product per row: lane partial sums over its k, added over the four lanes
+// of the row.
+template <typename T, int NTL, int AM, bool VA>
+__global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int nq, int64_t rows, const T *__restrict__ A0,
+                                                  const T *__restrict__ A1, const double *__restrict__ gb,
+                                                  const T *__restrict__ xiblk, T *__restrict__ out) {
     typedef Mfma<T> MF;
-    constexpr int NTL = 4 * QB, CG = 64 * QB, HS = 17, XS = CG + 4;
-    __shared__ T hs[64 * HS];
-    __shared__ T xs[16 * XS];
-    __shared__ double ab[64 * 3];
+    constexpr int CW = 16 * NTL, KPT = CW / 16, NA = AM == 2 ? 16 : (AM == 1 ? 8 : 4);
+    constexpr int VL = 16 / sizeof(T), PS = NTL + VL, KS = 16 * PS;   // vector length, row and k strides
+    static_assert(256 % CW == 0 && 16 % (256 / CW) == 0 && NTL % VL == 0, "column group");
+    typedef T V16 __attribute__((ext_vector_type(VL)));
+    __shared__ __align__(16) T xs[2][16 * KS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ml = lane & 15, kg = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * 64;
-    for (int i = tid; i < 64 * 3; i += 256) {
-        const int r = i / 3, d = i - 3 * (i / 3);
-        const int64_t row = row0 + r;
-        ab[i] = row < rows ? -(gb[row * 6 + d] + gb[row * 6 + 3 + d]) : 0.0;
-    }
-    const int nqm = (MJ + 63) / 64;   // column blocks holding xi3 columns
-    for (int q0 = 0; q0 < nqm; q0 += QB) {
+    const int64_t row0 = (int64_t)blockIdx.x * 64, arow = row0 + 16 * wave + ml;
+    const bool rok = arow < rows;
+    double ab[3] = {0.0, 0.0, 0.0};
+    if (AM == 2 && rok)
+        for (int d = 0; d < 3; ++d) ab[d] = -(gb[arow * 6 + d] + gb[arow * 6 + 3 + d]);
+    const T *x1 = xiblk + (size_t)(MJ >> 6) * MJ * 64 + (MJ & 63);   // the xi1 column
+    const int nt = (MJ + 15) / 16, nk = (MJ + 15) / 16;
+    // (loads read clamped, in-bounds addresses unconditionally; the entries
+    // outside the matrices are then replaced by zeros)
+    const int64_t arc = min(arow, rows - 1);
+    // the staging thread's column of the group and its first k in a chunk
+    const int scol = tid % CW, sk = (tid / CW) * KPT;
+    for (int t0 = 0; t0 < nt; t0 += NTL) {
+        const int ntg = min(NTL, nt - t0), col = 16 * t0 + scol, colc = min(col, MJ - 1);
+        const bool cok = col < MJ;
+        const T *xcol = xiblk + (size_t)(colc >> 6) * MJ * 64 + (colc & 63);
         typename MF::acc_t acc[NTL];
 #pragma unroll
         for (int t = 0; t < NTL; ++t) acc[t] = MF::zero();
-        for (int k0 = 0; k0 < MJ; k0 += 16) {
-            __syncthreads();
-            for (int i = tid; i < 64 * 16; i += 256) {
-                const int r = i >> 4, kk = i & 15, k = k0 + kk;
-                const int64_t row = row0 + r;
-                double h = 0.0;
-                if (row < rows && k < MJ) {
-                    const T *d = D + row * 4 * MJ + k;
-                    h = ab[3 * r] * (double)d[0] + ab[3 * r + 1] * (double)d[MJ] + ab[3 * r + 2] * (double)d[2 * MJ] -
-                        0.5 * (double)d[3 * MJ];
+        T ra[NA], rb[KPT], p1 = T(0);
+        // a lane's four entries k0 + 4 g + (0..3) of a row of A (of A0 and
+        // A1; of the four components of D): VA (MJ a multiple of 4) as 16-byte
+        // vectors, else one by one
+        // (a chunk inside the basis needs no clamping: FULL)
+        auto load4 = [&](const T *src, T *dst, int k0, bool full) {
+            const int k = k0 + 4 * kg;
+            if constexpr (VA) {
+                typedef T V4 __attribute__((ext_vector_type(4)));
+                const V4 v = *(const V4 *)(src + (full ? k : min(k, MJ - 4)));
+                const bool ok = rok && (full || k < MJ);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dst[j] = ok ? v[j] : T(0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T v = src[full ? k + j : min(k + j, MJ - 1)];
+                    dst[j] = (rok && (full || k + j < MJ)) ? v : T(0);
                 }
-                hs[r * HS + kk] = (T)h;
             }
-            for (int i = tid; i < 16 * CG; i += 256) {
-                const int kk = i / CG, c = i - (i / CG) * CG, k = k0 + kk, q = q0 + c / 64;
-                xs[kk * XS + c] = (k < MJ && q < nq) ? xiblk[((size_t)q * MJ + k) * 64 + (c & 63)] : T(0);
+        };
+        auto load = [&](int k0) {
+            const bool full = k0 + 16 <= MJ;
+            if constexpr (AM == 2) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) load4(A0 + (arc * 4 + c) * MJ, ra + 4 * c, k0, full);
+            } else {
+                load4(A0 + arc * MJ, ra, k0, full);
+                if constexpr (AM == 1) load4(A1 + arc * MJ, ra + 4, k0, full);
             }
+            if (full) {
+                const T *p = xcol + (size_t)(k0 + sk) * 64;
+#pragma unroll
+                for (int m = 0; m < KPT; ++m) {
+                    const T v = p[m * 64];
+                    rb[m] = cok ? v : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < KPT; ++m) {
+                    const int k = k0 + sk + m;
+                    const T v = xcol[(size_t)min(k, MJ - 1) * 64];
+                    rb[m] = (cok && k < MJ) ? v : T(0);
+                }
+            }
+        };
+        auto stage = [&](int buf) {
+#pragma unroll
+            for (int m = 0; m < KPT; ++m) xs[buf][(sk + m) * KS + (scol & 15) * PS + (scol >> 4)] = rb[m];
+        };
+        // the chunks; FULL: all NTL tiles of the group hold columns (the
+        // last group of a basis of fewer functions may not)
+        auto chunks = [&](auto full) {
+            load(0);
+            stage(0);
             __syncthreads();
+            for (int c = 0; c < nk; ++c) {
+                T a[4];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const T a = hs[(16 * wave + ml) * HS + 4 * ks + kg];
+                for (int j = 0; j < 4; ++j) {
+                    if constexpr (AM == 2)
+                        a[j] = (T)(ab[0] * (double)ra[j] + ab[1] * (double)ra[4 + j] + ab[2] * (double)ra[8 + j] -
+                                   0.5 * (double)ra[12 + j]);
+                    else if constexpr (AM == 1)
+                        a[j] = ra[j] - ra[4 + j];
+                    else
+                        a[j] = ra[j];
+                }
+                if (AM != 2 && t0 == 0) {
+                    // (a[j] is zero past the basis)
 #pragma unroll
-                for (int t = 0; t < NTL; ++t) acc[t] = MF::fma(a, xs[(4 * ks + kg) * XS + 16 * t + ml], acc[t]);
+                    for (int j = 0; j < 4; ++j) p1 += a[j] * x1[(size_t)min(16 * c + 4 * kg + j, MJ - 1) * 64];
+                }
+                if (c + 1 < nk) load(16 * (c + 1));
+                const T *xb = xs[c & 1] + 4 * kg * KS + ml * PS;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    T b[NTL];
+#pragma unroll
+                    for (int u = 0; u < NTL; u += VL) {
+                        const V16 v = *(const V16 *)(xb + j * KS + u);
+#pragma unroll
+                        for (int i = 0; i < VL; ++i) b[u + i] = v[i];
+                    }
+#pragma unroll
+                    for (int t = 0; t < NTL; ++t)
+                        if (decltype(full)::value || t < ntg) acc[t] = MF::fma(a[j], b[t], acc[t]);
+                }
+                if (c + 1 < nk) stage((c + 1) & 1);
+                __syncthreads();
             }
-        }
+        };
+        if (ntg == NTL)
+            chunks(std::true_type{});
+        else
+            chunks(std::false_type{});
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = row0 + 16 * wave + MF::row(lane, v);
             if (row >= rows) continue;
 #pragma unroll
             for (int t = 0; t < NTL; ++t) {
-                const int mu = 64 * q0 + 16 * t + ml;
-                if (mu < MJ) Q[row * MJ + mu] = acc[t][v];
+                const int oc = 16 * (t0 + t) + ml;
+                if (t >= ntg || oc >= MJ) continue;
+                if constexpr (AM == 2)
+                    out[row * MJ + oc] = acc[t][v];
+                else
+                    out[((size_t)(oc >> 6) * rows + row) * 64 + (oc & 63)] = acc[t][v];
             }
+        }
+        if (AM != 2 && t0 == 0) {
+            // (the four lanes of row ml: kg = 0..3, 16 apart)
+            p1 += __shfl_xor(p1, 16);
+            p1 += __shfl_xor(p1, 32);
+            if (kg == 0 && rok) out[((size_t)(MJ >> 6) * rows + arow) * 64 + (MJ & 63)] = p1;
         }
     }
 }
@@ -339,20 +448,32 @@ hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double
     return hipGetLastError();
 }
 
+// (a column group's accumulators: 64 registers in either type, the xi3
+// columns of MJ <= 256 in one group in FP32)
 template <typename T>
-hipError_t launch_jas_products(const SysDev &S, const BasisDev &JB, const AoTiles &jt, int nq, const T *xiblk,
-                               const double *R, const double *pos, int64_t rows, int nc, T *out, T *cpad,
-                               hipStream_t st) {
-    SysDev J = S;
-    J.basis = JB;
-    J.M = JB.n_ao;
-    J.n_occ = 64;
-    for (int q = 0; q < nq; ++q) {
-        const hipError_t e = launch_mo_rows_mfma<T>(J, xiblk + (size_t)q * JB.n_ao * 64, R, pos, rows, jt,
-                                                    out + (size_t)q * rows * nc * 64, nc, cpad, st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+constexpr int jas_gemm_ntl() { return sizeof(T) == sizeof(float) ? 16 : 8; }
+
+template <typename T, int AM>
+static void launch_jas_gemm(int MJ, int nq, int64_t rows, const T *A0, const T *A1, const double *gb,
+                            const T *xiblk, T *out, hipStream_t st) {
+    const dim3 g((unsigned)((rows + 63) / 64)), b(256);
+    if (MJ % 4 == 0)
+        hipLaunchKernelGGL((k_jas_gemm<T, jas_gemm_ntl<T>(), AM, true>), g, b, 0, st, MJ, nq, rows, A0, A1, gb, xiblk,
+                           out);
+    else
+        hipLaunchKernelGGL((k_jas_gemm<T, jas_gemm_ntl<T>(), AM, false>), g, b, 0, st, MJ, nq, rows, A0, A1, gb,
+                           xiblk, out);
+}
+
+template <typename T>
+hipError_t launch_jas_vprod(int MJ, int nq, int64_t rows, const T *X, const T *X0, const T *xiblk, T *V,
+                            hipStream_t st) {
+    if (rows < 1) return hipSuccess;
+    if (X0)
+        launch_jas_gemm<T, 1>(MJ, nq, rows, X, X0, nullptr, xiblk, V, st);
+    else
+        launch_jas_gemm<T, 0>(MJ, nq, rows, X, nullptr, nullptr, xiblk, V, st);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -367,10 +488,7 @@ template <typename T>
 hipError_t launch_jas_hxi(int MJ, int nq, int64_t rows, const T *D, const double *gb, const T *xiblk, T *Q,
                           hipStream_t st) {
     if (rows < 1) return hipSuccess;
-    // (a column group's accumulators: 64 VGPRs in either type)
-    constexpr int QB = sizeof(T) == sizeof(float) ? 4 : 2;
-    hipLaunchKernelGGL((k_jas_hxi<T, QB>), dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, st, MJ, nq, rows, D, gb,
-                       xiblk, Q);
+    launch_jas_gemm<T, 2>(MJ, nq, rows, D, nullptr, gb, xiblk, Q, st);
     return hipGetLastError();
 }
 
@@ -386,9 +504,8 @@ hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int64_
 #define JAS_INST(T)                                                                                               \
     template hipError_t launch_jas_values<T>(const BasisDev &, const AoTiles &, const double *, const double *,   \
                                              int64_t, T *, hipStream_t, T *);                                      \
-    template hipError_t launch_jas_products<T>(const SysDev &, const BasisDev &, const AoTiles &, int, const T *, \
-                                               const double *, const double *, int64_t, int, T *, T *,            \
-                                               hipStream_t);                                                       \
+    template hipError_t launch_jas_vprod<T>(int, int, int64_t, const T *, const T *, const T *, T *,             \
+                                            hipStream_t);                                                          \
     template hipError_t launch_jas_assemble<T>(int, int, int, int64_t, int64_t, int, const T *, const T *,        \
                                                const T *, const double *, double *, double *, hipStream_t);        \
     template hipError_t launch_jas_hxi<T>(int, int, int64_t, const T *, const double *, const T *, T *,           \

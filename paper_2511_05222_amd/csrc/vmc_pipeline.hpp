@@ -148,9 +148,9 @@ hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, con
                                const int *rows_dev = nullptr);
 // One-/three-body Jastrow terms (vmc_jastrow.hip).  jas_values: out[row][mu]
 // = chi_mu(pos[row]) and, with der, der[row][c][mu] its gradient (c < 3) and
-// Laplacian (c = 3).  jas_products: for each of the nq column blocks q of
-// [xi3 | xi1] ([nq][MJ][64] in xiblk) the nc derivative components'
-// products, out[q][row][nc][64] (the measurement uses nc = 1, the values).
+// Laplacian (c = 3).  jas_vprod: the products of the rows of X (of X - X0
+// when X0 is given) with [xi3 | xi1] ([nq][MJ][64] in xiblk), MJ + 1 columns
+// in blocks of 64, V[q][row][64].
 // jas_assemble: grad_e U, lap_e U, U from the values, their derivatives and
 // the value products.  jas_hxi: Q[row] = xi3 h_row (h = grad chi abar -
 // lap chi / 2, abar from gb).  jas_adjoint: its terms of dE_L/dr_e (added to
@@ -159,9 +159,8 @@ template <typename T>
 hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double *R, const double *pos, int64_t rows,
                              T *out, hipStream_t st, T *der = nullptr);
 template <typename T>
-hipError_t launch_jas_products(const SysDev &S, const BasisDev &JB, const AoTiles &jt, int nq, const T *xiblk,
-                               const double *R, const double *pos, int64_t rows, int nc, T *out, T *cpad,
-                               hipStream_t st);
+hipError_t launch_jas_vprod(int MJ, int nq, int64_t rows, const T *X, const T *X0, const T *xiblk, T *V,
+                            hipStream_t st);
 template <typename T>
 hipError_t launch_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0, int W, const T *X, const T *D,
                                const T *V, const double *xi1, double *jg, double *ju, hipStream_t st);
@@ -180,11 +179,11 @@ hipError_t launch_xi_sums(const double *X, int N, int MJ, int W, const double *E
                           const double *wt, double *part, double *scratch, double *acc, double *comp,
                           hipStream_t st);
 // The sweep's one-/three-body terms (null Xp: none): chi at the proposals and
-// at the positions of the sweep's start ([W N][MJ]), their [xi3 | xi1]
-// products ([nq][W N][64]).
+// at the positions of the sweep's start ([W N][MJ]) and the [xi3 | xi1]
+// products of their difference ([nq][W N][64]).
 template <typename T>
 struct JasSweep {
-    const T *Xp = nullptr, *X0 = nullptr, *Pp = nullptr, *T0 = nullptr;
+    const T *Xp = nullptr, *X0 = nullptr, *Pd = nullptr;
     int MJ = 0, nq = 0;
     int64_t rows = 0;
 };

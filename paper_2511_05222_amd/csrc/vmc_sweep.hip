@@ -174,17 +174,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
     bool bad = false;
     T Kr[KN];
     int sig = lane;
-    // one-/three-body Jastrow: t = xi3 s over this lane's basis slots, s the
-    // sum of chi over the electrons' current positions (kept current by the
-    // accepted moves; rebuilt from the start positions every sweep)
-    T tq[JQ];
+    // one-/three-body Jastrow: s = the sum of chi over the electrons' current
+    // positions, over this lane's basis slots (kept current by the accepted
+    // moves; rebuilt from the start positions every sweep)
+    T sq[JQ];
     if constexpr (J13) {
 #pragma unroll
         for (int q = 0; q < JQ; ++q) {
             T a = T(0);
             if (q < js.nq && 64 * q + lane < js.MJ)
-                for (int e = 0; e < N; ++e) a += js.T0[((size_t)q * js.rows + (size_t)w * N + e) * 64 + lane];
-            tq[q] = a;
+                for (int e = 0; e < N; ++e) a += js.X0[((size_t)w * N + e) * js.MJ + 64 * q + lane];
+            sq[q] = a;
         }
     }
 
@@ -233,24 +233,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         // Jastrow difference over the pairs (e, k), k held by this lane (in
         // the arithmetic type: it only enters the acceptance ratio)
         double dj = jastrow_delta<T>(S, N, e, lane, rx, ry, rz, ex, ey, ez, px, py, pz);
-        // one-/three-body difference: (chi' - chi) . (t - xi3 chi) over the
-        // basis, plus xi1 . (chi' - chi) from the last column
-        T jp[JQ], jt0[JQ];
+        // one-/three-body difference, with d = chi' - chi_e and xi3 symmetric:
+        // d^T xi3 (s - chi_e) = (xi3 d) . (s - chi_e) over the basis, plus
+        // xi1 . d from the last column of the products
+        T jd[JQ];
         if constexpr (J13) {
             const size_t row = (size_t)w * N + e;
             T loc = T(0);
 #pragma unroll
             for (int q = 0; q < JQ; ++q) {
-                jp[q] = jt0[q] = T(0);
+                jd[q] = T(0);
                 const int mu = 64 * q + lane;
                 if (q < js.nq && mu <= js.MJ) {
-                    jp[q] = js.Pp[((size_t)q * js.rows + row) * 64 + lane];
-                    jt0[q] = js.T0[((size_t)q * js.rows + row) * 64 + lane];
+                    const T pd = js.Pd[((size_t)q * js.rows + row) * 64 + lane];
                     if (mu < js.MJ) {
-                        const T d = js.Xp[row * js.MJ + mu] - js.X0[row * js.MJ + mu];
-                        loc += d * (tq[q] - jt0[q]);
+                        const T x0 = js.X0[row * js.MJ + mu];
+                        jd[q] = js.Xp[row * js.MJ + mu] - x0;
+                        loc += pd * (sq[q] - x0);
                     } else {
-                        loc += jp[q] - jt0[q];
+                        loc += pd;
                     }
                 }
             }
@@ -306,8 +307,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             wave_sync_s();
             if constexpr (J13) {
 #pragma unroll
-                for (int q = 0; q < JQ; ++q)
-                    if (64 * q + lane < js.MJ) tq[q] += jp[q] - jt0[q];
+                for (int q = 0; q < JQ; ++q) sq[q] += jd[q];
             }
             const T rr = sizeof(T) == sizeof(float) ? (T)__builtin_amdgcn_rcpf((float)ratio) : (T)rcp_nr(ratio);
             const T t = (v - (lane == pj ? T(1) : T(0))) * rr;
