@@ -114,6 +114,60 @@ def test_measure_parity_21atom(dev):
         close(out[k].cpu().numpy(), ref[k], what=k)
 
 
+def _drop_shell(mol, s_drop):
+    """mol with Jastrow shell s_drop (one primitive per shell) and its
+    functions' rows of xi1 and xi3 removed."""
+    import dataclasses
+    jb, jas = mol.jastrow.jas_basis, mol.jastrow
+    nf = [inputs.N_CART[int(l)] for l in jb.shell_l]
+    mu0 = int(sum(nf[:s_drop]))
+    keep_s = np.arange(jb.n_shells) != s_drop
+    keep_f = np.ones(jb.n_ao, bool)
+    keep_f[mu0:mu0 + nf[s_drop]] = False
+    nb = inputs.Basis(jb.shell_atom[keep_s], jb.shell_l[keep_s], jb.shell_nprim[keep_s], jb.prim_exp[keep_s],
+                      jb.prim_coef[keep_s])
+    j2 = dataclasses.replace(jas, jas_basis=nb, xi1=jas.xi1[keep_f], xi3=jas.xi3[np.ix_(keep_f, keep_f)])
+    return dataclasses.replace(mol, jastrow=j2)
+
+
+def test_odd_basis_size(dev, mol9j):
+    """A Jastrow basis of 81 functions (one p shell of a hydrogen dropped):
+    not a multiple of 4 (the products' rows read element by element) nor of
+    16 (a partial last chunk and column tile).  FP64 accept bits and
+    measurement against the oracle; mixed against FP64."""
+    from oracle import sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    jb = mol9j.jastrow.jas_basis
+    assert np.all(jb.shell_nprim == 1)
+    h = [i for i, sym in enumerate(mol9j.symbols) if sym == "H"][0]
+    s_drop = int(np.nonzero((jb.shell_atom == h) & (jb.shell_l == 1))[0][0])
+    mol = _drop_shell(mol9j, s_drop)
+    assert mol.jastrow.jas_basis.n_ao == 81
+    W, sweeps, seed = 8, 2, 557
+    w0 = inputs.initial_walkers(mol, W, 4)
+    ch, bits = sampler.run(wf.System(mol), w0, sweeps, seed)
+    ctx = vmc.Context(mol, max_walkers=W)
+    tw = torch.tensor(w0, device=dev)
+    acc = torch.zeros((sweeps, mol.n_elec, W), dtype=torch.uint8, device=dev)
+    print("case: 81-function J1/J3 sweep", flush=True)
+    ctx.sweep(tw, sweeps, seed, measure=False, accept=acc)
+    torch.cuda.synchronize()
+    assert np.array_equal(acc.cpu().numpy().astype(bool), bits)
+    close(tw.cpu().numpy(), ch.r, tol=1e-13, what="positions")
+    ref = per_walker_oracle(mol, ch.r)
+    print("case: 81-function J1/J3 measurement", flush=True)
+    out = ctx.measure(torch.tensor(ch.r, device=dev))
+    torch.cuda.synchronize()
+    for k in ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G"):
+        close(out[k].cpu().numpy(), ref[k], what=k)
+    ctx32 = vmc.Context(mol, max_walkers=W, precision="mixed")
+    print("case: 81-function J1/J3 mixed measurement", flush=True)
+    o32 = ctx32.measure(torch.tensor(ch.r, device=dev), outputs=("EL", "dEL_dR"))
+    torch.cuda.synchronize()
+    dE = o32["EL"].cpu().numpy() - ref["EL"]
+    assert np.median(np.abs(dE)) < 1e-3 and abs(dE.mean()) < 5e-3, dE
+
+
 def test_estimators(dev, mol9j):
     from oracle import vmc as ovmc
     from paper_2511_05222_amd import vmc
