@@ -326,25 +326,25 @@ __device__ inline void jas_function14(const BasisDev &JB, const double *R, int m
     ao_components<14, T>((T)dx, (T)dy, (T)dz, (T)rho_d, R0, R1, R2, R3, JB.ao_pow[mu], (T)JB.ao_eta[mu], c);
 }
 
-// dE_L/dr_e and dlnPsi/dr_e contributions of function mu at electron e.
+// dE_L/dr_e and dlnPsi/dr_e contributions of function mu at electron e, in
+// the arithmetic type (ab = abar_e).
+template <typename T>
 struct JasTerm {
-    double f[3], p[3];
+    T f[3], p[3];
 };
 
 template <typename T>
-__device__ inline JasTerm jas_term(const BasisDev &JB, const double *R, int mu, const double *pe, const double *ab,
-                                   double g, double q) {
+__device__ inline JasTerm<T> jas_term(const BasisDev &JB, const double *R, int mu, const double *pe, const T *ab, T g,
+                                      T q) {
     T c[14];
     jas_function14<T>(JB, R, mu, pe[0], pe[1], pe[2], c);
-    JasTerm o;
-    const double hs[3][3] = {{(double)c[5], (double)c[6], (double)c[7]},
-                             {(double)c[6], (double)c[8], (double)c[9]},
-                             {(double)c[7], (double)c[9], (double)c[10]}};
+    JasTerm<T> o;
+    const T hs[3][3] = {{c[5], c[6], c[7]}, {c[6], c[8], c[9]}, {c[7], c[9], c[10]}};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double ha = hs[k][0] * ab[0] + hs[k][1] * ab[1] + hs[k][2] * ab[2];
-        o.f[k] = q * (double)c[1 + k] + g * ha - 0.5 * g * (double)c[11 + k];
-        o.p[k] = g * (double)c[1 + k];
+        const T ha = hs[k][0] * ab[0] + hs[k][1] * ab[1] + hs[k][2] * ab[2];
+        o.f[k] = q * c[1 + k] + g * (ha - T(0.5) * c[11 + k]);
+        o.p[k] = g * c[1 + k];
     }
     return o;
 }
@@ -355,7 +355,9 @@ __device__ inline JasTerm jas_term(const BasisDev &JB, const double *R, int mu, 
 // determinant gradient (3..5).  Each (electron, function) term is evaluated
 // once: wavefront v takes the electrons e = v mod 4, lanes the functions
 // mu = lane + 64 k; per electron the sum over functions by a wavefront sum,
-// per function the wavefronts' partial sums added in wavefront order.
+// per function the wavefronts' partial sums added in wavefront order.  The
+// terms and the sums inside a wavefront are in the arithmetic type, FP64 from
+// the wavefront sums on.
 template <typename T>
 __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *__restrict__ R, int N, int MJ,
                                                      int64_t rows, int64_t row0, const double *__restrict__ pos,
@@ -388,20 +390,20 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
         xh[mu] = h;
     }
     __syncthreads();
-    double F[4][3], P[4][3];
+    T F[4][3], P[4][3];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) F[k][d] = P[k][d] = 0.0;
+        for (int d = 0; d < 3; ++d) F[k][d] = P[k][d] = T(0);
     for (int e = wave; e < N; e += 4) {
-        const double *a = ab + 3 * e;
-        double f3[3] = {0.0, 0.0, 0.0};
+        const T a[3] = {(T)ab[3 * e], (T)ab[3 * e + 1], (T)ab[3 * e + 2]};
+        T f3[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int mu = lane + 64 * k;
             if (mu >= MJ) continue;
-            const double g = xi1[mu] + tv[mu] - Vat(e, mu);
-            const JasTerm o = jas_term<T>(JB, R, mu, pe + 3 * e, a, g, xh[mu] - Qat(e, mu));
+            const T g = (T)(xi1[mu] + tv[mu] - Vat(e, mu)), q = (T)(xh[mu] - Qat(e, mu));
+            const JasTerm<T> o = jas_term<T>(JB, R, mu, pe + 3 * e, a, g, q);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 F[k][d] += o.f[d];
@@ -409,12 +411,13 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
                 f3[d] += o.f[d];
             }
         }
+        double f3d[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) f3[d] = wave_sum_dpp(f3[d]);
+        for (int d = 0; d < 3; ++d) f3d[d] = wave_sum_dpp((double)f3[d]);
         if (lane == 0) {
-            fe[3 * e] = f3[0];
-            fe[3 * e + 1] = f3[1];
-            fe[3 * e + 2] = f3[2];
+            fe[3 * e] = f3d[0];
+            fe[3 * e + 1] = f3d[1];
+            fe[3 * e + 2] = f3d[2];
         }
     }
     // per function: the wavefronts' partials, in wavefront order
@@ -426,8 +429,8 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
                 if (mu >= MJ) continue;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    fp[6 * mu + d] = (v ? fp[6 * mu + d] : 0.0) + F[k][d];
-                    fp[6 * mu + 3 + d] = (v ? fp[6 * mu + 3 + d] : 0.0) + P[k][d];
+                    fp[6 * mu + d] = (v ? fp[6 * mu + d] : 0.0) + (double)F[k][d];
+                    fp[6 * mu + 3 + d] = (v ? fp[6 * mu + 3 + d] : 0.0) + (double)P[k][d];
                 }
             }
         __syncthreads();
@@ -531,10 +534,12 @@ namespace vmcx {
 // Y = [W N x MJ] the basis values of every electron, S = [W x MJ] their
 // walker sums and D, D' the walker weights (repeated over the electrons for
 // D'), formed on FP64 MFMA: k_wgram computes a 64 x 64 block-tile of both
-// weightings over a range of rows; the row ranges' partials are added in
-// order by k_xi_finish.  X[w][i][mu] = chi_mu(r_i) in FP64.
+// weightings over a range of rows, for the block-tiles on and above the
+// diagonal (the matrices are symmetric); the row ranges' partials are added
+// in order by k_xi_finish, which takes the entries below the diagonal tiles
+// from their mirror images.  X[w][i][mu] = chi_mu(r_i) in FP64.
 // ---------------------------------------------------------------------------
-constexpr int XI_SPLIT_Y = 32, XI_SPLIT_S = 8;   // row ranges of the two products
+constexpr int XI_SPLIT_Y = 96, XI_SPLIT_S = 8;   // row ranges of the two products
 
 size_t xi_scratch_doubles(int W, int MJ) {
     return (size_t)W * MJ + (size_t)(XI_SPLIT_Y + XI_SPLIT_S) * 2 * MJ * MJ;
@@ -554,42 +559,64 @@ __global__ __launch_bounds__(256) void k_xi_walker_sums(const double *__restrict
 // Block (tile, range): rows [k0, k1) of Z [K][MJ], row k belonging to walker
 // k / rpw; alpha_k = wt[w] (1 without weights), beta_k = alpha_k (EL[w] - shift).
 // part[range][0 / 1][mu][nu] = sum_k alpha_k / beta_k z_k[mu] z_k[nu] over the
-// block-tile's 64 x 64 entries.  Wavefront v takes the 16 rows mu of sub-tile
-// v and all four nu sub-tiles.
+// block-tile's 64 x 64 entries; blockIdx.x enumerates the block-tiles (bi, bj)
+// with bi <= bj.  Wavefront v takes the 16 rows mu of sub-tile v and all four
+// nu sub-tiles.  The next 16 rows are loaded into registers while the matrix
+// cores work on the current ones.
 __global__ __launch_bounds__(256) void k_wgram(const double *__restrict__ Z, int64_t K, int MJ, int rpw,
                                                const double *__restrict__ wt, const double *__restrict__ EL,
                                                const double *__restrict__ shift, int64_t per, double *part) {
     typedef Mfma<double> MF;
     __shared__ double zm[16][64], zn[16][64], al[16], be[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ml = lane & 15, kg = lane >> 4;
-    const int nbt = (MJ + 63) / 64, bi = blockIdx.x / nbt, bj = blockIdx.x - (blockIdx.x / nbt) * nbt;
+    const int nbt = (MJ + 63) / 64;
+    int bi = 0, bj = blockIdx.x;
+    while (bj >= nbt - bi) {
+        bj -= nbt - bi;
+        ++bi;
+    }
+    bj += bi;
     const int64_t k0 = (int64_t)blockIdx.y * per, k1 = min(K, k0 + per);
     const double sh = *shift;
     MF::acc_t ga[4], gb[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) ga[j] = gb[j] = MF::zero();
-    for (int64_t kb = k0; kb < k1; kb += 16) {
-        __syncthreads();
-        for (int idx = tid; idx < 16 * 64; idx += 256) {
-            const int r = idx >> 6, c = idx & 63;
-            const int64_t k = kb + r;
-            const bool in = k < k1;
-            const int cm = 64 * bi + c, cn = 64 * bj + c;
-            zm[r][c] = (in && cm < MJ) ? Z[k * MJ + cm] : 0.0;
-            zn[r][c] = (in && cn < MJ) ? Z[k * MJ + cn] : 0.0;
+    // this thread's staging slots: rows r = idx / 64 of the chunk, column c
+    double rm[4], rn[4], ra = 0.0, rb = 0.0;
+    auto load = [&](int64_t kb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = tid + 256 * i, r = idx >> 6, c = idx & 63, cm = 64 * bi + c, cn = 64 * bj + c;
+            const int64_t k = kb + r, kc = min(k, K - 1);
+            const double vm = Z[kc * MJ + min(cm, MJ - 1)], vn = Z[kc * MJ + min(cn, MJ - 1)];
+            rm[i] = (k < k1 && cm < MJ) ? vm : 0.0;
+            rn[i] = (k < k1 && cn < MJ) ? vn : 0.0;
         }
         if (tid < 16) {
             const int64_t k = kb + tid;
-            double a = 0.0, b = 0.0;
+            ra = rb = 0.0;
             if (k < k1) {
                 const int64_t w = k / rpw;
-                a = wt ? wt[w] : 1.0;
-                b = a * (EL[w] - sh);
+                ra = wt ? wt[w] : 1.0;
+                rb = ra * (EL[w] - sh);
             }
-            al[tid] = a;
-            be[tid] = b;
+        }
+    };
+    if (k0 < k1) load(k0);
+    for (int64_t kb = k0; kb < k1; kb += 16) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = tid + 256 * i;
+            zm[idx >> 6][idx & 63] = rm[i];
+            zn[idx >> 6][idx & 63] = rn[i];
+        }
+        if (tid < 16) {
+            al[tid] = ra;
+            be[tid] = rb;
         }
         __syncthreads();
+        if (kb + 16 < k1) load(kb + 16);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int r = 4 * ks + kg;
@@ -652,9 +679,12 @@ __global__ void k_xi_finish(int MJ, const double *__restrict__ pY, int nY, const
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t m2 = (int64_t)MJ * MJ;
     if (t < 2 * m2) {
+        // (mu, nu) in a block-tile below the diagonal: its mirror (nu, mu)
+        const int64_t h = t / m2, mu = (t - h * m2) / MJ, nu = t - h * m2 - mu * MJ;
+        const int64_t src = (mu >> 6) > (nu >> 6) ? h * m2 + nu * MJ + mu : t;
         double y = 0.0, q = 0.0;
-        for (int g = 0; g < nY; ++g) y += pY[(size_t)g * 2 * m2 + t];
-        for (int g = 0; g < nS; ++g) q += pS[(size_t)g * 2 * m2 + t];
+        for (int g = 0; g < nY; ++g) y += pY[(size_t)g * 2 * m2 + src];
+        for (int g = 0; g < nS; ++g) q += pS[(size_t)g * 2 * m2 + src];
         part[2 * MJ + t] = 0.5 * (q - y);
     }
 }
@@ -678,10 +708,10 @@ hipError_t launch_xi_sums(const double *X, int N, int MJ, int W, const double *E
     const int nbt = (MJ + 63) / 64;
     const int64_t KY = (int64_t)W * N, perY = (KY + XI_SPLIT_Y - 1) / XI_SPLIT_Y;
     const int64_t perS = ((int64_t)W + XI_SPLIT_S - 1) / XI_SPLIT_S;
-    hipLaunchKernelGGL(k_wgram, dim3((unsigned)(nbt * nbt), XI_SPLIT_Y), dim3(256), 0, st, X, KY, MJ, N, wt, EL,
-                       shift, perY, pY);
-    hipLaunchKernelGGL(k_wgram, dim3((unsigned)(nbt * nbt), XI_SPLIT_S), dim3(256), 0, st, Sm, (int64_t)W, MJ, 1,
-                       wt, EL, shift, perS, pS);
+    const unsigned ntri = (unsigned)(nbt * (nbt + 1) / 2);
+    hipLaunchKernelGGL(k_wgram, dim3(ntri, XI_SPLIT_Y), dim3(256), 0, st, X, KY, MJ, N, wt, EL, shift, perY, pY);
+    hipLaunchKernelGGL(k_wgram, dim3(ntri, XI_SPLIT_S), dim3(256), 0, st, Sm, (int64_t)W, MJ, 1, wt, EL, shift, perS,
+                       pS);
     const int64_t n = 2 * (int64_t)MJ + 2 * (int64_t)m2;
     hipLaunchKernelGGL(k_xi_s1, dim3((unsigned)MJ), dim3(256), 0, st, Sm, W, MJ, EL, shift, wt, part);
     hipLaunchKernelGGL(k_xi_finish, dim3((unsigned)((2 * m2 + 255) / 256)), dim3(256), 0, st, MJ, pY, XI_SPLIT_Y,
