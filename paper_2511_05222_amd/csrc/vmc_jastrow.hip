@@ -91,21 +91,44 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
     auto Vat = [&](int e, int mu) -> double {
         return (double)V[((size_t)(mu >> 6) * rows + row0 + (size_t)w * N + e) * 64 + (mu & 63)];
     };
-    for (int mu = tid; mu < MJ; mu += 256) {
-        double a = 0.0, t = 0.0;
-        for (int e = 0; e < N; ++e) {
-            a += (double)Xw[(size_t)e * MJ + mu];
-            t += Vat(e, mu);
+    // s and t = xi3 s: wavefront v sums the electrons e = v mod 4 for the
+    // functions mu = lane + 64 k (eight independent chains per lane), then
+    // the wavefronts' partials are added in wavefront order
+    {
+        double pa[4] = {0.0, 0.0, 0.0, 0.0}, pt[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int e = wave; e < N; e += 4) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int mu = lane + 64 * k;
+                if (mu < MJ) {
+                    pa[k] += (double)Xw[(size_t)e * MJ + mu];
+                    pt[k] += Vat(e, mu);
+                }
+            }
         }
-        sv[mu] = a;
-        tv[mu] = t;
+        for (int v = 0; v < 4; ++v) {
+            if (wave == v)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int mu = lane + 64 * k;
+                    if (mu < MJ) {
+                        sv[mu] = (v ? sv[mu] : 0.0) + pa[k];
+                        tv[mu] = (v ? tv[mu] : 0.0) + pt[k];
+                    }
+                }
+            __syncthreads();
+        }
     }
-    __syncthreads();
     for (int e = wave; e < N; e += 4) {
         const size_t row = row0 + (size_t)w * N + e;
         const T *de = D + row * 4 * MJ;
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int mu = lane; mu <= MJ; mu += 64) {
+        // (the slots k = 0..4 cover mu <= MJ <= 256: their loads are issued
+        // together)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int mu = lane + 64 * k;
+            if (mu > MJ) continue;
             const double v = Vat(e, mu);
             if (mu == MJ) {
                 acc[0] += v;   // xi1 . chi_e
