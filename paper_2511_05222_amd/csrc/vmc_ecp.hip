@@ -548,6 +548,27 @@ __global__ __launch_bounds__(256) void k_ecp_energy_pts(SysDev S, EcpDev E, cons
 
 // ---------------------------------------------------------------------------
 // The derivatives through the points, two kernels with one block per walker.
+// The value and gradient of the lane's AO at displacement (x, y, z) from the
+// radial sums R0 and u1 = 2 R' of ao_lane_radial (the first four of the 14
+// components of ao_lane_components).
+template <typename T, int NPR>
+__device__ inline void ao_lane_value_grad(const AoLane<T, NPR> &L, T x, T y, T z, T R0, T u1, T *d) {
+    const T r[3] = {x, y, z};
+    T f[3], f1[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const T h = fma(L.c2[q], r[q], L.c1[q]);
+        f[q] = fma(h, r[q], L.c0[q]);
+        f1[q] = fma(L.c2[q], r[q], h);
+    }
+    const T fyz = f[1] * f[2];
+    const T P = f[0] * fyz, PR1 = P * u1;
+    d[0] = P * R0;
+    d[1] = fma(f1[0] * fyz, R0, x * PR1);
+    d[2] = fma(f1[1] * f[0] * f[2], R0, y * PR1);
+    d[3] = fma(f1[2] * f[0] * f[1], R0, z * PR1);
+}
+
 // k_ecp_points_ao (threads over (AO mu, slot), the slots splitting the
 //   points when the AOs are fewer than the threads): G[mu] += sum_q
 //   psi_mu(r_q) y_q and tc[mu] = sum_q kappa_q,mu grad psi_mu(r_q),
@@ -589,13 +610,16 @@ __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__rest
     double *stc = eb.tc + (size_t)w * M * 3;
     const int nsl = M < 256 ? 256 / M : 1;
     const int per = 256 / nsl;
+    constexpr int NPR = sizeof(T) == 4 ? 3 : 0;   // primitives held in registers (FP32)
     for (int mu0 = 0; mu0 < M; mu0 += per) {
         const int mu = mu0 + tid / nsl, slot = tid - (tid / nsl) * nsl;
         const bool vm = tid < per * nsl && mu < M;
         const int mm = vm ? mu : M - 1;
-        const int s = B.ao_shell[mm], atom = B.shell_atom[s], pwr = B.ao_pow[mm];
-        const double eta = B.ao_eta[mm];
+        const int atom = B.shell_atom[B.ao_shell[mm]];
         const double Rx = R[3 * atom], Ry = R[3 * atom + 1], Rz = R[3 * atom + 2];
+        // the thread's AO for all points: monomial and primitives in registers
+        AoLane<T, NPR> al;
+        ao_lane_load<T, NPR>(B, mm, al);
         // (sums over the points in the arithmetic type: in FP32 the mixed
         // measurement's G rows are FP32 too)
         T cr[NW], g[NW];
@@ -628,9 +652,9 @@ __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__rest
                 const double rho = dx * dx + dy * dy + dz * dz;
                 // the AO and its gradient in the arithmetic type (FP32: the
                 // split exponential, as in the measurement's adjoint)
-                T R0, R1, R2, R3, o[5];
-                shell_radial<5, T>(B, s, rho, R0, R1, R2, R3);
-                ao_components<5, T>((T)dx, (T)dy, (T)dz, (T)rho, R0, R1, R2, R3, pwr, (T)eta, o);
+                T R0, u1, u2, u3, o[4];
+                ao_lane_radial<T, NPR>(al, B, rho, R0, u1, u2, u3);
+                ao_lane_value_grad<T, NPR>(al, (T)dx, (T)dy, (T)dz, R0, u1, o);
                 T kap = T(0);
                 const T *y = sy + (size_t)r * n;
 #pragma unroll
