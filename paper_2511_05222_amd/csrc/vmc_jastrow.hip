@@ -328,25 +328,22 @@ __global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int nq, int64_t rows, 
 }
 
 // The 14 derivative components (value, gradient, Laplacian, Hessian,
-// gradient of the Laplacian) of Jastrow function mu at (x, y, z).
+// gradient of the Laplacian) of Jastrow function mu at (x, y, z): the lane's
+// function data as in the adjoint's AO lanes (monomial as branch-free
+// per-axis quadratics; the first primitive in registers in FP32, the
+// Jastrow basis being uncontracted).
 template <typename T>
 __device__ inline void jas_function14(const BasisDev &JB, const double *R, int mu, double x, double y, double z,
                                       T *c) {
-    const int s = JB.ao_shell[mu];
-    const int atom = JB.shell_atom[s];
+    constexpr int NPR = sizeof(T) == 4 ? 1 : 0;
+    AoLane<T, NPR> al;
+    ao_lane_load<T, NPR>(JB, mu, al);
+    const int atom = JB.shell_atom[JB.ao_shell[mu]];
     const double dx = x - R[3 * atom], dy = y - R[3 * atom + 1], dz = z - R[3 * atom + 2];
     const double rho_d = dx * dx + dy * dy + dz * dz;
-    const int p0 = JB.shell_p0[s], np = JB.shell_np[s];
-    T R0 = T(0), R1 = T(0), R2 = T(0), R3 = T(0);
-    for (int k = 0; k < np; ++k) {
-        const T al = (T)JB.prim_exp[p0 + k];
-        const T e = (T)JB.prim_cp[p0 + k] * exp_neg((double)al, rho_d, T(0));
-        R0 += e;
-        R1 -= al * e;
-        R2 += al * al * e;
-        R3 -= al * al * al * e;
-    }
-    ao_components<14, T>((T)dx, (T)dy, (T)dz, (T)rho_d, R0, R1, R2, R3, JB.ao_pow[mu], (T)JB.ao_eta[mu], c);
+    T R0, u1, u2, u3;
+    ao_lane_radial<T, NPR>(al, JB, rho_d, R0, u1, u2, u3);
+    ao_lane_components<T, NPR>(al, (T)dx, (T)dy, (T)dz, (T)rho_d, R0, u1, u2, u3, c);
 }
 
 // dE_L/dr_e and dlnPsi/dr_e contributions of function mu at electron e, in
