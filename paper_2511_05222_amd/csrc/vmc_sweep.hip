@@ -179,12 +179,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
     // moves; rebuilt from the start positions every sweep)
     T sq[JQ];
     if constexpr (J13) {
+        // (four partial sums per slot: the electrons' loads in flight together)
+        const T *x0 = js.X0 + (size_t)w * N * js.MJ + lane;
 #pragma unroll
         for (int q = 0; q < JQ; ++q) {
-            T a = T(0);
-            if (q < js.nq && 64 * q + lane < js.MJ)
-                for (int e = 0; e < N; ++e) a += js.X0[((size_t)w * N + e) * js.MJ + 64 * q + lane];
-            sq[q] = a;
+            T a[4] = {T(0), T(0), T(0), T(0)};
+            if (q < js.nq && 64 * q + lane < js.MJ) {
+                int e = 0;
+                for (; e + 4 <= N; e += 4)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a[u] += x0[(size_t)(e + u) * js.MJ + 64 * q];
+                for (; e < N; ++e) a[0] += x0[(size_t)e * js.MJ + 64 * q];
+            }
+            sq[q] = (a[0] + a[1]) + (a[2] + a[3]);
         }
     }
 
