@@ -177,8 +177,9 @@ def cpu_baseline(spec, budget_s=12.0):
                       f"{dt:.1f} s wall, {cpu:.1f} s CPU; numpy with its BLAS threads over the host cores"}
 
 
-def run_steps(ctx, walkers, seed, warmup, steps):
-    """One vmc_sweep call of `warmup` sweeps, then the timed call of `steps`."""
+def run_steps(ctx, walkers, seed, warmup, steps, kernels=("adjoint", "dense", "mo_rows", "sweep", "proposals")):
+    """One vmc_sweep call of `warmup` sweeps, then the timed call of `steps`
+    (the kernels' HIP-event times over it)."""
     import torch
     ctx.sweep(walkers, warmup, seed, sweep_offset=0)
     torch.cuda.synchronize()
@@ -189,7 +190,7 @@ def run_steps(ctx, walkers, seed, warmup, steps):
     ctx.sweep(walkers, steps, seed, sweep_offset=warmup)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = {k: ctx.profile_read(k) for k in ("adjoint", "dense", "mo_rows", "sweep", "proposals")}
+    prof = {k: ctx.profile_read(k) for k in kernels}
     ctx.profile(False)
     res = ctx.accumulate(reset=True)
     # acceptance of one more sweep on a copy (untimed, not accumulated)
@@ -301,9 +302,25 @@ def next_rows_entry(args, dev, W=16384, warmup=5, steps=3):
     def rate(m, prec, **kw):
         ctx = vmc.Context(m, max_walkers=W, refresh_period=32, precision=prec, **kw)
         w = torch.tensor(inputs.initial_walkers(m, W, spec.seed), device=dev)
-        dt, _, _, _ = run_steps(ctx, w, spec.seed, warmup, steps)
+        jas = m.jastrow.jas_basis is not None
+        dt, _, prof, _ = run_steps(ctx, w, spec.seed, warmup, steps, kernels=("jas_gemm",) if jas else ())
         del ctx, w
-        return {"value": W * steps / dt, "ms_per_step": dt / steps * 1e3}
+        r = {"value": W * steps / dt, "ms_per_step": dt / steps * 1e3}
+        ms, nl, nw = prof.get("jas_gemm", (0.0, 0, 0))
+        if nl > 0:
+            # k_jas_gemm: per walker and launch 2 N MJ^2 matrix-core flops
+            # (the xi1 column is a dot product); A rows of MJ entries (V,
+            # Q: 1 and 4 components, the sweep's differences 2) and MJ + 1
+            # output columns in the arithmetic type
+            MJ, ts = m.jastrow.jas_basis.n_ao, 4 if prec == "mixed" else 8
+            work = {"mfma": 2.0 * m.n_elec * MJ * MJ, "alu": 0.0,
+                    "hbm": float(m.n_elec * ts * (2 * MJ + MJ + 1))}
+            rf = roof(work, prec, ms * 1e-3 / max(nw, 1))
+            rf.update({"kernel": "k_jas_gemm", "share_of_step": ms / steps / r["ms_per_step"],
+                       "avg_launch_ms": ms / nl, "launches": nl, "units_per_launch": nw / nl,
+                       "work_per_unit": work})
+            r["kernels"] = {"jas_gemm": rf}
+        return r
 
     mj = inputs.with_body_jastrow(mol, 7)
     out["body_jastrow"] = {

@@ -498,7 +498,11 @@ int64_t vmc_staging_walkers(const vmc_ctx *ctx);
                                 points of the pseudopotential                    */
 #define VMC_K_ECP_ENERGY  6  /* k_ecp_energy                                     */
 #define VMC_K_ECP_ADJOINT 7  /* k_ecp_adjoint                                    */
-#define VMC_N_PROFILED  8
+#define VMC_K_JAS_GEMM  8    /* k_jas_gemm: the one-/three-body Jastrow's products
+                                with [xi3 | xi1] (the values' and xi3 h per
+                                measurement launch, the moves' differences per
+                                sweep)                                           */
+#define VMC_N_PROFILED  9
 int vmc_profile(vmc_ctx *ctx, int32_t enable);
 int vmc_profile_read(vmc_ctx *ctx, int32_t kernel, double *ms, int64_t *launches, int64_t *walkers);
 

@@ -343,7 +343,9 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
         // value products with [xi3 | xi1]; gradient, Laplacian and value per
         // walker (the dense kernel adds them)
         HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, R, pos, jrows, jX, st, jD));
+        const int pg = prof_begin(c, VMC_K_JAS_GEMM, prof, cw, st);
         HIP_OK(c, vmcx::launch_jas_vprod<T>(c->MJ, c->nq, jrows, jX, (const T *)nullptr, xi_blocks<T>(c), jV, st));
+        prof_end(c, VMC_K_JAS_GEMM, pg, st);
         HIP_OK(c, vmcx::launch_jas_assemble<T>(c->N, c->MJ, c->nq, jrows, 0, (int)cw, jX, jD, jV, c->d_xi1, c->jm_g,
                                                c->jm_u, st));
         mb.jg = c->jm_g;
@@ -380,7 +382,9 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
     if (c->MJ > 0) {
         // (writes the per-function sums jtao that the pseudopotential's
         // one-/three-body terms then add to)
+        const int pg = prof_begin(c, VMC_K_JAS_GEMM, prof, cw, st);
         HIP_OK(c, vmcx::launch_jas_hxi<T>(c->MJ, c->nq, jrows, jD, c->mb_gb, xi_blocks<T>(c), jQ, st));
+        prof_end(c, VMC_K_JAS_GEMM, pg, st);
         HIP_OK(c, vmcx::launch_jas_adjoint<T>(c->jdev, R, c->N, jrows, 0, (int)cw, pos, jV, jQ, c->mb_gb, c->d_xi1,
                                               c->mb_dpart, c->jm_tao, st));
         md.jtao = c->jm_tao;
@@ -474,7 +478,9 @@ static int sweep_once(vmc_ctx *c, double *walkers, int64_t W, int t, uint32_t si
         T *Xp = (T *)c->js_Xp, *X0 = (T *)c->js_X0, *Pd = (T *)c->js_Pd;
         HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, c->d_R, c->prop, rows, Xp, st));
         HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, c->d_R, walkers, rows, X0, st));
+        const int pg = prof_begin(c, VMC_K_JAS_GEMM, true, W, st);
         HIP_OK(c, vmcx::launch_jas_vprod<T>(c->MJ, c->nq, rows, Xp, X0, xi_blocks<T>(c), Pd, st));
+        prof_end(c, VMC_K_JAS_GEMM, pg, st);
         js.Xp = Xp;
         js.X0 = X0;
         js.Pd = Pd;

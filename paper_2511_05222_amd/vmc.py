@@ -280,9 +280,9 @@ class Context:
     def profile_read(self, kernel):
         """(total ms, launches, walkers) of a kernel since profile(True);
         kernel in ("adjoint", "dense", "mo_rows", "sweep", "proposals", "ecp_points", "ecp_energy",
-        "ecp_adjoint")."""
+        "ecp_adjoint", "jas_gemm")."""
         k = {"adjoint": 0, "dense": 1, "mo_rows": 2, "sweep": 3, "proposals": 4, "ecp_points": 5, "ecp_energy": 6,
-             "ecp_adjoint": 7}[kernel]
+             "ecp_adjoint": 7, "jas_gemm": 8}[kernel]
         ms, nl, nw = ct.c_double(0), ct.c_int64(0), ct.c_int64(0)
         self._rc(lib().vmc_profile_read(self._h, k, ct.byref(ms), ct.byref(nl), ct.byref(nw)))
         return ms.value, nl.value, nw.value
