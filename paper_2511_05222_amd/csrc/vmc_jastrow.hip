@@ -165,8 +165,9 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
 //   AM = 2: A = h = grad chi abar - lap chi / 2 at the row's electron, from
 //           D = [rows][4][MJ] (gradient, Laplacian) and abar = -(Jastrow +
 //           determinant gradient) from gb.
-// AM 0 and 1 write the MJ + 1 columns in blocks of 64 ([nq][rows][64]); AM 2
-// writes xi3 h, MJ columns row by row ([rows][MJ]).  The xi3 columns on the
+// AM 0 writes the MJ + 1 columns in blocks of 64 ([nq][rows][64]); AM 1 row
+// by row with a row stride of MJ + 1 rounded up to a multiple of 4, the xi1
+// column at MJ; AM 2 writes xi3 h, MJ columns row by row ([rows][MJ]).  The xi3 columns on the
 // matrix cores: 64 rows per block, 16 per wavefront; the columns in groups of
 // NTL tiles of 16 whose accumulators stay in registers; k in chunks of 16
 // with the chunk of xi3 staged in LDS (two buffers, one barrier per chunk;
@@ -314,6 +315,8 @@ __global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int nq, int64_t rows, 
                 if (t >= ntg || oc >= MJ) continue;
                 if constexpr (AM == 2)
                     out[row * MJ + oc] = acc[t][v];
+                else if constexpr (AM == 1)
+                    out[row * ((MJ + 4) & ~3) + oc] = acc[t][v];
                 else
                     out[((size_t)(oc >> 6) * rows + row) * 64 + (oc & 63)] = acc[t][v];
             }
@@ -322,7 +325,12 @@ __global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int nq, int64_t rows, 
             // (the four lanes of row ml: kg = 0..3, 16 apart)
             p1 += __shfl_xor(p1, 16);
             p1 += __shfl_xor(p1, 32);
-            if (kg == 0 && rok) out[((size_t)(MJ >> 6) * rows + arow) * 64 + (MJ & 63)] = p1;
+            if (kg == 0 && rok) {
+                if constexpr (AM == 1)
+                    out[arow * ((MJ + 4) & ~3) + MJ] = p1;
+                else
+                    out[((size_t)(MJ >> 6) * rows + arow) * 64 + (MJ & 63)] = p1;
+            }
         }
     }
 }

@@ -149,8 +149,9 @@ hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, con
 // One-/three-body Jastrow terms (vmc_jastrow.hip).  jas_values: out[row][mu]
 // = chi_mu(pos[row]) and, with der, der[row][c][mu] its gradient (c < 3) and
 // Laplacian (c = 3).  jas_vprod: the products of the rows of X (of X - X0
-// when X0 is given) with [xi3 | xi1] ([nq][MJ][64] in xiblk), MJ + 1 columns
-// in blocks of 64, V[q][row][64].
+// when X0 is given) with [xi3 | xi1] ([nq][MJ][64] in xiblk), MJ + 1 columns:
+// in blocks of 64, V[q][row][64] (X), or row by row with a row stride of
+// MJ + 1 rounded up to a multiple of 4 (X - X0).
 // jas_assemble: grad_e U, lap_e U, U from the values, their derivatives and
 // the value products.  jas_hxi: Q[row] = xi3 h_row (h = grad chi abar -
 // lap chi / 2, abar from gb).  jas_adjoint: its terms of dE_L/dr_e (added to
@@ -180,7 +181,7 @@ hipError_t launch_xi_sums(const double *X, int N, int MJ, int W, const double *E
                           hipStream_t st);
 // The sweep's one-/three-body terms (null Xp: none): chi at the proposals and
 // at the positions of the sweep's start ([W N][MJ]) and the [xi3 | xi1]
-// products of their difference ([nq][W N][64]).
+// products of their difference (rows of MJ + 1 rounded up to a multiple of 4).
 template <typename T>
 struct JasSweep {
     const T *Xp = nullptr, *X0 = nullptr, *Pd = nullptr;

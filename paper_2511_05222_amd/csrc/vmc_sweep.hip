@@ -134,9 +134,26 @@ constexpr int sweep_waves() {
     return (sizeof(T) == 4 && KN <= 48) ? 3 : 2;
 }
 
-// The one-/three-body Jastrow slots of a lane: basis function 64 q + lane for
-// q < JQ (the last slot past the basis, 64 q + lane = MJ, is xi1's column).
-constexpr int JQ = 5;
+// The one-/three-body Jastrow slots of a lane: basis functions 4 lane + u,
+// u < JQ (at most 256 functions).  Row e of chi(r') - chi(r) times
+// [xi3 | xi1] is row-major with the xi1 column at MJ and a row stride of MJ + 1
+// rounded up to a multiple of 4.  jrow4 reads a lane's four entries of a row
+// as one vector when the row starts are 16-byte aligned (vec), else one by one;
+// entries past n read 0.
+constexpr int JQ = 4;
+
+template <typename T>
+__device__ inline void jrow4(const T *row, int mu0, int n, bool vec, T *d) {
+    typedef T V4 __attribute__((ext_vector_type(4)));
+    if (vec) {
+        const V4 v = *(const V4 *)(row + mu0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = mu0 + u < n ? v[u] : T(0);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = mu0 + u < n ? row[mu0 + u] : T(0);
+    }
+}
 
 template <typename T, int KN, bool J13>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves<T, KN>()))) void k_sweep_r(
@@ -178,21 +195,35 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
     // positions, over this lane's basis slots (kept current by the accepted
     // moves; rebuilt from the start positions every sweep)
     T sq[JQ];
+    // (the lane's first slot; the rows' vector reads: X rows need MJ % 4 == 0,
+    // the product rows are padded)
+    const int jm0 = 4 * lane, jld = (js.MJ + 4) & ~3;
+    const bool jvx = (js.MJ & 3) == 0 && jm0 < js.MJ, jvp = jm0 < js.MJ;
     if constexpr (J13) {
-        // (four partial sums per slot: the electrons' loads in flight together)
-        const T *x0 = js.X0 + (size_t)w * N * js.MJ + lane;
+        // (two partial sums per slot: the electrons' loads in flight together)
+        const T *x0 = js.X0 + (size_t)w * N * js.MJ;
+        T a[2][JQ];
 #pragma unroll
-        for (int q = 0; q < JQ; ++q) {
-            T a[4] = {T(0), T(0), T(0), T(0)};
-            if (q < js.nq && 64 * q + lane < js.MJ) {
-                int e = 0;
-                for (; e + 4 <= N; e += 4)
+        for (int u = 0; u < JQ; ++u) a[0][u] = a[1][u] = T(0);
+        int e = 0;
+        for (; e + 2 <= N; e += 2) {
+            T v0[JQ], v1[JQ];
+            jrow4<T>(x0 + (size_t)e * js.MJ, jm0, js.MJ, jvx, v0);
+            jrow4<T>(x0 + (size_t)(e + 1) * js.MJ, jm0, js.MJ, jvx, v1);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) a[u] += x0[(size_t)(e + u) * js.MJ + 64 * q];
-                for (; e < N; ++e) a[0] += x0[(size_t)e * js.MJ + 64 * q];
+            for (int u = 0; u < JQ; ++u) {
+                a[0][u] += v0[u];
+                a[1][u] += v1[u];
             }
-            sq[q] = (a[0] + a[1]) + (a[2] + a[3]);
         }
+        if (e < N) {
+            T v0[JQ];
+            jrow4<T>(x0 + (size_t)e * js.MJ, jm0, js.MJ, jvx, v0);
+#pragma unroll
+            for (int u = 0; u < JQ; ++u) a[0][u] += v0[u];
+        }
+#pragma unroll
+        for (int u = 0; u < JQ; ++u) sq[u] = a[0][u] + a[1][u];
     }
 
     // the proposal's MO row of the first move (later rows are loaded one move
@@ -246,23 +277,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         T jd[JQ];
         if constexpr (J13) {
             const size_t row = (size_t)w * N + e;
+            const T *pr = js.Pd + row * jld;
+            T pd[JQ], xp[JQ], x0[JQ];
+            jrow4<T>(pr, jm0, js.MJ, jvp, pd);
+            jrow4<T>(js.Xp + row * js.MJ, jm0, js.MJ, jvx, xp);
+            jrow4<T>(js.X0 + row * js.MJ, jm0, js.MJ, jvx, x0);
+            const T p1 = pr[js.MJ];   // xi1 . d, the same in every lane
             T loc = T(0);
 #pragma unroll
-            for (int q = 0; q < JQ; ++q) {
-                jd[q] = T(0);
-                const int mu = 64 * q + lane;
-                if (q < js.nq && mu <= js.MJ) {
-                    const T pd = js.Pd[((size_t)q * js.rows + row) * 64 + lane];
-                    if (mu < js.MJ) {
-                        const T x0 = js.X0[row * js.MJ + mu];
-                        jd[q] = js.Xp[row * js.MJ + mu] - x0;
-                        loc += pd * (sq[q] - x0);
-                    } else {
-                        loc += pd;
-                    }
-                }
+            for (int u = 0; u < JQ; ++u) {
+                jd[u] = xp[u] - x0[u];
+                loc += pd[u] * (sq[u] - x0[u]);
             }
-            dj += wave_sum_dpp((double)loc);
+            dj += wave_sum_dpp((double)loc) + (double)p1;
         }
         // lane i < KN holds phi_i (zero from nb on): store it at the register
         // slot of orbital i
@@ -314,7 +341,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             wave_sync_s();
             if constexpr (J13) {
 #pragma unroll
-                for (int q = 0; q < JQ; ++q) sq[q] += jd[q];
+                for (int u = 0; u < JQ; ++u) sq[u] += jd[u];
             }
             const T rr = sizeof(T) == sizeof(float) ? (T)__builtin_amdgcn_rcpf((float)ratio) : (T)rcp_nr(ratio);
             const T t = (v - (lane == pj ? T(1) : T(0))) * rr;
