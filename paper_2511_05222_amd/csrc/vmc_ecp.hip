@@ -873,7 +873,7 @@ __global__ __launch_bounds__(256) void k_ecp_jas(int N, EcpJas<T> J, const doubl
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const double *__restrict__ R,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_ecp_chain(SysDev S, EcpDev E, const double *__restrict__ R,
                                                    const double *__restrict__ pos, EcpBufs<T> eb,
                                                    const T *__restrict__ ktil, double *dedr,
                                                    const double *__restrict__ jg) {
@@ -957,6 +957,8 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
         // dE/dr_q through the orbitals: cq sum_j K~[e][j] grad phi_j(r_q)
         double g[3] = {0.0, 0.0, 0.0};
         const T *pr5 = ph + (size_t)row * 5 * n;
+        // (unrolled: the loads of several orbitals in flight together)
+#pragma unroll 4
         for (int j = 0; j < n; ++j) {
             const double kj = (double)kt[(size_t)e * n + j];
             g[0] += kj * (double)pr5[n + j];
@@ -1003,6 +1005,7 @@ __global__ __launch_bounds__(256) void k_ecp_chain(SysDev S, EcpDev E, const dou
         double s3[3] = {0.0, 0.0, 0.0};
         if (j < N) {
             const double xj = sp[3 * j], yj = sp[3 * j + 1], zj = sp[3 * j + 2];
+#pragma unroll 4
             for (int row = slot; row < nrow; row += esl) {
                 const double *o = rw + (size_t)row * ECP_ROW;
                 if ((pw[row / 12] & 255) == j) {
