@@ -414,7 +414,7 @@ __global__ __launch_bounds__(256) void k_ecp_energy(SysDev S, EcpDev E, const do
 // abar, Z^T[e][j] by threads over (electron, orbital) from the points' rows,
 // then dE/dA as above.
 size_t ecp_energy_pts_lds(int N, int n) {
-    return sizeof(double) * ((size_t)4 * N + (size_t)N * n + (size_t)n * n + 256 + 4);
+    return sizeof(double) * ((size_t)4 * N + (size_t)2 * N * n + (size_t)n * n + 256 + 4) + sizeof(int) * 2 * N;
 }
 
 template <typename T>
@@ -430,6 +430,8 @@ __global__ __launch_bounds__(256) void k_ecp_energy_pts(SysDev S, EcpDev E, cons
     double *sz = suo + N;          // [N][n]: Z^T
     double *sP = sz + N * n;       // [n][n]
     double *red = sP + n * n;      // [256] E_nl partials, then the local terms
+    double *skt = red + 260;       // [N][n]: K~ of the walker
+    int *pr0 = (int *)(skt + N * n);   // [2][N]: each electron's pairs [pr0, pr1)
     for (int i = tid; i < 3 * N; i += 256) sp[i] = pos[(size_t)w * N * 3 + i];
     __syncthreads();
     for (int e = tid; e < N; e += 256) {
@@ -511,13 +513,23 @@ __global__ __launch_bounds__(256) void k_ecp_energy_pts(SysDev S, EcpDev E, cons
         if (!isfinite(e_l)) atomicOr(status, STATUS_NONFINITE);
     }
     if (!abar) return;
-    // Z^T[e][j] = sum over e's points c'_q phi_q[j] (the rows written above)
+    // K~ of the walker into LDS; each electron's pairs (the pairs are placed
+    // electron by electron, so an electron's pairs are one range)
+    for (int i = tid; i < N * n; i += 256) skt[i] = (double)kt[i];
+    for (int e = tid; e < N; e += 256) pr0[e] = pr0[N + e] = 0;
     __syncthreads();
+    for (int pi = tid; pi < np; pi += 256) {
+        const int e = pw[pi] & 255;
+        if (pi == 0 || (pw[pi - 1] & 255) != e) pr0[e] = pi;
+        if (pi == np - 1 || (pw[pi + 1] & 255) != e) pr0[N + e] = pi + 1;
+    }
+    __syncthreads();
+    // Z^T[e][j] = sum over e's points c'_q phi_q[j] (the rows written above)
     for (int idx = tid; idx < N * n; idx += 256) {
         const int e = idx / n, j = idx - (idx / n) * n;
         double z = 0.0;
-        for (int pi = 0; pi < np; ++pi) {
-            if ((pw[pi] & 255) != e) continue;
+        for (int pi = pr0[e]; pi < pr0[N + e]; ++pi) {
+#pragma unroll
             for (int q = 0; q < 12; ++q) {
                 const int row = 12 * pi + q;
                 z += rw[(size_t)row * ECP_ROW] * (double)ph[(size_t)row * nc * n + j];
@@ -532,14 +544,14 @@ __global__ __launch_bounds__(256) void k_ecp_energy_pts(SysDev S, EcpDev E, cons
         for (int idx = tid; idx < n * n; idx += 256) {
             const int a = idx / n, j = idx - (idx / n) * n;
             double s = 0.0;
-            for (int i = 0; i < nb; ++i) s += sz[(size_t)(off + i) * n + a] * (double)kt[(size_t)(off + i) * n + j];
+            for (int i = 0; i < nb; ++i) s += sz[(size_t)(off + i) * n + a] * skt[(size_t)(off + i) * n + j];
             sP[idx] = s;
         }
         __syncthreads();
         for (int idx = tid; idx < nb * n; idx += 256) {
             const int ei = idx / n, j = idx - (idx / n) * n;
             double s = 0.0;
-            for (int a = 0; a < n; ++a) s += (double)kt[(size_t)(off + ei) * n + a] * sP[(size_t)a * n + j];
+            for (int a = 0; a < n; ++a) s += skt[(size_t)(off + ei) * n + a] * sP[(size_t)a * n + j];
             T *ab = abar + ((size_t)w * N + off + ei) * n + j;
             *ab = (T)((double)*ab - s);
         }
