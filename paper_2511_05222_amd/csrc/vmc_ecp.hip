@@ -599,7 +599,7 @@ __device__ inline void ao_lane_value_grad(const AoLane<T, NPR> &L, T x, T y, T z
 // The pair sums go through LDS in chunks of 256 pairs.
 // ---------------------------------------------------------------------------
 
-constexpr int ECP_AO_ROWS = 32;   // points staged per batch
+constexpr int ECP_AO_ROWS = 64;   // points staged per batch
 
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void k_ecp_points_ao(SysDev S, const T *__restrict__ C,
