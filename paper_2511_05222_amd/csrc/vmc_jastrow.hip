@@ -167,18 +167,18 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
 //           determinant gradient) from gb.
 // AM 0 writes the MJ + 1 columns in blocks of 64 ([nq][rows][64]); AM 1 row
 // by row with a row stride of MJ + 1 rounded up to a multiple of 4, the xi1
-// column at MJ; AM 2 writes xi3 h, MJ columns row by row ([rows][MJ]).  The xi3 columns on the
-// matrix cores: 64 rows per block, 16 per wavefront; the columns in groups of
-// NTL tiles of 16 whose accumulators stay in registers; k in chunks of 16
-// with the chunk of xi3 staged in LDS (two buffers, one barrier per chunk;
-// thread i stages column i mod 16 NTL) and each lane's A entries read from
-// memory directly, both loaded one chunk ahead.  In a chunk, lane (m, g) of
-// the 16x16x4 product takes k = 4 g + j at step j: a permutation of k that
-// the A entries and the LDS reads share.  The LDS chunk is laid out
-// [k][m][tile] (rows of NTL + 16 bytes), so that a lane reads its NTL B
-// entries of a step as 16-byte vectors without bank conflicts.  The xi1 column (AM 0, 1) is a dot
-// product per row: lane partial sums over its k, added over the four lanes
-// of the row.
+// column at MJ; AM 2 writes xi3 h, MJ columns row by row ([rows][MJ]).
+// The xi3 columns on the matrix cores: 64 rows per block, 16 per wavefront;
+// the columns in groups of NTL tiles of 16 whose accumulators stay in
+// registers; k in chunks of 16 with the chunk of xi3 staged in LDS (two
+// buffers, one barrier per chunk; thread i stages column i mod 16 NTL) and
+// each lane's A entries read from memory directly, both loaded one chunk
+// ahead.  In a chunk, lane (m, g) of the 16x16x4 product takes k = 4 g + j at
+// step j: a permutation of k that the A entries and the LDS reads share.
+// The LDS chunk is laid out [k][m][tile] (rows of NTL + 16 bytes), so that a
+// lane reads its NTL B entries of a step as 16-byte vectors without bank
+// conflicts.  The xi1 column (AM 0, 1) is a dot product per row: lane
+// partial sums over its k, added over the four lanes of the row.
 template <typename T, int NTL, int AM, bool VA>
 __global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int nq, int64_t rows, const T *__restrict__ A0,
                                                   const T *__restrict__ A1, const double *__restrict__ gb,
@@ -212,8 +212,8 @@ __global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int nq, int64_t rows, 
         T ra[NA], rb[KPT], p1 = T(0);
         // a lane's four entries k0 + 4 g + (0..3) of a row of A (of A0 and
         // A1; of the four components of D): VA (MJ a multiple of 4) as 16-byte
-        // vectors, else one by one
-        // (a chunk inside the basis needs no clamping: FULL)
+        // vectors, else one by one; a chunk inside the basis (full) needs no
+        // clamping
         auto load4 = [&](const T *src, T *dst, int k0, bool full) {
             const int k = k0 + 4 * kg;
             if constexpr (VA) {
