@@ -85,15 +85,17 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
                                                       const T *__restrict__ V, const double *__restrict__ xi1,
                                                       double *__restrict__ jg, double *__restrict__ ju) {
     __shared__ double sv[JAS_MAX], tv[JAS_MAX];
-    __shared__ double ue[JAS_ELEC];
+    __shared__ double uw[4];
     const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const T *Xw = X + (size_t)w * N * MJ;
     auto Vat = [&](int e, int mu) -> double {
         return (double)V[((size_t)(mu >> 6) * rows + row0 + (size_t)w * N + e) * 64 + (mu & 63)];
     };
-    // s and t = xi3 s: wavefront v sums the electrons e = v mod 4 for the
-    // functions mu = lane + 64 k (eight independent chains per lane), then
-    // the wavefronts' partials are added in wavefront order
+    // s, t = xi3 s and sum_e V[e] . chi_e: wavefront v sums the electrons
+    // e = v mod 4 for the functions mu = lane + 64 k (independent chains per
+    // lane), then the wavefronts' partials of s and t are added in wavefront
+    // order.  U = t . s / 2 - sum_e V[e] . chi_e / 2 + xi1 . s.
+    double dvl = 0.0;
     {
         double pa[4] = {0.0, 0.0, 0.0, 0.0}, pt[4] = {0.0, 0.0, 0.0, 0.0};
         for (int e = wave; e < N; e += 4) {
@@ -101,8 +103,10 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
             for (int k = 0; k < 4; ++k) {
                 const int mu = lane + 64 * k;
                 if (mu < MJ) {
-                    pa[k] += (double)Xw[(size_t)e * MJ + mu];
-                    pt[k] += Vat(e, mu);
+                    const double x = (double)Xw[(size_t)e * MJ + mu], v = Vat(e, mu);
+                    pa[k] += x;
+                    pt[k] += v;
+                    dvl += v * x;
                 }
             }
         }
@@ -119,43 +123,40 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
             __syncthreads();
         }
     }
+    {
+        // (MJ <= 256: one function per thread)
+        const double q = tid < MJ ? (0.5 * tv[tid] + xi1[tid]) * sv[tid] : 0.0;
+        const double u = wave_sum_dpp(q - 0.5 * dvl);
+        if (lane == 0) uw[wave] = u;
+    }
+    // per electron: grad_e U and lap_e U, dot products of the basis
+    // derivatives with g_e = xi1 + t - V[e]
     for (int e = wave; e < N; e += 4) {
         const size_t row = row0 + (size_t)w * N + e;
         const T *de = D + row * 4 * MJ;
-        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        // (the slots k = 0..4 cover mu <= MJ <= 256: their loads are issued
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        // (the slots k = 0..3 cover mu < MJ <= 256: their loads are issued
         // together)
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 4; ++k) {
             const int mu = lane + 64 * k;
-            if (mu > MJ) continue;
-            const double v = Vat(e, mu);
-            if (mu == MJ) {
-                acc[0] += v;   // xi1 . chi_e
-                continue;
-            }
-            const double g = xi1[mu] + tv[mu] - v;
-            acc[0] += 0.5 * v * (sv[mu] - (double)Xw[(size_t)e * MJ + mu]);
+            if (mu >= MJ) continue;
+            const double g = xi1[mu] + tv[mu] - Vat(e, mu);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[1 + c] += (double)de[(size_t)c * MJ + mu] * g;
+            for (int c = 0; c < 4; ++c) acc[c] += (double)de[(size_t)c * MJ + mu] * g;
         }
 #pragma unroll
-        for (int c = 0; c < 5; ++c) acc[c] = wave_sum_dpp(acc[c]);
+        for (int c = 0; c < 4; ++c) acc[c] = wave_sum_dpp(acc[c]);
         if (lane == 0) {
             double *g = jg + ((size_t)w * N + e) * 4;
-            g[0] = acc[1];
-            g[1] = acc[2];
-            g[2] = acc[3];
-            g[3] = acc[4];
-            ue[e] = acc[0];
+            g[0] = acc[0];
+            g[1] = acc[1];
+            g[2] = acc[2];
+            g[3] = acc[3];
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        double u = 0.0;
-        for (int e = 0; e < N; ++e) u += ue[e];
-        ju[w] = u;
-    }
+    if (tid == 0) ju[w] = (uw[0] + uw[1]) + (uw[2] + uw[3]);
 }
 
 // out = A [xi3 | xi1] over the Jastrow basis (k < MJ), for three kinds of
