@@ -70,7 +70,7 @@ struct vmc_ctx {
     // [xi3 | xi1] in column blocks of 64 ([nq][MJ][64], FP64 and FP32), xi1
     int MJ = 0, nq = 0;
     vmcx::BasisDev jdev{};
-    AoTiles jtiles16{};
+    AoTiles jtiles16{}, jtiles32{};   // the Jastrow basis in tiles of <= 16 and <= 32 functions
     double *d_xiblk = nullptr, *d_xi1 = nullptr;
     // the Jastrow-parameter gradient's sums (jastrow_gradient): per launch
     // the FP64 basis values at the electrons and the partial sums, and the
@@ -342,7 +342,7 @@ static int measure_core(vmc_ctx *c, const double *pos, const double *pos0, int64
         // one-/three-body Jastrow: chi with its gradients and Laplacians, the
         // value products with [xi3 | xi1]; gradient, Laplacian and value per
         // walker (the dense kernel adds them)
-        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, R, pos, jrows, jX, st, jD));
+        HIP_OK(c, vmcx::launch_jas_values<T>(c->jdev, c->jtiles16, R, pos, jrows, jX, st, jD, &c->jtiles32));
         const int pg = prof_begin(c, VMC_K_JAS_GEMM, prof, cw, st);
         HIP_OK(c, vmcx::launch_jas_vprod<T>(c->MJ, c->nq, jrows, jX, (const T *)nullptr, xi_blocks<T>(c), jV, st));
         prof_end(c, VMC_K_JAS_GEMM, pg, st);
@@ -601,7 +601,8 @@ static size_t ts_of(int precision) { return precision == VMC_MIXED ? sizeof(floa
 // primitives; every cartesian component renormalised to unit norm) and upload
 // its tables and AO tiles (whole shells of at most 16 AOs).  Shell counts,
 // angular momenta and exponents have been validated.
-static int upload_basis(vmc_ctx *c, const vmc_basis *basis, int A, vmcx::BasisDev &bd, AoTiles &tiles) {
+static int upload_basis(vmc_ctx *c, const vmc_basis *basis, int A, vmcx::BasisDev &bd, AoTiles &tiles,
+                        AoTiles *tiles32 = nullptr) {
     const int S = basis->n_shells;
     int P = 0;
     for (int s = 0; s < S; ++s) P += basis->shell_nprim[s];
@@ -639,25 +640,30 @@ static int upload_basis(vmc_ctx *c, const vmc_basis *basis, int A, vmcx::BasisDe
         }
     }
     const int M = (int)ao_shell.size();
-    // AO tiles: consecutive whole shells with at most 16 AOs, as four arrays
+    // AO tiles: consecutive whole shells with at most mt AOs, as four arrays
     // (first shell, end shell, first AO, end AO)
-    std::vector<int> tl;
-    for (int s = 0; s < S;) {
-        int s1 = s, cnt = 0;
-        while (s1 < S && cnt + (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2 <= 16) {
-            cnt += (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2;
-            ++s1;
+    auto make_tiles = [&](int mt) {
+        std::vector<int> tl;
+        for (int s = 0; s < S;) {
+            int s1 = s, cnt = 0;
+            while (s1 < S && cnt + (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2 <= mt) {
+                cnt += (basis->shell_l[s1] + 1) * (basis->shell_l[s1] + 2) / 2;
+                ++s1;
+            }
+            tl.push_back(s);
+            tl.push_back(s1);
+            tl.push_back(shell_mu0[s]);
+            tl.push_back(s1 < S ? shell_mu0[s1] : M);
+            s = s1;
         }
-        tl.push_back(s);
-        tl.push_back(s1);
-        tl.push_back(shell_mu0[s]);
-        tl.push_back(s1 < S ? shell_mu0[s1] : M);
-        s = s1;
-    }
-    const int nt = (int)tl.size() / 4;
-    std::vector<int> soa(4 * nt);
-    for (int t = 0; t < nt; ++t)
-        for (int k = 0; k < 4; ++k) soa[k * nt + t] = tl[4 * t + k];
+        const int n = (int)tl.size() / 4;
+        std::vector<int> soa(4 * n);
+        for (int t = 0; t < n; ++t)
+            for (int k = 0; k < 4; ++k) soa[k * n + t] = tl[4 * t + k];
+        return soa;
+    };
+    const std::vector<int> soa = make_tiles(16);
+    const int nt = (int)soa.size() / 4;
     // the AOs of each atom (any shell order), for per-nucleus sums
     std::vector<int> atom_ao_ptr(A + 1, 0), atom_ao(M);
     for (int m = 0; m < M; ++m) ++atom_ao_ptr[basis->shell_atom[ao_shell[m]] + 1];
@@ -683,6 +689,13 @@ static int upload_basis(vmc_ctx *c, const vmc_basis *basis, int A, vmcx::BasisDe
     bd = vmcx::BasisDev{M,           S,         d_ao_shell, d_ao_pow, d_eta,       d_shell_atom, d_shell_p0,
                         d_shell_np, d_exp,     d_cp,       d_shell_l, d_shell_mu0, d_ptr,        d_aa};
     tiles = AoTiles{d_tiles, d_tiles + nt, d_tiles + 2 * nt, d_tiles + 3 * nt, nt};
+    if (tiles32) {
+        const std::vector<int> s32 = make_tiles(32);
+        const int n32 = (int)s32.size() / 4;
+        int *d32;
+        if ((rc = c->upload(&d32, s32.data(), 4 * n32))) return rc;
+        *tiles32 = AoTiles{d32, d32 + n32, d32 + 2 * n32, d32 + 3 * n32, n32};
+    }
     return VMC_OK;
 }
 
@@ -789,7 +802,7 @@ static int setup_ecp(vmc_ctx *c, const vmc_ecp *e, int A) {
 
 static int setup_body_jastrow(vmc_ctx *c, const vmc_jastrow *jas, int A) {
     int rc;
-    if ((rc = upload_basis(c, jas->jas_basis, A, c->jdev, c->jtiles16))) return rc;
+    if ((rc = upload_basis(c, jas->jas_basis, A, c->jdev, c->jtiles16, &c->jtiles32))) return rc;
     const int MJ = c->MJ, nq = c->nq;
     std::vector<double> blk((size_t)nq * MJ * 64, 0.0);
     for (int q = 0; q < nq; ++q)

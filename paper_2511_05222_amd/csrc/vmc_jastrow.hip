@@ -41,15 +41,15 @@ constexpr int JAS_ELEC = 128;  // electrons
 
 // out[row][mu] = chi_mu(pos[row]) for the rows' positions and, with NC = 5,
 // der[row][c][mu] = (d/dx, d/dy, d/dz, Laplacian)_c chi_mu(pos[row]); one
-// block per 64 rows.  Per tile of whole shells (<= 16 functions) a wavefront
+// block per 64 rows.  Per tile of whole shells (<= MT functions) a wavefront
 // evaluates one shell at 64 rows (uniform angular momentum) into an LDS
 // tile, which the block then writes row by row (consecutive threads,
 // consecutive functions).
-template <typename T, int NC>
+template <typename T, int NC, int MT>
 __global__ __launch_bounds__(256) void k_jas_values(BasisDev JB, AoTiles tiles, const double *__restrict__ R,
                                                     const double *__restrict__ pos, int64_t rows,
                                                     T *__restrict__ out, T *__restrict__ der) {
-    constexpr int RB = 64, TS = 16 * NC + 1;
+    constexpr int RB = 64, TS = MT * NC + 1;
     __shared__ double sp[RB * 3];
     __shared__ T tv[RB * TS];
     const int tid = threadIdx.x, MJ = JB.n_ao;
@@ -470,13 +470,20 @@ __global__ __launch_bounds__(256) void k_jas_adjoint(BasisDev JB, const double *
 
 template <typename T>
 hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double *R, const double *pos, int64_t rows,
-                             T *out, hipStream_t st, T *der) {
+                             T *out, hipStream_t st, T *der, const AoTiles *jt32) {
     if (rows < 1) return hipSuccess;
     const dim3 g((unsigned)((rows + 63) / 64));
+    // (wider tiles: half the barriers and row segments twice as long; the
+    // FP64 tile of 32 functions would not fit the static LDS)
+    if constexpr (sizeof(T) == sizeof(float))
+        if (der && jt32) {
+            hipLaunchKernelGGL((k_jas_values<T, 5, 32>), g, dim3(256), 0, st, JB, *jt32, R, pos, rows, out, der);
+            return hipGetLastError();
+        }
     if (der)
-        hipLaunchKernelGGL((k_jas_values<T, 5>), g, dim3(256), 0, st, JB, jt, R, pos, rows, out, der);
+        hipLaunchKernelGGL((k_jas_values<T, 5, 16>), g, dim3(256), 0, st, JB, jt, R, pos, rows, out, der);
     else
-        hipLaunchKernelGGL((k_jas_values<T, 1>), g, dim3(256), 0, st, JB, jt, R, pos, rows, out, der);
+        hipLaunchKernelGGL((k_jas_values<T, 1, 16>), g, dim3(256), 0, st, JB, jt, R, pos, rows, out, der);
     return hipGetLastError();
 }
 
@@ -535,7 +542,7 @@ hipError_t launch_jas_adjoint(const BasisDev &JB, const double *R, int N, int64_
 
 #define JAS_INST(T)                                                                                               \
     template hipError_t launch_jas_values<T>(const BasisDev &, const AoTiles &, const double *, const double *,   \
-                                             int64_t, T *, hipStream_t, T *);                                      \
+                                             int64_t, T *, hipStream_t, T *, const AoTiles *);                     \
     template hipError_t launch_jas_vprod<T>(int, int, int64_t, const T *, const T *, const T *, T *,             \
                                             hipStream_t);                                                          \
     template hipError_t launch_jas_assemble<T>(int, int, int, int64_t, int64_t, int, const T *, const T *,        \

@@ -148,7 +148,8 @@ hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, con
                                const int *rows_dev = nullptr);
 // One-/three-body Jastrow terms (vmc_jastrow.hip).  jas_values: out[row][mu]
 // = chi_mu(pos[row]) and, with der, der[row][c][mu] its gradient (c < 3) and
-// Laplacian (c = 3).  jas_vprod: the products of the rows of X (of X - X0
+// Laplacian (c = 3) (in FP32 over the tiles of <= 32 functions jt32 when
+// given, else jt's of <= 16).  jas_vprod: the products of the rows of X (of X - X0
 // when X0 is given) with [xi3 | xi1] ([nq][MJ][64] in xiblk), MJ + 1 columns:
 // in blocks of 64, V[q][row][64] (X), or row by row with a row stride of
 // MJ + 1 rounded up to a multiple of 4 (X - X0).
@@ -158,7 +159,7 @@ hipError_t launch_mo_rows_mfma(const SysDev &S, const T *C, const double *R, con
 // dedr) and the per-function sums jtao.
 template <typename T>
 hipError_t launch_jas_values(const BasisDev &JB, const AoTiles &jt, const double *R, const double *pos, int64_t rows,
-                             T *out, hipStream_t st, T *der = nullptr);
+                             T *out, hipStream_t st, T *der = nullptr, const AoTiles *jt32 = nullptr);
 template <typename T>
 hipError_t launch_jas_vprod(int MJ, int nq, int64_t rows, const T *X, const T *X0, const T *xiblk, T *V,
                             hipStream_t st);
