@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_jas_values(BasisDev JB, AoTiles tiles, 
 // X[row][MJ]: chi values; D[row][4][MJ]: their gradients and Laplacians;
 // V: nq blocks of [rows][64] (value products with [xi3 | xi1]).
 template <typename T>
-__global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0,
+__global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int64_t rows, int64_t row0,
                                                       const T *__restrict__ X, const T *__restrict__ D,
                                                       const T *__restrict__ V, const double *__restrict__ xi1,
                                                       double *__restrict__ jg, double *__restrict__ ju) {
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_jas_assemble(int N, int MJ, int nq, int
 // conflicts.  The xi1 column (AM 0, 1) is a dot product per row: lane
 // partial sums over its k, added over the four lanes of the row.
 template <typename T, int NTL, int AM, bool VA>
-__global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int nq, int64_t rows, const T *__restrict__ A0,
+__global__ __launch_bounds__(256) void k_jas_gemm(int MJ, int64_t rows, const T *__restrict__ A0,
                                                   const T *__restrict__ A1, const double *__restrict__ gb,
                                                   const T *__restrict__ xiblk, T *__restrict__ out) {
     typedef Mfma<T> MF;
@@ -493,41 +493,41 @@ template <typename T>
 constexpr int jas_gemm_ntl() { return sizeof(T) == sizeof(float) ? 16 : 8; }
 
 template <typename T, int AM>
-static void launch_jas_gemm(int MJ, int nq, int64_t rows, const T *A0, const T *A1, const double *gb,
-                            const T *xiblk, T *out, hipStream_t st) {
+static void launch_jas_gemm(int MJ, int64_t rows, const T *A0, const T *A1, const double *gb, const T *xiblk, T *out,
+                            hipStream_t st) {
     const dim3 g((unsigned)((rows + 63) / 64)), b(256);
     if (MJ % 4 == 0)
-        hipLaunchKernelGGL((k_jas_gemm<T, jas_gemm_ntl<T>(), AM, true>), g, b, 0, st, MJ, nq, rows, A0, A1, gb, xiblk,
+        hipLaunchKernelGGL((k_jas_gemm<T, jas_gemm_ntl<T>(), AM, true>), g, b, 0, st, MJ, rows, A0, A1, gb, xiblk,
                            out);
     else
-        hipLaunchKernelGGL((k_jas_gemm<T, jas_gemm_ntl<T>(), AM, false>), g, b, 0, st, MJ, nq, rows, A0, A1, gb,
-                           xiblk, out);
+        hipLaunchKernelGGL((k_jas_gemm<T, jas_gemm_ntl<T>(), AM, false>), g, b, 0, st, MJ, rows, A0, A1, gb, xiblk,
+                           out);
 }
 
 template <typename T>
-hipError_t launch_jas_vprod(int MJ, int nq, int64_t rows, const T *X, const T *X0, const T *xiblk, T *V,
-                            hipStream_t st) {
+hipError_t launch_jas_vprod(int MJ, int /* nq (implied by MJ) */, int64_t rows, const T *X, const T *X0,
+                            const T *xiblk, T *V, hipStream_t st) {
     if (rows < 1) return hipSuccess;
     if (X0)
-        launch_jas_gemm<T, 1>(MJ, nq, rows, X, X0, nullptr, xiblk, V, st);
+        launch_jas_gemm<T, 1>(MJ, rows, X, X0, nullptr, xiblk, V, st);
     else
-        launch_jas_gemm<T, 0>(MJ, nq, rows, X, nullptr, nullptr, xiblk, V, st);
+        launch_jas_gemm<T, 0>(MJ, rows, X, nullptr, nullptr, xiblk, V, st);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_jas_assemble(int N, int MJ, int nq, int64_t rows, int64_t row0, int W, const T *X, const T *D,
-                               const T *V, const double *xi1, double *jg, double *ju, hipStream_t st) {
-    hipLaunchKernelGGL(k_jas_assemble<T>, dim3((unsigned)W), dim3(256), 0, st, N, MJ, nq, rows, row0, X, D, V, xi1,
-                       jg, ju);
+hipError_t launch_jas_assemble(int N, int MJ, int /* nq */, int64_t rows, int64_t row0, int W, const T *X,
+                               const T *D, const T *V, const double *xi1, double *jg, double *ju, hipStream_t st) {
+    hipLaunchKernelGGL(k_jas_assemble<T>, dim3((unsigned)W), dim3(256), 0, st, N, MJ, rows, row0, X, D, V, xi1, jg,
+                       ju);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_jas_hxi(int MJ, int nq, int64_t rows, const T *D, const double *gb, const T *xiblk, T *Q,
+hipError_t launch_jas_hxi(int MJ, int /* nq */, int64_t rows, const T *D, const double *gb, const T *xiblk, T *Q,
                           hipStream_t st) {
     if (rows < 1) return hipSuccess;
-    launch_jas_gemm<T, 2>(MJ, nq, rows, D, nullptr, gb, xiblk, Q, st);
+    launch_jas_gemm<T, 2>(MJ, rows, D, nullptr, gb, xiblk, Q, st);
     return hipGetLastError();
 }
 
@@ -582,7 +582,7 @@ size_t xi_scratch_doubles(int W, int MJ) {
 }
 
 // S[w][mu] = sum_i X[w][i][mu]
-__global__ __launch_bounds__(256) void k_xi_walker_sums(const double *__restrict__ X, int N, int MJ, int W,
+__global__ __launch_bounds__(256) void k_xi_walker_sums(const double *__restrict__ X, int N, int MJ,
                                                         double *__restrict__ Sm) {
     const int w = blockIdx.x;
     for (int mu = threadIdx.x; mu < MJ; mu += 256) {
@@ -740,7 +740,7 @@ hipError_t launch_xi_sums(const double *X, int N, int MJ, int W, const double *E
     if (W < 1 || MJ < 1) return hipSuccess;
     const size_t m2 = (size_t)MJ * MJ;
     double *Sm = scratch, *pY = Sm + (size_t)W * MJ, *pS = pY + (size_t)XI_SPLIT_Y * 2 * m2;
-    hipLaunchKernelGGL(k_xi_walker_sums, dim3((unsigned)W), dim3(256), 0, st, X, N, MJ, W, Sm);
+    hipLaunchKernelGGL(k_xi_walker_sums, dim3((unsigned)W), dim3(256), 0, st, X, N, MJ, Sm);
     const int nbt = (MJ + 63) / 64;
     const int64_t KY = (int64_t)W * N, perY = (KY + XI_SPLIT_Y - 1) / XI_SPLIT_Y;
     const int64_t perS = ((int64_t)W + XI_SPLIT_S - 1) / XI_SPLIT_S;
