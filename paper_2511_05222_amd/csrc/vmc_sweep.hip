@@ -78,7 +78,8 @@ __global__ __launch_bounds__(256) void k_propose(const double *__restrict__ walk
 }
 
 // Sum over the pairs (e, k) of u(|r' - r_k|) - u(|r_e - r_k|), the lane's k
-// being lane and lane + 64, reduced over the wavefront.  FP64: exact sqrt and
+// being lane and lane + 64, reduced over the wavefront together with a term
+// of each lane (extra: the lane's part of the one-/three-body difference).  FP64: exact sqrt and
 // division.  FP32 (the mixed sweep, where it only enters the acceptance
 // ratio): differences of FP64 positions rounded to FP32, hardware square root
 // and reciprocal (about one ulp each), so the sum carries a relative error of
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void k_propose(const double *__restrict__ walk
 template <typename T>
 __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, double rx, double ry, double rz,
                                        double ex, double ey, double ez, const double *px, const double *py,
-                                       const double *pz) {
+                                       const double *pz, T extra) {
     if constexpr (sizeof(T) == sizeof(float)) {
         const float a = (float)S.ee_a, F = (float)S.ee_F;
         const float aF = S.ee_form == 1 ? (float)(S.ee_a / S.ee_F) : 0.0f;
@@ -104,6 +105,7 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
                                       a * rb * __builtin_amdgcn_rcpf(1.0f + F * rb);
             d += (k < N && k != e) ? t : 0.0f;
         }
+        d += (float)extra;
         // wavefront sum in FP32: DPP sums of the four rows, then their totals
         d = row16_sum_last<float>(d);
         const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), 15));
@@ -112,7 +114,7 @@ __device__ inline double jastrow_delta(const SysDev &S, int N, int e, int lane, 
         const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), 63));
         return (double)((r0 + r1) + (r2 + r3));
     } else {
-        double dj = 0.0;
+        double dj = (double)extra;
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             const int k = lane + 64 * hh;
@@ -270,11 +272,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         }
         // Jastrow difference over the pairs (e, k), k held by this lane (in
         // the arithmetic type: it only enters the acceptance ratio)
-        double dj = jastrow_delta<T>(S, N, e, lane, rx, ry, rz, ex, ey, ez, px, py, pz);
         // one-/three-body difference, with d = chi' - chi_e and xi3 symmetric:
-        // d^T xi3 (s - chi_e) = (xi3 d) . (s - chi_e) over the basis, plus
-        // xi1 . d from the last column of the products
-        T jd[JQ];
+        // d^T xi3 (s - chi_e) = (xi3 d) . (s - chi_e) over the basis (this
+        // lane's part, summed over the wavefront with the two-body terms),
+        // plus xi1 . d from the last column of the products
+        T jd[JQ], loc = T(0), p1 = T(0);
         if constexpr (J13) {
             const size_t row = (size_t)w * N + e;
             const T *pr = js.Pd + row * jld;
@@ -282,15 +284,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             jrow4<T>(pr, jm0, js.MJ, jvp, pd);
             jrow4<T>(js.Xp + row * js.MJ, jm0, js.MJ, jvx, xp);
             jrow4<T>(js.X0 + row * js.MJ, jm0, js.MJ, jvx, x0);
-            const T p1 = pr[js.MJ];   // xi1 . d, the same in every lane
-            T loc = T(0);
+            p1 = pr[js.MJ];   // the same in every lane
 #pragma unroll
             for (int u = 0; u < JQ; ++u) {
                 jd[u] = xp[u] - x0[u];
                 loc += pd[u] * (sq[u] - x0[u]);
             }
-            dj += wave_sum_dpp((double)loc) + (double)p1;
         }
+        double dj = jastrow_delta<T>(S, N, e, lane, rx, ry, rz, ex, ey, ez, px, py, pz, loc) + (double)p1;
         // lane i < KN holds phi_i (zero from nb on): store it at the register
         // slot of orbital i
         if (lane < KN) phin[sig] = ph;
