@@ -238,3 +238,58 @@ def test_jastrow_parameter_gradient(dev, mol9j):
     ctx.accumulate()
     close(g1, rw["dE_dxi1"], what="weighted dE_dxi1")
     close(g3, rw["dE_dxi3"], what="weighted dE_dxi3")
+
+
+def test_fullsize_sampled(dev):
+    """The one-/three-body Jastrow workload as the throughput run launches it:
+    the 21-atom molecule with 256 Jastrow functions, 16384 walkers, inverse
+    refresh every 32 moves, measurement after every sweep.  The oracle runs a
+    sample of walker indices (each chain depends only on its own index):
+    accept bits, positions and every per-walker measured quantity; on the
+    whole batch the invariants C^T dE/dC = 0 and sum_a F_a = 0, and mixed
+    against FP64 on the same configurations within the bounds."""
+    from oracle import derivatives as dv, sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    mol = inputs.with_body_jastrow(inputs.make_config(2).molecule, 9)
+    W, sweeps, seed = 16384, 2, 1
+    w0 = inputs.initial_walkers(mol, W, seed)
+    ctx = vmc.Context(mol, max_walkers=W, refresh_period=32)
+    tw = torch.tensor(w0, device=dev)
+    acc = torch.zeros((sweeps, mol.n_elec, W), dtype=torch.uint8, device=dev)
+    print("case: 21-atom J1/J3, 16384 walkers, FP64", flush=True)
+    ctx.sweep(tw, sweeps, seed, measure=True, accept=acc)
+    res = ctx.accumulate()
+    torch.cuda.synchronize()
+    # the first walker, the last of the first measurement chunk, the last
+    step = -(-W // -(-W // ctx.chunk_walkers()))
+    ids = sorted({0, step - 1, W - 1})
+    s = wf.System(mol)
+    ch, bits = sampler.run(s, w0[ids], sweeps, seed, walker_ids=np.array(ids, np.uint64), refresh_period=32)
+    assert np.array_equal(acc[:, :, ids].cpu().numpy().astype(bool), bits)
+    close(tw[ids].cpu().numpy(), ch.r, 1e-13, "positions")
+    C = np.asarray(mol.C)
+    assert np.abs(C.T @ res["dE_dC"]).max() <= 1e-9 * np.abs(C).max() * np.abs(res["dE_dC"]).max()
+    assert np.abs(res["F_bare"].sum(axis=0)).max() <= 1e-9 * np.abs(res["F_bare"]).max()
+    out = ctx.measure(tw, outputs=("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G"))
+    got = {k: v[ids].cpu().numpy() for k, v in out.items()}
+    o64 = {k: out[k] for k in ("EL", "dEL_dR", "dlnpsi_dR")}
+    dE, dP, _ = dv.nuclear_derivatives(s, s.xyz, s.xyz, ch.r)
+    O, G, ev = dv.coefficient_derivatives(s, s.xyz, ch.r)
+    ref = dict(EL=ev["E_L"], lnpsi=ev["lnpsi"], dEL_dR=dE, dlnpsi_dR=dP, O=O, G=G)
+    for k, v in ref.items():
+        close(got[k], v, TOL, f"sampled {k}")
+    # mixed against FP64 on the same 16384 configurations
+    c32 = vmc.Context(mol, max_walkers=W, precision="mixed")
+    o32 = c32.measure(tw, outputs=("EL", "dEL_dR", "dlnpsi_dR"))
+    torch.cuda.synchronize()
+
+    def ef(o):
+        E, H, Pp = o["EL"], o["dEL_dR"], o["dlnpsi_dR"]
+        e = E - E.mean()
+        return E.mean().item(), -H.mean(0) - 2.0 * ((e[:, None, None] * Pp).mean(0) - e.mean() * Pp.mean(0))
+
+    E64, F64 = ef(o64)
+    E32, F32 = ef(o32)
+    dEm, dFm = abs(E32 - E64), (F32 - F64).abs().max().item()
+    print(f"[one-/three-body Jastrow full size mixed vs fp64] |dE| = {dEm:.2e} Ha, max |dF| = {dFm:.2e} Ha/bohr")
+    assert dEm <= 5e-6 and dFm < 1e-4
