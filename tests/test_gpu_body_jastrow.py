@@ -250,7 +250,7 @@ def test_fullsize_sampled(dev):
     against FP64 on the same configurations within the bounds."""
     from oracle import derivatives as dv, sampler, wavefunction as wf
     from paper_2511_05222_amd import vmc
-    mol = inputs.with_body_jastrow(inputs.make_config(2).molecule, 9)
+    mol = inputs.with_body_jastrow(inputs.make_config(2).molecule, 7)
     W, sweeps, seed = 16384, 2, 1
     w0 = inputs.initial_walkers(mol, W, seed)
     ctx = vmc.Context(mol, max_walkers=W, refresh_period=32)

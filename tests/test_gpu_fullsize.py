@@ -151,3 +151,50 @@ def test_fullsize_mixed(dev, full):
     print(f"[full size mixed vs fp64] |dE| = {dE:.2e} Ha, max |dF| = {dF:.2e} Ha/bohr")
     assert dE < 5e-6
     assert dF < 1e-4
+
+
+def test_fullsize_exponential_jastrow(dev, full):
+    """The exponential two-body workload as the throughput run launches it:
+    the 21-atom molecule with u = a(1 - e^{-F r})/F (eq. twobody_v_exp),
+    16384 walkers.  FP64: accept bits, positions and every per-walker
+    measured quantity of three sampled walkers against the oracle, the
+    invariants on the whole batch; mixed against FP64 on the same
+    configurations within the bounds."""
+    import dataclasses
+    from oracle import derivatives as dv, sampler, wavefunction as wf
+    from paper_2511_05222_amd import vmc
+    spec, mol, _, _ = full
+    me = dataclasses.replace(mol, jastrow=dataclasses.replace(mol.jastrow, ee_form=1))
+    W = 16384
+    w0 = inputs.initial_walkers(me, W, spec.seed)
+    print("case: 21-atom exponential two-body Jastrow, 16384 walkers, FP64", flush=True)
+    ctx, tw, acc, res = run_gpu(dev, spec, me, W, w0, "fp64")
+    step = -(-W // -(-W // ctx.chunk_walkers()))
+    ids = sorted({0, step - 1, W - 1})
+    s = wf.System(me)
+    ch, bits = sampler.run(s, w0[ids], SWEEPS, spec.seed, walker_ids=np.array(ids, np.uint64), refresh_period=32)
+    assert np.array_equal(acc[:, :, ids].cpu().numpy().astype(bool), bits)
+    close(tw[ids].cpu().numpy(), ch.r, 1e-13, "positions")
+    check_invariants(me, res, W, 1e-9)
+    outs = ("EL", "lnpsi", "dEL_dR", "dlnpsi_dR", "O", "G")
+    out = ctx.measure(tw, outputs=outs)
+    got = {k: v[ids].cpu().numpy() for k, v in out.items()}
+    dE, dP, _ = dv.nuclear_derivatives(s, s.xyz, s.xyz, ch.r)
+    O, G, ev = dv.coefficient_derivatives(s, s.xyz, ch.r)
+    ref = dict(EL=ev["E_L"], lnpsi=ev["lnpsi"], dEL_dR=dE, dlnpsi_dR=dP, O=O, G=G)
+    for k, v in ref.items():
+        close(got[k], v, 1e-10, f"sampled {k}")
+    c32 = vmc.Context(me, max_walkers=W, refresh_period=32, precision="mixed")
+    o32 = c32.measure(tw, outputs=("EL", "dEL_dR", "dlnpsi_dR"))
+    torch.cuda.synchronize()
+
+    def ef(o):
+        E, H, Pp = o["EL"], o["dEL_dR"], o["dlnpsi_dR"]
+        e = E - E.mean()
+        return E.mean().item(), -H.mean(0) - 2.0 * ((e[:, None, None] * Pp).mean(0) - e.mean() * Pp.mean(0))
+
+    E64, F64 = ef(out)
+    E32, F32 = ef(o32)
+    dEm, dFm = abs(E32 - E64), (F32 - F64).abs().max().item()
+    print(f"[exponential Jastrow full size mixed vs fp64] |dE| = {dEm:.2e} Ha, max |dF| = {dFm:.2e} Ha/bohr")
+    assert dEm <= 5e-6 and dFm < 1e-4
