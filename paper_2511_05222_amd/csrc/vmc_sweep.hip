@@ -276,20 +276,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         // d^T xi3 (s - chi_e) = (xi3 d) . (s - chi_e) over the basis (this
         // lane's part, summed over the wavefront with the two-body terms),
         // plus xi1 . d from the last column of the products
-        T jd[JQ], loc = T(0), p1 = T(0);
+        // (chi(r') itself is read only on an accepted move, for s += d)
+        T x0[JQ], loc = T(0), p1 = T(0);
         if constexpr (J13) {
             const size_t row = (size_t)w * N + e;
             const T *pr = js.Pd + row * jld;
-            T pd[JQ], xp[JQ], x0[JQ];
+            T pd[JQ];
             jrow4<T>(pr, jm0, js.MJ, jvp, pd);
-            jrow4<T>(js.Xp + row * js.MJ, jm0, js.MJ, jvx, xp);
             jrow4<T>(js.X0 + row * js.MJ, jm0, js.MJ, jvx, x0);
             p1 = pr[js.MJ];   // the same in every lane
 #pragma unroll
-            for (int u = 0; u < JQ; ++u) {
-                jd[u] = xp[u] - x0[u];
-                loc += pd[u] * (sq[u] - x0[u]);
-            }
+            for (int u = 0; u < JQ; ++u) loc += pd[u] * (sq[u] - x0[u]);
         }
         double dj = jastrow_delta<T>(S, N, e, lane, rx, ry, rz, ex, ey, ez, px, py, pz, loc) + (double)p1;
         // lane i < KN holds phi_i (zero from nb on): store it at the register
@@ -318,6 +315,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
         const double qv = ratio * (sizeof(T) == sizeof(float) ? (double)expf((float)dj) : exp(dj));
         const bool acc = u < qv * qv;
         if (acc) {
+            T xp[JQ];
+            if constexpr (J13) jrow4<T>(js.Xp + ((size_t)w * N + e) * js.MJ, jm0, js.MJ, jvx, xp);
             if (lane < nb) Aw[(size_t)e * n + lane] = ph;
             if (lane == src) {
                 if (h) {
@@ -342,7 +341,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_waves
             wave_sync_s();
             if constexpr (J13) {
 #pragma unroll
-                for (int u = 0; u < JQ; ++u) sq[u] += jd[u];
+                for (int u = 0; u < JQ; ++u) sq[u] += xp[u] - x0[u];
             }
             const T rr = sizeof(T) == sizeof(float) ? (T)__builtin_amdgcn_rcpf((float)ratio) : (T)rcp_nr(ratio);
             const T t = (v - (lane == pj ? T(1) : T(0))) * rr;
